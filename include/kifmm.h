@@ -1,0 +1,193 @@
+/*
+ * kifmm.h - C ABI of the MI355X (gfx950) kernel-independent FMM library.
+ *
+ * The library evaluates potentials phi_i = sum_j K(x_i, y_j) q_j of the 3D
+ * Laplace kernel K(x, y) = 1 / (4 pi |x - y|) (the N-body sum and kernel of
+ * Section 1 of arXiv 2408.07436) with the kernel-independent FMM on a pruned
+ * uniform octree (Section 2), and applies the multipole-to-local (M2L)
+ * translation in one of three forms:
+ *   KIFMM_M2L_DENSE - the uncompressed M2L matvec of Section 2.2,
+ *   KIFMM_M2L_FFT   - the convolution form on a 2P-point grid with Hadamard
+ *                     products grouped by sibling cluster (Appendix A.1-A.2),
+ *   KIFMM_M2L_BLAS  - SVD-compressed operators with directional
+ *                     recompression (Section 3.1-3.2).
+ *
+ * Workflow (the paper's setup / runtime split, Section 4 and Section 5.1):
+ *   kifmm_create -> kifmm_set_points -> kifmm_precompute -> kifmm_evaluate*
+ *   -> kifmm_destroy.
+ * create, set_points, precompute and the introspection calls run on the host
+ * only (no GPU is touched).  The first evaluate or stage call uploads the
+ * tree and operators to the device selected in the config.
+ *
+ * Conventions (fixed here because the paper leaves them open):
+ *   - Domain: cube [origin, origin + width]^3; width <= 0 selects the
+ *     tightest cube around all points, centred on their bounding box.
+ *     A point x lies in the leaf with anchor
+ *     a = min(floor((x - origin) / width * 2^depth), 2^depth - 1) per axis.
+ *   - Morton key of a box with anchor a at level l: bit b of a_x at bit 3b,
+ *     of a_y at 3b+1, of a_z at 3b+2, plus a sentinel bit 3l.  parent =
+ *     key >> 3, octant = key & 7.  Points are ordered by (leaf key, index).
+ *   - Boxes at a level are the ancestors of non-empty leaves, ascending key.
+ *   - Interaction list of a box at level l >= 2: boxes of the level whose
+ *     parent is adjacent to (or is) the box's parent, minus the box's own
+ *     3x3x3 neighbourhood; ascending source key.  Transfer vector
+ *     t = anchor(source) - anchor(target), index = rank of t in
+ *     lexicographic (tx, ty, tz) order over the 316 offsets of [-3,3]^3
+ *     with max |t_i| >= 2 (Section 3.1).
+ *   - Surfaces of order p: c + alpha r (-1 + 2 i/(p-1)), i in [0,p-1]^3 on
+ *     the lattice boundary, i_x slowest; 6(p-1)^2 + 2 points (Appendix A.3).
+ *     Upward-equivalent and downward-check surfaces use alpha_inner,
+ *     upward-check and downward-equivalent surfaces alpha_outer.
+ *   - K(x, y) = 0 when x and y are bitwise equal.
+ *   - Pseudo-inverses keep singular values > max(M,N) * 2^-52 * sigma_0 and
+ *     are applied as two FP64 factors V (Sigma^-1 U^T) (Section 2.1.1).
+ *   - The M2L and L2L check potentials of a box are summed before its
+ *     check-to-equivalent pseudo-inverse is applied once.
+ *
+ * Errors: every call returns a kifmm_status and never aborts; the message
+ * of the last failure on the calling thread is kifmm_last_error().
+ * A handle is not thread-safe; use one handle per host thread.
+ */
+#ifndef KIFMM_H
+#define KIFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kifmm_handle kifmm_handle;
+
+typedef enum {
+  KIFMM_OK = 0,
+  KIFMM_EINVAL = 1,       /* bad argument: null pointer, bad size, point outside domain */
+  KIFMM_ESTATE = 2,       /* call out of order (e.g. evaluate before precompute) */
+  KIFMM_ENOMEM = 3,       /* host or device allocation failed */
+  KIFMM_EDEVICE = 4,      /* HIP runtime error (no device, launch failure) */
+  KIFMM_EUNSUPPORTED = 5, /* valid but unsupported combination */
+  KIFMM_ENUMERIC = 6      /* SVD failed to converge */
+} kifmm_status;
+
+typedef enum { KIFMM_M2L_DENSE = 0, KIFMM_M2L_FFT = 1, KIFMM_M2L_BLAS = 2 } kifmm_m2l;
+
+/* Arithmetic of the M2L step.  P2M, M2M, L2L, the pseudo-inverses, L2P and
+ * the accumulation of check potentials and local expansions are FP64 in
+ * every mode; P2P runs in the precision of the charges.
+ *   KIFMM_FP64   - charges/potentials double; M2L in FP64.
+ *   KIFMM_FP32   - charges/potentials float; M2L in FP32 (FFT: FP32 complex
+ *                  transforms and Hadamard products; BLAS/DENSE: FP32 GEMMs).
+ *   KIFMM_BF16X3 - charges/potentials float; BLAS/DENSE M2L GEMMs on bf16
+ *                  MFMA with hi+lo split operands (a = hi + lo, products
+ *                  hi*hi + hi*lo + lo*hi, FP32 accumulation); FFT M2L as FP32. */
+typedef enum { KIFMM_FP64 = 0, KIFMM_FP32 = 1, KIFMM_BF16X3 = 2 } kifmm_prec;
+
+typedef struct {
+  uint32_t size;            /* sizeof(kifmm_config), for ABI versioning */
+  int32_t order;            /* expansion order p >= 2 (points per surface edge) */
+  int32_t depth;            /* uniform leaf depth, 2..16 */
+  int32_t m2l;              /* kifmm_m2l */
+  int32_t prec;             /* kifmm_prec */
+  int32_t device;           /* HIP device ordinal used by evaluate */
+  double svd_rel_tol;       /* BLAS: keep sigma_i(K_fat) > tol * sigma_0; 0 = full rank */
+  double svd_rel_tol_dir;   /* BLAS: keep sigma_i(C_t) > tol * sigma_0(C_t); < 0 = no recompression */
+  double alpha_inner;       /* 0 selects 1.05 */
+  double alpha_outer;       /* 0 selects 2.95 */
+  double origin[3];         /* lower corner of the domain cube */
+  double width;             /* side of the domain cube; <= 0 selects the tight cube */
+} kifmm_config;
+
+/* Fill *cfg with defaults: p = 6, depth = 4, FFT, FP64, tolerances 0 / -1,
+ * alpha 1.05 / 2.95, origin 0, width 1, device 0. */
+void kifmm_config_default(kifmm_config* cfg);
+
+/* Create a handle.  Validates the config (EINVAL: order < 2, depth outside
+ * 2..16, unknown m2l/prec; EUNSUPPORTED: BF16X3 with FFT).  *out receives
+ * the handle, owned by the caller until kifmm_destroy. */
+kifmm_status kifmm_create(const kifmm_config* cfg, kifmm_handle** out);
+
+/* Build the tree and all lists from host positions src[n_src][3] and
+ * tgt[n_tgt][3] (row-major doubles; copied).  tgt may equal src.
+ * EINVAL: null pointers, n <= 0, or a point outside the domain cube. */
+kifmm_status kifmm_set_points(kifmm_handle* h, const double* src, int64_t n_src,
+                              const double* tgt, int64_t n_tgt);
+
+/* Compute all operators in FP64 on the host: pseudo-inverse factors, M2M
+ * and L2L kernel matrices, and the M2L operators of the selected form.
+ * Depends only on the configuration (Section 5.1).  Idempotent.
+ * ENUMERIC: an SVD did not converge. */
+kifmm_status kifmm_precompute(kifmm_handle* h);
+
+/* Evaluate potentials on the device, asynchronously on hip_stream (a
+ * hipStream_t; NULL = default stream).  q_dev holds n_vec charge vectors,
+ * column-major [n_vec][ldq] in the caller's source order; phi_dev receives
+ * [n_vec][ldphi] in the caller's target order (overwritten).  Element type
+ * is double for KIFMM_FP64 and float otherwise; both are device pointers
+ * owned by the caller.  ldq >= n_src, ldphi >= n_tgt, n_vec >= 1.
+ * ESTATE: called before set_points / precompute.  EDEVICE: HIP error. */
+kifmm_status kifmm_evaluate(kifmm_handle* h, const void* q_dev, int64_t ldq, int32_t n_vec,
+                            void* phi_dev, int64_t ldphi, void* hip_stream);
+
+/* Release the handle and all device memory it owns.  NULL is accepted. */
+kifmm_status kifmm_destroy(kifmm_handle* h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* kifmm_last_error(void);
+
+/* ---- introspection (host only, valid after set_points) ---------------- */
+
+/* Number of boxes at a level (0..depth). */
+kifmm_status kifmm_num_boxes(const kifmm_handle* h, int32_t level, int64_t* n);
+/* Sorted Morton keys of the boxes of a level; cap = capacity of keys. */
+kifmm_status kifmm_box_keys(const kifmm_handle* h, int32_t level, uint64_t* keys, int64_t cap);
+/* Sorting permutation: sorted position i holds original point perm[i].
+ * which = 0 for sources, 1 for targets. */
+kifmm_status kifmm_point_perm(const kifmm_handle* h, int32_t which, int64_t* perm, int64_t cap);
+/* Interaction lists of level >= 2 in CSR form: offs[n_boxes + 1], source box
+ * indices src[offs[n]] and transfer-vector indices tidx[offs[n]].  Passing
+ * NULL arrays returns only the total count in *n_pairs. */
+kifmm_status kifmm_interactions(const kifmm_handle* h, int32_t level, int64_t* offs,
+                                int64_t* src, int32_t* tidx, int64_t cap, int64_t* n_pairs);
+/* Near-field (P2P) lists of the leaves in CSR form, like kifmm_interactions. */
+kifmm_status kifmm_near(const kifmm_handle* h, int64_t* offs, int64_t* src, int64_t cap,
+                        int64_t* n_pairs);
+
+/* Host FP64 operators (valid after precompute), for checks.  which:
+ *   0 KIFMM_OP_UP_PINV_V, 1 KIFMM_OP_UP_PINV_UT, 2 KIFMM_OP_DOWN_PINV_V,
+ *   3 KIFMM_OP_DOWN_PINV_UT (unit box, level scale applied by the library),
+ *   4 KIFMM_OP_FFT_SPECTRA: kernel spectra of the unit box, [316][F] complex
+ *     as interleaved (re, im) doubles with F = (2p)^2 (p+1) ordered
+ *     [kx][ky][kz], kz fastest; the convolution grid is the reading of
+ *     Appendix A.1 stated in the design doc (kernel at offset m mod 2p,
+ *     densities at their lattice positions);
+ *   5 KIFMM_OP_BLAS_U: U (n_s x k, row-major), 6 KIFMM_OP_BLAS_RANKS: k then
+ *     k_t for the 316 transfer vectors (as doubles), 7 KIFMM_OP_BLAS_APPLIED:
+ *     the applied operator U Ubar_t Vbar'_t^T S^T of every t, [316][n_s][n_s],
+ *     for the unit box.
+ * *n receives the element count; out may be NULL to query it. */
+kifmm_status kifmm_operator(const kifmm_handle* h, int32_t which, double* out, int64_t cap,
+                            int64_t* n);
+
+/* ---- stages and timings (device) ---------------------------------------- */
+
+/* Run one M2L level on caller device buffers, asynchronously:
+ * in_dev = upward-equivalent densities [n_boxes(level)][n_vec][n_s] (double,
+ * boxes in key order), out_dev = M2L check potentials, same layout (double,
+ * overwritten).  Uses the configured M2L form and precision.  stage must be
+ * KIFMM_STAGE_M2L (0). */
+kifmm_status kifmm_stage(kifmm_handle* h, int32_t stage, int32_t level, const void* in_dev,
+                         void* out_dev, int32_t n_vec, void* hip_stream);
+
+/* Enable (1) or disable (0) per-stage timing of evaluate with HIP events.
+ * Timing synchronises the stream at the end of evaluate. */
+kifmm_status kifmm_set_timing(kifmm_handle* h, int32_t on);
+/* Milliseconds of the last timed evaluate, per stage: [0] upward (P2M+M2M),
+ * [1] M2L (all levels), [2] downward rest (pinv + L2L), [3] leaves (L2P +
+ * P2P), [4] total.  cap >= 5. */
+kifmm_status kifmm_timings(const kifmm_handle* h, double* ms, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KIFMM_H */

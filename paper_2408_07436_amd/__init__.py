@@ -1,0 +1,239 @@
+"""Python binding of libkifmm, the MI355X kernel-independent FMM library.
+
+Argument marshalling only: every step of the FMM runs in the HIP library
+(``csrc/``) behind the C ABI of ``include/kifmm.h``.  PyTorch supplies device
+memory and streams.  There is no CPU fallback: importing the binding fails
+loudly when ``libkifmm.so`` has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkifmm.so")
+
+M2L = {"dense": 0, "fft": 1, "blas": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+STATUS = {0: "OK", 1: "EINVAL", 2: "ESTATE", 3: "ENOMEM", 4: "EDEVICE", 5: "EUNSUPPORTED",
+          6: "ENUMERIC"}
+
+EXPORTS = [
+    "kifmm_config_default", "kifmm_create", "kifmm_set_points", "kifmm_precompute",
+    "kifmm_evaluate", "kifmm_destroy", "kifmm_last_error", "kifmm_num_boxes", "kifmm_box_keys",
+    "kifmm_point_perm", "kifmm_interactions", "kifmm_near", "kifmm_operator", "kifmm_stage",
+    "kifmm_set_timing", "kifmm_timings",
+]
+
+
+class KifmmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("size", ctypes.c_uint32),
+        ("order", ctypes.c_int32),
+        ("depth", ctypes.c_int32),
+        ("m2l", ctypes.c_int32),
+        ("prec", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("svd_rel_tol", ctypes.c_double),
+        ("svd_rel_tol_dir", ctypes.c_double),
+        ("alpha_inner", ctypes.c_double),
+        ("alpha_outer", ctypes.c_double),
+        ("origin", ctypes.c_double * 3),
+        ("width", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libkifmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2408_07436_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    L.kifmm_config_default.argtypes = [ctypes.POINTER(Config)]
+    L.kifmm_config_default.restype = None
+    L.kifmm_create.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(vp)]
+    L.kifmm_set_points.argtypes = [vp, dp, i64, dp, i64]
+    L.kifmm_precompute.argtypes = [vp]
+    L.kifmm_evaluate.argtypes = [vp, vp, i64, i32, vp, i64, vp]
+    L.kifmm_destroy.argtypes = [vp]
+    L.kifmm_last_error.restype = ctypes.c_char_p
+    L.kifmm_num_boxes.argtypes = [vp, i32, ctypes.POINTER(i64)]
+    L.kifmm_box_keys.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_uint64), i64]
+    L.kifmm_point_perm.argtypes = [vp, i32, ctypes.POINTER(i64), i64]
+    L.kifmm_interactions.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                     ctypes.POINTER(i32), i64, ctypes.POINTER(i64)]
+    L.kifmm_near.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), i64, ctypes.POINTER(i64)]
+    L.kifmm_operator.argtypes = [vp, i32, dp, i64, ctypes.POINTER(i64)]
+    L.kifmm_stage.argtypes = [vp, i32, i32, vp, vp, i32, vp]
+    L.kifmm_set_timing.argtypes = [vp, i32]
+    L.kifmm_timings.argtypes = [vp, dp, i32]
+    for name in EXPORTS:
+        if name not in ("kifmm_config_default", "kifmm_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(code: int):
+    if code != 0:
+        raise KifmmError(code, lib().kifmm_last_error().decode())
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+class KiFMM:
+    """A kiFMM problem: configuration, points, precomputed operators.
+
+    ``m2l`` is "dense", "fft" or "blas"; ``prec`` is "fp64", "fp32" or
+    "bf16x3" (see ``include/kifmm.h``).
+    """
+
+    def __init__(self, order: int, depth: int, m2l: str = "fft", prec: str = "fp64",
+                 origin=(0.0, 0.0, 0.0), width: float = 1.0, svd_rel_tol: float = 0.0,
+                 svd_rel_tol_dir: float = -1.0, device: int = 0, alpha_inner: float = 1.05,
+                 alpha_outer: float = 2.95):
+        L = lib()
+        cfg = Config()
+        L.kifmm_config_default(ctypes.byref(cfg))
+        cfg.order, cfg.depth = order, depth
+        cfg.m2l, cfg.prec = M2L[m2l], PREC[prec]
+        cfg.device = device
+        cfg.svd_rel_tol, cfg.svd_rel_tol_dir = svd_rel_tol, svd_rel_tol_dir
+        cfg.alpha_inner, cfg.alpha_outer = alpha_inner, alpha_outer
+        cfg.origin[:] = list(origin)
+        cfg.width = width
+        h = ctypes.c_void_p()
+        _check(L.kifmm_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.order, self.depth, self.m2l, self.prec = order, depth, m2l, prec
+        self.n_src = self.n_tgt = 0
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().kifmm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.float64 if self.prec == "fp64" else torch.float32
+
+    def set_points(self, sources: np.ndarray, targets: np.ndarray | None = None):
+        s = np.ascontiguousarray(sources, dtype=np.float64)
+        t = s if targets is None else np.ascontiguousarray(targets, dtype=np.float64)
+        _check(lib().kifmm_set_points(self._h, _ptr(s, ctypes.c_double), s.shape[0],
+                                      _ptr(t, ctypes.c_double), t.shape[0]))
+        self.n_src, self.n_tgt = s.shape[0], t.shape[0]
+        return self
+
+    def precompute(self):
+        _check(lib().kifmm_precompute(self._h))
+        return self
+
+    def evaluate(self, q, out=None, stream=None):
+        """Potentials (nvec, n_tgt) on the device for charges ``q`` (nvec, n_src)."""
+        import torch
+        if q.dim() == 1:
+            q = q[None]
+        assert q.is_cuda and q.dtype == self.dtype and q.stride(1) == 1
+        nvec = q.shape[0]
+        if out is None:
+            out = torch.empty((nvec, self.n_tgt), dtype=self.dtype, device=q.device)
+        assert out.is_cuda and out.dtype == self.dtype and out.stride(1) == 1
+        s = torch.cuda.current_stream(q.device) if stream is None else stream
+        _check(lib().kifmm_evaluate(self._h, q.data_ptr(), q.stride(0), nvec, out.data_ptr(),
+                                    out.stride(0), ctypes.c_void_p(s.cuda_stream)))
+        return out
+
+    def stage_m2l(self, level: int, mult, out=None, stream=None):
+        """M2L check potentials of one level for densities ``mult`` (n_boxes, nvec, n_s), FP64."""
+        import torch
+        assert mult.is_cuda and mult.dtype == torch.float64 and mult.is_contiguous()
+        if out is None:
+            out = torch.empty_like(mult)
+        s = torch.cuda.current_stream(mult.device) if stream is None else stream
+        _check(lib().kifmm_stage(self._h, 0, level, mult.data_ptr(), out.data_ptr(), mult.shape[1],
+                                 ctypes.c_void_p(s.cuda_stream)))
+        return out
+
+    # ---- introspection -----------------------------------------------------
+    def num_boxes(self, level: int) -> int:
+        n = ctypes.c_int64()
+        _check(lib().kifmm_num_boxes(self._h, level, ctypes.byref(n)))
+        return n.value
+
+    def box_keys(self, level: int) -> np.ndarray:
+        n = self.num_boxes(level)
+        out = np.zeros(n, dtype=np.uint64)
+        _check(lib().kifmm_box_keys(self._h, level, _ptr(out, ctypes.c_uint64), n))
+        return out
+
+    def point_perm(self, which: int = 0) -> np.ndarray:
+        n = self.n_src if which == 0 else self.n_tgt
+        out = np.zeros(n, dtype=np.int64)
+        _check(lib().kifmm_point_perm(self._h, which, _ptr(out, ctypes.c_int64), n))
+        return out
+
+    def interactions(self, level: int):
+        L = lib()
+        cnt = ctypes.c_int64()
+        _check(L.kifmm_interactions(self._h, level, None, None, None, 0, ctypes.byref(cnt)))
+        nb = self.num_boxes(level)
+        offs = np.zeros(nb + 1, dtype=np.int64)
+        src = np.zeros(max(cnt.value, 1), dtype=np.int64)
+        tid = np.zeros(max(cnt.value, 1), dtype=np.int32)
+        _check(L.kifmm_interactions(self._h, level, _ptr(offs, ctypes.c_int64), _ptr(src, ctypes.c_int64),
+                                    _ptr(tid, ctypes.c_int32), src.size, ctypes.byref(cnt)))
+        return offs, src[:cnt.value], tid[:cnt.value]
+
+    def near(self):
+        L = lib()
+        cnt = ctypes.c_int64()
+        _check(L.kifmm_near(self._h, None, None, 0, ctypes.byref(cnt)))
+        offs = np.zeros(self.num_boxes(self.depth) + 1, dtype=np.int64)
+        src = np.zeros(cnt.value, dtype=np.int64)
+        _check(L.kifmm_near(self._h, _ptr(offs, ctypes.c_int64), _ptr(src, ctypes.c_int64), src.size,
+                            ctypes.byref(cnt)))
+        return offs, src
+
+    def operator(self, which: int) -> np.ndarray:
+        L = lib()
+        n = ctypes.c_int64()
+        _check(L.kifmm_operator(self._h, which, None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, dtype=np.float64)
+        _check(L.kifmm_operator(self._h, which, _ptr(out, ctypes.c_double), n.value, ctypes.byref(n)))
+        return out
+
+    def set_timing(self, on: bool = True):
+        _check(lib().kifmm_set_timing(self._h, 1 if on else 0))
+
+    def timings(self) -> dict:
+        ms = np.zeros(5, dtype=np.float64)
+        _check(lib().kifmm_timings(self._h, _ptr(ms, ctypes.c_double), 5))
+        return dict(upward=ms[0], m2l=ms[1], downward=ms[2], leaves=ms[3], total=ms[4])
+
+
+OP_UP_V, OP_UP_UT, OP_DOWN_V, OP_DOWN_UT, OP_FFT_SPECTRA, OP_BLAS_U, OP_BLAS_RANKS, OP_BLAS_APPLIED = range(8)

@@ -1,0 +1,275 @@
+// extern "C" entry points of libkifmm (declared in include/kifmm.h).
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.h"
+
+namespace kifmm {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+kifmm_status fail(kifmm_status code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nvec, void* phi,
+                             int64_t ldphi, hipStream_t s);
+kifmm_status device_stage(kifmm_handle* h, int level, const void* in, void* out, int nvec,
+                          hipStream_t s);
+
+}  // namespace kifmm
+
+using kifmm::fail;
+
+extern "C" {
+
+void kifmm_config_default(kifmm_config* cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->size = sizeof(kifmm_config);
+  cfg->order = 6;
+  cfg->depth = 4;
+  cfg->m2l = KIFMM_M2L_FFT;
+  cfg->prec = KIFMM_FP64;
+  cfg->device = 0;
+  cfg->svd_rel_tol = 0.0;
+  cfg->svd_rel_tol_dir = -1.0;
+  cfg->alpha_inner = 1.05;
+  cfg->alpha_outer = 2.95;
+  cfg->width = 1.0;
+}
+
+const char* kifmm_last_error(void) { return kifmm::g_last_error.c_str(); }
+
+kifmm_status kifmm_create(const kifmm_config* cfg, kifmm_handle** out) {
+  if (!cfg || !out) return fail(KIFMM_EINVAL, "null argument");
+  *out = nullptr;
+  if (cfg->size != sizeof(kifmm_config)) return fail(KIFMM_EINVAL, "kifmm_config.size mismatch");
+  if (cfg->order < 2) return fail(KIFMM_EINVAL, "order must be >= 2");
+  if (cfg->depth < 2 || cfg->depth > 16) return fail(KIFMM_EINVAL, "depth must be in 2..16");
+  if (cfg->m2l < KIFMM_M2L_DENSE || cfg->m2l > KIFMM_M2L_BLAS)
+    return fail(KIFMM_EINVAL, "unknown m2l form");
+  if (cfg->prec < KIFMM_FP64 || cfg->prec > KIFMM_BF16X3)
+    return fail(KIFMM_EINVAL, "unknown precision");
+  if (cfg->m2l == KIFMM_M2L_FFT && cfg->order > 8)
+    return fail(KIFMM_EUNSUPPORTED, "FFT M2L is built for orders 2..8");
+  if (cfg->m2l == KIFMM_M2L_FFT && cfg->prec == KIFMM_BF16X3)
+    return fail(KIFMM_EUNSUPPORTED, "bf16 split precision applies to the BLAS and dense M2L only");
+  auto* h = new (std::nothrow) kifmm_handle();
+  if (!h) return fail(KIFMM_ENOMEM, "out of host memory");
+  h->cfg = *cfg;
+  if (h->cfg.alpha_inner <= 0) h->cfg.alpha_inner = 1.05;
+  if (h->cfg.alpha_outer <= 0) h->cfg.alpha_outer = 2.95;
+  *out = h;
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_set_points(kifmm_handle* h, const double* src, int64_t n_src, const double* tgt,
+                              int64_t n_tgt) {
+  if (!h || !src || !tgt) return fail(KIFMM_EINVAL, "null argument");
+  if (n_src <= 0 || n_tgt <= 0) return fail(KIFMM_EINVAL, "point counts must be positive");
+  if (n_src > INT32_MAX || n_tgt > INT32_MAX) return fail(KIFMM_EINVAL, "too many points");
+  if (h->dev) {
+    kifmm::destroy_device(h->dev);
+    h->dev = nullptr;
+  }
+  h->has_points = false;
+  kifmm_status st = kifmm::build_tree(h->tree, h->cfg.depth, h->cfg.origin, h->cfg.width, src, n_src,
+                                      tgt, n_tgt);
+  if (st != KIFMM_OK) return st;
+  h->has_points = true;
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_precompute(kifmm_handle* h) {
+  if (!h) return fail(KIFMM_EINVAL, "null handle");
+  if (h->op.ready) return KIFMM_OK;
+  if (h->dev) {
+    kifmm::destroy_device(h->dev);
+    h->dev = nullptr;
+  }
+  return kifmm::precompute_operators(h->op, h->cfg);
+}
+
+kifmm_status kifmm_evaluate(kifmm_handle* h, const void* q_dev, int64_t ldq, int32_t n_vec,
+                            void* phi_dev, int64_t ldphi, void* hip_stream) {
+  if (!h) return fail(KIFMM_EINVAL, "null handle");
+  if (!h->has_points) return fail(KIFMM_ESTATE, "evaluate before set_points");
+  if (!h->op.ready) return fail(KIFMM_ESTATE, "evaluate before precompute");
+  if (!q_dev || !phi_dev) return fail(KIFMM_EINVAL, "null buffer");
+  if (n_vec < 1 || ldq < h->tree.n_src || ldphi < h->tree.n_tgt)
+    return fail(KIFMM_EINVAL, "bad n_vec or leading dimension");
+  if (h->cfg.m2l != KIFMM_M2L_FFT && h->cfg.prec != KIFMM_FP64)
+    return fail(KIFMM_EUNSUPPORTED, "reduced-precision BLAS/dense M2L not available");
+  return kifmm::device_evaluate(h, q_dev, ldq, n_vec, phi_dev, ldphi, (hipStream_t)hip_stream);
+}
+
+kifmm_status kifmm_destroy(kifmm_handle* h) {
+  if (!h) return KIFMM_OK;
+  kifmm::destroy_device(h->dev);
+  delete h;
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_num_boxes(const kifmm_handle* h, int32_t level, int64_t* n) {
+  if (!h || !n) return fail(KIFMM_EINVAL, "null argument");
+  if (!h->has_points) return fail(KIFMM_ESTATE, "no points set");
+  if (level < 0 || level > h->tree.depth) return fail(KIFMM_EINVAL, "level out of range");
+  *n = h->tree.levels[level].n;
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_box_keys(const kifmm_handle* h, int32_t level, uint64_t* keys, int64_t cap) {
+  if (!h || !keys) return fail(KIFMM_EINVAL, "null argument");
+  if (!h->has_points) return fail(KIFMM_ESTATE, "no points set");
+  if (level < 0 || level > h->tree.depth) return fail(KIFMM_EINVAL, "level out of range");
+  const auto& k = h->tree.levels[level].keys;
+  if (cap < (int64_t)k.size()) return fail(KIFMM_EINVAL, "capacity too small");
+  std::memcpy(keys, k.data(), k.size() * sizeof(uint64_t));
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_point_perm(const kifmm_handle* h, int32_t which, int64_t* perm, int64_t cap) {
+  if (!h || !perm) return fail(KIFMM_EINVAL, "null argument");
+  if (!h->has_points) return fail(KIFMM_ESTATE, "no points set");
+  if (which != 0 && which != 1) return fail(KIFMM_EINVAL, "which must be 0 or 1");
+  const auto& p = which == 0 ? h->tree.src_perm : h->tree.tgt_perm;
+  if (cap < (int64_t)p.size()) return fail(KIFMM_EINVAL, "capacity too small");
+  std::memcpy(perm, p.data(), p.size() * sizeof(int64_t));
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_interactions(const kifmm_handle* h, int32_t level, int64_t* offs, int64_t* src,
+                                int32_t* tidx, int64_t cap, int64_t* n_pairs) {
+  if (!h || !n_pairs) return fail(KIFMM_EINVAL, "null argument");
+  if (!h->has_points) return fail(KIFMM_ESTATE, "no points set");
+  if (level < 2 || level > h->tree.depth) return fail(KIFMM_EINVAL, "level out of range");
+  const auto& L = h->tree.levels[level];
+  *n_pairs = (int64_t)L.il_src.size();
+  if (!offs && !src && !tidx) return KIFMM_OK;
+  if (!offs || !src || !tidx) return fail(KIFMM_EINVAL, "null array");
+  if (cap < *n_pairs) return fail(KIFMM_EINVAL, "capacity too small");
+  std::memcpy(offs, L.il_offs.data(), L.il_offs.size() * sizeof(int64_t));
+  for (size_t e = 0; e < L.il_src.size(); ++e) {
+    src[e] = L.il_src[e];
+    tidx[e] = L.il_t[e];
+  }
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_near(const kifmm_handle* h, int64_t* offs, int64_t* src, int64_t cap,
+                        int64_t* n_pairs) {
+  if (!h || !n_pairs) return fail(KIFMM_EINVAL, "null argument");
+  if (!h->has_points) return fail(KIFMM_ESTATE, "no points set");
+  *n_pairs = (int64_t)h->tree.near_src.size();
+  if (!offs && !src) return KIFMM_OK;
+  if (!offs || !src) return fail(KIFMM_EINVAL, "null array");
+  if (cap < *n_pairs) return fail(KIFMM_EINVAL, "capacity too small");
+  std::memcpy(offs, h->tree.near_offs.data(), h->tree.near_offs.size() * sizeof(int64_t));
+  for (size_t e = 0; e < h->tree.near_src.size(); ++e) src[e] = h->tree.near_src[e];
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_operator(const kifmm_handle* h, int32_t which, double* out, int64_t cap,
+                            int64_t* n) {
+  if (!h || !n) return fail(KIFMM_EINVAL, "null argument");
+  if (!h->op.ready) return fail(KIFMM_ESTATE, "operators not precomputed");
+  const kifmm::Operators& op = h->op;
+  std::vector<double> buf;
+  const std::vector<double>* src = nullptr;
+  switch (which) {
+    case 0: src = &op.up_V; break;
+    case 1: src = &op.up_Ut; break;
+    case 2: src = &op.down_V; break;
+    case 3: src = &op.down_Ut; break;
+    case 4:
+      if (h->cfg.m2l != KIFMM_M2L_FFT) return fail(KIFMM_EINVAL, "no FFT spectra in this mode");
+      src = &op.spectra;
+      break;
+    case 5:
+      if (h->cfg.m2l == KIFMM_M2L_FFT) return fail(KIFMM_EINVAL, "no BLAS operators in this mode");
+      src = &op.U;
+      break;
+    case 6:
+      if (h->cfg.m2l == KIFMM_M2L_FFT) return fail(KIFMM_EINVAL, "no BLAS operators in this mode");
+      buf.push_back(op.k);
+      for (int r : op.kt) buf.push_back(r);
+      src = &buf;
+      break;
+    case 7: {
+      if (h->cfg.m2l == KIFMM_M2L_FFT) return fail(KIFMM_EINVAL, "no BLAS operators in this mode");
+      const int ns = op.ns, k = op.k;
+      buf.assign((size_t)kifmm::kNumTransfer * ns * ns, 0.0);
+      std::vector<double> C((size_t)k * k), UC((size_t)ns * k);
+      for (int it = 0; it < kifmm::kNumTransfer; ++it) {
+        if (!op.recompressed) {
+          C = op.Vbarp[it];
+        } else {
+          const int r = op.kt[it];
+          for (int i = 0; i < k; ++i)
+            for (int j = 0; j < k; ++j) {
+              double acc = 0;
+              for (int l = 0; l < r; ++l)
+                acc += op.Ubar[it][(size_t)i * r + l] * op.Vbarp[it][(size_t)j * r + l];
+              C[(size_t)i * k + j] = acc;
+            }
+        }
+        for (int i = 0; i < ns; ++i)
+          for (int j = 0; j < k; ++j) {
+            double acc = 0;
+            for (int l = 0; l < k; ++l) acc += op.U[(size_t)i * k + l] * C[(size_t)l * k + j];
+            UC[(size_t)i * k + j] = acc;
+          }
+        double* dst = &buf[(size_t)it * ns * ns];
+        for (int i = 0; i < ns; ++i)
+          for (int j = 0; j < ns; ++j) {
+            double acc = 0;
+            for (int l = 0; l < k; ++l) acc += UC[(size_t)i * k + l] * op.U[(size_t)j * k + l];
+            dst[(size_t)i * ns + j] = acc;
+          }
+      }
+      src = &buf;
+      break;
+    }
+    default:
+      return fail(KIFMM_EINVAL, "unknown operator id");
+  }
+  *n = (int64_t)src->size();
+  if (!out) return KIFMM_OK;
+  if (cap < *n) return fail(KIFMM_EINVAL, "capacity too small");
+  std::memcpy(out, src->data(), src->size() * sizeof(double));
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_stage(kifmm_handle* h, int32_t stage, int32_t level, const void* in_dev,
+                         void* out_dev, int32_t n_vec, void* hip_stream) {
+  if (!h) return fail(KIFMM_EINVAL, "null handle");
+  if (stage != 0) return fail(KIFMM_EINVAL, "unknown stage");
+  if (!h->has_points || !h->op.ready) return fail(KIFMM_ESTATE, "stage before set_points / precompute");
+  if (level < 2 || level > h->tree.depth) return fail(KIFMM_EINVAL, "level out of range");
+  if (!in_dev || !out_dev || n_vec < 1) return fail(KIFMM_EINVAL, "bad buffers or n_vec");
+  if (h->cfg.m2l != KIFMM_M2L_FFT && h->cfg.prec != KIFMM_FP64)
+    return fail(KIFMM_EUNSUPPORTED, "reduced-precision BLAS/dense M2L not available");
+  return kifmm::device_stage(h, level, in_dev, out_dev, n_vec, (hipStream_t)hip_stream);
+}
+
+kifmm_status kifmm_set_timing(kifmm_handle* h, int32_t on) {
+  if (!h) return fail(KIFMM_EINVAL, "null handle");
+  h->timing = on != 0;
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_timings(const kifmm_handle* h, double* ms, int32_t cap) {
+  if (!h || !ms) return fail(KIFMM_EINVAL, "null argument");
+  if (cap < 5) return fail(KIFMM_EINVAL, "capacity too small");
+  for (int i = 0; i < 5; ++i) ms[i] = h->timings[i];
+  return KIFMM_OK;
+}
+
+}  // extern "C"

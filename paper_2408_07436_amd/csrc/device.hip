@@ -1,0 +1,463 @@
+// Device state and the evaluate pipeline of the kiFMM (Section 2: upward
+// pass P2M + M2M, downward pass M2L + L2L per level, then L2P + P2P).
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace kifmm {
+
+struct DevLevel {
+  int64_t n = 0;
+  double w = 1.0;               // box width
+  int32_t* child = nullptr;     // [n][8]
+  int32_t* halo = nullptr;      // [26][n_{l-1}]
+  // BLAS / dense M2L: pairs grouped by transfer vector
+  std::vector<int64_t> t_offs;  // host, [317]
+  int32_t* t_tgt = nullptr;
+  int32_t* t_src = nullptr;
+};
+
+struct DeviceState {
+  int device = 0;
+  bool fp64 = true;
+  std::vector<void*> allocs;
+  // points and leaves
+  double* src_xyz = nullptr;
+  float* src_xyz_f = nullptr;
+  double* tgt_xyz = nullptr;
+  int64_t* src_perm = nullptr;
+  int64_t* tgt_perm = nullptr;
+  int32_t *src_start = nullptr, *src_end = nullptr, *tgt_start = nullptr, *tgt_end = nullptr;
+  int64_t* near_offs = nullptr;
+  int32_t* near_src = nullptr;
+  double* leaf_centers = nullptr;
+  // operators
+  double* surf = nullptr;
+  int16_t* lat2surf = nullptr;
+  int16_t* surf_lat = nullptr;
+  double *up_V = nullptr, *up_Ut = nullptr, *down_V = nullptr, *down_Ut = nullptr;
+  double *m2m = nullptr, *l2l = nullptr;
+  void* khat = nullptr;
+  void* twiddle = nullptr;
+  double* Ublas = nullptr;   // ns x k
+  double* UblasT = nullptr;  // k x ns
+  std::vector<double*> Ct;   // per t: k x k (not recompressed) or Vbar'^T (kt x k)
+  std::vector<double*> Ub;   // per t: Ubar (k x kt)
+  std::vector<DevLevel> lv;
+  // work buffers
+  int nvec_cap = 0;
+  void* qs = nullptr;
+  std::vector<double*> mult, local;
+  double* phi = nullptr;
+  double* tmp = nullptr;
+  double* tmp2 = nullptr;
+  void* Qhat = nullptr;
+  void* Phat = nullptr;
+  std::vector<void*> work_allocs;
+  hipEvent_t ev[6] = {};
+  bool events = false;
+};
+
+namespace {
+
+template <typename T>
+kifmm_status dalloc(DeviceState* d, T** p, size_t count, bool work = false) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) return fail(KIFMM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  (work ? d->work_allocs : d->allocs).push_back(*p);
+  return KIFMM_OK;
+}
+
+template <typename T>
+kifmm_status upload(DeviceState* d, T** p, const T* host, size_t count) {
+  kifmm_status st = dalloc(d, p, count);
+  if (st != KIFMM_OK) return st;
+  if (count) KIFMM_HIP(hipMemcpy(*p, host, count * sizeof(T), hipMemcpyHostToDevice));
+  return KIFMM_OK;
+}
+
+#define KIFMM_TRY(expr)                     \
+  do {                                      \
+    kifmm_status s_ = (expr);               \
+    if (s_ != KIFMM_OK) return s_;          \
+  } while (0)
+
+#define KIFMM_LAUNCH(expr)                                                                     \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) return fail(KIFMM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+kifmm_status upload_all(kifmm_handle* h) {
+  const Tree& t = h->tree;
+  const Operators& op = h->op;
+  auto* d = new DeviceState();
+  h->dev = d;
+  d->device = h->cfg.device;
+  d->fp64 = h->cfg.prec == KIFMM_FP64;
+  KIFMM_HIP(hipSetDevice(d->device));
+  const int depth = t.depth;
+  const int ns = op.ns;
+
+  KIFMM_TRY(upload(d, &d->src_xyz, t.src_sorted.data(), t.src_sorted.size()));
+  KIFMM_TRY(upload(d, &d->tgt_xyz, t.tgt_sorted.data(), t.tgt_sorted.size()));
+  {
+    std::vector<float> f(t.src_sorted.begin(), t.src_sorted.end());
+    KIFMM_TRY(upload(d, &d->src_xyz_f, f.data(), f.size()));
+  }
+  KIFMM_TRY(upload(d, &d->src_perm, t.src_perm.data(), t.src_perm.size()));
+  KIFMM_TRY(upload(d, &d->tgt_perm, t.tgt_perm.data(), t.tgt_perm.size()));
+  KIFMM_TRY(upload(d, &d->src_start, t.src_start.data(), t.src_start.size()));
+  KIFMM_TRY(upload(d, &d->src_end, t.src_end.data(), t.src_end.size()));
+  KIFMM_TRY(upload(d, &d->tgt_start, t.tgt_start.data(), t.tgt_start.size()));
+  KIFMM_TRY(upload(d, &d->tgt_end, t.tgt_end.data(), t.tgt_end.size()));
+  KIFMM_TRY(upload(d, &d->near_offs, t.near_offs.data(), t.near_offs.size()));
+  KIFMM_TRY(upload(d, &d->near_src, t.near_src.data(), t.near_src.size()));
+  {
+    const Level& L = t.levels[depth];
+    const double w = t.width / std::ldexp(1.0, depth);
+    std::vector<double> c(3 * L.n);
+    for (int64_t i = 0; i < L.n; ++i)
+      for (int k = 0; k < 3; ++k) c[3 * i + k] = t.origin[k] + (L.anchor[3 * i + k] + 0.5) * w;
+    KIFMM_TRY(upload(d, &d->leaf_centers, c.data(), c.size()));
+  }
+
+  KIFMM_TRY(upload(d, &d->surf, op.surf.data(), op.surf.size()));
+  {
+    std::vector<int16_t> sl(op.lattice.begin(), op.lattice.end());
+    KIFMM_TRY(upload(d, &d->surf_lat, sl.data(), sl.size()));
+    std::vector<int16_t> l2s((size_t)op.p * op.p * op.p, -1);
+    for (int s = 0; s < ns; ++s)
+      l2s[((size_t)op.lattice[3 * s] * op.p + op.lattice[3 * s + 1]) * op.p + op.lattice[3 * s + 2]] = (int16_t)s;
+    KIFMM_TRY(upload(d, &d->lat2surf, l2s.data(), l2s.size()));
+  }
+  KIFMM_TRY(upload(d, &d->up_V, op.up_V.data(), op.up_V.size()));
+  KIFMM_TRY(upload(d, &d->up_Ut, op.up_Ut.data(), op.up_Ut.size()));
+  KIFMM_TRY(upload(d, &d->down_V, op.down_V.data(), op.down_V.size()));
+  KIFMM_TRY(upload(d, &d->down_Ut, op.down_Ut.data(), op.down_Ut.size()));
+  KIFMM_TRY(upload(d, &d->m2m, op.m2m.data(), op.m2m.size()));
+  KIFMM_TRY(upload(d, &d->l2l, op.l2l.data(), op.l2l.size()));
+
+  d->lv.resize(depth + 1);
+  for (int l = 0; l <= depth; ++l) {
+    DevLevel& D = d->lv[l];
+    const Level& L = t.levels[l];
+    D.n = L.n;
+    D.w = t.width / std::ldexp(1.0, l);
+    if (l < depth) KIFMM_TRY(upload(d, &D.child, L.child.data(), L.child.size()));
+    if (l >= 2 && h->cfg.m2l == KIFMM_M2L_FFT)
+      KIFMM_TRY(upload(d, &D.halo, L.halo.data(), L.halo.size()));
+    if (l >= 2 && h->cfg.m2l != KIFMM_M2L_FFT) {
+      // pairs grouped by transfer vector (Section 3.2, step 1)
+      D.t_offs.assign(kNumTransfer + 1, 0);
+      for (size_t e = 0; e < L.il_t.size(); ++e) D.t_offs[L.il_t[e] + 1]++;
+      for (int i = 0; i < kNumTransfer; ++i) D.t_offs[i + 1] += D.t_offs[i];
+      std::vector<int32_t> tg(L.il_src.size()), sr(L.il_src.size());
+      std::vector<int64_t> pos(D.t_offs.begin(), D.t_offs.end() - 1);
+      for (int64_t i = 0; i < L.n; ++i)
+        for (int64_t e = L.il_offs[i]; e < L.il_offs[i + 1]; ++e) {
+          const int64_t k = pos[L.il_t[e]]++;
+          tg[k] = (int32_t)i;
+          sr[k] = L.il_src[e];
+        }
+      KIFMM_TRY(upload(d, &D.t_tgt, tg.data(), tg.size()));
+      KIFMM_TRY(upload(d, &D.t_src, sr.data(), sr.size()));
+    }
+  }
+
+  if (h->cfg.m2l == KIFMM_M2L_FFT) {
+    const int n = op.n, F = op.F;
+    // twiddles exp(-2 pi i m / n)
+    std::vector<double> tw(2 * n);
+    for (int m = 0; m < n; ++m) {
+      tw[2 * m] = std::cos(2.0 * M_PI * m / n);
+      tw[2 * m + 1] = -std::sin(2.0 * M_PI * m / n);
+    }
+    // kernel spectra in sibling-cluster frequency order [f][26][8 i][8 j]
+    std::vector<double> kh((size_t)F * 26 * 64 * 2, 0.0);
+    for (int dd = 0; dd < 26; ++dd) {
+      int D[3];
+      direction_vector(dd, D);
+      for (int i = 0; i < 8; ++i)
+        for (int j = 0; j < 8; ++j) {
+          const int tx = 2 * D[0] + (j & 1) - (i & 1);
+          const int ty = 2 * D[1] + ((j >> 1) & 1) - ((i >> 1) & 1);
+          const int tz = 2 * D[2] + ((j >> 2) & 1) - ((i >> 2) & 1);
+          const int it = transfer_index(tx, ty, tz);
+          if (it < 0) continue;  // adjacent pair: zero kernel
+          for (int f = 0; f < F; ++f) {
+            const size_t o = ((((size_t)f * 26 + dd) * 8 + i) * 8 + j) * 2;
+            kh[o] = op.spectra[((size_t)it * F + f) * 2];
+            kh[o + 1] = op.spectra[((size_t)it * F + f) * 2 + 1];
+          }
+        }
+    }
+    if (d->fp64) {
+      double* p1;
+      double* p2;
+      KIFMM_TRY(upload(d, &p1, tw.data(), tw.size()));
+      KIFMM_TRY(upload(d, &p2, kh.data(), kh.size()));
+      d->twiddle = p1;
+      d->khat = p2;
+    } else {
+      std::vector<float> twf(tw.begin(), tw.end()), khf(kh.begin(), kh.end());
+      float* p1;
+      float* p2;
+      KIFMM_TRY(upload(d, &p1, twf.data(), twf.size()));
+      KIFMM_TRY(upload(d, &p2, khf.data(), khf.size()));
+      d->twiddle = p1;
+      d->khat = p2;
+    }
+  } else {
+    const int k = op.k;
+    std::vector<double> Ut((size_t)k * ns);
+    for (int i = 0; i < ns; ++i)
+      for (int j = 0; j < k; ++j) Ut[(size_t)j * ns + i] = op.U[(size_t)i * k + j];
+    KIFMM_TRY(upload(d, &d->Ublas, op.U.data(), op.U.size()));
+    KIFMM_TRY(upload(d, &d->UblasT, Ut.data(), Ut.size()));
+    d->Ct.assign(kNumTransfer, nullptr);
+    d->Ub.assign(kNumTransfer, nullptr);
+    for (int it = 0; it < kNumTransfer; ++it) {
+      if (!op.recompressed) {
+        KIFMM_TRY(upload(d, &d->Ct[it], op.Vbarp[it].data(), op.Vbarp[it].size()));
+      } else {
+        const int r = op.kt[it];
+        std::vector<double> vt((size_t)r * k);  // Vbar'^T, r x k
+        for (int i = 0; i < k; ++i)
+          for (int j = 0; j < r; ++j) vt[(size_t)j * k + i] = op.Vbarp[it][(size_t)i * r + j];
+        KIFMM_TRY(upload(d, &d->Ct[it], vt.data(), vt.size()));
+        KIFMM_TRY(upload(d, &d->Ub[it], op.Ubar[it].data(), op.Ubar[it].size()));
+      }
+    }
+  }
+  for (int e = 0; e < 6; ++e) KIFMM_HIP(hipEventCreate(&d->ev[e]));
+  d->events = true;
+  return KIFMM_OK;
+}
+
+kifmm_status ensure_work(kifmm_handle* h, int nvec) {
+  DeviceState* d = h->dev;
+  if (nvec <= d->nvec_cap) return KIFMM_OK;
+  for (void* p : d->work_allocs) hipFree(p);
+  d->work_allocs.clear();
+  d->nvec_cap = 0;
+  const Tree& t = h->tree;
+  const Operators& op = h->op;
+  const int depth = t.depth;
+  const size_t ns = op.ns;
+  int64_t maxn = 0;
+  for (int l = 0; l <= depth; ++l) maxn = std::max(maxn, t.levels[l].n);
+  const size_t qbytes = (d->fp64 ? 8 : 4);
+  {
+    char* q;
+    KIFMM_TRY(dalloc(d, &q, (size_t)nvec * t.n_src * qbytes, true));
+    d->qs = q;
+  }
+  d->mult.assign(depth + 1, nullptr);
+  d->local.assign(depth + 1, nullptr);
+  for (int l = 2; l <= depth; ++l) {
+    KIFMM_TRY(dalloc(d, &d->mult[l], (size_t)t.levels[l].n * nvec * ns, true));
+    KIFMM_TRY(dalloc(d, &d->local[l], (size_t)t.levels[l].n * nvec * ns, true));
+  }
+  const size_t kmax = std::max<size_t>(ns, (size_t)std::max(op.k, 1));
+  KIFMM_TRY(dalloc(d, &d->phi, (size_t)maxn * nvec * ns, true));
+  KIFMM_TRY(dalloc(d, &d->tmp, (size_t)maxn * nvec * kmax, true));
+  KIFMM_TRY(dalloc(d, &d->tmp2, (size_t)maxn * nvec * kmax, true));
+  if (h->cfg.m2l == KIFMM_M2L_FFT) {
+    int64_t maxc = 0;
+    for (int l = 2; l <= depth; ++l) maxc = std::max(maxc, t.levels[l - 1].n);
+    const size_t cb = d->fp64 ? 16 : 8;
+    char *a, *b;
+    KIFMM_TRY(dalloc(d, &a, (size_t)op.F * maxc * nvec * 8 * cb, true));
+    KIFMM_TRY(dalloc(d, &b, (size_t)op.F * maxc * nvec * 8 * cb, true));
+    d->Qhat = a;
+    d->Phat = b;
+  }
+  d->nvec_cap = nvec;
+  return KIFMM_OK;
+}
+
+// Apply a unit-box pseudo-inverse V (Ut phi) scaled by the box width w.
+kifmm_status pinv_apply(kifmm_handle* h, const double* V, const double* Ut, int r, double w,
+                        const double* in, double* out, int64_t nbox, int nvec, hipStream_t s) {
+  DeviceState* d = h->dev;
+  const int ns = h->op.ns;
+  Gemm64 g1{Ut, r, ns, ns, w, in, ns, 1, nullptr, (int64_t)nvec * ns, ns,
+            d->tmp, r, 1, nullptr, (int64_t)nvec * r, r, nbox, nvec, 0};
+  KIFMM_LAUNCH(launch_gemm64(g1, s));
+  Gemm64 g2{V, ns, r, r, 1.0, d->tmp, r, 1, nullptr, (int64_t)nvec * r, r,
+            out, ns, 1, nullptr, (int64_t)nvec * ns, ns, nbox, nvec, 0};
+  KIFMM_LAUNCH(launch_gemm64(g2, s));
+  return KIFMM_OK;
+}
+
+// M2L check potentials of one level: out[box][v][ns] (overwritten)
+kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, int nvec,
+                       hipStream_t s) {
+  DeviceState* d = h->dev;
+  const Operators& op = h->op;
+  const DevLevel& D = d->lv[l];
+  const int ns = op.ns;
+  if (h->cfg.m2l == KIFMM_M2L_FFT) {
+    const int64_t nc = d->lv[l - 1].n;
+    const int32_t* child = d->lv[l - 1].child;
+    KIFMM_LAUNCH(launch_fft_forward(op.p, d->fp64, in, child, nc, nvec, d->lat2surf, d->twiddle,
+                                    d->Qhat, s));
+    KIFMM_LAUNCH(launch_hadamard(d->fp64, op.F, d->khat, d->Qhat, D.halo, nc, nvec, d->Phat, s));
+    const double scale = 1.0 / ((double)op.n * op.n * op.n * D.w);
+    KIFMM_LAUNCH(launch_fft_inverse(op.p, d->fp64, d->Phat, child, nc, nvec, d->surf_lat,
+                                    d->twiddle, scale, out, s));
+    return KIFMM_OK;
+  }
+  // dense / compressed M2L, one product per transfer vector (Section 3.2)
+  const int k = op.k;
+  const bool dense = h->cfg.m2l == KIFMM_M2L_DENSE;
+  const double* q = in;
+  double* acc = out;
+  if (!dense) {
+    // compressed multipoles  Q~ = S^T Q  (S = U)
+    Gemm64 g{d->UblasT, k, ns, ns, 1.0, in, ns, 1, nullptr, (int64_t)nvec * ns, ns,
+             d->tmp, k, 1, nullptr, (int64_t)nvec * k, k, D.n, nvec, 0};
+    KIFMM_LAUNCH(launch_gemm64(g, s));
+    q = d->tmp;
+    acc = d->tmp2;
+  }
+  KIFMM_HIP(hipMemsetAsync(acc, 0, sizeof(double) * (size_t)D.n * nvec * k, s));
+  const double inv_w = 1.0 / D.w;
+  for (int it = 0; it < kNumTransfer; ++it) {
+    const int64_t a = D.t_offs[it], b = D.t_offs[it + 1];
+    if (b == a) continue;
+    if (!op.recompressed) {
+      Gemm64 g{d->Ct[it], k, k, k, inv_w, q, k, 1, D.t_src + a, (int64_t)nvec * k, k,
+               acc, k, 1, D.t_tgt + a, (int64_t)nvec * k, k, b - a, nvec, 1};
+      KIFMM_LAUNCH(launch_gemm64(g, s));
+    } else {
+      const int r = op.kt[it];
+      // xi = Vbar'^T q~[src]  (r x cols, contiguous), then acc[tgt] += Ubar xi
+      Gemm64 g1{d->Ct[it], r, k, k, inv_w, q, k, 1, D.t_src + a, (int64_t)nvec * k, k,
+                out, r, 1, nullptr, (int64_t)nvec * r, r, b - a, nvec, 0};
+      KIFMM_LAUNCH(launch_gemm64(g1, s));
+      Gemm64 g2{d->Ub[it], k, r, r, 1.0, out, r, 1, nullptr, (int64_t)nvec * r, r,
+                acc, k, 1, D.t_tgt + a, (int64_t)nvec * k, k, b - a, nvec, 1};
+      KIFMM_LAUNCH(launch_gemm64(g2, s));
+    }
+  }
+  if (!dense) {
+    // check potentials  Phi = U Phi~
+    Gemm64 g{d->Ublas, ns, k, k, 1.0, acc, k, 1, nullptr, (int64_t)nvec * k, k,
+             out, ns, 1, nullptr, (int64_t)nvec * ns, ns, D.n, nvec, 0};
+    KIFMM_LAUNCH(launch_gemm64(g, s));
+  }
+  return KIFMM_OK;
+}
+
+}  // namespace
+
+void destroy_device(DeviceState* d) {
+  if (!d) return;
+  hipSetDevice(d->device);
+  if (d->events)
+    for (auto& e : d->ev) hipEventDestroy(e);
+  for (void* p : d->work_allocs) hipFree(p);
+  for (void* p : d->allocs) hipFree(p);
+  delete d;
+}
+
+kifmm_status device_ready(kifmm_handle* h, int nvec) {
+  if (!h->dev) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0)
+      return fail(KIFMM_EDEVICE, "no HIP device available");
+    if (h->cfg.device < 0 || h->cfg.device >= count)
+      return fail(KIFMM_EINVAL, "device ordinal out of range");
+    kifmm_status st = upload_all(h);
+    if (st != KIFMM_OK) {
+      destroy_device(h->dev);
+      h->dev = nullptr;
+      return st;
+    }
+  }
+  KIFMM_HIP(hipSetDevice(h->dev->device));
+  return ensure_work(h, nvec);
+}
+
+kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nvec, void* phi,
+                             int64_t ldphi, hipStream_t s) {
+  KIFMM_TRY(device_ready(h, nvec));
+  DeviceState* d = h->dev;
+  const Tree& t = h->tree;
+  const Operators& op = h->op;
+  const int depth = t.depth, ns = op.ns;
+  const bool timed = h->timing;
+  if (timed) KIFMM_HIP(hipEventRecord(d->ev[0], s));
+
+  KIFMM_LAUNCH(launch_gather(q, ldq, d->src_perm, t.n_src, nvec, d->fp64, d->qs, s));
+  // upward pass
+  const DevLevel& leaf = d->lv[depth];
+  KIFMM_LAUNCH(launch_p2m(d->src_xyz, d->qs, d->fp64, t.n_src, d->src_start, d->src_end,
+                          d->leaf_centers, leaf.n, d->surf, op.ao * 0.5 * leaf.w, ns, nvec, d->phi, s));
+  KIFMM_TRY(pinv_apply(h, d->up_V, d->up_Ut, op.r_up, leaf.w, d->phi, d->mult[depth], leaf.n, nvec, s));
+  for (int l = depth - 1; l >= 2; --l) {
+    const DevLevel& D = d->lv[l];
+    Gemm64 g{d->m2m, ns, 8 * ns, 8 * ns, 1.0 / D.w, d->mult[l + 1], ns, 8, D.child,
+             (int64_t)nvec * ns, ns, d->phi, ns, 1, nullptr, (int64_t)nvec * ns, ns, D.n, nvec, 0};
+    KIFMM_LAUNCH(launch_gemm64(g, s));
+    KIFMM_TRY(pinv_apply(h, d->up_V, d->up_Ut, op.r_up, D.w, d->phi, d->mult[l], D.n, nvec, s));
+  }
+  if (timed) KIFMM_HIP(hipEventRecord(d->ev[1], s));
+  // downward pass
+  float m2l_ms = 0.f;
+  for (int l = 2; l <= depth; ++l) {
+    const DevLevel& D = d->lv[l];
+    if (timed) KIFMM_HIP(hipEventRecord(d->ev[4], s));
+    KIFMM_TRY(m2l_level(h, l, d->mult[l], d->phi, nvec, s));
+    if (timed) {
+      KIFMM_HIP(hipEventRecord(d->ev[5], s));
+      KIFMM_HIP(hipEventSynchronize(d->ev[5]));
+      float ms = 0.f;
+      KIFMM_HIP(hipEventElapsedTime(&ms, d->ev[4], d->ev[5]));
+      m2l_ms += ms;
+    }
+    if (l >= 3) {
+      const DevLevel& P = d->lv[l - 1];
+      Gemm64 g{d->l2l, 8 * ns, ns, ns, 1.0 / P.w, d->local[l - 1], ns, 1, nullptr,
+               (int64_t)nvec * ns, ns, d->phi, ns, 8, P.child, (int64_t)nvec * ns, ns, P.n, nvec, 1};
+      KIFMM_LAUNCH(launch_gemm64(g, s));
+    }
+    KIFMM_TRY(pinv_apply(h, d->down_V, d->down_Ut, op.r_down, D.w, d->phi, d->local[l], D.n, nvec, s));
+  }
+  if (timed) KIFMM_HIP(hipEventRecord(d->ev[2], s));
+  KIFMM_LAUNCH(launch_leaf_eval(d->tgt_xyz, d->src_xyz, d->src_xyz_f, d->qs, d->fp64, t.n_src,
+                                d->tgt_start, d->tgt_end, d->src_start, d->src_end, d->near_offs,
+                                d->near_src, d->leaf_centers, leaf.n, d->surf, op.ao * 0.5 * leaf.w, ns,
+                                d->local[depth], d->tgt_perm, phi, ldphi, nvec, s));
+  if (timed) {
+    KIFMM_HIP(hipEventRecord(d->ev[3], s));
+    KIFMM_HIP(hipEventSynchronize(d->ev[3]));
+    float a = 0, b = 0, c = 0, tot = 0;
+    KIFMM_HIP(hipEventElapsedTime(&a, d->ev[0], d->ev[1]));
+    KIFMM_HIP(hipEventElapsedTime(&b, d->ev[1], d->ev[2]));
+    KIFMM_HIP(hipEventElapsedTime(&c, d->ev[2], d->ev[3]));
+    KIFMM_HIP(hipEventElapsedTime(&tot, d->ev[0], d->ev[3]));
+    h->timings[0] = a;
+    h->timings[1] = m2l_ms;
+    h->timings[2] = b - m2l_ms;
+    h->timings[3] = c;
+    h->timings[4] = tot;
+  }
+  return KIFMM_OK;
+}
+
+kifmm_status device_stage(kifmm_handle* h, int level, const void* in, void* out, int nvec,
+                          hipStream_t s) {
+  KIFMM_TRY(device_ready(h, nvec));
+  return m2l_level(h, level, (const double*)in, (double*)out, nvec, s);
+}
+
+}  // namespace kifmm

@@ -1,0 +1,120 @@
+// Internal declarations of the kiFMM library (host side and kernel launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/kifmm.h"
+
+namespace kifmm {
+
+// ---- error plumbing ------------------------------------------------------
+struct Error {
+  kifmm_status code;
+  std::string msg;
+};
+void set_error(const std::string& msg);
+kifmm_status fail(kifmm_status code, const std::string& msg);
+
+#define KIFMM_HIP(expr)                                                               \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return ::kifmm::fail(KIFMM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kNumTransfer = 316;   // offsets in [-3,3]^3 with max |t_i| >= 2
+constexpr int kNumDirections = 26;  // neighbour directions of a sibling cluster
+
+// ---- tree ---------------------------------------------------------------
+struct Level {
+  int64_t n = 0;
+  std::vector<uint64_t> keys;     // sorted Morton keys
+  std::vector<int32_t> anchor;    // [n][3]
+  std::vector<int32_t> parent;    // index at level-1 (-1 at level 0)
+  std::vector<int32_t> child;     // [n][8] index at level+1 or -1 (empty at the leaf level)
+  // interaction lists (level >= 2), CSR over targets
+  std::vector<int64_t> il_offs;
+  std::vector<int32_t> il_src;
+  std::vector<int16_t> il_t;
+  // FFT sibling clusters of this level are the boxes of level-1; halo[d][c]
+  // is the cluster in direction d of cluster c (or -1)
+  std::vector<int32_t> halo;      // [26][n_{level-1}]
+};
+
+struct Tree {
+  int depth = 0;
+  double origin[3] = {0, 0, 0};
+  double width = 1.0;
+  int64_t n_src = 0, n_tgt = 0;
+  std::vector<double> src_sorted, tgt_sorted;  // [n][3] in sorted order
+  std::vector<int64_t> src_perm, tgt_perm;     // sorted position -> original index
+  std::vector<Level> levels;                   // 0..depth
+  std::vector<int32_t> src_start, src_end, tgt_start, tgt_end;  // per leaf
+  std::vector<int64_t> near_offs;              // per leaf CSR
+  std::vector<int32_t> near_src;
+};
+
+// Builds the tree; returns KIFMM_OK or an error (sets message).
+kifmm_status build_tree(Tree& t, int depth, const double origin[3], double width, const double* src,
+                        int64_t n_src, const double* tgt, int64_t n_tgt);
+
+// Transfer-vector helpers.
+int transfer_index(int tx, int ty, int tz);  // -1 if not one of the 316
+void transfer_vector(int idx, int t[3]);
+void direction_vector(int d, int D[3]);      // 26 directions, lexicographic, 0 skipped
+
+// ---- dense linear algebra (host, FP64) -----------------------------------
+// A = U diag(s) V^T for A (m x n) row-major; U (m x r), s (r), V (n x r) with
+// r = min(m, n), singular values descending.  One-sided Jacobi.
+bool svd(const double* A, int m, int n, std::vector<double>& U, std::vector<double>& s,
+         std::vector<double>& V);
+// Left singular vectors and values of a wide matrix A (m x n, m << n):
+// QR of A^T then an SVD of the small factor.
+bool svd_left_wide(const double* A, int m, int n, std::vector<double>& U, std::vector<double>& s);
+
+// ---- operators ------------------------------------------------------------
+struct Operators {
+  int p = 0, ns = 0, F = 0, n = 0;  // order, surface points, spectrum length, grid size 2p
+  double ai = 1.05, ao = 2.95;
+  std::vector<double> surf;         // [ns][3] unit offsets -1 + 2 i/(p-1)
+  std::vector<int32_t> lattice;     // [ns][3] integer positions
+  // pseudo-inverses of the unit box (width 1), V (ns x r) and Ut (r x ns)
+  int r_up = 0, r_down = 0;
+  std::vector<double> up_V, up_Ut, down_V, down_Ut;
+  // M2M: [ns] x [8 ns] = [K_0 .. K_7] for a parent of width 1
+  std::vector<double> m2m;
+  // L2L: [8 ns] x [ns] = [L_0; ..; L_7] for a parent of width 1
+  std::vector<double> l2l;
+  // FFT: kernel spectra of the unit box, [316][F] complex (re, im)
+  std::vector<double> spectra;
+  // BLAS / dense M2L of the unit box
+  int k = 0;                         // compressed rank (= ns for dense)
+  std::vector<double> U;             // ns x k (row-major)
+  std::vector<int> kt;               // per t rank (k when not recompressed)
+  std::vector<std::vector<double>> Ubar, Vbarp;  // per t: k x kt (row-major)
+  bool recompressed = false;
+  bool ready = false;
+};
+
+kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg);
+
+// ---- device side -------------------------------------------------------------
+struct DeviceState;  // defined in device.hip
+void destroy_device(DeviceState* d);
+
+}  // namespace kifmm
+
+struct kifmm_handle {
+  kifmm_config cfg;
+  kifmm::Tree tree;
+  kifmm::Operators op;
+  bool has_points = false;
+  kifmm::DeviceState* dev = nullptr;
+  bool timing = false;
+  double timings[5] = {0, 0, 0, 0, 0};
+};

@@ -1,0 +1,393 @@
+// FFT-M2L on gfx950 (Appendix A.1-A.2 of arXiv 2408.07436).
+//
+// 1. fft_forward: the upward-equivalent densities of each box sit on the
+//    (2p)^3 convolution grid at their lattice positions (zeros elsewhere).
+//    A real-to-complex 3D DFT that skips the zero planes gives (2p)^2 (p+1)
+//    coefficients per box, written in frequency order [f][cluster, v][child]
+//    so that the eight siblings of a cluster are contiguous per frequency.
+// 2. hadamard: for every frequency f and target cluster, the 8 x 8 complex
+//    products against the kernel spectra of the 26 source clusters of its
+//    halo, summed.  Per frequency this is a real GEMM
+//       [rows = (cluster, v)] x [K = 26 dirs x 8 sources x (re, im)]
+//         x [N = 8 targets x (re, im)],
+//    with the A operand gathered through the halo table; it runs on
+//    v_mfma_f32_16x16x4f32 (FP32) or v_mfma_f64_16x16x4f64 (FP64).
+// 3. fft_inverse: complex inverse DFTs along x and y, then the c2r step along
+//    z, evaluated only at the check-surface lattice points.
+#include "kernels.h"
+
+namespace kifmm {
+
+namespace {
+
+template <typename T> struct C2T;
+template <> struct C2T<float> { using type = float2; };
+template <> struct C2T<double> { using type = double2; };
+
+template <typename C2>
+__device__ inline C2 cmul(C2 a, C2 b) {
+  C2 r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+// a * conj(b)
+template <typename C2>
+__device__ inline C2 cmulc(C2 a, C2 b) {
+  C2 r;
+  r.x = a.x * b.x + a.y * b.y;
+  r.y = a.y * b.x - a.x * b.y;
+  return r;
+}
+
+constexpr int kFftThreads = 256;
+
+template <typename T, int P, int ITEMS>
+__global__ __launch_bounds__(kFftThreads) void fft_forward_kernel(
+    const double* __restrict__ M, const int32_t* __restrict__ child, int64_t n_rows, int nvec,
+    const int16_t* __restrict__ lat2surf, const typename C2T<T>::type* __restrict__ tw,
+    typename C2T<T>::type* __restrict__ Qhat) {
+  using C2 = typename C2T<T>::type;
+  constexpr int N = 2 * P, H = P + 1, NS = 6 * (P - 1) * (P - 1) + 2;
+  __shared__ C2 w[N];
+  __shared__ int16_t l2s[P * P * P];
+  __shared__ T sv[ITEMS][NS];
+  __shared__ C2 a1[ITEMS][P][P][H];
+  const int tid = threadIdx.x;
+  const int64_t g0 = (int64_t)blockIdx.x * ITEMS;  // first (row, child) item
+  for (int t = tid; t < N; t += kFftThreads) w[t] = tw[t];
+  for (int t = tid; t < P * P * P; t += kFftThreads) l2s[t] = lat2surf[t];
+  for (int idx = tid; idx < ITEMS * NS; idx += kFftThreads) {
+    const int it = idx / NS, s = idx % NS;
+    const int64_t g = g0 + it, row = g / 8;
+    double val = 0.0;
+    if (row < n_rows) {
+      const int64_t c = row / nvec;
+      const int v = (int)(row - c * nvec);
+      const int32_t box = child[c * 8 + (g % 8)];
+      if (box >= 0) val = M[((int64_t)box * nvec + v) * NS + s];
+    }
+    sv[it][s] = (T)val;
+  }
+  __syncthreads();
+  // z: real -> complex, kz in [0, p]
+  for (int idx = tid; idx < ITEMS * P * P * H; idx += kFftThreads) {
+    const int it = idx / (P * P * H);
+    const int rem = idx % (P * P * H);
+    const int x = rem / (P * H), y = (rem / H) % P, kz = rem % H;
+    C2 acc;
+    acc.x = T(0);
+    acc.y = T(0);
+#pragma unroll
+    for (int z = 0; z < P; ++z) {
+      const int s = l2s[(x * P + y) * P + z];
+      if (s >= 0) {
+        const T d = sv[it][s];
+        const C2 wz = w[(kz * z) % N];
+        acc.x += d * wz.x;
+        acc.y += d * wz.y;
+      }
+    }
+    a1[it][x][y][kz] = acc;
+  }
+  __syncthreads();
+  // y then x; each task owns one (ky, kz) column of one item
+  for (int idx = tid; idx < ITEMS * N * H; idx += kFftThreads) {
+    const int it = idx % ITEMS, col = idx / ITEMS;
+    const int ky = col / H, kz = col % H;
+    const int64_t g = g0 + it, row = g / 8;
+    if (row >= n_rows) continue;
+    C2 cx[P];
+#pragma unroll
+    for (int x = 0; x < P; ++x) {
+      C2 acc;
+      acc.x = T(0);
+      acc.y = T(0);
+#pragma unroll
+      for (int y = 0; y < P; ++y) {
+        const C2 t = cmul(a1[it][x][y][kz], w[(ky * y) % N]);
+        acc.x += t.x;
+        acc.y += t.y;
+      }
+      cx[x] = acc;
+    }
+#pragma unroll
+    for (int kx = 0; kx < N; ++kx) {
+      C2 acc;
+      acc.x = T(0);
+      acc.y = T(0);
+#pragma unroll
+      for (int x = 0; x < P; ++x) {
+        const C2 t = cmul(cx[x], w[(kx * x) % N]);
+        acc.x += t.x;
+        acc.y += t.y;
+      }
+      const int64_t f = ((int64_t)kx * N + ky) * H + kz;
+      Qhat[(f * n_rows + row) * 8 + (g % 8)] = acc;
+    }
+  }
+}
+
+template <typename T, int P, int ITEMS>
+__global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(
+    const typename C2T<T>::type* __restrict__ Phat, const int32_t* __restrict__ child,
+    int64_t n_rows, int nvec, const int16_t* __restrict__ surf_lat,
+    const typename C2T<T>::type* __restrict__ tw, double scale, double* __restrict__ out) {
+  using C2 = typename C2T<T>::type;
+  constexpr int N = 2 * P, H = P + 1, NS = 6 * (P - 1) * (P - 1) + 2;
+  __shared__ C2 w[N];
+  __shared__ C2 b2[ITEMS][P][N][H];
+  __shared__ C2 b1[ITEMS][P][P][H];
+  const int tid = threadIdx.x;
+  const int64_t g0 = (int64_t)blockIdx.x * ITEMS;
+  for (int t = tid; t < N; t += kFftThreads) w[t] = tw[t];
+  __syncthreads();
+  // x: complex inverse, only x in [0, p) is kept
+  for (int idx = tid; idx < ITEMS * N * H; idx += kFftThreads) {
+    const int it = idx % ITEMS, col = idx / ITEMS;
+    const int ky = col / H, kz = col % H;
+    const int64_t g = g0 + it, row = g / 8;
+    C2 v[N];
+#pragma unroll
+    for (int kx = 0; kx < N; ++kx) {
+      const int64_t f = ((int64_t)kx * N + ky) * H + kz;
+      if (row < n_rows) {
+        v[kx] = Phat[(f * n_rows + row) * 8 + (g % 8)];
+      } else {
+        v[kx].x = T(0);
+        v[kx].y = T(0);
+      }
+    }
+#pragma unroll
+    for (int x = 0; x < P; ++x) {
+      C2 acc;
+      acc.x = T(0);
+      acc.y = T(0);
+#pragma unroll
+      for (int kx = 0; kx < N; ++kx) {
+        const C2 t = cmulc(v[kx], w[(kx * x) % N]);
+        acc.x += t.x;
+        acc.y += t.y;
+      }
+      b2[it][x][ky][kz] = acc;
+    }
+  }
+  __syncthreads();
+  // y: complex inverse, y in [0, p)
+  for (int idx = tid; idx < ITEMS * P * P * H; idx += kFftThreads) {
+    const int it = idx / (P * P * H);
+    const int rem = idx % (P * P * H);
+    const int x = rem / (P * H), y = (rem / H) % P, kz = rem % H;
+    C2 acc;
+    acc.x = T(0);
+    acc.y = T(0);
+#pragma unroll
+    for (int ky = 0; ky < N; ++ky) {
+      const C2 t = cmulc(b2[it][x][ky][kz], w[(ky * y) % N]);
+      acc.x += t.x;
+      acc.y += t.y;
+    }
+    b1[it][x][y][kz] = acc;
+  }
+  __syncthreads();
+  // z: complex -> real on the check-surface points only
+  for (int idx = tid; idx < ITEMS * NS; idx += kFftThreads) {
+    const int it = idx / NS, s = idx % NS;
+    const int64_t g = g0 + it, row = g / 8;
+    if (row >= n_rows) continue;
+    const int64_t c = row / nvec;
+    const int v = (int)(row - c * nvec);
+    const int32_t box = child[c * 8 + (g % 8)];
+    if (box < 0) continue;
+    const int x = surf_lat[3 * s], y = surf_lat[3 * s + 1], z = surf_lat[3 * s + 2];
+    T val = b1[it][x][y][0].x + ((z & 1) ? -b1[it][x][y][P].x : b1[it][x][y][P].x);
+    T acc = T(0);
+#pragma unroll
+    for (int kz = 1; kz < P; ++kz) acc += cmulc(b1[it][x][y][kz], w[(kz * z) % N]).x;
+    val += T(2) * acc;
+    out[((int64_t)box * nvec + v) * NS + s] = scale * (double)val;
+  }
+}
+
+// ---- Hadamard products on MFMA ---------------------------------------------
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ inline v4f mfma16(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// accumulator row of element i of lane group g (measured lane layouts)
+__device__ inline int out_row(float, int g, int i) { return 4 * g + i; }
+__device__ inline int out_row(double, int g, int i) { return g + 4 * i; }
+
+template <typename T> struct V4T;
+template <> struct V4T<float> { using type = v4f; };
+template <> struct V4T<double> { using type = v4d; };
+
+constexpr int kHadThreads = 256;
+
+// Workgroup = one frequency x a chunk of 16-row tiles; four waves share the
+// frequency's B operand (the 416 x 16 real form of its 26 x 8 x 8 complex
+// kernel coefficients), staged in LDS in the lanes' operand order.
+template <typename T>
+__global__ __launch_bounds__(kHadThreads) void hadamard_kernel(
+    const typename C2T<T>::type* __restrict__ Khat, const T* __restrict__ Qhat,
+    const int32_t* __restrict__ halo, int64_t n_c, int nvec, int64_t n_rows, int n_chunks,
+    int tiles_per_wave, int64_t total_blocks, T* __restrict__ Phat) {
+  using C2 = typename C2T<T>::type;
+  using V4 = typename V4T<T>::type;
+  __shared__ T Bl[26][64][4];
+  const int64_t b = blockIdx.x;
+  const int64_t per_xcd = (total_blocks + 7) / 8;
+  const int64_t logical = (b % 8) * per_xcd + b / 8;  // consecutive work per XCD
+  if (logical >= total_blocks) return;
+  const int64_t f = logical / n_chunks;
+  const int chunk = (int)(logical % n_chunks);
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < 26 * 64 * 4; idx += kHadThreads) {
+    const int d = idx / 256, lane = (idx / 4) % 64, s = idx % 4;
+    const int n = lane % 16, g = lane / 16;
+    const int i = n / 2, cout = n % 2, j = 2 * g + s / 2, cin = s % 2;
+    const C2 K = Khat[((f * 26 + d) * 8 + i) * 8 + j];
+    T val;
+    if (cin == 0)
+      val = cout == 0 ? K.x : K.y;
+    else
+      val = cout == 0 ? -K.y : K.x;
+    Bl[d][lane][s] = val;
+  }
+  __syncthreads();
+  const int wave = tid / 64, lane = tid % 64;
+  const int rl = lane % 16, g = lane / 16;
+  const int64_t fbase = f * n_rows;
+  for (int t = 0; t < tiles_per_wave; ++t) {
+    const int64_t tile = ((int64_t)chunk * tiles_per_wave + t) * 4 + wave;
+    const int64_t row0 = tile * 16;
+    if (row0 >= n_rows) break;
+    const int64_t row = row0 + rl;
+    const bool valid = row < n_rows;
+    const int64_t c = valid ? row / nvec : 0;
+    const int v = valid ? (int)(row - c * nvec) : 0;
+    V4 acc;
+    acc[0] = acc[1] = acc[2] = acc[3] = T(0);
+#pragma unroll 2
+    for (int d = 0; d < 26; ++d) {
+      const int32_t nb = valid ? halo[(int64_t)d * n_c + c] : -1;
+      T a[4] = {T(0), T(0), T(0), T(0)};
+      if (nb >= 0) {
+        const T* src = Qhat + ((fbase + (int64_t)nb * nvec + v) * 16 + 4 * g);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) a[s] = src[s];
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc = mfma16(a[s], Bl[d][lane][s], acc);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = row0 + out_row(T(0), g, i);
+      if (r < n_rows) Phat[(fbase + r) * 16 + rl] = acc[i];
+    }
+  }
+}
+
+template <typename T, int P, int ITEMS>
+hipError_t fwd_launch(const double* M, const int32_t* child, int64_t n_rows, int nvec,
+                      const int16_t* lat2surf, const void* tw, void* Qhat, hipStream_t s) {
+  using C2 = typename C2T<T>::type;
+  const int64_t items = n_rows * 8;
+  const unsigned grid = (unsigned)((items + ITEMS - 1) / ITEMS);
+  fft_forward_kernel<T, P, ITEMS><<<grid, kFftThreads, 0, s>>>(M, child, n_rows, nvec, lat2surf,
+                                                             (const C2*)tw, (C2*)Qhat);
+  return hipGetLastError();
+}
+
+template <typename T, int P, int ITEMS>
+hipError_t inv_launch(const void* Phat, const int32_t* child, int64_t n_rows, int nvec,
+                      const int16_t* surf_lat, const void* tw, double scale, double* out,
+                      hipStream_t s) {
+  using C2 = typename C2T<T>::type;
+  const int64_t items = n_rows * 8;
+  const unsigned grid = (unsigned)((items + ITEMS - 1) / ITEMS);
+  fft_inverse_kernel<T, P, ITEMS><<<grid, kFftThreads, 0, s>>>((const C2*)Phat, child, n_rows, nvec,
+                                                             surf_lat, (const C2*)tw, scale, out);
+  return hipGetLastError();
+}
+
+// items per workgroup, sized so the LDS stays within 64 KiB
+template <typename T, int P> struct Items {
+  static constexpr int bytes = sizeof(T) * 2;
+  static constexpr int per = P * (2 * P) * (P + 1) * bytes + P * P * (P + 1) * bytes;  // inverse
+  static constexpr int raw = 49152 / per;
+  static constexpr int value = raw >= 16 ? 16 : raw >= 8 ? 8 : raw >= 4 ? 4 : raw >= 2 ? 2 : 1;
+};
+
+template <typename T>
+hipError_t fwd_dispatch(int p, const double* M, const int32_t* child, int64_t n_rows, int nvec,
+                        const int16_t* l2s, const void* tw, void* Q, hipStream_t s) {
+  switch (p) {
+#define KIFMM_FWD(PP) \
+  case PP: return fwd_launch<T, PP, Items<T, PP>::value>(M, child, n_rows, nvec, l2s, tw, Q, s);
+    KIFMM_FWD(2) KIFMM_FWD(3) KIFMM_FWD(4) KIFMM_FWD(5) KIFMM_FWD(6) KIFMM_FWD(7) KIFMM_FWD(8)
+#undef KIFMM_FWD
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t inv_dispatch(int p, const void* Ph, const int32_t* child, int64_t n_rows, int nvec,
+                        const int16_t* sl, const void* tw, double scale, double* out, hipStream_t s) {
+  switch (p) {
+#define KIFMM_INV(PP) \
+  case PP: return inv_launch<T, PP, Items<T, PP>::value>(Ph, child, n_rows, nvec, sl, tw, scale, out, s);
+    KIFMM_INV(2) KIFMM_INV(3) KIFMM_INV(4) KIFMM_INV(5) KIFMM_INV(6) KIFMM_INV(7) KIFMM_INV(8)
+#undef KIFMM_INV
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fft_forward(int p, bool fp64, const double* M, const int32_t* child,
+                              int64_t n_clusters, int nvec, const int16_t* lat2surf,
+                              const void* twiddle, void* Qhat, hipStream_t stream) {
+  const int64_t n_rows = n_clusters * nvec;
+  if (n_rows == 0) return hipSuccess;
+  return fp64 ? fwd_dispatch<double>(p, M, child, n_rows, nvec, lat2surf, twiddle, Qhat, stream)
+              : fwd_dispatch<float>(p, M, child, n_rows, nvec, lat2surf, twiddle, Qhat, stream);
+}
+
+hipError_t launch_fft_inverse(int p, bool fp64, const void* Phat, const int32_t* child,
+                              int64_t n_clusters, int nvec, const int16_t* surf_lat,
+                              const void* twiddle, double scale, double* out, hipStream_t stream) {
+  const int64_t n_rows = n_clusters * nvec;
+  if (n_rows == 0) return hipSuccess;
+  return fp64 ? inv_dispatch<double>(p, Phat, child, n_rows, nvec, surf_lat, twiddle, scale, out, stream)
+              : inv_dispatch<float>(p, Phat, child, n_rows, nvec, surf_lat, twiddle, scale, out, stream);
+}
+
+hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
+                           const int32_t* halo, int64_t n_clusters, int nvec, void* Phat,
+                           hipStream_t stream) {
+  const int64_t n_rows = n_clusters * nvec;
+  if (n_rows == 0) return hipSuccess;
+  const int64_t tiles = (n_rows + 15) / 16;
+  const int tpw = tiles >= 256 ? 8 : tiles >= 64 ? 4 : 1;
+  const int n_chunks = (int)((tiles + 4 * tpw - 1) / (4 * tpw));
+  const int64_t total = (int64_t)F * n_chunks;
+  const unsigned grid = (unsigned)(8 * ((total + 7) / 8));
+  if (fp64)
+    hadamard_kernel<double><<<grid, kHadThreads, 0, stream>>>(
+        (const double2*)Khat, (const double*)Qhat, halo, n_clusters, nvec, n_rows, n_chunks, tpw,
+        total, (double*)Phat);
+  else
+    hadamard_kernel<float><<<grid, kHadThreads, 0, stream>>>(
+        (const float2*)Khat, (const float*)Qhat, halo, n_clusters, nvec, n_rows, n_chunks, tpw,
+        total, (float*)Phat);
+  return hipGetLastError();
+}
+
+}  // namespace kifmm

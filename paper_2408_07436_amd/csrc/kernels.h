@@ -1,0 +1,62 @@
+// Launchers of the gfx950 kernels.  All pointers are device pointers; every
+// launcher enqueues on `stream` and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace kifmm {
+
+// qs[v][i] = q[v * ldq + perm[i]] (gather of charges into sorted order)
+hipError_t launch_gather(const void* q, int64_t ldq, const int64_t* perm, int64_t n, int nvec,
+                         bool fp64, void* qs, hipStream_t stream);
+
+// P2M check potentials at the leaves (Section 2.1.1):
+// phi[leaf][v][i] = sum_{y in leaf} K(c + ar s_i, y) q_y,v  (FP64 result)
+hipError_t launch_p2m(const double* src_xyz, const void* qs, bool q_fp64, int64_t n_src,
+                      const int32_t* start, const int32_t* end, const double* centers, int64_t n_leaf,
+                      const double* surf, double ar, int ns, int nvec, double* phi,
+                      hipStream_t stream);
+
+// Leaf evaluation: L2P (FP64) + P2P over the near field (precision of the
+// charges), written to the caller's target order.
+hipError_t launch_leaf_eval(const double* tgt_xyz, const double* src_xyz, const float* src_xyz_f,
+                            const void* qs, bool fp64, int64_t n_src, const int32_t* tstart,
+                            const int32_t* tend, const int32_t* sstart, const int32_t* send,
+                            const int64_t* near_offs, const int32_t* near_src,
+                            const double* centers, int64_t n_leaf, const double* surf, double ar,
+                            int ns, const double* local, const int64_t* tgt_perm, void* phi,
+                            int64_t ldphi, int nvec, hipStream_t stream);
+
+// FP64 GEMM with gathered columns: C(:, col) = alpha * A * B(:, col) (+ C).
+// Columns are (box, v) pairs, col = box * nvec + v.  B's row k of column
+// (b, v) lives at B[bb * b_box + v * b_vec + k % ks] with
+// bb = bmap ? bmap[b * nsegk + k / ks] : b  (bb < 0 reads zero); C's row m
+// of column (b, v) at C[cb * c_box + v * c_vec + m % ms] with
+// cb = cmap ? cmap[b * nsegm + m / ms] : b  (cb < 0 is skipped).
+struct Gemm64 {
+  const double* A; int M; int K; int lda; double alpha;
+  const double* B; int ks; int nsegk; const int32_t* bmap; int64_t b_box; int b_vec;
+  double* C; int ms; int nsegm; const int32_t* cmap; int64_t c_box; int c_vec;
+  int64_t nbox; int nvec; int accumulate;
+};
+hipError_t launch_gemm64(const Gemm64& g, hipStream_t stream);
+
+// ---- FFT-M2L (Appendix A.1) ----------------------------------------------
+// Forward: densities M[box][v][ns] (FP64) of the children of each cluster
+// -> spectra Qhat[f][row][8] (complex, T), row = cluster * nvec + v.
+hipError_t launch_fft_forward(int p, bool fp64, const double* M, const int32_t* child,
+                              int64_t n_clusters, int nvec, const int16_t* lat2surf,
+                              const void* twiddle, void* Qhat, hipStream_t stream);
+// Hadamard products by sibling cluster: Phat[f][row][i] = sum_d sum_j
+// Khat[f][d][i][j] Qhat[f][halo[d][c] * nvec + v][j].
+hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
+                           const int32_t* halo, int64_t n_clusters, int nvec, void* Phat,
+                           hipStream_t stream);
+// Inverse: spectra -> check potentials out[box][v][s] = scale * phi (FP64).
+hipError_t launch_fft_inverse(int p, bool fp64, const void* Phat, const int32_t* child,
+                              int64_t n_clusters, int nvec, const int16_t* surf_lat,
+                              const void* twiddle, double scale, double* out, hipStream_t stream);
+
+}  // namespace kifmm

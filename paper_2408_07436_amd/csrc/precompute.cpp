@@ -1,0 +1,250 @@
+// FP64 host precomputation of the kiFMM operators for a box of unit width.
+//
+// Surfaces and pseudo-inverses follow Section 2.1.1 of arXiv 2408.07436,
+// M2M/L2L the translation operators of Section 2.2, FFT kernel spectra the
+// convolution grid of Appendix A.1 (real-kernel halving of Appendix A.2),
+// and the SVD compression with directional recompression Section 3.1.
+//
+// The Laplace kernel is homogeneous of degree -1, so every operator of a box
+// of width w equals the unit-box operator divided by w (pseudo-inverses are
+// multiplied by w); the device code applies that scale per level.
+#include <cmath>
+#include <complex>
+
+#include "internal.h"
+
+namespace kifmm {
+
+namespace {
+
+constexpr double kInv4Pi = 0.07957747154594767;  // 1 / (4 pi)
+
+double lap(const double* x, const double* y) {
+  const double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+  const double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+  return r == 0.0 ? 0.0 : kInv4Pi / r;
+}
+
+// points c + alpha * r * s_i
+std::vector<double> place(const Operators& op, double alpha, double r, const double c[3]) {
+  std::vector<double> pts((size_t)op.ns * 3);
+  const double ar = alpha * r;
+  for (int i = 0; i < op.ns; ++i)
+    for (int k = 0; k < 3; ++k) pts[3 * i + k] = c[k] + ar * op.surf[3 * i + k];
+  return pts;
+}
+
+void kernel_block(const std::vector<double>& x, const std::vector<double>& y, int nx, int ny,
+                  double* out, int ld) {
+  for (int i = 0; i < nx; ++i)
+    for (int j = 0; j < ny; ++j) out[(size_t)i * ld + j] = lap(&x[3 * i], &y[3 * j]);
+}
+
+// two-factor pseudo-inverse (Section 2.1.1): keep sigma > max(m,n) eps sigma_0
+kifmm_status pinv(const std::vector<double>& K, int m, int n, int& rank, std::vector<double>& V,
+                  std::vector<double>& Ut) {
+  std::vector<double> U, s, W;
+  if (!svd(K.data(), m, n, U, s, W)) return fail(KIFMM_ENUMERIC, "Jacobi SVD did not converge");
+  const int r0 = std::min(m, n);
+  const double tol = std::max(m, n) * 2.220446049250313e-16 * s[0];
+  rank = 0;
+  while (rank < r0 && s[rank] > tol) ++rank;
+  V.assign((size_t)n * rank, 0.0);
+  Ut.assign((size_t)rank * m, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < rank; ++j) V[(size_t)i * rank + j] = W[(size_t)i * r0 + j];
+  for (int j = 0; j < rank; ++j)
+    for (int i = 0; i < m; ++i) Ut[(size_t)j * m + i] = U[(size_t)i * r0 + j] / s[j];
+  return KIFMM_OK;
+}
+
+// r2c DFT of a real (n x n x n) grid, output [kx][ky][kz], kz in [0, n/2]
+void rdft3(const std::vector<double>& g, int n, std::vector<std::complex<double>>& out) {
+  const int h = n / 2 + 1;
+  std::vector<std::complex<double>> w(n);
+  for (int m = 0; m < n; ++m) w[m] = std::polar(1.0, -2.0 * M_PI * m / n);
+  std::vector<std::complex<double>> a((size_t)n * n * h), b((size_t)n * n * h);
+  for (int x = 0; x < n; ++x)
+    for (int y = 0; y < n; ++y)
+      for (int kz = 0; kz < h; ++kz) {
+        std::complex<double> acc = 0;
+        for (int z = 0; z < n; ++z) acc += g[((size_t)x * n + y) * n + z] * w[(kz * z) % n];
+        a[((size_t)x * n + y) * h + kz] = acc;
+      }
+  for (int x = 0; x < n; ++x)
+    for (int ky = 0; ky < n; ++ky)
+      for (int kz = 0; kz < h; ++kz) {
+        std::complex<double> acc = 0;
+        for (int y = 0; y < n; ++y) acc += a[((size_t)x * n + y) * h + kz] * w[(ky * y) % n];
+        b[((size_t)x * n + ky) * h + kz] = acc;
+      }
+  out.assign((size_t)n * n * h, 0);
+  for (int kx = 0; kx < n; ++kx)
+    for (int ky = 0; ky < n; ++ky)
+      for (int kz = 0; kz < h; ++kz) {
+        std::complex<double> acc = 0;
+        for (int x = 0; x < n; ++x) acc += b[((size_t)x * n + ky) * h + kz] * w[(kx * x) % n];
+        out[((size_t)kx * n + ky) * h + kz] = acc;
+      }
+}
+
+}  // namespace
+
+kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg) {
+  op = Operators();
+  const int p = cfg.order;
+  op.p = p;
+  op.ai = cfg.alpha_inner > 0 ? cfg.alpha_inner : 1.05;
+  op.ao = cfg.alpha_outer > 0 ? cfg.alpha_outer : 2.95;
+  for (int ix = 0; ix < p; ++ix)
+    for (int iy = 0; iy < p; ++iy)
+      for (int iz = 0; iz < p; ++iz) {
+        const bool bnd = ix == 0 || iy == 0 || iz == 0 || ix == p - 1 || iy == p - 1 || iz == p - 1;
+        if (!bnd) continue;
+        const int id[3] = {ix, iy, iz};
+        for (int k = 0; k < 3; ++k) {
+          op.lattice.push_back(id[k]);
+          op.surf.push_back(-1.0 + 2.0 * id[k] / (p - 1));
+        }
+      }
+  op.ns = (int)op.lattice.size() / 3;
+  op.n = 2 * p;
+  op.F = op.n * op.n * (p + 1);
+  const int ns = op.ns;
+  const double zero[3] = {0, 0, 0};
+
+  // pseudo-inverses of the unit box: up K(UC, UE), down K(DC, DE)
+  {
+    std::vector<double> K((size_t)ns * ns);
+    kernel_block(place(op, op.ao, 0.5, zero), place(op, op.ai, 0.5, zero), ns, ns, K.data(), ns);
+    kifmm_status st = pinv(K, ns, ns, op.r_up, op.up_V, op.up_Ut);
+    if (st != KIFMM_OK) return st;
+    kernel_block(place(op, op.ai, 0.5, zero), place(op, op.ao, 0.5, zero), ns, ns, K.data(), ns);
+    st = pinv(K, ns, ns, op.r_down, op.down_V, op.down_Ut);
+    if (st != KIFMM_OK) return st;
+  }
+  // M2M [K_0 .. K_7] and L2L [L_0; ..; L_7] for a parent of width 1
+  op.m2m.assign((size_t)ns * 8 * ns, 0.0);
+  op.l2l.assign((size_t)8 * ns * ns, 0.0);
+  {
+    const auto uc = place(op, op.ao, 0.5, zero);
+    const auto de = place(op, op.ao, 0.5, zero);
+    for (int o = 0; o < 8; ++o) {
+      const double c[3] = {(((o >> 0) & 1) - 0.5) * 0.5, (((o >> 1) & 1) - 0.5) * 0.5,
+                           (((o >> 2) & 1) - 0.5) * 0.5};
+      kernel_block(uc, place(op, op.ai, 0.25, c), ns, ns, &op.m2m[(size_t)o * ns], 8 * ns);
+      kernel_block(place(op, op.ai, 0.25, c), de, ns, ns, &op.l2l[(size_t)o * ns * ns], ns);
+    }
+  }
+
+  if (cfg.m2l == KIFMM_M2L_FFT) {
+    // kernel sequences G[m] = K(c_tau - c_sigma + h m) on the 2p grid
+    const int n = op.n;
+    const double h = 2.0 * op.ai * 0.5 / (p - 1);
+    op.spectra.assign((size_t)kNumTransfer * op.F * 2, 0.0);
+    std::vector<double> g((size_t)n * n * n);
+    std::vector<std::complex<double>> spec;
+    for (int it = 0; it < kNumTransfer; ++it) {
+      int t[3];
+      transfer_vector(it, t);
+      std::fill(g.begin(), g.end(), 0.0);
+      for (int mx = -(p - 1); mx <= p - 1; ++mx)
+        for (int my = -(p - 1); my <= p - 1; ++my)
+          for (int mz = -(p - 1); mz <= p - 1; ++mz) {
+            const double d[3] = {-t[0] + h * mx, -t[1] + h * my, -t[2] + h * mz};
+            const double r = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            g[(((size_t)((mx + n) % n) * n) + (my + n) % n) * n + (mz + n) % n] = kInv4Pi / r;
+          }
+      rdft3(g, n, spec);
+      for (int f = 0; f < op.F; ++f) {
+        op.spectra[((size_t)it * op.F + f) * 2] = spec[f].real();
+        op.spectra[((size_t)it * op.F + f) * 2 + 1] = spec[f].imag();
+      }
+    }
+  } else {
+    // M2L matrices K_t of the unit box (check surface around 0, equivalent
+    // surface around t), both on the inner surface
+    const auto dc = place(op, op.ai, 0.5, zero);
+    std::vector<std::vector<double>> Kt(kNumTransfer, std::vector<double>((size_t)ns * ns));
+    for (int it = 0; it < kNumTransfer; ++it) {
+      int t[3];
+      transfer_vector(it, t);
+      const double c[3] = {(double)t[0], (double)t[1], (double)t[2]};
+      kernel_block(dc, place(op, op.ai, 0.5, c), ns, ns, Kt[it].data(), ns);
+    }
+    op.Ubar.assign(kNumTransfer, {});
+    op.Vbarp.assign(kNumTransfer, {});
+    op.kt.assign(kNumTransfer, 0);
+    if (cfg.m2l == KIFMM_M2L_DENSE) {
+      op.k = ns;
+      op.U.assign((size_t)ns * ns, 0.0);
+      for (int i = 0; i < ns; ++i) op.U[(size_t)i * ns + i] = 1.0;
+      for (int it = 0; it < kNumTransfer; ++it) {
+        op.kt[it] = ns;
+        op.Vbarp[it] = Kt[it];  // applied directly as C_t = K_t
+      }
+      op.recompressed = false;
+    } else {
+      // K_fat = [K_1 .. K_T]; K_t^T = K_{-t} makes K_thin's right vectors equal
+      // K_fat's left vectors, so S = U (Section 3.1, symmetric kernels)
+      std::vector<double> Kfat((size_t)ns * kNumTransfer * ns);
+      for (int i = 0; i < ns; ++i)
+        for (int it = 0; it < kNumTransfer; ++it)
+          std::copy(&Kt[it][(size_t)i * ns], &Kt[it][(size_t)i * ns] + ns,
+                    &Kfat[((size_t)i * kNumTransfer + it) * ns]);
+      std::vector<double> Uf, sf;
+      if (!svd_left_wide(Kfat.data(), ns, kNumTransfer * ns, Uf, sf))
+        return fail(KIFMM_ENUMERIC, "SVD of K_fat did not converge");
+      const int r0 = (int)sf.size();
+      int k = 0;
+      if (cfg.svd_rel_tol > 0) {
+        while (k < r0 && sf[k] > cfg.svd_rel_tol * sf[0]) ++k;
+      } else {
+        while (k < r0 && sf[k] > 0.0) ++k;
+      }
+      op.k = k;
+      op.U.assign((size_t)ns * k, 0.0);
+      for (int i = 0; i < ns; ++i)
+        for (int j = 0; j < k; ++j) op.U[(size_t)i * k + j] = Uf[(size_t)i * r0 + j];
+      op.recompressed = cfg.svd_rel_tol_dir >= 0;
+      std::vector<double> tmp((size_t)ns * k), C((size_t)k * k);
+      for (int it = 0; it < kNumTransfer; ++it) {
+        // C_t = U^T K_t U
+        for (int i = 0; i < ns; ++i)
+          for (int j = 0; j < k; ++j) {
+            double acc = 0;
+            for (int l = 0; l < ns; ++l) acc += Kt[it][(size_t)i * ns + l] * op.U[(size_t)l * k + j];
+            tmp[(size_t)i * k + j] = acc;
+          }
+        for (int i = 0; i < k; ++i)
+          for (int j = 0; j < k; ++j) {
+            double acc = 0;
+            for (int l = 0; l < ns; ++l) acc += op.U[(size_t)l * k + i] * tmp[(size_t)l * k + j];
+            C[(size_t)i * k + j] = acc;
+          }
+        if (!op.recompressed) {
+          op.kt[it] = k;
+          op.Vbarp[it] = C;  // applied directly
+          continue;
+        }
+        std::vector<double> cu, cs, cv;
+        if (!svd(C.data(), k, k, cu, cs, cv)) return fail(KIFMM_ENUMERIC, "SVD of C_t did not converge");
+        int r = 0;
+        while (r < k && cs[r] > cfg.svd_rel_tol_dir * cs[0]) ++r;
+        if (r == 0) r = 1;
+        op.kt[it] = r;
+        op.Ubar[it].assign((size_t)k * r, 0.0);
+        op.Vbarp[it].assign((size_t)k * r, 0.0);
+        for (int i = 0; i < k; ++i)
+          for (int j = 0; j < r; ++j) {
+            op.Ubar[it][(size_t)i * r + j] = cu[(size_t)i * k + j];
+            op.Vbarp[it][(size_t)i * r + j] = cv[(size_t)i * k + j] * cs[j];
+          }
+      }
+    }
+  }
+  op.ready = true;
+  return KIFMM_OK;
+}
+
+}  // namespace kifmm
