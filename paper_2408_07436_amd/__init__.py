@@ -25,7 +25,7 @@ EXPORTS = [
     "kifmm_config_default", "kifmm_create", "kifmm_set_points", "kifmm_precompute",
     "kifmm_evaluate", "kifmm_destroy", "kifmm_last_error", "kifmm_num_boxes", "kifmm_box_keys",
     "kifmm_point_perm", "kifmm_interactions", "kifmm_near", "kifmm_operator", "kifmm_stage",
-    "kifmm_set_timing", "kifmm_timings",
+    "kifmm_set_timing", "kifmm_timings", "kifmm_m2l_counts",
 ]
 
 
@@ -82,6 +82,7 @@ def lib() -> ctypes.CDLL:
     L.kifmm_stage.argtypes = [vp, i32, i32, vp, vp, i32, vp]
     L.kifmm_set_timing.argtypes = [vp, i32]
     L.kifmm_timings.argtypes = [vp, dp, i32]
+    L.kifmm_m2l_counts.argtypes = [vp, i32, ctypes.POINTER(i64), i32]
     for name in EXPORTS:
         if name not in ("kifmm_config_default", "kifmm_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -231,9 +232,15 @@ class KiFMM:
         _check(lib().kifmm_set_timing(self._h, 1 if on else 0))
 
     def timings(self) -> dict:
-        ms = np.zeros(5, dtype=np.float64)
-        _check(lib().kifmm_timings(self._h, _ptr(ms, ctypes.c_double), 5))
-        return dict(upward=ms[0], m2l=ms[1], downward=ms[2], leaves=ms[3], total=ms[4])
+        ms = np.zeros(9, dtype=np.float64)
+        _check(lib().kifmm_timings(self._h, _ptr(ms, ctypes.c_double), 9))
+        return dict(upward=ms[0], m2l=ms[1], downward=ms[2], leaves=ms[3], total=ms[4],
+                    m2l_first=ms[5], m2l_main=ms[6], m2l_last=ms[7], m2l_levels=int(ms[8]))
+
+    def m2l_counts(self, level: int) -> dict:
+        c = np.zeros(4, dtype=np.int64)
+        _check(lib().kifmm_m2l_counts(self._h, level, _ptr(c, ctypes.c_int64), 4))
+        return dict(boxes=int(c[0]), pairs=int(c[1]), clusters=int(c[2]), cluster_pairs=int(c[3]))
 
 
 OP_UP_V, OP_UP_UT, OP_DOWN_V, OP_DOWN_UT, OP_FFT_SPECTRA, OP_BLAS_U, OP_BLAS_RANKS, OP_BLAS_APPLIED = range(8)

@@ -268,7 +268,22 @@ kifmm_status kifmm_set_timing(kifmm_handle* h, int32_t on) {
 kifmm_status kifmm_timings(const kifmm_handle* h, double* ms, int32_t cap) {
   if (!h || !ms) return fail(KIFMM_EINVAL, "null argument");
   if (cap < 5) return fail(KIFMM_EINVAL, "capacity too small");
-  for (int i = 0; i < 5; ++i) ms[i] = h->timings[i];
+  for (int i = 0; i < cap && i < 9; ++i) ms[i] = h->timings[i];
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_m2l_counts(const kifmm_handle* h, int32_t level, int64_t* counts, int32_t cap) {
+  if (!h || !counts) return fail(KIFMM_EINVAL, "null argument");
+  if (!h->has_points) return fail(KIFMM_ESTATE, "no points set");
+  if (level < 2 || level > h->tree.depth) return fail(KIFMM_EINVAL, "level out of range");
+  if (cap < 4) return fail(KIFMM_EINVAL, "capacity too small");
+  const auto& L = h->tree.levels[level];
+  counts[0] = L.n;
+  counts[1] = (int64_t)L.il_src.size();
+  counts[2] = h->tree.levels[level - 1].n;
+  int64_t cp = 0;
+  for (int32_t v : L.halo) cp += v >= 0;
+  counts[3] = cp;
   return KIFMM_OK;
 }
 

@@ -59,6 +59,7 @@ struct DeviceState {
   void* Phat = nullptr;
   std::vector<void*> work_allocs;
   hipEvent_t ev[6] = {};
+  std::vector<hipEvent_t> lev_ev;  // [level][4] marks around the M2L kernels
   bool events = false;
 };
 
@@ -237,6 +238,8 @@ kifmm_status upload_all(kifmm_handle* h) {
     }
   }
   for (int e = 0; e < 6; ++e) KIFMM_HIP(hipEventCreate(&d->ev[e]));
+  d->lev_ev.assign(4 * (depth + 1), nullptr);
+  for (auto& e : d->lev_ev) KIFMM_HIP(hipEventCreate(&e));
   d->events = true;
   return KIFMM_OK;
 }
@@ -299,20 +302,25 @@ kifmm_status pinv_apply(kifmm_handle* h, const double* V, const double* Ut, int 
 
 // M2L check potentials of one level: out[box][v][ns] (overwritten)
 kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, int nvec,
-                       hipStream_t s) {
+                       hipStream_t s, bool timed) {
   DeviceState* d = h->dev;
   const Operators& op = h->op;
   const DevLevel& D = d->lv[l];
   const int ns = op.ns;
+  hipEvent_t* mark = timed ? &d->lev_ev[4 * l] : nullptr;
+  if (mark) KIFMM_HIP(hipEventRecord(mark[0], s));
   if (h->cfg.m2l == KIFMM_M2L_FFT) {
     const int64_t nc = d->lv[l - 1].n;
     const int32_t* child = d->lv[l - 1].child;
     KIFMM_LAUNCH(launch_fft_forward(op.p, d->fp64, in, child, nc, nvec, d->lat2surf, d->twiddle,
                                     d->Qhat, s));
+    if (mark) KIFMM_HIP(hipEventRecord(mark[1], s));
     KIFMM_LAUNCH(launch_hadamard(d->fp64, op.F, d->khat, d->Qhat, D.halo, nc, nvec, d->Phat, s));
+    if (mark) KIFMM_HIP(hipEventRecord(mark[2], s));
     const double scale = 1.0 / ((double)op.n * op.n * op.n * D.w);
     KIFMM_LAUNCH(launch_fft_inverse(op.p, d->fp64, d->Phat, child, nc, nvec, d->surf_lat,
                                     d->twiddle, scale, out, s));
+    if (mark) KIFMM_HIP(hipEventRecord(mark[3], s));
     return KIFMM_OK;
   }
   // dense / compressed M2L, one product per transfer vector (Section 3.2)
@@ -328,6 +336,7 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
     q = d->tmp;
     acc = d->tmp2;
   }
+  if (mark) KIFMM_HIP(hipEventRecord(mark[1], s));
   KIFMM_HIP(hipMemsetAsync(acc, 0, sizeof(double) * (size_t)D.n * nvec * k, s));
   const double inv_w = 1.0 / D.w;
   for (int it = 0; it < kNumTransfer; ++it) {
@@ -348,12 +357,14 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
       KIFMM_LAUNCH(launch_gemm64(g2, s));
     }
   }
+  if (mark) KIFMM_HIP(hipEventRecord(mark[2], s));
   if (!dense) {
     // check potentials  Phi = U Phi~
     Gemm64 g{d->Ublas, ns, k, k, 1.0, acc, k, 1, nullptr, (int64_t)nvec * k, k,
              out, ns, 1, nullptr, (int64_t)nvec * ns, ns, D.n, nvec, 0};
     KIFMM_LAUNCH(launch_gemm64(g, s));
   }
+  if (mark) KIFMM_HIP(hipEventRecord(mark[3], s));
   return KIFMM_OK;
 }
 
@@ -364,6 +375,8 @@ void destroy_device(DeviceState* d) {
   hipSetDevice(d->device);
   if (d->events)
     for (auto& e : d->ev) hipEventDestroy(e);
+  for (auto& e : d->lev_ev)
+    if (e) hipEventDestroy(e);
   for (void* p : d->work_allocs) hipFree(p);
   for (void* p : d->allocs) hipFree(p);
   delete d;
@@ -412,18 +425,9 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
   }
   if (timed) KIFMM_HIP(hipEventRecord(d->ev[1], s));
   // downward pass
-  float m2l_ms = 0.f;
   for (int l = 2; l <= depth; ++l) {
     const DevLevel& D = d->lv[l];
-    if (timed) KIFMM_HIP(hipEventRecord(d->ev[4], s));
-    KIFMM_TRY(m2l_level(h, l, d->mult[l], d->phi, nvec, s));
-    if (timed) {
-      KIFMM_HIP(hipEventRecord(d->ev[5], s));
-      KIFMM_HIP(hipEventSynchronize(d->ev[5]));
-      float ms = 0.f;
-      KIFMM_HIP(hipEventElapsedTime(&ms, d->ev[4], d->ev[5]));
-      m2l_ms += ms;
-    }
+    KIFMM_TRY(m2l_level(h, l, d->mult[l], d->phi, nvec, s, timed));
     if (l >= 3) {
       const DevLevel& P = d->lv[l - 1];
       Gemm64 g{d->l2l, 8 * ns, ns, ns, 1.0 / P.w, d->local[l - 1], ns, 1, nullptr,
@@ -445,11 +449,23 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
     KIFMM_HIP(hipEventElapsedTime(&b, d->ev[1], d->ev[2]));
     KIFMM_HIP(hipEventElapsedTime(&c, d->ev[2], d->ev[3]));
     KIFMM_HIP(hipEventElapsedTime(&tot, d->ev[0], d->ev[3]));
+    double parts[3] = {0, 0, 0};
+    for (int l = 2; l <= depth; ++l)
+      for (int k = 0; k < 3; ++k) {
+        float ms = 0.f;
+        KIFMM_HIP(hipEventElapsedTime(&ms, d->lev_ev[4 * l + k], d->lev_ev[4 * l + k + 1]));
+        parts[k] += ms;
+      }
+    const double m2l_ms = parts[0] + parts[1] + parts[2];
     h->timings[0] = a;
     h->timings[1] = m2l_ms;
     h->timings[2] = b - m2l_ms;
     h->timings[3] = c;
     h->timings[4] = tot;
+    h->timings[5] = parts[0];
+    h->timings[6] = parts[1];
+    h->timings[7] = parts[2];
+    h->timings[8] = depth - 1;
   }
   return KIFMM_OK;
 }
@@ -457,7 +473,7 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
 kifmm_status device_stage(kifmm_handle* h, int level, const void* in, void* out, int nvec,
                           hipStream_t s) {
   KIFMM_TRY(device_ready(h, nvec));
-  return m2l_level(h, level, (const double*)in, (double*)out, nvec, s);
+  return m2l_level(h, level, (const double*)in, (double*)out, nvec, s, false);
 }
 
 }  // namespace kifmm

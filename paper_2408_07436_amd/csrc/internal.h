@@ -116,5 +116,5 @@ struct kifmm_handle {
   bool has_points = false;
   kifmm::DeviceState* dev = nullptr;
   bool timing = false;
-  double timings[5] = {0, 0, 0, 0, 0};
+  double timings[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 };
