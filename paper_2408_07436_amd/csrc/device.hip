@@ -55,6 +55,8 @@ struct DeviceState {
   double* phi = nullptr;
   double* tmp = nullptr;
   double* tmp2 = nullptr;
+  double* gemm_ws = nullptr;  // split-K partials
+  int64_t gemm_ws_elems = 0;
   void* Qhat = nullptr;
   void* Phat = nullptr;
   std::vector<void*> work_allocs;
@@ -272,6 +274,8 @@ kifmm_status ensure_work(kifmm_handle* h, int nvec) {
   KIFMM_TRY(dalloc(d, &d->phi, (size_t)maxn * nvec * ns, true));
   KIFMM_TRY(dalloc(d, &d->tmp, (size_t)maxn * nvec * kmax, true));
   KIFMM_TRY(dalloc(d, &d->tmp2, (size_t)maxn * nvec * kmax, true));
+  d->gemm_ws_elems = (int64_t)8 << 20;  // 64 MiB of split-K partials
+  KIFMM_TRY(dalloc(d, &d->gemm_ws, (size_t)d->gemm_ws_elems, true));
   if (h->cfg.m2l == KIFMM_M2L_FFT) {
     int64_t maxc = 0;
     for (int l = 2; l <= depth; ++l) maxc = std::max(maxc, t.levels[l - 1].n);
@@ -286,6 +290,12 @@ kifmm_status ensure_work(kifmm_handle* h, int nvec) {
   return KIFMM_OK;
 }
 
+hipError_t gemm(DeviceState* d, Gemm64 g, hipStream_t s) {
+  g.work = d->gemm_ws;
+  g.work_elems = d->gemm_ws_elems;
+  return launch_gemm64(g, s);
+}
+
 // Apply a unit-box pseudo-inverse V (Ut phi) scaled by the box width w.
 kifmm_status pinv_apply(kifmm_handle* h, const double* V, const double* Ut, int r, double w,
                         const double* in, double* out, int64_t nbox, int nvec, hipStream_t s) {
@@ -293,10 +303,10 @@ kifmm_status pinv_apply(kifmm_handle* h, const double* V, const double* Ut, int 
   const int ns = h->op.ns;
   Gemm64 g1{Ut, r, ns, ns, w, in, ns, 1, nullptr, (int64_t)nvec * ns, ns,
             d->tmp, r, 1, nullptr, (int64_t)nvec * r, r, nbox, nvec, 0};
-  KIFMM_LAUNCH(launch_gemm64(g1, s));
+  KIFMM_LAUNCH(gemm(d, g1, s));
   Gemm64 g2{V, ns, r, r, 1.0, d->tmp, r, 1, nullptr, (int64_t)nvec * r, r,
             out, ns, 1, nullptr, (int64_t)nvec * ns, ns, nbox, nvec, 0};
-  KIFMM_LAUNCH(launch_gemm64(g2, s));
+  KIFMM_LAUNCH(gemm(d, g2, s));
   return KIFMM_OK;
 }
 
@@ -332,7 +342,7 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
     // compressed multipoles  Q~ = S^T Q  (S = U)
     Gemm64 g{d->UblasT, k, ns, ns, 1.0, in, ns, 1, nullptr, (int64_t)nvec * ns, ns,
              d->tmp, k, 1, nullptr, (int64_t)nvec * k, k, D.n, nvec, 0};
-    KIFMM_LAUNCH(launch_gemm64(g, s));
+    KIFMM_LAUNCH(gemm(d, g, s));
     q = d->tmp;
     acc = d->tmp2;
   }
@@ -345,16 +355,16 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
     if (!op.recompressed) {
       Gemm64 g{d->Ct[it], k, k, k, inv_w, q, k, 1, D.t_src + a, (int64_t)nvec * k, k,
                acc, k, 1, D.t_tgt + a, (int64_t)nvec * k, k, b - a, nvec, 1};
-      KIFMM_LAUNCH(launch_gemm64(g, s));
+      KIFMM_LAUNCH(gemm(d, g, s));
     } else {
       const int r = op.kt[it];
       // xi = Vbar'^T q~[src]  (r x cols, contiguous), then acc[tgt] += Ubar xi
       Gemm64 g1{d->Ct[it], r, k, k, inv_w, q, k, 1, D.t_src + a, (int64_t)nvec * k, k,
                 out, r, 1, nullptr, (int64_t)nvec * r, r, b - a, nvec, 0};
-      KIFMM_LAUNCH(launch_gemm64(g1, s));
+      KIFMM_LAUNCH(gemm(d, g1, s));
       Gemm64 g2{d->Ub[it], k, r, r, 1.0, out, r, 1, nullptr, (int64_t)nvec * r, r,
                 acc, k, 1, D.t_tgt + a, (int64_t)nvec * k, k, b - a, nvec, 1};
-      KIFMM_LAUNCH(launch_gemm64(g2, s));
+      KIFMM_LAUNCH(gemm(d, g2, s));
     }
   }
   if (mark) KIFMM_HIP(hipEventRecord(mark[2], s));
@@ -362,7 +372,7 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
     // check potentials  Phi = U Phi~
     Gemm64 g{d->Ublas, ns, k, k, 1.0, acc, k, 1, nullptr, (int64_t)nvec * k, k,
              out, ns, 1, nullptr, (int64_t)nvec * ns, ns, D.n, nvec, 0};
-    KIFMM_LAUNCH(launch_gemm64(g, s));
+    KIFMM_LAUNCH(gemm(d, g, s));
   }
   if (mark) KIFMM_HIP(hipEventRecord(mark[3], s));
   return KIFMM_OK;
@@ -420,7 +430,7 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
     const DevLevel& D = d->lv[l];
     Gemm64 g{d->m2m, ns, 8 * ns, 8 * ns, 1.0 / D.w, d->mult[l + 1], ns, 8, D.child,
              (int64_t)nvec * ns, ns, d->phi, ns, 1, nullptr, (int64_t)nvec * ns, ns, D.n, nvec, 0};
-    KIFMM_LAUNCH(launch_gemm64(g, s));
+    KIFMM_LAUNCH(gemm(d, g, s));
     KIFMM_TRY(pinv_apply(h, d->up_V, d->up_Ut, op.r_up, D.w, d->phi, d->mult[l], D.n, nvec, s));
   }
   if (timed) KIFMM_HIP(hipEventRecord(d->ev[1], s));
@@ -432,7 +442,7 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
       const DevLevel& P = d->lv[l - 1];
       Gemm64 g{d->l2l, 8 * ns, ns, ns, 1.0 / P.w, d->local[l - 1], ns, 1, nullptr,
                (int64_t)nvec * ns, ns, d->phi, ns, 8, P.child, (int64_t)nvec * ns, ns, P.n, nvec, 1};
-      KIFMM_LAUNCH(launch_gemm64(g, s));
+      KIFMM_LAUNCH(gemm(d, g, s));
     }
     KIFMM_TRY(pinv_apply(h, d->down_V, d->down_Ut, op.r_down, D.w, d->phi, d->local[l], D.n, nvec, s));
   }

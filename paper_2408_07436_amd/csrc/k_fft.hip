@@ -230,9 +230,27 @@ template <> struct V4T<double> { using type = v4d; };
 
 constexpr int kHadThreads = 256;
 
+template <typename T> struct Vec4T;
+template <> struct Vec4T<float> { using type = float4; };
+template <> struct Vec4T<double> { using type = double4; };
+
+// directions handled per batch of loads: all 26 in FP32; 13 in FP64 to
+// stay within the register file
+template <typename T> struct HadChunk { static constexpr int value = 26; };
+template <> struct HadChunk<double> { static constexpr int value = 13; };
+
+__device__ inline float4 load4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+__device__ inline double4 load4(const double* p) {
+  const double2 lo = *reinterpret_cast<const double2*>(p);
+  const double2 hi = *reinterpret_cast<const double2*>(p + 2);
+  return double4{lo.x, lo.y, hi.x, hi.y};
+}
+
 // Workgroup = one frequency x a chunk of 16-row tiles; four waves share the
 // frequency's B operand (the 416 x 16 real form of its 26 x 8 x 8 complex
-// kernel coefficients), staged in LDS in the lanes' operand order.
+// kernel coefficients), staged in LDS in the lanes' operand order.  Each
+// wave issues the halo indices and the source spectra of a whole batch of
+// directions before its MFMAs, so that the loads are in flight together.
 template <typename T>
 __global__ __launch_bounds__(kHadThreads) void hadamard_kernel(
     const typename C2T<T>::type* __restrict__ Khat, const T* __restrict__ Qhat,
@@ -240,7 +258,9 @@ __global__ __launch_bounds__(kHadThreads) void hadamard_kernel(
     int tiles_per_wave, int64_t total_blocks, T* __restrict__ Phat) {
   using C2 = typename C2T<T>::type;
   using V4 = typename V4T<T>::type;
-  __shared__ T Bl[26][64][4];
+  using T4 = typename Vec4T<T>::type;
+  constexpr int DC = HadChunk<T>::value;
+  __shared__ T4 Bl[26][64];
   const int64_t b = blockIdx.x;
   const int64_t per_xcd = (total_blocks + 7) / 8;
   const int64_t logical = (b % 8) * per_xcd + b / 8;  // consecutive work per XCD
@@ -248,17 +268,21 @@ __global__ __launch_bounds__(kHadThreads) void hadamard_kernel(
   const int64_t f = logical / n_chunks;
   const int chunk = (int)(logical % n_chunks);
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < 26 * 64 * 4; idx += kHadThreads) {
-    const int d = idx / 256, lane = (idx / 4) % 64, s = idx % 4;
+  for (int idx = tid; idx < 26 * 64; idx += kHadThreads) {
+    const int d = idx / 64, lane = idx % 64;
     const int n = lane % 16, g = lane / 16;
-    const int i = n / 2, cout = n % 2, j = 2 * g + s / 2, cin = s % 2;
-    const C2 K = Khat[((f * 26 + d) * 8 + i) * 8 + j];
-    T val;
-    if (cin == 0)
-      val = cout == 0 ? K.x : K.y;
-    else
-      val = cout == 0 ? -K.y : K.x;
-    Bl[d][lane][s] = val;
+    const int i = n / 2, cout = n % 2;
+    T val[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int j = 2 * g + s / 2, cin = s % 2;
+      const C2 K = Khat[((f * 26 + d) * 8 + i) * 8 + j];
+      if (cin == 0)
+        val[s] = cout == 0 ? K.x : K.y;
+      else
+        val[s] = cout == 0 ? -K.y : K.x;
+    }
+    Bl[d][lane] = T4{val[0], val[1], val[2], val[3]};
   }
   __syncthreads();
   const int wave = tid / 64, lane = tid % 64;
@@ -274,17 +298,27 @@ __global__ __launch_bounds__(kHadThreads) void hadamard_kernel(
     const int v = valid ? (int)(row - c * nvec) : 0;
     V4 acc;
     acc[0] = acc[1] = acc[2] = acc[3] = T(0);
-#pragma unroll 2
-    for (int d = 0; d < 26; ++d) {
-      const int32_t nb = valid ? halo[(int64_t)d * n_c + c] : -1;
-      T a[4] = {T(0), T(0), T(0), T(0)};
-      if (nb >= 0) {
-        const T* src = Qhat + ((fbase + (int64_t)nb * nvec + v) * 16 + 4 * g);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) a[s] = src[s];
+    for (int d0 = 0; d0 < 26; d0 += DC) {
+      int32_t nb[DC];
+#pragma unroll
+      for (int dd = 0; dd < DC; ++dd) nb[dd] = valid ? halo[(int64_t)(d0 + dd) * n_c + c] : -1;
+      T4 a[DC];
+#pragma unroll
+      for (int dd = 0; dd < DC; ++dd) {
+        if (nb[dd] >= 0)
+          a[dd] = load4(Qhat + ((fbase + (int64_t)nb[dd] * nvec + v) * 16 + 4 * g));
+        else
+          a[dd] = T4{T(0), T(0), T(0), T(0)};
       }
 #pragma unroll
-      for (int s = 0; s < 4; ++s) acc = mfma16(a[s], Bl[d][lane][s], acc);
+      for (int dd = 0; dd < DC; ++dd) {
+        const T4 bv = Bl[d0 + dd][lane];
+        acc = mfma16(a[dd].x, bv.x, acc);
+        acc = mfma16(a[dd].y, bv.y, acc);
+        acc = mfma16(a[dd].z, bv.z, acc);
+        acc = mfma16(a[dd].w, bv.w, acc);
+      }
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {

@@ -1,91 +1,186 @@
 // FP64 GEMM with gathered / scattered columns for the kiFMM's small dense
 // operators: the two pseudo-inverse factors (Section 2.1.1) and the M2M /
-// L2L translations (Section 2.2).  FP64 vector arithmetic: on MI355X the
-// FP64 vector and matrix rates are equal, so no MFMA is used here.
+// L2L translations (Section 2.2).
 //
-// Tile: 64 rows x 64 columns per 256-thread workgroup, K in steps of 16
-// staged through LDS.  Lane (tm, tn) owns rows tm + 16 i and columns
-// tn + 16 j; consecutive lanes own consecutive rows so that stores of a
-// column (contiguous in memory) coalesce.
+// The operators have few rows (n_s = 152 at p = 6, or 8 n_s for L2L) and the
+// data has many columns (boxes x charge vectors), so a workgroup owns 64
+// data columns and a block of 160 operator rows: each of its four waves
+// computes 16 data columns x 160 rows on v_mfma_f64_16x16x4f64 (ten 16 x 16
+// accumulator tiles).  The product runs in transposed form - data columns
+// are the MFMA rows - so the sixteen lanes holding one accumulator row store
+// sixteen consecutive entries of one output column.  K is staged through LDS
+// sixteen at a time, with the next slice's global loads issued before the
+// current slice's MFMAs.
+//
+// Coarse tree levels have few columns; there the K range is split over
+// several workgroups that write partial products, and a second kernel sums
+// the partials in a fixed order (deterministic) and applies the scatter.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace kifmm {
 
 namespace {
 
-constexpr int kBM = 64, kBN = 64, kBK = 16;
+typedef double v4d __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void gemm64_kernel(Gemm64 g) {
-  __shared__ double As[kBK][kBM + 1];
-  __shared__ double Bs[kBK][kBN + 1];
+constexpr int kMT = 10;            // 16-row MFMA tiles per wave along the operator rows
+constexpr int kBM = 16 * kMT;      // 160 operator rows per workgroup
+constexpr int kBN = 64;            // data columns per workgroup (16 per wave)
+constexpr int kBK = 16;
+constexpr int kALoads = kBK * kBM / 256;  // operator values per thread per K slice
+
+__device__ inline void col_split(int64_t col, int nvec, int64_t& b, int& v) {
+  if (nvec == 1) {
+    b = col;
+    v = 0;
+  } else {
+    b = (int64_t)((uint32_t)col / (uint32_t)nvec);
+    v = (int)(col - b * nvec);
+  }
+}
+
+// blockIdx.z selects the K range [kz0, kz1) of a split product; with
+// `partial` set the raw sums go to partial[z][col][m] (m < M) instead of C.
+__global__ __launch_bounds__(256) void gemm64_kernel(Gemm64 g, int kchunk, double* partial) {
+  __shared__ double As[kBK][kBM + 2];  // operator, k-major
+  __shared__ double Bs[kBK][kBN + 2];  // data columns, k-major
   const int tid = threadIdx.x;
-  const int tm = tid % 16, tn = tid / 16;
+  const int wave = tid / 64, lane = tid % 64;
+  const int l16 = lane % 16, g4 = lane / 16;
   const int m0 = blockIdx.y * kBM;
   const int64_t n0 = (int64_t)blockIdx.x * kBN;
   const int64_t ncols = g.nbox * g.nvec;
-  double acc[4][4];
+  const int kz0 = blockIdx.z * kchunk;
+  const int kz1 = min(g.K, kz0 + kchunk);
+  v4d acc[kMT];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int j = 0; j < kMT; ++j) acc[j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = 0; k0 < g.K; k0 += kBK) {
-    // A tile: As[kk][mm] = A[m0 + mm][k0 + kk]
+  // data loads: four consecutive k of one column per thread and K slice; the
+  // column's (box, vector) split is computed once
+  const int cs = tid >> 2, kq = (tid & 3) * 4;
+  const int64_t mycol = n0 + cs;
+  const bool col_ok = mycol < ncols;
+  int64_t cb_box = 0;
+  int cb_v = 0;
+  if (col_ok) col_split(mycol, g.nvec, cb_box, cb_v);
+  const int32_t* bmap_row = g.bmap ? g.bmap + cb_box * g.nsegk : nullptr;
+  const double* bcol = g.B + (int64_t)cb_v * g.b_vec;
+  const double* bdirect = g.B + cb_box * g.b_box + (int64_t)cb_v * g.b_vec;
+  const bool single_seg = g.nsegk == 1 && bmap_row == nullptr;
+
+  double ra[kALoads], rb[4];
+  auto fetch = [&](int k0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int kk = tid % kBK, mm = tid / kBK + 16 * r;
+    for (int r = 0; r < kALoads; ++r) {
+      const int idx = tid + 256 * r;
+      const int kk = idx % kBK, mm = idx / kBK;
       const int m = m0 + mm, k = k0 + kk;
-      As[kk][mm] = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.lda + k] : 0.0;
+      ra[r] = (m < g.M && k < kz1) ? g.A[(int64_t)m * g.lda + k] : 0.0;
     }
-    // B tile: Bs[kk][nn] = B(k0 + kk, n0 + nn), gathered
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int kk = tid % kBK, nn = tid / kBK + 16 * r;
-      const int64_t col = n0 + nn;
-      const int k = k0 + kk;
+    for (int e = 0; e < 4; ++e) {
+      const int k = k0 + kq + e;
       double val = 0.0;
-      if (col < ncols && k < g.K) {
-        const int64_t b = col / g.nvec;
-        const int v = (int)(col - b * g.nvec);
-        const int seg = k / g.ks, kk2 = k - seg * g.ks;
-        const int64_t bb = g.bmap ? (int64_t)g.bmap[b * g.nsegk + seg] : b;
-        if (bb >= 0) val = g.B[bb * g.b_box + (int64_t)v * g.b_vec + kk2];
+      if (col_ok && k < kz1) {
+        if (single_seg) {
+          val = bdirect[k];
+        } else {
+          int seg = 0, kk2 = k;
+          if (g.nsegk != 1) {
+            seg = k / g.ks;
+            kk2 = k - seg * g.ks;
+          }
+          const int64_t bb = bmap_row ? (int64_t)bmap_row[seg] : cb_box;
+          if (bb >= 0) val = bcol[bb * g.b_box + kk2];
+        }
       }
-      Bs[kk][nn] = val;
+      rb[e] = val;
     }
+  };
+
+  fetch(kz0);
+  for (int k0 = kz0; k0 < kz1; k0 += kBK) {
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < kBK; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tm + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tn + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    for (int r = 0; r < kALoads; ++r) {
+      const int idx = tid + 256 * r;
+      As[idx % kBK][idx / kBK] = ra[r];
     }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Bs[kq + e][cs] = rb[e];
     __syncthreads();
+    if (k0 + kBK < kz1) fetch(k0 + kBK);
+#pragma unroll
+    for (int ks = 0; ks < kBK; ks += 4) {
+      const double a = Bs[ks + g4][wave * 16 + l16];
+#pragma unroll
+      for (int j = 0; j < kMT; ++j)
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, As[ks + g4][16 * j + l16], acc[j], 0, 0, 0);
+    }
   }
+  // lane holds data columns g4 + 4 e (of the wave's 16) and operator row l16
+  // of each tile
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int64_t col = n0 + tn + 16 * j;
+  for (int e = 0; e < 4; ++e) {
+    const int64_t col = n0 + wave * 16 + g4 + 4 * e;
     if (col >= ncols) continue;
-    const int64_t b = col / g.nvec;
-    const int v = (int)(col - b * g.nvec);
+    if (partial) {
+      double* dst = partial + ((int64_t)blockIdx.z * ncols + col) * g.M;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int m = m0 + tm + 16 * i;
+      for (int j = 0; j < kMT; ++j) {
+        const int m = m0 + 16 * j + l16;
+        if (m < g.M) dst[m] = acc[j][e];
+      }
+      continue;
+    }
+    int64_t b;
+    int v;
+    col_split(col, g.nvec, b, v);
+#pragma unroll
+    for (int j = 0; j < kMT; ++j) {
+      const int m = m0 + 16 * j + l16;
       if (m >= g.M) continue;
-      const int seg = m / g.ms, mm = m - seg * g.ms;
+      int seg = 0, mm = m;
+      if (g.nsegm != 1) {
+        seg = m / g.ms;
+        mm = m - seg * g.ms;
+      }
       const int64_t cb = g.cmap ? (int64_t)g.cmap[b * g.nsegm + seg] : b;
       if (cb < 0) continue;
       double* dst = &g.C[cb * g.c_box + (int64_t)v * g.c_vec + mm];
-      const double val = g.alpha * acc[i][j];
+      const double val = g.alpha * acc[j][e];
       *dst = g.accumulate ? *dst + val : val;
     }
   }
+}
+
+// Sum the split-K partials in order z = 0, 1, ... and scatter like the GEMM.
+__global__ __launch_bounds__(256) void gemm64_reduce_kernel(Gemm64 g, int nsplit,
+                                                            const double* __restrict__ partial) {
+  const int64_t ncols = g.nbox * g.nvec;
+  const int64_t total = ncols * g.M;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  const int64_t col = i / g.M;
+  const int m = (int)(i - col * g.M);
+  double sum = 0.0;
+  for (int z = 0; z < nsplit; ++z) sum += partial[(int64_t)z * total + i];
+  int64_t b;
+  int v;
+  col_split(col, g.nvec, b, v);
+  int seg = 0, mm = m;
+  if (g.nsegm != 1) {
+    seg = m / g.ms;
+    mm = m - seg * g.ms;
+  }
+  const int64_t cb = g.cmap ? (int64_t)g.cmap[b * g.nsegm + seg] : b;
+  if (cb < 0) return;
+  double* dst = &g.C[cb * g.c_box + (int64_t)v * g.c_vec + mm];
+  const double val = g.alpha * sum;
+  *dst = g.accumulate ? *dst + val : val;
 }
 
 }  // namespace
@@ -93,8 +188,29 @@ __global__ __launch_bounds__(256) void gemm64_kernel(Gemm64 g) {
 hipError_t launch_gemm64(const Gemm64& g, hipStream_t stream) {
   const int64_t ncols = g.nbox * g.nvec;
   if (ncols == 0 || g.M == 0) return hipSuccess;
-  dim3 grid((unsigned)((ncols + kBN - 1) / kBN), (unsigned)((g.M + kBM - 1) / kBM));
-  gemm64_kernel<<<grid, 256, 0, stream>>>(g);
+  if (ncols >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  const int64_t gx = (ncols + kBN - 1) / kBN, gy = (g.M + kBM - 1) / kBM;
+  // split K when the grid cannot fill the chip, within the workspace
+  const int64_t slices = (g.K + kBK - 1) / kBK;
+  int64_t split = 1;
+  const int64_t target = 512;
+  if (g.work && gx * gy < target && slices >= 4) {
+    split = std::min<int64_t>((target + gx * gy - 1) / (gx * gy), slices / 2);
+    const int64_t cap = g.work_elems / (ncols * g.M);
+    split = std::max<int64_t>(1, std::min(split, cap));
+  }
+  const int kchunk = (int)(((slices + split - 1) / split) * kBK);
+  split = (g.K + kchunk - 1) / kchunk;
+  dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)split);
+  if (split == 1) {
+    gemm64_kernel<<<grid, 256, 0, stream>>>(g, kchunk, nullptr);
+    return hipGetLastError();
+  }
+  gemm64_kernel<<<grid, 256, 0, stream>>>(g, kchunk, g.work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t total = ncols * g.M;
+  gemm64_reduce_kernel<<<(unsigned)((total + 255) / 256), 256, 0, stream>>>(g, (int)split, g.work);
   return hipGetLastError();
 }
 

@@ -83,13 +83,16 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_kernel(
 }
 
 constexpr int kLeafThreads = 128;
-constexpr int kLeafChunk = 128;
 constexpr int kLeafVec = 4;
+constexpr int kLeafChunk = 256;  // near-field sources staged per pass
+constexpr int kL2PChunk = 160;   // downward-equivalent points staged per pass
 
-// One workgroup per target leaf.  1, 2 or 4 lanes share a target (by leaf
-// occupancy) and split its sources; lanes reduce with cross-lane shuffles.
-// L2P runs in FP64 from the leaf's downward-equivalent densities; P2P runs
-// in T over the sources of the near field.
+// One workgroup per target leaf.  The near-field sources (up to 27 leaves,
+// each a contiguous run in Morton order) are staged through LDS in chunks;
+// a thread finds the run of a staged source by binary search over the run
+// offsets.  1, 2 or 4 lanes share a target (by leaf occupancy), split the
+// staged sources and reduce with cross-lane shuffles.  L2P runs in FP64 from
+// the leaf's downward-equivalent densities; P2P runs in T.
 template <typename T, typename TQ>
 __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
     const double* __restrict__ txyz, const T* __restrict__ sxyz, const TQ* __restrict__ qs,
@@ -99,8 +102,8 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
     const double* __restrict__ centers, const double* __restrict__ surf, double ar, int ns,
     const double* __restrict__ local, const int64_t* __restrict__ tperm, TQ* __restrict__ phi,
     int64_t ldphi, int nvec) {
-  __shared__ double lx[kLeafChunk], ly[kLeafChunk], lz[kLeafChunk];
-  __shared__ double lq[kLeafVec][kLeafChunk];
+  __shared__ double lx[kL2PChunk], ly[kL2PChunk], lz[kL2PChunk];
+  __shared__ double lq[kLeafVec][kL2PChunk];
   __shared__ T px[kLeafChunk], py[kLeafChunk], pz[kLeafChunk];
   __shared__ T pq[kLeafVec][kLeafChunk];
   __shared__ int32_t nb_first[27];
@@ -150,17 +153,16 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
         accp[v] = T(0);
       }
       // L2P: the leaf's downward-equivalent surface as sources (FP64)
-      for (int c0 = 0; c0 < ns; c0 += kLeafChunk) {
-        const int cn = min(kLeafChunk, ns - c0);
+      for (int c0 = 0; c0 < ns; c0 += kL2PChunk) {
+        const int cn = min(kL2PChunk, ns - c0);
         __syncthreads();
         for (int t = threadIdx.x; t < cn; t += kLeafThreads) {
           lx[t] = cx + ar * surf[3 * (c0 + t)];
           ly[t] = cy + ar * surf[3 * (c0 + t) + 1];
           lz[t] = cz + ar * surf[3 * (c0 + t) + 2];
-        }
-        for (int t = threadIdx.x; t < kLeafVec * kLeafChunk; t += kLeafThreads) {
-          const int v = t / kLeafChunk, s = t % kLeafChunk;
-          lq[v][s] = (s < cn && vb + v < nvec) ? local[((int64_t)leaf * nvec + vb + v) * ns + c0 + s] : 0.0;
+#pragma unroll
+          for (int v = 0; v < kLeafVec; ++v)
+            lq[v][t] = vb + v < nvec ? local[((int64_t)leaf * nvec + vb + v) * ns + c0 + t] : 0.0;
         }
         __syncthreads();
         if (act) {
@@ -177,19 +179,20 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
       for (int c0 = 0; c0 < total; c0 += kLeafChunk) {
         const int cn = min(kLeafChunk, total - c0);
         __syncthreads();
-        for (int t = threadIdx.x; t < kLeafChunk; t += kLeafThreads) {
-          if (t < cn) {
-            const int g = c0 + t;
-            int k = 0;
-            while (k + 1 < nnb && nb_pref[k + 1] <= g) ++k;
-            const int64_t si = (int64_t)nb_first[k] + (g - nb_pref[k]);
-            px[t] = sxyz[3 * si];
-            py[t] = sxyz[3 * si + 1];
-            pz[t] = sxyz[3 * si + 2];
-#pragma unroll
-            for (int v = 0; v < kLeafVec; ++v)
-              pq[v][t] = vb + v < nvec ? (T)qs[(int64_t)(vb + v) * n_src + si] : T(0);
+        for (int t = threadIdx.x; t < cn; t += kLeafThreads) {
+          const int g = c0 + t;
+          int lo = 0, hi = nnb - 1;  // largest k with nb_pref[k] <= g
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (nb_pref[mid] <= g) lo = mid; else hi = mid - 1;
           }
+          const int64_t si = (int64_t)nb_first[lo] + (g - nb_pref[lo]);
+          px[t] = sxyz[3 * si];
+          py[t] = sxyz[3 * si + 1];
+          pz[t] = sxyz[3 * si + 2];
+#pragma unroll
+          for (int v = 0; v < kLeafVec; ++v)
+            pq[v][t] = vb + v < nvec ? (T)qs[(int64_t)(vb + v) * n_src + si] : T(0);
         }
         __syncthreads();
         if (act) {
