@@ -105,8 +105,6 @@ kifmm_status kifmm_evaluate(kifmm_handle* h, const void* q_dev, int64_t ldq, int
   if (!q_dev || !phi_dev) return fail(KIFMM_EINVAL, "null buffer");
   if (n_vec < 1 || ldq < h->tree.n_src || ldphi < h->tree.n_tgt)
     return fail(KIFMM_EINVAL, "bad n_vec or leading dimension");
-  if (h->cfg.m2l != KIFMM_M2L_FFT && h->cfg.prec != KIFMM_FP64)
-    return fail(KIFMM_EUNSUPPORTED, "reduced-precision BLAS/dense M2L not available");
   return kifmm::device_evaluate(h, q_dev, ldq, n_vec, phi_dev, ldphi, (hipStream_t)hip_stream);
 }
 
@@ -254,8 +252,6 @@ kifmm_status kifmm_stage(kifmm_handle* h, int32_t stage, int32_t level, const vo
   if (!h->has_points || !h->op.ready) return fail(KIFMM_ESTATE, "stage before set_points / precompute");
   if (level < 2 || level > h->tree.depth) return fail(KIFMM_EINVAL, "level out of range");
   if (!in_dev || !out_dev || n_vec < 1) return fail(KIFMM_EINVAL, "bad buffers or n_vec");
-  if (h->cfg.m2l != KIFMM_M2L_FFT && h->cfg.prec != KIFMM_FP64)
-    return fail(KIFMM_EUNSUPPORTED, "reduced-precision BLAS/dense M2L not available");
   return kifmm::device_stage(h, level, in_dev, out_dev, n_vec, (hipStream_t)hip_stream);
 }
 

@@ -15,10 +15,13 @@ struct DevLevel {
   double w = 1.0;               // box width
   int32_t* child = nullptr;     // [n][8]
   int32_t* halo = nullptr;      // [26][n_{l-1}]
-  // BLAS / dense M2L: pairs grouped by transfer vector
-  std::vector<int64_t> t_offs;  // host, [317]
-  int32_t* t_tgt = nullptr;
-  int32_t* t_src = nullptr;
+  // BLAS / dense M2L: target tiles of one octant class and, per tile, the
+  // transfer vectors present with the source box of every tile slot
+  int64_t ntiles = 0;
+  int32_t* tile_box = nullptr;
+  int64_t* tl_offs = nullptr;
+  int32_t* tl_t = nullptr;
+  int32_t* tl_src = nullptr;
 };
 
 struct DeviceState {
@@ -45,8 +48,15 @@ struct DeviceState {
   void* twiddle = nullptr;
   double* Ublas = nullptr;   // ns x k
   double* UblasT = nullptr;  // k x ns
-  std::vector<double*> Ct;   // per t: k x k (not recompressed) or Vbar'^T (kt x k)
-  std::vector<double*> Ub;   // per t: Ubar (k x kt)
+  // packed per-t M2L operators of the fused kernel (see pack_blas_operators)
+  int blas_mode = 0, kp = 0;
+  bool two_stage = false;
+  int64_t* op_off = nullptr;
+  int32_t* ktp = nullptr;
+  void* op_hi = nullptr;
+  void* op_lo = nullptr;
+  int tile_tb = 0;            // target boxes per tile of the current tiles
+  void* qpad = nullptr;       // padded compressed multipoles
   std::vector<DevLevel> lv;
   // work buffers
   int nvec_cap = 0;
@@ -96,6 +106,156 @@ kifmm_status upload(DeviceState* d, T** p, const T* host, size_t count) {
     hipError_t e_ = (expr);                                                                    \
     if (e_ != hipSuccess) return fail(KIFMM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
+
+// round-to-nearest-even bf16 bits of a float
+uint16_t bf16_bits(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7FFFu + lsb;
+  return (uint16_t)(u >> 16);
+}
+float bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float x;
+  std::memcpy(&x, &u, 4);
+  return x;
+}
+
+// Position of column c of a second-product operator in its packed row, per
+// mode: FP32 keeps the order; FP64 accumulator rows are g + 4 s, so a lane's
+// four K values (c = 16 j + g + 4 s) are packed at 16 j + 4 g + s; bf16 steps
+// of 32 take Xi rows 16 h + 4 g + i of blocks (2 j, 2 j + 1), packed at
+// 32 j + 8 g + 4 h + i.
+int packed_col(int mode, int c) {
+  if (mode == 0) {
+    const int j = c / 16, r = c % 16, g = r % 4, s = r / 4;
+    return 16 * j + 4 * g + s;
+  }
+  if (mode == 2) {
+    const int j = c / 32, r = c % 32, h = r / 16, g = (r % 16) / 4, i = r % 4;
+    return 32 * j + 8 * g + 4 * h + i;
+  }
+  return c;
+}
+
+// Operators of the fused BLAS / dense M2L kernel, per t, unit box:
+//   two-stage: Vbar'_t^T (ktp x kp) then Ubar_t (kp x ktp, packed columns)
+//   single:    C_t (kp x kp)
+// ktp = k_t and kp = k rounded up to 16 (FP32 / FP64) or 32 (bf16).
+kifmm_status pack_blas_operators(kifmm_handle* h, DeviceState* d) {
+  const Operators& op = h->op;
+  const int mode = h->cfg.prec == KIFMM_FP64 ? 0 : (h->cfg.prec == KIFMM_FP32 ? 1 : 2);
+  const int q = mode == 2 ? 32 : 16;
+  const int k = op.k;
+  const int kp = (k + q - 1) / q * q;
+  if (kp > 160) return fail(KIFMM_EUNSUPPORTED, "compressed rank above 160 is not supported");
+  d->blas_mode = mode;
+  d->kp = kp;
+  d->two_stage = op.recompressed;
+  std::vector<int64_t> off(kNumTransfer);
+  std::vector<int32_t> ktp(kNumTransfer, 0);
+  std::vector<double> packed;
+  for (int t = 0; t < kNumTransfer; ++t) {
+    off[t] = (int64_t)packed.size();
+    if (!op.recompressed) {
+      std::vector<double> C((size_t)kp * kp, 0.0);
+      for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) C[(size_t)i * kp + j] = op.Vbarp[t][(size_t)i * k + j];
+      packed.insert(packed.end(), C.begin(), C.end());
+      continue;
+    }
+    const int kt = op.kt[t];
+    const int tp = (kt + q - 1) / q * q;
+    if (tp > (mode == 2 ? 64 : 48))
+      return fail(KIFMM_EUNSUPPORTED, "directional rank above the fused kernel's limit");
+    ktp[t] = tp;
+    std::vector<double> V((size_t)tp * kp, 0.0), Ub((size_t)kp * tp, 0.0);
+    for (int r = 0; r < kt; ++r)
+      for (int c = 0; c < k; ++c) V[(size_t)r * kp + c] = op.Vbarp[t][(size_t)c * kt + r];
+    for (int r = 0; r < k; ++r)
+      for (int c = 0; c < kt; ++c) Ub[(size_t)r * tp + packed_col(mode, c)] = op.Ubar[t][(size_t)r * kt + c];
+    packed.insert(packed.end(), V.begin(), V.end());
+    packed.insert(packed.end(), Ub.begin(), Ub.end());
+  }
+  KIFMM_TRY(upload(d, &d->op_off, off.data(), off.size()));
+  KIFMM_TRY(upload(d, &d->ktp, ktp.data(), ktp.size()));
+  if (mode == 0) {
+    double* p;
+    KIFMM_TRY(upload(d, &p, packed.data(), packed.size()));
+    d->op_hi = p;
+  } else if (mode == 1) {
+    std::vector<float> f(packed.begin(), packed.end());
+    float* p;
+    KIFMM_TRY(upload(d, &p, f.data(), f.size()));
+    d->op_hi = p;
+  } else {
+    std::vector<uint16_t> hi(packed.size()), lo(packed.size());
+    for (size_t i = 0; i < packed.size(); ++i) {
+      const float x = (float)packed[i];
+      hi[i] = bf16_bits(x);
+      lo[i] = bf16_bits(x - bf16_value(hi[i]));
+    }
+    uint16_t *ph, *pl;
+    KIFMM_TRY(upload(d, &ph, hi.data(), hi.size()));
+    KIFMM_TRY(upload(d, &pl, lo.data(), lo.size()));
+    d->op_hi = ph;
+    d->op_lo = pl;
+  }
+  return KIFMM_OK;
+}
+
+// Target tiles of TB boxes of one octant class per level (boxes of a class
+// share their transfer vectors) and, per tile, the transfer vectors present
+// in ascending order with the source box of each slot.
+kifmm_status build_blas_tiles(kifmm_handle* h, DeviceState* d, int TB) {
+  const Tree& t = h->tree;
+  for (int l = 2; l <= t.depth; ++l) {
+    const Level& L = t.levels[l];
+    DevLevel& D = d->lv[l];
+    for (void* p : {(void*)D.tile_box, (void*)D.tl_offs, (void*)D.tl_t, (void*)D.tl_src}) {
+      if (!p) continue;
+      hipFree(p);
+      d->allocs.erase(std::remove(d->allocs.begin(), d->allocs.end(), p), d->allocs.end());
+    }
+    std::vector<int32_t> tile_box, tl_t, tl_src;
+    std::vector<int64_t> tl_offs(1, 0);
+    std::vector<int32_t> map((size_t)TB * kNumTransfer, -1);
+    for (int o = 0; o < 8; ++o) {
+      std::vector<int32_t> boxes;
+      for (int64_t i = 0; i < L.n; ++i)
+        if ((int)(L.keys[i] & 7) == o) boxes.push_back((int32_t)i);
+      for (size_t b0 = 0; b0 < boxes.size(); b0 += TB) {
+        const size_t nb = std::min<size_t>(TB, boxes.size() - b0);
+        for (size_t sl = 0; sl < (size_t)TB; ++sl) tile_box.push_back(sl < nb ? boxes[b0 + sl] : -1);
+        for (size_t sl = 0; sl < nb; ++sl) {
+          const int32_t bx = boxes[b0 + sl];
+          for (int64_t e = L.il_offs[bx]; e < L.il_offs[bx + 1]; ++e)
+            map[(size_t)sl * kNumTransfer + L.il_t[e]] = L.il_src[e];
+        }
+        for (int tt = 0; tt < kNumTransfer; ++tt) {
+          bool any = false;
+          for (size_t sl = 0; sl < nb; ++sl) any |= map[(size_t)sl * kNumTransfer + tt] >= 0;
+          if (!any) continue;
+          tl_t.push_back(tt);
+          for (size_t sl = 0; sl < (size_t)TB; ++sl) {
+            int32_t& m = map[sl * kNumTransfer + tt];
+            tl_src.push_back(sl < nb ? m : -1);
+            m = -1;
+          }
+        }
+        tl_offs.push_back((int64_t)tl_t.size());
+      }
+    }
+    D.ntiles = (int64_t)tl_offs.size() - 1;
+    KIFMM_TRY(upload(d, &D.tile_box, tile_box.data(), tile_box.size()));
+    KIFMM_TRY(upload(d, &D.tl_offs, tl_offs.data(), tl_offs.size()));
+    KIFMM_TRY(upload(d, &D.tl_t, tl_t.data(), tl_t.size()));
+    KIFMM_TRY(upload(d, &D.tl_src, tl_src.data(), tl_src.size()));
+  }
+  d->tile_tb = TB;
+  return KIFMM_OK;
+}
 
 kifmm_status upload_all(kifmm_handle* h) {
   const Tree& t = h->tree;
@@ -156,22 +316,6 @@ kifmm_status upload_all(kifmm_handle* h) {
     if (l < depth) KIFMM_TRY(upload(d, &D.child, L.child.data(), L.child.size()));
     if (l >= 2 && h->cfg.m2l == KIFMM_M2L_FFT)
       KIFMM_TRY(upload(d, &D.halo, L.halo.data(), L.halo.size()));
-    if (l >= 2 && h->cfg.m2l != KIFMM_M2L_FFT) {
-      // pairs grouped by transfer vector (Section 3.2, step 1)
-      D.t_offs.assign(kNumTransfer + 1, 0);
-      for (size_t e = 0; e < L.il_t.size(); ++e) D.t_offs[L.il_t[e] + 1]++;
-      for (int i = 0; i < kNumTransfer; ++i) D.t_offs[i + 1] += D.t_offs[i];
-      std::vector<int32_t> tg(L.il_src.size()), sr(L.il_src.size());
-      std::vector<int64_t> pos(D.t_offs.begin(), D.t_offs.end() - 1);
-      for (int64_t i = 0; i < L.n; ++i)
-        for (int64_t e = L.il_offs[i]; e < L.il_offs[i + 1]; ++e) {
-          const int64_t k = pos[L.il_t[e]]++;
-          tg[k] = (int32_t)i;
-          sr[k] = L.il_src[e];
-        }
-      KIFMM_TRY(upload(d, &D.t_tgt, tg.data(), tg.size()));
-      KIFMM_TRY(upload(d, &D.t_src, sr.data(), sr.size()));
-    }
   }
 
   if (h->cfg.m2l == KIFMM_M2L_FFT) {
@@ -224,20 +368,7 @@ kifmm_status upload_all(kifmm_handle* h) {
       for (int j = 0; j < k; ++j) Ut[(size_t)j * ns + i] = op.U[(size_t)i * k + j];
     KIFMM_TRY(upload(d, &d->Ublas, op.U.data(), op.U.size()));
     KIFMM_TRY(upload(d, &d->UblasT, Ut.data(), Ut.size()));
-    d->Ct.assign(kNumTransfer, nullptr);
-    d->Ub.assign(kNumTransfer, nullptr);
-    for (int it = 0; it < kNumTransfer; ++it) {
-      if (!op.recompressed) {
-        KIFMM_TRY(upload(d, &d->Ct[it], op.Vbarp[it].data(), op.Vbarp[it].size()));
-      } else {
-        const int r = op.kt[it];
-        std::vector<double> vt((size_t)r * k);  // Vbar'^T, r x k
-        for (int i = 0; i < k; ++i)
-          for (int j = 0; j < r; ++j) vt[(size_t)j * k + i] = op.Vbarp[it][(size_t)i * r + j];
-        KIFMM_TRY(upload(d, &d->Ct[it], vt.data(), vt.size()));
-        KIFMM_TRY(upload(d, &d->Ub[it], op.Ubar[it].data(), op.Ubar[it].size()));
-      }
-    }
+    KIFMM_TRY(pack_blas_operators(h, d));
   }
   for (int e = 0; e < 6; ++e) KIFMM_HIP(hipEventCreate(&d->ev[e]));
   d->lev_ev.assign(4 * (depth + 1), nullptr);
@@ -248,6 +379,10 @@ kifmm_status upload_all(kifmm_handle* h) {
 
 kifmm_status ensure_work(kifmm_handle* h, int nvec) {
   DeviceState* d = h->dev;
+  if (h->cfg.m2l != KIFMM_M2L_FFT) {
+    const int TB = std::max(1, 128 / nvec);
+    if (TB != d->tile_tb) KIFMM_TRY(build_blas_tiles(h, d, TB));
+  }
   if (nvec <= d->nvec_cap) return KIFMM_OK;
   for (void* p : d->work_allocs) hipFree(p);
   d->work_allocs.clear();
@@ -276,6 +411,11 @@ kifmm_status ensure_work(kifmm_handle* h, int nvec) {
   KIFMM_TRY(dalloc(d, &d->tmp2, (size_t)maxn * nvec * kmax, true));
   d->gemm_ws_elems = (int64_t)8 << 20;  // 64 MiB of split-K partials
   KIFMM_TRY(dalloc(d, &d->gemm_ws, (size_t)d->gemm_ws_elems, true));
+  if (h->cfg.m2l != KIFMM_M2L_FFT) {
+    char* qp;
+    KIFMM_TRY(dalloc(d, &qp, (size_t)maxn * nvec * d->kp * (d->blas_mode == 0 ? 8 : 4), true));
+    d->qpad = qp;
+  }
   if (h->cfg.m2l == KIFMM_M2L_FFT) {
     int64_t maxc = 0;
     for (int l = 2; l <= depth; ++l) maxc = std::max(maxc, t.levels[l - 1].n);
@@ -333,44 +473,42 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
     if (mark) KIFMM_HIP(hipEventRecord(mark[3], s));
     return KIFMM_OK;
   }
-  // dense / compressed M2L, one product per transfer vector (Section 3.2)
+  // dense / compressed M2L (Section 3.2), fused per target tile
   const int k = op.k;
   const bool dense = h->cfg.m2l == KIFMM_M2L_DENSE;
-  const double* q = in;
-  double* acc = out;
+  const double* qsrc = in;
   if (!dense) {
     // compressed multipoles  Q~ = S^T Q  (S = U)
     Gemm64 g{d->UblasT, k, ns, ns, 1.0, in, ns, 1, nullptr, (int64_t)nvec * ns, ns,
              d->tmp, k, 1, nullptr, (int64_t)nvec * k, k, D.n, nvec, 0};
     KIFMM_LAUNCH(gemm(d, g, s));
-    q = d->tmp;
-    acc = d->tmp2;
+    qsrc = d->tmp;
   }
+  KIFMM_LAUNCH(launch_pad_convert(qsrc, k, D.n * nvec, d->kp, d->blas_mode == 0, d->qpad, s));
   if (mark) KIFMM_HIP(hipEventRecord(mark[1], s));
-  KIFMM_HIP(hipMemsetAsync(acc, 0, sizeof(double) * (size_t)D.n * nvec * k, s));
-  const double inv_w = 1.0 / D.w;
-  for (int it = 0; it < kNumTransfer; ++it) {
-    const int64_t a = D.t_offs[it], b = D.t_offs[it + 1];
-    if (b == a) continue;
-    if (!op.recompressed) {
-      Gemm64 g{d->Ct[it], k, k, k, inv_w, q, k, 1, D.t_src + a, (int64_t)nvec * k, k,
-               acc, k, 1, D.t_tgt + a, (int64_t)nvec * k, k, b - a, nvec, 1};
-      KIFMM_LAUNCH(gemm(d, g, s));
-    } else {
-      const int r = op.kt[it];
-      // xi = Vbar'^T q~[src]  (r x cols, contiguous), then acc[tgt] += Ubar xi
-      Gemm64 g1{d->Ct[it], r, k, k, inv_w, q, k, 1, D.t_src + a, (int64_t)nvec * k, k,
-                out, r, 1, nullptr, (int64_t)nvec * r, r, b - a, nvec, 0};
-      KIFMM_LAUNCH(gemm(d, g1, s));
-      Gemm64 g2{d->Ub[it], k, r, r, 1.0, out, r, 1, nullptr, (int64_t)nvec * r, r,
-                acc, k, 1, D.t_tgt + a, (int64_t)nvec * k, k, b - a, nvec, 1};
-      KIFMM_LAUNCH(gemm(d, g2, s));
-    }
-  }
+  BlasM2L b;
+  b.q = d->qpad;
+  b.kp = d->kp;
+  b.k = k;
+  b.nvec = nvec;
+  b.TB = d->tile_tb;
+  b.C = d->tile_tb * nvec;
+  b.ntiles = D.ntiles;
+  b.tile_box = D.tile_box;
+  b.tl_offs = D.tl_offs;
+  b.tl_t = D.tl_t;
+  b.tl_src = D.tl_src;
+  b.op_off = d->op_off;
+  b.ktp = d->ktp;
+  b.op_hi = d->op_hi;
+  b.op_lo = d->op_lo;
+  b.out = dense ? out : d->tmp2;
+  b.scale = 1.0 / D.w;
+  KIFMM_LAUNCH(launch_blas_m2l(b, d->blas_mode, d->two_stage, s));
   if (mark) KIFMM_HIP(hipEventRecord(mark[2], s));
   if (!dense) {
     // check potentials  Phi = U Phi~
-    Gemm64 g{d->Ublas, ns, k, k, 1.0, acc, k, 1, nullptr, (int64_t)nvec * k, k,
+    Gemm64 g{d->Ublas, ns, k, k, 1.0, d->tmp2, k, 1, nullptr, (int64_t)nvec * k, k,
              out, ns, 1, nullptr, (int64_t)nvec * ns, ns, D.n, nvec, 0};
     KIFMM_LAUNCH(gemm(d, g, s));
   }

@@ -62,4 +62,28 @@ hipError_t launch_fft_inverse(int p, bool fp64, const void* Phat, const int32_t*
                               int64_t n_clusters, int nvec, const int16_t* surf_lat,
                               const void* twiddle, double scale, double* out, hipStream_t stream);
 
+// ---- BLAS-M2L (Section 3.2) -----------------------------------------------
+// Fused per-level compressed M2L: out[box][v][0:k] = scale * sum over the
+// tile's transfer vectors t of (Ubar_t Vbar'_t^T | C_t) q[src][v][0:kp].
+// Tiles hold TB target boxes of one octant class; columns C = TB * nvec
+// <= 128.  Operators are packed per t at op_off[t] (see device.hip).
+struct BlasM2L {
+  const void* q; int kp; int k; int nvec; int TB; int C; int64_t ntiles;
+  const int32_t* tile_box;  // [ntiles][TB], -1 padded
+  const int64_t* tl_offs;   // [ntiles + 1]
+  const int32_t* tl_t;      // [E] transfer-vector index, ascending per tile
+  const int32_t* tl_src;    // [E][TB] source box per slot, -1 if none
+  const int64_t* op_off;    // [316] element offset of t's operators
+  const int32_t* ktp;       // [316] padded rank (two-stage)
+  const void* op_hi;        // FP64 / FP32 operators, or bf16 high parts
+  const void* op_lo;        // bf16 low parts
+  double* out;
+  double scale;
+};
+// mode 0 FP64, 1 FP32, 2 BF16x3
+hipError_t launch_blas_m2l(const BlasM2L& a, int mode, bool two_stage, hipStream_t stream);
+// q~ [col][k] FP64 -> [col][kp] zero-padded, FP64 or FP32
+hipError_t launch_pad_convert(const double* in, int k, int64_t ncols, int kp, bool fp64, void* out,
+                              hipStream_t stream);
+
 }  // namespace kifmm

@@ -111,3 +111,65 @@ def test_fft_full_size_sampled(prec, gate):
     say(f"  rel err vs oracle {e:.3e}")
     assert e <= gate
     assert np.all(np.isfinite(got))
+
+
+@pytest.mark.parametrize("prec,gate", [("fp64", FP64_GATE), ("fp32", FP32_GATE), ("bf16x3", FP32_GATE)])
+@pytest.mark.parametrize("nvec", [1, 3])
+def test_blas_fused_precisions(prec, gate, nvec):
+    pts = workloads.uniform_cube(20000, 93)
+    q = workloads.charges(20000, nvec, 94, "upm1")
+    say(f"case: blas {prec} tol 1e-6/1e-6 uniform 20k depth 3 p6 nvec {nvec}")
+    got, _ = evaluate(K, pts, q, 3, 6, "blas", prec, tol=1e-6, tol_dir=1e-6)
+    ref = fmm.KiFMM(pts, pts, 3, 6, m2l="blas", svd_rel_tol=1e-6, svd_rel_tol_dir=1e-6).evaluate(q)
+    e = kernel.rel_l2(got, ref)
+    say(f"  rel err vs oracle (projected operator) {e:.3e}")
+    assert e <= gate
+
+
+@pytest.mark.parametrize("prec,gate", [("fp32", FP32_GATE), ("bf16x3", FP32_GATE)])
+def test_dense_reduced_precision_20k(prec, gate):
+    w = workloads.config(1)
+    say(f"case: {w.name} dense {prec}")
+    got, _ = evaluate(K, w.points, w.q, w.depth, w.order, "dense", prec)
+    ref = fmm.KiFMM(w.points, w.points, w.depth, w.order).evaluate(w.q)
+    e = kernel.rel_l2(got, ref)
+    say(f"  rel err vs oracle {e:.3e}")
+    assert e <= gate
+
+
+# FP32 stage gate: inner products of up to k ~ 130 terms in FP32 round to about
+# sqrt(k) * 2^-24 ~ 7e-7 relative; bf16x3 operands carry about 16 bits.
+@pytest.mark.parametrize("prec,gate", [("fp64", 1e-12), ("fp32", 2e-6), ("bf16x3", 2e-5)])
+@pytest.mark.parametrize("tol_dir", [1e-6, -1.0])
+def test_blas_stage_check_potentials(prec, gate, tol_dir):
+    pts = workloads.sphere_surface(30000, 95)
+    ora = fmm.KiFMM(pts, pts, 5, 5, origin=(-1, -1, -1), width=2.0, m2l="blas",
+                    svd_rel_tol=1e-7, svd_rel_tol_dir=tol_dir)
+    f = K.KiFMM(5, 5, m2l="blas", prec=prec, origin=(-1, -1, -1), width=2.0, svd_rel_tol=1e-7,
+                svd_rel_tol_dir=tol_dir).set_points(pts).precompute()
+    rng = np.random.default_rng(96)
+    for lev in (2, 4, 5):
+        nb = len(ora.tree.levels[lev])
+        mult = rng.standard_normal((nb, 5, ora.ns))
+        say(f"case: stage blas {prec} tol_dir {tol_dir} level {lev} boxes {nb} nvec 5")
+        out = f.stage_m2l(lev, torch.as_tensor(mult, device="cuda"))
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        ref = ora.m2l_level(lev, mult.transpose(0, 2, 1)).transpose(0, 2, 1)
+        e = kernel.rel_l2(got, ref)
+        say(f"  rel err {e:.3e}")
+        assert e <= gate
+
+
+@pytest.mark.parametrize("prec,gate", [("fp32", FP32_GATE), ("bf16x3", FP32_GATE)])
+def test_blas_full_size_sampled(prec, gate):
+    w = workloads.config(3, nvec=8)
+    s = workloads.sample_indices(w.n, 24, workloads.SEED_SAMPLES + 3)
+    say(f"case: {w.name} (8 of 32 vectors) {prec} at 24 sampled targets")
+    got, _ = evaluate(K, w.points, w.q, w.depth, w.order, "blas", prec, tol=1e-6, tol_dir=1e-6)
+    ref = fmm.KiFMM(w.points, w.points, w.depth, w.order, m2l="blas", svd_rel_tol=1e-6,
+                    svd_rel_tol_dir=1e-6).evaluate(w.q, s)
+    e = kernel.rel_l2(got[:, s], ref)
+    say(f"  rel err vs oracle (projected operator) {e:.3e}")
+    assert e <= gate
+    assert np.all(np.isfinite(got))
