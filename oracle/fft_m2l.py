@@ -16,6 +16,10 @@ positions with zeros elsewhere.  The check potential at lattice point a is
 entry a of the inverse DFT of DFT(G) * DFT(D).  Since 2P > 2P - 1 the
 circular convolution does not wrap onto used entries.  The kernel being real,
 only (2P)^2 (P + 1) Fourier coefficients are independent (Appendix A.2).
+
+The same argument holds for any grid of n >= 2P - 1 points per axis (the
+offsets m span 2P - 1 values); every function takes the grid size ``n``,
+2P by default as in the paper.
 """
 
 from __future__ import annotations
@@ -26,9 +30,11 @@ from .kernel import INV_4PI
 from .surfaces import lattice_indices
 
 
-def kernel_grid(p: int, spacing: float, dc: np.ndarray) -> np.ndarray:
-    """G on the (2p)^3 grid for centre offset dc = c_target - c_source."""
-    n = 2 * p
+def kernel_grid(p: int, spacing: float, dc: np.ndarray, n: int | None = None) -> np.ndarray:
+    """G on the n^3 grid (n = 2p by default) for centre offset dc = c_target - c_source."""
+    n = 2 * p if n is None else n
+    if n < 2 * p - 1:
+        raise ValueError("grid too small: the circular convolution would wrap")
     g = np.zeros((n, n, n))
     r = np.arange(-(p - 1), p)
     mx, my, mz = np.meshgrid(r, r, r, indexing="ij")
@@ -38,24 +44,25 @@ def kernel_grid(p: int, spacing: float, dc: np.ndarray) -> np.ndarray:
     return g
 
 
-def density_grid(p: int, q: np.ndarray) -> np.ndarray:
-    """Densities (n_s,) on their lattice positions of the (2p)^3 grid."""
-    n = 2 * p
+def density_grid(p: int, q: np.ndarray, n: int | None = None) -> np.ndarray:
+    """Densities (n_s,) on their lattice positions of the n^3 grid."""
+    n = 2 * p if n is None else n
     d = np.zeros((n, n, n))
     idx = lattice_indices(p)
     d[idx[:, 0], idx[:, 1], idx[:, 2]] = q
     return d
 
 
-def kernel_spectrum(p: int, spacing: float, dc: np.ndarray) -> np.ndarray:
-    """Real-to-complex spectrum, shape (2p, 2p, p+1)."""
-    return np.fft.rfftn(kernel_grid(p, spacing, dc))
+def kernel_spectrum(p: int, spacing: float, dc: np.ndarray, n: int | None = None) -> np.ndarray:
+    """Real-to-complex spectrum, shape (n, n, n // 2 + 1)."""
+    return np.fft.rfftn(kernel_grid(p, spacing, dc, n))
 
 
-def check_potential(p: int, spacing: float, dc: np.ndarray, q: np.ndarray) -> np.ndarray:
+def check_potential(p: int, spacing: float, dc: np.ndarray, q: np.ndarray,
+                    n: int | None = None) -> np.ndarray:
     """Check potential (n_s,) of densities q through the convolution grid."""
-    n = 2 * p
-    spec = kernel_spectrum(p, spacing, dc) * np.fft.rfftn(density_grid(p, q))
+    n = 2 * p if n is None else n
+    spec = kernel_spectrum(p, spacing, dc, n) * np.fft.rfftn(density_grid(p, q, n))
     full = np.fft.irfftn(spec, s=(n, n, n), axes=(0, 1, 2))
     idx = lattice_indices(p)
     return full[idx[:, 0], idx[:, 1], idx[:, 2]]

@@ -34,17 +34,26 @@ def test_dense_m2l_equals_explicit_pair_products():
 
 
 @pytest.mark.parametrize("p", [2, 3, 4, 6])
-def test_fft_m2l_equals_dense_toeplitz_product(p):
+@pytest.mark.parametrize("grid", ["2p", "2p-1"])
+def test_fft_m2l_equals_dense_toeplitz_product(p, grid):
     rng = np.random.default_rng(p)
     r = 0.125
     h = 2 * 1.05 * r / (p - 1)
+    n = 2 * p if grid == "2p" else 2 * p - 1
     x = surfaces.surface(p, 1.05, r)
     for it in range(0, 316, 5):
         t = TRANSFER_VECTORS[it] * 2 * r
         q = rng.standard_normal(surfaces.n_surface(p))
         dense = kernel.kernel_matrix(x, surfaces.surface(p, 1.05, r, t)) @ q
-        fft = fft_m2l.check_potential(p, h, -t, q)
+        fft = fft_m2l.check_potential(p, h, -t, q, n)
         assert np.linalg.norm(fft - dense) <= 1e-13 * np.linalg.norm(dense) * p
+
+
+def test_fft_grid_below_2p_minus_1_wraps():
+    # one point fewer than 2p - 1 folds the kernel onto used entries
+    p, r = 4, 0.125
+    with pytest.raises(ValueError):
+        fft_m2l.kernel_grid(p, 2 * 1.05 * r / (p - 1), np.array([0.5, 0.0, 0.0]), 2 * p - 2)
 
 
 def test_fft_storage_matches_paper_table(repo_root):
