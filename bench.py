@@ -42,8 +42,8 @@ def log(msg):
 
 def m2l_work(f, depth, order, nvec, prec):
     """Algorithmic flops of the Hadamard launches and HBM bytes of the M2L."""
-    n = 2 * order
-    F = n * n * (order + 1)
+    n = 2 * order - 1
+    F = n * n * (n // 2 + 1)
     ns = 6 * (order - 1) ** 2 + 2
     cb = 8 if prec == "fp32" else 16
     had_flops = 0.0
@@ -121,6 +121,66 @@ def direct_error(torch, w, phi, n_sample=1000):
     return float(torch.linalg.norm(got - ref) / torch.linalg.norm(ref))
 
 
+def run_blas(K, torch, steps, warmup):
+    """The 32-vector BLAS-M2L workload in FP64, FP32 and bf16x3."""
+    import workloads
+    w = workloads.config(3)
+    out = {"workload": w.name, "n_vec": w.nvec, "svd_rel_tol": 1e-6, "svd_rel_tol_dir": 1e-6}
+    ref_phi = None
+    flops = None
+    for prec in ("fp64", "fp32", "bf16x3"):
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        t0 = time.perf_counter()
+        f = K.KiFMM(w.order, w.depth, m2l="blas", prec=prec, svd_rel_tol=1e-6,
+                    svd_rel_tol_dir=1e-6).set_points(w.points).precompute()
+        setup_s = time.perf_counter() - t0
+        if flops is None:
+            ranks = f.operator(K.OP_BLAS_RANKS)
+            k, kt = int(ranks[0]), ranks[1:]
+            flops = 0.0
+            for lev in range(2, w.depth + 1):
+                _, _, tid = f.interactions(lev)
+                cnt = np.bincount(tid, minlength=316)
+                flops += float(np.sum(cnt * 4.0 * k * kt)) * w.nvec
+            out["k"] = k
+            out["kt_mean"] = round(float(kt.mean()), 2)
+        q = torch.as_tensor(w.q, dtype=dt, device="cuda")
+        phi = torch.empty((w.nvec, w.n), dtype=dt, device="cuda")
+        for _ in range(warmup):
+            f.evaluate(q, phi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            f.evaluate(q, phi)
+        torch.cuda.synchronize()
+        ms_step = (time.perf_counter() - t0) / steps * 1e3
+        f.set_timing(True)
+        acc = {}
+        for _ in range(steps):
+            f.evaluate(q, phi)
+            for kk, v in f.timings().items():
+                acc[kk] = acc.get(kk, 0.0) + v
+        f.set_timing(False)
+        tm = {kk: v / steps for kk, v in acc.items()}
+        if ref_phi is None:
+            ref_phi = phi.double().clone()
+        rel = float(torch.linalg.norm(phi.double() - ref_phi) / torch.linalg.norm(ref_phi))
+        main_s = tm["m2l_main"] * 1e-3
+        peak = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2500e12 / 3}[prec]
+        out[prec] = {"m2l_ms": round(tm["m2l"], 3), "m2l_ms_per_vector": round(tm["m2l"] / w.nvec, 4),
+                     "fused_kernel_ms": round(tm["m2l_main"], 3), "ms_per_step": round(ms_step, 3),
+                     "fused_tflops": round(flops / main_s / 1e12, 2),
+                     "fused_frac_of_peak": round(flops / main_s / peak, 4),
+                     "rel_err_vs_fp64_run": rel, "setup_s": round(setup_s, 2)}
+        log(f"  blas {prec}: step {ms_step:.2f} ms, m2l {tm['m2l']:.2f} ms (fused {tm['m2l_main']:.2f}), "
+            f"{flops / main_s / 1e12:.1f} TFLOP/s, rel vs fp64 {rel:.2e}")
+        del f, q, phi
+        torch.cuda.empty_cache()
+    out["algorithmic_gflop"] = round(flops / 1e9, 1)
+    out["peaks_tflops"] = {"fp64": 78.6, "fp32": 157.3, "bf16x3": round(2500 / 3, 1)}
+    return out
+
+
 def cpu_baseline(w, budget_boxes=2048):
     """FP64 oracle dense M2L timed on a bounded sample of target boxes."""
     from oracle import fmm
@@ -159,6 +219,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-blas", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the FMM here is a single-GPU build "
@@ -248,6 +309,9 @@ def main():
                          "(8 cores); 240 ms on AMD 3790X at depth 4 (32 cores) - CPU context only",
         "setup_s": {"fp32": round(mix["setup_s"], 2), "fp64": round(ref["setup_s"], 2)},
     }
+    if not args.no_blas:
+        log("blas-m2l workload: 32 vectors, fp64 / fp32 / bf16x3")
+        line["blas_32rhs"] = run_blas(K, torch, max(1, min(args.steps, 3)), 1)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle dense M2L on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(w)

@@ -7,8 +7,9 @@
  * uniform octree (Section 2), and applies the multipole-to-local (M2L)
  * translation in one of three forms:
  *   KIFMM_M2L_DENSE - the uncompressed M2L matvec of Section 2.2,
- *   KIFMM_M2L_FFT   - the convolution form on a 2P-point grid with Hadamard
- *                     products grouped by sibling cluster (Appendix A.1-A.2),
+ *   KIFMM_M2L_FFT   - the convolution form (Appendix A.1-A.2) on a grid of
+ *                     2P-1 points per axis, Hadamard products grouped by
+ *                     sibling cluster,
  *   KIFMM_M2L_BLAS  - SVD-compressed operators with directional
  *                     recompression (Section 3.1-3.2).
  *
@@ -156,10 +157,12 @@ kifmm_status kifmm_near(const kifmm_handle* h, int64_t* offs, int64_t* src, int6
  *   0 KIFMM_OP_UP_PINV_V, 1 KIFMM_OP_UP_PINV_UT, 2 KIFMM_OP_DOWN_PINV_V,
  *   3 KIFMM_OP_DOWN_PINV_UT (unit box, level scale applied by the library),
  *   4 KIFMM_OP_FFT_SPECTRA: kernel spectra of the unit box, [316][F] complex
- *     as interleaved (re, im) doubles with F = (2p)^2 (p+1) ordered
- *     [kx][ky][kz], kz fastest; the convolution grid is the reading of
- *     Appendix A.1 stated in the design doc (kernel at offset m mod 2p,
- *     densities at their lattice positions);
+ *     as interleaved (re, im) doubles with F = n^2 (n/2 + 1), n = 2p - 1,
+ *     ordered [kx][ky][kz], kz fastest.  Convolution grid (Appendix A.1):
+ *     n = 2p - 1 points per axis (enough for the circular convolution not
+ *     to wrap; the paper pads to 2p), kernel value K(c_tau - c_sigma + h m)
+ *     at index m mod n for m in [-(p-1), p-1]^3, densities at their lattice
+ *     positions;
  *   5 KIFMM_OP_BLAS_U: U (n_s x k, row-major), 6 KIFMM_OP_BLAS_RANKS: k then
  *     k_t for the 316 transfer vectors (as doubles), 7 KIFMM_OP_BLAS_APPLIED:
  *     the applied operator U Ubar_t Vbar'_t^T S^T of every t, [316][n_s][n_s],

@@ -467,7 +467,7 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
     if (mark) KIFMM_HIP(hipEventRecord(mark[1], s));
     KIFMM_LAUNCH(launch_hadamard(d->fp64, op.F, d->khat, d->Qhat, D.halo, nc, nvec, d->Phat, s));
     if (mark) KIFMM_HIP(hipEventRecord(mark[2], s));
-    const double scale = 1.0 / ((double)op.n * op.n * op.n * D.w);
+    const double scale = 1.0 / ((double)op.n * op.n * op.n * D.w);  // 1 / (n^3 w)
     KIFMM_LAUNCH(launch_fft_inverse(op.p, d->fp64, d->Phat, child, nc, nvec, d->surf_lat,
                                     d->twiddle, scale, out, s));
     if (mark) KIFMM_HIP(hipEventRecord(mark[3], s));

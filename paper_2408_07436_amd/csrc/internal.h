@@ -79,7 +79,7 @@ bool svd_left_wide(const double* A, int m, int n, std::vector<double>& U, std::v
 
 // ---- operators ------------------------------------------------------------
 struct Operators {
-  int p = 0, ns = 0, F = 0, n = 0;  // order, surface points, spectrum length, grid size 2p
+  int p = 0, ns = 0, F = 0, n = 0;  // order, surface points, spectrum length, grid size 2p-1
   double ai = 1.05, ao = 2.95;
   std::vector<double> surf;         // [ns][3] unit offsets -1 + 2 i/(p-1)
   std::vector<int32_t> lattice;     // [ns][3] integer positions

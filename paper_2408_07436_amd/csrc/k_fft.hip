@@ -1,8 +1,9 @@
 // FFT-M2L on gfx950 (Appendix A.1-A.2 of arXiv 2408.07436).
 //
 // 1. fft_forward: the upward-equivalent densities of each box sit on the
-//    (2p)^3 convolution grid at their lattice positions (zeros elsewhere).
-//    A real-to-complex 3D DFT that skips the zero planes gives (2p)^2 (p+1)
+//    (2p-1)^3 convolution grid at their lattice positions (zeros elsewhere;
+//    2p - 1 points per axis are enough for the convolution not to wrap).  A
+//    real-to-complex 3D DFT that skips the zero planes gives (2p-1)^2 p
 //    coefficients per box, written in frequency order [f][cluster, v][child]
 //    so that the eight siblings of a cluster are contiguous per frequency.
 // 2. hadamard: for every frequency f and target cluster, the 8 x 8 complex
@@ -13,7 +14,8 @@
 //    with the A operand gathered through the halo table; it runs on
 //    v_mfma_f32_16x16x4f32 (FP32) or v_mfma_f64_16x16x4f64 (FP64).
 // 3. fft_inverse: complex inverse DFTs along x and y, then the c2r step along
-//    z, evaluated only at the check-surface lattice points.
+//    z (odd length: no Nyquist term), evaluated only at the check-surface
+//    lattice points.
 #include "kernels.h"
 
 namespace kifmm {
@@ -48,7 +50,7 @@ __global__ __launch_bounds__(kFftThreads) void fft_forward_kernel(
     const int16_t* __restrict__ lat2surf, const typename C2T<T>::type* __restrict__ tw,
     typename C2T<T>::type* __restrict__ Qhat) {
   using C2 = typename C2T<T>::type;
-  constexpr int N = 2 * P, H = P + 1, NS = 6 * (P - 1) * (P - 1) + 2;
+  constexpr int N = 2 * P - 1, H = P, NS = 6 * (P - 1) * (P - 1) + 2;
   __shared__ C2 w[N];
   __shared__ int16_t l2s[P * P * P];
   __shared__ T sv[ITEMS][NS];
@@ -70,7 +72,7 @@ __global__ __launch_bounds__(kFftThreads) void fft_forward_kernel(
     sv[it][s] = (T)val;
   }
   __syncthreads();
-  // z: real -> complex, kz in [0, p]
+  // z: real -> complex, kz in [0, p)
   for (int idx = tid; idx < ITEMS * P * P * H; idx += kFftThreads) {
     const int it = idx / (P * P * H);
     const int rem = idx % (P * P * H);
@@ -134,7 +136,7 @@ __global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(
     int64_t n_rows, int nvec, const int16_t* __restrict__ surf_lat,
     const typename C2T<T>::type* __restrict__ tw, double scale, double* __restrict__ out) {
   using C2 = typename C2T<T>::type;
-  constexpr int N = 2 * P, H = P + 1, NS = 6 * (P - 1) * (P - 1) + 2;
+  constexpr int N = 2 * P - 1, H = P, NS = 6 * (P - 1) * (P - 1) + 2;
   __shared__ C2 w[N];
   __shared__ C2 b2[ITEMS][P][N][H];
   __shared__ C2 b1[ITEMS][P][P][H];
@@ -200,10 +202,10 @@ __global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(
     const int32_t box = child[c * 8 + (g % 8)];
     if (box < 0) continue;
     const int x = surf_lat[3 * s], y = surf_lat[3 * s + 1], z = surf_lat[3 * s + 2];
-    T val = b1[it][x][y][0].x + ((z & 1) ? -b1[it][x][y][P].x : b1[it][x][y][P].x);
+    T val = b1[it][x][y][0].x;
     T acc = T(0);
 #pragma unroll
-    for (int kz = 1; kz < P; ++kz) acc += cmulc(b1[it][x][y][kz], w[(kz * z) % N]).x;
+    for (int kz = 1; kz < H; ++kz) acc += cmulc(b1[it][x][y][kz], w[(kz * z) % N]).x;
     val += T(2) * acc;
     out[((int64_t)box * nvec + v) * NS + s] = scale * (double)val;
   }
@@ -296,30 +298,41 @@ __global__ __launch_bounds__(kHadThreads) void hadamard_kernel(
     const bool valid = row < n_rows;
     const int64_t c = valid ? row / nvec : 0;
     const int v = valid ? (int)(row - c * nvec) : 0;
-    V4 acc;
-    acc[0] = acc[1] = acc[2] = acc[3] = T(0);
+    // two accumulators (even / odd directions) so consecutive MFMAs are
+    // independent; absent neighbours read row 0 and are zeroed by a select
+    V4 acc0, acc1;
+    acc0[0] = acc0[1] = acc0[2] = acc0[3] = T(0);
+    acc1 = acc0;
+    const T* qv = Qhat + (fbase * 16 + (int64_t)v * 16 + 4 * g);
 #pragma unroll
     for (int d0 = 0; d0 < 26; d0 += DC) {
       int32_t nb[DC];
 #pragma unroll
-      for (int dd = 0; dd < DC; ++dd) nb[dd] = valid ? halo[(int64_t)(d0 + dd) * n_c + c] : -1;
+      for (int dd = 0; dd < DC; ++dd) {
+        const int32_t h = halo[(int64_t)(d0 + dd) * n_c + c];  // c = 0 for padding rows
+        nb[dd] = valid ? h : -1;
+      }
       T4 a[DC];
 #pragma unroll
       for (int dd = 0; dd < DC; ++dd) {
-        if (nb[dd] >= 0)
-          a[dd] = load4(Qhat + ((fbase + (int64_t)nb[dd] * nvec + v) * 16 + 4 * g));
-        else
-          a[dd] = T4{T(0), T(0), T(0), T(0)};
+        const int64_t src = (int64_t)(nb[dd] < 0 ? 0 : nb[dd]) * nvec;
+        const T4 x = load4(qv + src * 16);
+        const T keep = nb[dd] < 0 ? T(0) : T(1);
+        a[dd] = T4{x.x * keep, x.y * keep, x.z * keep, x.w * keep};
       }
 #pragma unroll
       for (int dd = 0; dd < DC; ++dd) {
         const T4 bv = Bl[d0 + dd][lane];
+        V4& acc = ((d0 + dd) & 1) ? acc1 : acc0;
         acc = mfma16(a[dd].x, bv.x, acc);
         acc = mfma16(a[dd].y, bv.y, acc);
         acc = mfma16(a[dd].z, bv.z, acc);
         acc = mfma16(a[dd].w, bv.w, acc);
       }
     }
+    V4 acc;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = acc0[i] + acc1[i];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int64_t r = row0 + out_row(T(0), g, i);
@@ -354,7 +367,7 @@ hipError_t inv_launch(const void* Phat, const int32_t* child, int64_t n_rows, in
 // items per workgroup, sized so the LDS stays within 64 KiB
 template <typename T, int P> struct Items {
   static constexpr int bytes = sizeof(T) * 2;
-  static constexpr int per = P * (2 * P) * (P + 1) * bytes + P * P * (P + 1) * bytes;  // inverse
+  static constexpr int per = P * (2 * P - 1) * P * bytes + P * P * P * bytes;  // inverse
   static constexpr int raw = 49152 / per;
   static constexpr int value = raw >= 16 ? 16 : raw >= 8 ? 8 : raw >= 4 ? 4 : raw >= 2 ? 2 : 1;
 };

@@ -108,8 +108,11 @@ kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg) {
         }
       }
   op.ns = (int)op.lattice.size() / 3;
-  op.n = 2 * p;
-  op.F = op.n * op.n * (p + 1);
+  // convolution grid of 2p - 1 points per axis: the offsets of check and
+  // equivalent lattice points span 2p - 1 values, so the circular
+  // convolution does not wrap (the paper pads to 2p)
+  op.n = 2 * p - 1;
+  op.F = op.n * op.n * (op.n / 2 + 1);
   const int ns = op.ns;
   const double zero[3] = {0, 0, 0};
 
@@ -138,7 +141,7 @@ kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg) {
   }
 
   if (cfg.m2l == KIFMM_M2L_FFT) {
-    // kernel sequences G[m] = K(c_tau - c_sigma + h m) on the 2p grid
+    // kernel sequences G[m] = K(c_tau - c_sigma + h m) on the (2p-1)^3 grid
     const int n = op.n;
     const double h = 2.0 * op.ai * 0.5 / (p - 1);
     op.spectra.assign((size_t)kNumTransfer * op.F * 2, 0.0);

@@ -61,8 +61,10 @@ def test_fft_spectra_match_oracle():
     f = K.KiFMM(p, 3, m2l="fft").set_points(workloads.uniform_cube(100, 55)).precompute()
     spec = f.operator(K.OP_FFT_SPECTRA).reshape(316, -1, 2)
     h = 2 * surfaces.ALPHA_INNER * 0.5 / (p - 1)
+    n = 2 * p - 1
+    assert spec.shape[1] == n * n * (n // 2 + 1)
     for it in range(0, 316, 3):
-        ref = fft_m2l.kernel_spectrum(p, h, -T.TRANSFER_VECTORS[it].astype(float)).ravel()
+        ref = fft_m2l.kernel_spectrum(p, h, -T.TRANSFER_VECTORS[it].astype(float), n).ravel()
         got = spec[it, :, 0] + 1j * spec[it, :, 1]
         assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max()
 
