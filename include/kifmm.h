@@ -200,6 +200,29 @@ kifmm_status kifmm_timings(const kifmm_handle* h, double* ms, int32_t cap);
  * halos.  cap >= 4. */
 kifmm_status kifmm_m2l_counts(const kifmm_handle* h, int32_t level, int64_t* counts, int32_t cap);
 
+/* ---- batches of independent problems ------------------------------------ */
+
+/* A batch replays the evaluates of n independent, precomputed handles with
+ * one graph launch (many problems of uneven sizes served together).
+ * kifmm_batch_create runs every evaluate once eagerly on hip_stream (which
+ * finishes all lazy device setup), then records them into one HIP graph:
+ * problem i is captured on its own forked stream, so the problems are
+ * independent branches of the graph.  The device buffers q_dev[i] /
+ * phi_dev[i] (layout and types as in kifmm_evaluate, n_vec[i] vectors,
+ * leading dimensions ldq[i] / ldphi[i]) are captured by address: they must
+ * stay valid, and a launch reads the charges they hold at that time.  A
+ * handle may appear at most once; handles must not be evaluated or changed
+ * while a batch that holds them is alive.  EINVAL: bad arguments or a
+ * repeated handle; ESTATE: a handle without points or operators. */
+typedef struct kifmm_batch kifmm_batch;
+kifmm_status kifmm_batch_create(kifmm_handle* const* handles, int32_t n, const void* const* q_dev,
+                                const int64_t* ldq, const int32_t* n_vec, void* const* phi_dev,
+                                const int64_t* ldphi, void* hip_stream, kifmm_batch** out);
+/* Launch the recorded graph on hip_stream (asynchronous). */
+kifmm_status kifmm_batch_launch(kifmm_batch* batch, void* hip_stream);
+/* Destroy the graph and its capture streams (not the handles). */
+kifmm_status kifmm_batch_destroy(kifmm_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

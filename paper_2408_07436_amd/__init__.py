@@ -25,7 +25,8 @@ EXPORTS = [
     "kifmm_config_default", "kifmm_create", "kifmm_set_points", "kifmm_precompute",
     "kifmm_evaluate", "kifmm_destroy", "kifmm_last_error", "kifmm_num_boxes", "kifmm_box_keys",
     "kifmm_point_perm", "kifmm_interactions", "kifmm_near", "kifmm_operator", "kifmm_stage",
-    "kifmm_set_timing", "kifmm_timings", "kifmm_m2l_counts",
+    "kifmm_set_timing", "kifmm_timings", "kifmm_m2l_counts", "kifmm_batch_create",
+    "kifmm_batch_launch", "kifmm_batch_destroy",
 ]
 
 
@@ -83,6 +84,11 @@ def lib() -> ctypes.CDLL:
     L.kifmm_set_timing.argtypes = [vp, i32]
     L.kifmm_timings.argtypes = [vp, dp, i32]
     L.kifmm_m2l_counts.argtypes = [vp, i32, ctypes.POINTER(i64), i32]
+    L.kifmm_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(i64),
+                                     ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(i64), vp,
+                                     ctypes.POINTER(vp)]
+    L.kifmm_batch_launch.argtypes = [vp, vp]
+    L.kifmm_batch_destroy.argtypes = [vp]
     for name in EXPORTS:
         if name not in ("kifmm_config_default", "kifmm_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -241,6 +247,48 @@ class KiFMM:
         c = np.zeros(4, dtype=np.int64)
         _check(lib().kifmm_m2l_counts(self._h, level, _ptr(c, ctypes.c_int64), 4))
         return dict(boxes=int(c[0]), pairs=int(c[1]), clusters=int(c[2]), cluster_pairs=int(c[3]))
+
+
+class Batch:
+    """Independent problems replayed with one graph launch (see kifmm_batch_create).
+
+    ``items`` is a list of (KiFMM, q, phi) with device tensors q (nvec, n_src)
+    and phi (nvec, n_tgt) that stay alive as long as the batch.
+    """
+
+    def __init__(self, items, stream=None):
+        import torch
+        n = len(items)
+        self._items = items
+        hs = (ctypes.c_void_p * n)(*[f._h.value for f, _, _ in items])
+        qs = (ctypes.c_void_p * n)(*[q.data_ptr() for _, q, _ in items])
+        ps = (ctypes.c_void_p * n)(*[p.data_ptr() for _, _, p in items])
+        ldq = (ctypes.c_int64 * n)(*[q.stride(0) for _, q, _ in items])
+        ldp = (ctypes.c_int64 * n)(*[p.stride(0) for _, _, p in items])
+        nv = (ctypes.c_int32 * n)(*[q.shape[0] for _, q, _ in items])
+        for f, q, p in items:
+            assert q.is_cuda and p.is_cuda and q.dtype == f.dtype and p.dtype == f.dtype
+        s = torch.cuda.current_stream() if stream is None else stream
+        b = ctypes.c_void_p()
+        _check(lib().kifmm_batch_create(hs, n, qs, ldq, nv, ps, ldp, ctypes.c_void_p(s.cuda_stream),
+                                        ctypes.byref(b)))
+        self._b = b
+
+    def launch(self, stream=None):
+        import torch
+        s = torch.cuda.current_stream() if stream is None else stream
+        _check(lib().kifmm_batch_launch(self._b, ctypes.c_void_p(s.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            lib().kifmm_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 OP_UP_V, OP_UP_UT, OP_DOWN_V, OP_DOWN_UT, OP_FFT_SPECTRA, OP_BLAS_U, OP_BLAS_RANKS, OP_BLAS_APPLIED = range(8)

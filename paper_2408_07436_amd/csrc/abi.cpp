@@ -1,7 +1,10 @@
 // extern "C" entry points of libkifmm (declared in include/kifmm.h).
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 
 #include "internal.h"
 
@@ -94,7 +97,27 @@ kifmm_status kifmm_precompute(kifmm_handle* h) {
     kifmm::destroy_device(h->dev);
     h->dev = nullptr;
   }
-  return kifmm::precompute_operators(h->op, h->cfg);
+  // operators depend only on the configuration (Section 5.1): one FP64
+  // precomputation per distinct configuration and process
+  using Key = std::tuple<int, int, double, double, double, double>;
+  static std::mutex mu;
+  static std::map<Key, kifmm::Operators> cache;
+  const kifmm_config& c = h->cfg;
+  const Key key{c.order, c.m2l, c.m2l == KIFMM_M2L_BLAS ? c.svd_rel_tol : 0.0,
+                c.m2l == KIFMM_M2L_BLAS ? c.svd_rel_tol_dir : 0.0, c.alpha_inner, c.alpha_outer};
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      h->op = it->second;
+      return KIFMM_OK;
+    }
+  }
+  kifmm_status st = kifmm::precompute_operators(h->op, h->cfg);
+  if (st != KIFMM_OK) return st;
+  std::lock_guard<std::mutex> lock(mu);
+  cache.emplace(key, h->op);
+  return KIFMM_OK;
 }
 
 kifmm_status kifmm_evaluate(kifmm_handle* h, const void* q_dev, int64_t ldq, int32_t n_vec,

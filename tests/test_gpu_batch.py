@@ -1,0 +1,79 @@
+"""Batches of independent problems replayed as one HIP graph: every replay
+must reproduce the eager evaluate of each problem bit for bit, also after
+the charges change and with eager work between replays."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import fmm, kernel
+
+from gpu_util import say
+
+K = pytest.importorskip("paper_2408_07436_amd")
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+PROBLEMS = [
+    # n, depth, p, m2l, prec, nvec
+    (4000, 3, 4, "fft", "fp32", 1),
+    (12000, 3, 5, "fft", "fp32", 3),
+    (20000, 4, 6, "fft", "fp32", 2),
+    (9000, 3, 4, "blas", "bf16x3", 4),
+    (7000, 3, 3, "dense", "fp64", 1),
+    (15000, 4, 5, "fft", "fp64", 5),
+]
+
+
+def build(i, n, depth, p, m2l, prec, nvec):
+    pts = workloads.uniform_cube(n, 7000 + i)
+    q = workloads.charges(n, nvec, 7100 + i, "upm1")
+    kw = dict(svd_rel_tol=1e-6, svd_rel_tol_dir=1e-6) if m2l == "blas" else {}
+    f = K.KiFMM(p, depth, m2l=m2l, prec=prec, **kw).set_points(pts).precompute()
+    qt = torch.as_tensor(q, dtype=f.dtype, device="cuda")
+    return f, pts, q, qt
+
+
+def test_batch_graph_replays_match_eager():
+    items, eager, hosts = [], [], []
+    for i, spec in enumerate(PROBLEMS):
+        f, pts, q, qt = build(i, *spec)
+        ref = f.evaluate(qt).clone()
+        phi = torch.full_like(ref, float("nan"))
+        items.append((f, qt, phi))
+        eager.append(ref)
+        hosts.append((pts, q))
+    torch.cuda.synchronize()
+    say(f"case: batch of {len(items)} problems, graph capture")
+    b = K.Batch(items)
+    for rep in range(3):
+        for _, _, phi in items:
+            phi.fill_(float("nan"))
+        b.launch()
+        torch.cuda.synchronize()
+        for i, (_, _, phi) in enumerate(items):
+            assert torch.equal(phi, eager[i]), f"replay {rep} problem {i}"
+        # eager work between replays
+        items[0][0].evaluate(items[0][1])
+        torch.cuda.synchronize()
+    # new charges in place: the replay reads them
+    for _, qt, _ in items:
+        qt.mul_(2.0)
+    b.launch()
+    torch.cuda.synchronize()
+    for i, (_, _, phi) in enumerate(items):
+        assert torch.equal(phi, 2.0 * eager[i]), f"scaled charges problem {i}"
+    b.close()
+    # one problem against the oracle
+    pts, q = hosts[2]
+    ref = fmm.KiFMM(pts, pts, 4, 6).evaluate(q)
+    e = kernel.rel_l2(eager[2].cpu().numpy().astype(np.float64), ref)
+    say(f"  problem 2 rel err vs oracle {e:.3e}")
+    assert e <= 1e-5
+
+
+def test_batch_rejects_repeated_handle():
+    f, _, _, qt = build(0, *PROBLEMS[0])
+    phi = torch.empty((1, 4000), dtype=f.dtype, device="cuda")
+    with pytest.raises(K.KifmmError) as e:
+        K.Batch([(f, qt, phi), (f, qt, phi)])
+    assert e.value.code == 1
