@@ -181,6 +181,70 @@ def run_blas(K, torch, steps, warmup):
     return out
 
 
+def run_batch(K, torch, launches):
+    """128 independent problems (log-uniform sizes 1e4..2e5, depth 3-4,
+    p in {4,5,6}, 1-8 vectors), FFT-M2L in FP32 with FP64 local
+    accumulation, replayed as one graph launch."""
+    import workloads
+    specs = workloads.batch_problems(128)
+    t0 = time.perf_counter()
+    items = []
+    total_pts = 0
+    for sp in specs:
+        pts = workloads.uniform_cube(sp["n"], sp["seed_points"])
+        q = workloads.charges(sp["n"], sp["nvec"], sp["seed_charges"], "u01")
+        f = K.KiFMM(sp["order"], sp["depth"], m2l="fft", prec="fp32").set_points(pts).precompute()
+        qt = torch.as_tensor(q, dtype=torch.float32, device="cuda")
+        phi = torch.empty((sp["nvec"], sp["n"]), dtype=torch.float32, device="cuda")
+        items.append((f, qt, phi))
+        total_pts += sp["n"]
+    setup_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    b = K.Batch(items)
+    capture_s = time.perf_counter() - t0
+    s = torch.cuda.current_stream()
+    for _ in range(5):
+        b.launch()
+    torch.cuda.synchronize()
+    dev_ms, host_ms = [], []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(launches):
+        t0 = time.perf_counter()
+        ev0.record(s)
+        b.launch()
+        ev1.record(s)
+        ev1.synchronize()
+        host_ms.append((time.perf_counter() - t0) * 1e3)
+        dev_ms.append(ev0.elapsed_time(ev1))
+    dev = np.array(dev_ms)
+    host = np.array(host_ms)
+    # the same problems evaluated one by one (eager, one stream) for comparison
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        for f, qt, phi in items:
+            f.evaluate(qt, phi)
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t0) / 3 * 1e3
+    b.close()
+    p50 = float(np.percentile(host, 50))
+    out = {"problems": len(items), "total_points": total_pts,
+           "total_vectors": int(sum(sp["nvec"] for sp in specs)),
+           "launches": launches,
+           "latency_ms_p50": round(p50, 3), "latency_ms_p99": round(float(np.percentile(host, 99)), 3),
+           "device_ms_p50": round(float(np.percentile(dev, 50)), 3),
+           "device_ms_p99": round(float(np.percentile(dev, 99)), 3),
+           "problems_per_s": round(len(items) / (p50 * 1e-3), 1),
+           "points_per_s": round(total_pts / (p50 * 1e-3), 1),
+           "eager_sequential_ms": round(eager_ms, 3),
+           "setup_s": round(setup_s, 2), "capture_s": round(capture_s, 2),
+           "precision": "fp32 M2L, fp64 local accumulation", "m2l": "fft"}
+    log(f"  batch: p50 {p50:.2f} ms, p99 {out['latency_ms_p99']:.2f} ms, eager sequential {eager_ms:.2f} ms")
+    del items
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, budget_boxes=2048):
     """FP64 oracle dense M2L timed on a bounded sample of target boxes."""
     from oracle import fmm
@@ -220,6 +284,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-blas", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the FMM here is a single-GPU build "
@@ -312,6 +377,9 @@ def main():
     if not args.no_blas:
         log("blas-m2l workload: 32 vectors, fp64 / fp32 / bf16x3")
         line["blas_32rhs"] = run_blas(K, torch, max(1, min(args.steps, 3)), 1)
+    if not args.no_batch:
+        log("batched serving workload: 128 problems, one graph launch")
+        line["batch_128"] = run_batch(K, torch, 200)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle dense M2L on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(w)
