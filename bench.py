@@ -40,6 +40,23 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel_source: str, record: str):
+    """HBM bytes per dispatch from the committed rocprofv3 counter record, or
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", record)
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+        with open(os.path.join(ROOT, kernel_source), "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec["traffic_bytes_per_dispatch"]
+
+
 def m2l_work(f, depth, order, nvec, prec):
     """Algorithmic flops of the Hadamard launches and HBM bytes of the M2L."""
     n = 2 * order - 1
@@ -322,7 +339,10 @@ def main():
     dominant = max(kernels, key=kernels.get)
     roof_had = {"kernel": "hadamard_kernel<float> (v_mfma_f32_16x16x4f32)", "bound": "mfma",
                 "achieved": had_flops / n_launch / had_avg_s / 1e12, "peak": PEAK_MFMA["fp32"] / 1e12,
-                "unit": "TFLOP/s", "traffic": None,
+                "unit": "TFLOP/s",
+                "traffic": measured_traffic("paper_2408_07436_amd/csrc/k_fft.hip",
+                                            "hadamard_f32_uniform1M_p6_traffic.json"),
+                "algorithmic_bytes": round(had_bytes / n_launch),
                 "per_launch": f"{had_flops / n_launch / 1e9:.2f} GFLOP (8 flops x 64 pairs x F per "
                               f"cluster pair, averaged over {n_launch} level launches), "
                               f"avg {had_avg_s * 1e3:.4f} ms"}
