@@ -1,7 +1,10 @@
 // Point kernels of the kiFMM on gfx950: charge gather into Morton order,
 // P2M check potentials (Section 2.1.1) and the fused leaf evaluation
 // L2P + P2P (Section 2, downward pass).  Laplace kernel 1 / (4 pi r), zero
-// at r = 0.
+// at r = 0 (pairs with r^2 below the smallest normal number of the working
+// precision count as coincident).
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace kifmm {
@@ -10,8 +13,20 @@ namespace {
 
 constexpr double kInv4Pi = 0.07957747154594767;
 
-__device__ inline double inv_r(double r2) { return r2 > 0.0 ? rsqrt(r2) : 0.0; }
-__device__ inline float inv_r(float r2) { return r2 > 0.0f ? rsqrtf(r2) : 0.0f; }
+// 1 / sqrt(r2), branch-free.  FP64: the hardware estimate y refined by one
+// third-order step of the series (1 - e)^(-1/2) = 1 + e/2 + 3 e^2/8 + ...
+// with e = 1 - r2 y^2, which cubes the estimate's relative error.  FP32:
+// the hardware result as is (about 1 ulp).
+__device__ inline double inv_r(double r2) {
+  const double y = __builtin_amdgcn_rsq(r2);
+  const double e = fma(-r2 * y, y, 1.0);
+  const double r = fma(y * e, fma(e, 0.375, 0.5), y);
+  return r2 >= 2.2250738585072014e-308 ? r : 0.0;
+}
+__device__ inline float inv_r(float r2) {
+  const float r = __builtin_amdgcn_rsqf(r2);
+  return r2 >= 1.17549435e-38f ? r : 0.0f;
+}
 
 template <typename TQ>
 __global__ void gather_kernel(const TQ* __restrict__ q, int64_t ldq, const int64_t* __restrict__ perm,
@@ -21,79 +36,127 @@ __global__ void gather_kernel(const TQ* __restrict__ q, int64_t ldq, const int64
   if (i < n) qs[v * n + i] = q[v * ldq + perm[i]];
 }
 
-constexpr int kP2MThreads = 256;
-constexpr int kP2MChunk = 64;
-constexpr int kP2MVec = 8;
+constexpr int kP2MChunk = 64;  // sources staged per pass (one per lane)
 
-// One workgroup per leaf; a thread owns one upward-check point and
-// accumulates up to kP2MVec charge vectors at a time.
-template <typename TQ>
-__global__ __launch_bounds__(kP2MThreads) void p2m_kernel(
+// One wave per leaf.  Each lane owns PPL upward-check points (lane + 64 j)
+// and NV charge vectors, so one staged source (x, y, z, q) serves PPL x NV
+// accumulations; the source loop is uniform across the wave.
+template <typename TQ, int PPL, int NV>
+__global__ __launch_bounds__(64) void p2m_kernel(
     const double* __restrict__ xyz, const TQ* __restrict__ qs, int64_t n_src,
     const int32_t* __restrict__ start, const int32_t* __restrict__ end,
     const double* __restrict__ centers, const double* __restrict__ surf, double ar, int ns, int nvec,
     double* __restrict__ phi) {
-  __shared__ double sx[kP2MChunk], sy[kP2MChunk], sz[kP2MChunk];
-  __shared__ double sq[kP2MVec][kP2MChunk];
+  constexpr int NX = NV > 1 ? NV - 1 : 1;
+  __shared__ double4 sp[kP2MChunk];
+  __shared__ double sq[NX][kP2MChunk];
   const int64_t leaf = blockIdx.x;
+  const int lane = threadIdx.x;
   const int s0 = start[leaf], s1 = end[leaf];
   const double cx = centers[3 * leaf], cy = centers[3 * leaf + 1], cz = centers[3 * leaf + 2];
-  for (int i0 = 0; i0 < ns; i0 += kP2MThreads) {
-    const int i = i0 + (int)threadIdx.x;
-    const bool act = i < ns;
-    double px = 0, py = 0, pz = 0;
-    if (act) {
-      px = cx + ar * surf[3 * i];
-      py = cy + ar * surf[3 * i + 1];
-      pz = cz + ar * surf[3 * i + 2];
-    }
-    for (int vb = 0; vb < nvec; vb += kP2MVec) {
-      double acc[kP2MVec];
+  for (int i0 = 0; i0 < ns; i0 += 64 * PPL) {
+    double px[PPL], py[PPL], pz[PPL];
 #pragma unroll
-      for (int v = 0; v < kP2MVec; ++v) acc[v] = 0.0;
+    for (int j = 0; j < PPL; ++j) {
+      const int i = min(i0 + lane + 64 * j, ns - 1);  // surplus lanes repeat a point, unwritten
+      px[j] = cx + ar * surf[3 * i];
+      py[j] = cy + ar * surf[3 * i + 1];
+      pz[j] = cz + ar * surf[3 * i + 2];
+    }
+    for (int vb = 0; vb < nvec; vb += NV) {
+      double acc[PPL][NV];
+#pragma unroll
+      for (int j = 0; j < PPL; ++j)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[j][v] = 0.0;
       for (int c0 = s0; c0 < s1; c0 += kP2MChunk) {
         const int cn = min(kP2MChunk, s1 - c0);
         __syncthreads();
-        for (int t = threadIdx.x; t < cn; t += kP2MThreads) {
-          sx[t] = xyz[3 * (int64_t)(c0 + t)];
-          sy[t] = xyz[3 * (int64_t)(c0 + t) + 1];
-          sz[t] = xyz[3 * (int64_t)(c0 + t) + 2];
-        }
-        for (int t = threadIdx.x; t < kP2MVec * kP2MChunk; t += kP2MThreads) {
-          const int v = t / kP2MChunk, s = t % kP2MChunk;
-          sq[v][s] = (s < cn && vb + v < nvec) ? (double)qs[(int64_t)(vb + v) * n_src + c0 + s] : 0.0;
+        if (lane < cn) {
+          const int64_t si = c0 + lane;
+          sp[lane] = double4{xyz[3 * si], xyz[3 * si + 1], xyz[3 * si + 2],
+                             (double)qs[(int64_t)vb * n_src + si]};
+#pragma unroll
+          for (int v = 1; v < NV; ++v)
+            sq[v - 1][lane] = vb + v < nvec ? (double)qs[(int64_t)(vb + v) * n_src + si] : 0.0;
         }
         __syncthreads();
-        if (act) {
-          for (int s = 0; s < cn; ++s) {
-            const double dx = px - sx[s], dy = py - sy[s], dz = pz - sz[s];
-            const double ir = inv_r(dx * dx + dy * dy + dz * dz);
+        for (int s = 0; s < cn; ++s) {
+          const double4 src = sp[s];
 #pragma unroll
-            for (int v = 0; v < kP2MVec; ++v) acc[v] += ir * sq[v][s];
+          for (int j = 0; j < PPL; ++j) {
+            const double dx = px[j] - src.x, dy = py[j] - src.y, dz = pz[j] - src.z;
+            const double ir = inv_r(dx * dx + dy * dy + dz * dz);
+            acc[j][0] += ir * src.w;
+#pragma unroll
+            for (int v = 1; v < NV; ++v) acc[j][v] += ir * sq[v - 1][s];
           }
         }
       }
-      if (act) {
 #pragma unroll
-        for (int v = 0; v < kP2MVec; ++v)
-          if (vb + v < nvec) phi[((int64_t)leaf * nvec + vb + v) * ns + i] = kInv4Pi * acc[v];
+      for (int j = 0; j < PPL; ++j) {
+        const int i = i0 + lane + 64 * j;
+        if (i >= ns) continue;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          if (vb + v < nvec) phi[((int64_t)leaf * nvec + vb + v) * ns + i] = kInv4Pi * acc[j][v];
       }
     }
   }
 }
 
-constexpr int kLeafThreads = 128;
-constexpr int kLeafVec = 4;
-constexpr int kLeafChunk = 256;  // near-field sources staged per pass
-constexpr int kL2PChunk = 160;   // downward-equivalent points staged per pass
+template <typename TQ, int PPL>
+void p2m_launch_nv(int nvec, unsigned grid, hipStream_t stream, const double* xyz, const TQ* qs,
+                   int64_t n_src, const int32_t* start, const int32_t* end, const double* centers,
+                   const double* surf, double ar, int ns, double* phi) {
+#define KIFMM_P2M(NVV)                                                                   \
+  p2m_kernel<TQ, PPL, NVV><<<grid, 64, 0, stream>>>(xyz, qs, n_src, start, end, centers, \
+                                                     surf, ar, ns, nvec, phi)
+  if (nvec == 1)
+    KIFMM_P2M(1);
+  else if (nvec == 2)
+    KIFMM_P2M(2);
+  else if (nvec <= 4)
+    KIFMM_P2M(4);
+  else
+    KIFMM_P2M(8);
+#undef KIFMM_P2M
+}
 
-// One workgroup per target leaf.  The near-field sources (up to 27 leaves,
-// each a contiguous run in Morton order) are staged through LDS in chunks;
-// a thread finds the run of a staged source by binary search over the run
-// offsets.  1, 2 or 4 lanes share a target (by leaf occupancy), split the
-// staged sources and reduce with cross-lane shuffles.  L2P runs in FP64 from
-// the leaf's downward-equivalent densities; P2P runs in T.
-template <typename T, typename TQ>
+template <typename TQ>
+hipError_t p2m_launch(int nvec, unsigned grid, hipStream_t stream, const double* xyz, const TQ* qs,
+                      int64_t n_src, const int32_t* start, const int32_t* end,
+                      const double* centers, const double* surf, double ar, int ns, double* phi) {
+  const int ppl = std::min(4, (ns + 63) / 64);
+  if (ppl == 1)
+    p2m_launch_nv<TQ, 1>(nvec, grid, stream, xyz, qs, n_src, start, end, centers, surf, ar, ns, phi);
+  else if (ppl == 2)
+    p2m_launch_nv<TQ, 2>(nvec, grid, stream, xyz, qs, n_src, start, end, centers, surf, ar, ns, phi);
+  else if (ppl == 3)
+    p2m_launch_nv<TQ, 3>(nvec, grid, stream, xyz, qs, n_src, start, end, centers, surf, ar, ns, phi);
+  else
+    p2m_launch_nv<TQ, 4>(nvec, grid, stream, xyz, qs, n_src, start, end, centers, surf, ar, ns, phi);
+  return hipGetLastError();
+}
+
+constexpr int kLeafThreads = 128;
+constexpr int kLeafChunk = 256;  // near-field sources staged per pass (multiple of 16)
+constexpr int kL2PChunk = 160;   // downward-equivalent points staged per pass (multiple of 16)
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+
+// One workgroup per target leaf.  Sources are staged in LDS as (x, y, z, q)
+// quadruples (further charge vectors in separate arrays), so one LDS read
+// serves an interaction; each thread owns two targets, so each staged
+// source is used twice; 1 to 8 lanes share a target pair (by leaf
+// occupancy), split the staged sources and reduce with cross-lane shuffles.
+// The near-field sources (up to 27 leaves, each a contiguous run in Morton
+// order) are located by binary search over the run offsets.  L2P runs in
+// FP64 from the leaf's downward-equivalent densities; P2P runs in T.  NV
+// charge vectors are handled per pass.
+template <typename T, typename TQ, int NV>
 __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
     const double* __restrict__ txyz, const T* __restrict__ sxyz, const TQ* __restrict__ qs,
     int64_t n_src, const int32_t* __restrict__ tstart, const int32_t* __restrict__ tend,
@@ -102,10 +165,12 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
     const double* __restrict__ centers, const double* __restrict__ surf, double ar, int ns,
     const double* __restrict__ local, const int64_t* __restrict__ tperm, TQ* __restrict__ phi,
     int64_t ldphi, int nvec) {
-  __shared__ double lx[kL2PChunk], ly[kL2PChunk], lz[kL2PChunk];
-  __shared__ double lq[kLeafVec][kL2PChunk];
-  __shared__ T px[kLeafChunk], py[kLeafChunk], pz[kLeafChunk];
-  __shared__ T pq[kLeafVec][kLeafChunk];
+  using T4 = typename Vec4<T>::type;
+  constexpr int NX = NV > 1 ? NV - 1 : 1;
+  __shared__ double4 ls[kL2PChunk];
+  __shared__ double lq[NX][kL2PChunk];
+  __shared__ T4 ps[kLeafChunk];
+  __shared__ T pq[NX][kLeafChunk];
   __shared__ int32_t nb_first[27];
   __shared__ int32_t nb_pref[28];
   __shared__ int32_t n_nb;
@@ -130,55 +195,85 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
   __syncthreads();
   const int nnb = n_nb;
   const int total = nb_pref[nnb];
-  const int L = nt <= 32 ? 4 : (nt <= 64 ? 2 : 1);
+  const int pairs = (nt + 1) / 2;
+  const int L = pairs <= 16 ? 8 : pairs <= 32 ? 4 : pairs <= 64 ? 2 : 1;
   const int slots = kLeafThreads / L;
-  const int tt = threadIdx.x / L, sub = threadIdx.x % L;
+  const int tp = threadIdx.x / L, sub = threadIdx.x % L;
   const double cx = centers[3 * leaf], cy = centers[3 * leaf + 1], cz = centers[3 * leaf + 2];
 
-  for (int vb = 0; vb < nvec; vb += kLeafVec) {
-    for (int tb = 0; tb < nt; tb += slots) {
-      const int ti = tb + tt;
-      const bool act = ti < nt;
-      double x = 0, y = 0, z = 0;
-      if (act) {
-        x = txyz[3 * (int64_t)(t0 + ti)];
-        y = txyz[3 * (int64_t)(t0 + ti) + 1];
-        z = txyz[3 * (int64_t)(t0 + ti) + 2];
+  for (int vb = 0; vb < nvec; vb += NV) {
+    for (int pb = 0; pb < pairs; pb += slots) {
+      const int ti0 = 2 * (pb + tp), ti1 = ti0 + 1;
+      const bool act0 = ti0 < nt, act1 = ti1 < nt;
+      double x0 = 0, y0 = 0, z0 = 0, x1 = 0, y1 = 0, z1 = 0;
+      if (act0) {
+        x0 = txyz[3 * (int64_t)(t0 + ti0)];
+        y0 = txyz[3 * (int64_t)(t0 + ti0) + 1];
+        z0 = txyz[3 * (int64_t)(t0 + ti0) + 2];
       }
-      double accl[kLeafVec];
-      T accp[kLeafVec];
+      if (act1) {
+        x1 = txyz[3 * (int64_t)(t0 + ti1)];
+        y1 = txyz[3 * (int64_t)(t0 + ti1) + 1];
+        z1 = txyz[3 * (int64_t)(t0 + ti1) + 2];
+      }
+      double al0[NV], al1[NV];
+      T ap0[NV], ap1[NV];
 #pragma unroll
-      for (int v = 0; v < kLeafVec; ++v) {
-        accl[v] = 0.0;
-        accp[v] = T(0);
+      for (int v = 0; v < NV; ++v) {
+        al0[v] = al1[v] = 0.0;
+        ap0[v] = ap1[v] = T(0);
       }
       // L2P: the leaf's downward-equivalent surface as sources (FP64)
       for (int c0 = 0; c0 < ns; c0 += kL2PChunk) {
         const int cn = min(kL2PChunk, ns - c0);
+        const int cnp = (cn + 2 * L - 1) / (2 * L) * (2 * L);  // zero densities pad
         __syncthreads();
-        for (int t = threadIdx.x; t < cn; t += kLeafThreads) {
-          lx[t] = cx + ar * surf[3 * (c0 + t)];
-          ly[t] = cy + ar * surf[3 * (c0 + t) + 1];
-          lz[t] = cz + ar * surf[3 * (c0 + t) + 2];
+        for (int t = threadIdx.x; t < cnp; t += kLeafThreads) {
+          if (t < cn) {
+            ls[t] = double4{cx + ar * surf[3 * (c0 + t)], cy + ar * surf[3 * (c0 + t) + 1],
+                            cz + ar * surf[3 * (c0 + t) + 2],
+                            local[((int64_t)leaf * nvec + vb) * ns + c0 + t]};
 #pragma unroll
-          for (int v = 0; v < kLeafVec; ++v)
-            lq[v][t] = vb + v < nvec ? local[((int64_t)leaf * nvec + vb + v) * ns + c0 + t] : 0.0;
+            for (int v = 1; v < NV; ++v)
+              lq[v - 1][t] = vb + v < nvec ? local[((int64_t)leaf * nvec + vb + v) * ns + c0 + t] : 0.0;
+          } else {
+            ls[t] = double4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int v = 1; v < NV; ++v) lq[v - 1][t] = 0.0;
+          }
         }
         __syncthreads();
-        if (act) {
-          for (int s = sub; s < cn; s += L) {
-            const double dx = x - lx[s], dy = y - ly[s], dz = z - lz[s];
-            const double ir = inv_r(dx * dx + dy * dy + dz * dz);
+        auto l2p = [&](int s) {
+          const double4 src = ls[s];
+          const double dx0 = x0 - src.x, dy0 = y0 - src.y, dz0 = z0 - src.z;
+          const double dx1 = x1 - src.x, dy1 = y1 - src.y, dz1 = z1 - src.z;
+          const double r0 = inv_r(dx0 * dx0 + dy0 * dy0 + dz0 * dz0);
+          const double r1 = inv_r(dx1 * dx1 + dy1 * dy1 + dz1 * dz1);
+          al0[0] += r0 * src.w;
+          al1[0] += r1 * src.w;
 #pragma unroll
-            for (int v = 0; v < kLeafVec; ++v) accl[v] += ir * lq[v][s];
+          for (int v = 1; v < NV; ++v) {
+            const double qv = lq[v - 1][s];
+            al0[v] += r0 * qv;
+            al1[v] += r1 * qv;
           }
+        };
+        for (int s0 = 0; s0 < cnp; s0 += 2 * L) {
+          l2p(s0 + sub);
+          l2p(s0 + L + sub);
         }
       }
       // P2P over the near field
-      const T xt = (T)x, yt = (T)y, zt = (T)z;
+      const T xt0 = (T)x0, yt0 = (T)y0, zt0 = (T)z0, xt1 = (T)x1, yt1 = (T)y1, zt1 = (T)z1;
       for (int c0 = 0; c0 < total; c0 += kLeafChunk) {
         const int cn = min(kLeafChunk, total - c0);
+        const int cnp = (cn + 2 * L - 1) / (2 * L) * (2 * L);  // zero charges pad
         __syncthreads();
+        for (int t = cn + threadIdx.x; t < cnp; t += kLeafThreads) {
+          ps[t] = T4{T(0), T(0), T(0), T(0)};
+#pragma unroll
+          for (int v = 1; v < NV; ++v) pq[v - 1][t] = T(0);
+        }
         for (int t = threadIdx.x; t < cn; t += kLeafThreads) {
           const int g = c0 + t;
           int lo = 0, hi = nnb - 1;  // largest k with nb_pref[k] <= g
@@ -187,39 +282,76 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
             if (nb_pref[mid] <= g) lo = mid; else hi = mid - 1;
           }
           const int64_t si = (int64_t)nb_first[lo] + (g - nb_pref[lo]);
-          px[t] = sxyz[3 * si];
-          py[t] = sxyz[3 * si + 1];
-          pz[t] = sxyz[3 * si + 2];
+          const T q0 = vb < nvec ? (T)qs[(int64_t)vb * n_src + si] : T(0);
+          ps[t] = T4{sxyz[3 * si], sxyz[3 * si + 1], sxyz[3 * si + 2], q0};
 #pragma unroll
-          for (int v = 0; v < kLeafVec; ++v)
-            pq[v][t] = vb + v < nvec ? (T)qs[(int64_t)(vb + v) * n_src + si] : T(0);
+          for (int v = 1; v < NV; ++v)
+            pq[v - 1][t] = vb + v < nvec ? (T)qs[(int64_t)(vb + v) * n_src + si] : T(0);
         }
         __syncthreads();
-        if (act) {
-          for (int s = sub; s < cn; s += L) {
-            const T dx = xt - px[s], dy = yt - py[s], dz = zt - pz[s];
-            const T ir = inv_r(dx * dx + dy * dy + dz * dz);
+        auto p2p = [&](int s) {
+          const T4 src = ps[s];
+          const T dx0 = xt0 - src.x, dy0 = yt0 - src.y, dz0 = zt0 - src.z;
+          const T dx1 = xt1 - src.x, dy1 = yt1 - src.y, dz1 = zt1 - src.z;
+          const T r0 = inv_r(dx0 * dx0 + dy0 * dy0 + dz0 * dz0);
+          const T r1 = inv_r(dx1 * dx1 + dy1 * dy1 + dz1 * dz1);
+          ap0[0] += r0 * src.w;
+          ap1[0] += r1 * src.w;
 #pragma unroll
-            for (int v = 0; v < kLeafVec; ++v) accp[v] += ir * pq[v][s];
+          for (int v = 1; v < NV; ++v) {
+            const T qv = pq[v - 1][s];
+            ap0[v] += r0 * qv;
+            ap1[v] += r1 * qv;
           }
+        };
+        for (int s0 = 0; s0 < cnp; s0 += 2 * L) {
+          p2p(s0 + sub);
+          p2p(s0 + L + sub);
         }
       }
       for (int off = 1; off < L; off <<= 1) {
 #pragma unroll
-        for (int v = 0; v < kLeafVec; ++v) {
-          accl[v] += __shfl_xor(accl[v], off);
-          accp[v] += __shfl_xor(accp[v], off);
+        for (int v = 0; v < NV; ++v) {
+          al0[v] += __shfl_xor(al0[v], off);
+          al1[v] += __shfl_xor(al1[v], off);
+          ap0[v] += __shfl_xor(ap0[v], off);
+          ap1[v] += __shfl_xor(ap1[v], off);
         }
       }
-      if (act && sub == 0) {
-        const int64_t dst = tperm[t0 + ti];
+      if (sub == 0) {
 #pragma unroll
-        for (int v = 0; v < kLeafVec; ++v)
-          if (vb + v < nvec)
-            phi[(int64_t)(vb + v) * ldphi + dst] = (TQ)(kInv4Pi * (accl[v] + (double)accp[v]));
+        for (int v = 0; v < NV; ++v) {
+          if (vb + v >= nvec) continue;
+          if (act0)
+            phi[(int64_t)(vb + v) * ldphi + tperm[t0 + ti0]] = (TQ)(kInv4Pi * (al0[v] + (double)ap0[v]));
+          if (act1)
+            phi[(int64_t)(vb + v) * ldphi + tperm[t0 + ti1]] = (TQ)(kInv4Pi * (al1[v] + (double)ap1[v]));
+        }
       }
     }
   }
+}
+
+template <typename T, typename TQ>
+hipError_t leaf_launch(int nvec, unsigned grid, hipStream_t stream, const double* txyz, const T* sxyz,
+                       const TQ* qs, int64_t n_src, const int32_t* tstart, const int32_t* tend,
+                       const int32_t* sstart, const int32_t* send, const int64_t* near_offs,
+                       const int32_t* near_src, const double* centers, const double* surf, double ar,
+                       int ns, const double* local, const int64_t* tgt_perm, TQ* phi, int64_t ldphi) {
+#define KIFMM_LEAF(NVV)                                                                       \
+  leaf_eval_kernel<T, TQ, NVV><<<grid, kLeafThreads, 0, stream>>>(                            \
+      txyz, sxyz, qs, n_src, tstart, tend, sstart, send, near_offs, near_src, centers, surf, ar, \
+      ns, local, tgt_perm, phi, ldphi, nvec)
+  if (nvec == 1)
+    KIFMM_LEAF(1);
+  else if (nvec == 2)
+    KIFMM_LEAF(2);
+  else if (nvec <= 4)
+    KIFMM_LEAF(4);
+  else
+    KIFMM_LEAF(8);
+#undef KIFMM_LEAF
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -240,12 +372,10 @@ hipError_t launch_p2m(const double* src_xyz, const void* qs, bool q_fp64, int64_
                       hipStream_t stream) {
   if (n_leaf == 0) return hipSuccess;
   if (q_fp64)
-    p2m_kernel<double><<<(unsigned)n_leaf, kP2MThreads, 0, stream>>>(
-        src_xyz, (const double*)qs, n_src, start, end, centers, surf, ar, ns, nvec, phi);
-  else
-    p2m_kernel<float><<<(unsigned)n_leaf, kP2MThreads, 0, stream>>>(
-        src_xyz, (const float*)qs, n_src, start, end, centers, surf, ar, ns, nvec, phi);
-  return hipGetLastError();
+    return p2m_launch<double>(nvec, (unsigned)n_leaf, stream, src_xyz, (const double*)qs, n_src,
+                              start, end, centers, surf, ar, ns, phi);
+  return p2m_launch<float>(nvec, (unsigned)n_leaf, stream, src_xyz, (const float*)qs, n_src, start,
+                           end, centers, surf, ar, ns, phi);
 }
 
 hipError_t launch_leaf_eval(const double* tgt_xyz, const double* src_xyz, const float* src_xyz_f,
@@ -257,14 +387,14 @@ hipError_t launch_leaf_eval(const double* tgt_xyz, const double* src_xyz, const 
                             int64_t ldphi, int nvec, hipStream_t stream) {
   if (n_leaf == 0) return hipSuccess;
   if (fp64)
-    leaf_eval_kernel<double, double><<<(unsigned)n_leaf, kLeafThreads, 0, stream>>>(
-        tgt_xyz, src_xyz, (const double*)qs, n_src, tstart, tend, sstart, send, near_offs,
-        near_src, centers, surf, ar, ns, local, tgt_perm, (double*)phi, ldphi, nvec);
-  else
-    leaf_eval_kernel<float, float><<<(unsigned)n_leaf, kLeafThreads, 0, stream>>>(
-        tgt_xyz, src_xyz_f, (const float*)qs, n_src, tstart, tend, sstart, send, near_offs,
-        near_src, centers, surf, ar, ns, local, tgt_perm, (float*)phi, ldphi, nvec);
-  return hipGetLastError();
+    return leaf_launch<double, double>(nvec, (unsigned)n_leaf, stream, tgt_xyz, src_xyz,
+                                       (const double*)qs, n_src, tstart, tend, sstart, send,
+                                       near_offs, near_src, centers, surf, ar, ns, local, tgt_perm,
+                                       (double*)phi, ldphi);
+  return leaf_launch<float, float>(nvec, (unsigned)n_leaf, stream, tgt_xyz, src_xyz_f,
+                                   (const float*)qs, n_src, tstart, tend, sstart, send, near_offs,
+                                   near_src, centers, surf, ar, ns, local, tgt_perm, (float*)phi,
+                                   ldphi);
 }
 
 }  // namespace kifmm
