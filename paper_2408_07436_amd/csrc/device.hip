@@ -313,9 +313,20 @@ kifmm_status upload_all(kifmm_handle* h) {
     const Level& L = t.levels[l];
     D.n = L.n;
     D.w = t.width / std::ldexp(1.0, l);
-    if (l < depth) KIFMM_TRY(upload(d, &D.child, L.child.data(), L.child.size()));
-    if (l >= 2 && h->cfg.m2l == KIFMM_M2L_FFT)
-      KIFMM_TRY(upload(d, &D.halo, L.halo.data(), L.halo.size()));
+    if (l < depth) {
+      // one empty cluster past the end (all children absent): its FFT-M2L
+      // spectra are zero and stand in for absent sibling clusters
+      std::vector<int32_t> ch(L.child);
+      ch.resize(L.child.size() + 8, -1);
+      KIFMM_TRY(upload(d, &D.child, ch.data(), ch.size()));
+    }
+    if (l >= 2 && h->cfg.m2l == KIFMM_M2L_FFT) {
+      std::vector<int32_t> hl(L.halo);
+      const int32_t empty = (int32_t)t.levels[l - 1].n;
+      for (int32_t& x : hl)
+        if (x < 0) x = empty;
+      KIFMM_TRY(upload(d, &D.halo, hl.data(), hl.size()));
+    }
   }
 
   if (h->cfg.m2l == KIFMM_M2L_FFT) {
@@ -421,7 +432,7 @@ kifmm_status ensure_work(kifmm_handle* h, int nvec) {
     for (int l = 2; l <= depth; ++l) maxc = std::max(maxc, t.levels[l - 1].n);
     const size_t cb = d->fp64 ? 16 : 8;
     char *a, *b;
-    KIFMM_TRY(dalloc(d, &a, (size_t)op.F * maxc * nvec * 8 * cb, true));
+    KIFMM_TRY(dalloc(d, &a, (size_t)op.F * (maxc + 1) * nvec * 8 * cb, true));  // + empty cluster
     KIFMM_TRY(dalloc(d, &b, (size_t)op.F * maxc * nvec * 8 * cb, true));
     d->Qhat = a;
     d->Phat = b;
@@ -462,8 +473,9 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
   if (h->cfg.m2l == KIFMM_M2L_FFT) {
     const int64_t nc = d->lv[l - 1].n;
     const int32_t* child = d->lv[l - 1].child;
-    KIFMM_LAUNCH(launch_fft_forward(op.p, d->fp64, in, child, nc, nvec, d->lat2surf, d->twiddle,
-                                    d->Qhat, s));
+    // spectra of the nc clusters and of the empty cluster behind them
+    KIFMM_LAUNCH(launch_fft_forward(op.p, d->fp64, in, child, nc + 1, nvec, d->lat2surf,
+                                    d->twiddle, d->Qhat, s));
     if (mark) KIFMM_HIP(hipEventRecord(mark[1], s));
     KIFMM_LAUNCH(launch_hadamard(d->fp64, op.F, d->khat, d->Qhat, D.halo, nc, nvec, d->Phat, s));
     if (mark) KIFMM_HIP(hipEventRecord(mark[2], s));

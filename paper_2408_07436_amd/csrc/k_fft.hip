@@ -250,9 +250,11 @@ __device__ inline double4 load4(const double* p) {
 
 // Workgroup = one frequency x a chunk of 16-row tiles; four waves share the
 // frequency's B operand (the 416 x 16 real form of its 26 x 8 x 8 complex
-// kernel coefficients), staged in LDS in the lanes' operand order.  Each
-// wave issues the halo indices and the source spectra of a whole batch of
-// directions before its MFMAs, so that the loads are in flight together.
+// kernel coefficients), staged in LDS in the lanes' operand order.  The
+// source spectra are gathered through the halo table with 32-bit offsets
+// from the frequency's base; absent neighbours point at the empty cluster,
+// so the gather needs no masking and the VALU work per MFMA stays small
+// (on gfx950 the VALU does not co-issue with the MFMA of the same wave).
 template <typename T>
 __global__ __launch_bounds__(kHadThreads) void hadamard_kernel(
     const typename C2T<T>::type* __restrict__ Khat, const T* __restrict__ Qhat,
@@ -289,36 +291,32 @@ __global__ __launch_bounds__(kHadThreads) void hadamard_kernel(
   __syncthreads();
   const int wave = tid / 64, lane = tid % 64;
   const int rl = lane % 16, g = lane / 16;
-  const int64_t fbase = f * n_rows;
+  // this frequency's spectra (n_rows + nvec rows: the empty cluster last)
+  // and products; lanes address them with 32-bit byte offsets
+  const char* qf = reinterpret_cast<const char*>(Qhat + f * (n_rows + nvec) * 16);
+  T* pf = Phat + f * n_rows * 16;
   for (int t = 0; t < tiles_per_wave; ++t) {
     const int64_t tile = ((int64_t)chunk * tiles_per_wave + t) * 4 + wave;
     const int64_t row0 = tile * 16;
     if (row0 >= n_rows) break;
-    const int64_t row = row0 + rl;
-    const bool valid = row < n_rows;
-    const int64_t c = valid ? row / nvec : 0;
-    const int v = valid ? (int)(row - c * nvec) : 0;
+    // rows past the end repeat the last row; their results are not stored
+    const uint32_t row = (uint32_t)min(row0 + rl, n_rows - 1);
+    const uint32_t c = row / (uint32_t)nvec;
+    const uint32_t lane_off = ((row - c * (uint32_t)nvec) * 16 + 4 * g) * (uint32_t)sizeof(T);
     // two accumulators (even / odd directions) so consecutive MFMAs are
-    // independent; absent neighbours read row 0 and are zeroed by a select
+    // independent
     V4 acc0, acc1;
     acc0[0] = acc0[1] = acc0[2] = acc0[3] = T(0);
     acc1 = acc0;
-    const T* qv = Qhat + (fbase * 16 + (int64_t)v * 16 + 4 * g);
 #pragma unroll
     for (int d0 = 0; d0 < 26; d0 += DC) {
-      int32_t nb[DC];
-#pragma unroll
-      for (int dd = 0; dd < DC; ++dd) {
-        const int32_t h = halo[(int64_t)(d0 + dd) * n_c + c];  // c = 0 for padding rows
-        nb[dd] = valid ? h : -1;
-      }
       T4 a[DC];
 #pragma unroll
       for (int dd = 0; dd < DC; ++dd) {
-        const int64_t src = (int64_t)(nb[dd] < 0 ? 0 : nb[dd]) * nvec;
-        const T4 x = load4(qv + src * 16);
-        const T keep = nb[dd] < 0 ? T(0) : T(1);
-        a[dd] = T4{x.x * keep, x.y * keep, x.z * keep, x.w * keep};
+        const int32_t* hd = halo + (int64_t)(d0 + dd) * n_c;
+        const uint32_t nb = (uint32_t)hd[c];
+        const uint32_t off = __umul24(nb, (uint32_t)nvec) * (16 * (uint32_t)sizeof(T)) + lane_off;
+        a[dd] = load4(reinterpret_cast<const T*>(qf + off));
       }
 #pragma unroll
       for (int dd = 0; dd < DC; ++dd) {
@@ -336,7 +334,7 @@ __global__ __launch_bounds__(kHadThreads) void hadamard_kernel(
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int64_t r = row0 + out_row(T(0), g, i);
-      if (r < n_rows) Phat[(fbase + r) * 16 + rl] = acc[i];
+      if (r < n_rows) pf[r * 16 + rl] = acc[i];
     }
   }
 }
@@ -421,6 +419,10 @@ hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
                            hipStream_t stream) {
   const int64_t n_rows = n_clusters * nvec;
   if (n_rows == 0) return hipSuccess;
+  // 24-bit cluster products and 32-bit byte offsets within one frequency
+  if (n_clusters + 1 >= (int64_t(1) << 24) ||
+      (n_clusters + 1) * nvec * 16 * (fp64 ? 8 : 4) >= (int64_t(1) << 32))
+    return hipErrorInvalidValue;
   const int64_t tiles = (n_rows + 15) / 16;
   const int tpw = tiles >= 256 ? 8 : tiles >= 64 ? 4 : 1;
   const int n_chunks = (int)((tiles + 4 * tpw - 1) / (4 * tpw));

@@ -53,7 +53,9 @@ hipError_t launch_fft_forward(int p, bool fp64, const double* M, const int32_t* 
                               int64_t n_clusters, int nvec, const int16_t* lat2surf,
                               const void* twiddle, void* Qhat, hipStream_t stream);
 // Hadamard products by sibling cluster: Phat[f][row][i] = sum_d sum_j
-// Khat[f][d][i][j] Qhat[f][halo[d][c] * nvec + v][j].
+// Khat[f][d][i][j] Qhat[f][halo[d][c] * nvec + v][j], row = c * nvec + v.
+// Qhat holds n_clusters + 1 clusters per frequency, the last one zero;
+// absent neighbours have halo[d][c] = n_clusters.
 hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
                            const int32_t* halo, int64_t n_clusters, int nvec, void* Phat,
                            hipStream_t stream);
