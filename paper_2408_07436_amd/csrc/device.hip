@@ -15,6 +15,15 @@ struct DevLevel {
   double w = 1.0;               // box width
   int32_t* child = nullptr;     // [n][8]
   int32_t* halo = nullptr;      // [26][n_{l-1}]
+  // FFT-M2L source blocks: the clusters of one aligned 4 x 4 x 4 cube of
+  // level l-1 (consecutive in Morton order) share one list of at most 216
+  // source clusters with LDS slots; slots[c] holds, per direction, the slot
+  // of cluster c's neighbour (26 bytes in 7 words)
+  int64_t hb_n = 0;
+  int32_t* hb_tgt = nullptr;    // [hb_n + 1] first cluster of each block
+  int32_t* hb_src = nullptr;    // [hb_n + 1] offsets into hb_list
+  int32_t* hb_list = nullptr;   // cluster << 8 | slot (the empty cluster n_{l-1} included)
+  uint32_t* hb_slots = nullptr; // [n_{l-1}][7]
   // BLAS / dense M2L: target tiles of one octant class and, per tile, the
   // transfer vectors present with the source box of every tile slot
   int64_t ntiles = 0;
@@ -257,6 +266,66 @@ kifmm_status build_blas_tiles(kifmm_handle* h, DeviceState* d, int TB) {
   return KIFMM_OK;
 }
 
+// Source blocks of one FFT-M2L level (see DevLevel): clusters grouped by
+// Morton key >> 6 (aligned 4 x 4 x 4 cubes); each block lists the distinct
+// clusters its members' halos reach, each with a slot 8 r + the parity class
+// (x & 1) + 2 (y & 1) + 4 (z & 1) of its position, r counting within the
+// class, so the clusters of any aligned 2 x 2 x 2 cube get distinct slots
+// modulo 8.  The empty cluster (index nc) takes a free slot.
+static kifmm_status build_source_blocks(DeviceState* d, DevLevel& D, const Level& up,
+                                        const std::vector<int32_t>& halo) {
+  const int64_t nc = up.n;
+  std::vector<int32_t> tgt, src, list;
+  std::vector<uint32_t> slots((size_t)nc * 7, 0u);
+  int64_t c = 0;
+  while (c < nc) {
+    const uint64_t bk = up.keys[c] >> 6;
+    int64_t e = c;
+    while (e < nc && (up.keys[e] >> 6) == bk) ++e;
+    std::vector<int32_t> u;
+    u.reserve((size_t)(e - c) * kNumDirections);
+    for (int64_t i = c; i < e; ++i)
+      for (int dd = 0; dd < kNumDirections; ++dd) u.push_back(halo[(size_t)dd * nc + i]);
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    int count[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    std::vector<int32_t> slot_of(u.size(), -1);
+    for (size_t k = 0; k < u.size(); ++k) {
+      if (u[k] == nc) continue;
+      const int32_t* an = &up.anchor[3 * (size_t)u[k]];
+      const int par = (an[0] & 1) + 2 * (an[1] & 1) + 4 * (an[2] & 1);
+      slot_of[k] = 8 * count[par]++ + par;
+    }
+    for (size_t k = 0; k < u.size(); ++k) {
+      if (u[k] != nc) continue;
+      int par = 0;
+      while (par < 8 && count[par] >= 27) ++par;
+      if (par == 8) return fail(KIFMM_ENUMERIC, "FFT-M2L source block has no free slot");
+      slot_of[k] = 8 * count[par]++ + par;
+    }
+    for (int par = 0; par < 8; ++par)
+      if (count[par] > 27) return fail(KIFMM_ENUMERIC, "FFT-M2L source block exceeds 216 slots");
+    tgt.push_back((int32_t)c);
+    src.push_back((int32_t)list.size());
+    for (int64_t i = c; i < e; ++i)
+      for (int dd = 0; dd < kNumDirections; ++dd) {
+        const int32_t s = halo[(size_t)dd * nc + i];
+        const size_t k = (size_t)(std::lower_bound(u.begin(), u.end(), s) - u.begin());
+        slots[(size_t)i * 7 + dd / 4] |= (uint32_t)slot_of[k] << (8 * (dd % 4));
+      }
+    for (size_t k = 0; k < u.size(); ++k) list.push_back((int32_t)((uint32_t)u[k] << 8 | (uint32_t)slot_of[k]));
+    c = e;
+  }
+  D.hb_n = (int64_t)tgt.size();
+  tgt.push_back((int32_t)nc);
+  src.push_back((int32_t)list.size());
+  KIFMM_TRY(upload(d, &D.hb_tgt, tgt.data(), tgt.size()));
+  KIFMM_TRY(upload(d, &D.hb_src, src.data(), src.size()));
+  KIFMM_TRY(upload(d, &D.hb_list, list.data(), list.size()));
+  KIFMM_TRY(upload(d, &D.hb_slots, slots.data(), slots.size()));
+  return KIFMM_OK;
+}
+
 kifmm_status upload_all(kifmm_handle* h) {
   const Tree& t = h->tree;
   const Operators& op = h->op;
@@ -326,6 +395,7 @@ kifmm_status upload_all(kifmm_handle* h) {
       for (int32_t& x : hl)
         if (x < 0) x = empty;
       KIFMM_TRY(upload(d, &D.halo, hl.data(), hl.size()));
+      KIFMM_TRY(build_source_blocks(d, D, t.levels[l - 1], hl));
     }
   }
 
@@ -477,7 +547,8 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
     KIFMM_LAUNCH(launch_fft_forward(op.p, d->fp64, in, child, nc + 1, nvec, d->lat2surf,
                                     d->twiddle, d->Qhat, s));
     if (mark) KIFMM_HIP(hipEventRecord(mark[1], s));
-    KIFMM_LAUNCH(launch_hadamard(d->fp64, op.F, d->khat, d->Qhat, D.halo, nc, nvec, d->Phat, s));
+    KIFMM_LAUNCH(launch_hadamard(d->fp64, op.F, d->khat, d->Qhat, D.halo, D.hb_n, D.hb_tgt,
+                                 D.hb_src, D.hb_list, D.hb_slots, nc, nvec, d->Phat, s));
     if (mark) KIFMM_HIP(hipEventRecord(mark[2], s));
     const double scale = 1.0 / ((double)op.n * op.n * op.n * D.w);  // 1 / (n^3 w)
     KIFMM_LAUNCH(launch_fft_inverse(op.p, d->fp64, d->Phat, child, nc, nvec, d->surf_lat,

@@ -236,8 +236,8 @@ template <typename T> struct Vec4T;
 template <> struct Vec4T<float> { using type = float4; };
 template <> struct Vec4T<double> { using type = double4; };
 
-// directions handled per batch of loads: all 26 in FP32; 13 in FP64 to
-// stay within the register file
+// directions handled per batch of loads in the gather form: all 26 in
+// FP32, 13 in FP64 to stay within the register file
 template <typename T> struct HadChunk { static constexpr int value = 26; };
 template <> struct HadChunk<double> { static constexpr int value = 13; };
 
@@ -248,15 +248,17 @@ __device__ inline double4 load4(const double* p) {
   return double4{lo.x, lo.y, hi.x, hi.y};
 }
 
-// Workgroup = one frequency x a chunk of 16-row tiles; four waves share the
-// frequency's B operand (the 416 x 16 real form of its 26 x 8 x 8 complex
-// kernel coefficients), staged in LDS in the lanes' operand order.  The
+// Gather form (FP64).  Workgroup = one frequency x a chunk of 16-row tiles;
+// four waves share the
+// frequency's B operand (the 416 x 16 real form of its 26 x 8 x 8
+// complex kernel coefficients), staged in LDS in the lanes' operand order.
+// The
 // source spectra are gathered through the halo table with 32-bit offsets
 // from the frequency's base; absent neighbours point at the empty cluster,
 // so the gather needs no masking and the VALU work per MFMA stays small
 // (on gfx950 the VALU does not co-issue with the MFMA of the same wave).
 template <typename T>
-__global__ __launch_bounds__(kHadThreads) void hadamard_kernel(
+__global__ __launch_bounds__(kHadThreads) void hadamard_gather_kernel(
     const typename C2T<T>::type* __restrict__ Khat, const T* __restrict__ Qhat,
     const int32_t* __restrict__ halo, int64_t n_c, int nvec, int64_t n_rows, int n_chunks,
     int tiles_per_wave, int64_t total_blocks, T* __restrict__ Phat) {
@@ -339,6 +341,125 @@ __global__ __launch_bounds__(kHadThreads) void hadamard_kernel(
   }
 }
 
+constexpr int kHadSrcMax = 216;  // source slots of one 4 x 4 x 4 block: its 6 x 6 x 6 shell
+constexpr int kHadStage = (kHadSrcMax * 4 + kHadThreads - 1) / kHadThreads;
+
+// Block form (FP32).  Workgroup = one frequency x a run of (block, charge
+// vector) items.  Each lane holds the frequency's B operand for all 26
+// directions in registers (the 416 x 16 real form of the 26 x 8 x 8 complex
+// kernel coefficients, in its operand order).  Per item the spectra of the
+// block's source clusters (at most 216 rows of 16 reals) are staged in LDS
+// - the next item's rows are loaded into registers while the current one
+// computes - and each wave takes one 16-cluster tile of the block's (at
+// most 64) target clusters, reading its A operands at the slots of the
+// clusters' 26 neighbours.  A source slot is 8 x rank + the parity class of
+// the source's position, so the eight clusters of an aligned 2 x 2 x 2 cube
+// (eight consecutive lanes) always read distinct LDS banks.  Every source
+// spectrum crosses the cache hierarchy once per block, and the VALU work per
+// MFMA stays small (on gfx950 the VALU does not co-issue with the MFMA of the
+// same wave).
+__global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_kernel(
+    const float2* __restrict__ Khat, const float* __restrict__ Qhat,
+    const int32_t* __restrict__ blk_tgt, const int32_t* __restrict__ blk_src,
+    const int32_t* __restrict__ blk_list, const uint32_t* __restrict__ slots, int64_t n_items,
+    int nvec, int64_t n_rows, int items_per_wg, int n_groups, int64_t total_wgs,
+    float* __restrict__ Phat) {
+  constexpr int kRow = 5;  // LDS row stride in float4: 16 reals + padding
+  __shared__ float4 As[2][kHadSrcMax * kRow + 1];  // + one discard entry
+  const int64_t b = blockIdx.x;
+  const int64_t per_xcd = (total_wgs + 7) / 8;
+  const int64_t logical = (b % 8) * per_xcd + b / 8;  // consecutive work per XCD
+  if (logical >= total_wgs) return;
+  const int64_t f = logical / n_groups;
+  const int64_t item0 = (logical % n_groups) * items_per_wg;
+  const int64_t item1 = min(item0 + items_per_wg, n_items);
+  const int tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64;
+  const int rl = lane % 16, g = lane / 16;
+  // B operand: lane (n, g) multiplies inputs 2g, 2g + 1 (real, imaginary
+  // parts) into output n / 2, real part for even n and imaginary for odd n
+  float4 B[26];
+#pragma unroll
+  for (int d = 0; d < 26; ++d) {
+    const float4 k =
+        *reinterpret_cast<const float4*>(&Khat[((f * 26 + d) * 8 + rl / 2) * 8 + 2 * g]);
+    B[d] = (rl & 1) ? float4{k.y, k.x, k.w, k.z} : float4{k.x, -k.y, k.z, -k.w};
+  }
+  // this frequency's spectra (n_rows + nvec rows: the empty cluster last)
+  const char* qf = reinterpret_cast<const char*>(Qhat + f * (n_rows + nvec) * 16);
+  float* pf = Phat + f * n_rows * 16;
+  const int tr0 = wave * 16;  // this wave's tile of the block's targets
+  // staging registers: four 16-byte pieces per thread (216 rows x 4 pieces
+  // over 256 threads), named rather than an array so they stay in VGPRs
+  static_assert(kHadStage == 4, "staging pieces per thread");
+  float4 stg0, stg1, stg2, stg3;
+  int sl0 = 0, sl1 = 0, sl2 = 0, sl3 = 0;
+  uint32_t w[7], wn[7];
+  int buf = 0;
+  // iteration `it` issues the loads of item it (into registers) and then
+  // computes item it - 1, whose rows the previous iteration loaded
+  for (int64_t it = item0; it <= item1; ++it) {
+    if (it > item0) {
+      As[buf][sl0] = stg0;
+      As[buf][sl1] = stg1;
+      As[buf][sl2] = stg2;
+      As[buf][sl3] = stg3;
+#pragma unroll
+      for (int k = 0; k < 7; ++k) w[k] = wn[k];
+      __syncthreads();  // As[buf] complete; As[buf ^ 1] free for the next item
+    }
+    if (it < item1) {
+      const int64_t blk = it / nvec;
+      const uint32_t v = (uint32_t)(it - blk * nvec);
+      const int s0 = blk_src[blk], ns = blk_src[blk + 1] - s0;
+      const int t0 = blk_tgt[blk], nt = blk_tgt[blk + 1] - t0;
+      // piece k of this thread: row (tid + 256 k) / 4, quarter tid % 4;
+      // threads past the list read its first entry into the discard entry
+      auto piece = [&](int k, float4& st, int& slot) __attribute__((always_inline)) {
+        const int idx = tid + kHadThreads * k, r = idx >> 2, part = idx & 3;
+        const int32_t e = blk_list[s0 + (r < ns ? r : 0)];
+        const uint32_t src = (uint32_t)e >> 8;
+        const uint32_t off = ((src * (uint32_t)nvec + v) * 16 + 4 * part) * 4u;
+        st = *reinterpret_cast<const float4*>(qf + off);
+        slot = r < ns ? (e & 255) * kRow + part : kHadSrcMax * kRow;
+      };
+      piece(0, stg0, sl0);
+      piece(1, stg1, sl1);
+      piece(2, stg2, sl2);
+      piece(3, stg3, sl3);
+      const int tr = min(tr0 + rl, nt - 1);
+#pragma unroll
+      for (int k = 0; k < 7; ++k) wn[k] = slots[(int64_t)(t0 + tr) * 7 + k];
+    }
+    if (it == item0) continue;
+    const int64_t item = it - 1;
+    const int64_t blk = item / nvec;
+    const int v = (int)(item - blk * nvec);
+    const int t0 = blk_tgt[blk], nt = blk_tgt[blk + 1] - t0;
+    const int cur = buf;
+    buf ^= 1;
+    if (tr0 >= nt) continue;
+    // two accumulators (even / odd directions) so consecutive MFMAs are
+    // independent
+    v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+#pragma unroll
+    for (int d = 0; d < 26; ++d) {
+      const uint32_t slot = (w[d / 4] >> (8 * (d % 4))) & 0xffu;
+      const float4 a = As[cur][slot * kRow + g];
+      v4f& acc = (d & 1) ? acc1 : acc0;
+      acc = mfma16(a.x, B[d].x, acc);
+      acc = mfma16(a.y, B[d].y, acc);
+      acc = mfma16(a.z, B[d].z, acc);
+      acc = mfma16(a.w, B[d].w, acc);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int to = tr0 + out_row(0.f, g, i);
+      if (to < nt) pf[((int64_t)(t0 + to) * nvec + v) * 16 + rl] = acc0[i] + acc1[i];
+    }
+  }
+}
+
 template <typename T, int P, int ITEMS>
 hipError_t fwd_launch(const double* M, const int32_t* child, int64_t n_rows, int nvec,
                       const int16_t* lat2surf, const void* tw, void* Qhat, hipStream_t s) {
@@ -415,27 +536,34 @@ hipError_t launch_fft_inverse(int p, bool fp64, const void* Phat, const int32_t*
 }
 
 hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
-                           const int32_t* halo, int64_t n_clusters, int nvec, void* Phat,
-                           hipStream_t stream) {
+                           const int32_t* halo, int64_t n_blocks, const int32_t* blk_tgt,
+                           const int32_t* blk_src, const int32_t* blk_list, const uint32_t* slots,
+                           int64_t n_clusters, int nvec, void* Phat, hipStream_t stream) {
   const int64_t n_rows = n_clusters * nvec;
   if (n_rows == 0) return hipSuccess;
-  // 24-bit cluster products and 32-bit byte offsets within one frequency
-  if (n_clusters + 1 >= (int64_t(1) << 24) ||
+  // 24-bit cluster indices and 32-bit byte offsets within one frequency
+  if (n_clusters + 1 >= (int64_t(1) << 23) ||
       (n_clusters + 1) * nvec * 16 * (fp64 ? 8 : 4) >= (int64_t(1) << 32))
     return hipErrorInvalidValue;
-  const int64_t tiles = (n_rows + 15) / 16;
-  const int tpw = tiles >= 256 ? 8 : tiles >= 64 ? 4 : 1;
-  const int n_chunks = (int)((tiles + 4 * tpw - 1) / (4 * tpw));
-  const int64_t total = (int64_t)F * n_chunks;
-  const unsigned grid = (unsigned)(8 * ((total + 7) / 8));
-  if (fp64)
-    hadamard_kernel<double><<<grid, kHadThreads, 0, stream>>>(
+  if (fp64) {
+    const int64_t tiles = (n_rows + 15) / 16;
+    const int tpw = tiles >= 256 ? 8 : tiles >= 64 ? 4 : 1;
+    const int n_chunks = (int)((tiles + 4 * tpw - 1) / (4 * tpw));
+    const int64_t total = (int64_t)F * n_chunks;
+    const unsigned grid = (unsigned)(8 * ((total + 7) / 8));
+    hadamard_gather_kernel<double><<<grid, kHadThreads, 0, stream>>>(
         (const double2*)Khat, (const double*)Qhat, halo, n_clusters, nvec, n_rows, n_chunks, tpw,
         total, (double*)Phat);
-  else
-    hadamard_kernel<float><<<grid, kHadThreads, 0, stream>>>(
-        (const float2*)Khat, (const float*)Qhat, halo, n_clusters, nvec, n_rows, n_chunks, tpw,
-        total, (float*)Phat);
+    return hipGetLastError();
+  }
+  const int64_t n_items = n_blocks * nvec;
+  const int ipw = n_items >= 64 ? 8 : n_items >= 16 ? 4 : 1;
+  const int n_groups = (int)((n_items + ipw - 1) / ipw);
+  const int64_t total = (int64_t)F * n_groups;
+  const unsigned grid = (unsigned)(8 * ((total + 7) / 8));
+  hadamard_block_kernel<<<grid, kHadThreads, 0, stream>>>(
+      (const float2*)Khat, (const float*)Qhat, blk_tgt, blk_src, blk_list, slots, n_items, nvec,
+      n_rows, ipw, n_groups, total, (float*)Phat);
   return hipGetLastError();
 }
 

@@ -55,10 +55,14 @@ hipError_t launch_fft_forward(int p, bool fp64, const double* M, const int32_t* 
 // Hadamard products by sibling cluster: Phat[f][row][i] = sum_d sum_j
 // Khat[f][d][i][j] Qhat[f][halo[d][c] * nvec + v][j], row = c * nvec + v.
 // Qhat holds n_clusters + 1 clusters per frequency, the last one zero;
-// absent neighbours have halo[d][c] = n_clusters.
+// absent neighbours name it.  FP64 gathers through halo; FP32 stages
+// source blocks: block b covers clusters [blk_tgt[b], blk_tgt[b + 1]), its
+// sources are blk_list[blk_src[b] ...] packed as cluster << 8 | slot, and
+// byte d of slots[c] (7 words per cluster) is the slot of halo[d][c].
 hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
-                           const int32_t* halo, int64_t n_clusters, int nvec, void* Phat,
-                           hipStream_t stream);
+                           const int32_t* halo, int64_t n_blocks, const int32_t* blk_tgt,
+                           const int32_t* blk_src, const int32_t* blk_list, const uint32_t* slots,
+                           int64_t n_clusters, int nvec, void* Phat, hipStream_t stream);
 // Inverse: spectra -> check potentials out[box][v][s] = scale * phi (FP64).
 hipError_t launch_fft_inverse(int p, bool fp64, const void* Phat, const int32_t* child,
                               int64_t n_clusters, int nvec, const int16_t* surf_lat,
