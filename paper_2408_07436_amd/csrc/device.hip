@@ -15,6 +15,11 @@ struct DevLevel {
   double w = 1.0;               // box width
   int32_t* child = nullptr;     // [n][8]
   int32_t* halo = nullptr;      // [26][n_{l-1}]
+  // FFT-M2L work buffers of this level (levels run concurrently): spectra
+  // of the n_{l-1} + 1 clusters, their products, and the check potentials
+  void* Qhat = nullptr;
+  void* Phat = nullptr;
+  double* chk = nullptr;
   // FFT-M2L source blocks: the clusters of one aligned 4 x 4 x 4 cube of
   // level l-1 (consecutive in Morton order) share one list of at most 216
   // source clusters with LDS slots; slots[c] holds, per direction, the slot
@@ -76,8 +81,11 @@ struct DeviceState {
   double* tmp2 = nullptr;
   double* gemm_ws = nullptr;  // split-K partials
   int64_t gemm_ws_elems = 0;
-  void* Qhat = nullptr;
-  void* Phat = nullptr;
+  // FFT-M2L levels below the leaves run on side streams forked from the
+  // evaluate stream after the upward pass and joined before the downward pass
+  std::vector<hipStream_t> side;   // [depth + 1], levels 2 .. depth - 1
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipEvent_t> join_ev;  // [depth + 1]
   std::vector<void*> work_allocs;
   hipEvent_t ev[6] = {};
   std::vector<hipEvent_t> lev_ev;  // [level][4] marks around the M2L kernels
@@ -401,12 +409,14 @@ kifmm_status upload_all(kifmm_handle* h) {
 
   if (h->cfg.m2l == KIFMM_M2L_FFT) {
     const int n = op.n, F = op.F;
-    // twiddles exp(-2 pi i m / n)
-    std::vector<double> tw(2 * n);
-    for (int m = 0; m < n; ++m) {
-      tw[2 * m] = std::cos(2.0 * M_PI * m / n);
-      tw[2 * m + 1] = -std::sin(2.0 * M_PI * m / n);
-    }
+    // twiddle matrix Wm[k][j] = exp(-2 pi i (k j mod n) / n), k < n, j < p
+    std::vector<double> tw(2 * (size_t)n * op.p);
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < op.p; ++j) {
+        const int m = (k * j) % n;
+        tw[2 * ((size_t)k * op.p + j)] = std::cos(2.0 * M_PI * m / n);
+        tw[2 * ((size_t)k * op.p + j) + 1] = -std::sin(2.0 * M_PI * m / n);
+      }
     // kernel spectra in sibling-cluster frequency order [f][26][8 i][8 j]
     std::vector<double> kh((size_t)F * 26 * 64 * 2, 0.0);
     for (int dd = 0; dd < 26; ++dd) {
@@ -455,6 +465,15 @@ kifmm_status upload_all(kifmm_handle* h) {
   d->lev_ev.assign(4 * (depth + 1), nullptr);
   for (auto& e : d->lev_ev) KIFMM_HIP(hipEventCreate(&e));
   d->events = true;
+  if (h->cfg.m2l == KIFMM_M2L_FFT) {
+    KIFMM_HIP(hipEventCreateWithFlags(&d->fork_ev, hipEventDisableTiming));
+    d->side.assign(depth + 1, nullptr);
+    d->join_ev.assign(depth + 1, nullptr);
+    for (int l = 2; l < depth; ++l) {
+      KIFMM_HIP(hipStreamCreateWithFlags(&d->side[l], hipStreamNonBlocking));
+      KIFMM_HIP(hipEventCreateWithFlags(&d->join_ev[l], hipEventDisableTiming));
+    }
+  }
   return KIFMM_OK;
 }
 
@@ -498,14 +517,17 @@ kifmm_status ensure_work(kifmm_handle* h, int nvec) {
     d->qpad = qp;
   }
   if (h->cfg.m2l == KIFMM_M2L_FFT) {
-    int64_t maxc = 0;
-    for (int l = 2; l <= depth; ++l) maxc = std::max(maxc, t.levels[l - 1].n);
     const size_t cb = d->fp64 ? 16 : 8;
-    char *a, *b;
-    KIFMM_TRY(dalloc(d, &a, (size_t)op.F * (maxc + 1) * nvec * 8 * cb, true));  // + empty cluster
-    KIFMM_TRY(dalloc(d, &b, (size_t)op.F * maxc * nvec * 8 * cb, true));
-    d->Qhat = a;
-    d->Phat = b;
+    for (int l = 2; l <= depth; ++l) {
+      DevLevel& D = d->lv[l];
+      const size_t nc = (size_t)t.levels[l - 1].n;
+      char *a, *b;
+      KIFMM_TRY(dalloc(d, &a, (size_t)op.F * (nc + 1) * nvec * 8 * cb, true));  // + empty cluster
+      KIFMM_TRY(dalloc(d, &b, (size_t)op.F * nc * nvec * 8 * cb, true));
+      KIFMM_TRY(dalloc(d, &D.chk, (size_t)t.levels[l].n * nvec * ns, true));
+      D.Qhat = a;
+      D.Phat = b;
+    }
   }
   d->nvec_cap = nvec;
   return KIFMM_OK;
@@ -545,13 +567,13 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
     const int32_t* child = d->lv[l - 1].child;
     // spectra of the nc clusters and of the empty cluster behind them
     KIFMM_LAUNCH(launch_fft_forward(op.p, d->fp64, in, child, nc + 1, nvec, d->lat2surf,
-                                    d->twiddle, d->Qhat, s));
+                                    d->twiddle, D.Qhat, s));
     if (mark) KIFMM_HIP(hipEventRecord(mark[1], s));
-    KIFMM_LAUNCH(launch_hadamard(d->fp64, op.F, d->khat, d->Qhat, D.halo, D.hb_n, D.hb_tgt,
-                                 D.hb_src, D.hb_list, D.hb_slots, nc, nvec, d->Phat, s));
+    KIFMM_LAUNCH(launch_hadamard(d->fp64, op.F, d->khat, D.Qhat, D.halo, D.hb_n, D.hb_tgt,
+                                 D.hb_src, D.hb_list, D.hb_slots, nc, nvec, D.Phat, s));
     if (mark) KIFMM_HIP(hipEventRecord(mark[2], s));
     const double scale = 1.0 / ((double)op.n * op.n * op.n * D.w);  // 1 / (n^3 w)
-    KIFMM_LAUNCH(launch_fft_inverse(op.p, d->fp64, d->Phat, child, nc, nvec, d->surf_lat,
+    KIFMM_LAUNCH(launch_fft_inverse(op.p, d->fp64, D.Phat, child, nc, nvec, d->surf_lat,
                                     d->twiddle, scale, out, s));
     if (mark) KIFMM_HIP(hipEventRecord(mark[3], s));
     return KIFMM_OK;
@@ -608,6 +630,11 @@ void destroy_device(DeviceState* d) {
     for (auto& e : d->ev) hipEventDestroy(e);
   for (auto& e : d->lev_ev)
     if (e) hipEventDestroy(e);
+  if (d->fork_ev) hipEventDestroy(d->fork_ev);
+  for (auto& e : d->join_ev)
+    if (e) hipEventDestroy(e);
+  for (auto& st : d->side)
+    if (st) hipStreamDestroy(st);
   for (void* p : d->work_allocs) hipFree(p);
   for (void* p : d->allocs) hipFree(p);
   delete d;
@@ -656,16 +683,36 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
   }
   if (timed) KIFMM_HIP(hipEventRecord(d->ev[1], s));
   // downward pass
+  const bool fft = h->cfg.m2l == KIFMM_M2L_FFT;
+  // under stream capture (batches) the levels run back to back on s: the
+  // side-stream fork is not recorded into graphs
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  KIFMM_HIP(hipStreamIsCapturing(s, &cap));
+  const bool fork = fft && cap == hipStreamCaptureStatusNone;
+  if (fork) {
+    // M2L of every level needs only the upward pass: the levels below the
+    // leaves run on side streams while the leaf level runs on s
+    KIFMM_HIP(hipEventRecord(d->fork_ev, s));
+    for (int l = 2; l < depth; ++l) {
+      KIFMM_HIP(hipStreamWaitEvent(d->side[l], d->fork_ev, 0));
+      KIFMM_TRY(m2l_level(h, l, d->mult[l], d->lv[l].chk, nvec, d->side[l], timed));
+      KIFMM_HIP(hipEventRecord(d->join_ev[l], d->side[l]));
+    }
+    KIFMM_TRY(m2l_level(h, depth, d->mult[depth], d->lv[depth].chk, nvec, s, timed));
+    for (int l = 2; l < depth; ++l) KIFMM_HIP(hipStreamWaitEvent(s, d->join_ev[l], 0));
+    if (timed) KIFMM_HIP(hipEventRecord(d->ev[4], s));
+  }
   for (int l = 2; l <= depth; ++l) {
     const DevLevel& D = d->lv[l];
-    KIFMM_TRY(m2l_level(h, l, d->mult[l], d->phi, nvec, s, timed));
+    double* chk = fft ? D.chk : d->phi;
+    if (!fork) KIFMM_TRY(m2l_level(h, l, d->mult[l], chk, nvec, s, timed));
     if (l >= 3) {
       const DevLevel& P = d->lv[l - 1];
       Gemm64 g{d->l2l, 8 * ns, ns, ns, 1.0 / P.w, d->local[l - 1], ns, 1, nullptr,
-               (int64_t)nvec * ns, ns, d->phi, ns, 8, P.child, (int64_t)nvec * ns, ns, P.n, nvec, 1};
+               (int64_t)nvec * ns, ns, chk, ns, 8, P.child, (int64_t)nvec * ns, ns, P.n, nvec, 1};
       KIFMM_LAUNCH(gemm(d, g, s));
     }
-    KIFMM_TRY(pinv_apply(h, d->down_V, d->down_Ut, op.r_down, D.w, d->phi, d->local[l], D.n, nvec, s));
+    KIFMM_TRY(pinv_apply(h, d->down_V, d->down_Ut, op.r_down, D.w, chk, d->local[l], D.n, nvec, s));
   }
   if (timed) KIFMM_HIP(hipEventRecord(d->ev[2], s));
   KIFMM_LAUNCH(launch_leaf_eval(d->tgt_xyz, d->src_xyz, d->src_xyz_f, d->qs, d->fp64, t.n_src,
@@ -687,7 +734,14 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
         KIFMM_HIP(hipEventElapsedTime(&ms, d->lev_ev[4 * l + k], d->lev_ev[4 * l + k + 1]));
         parts[k] += ms;
       }
-    const double m2l_ms = parts[0] + parts[1] + parts[2];
+    // FFT: wall time from the fork to the join (levels overlap); otherwise
+    // the levels run back to back and their kernel phases add up
+    double m2l_ms = parts[0] + parts[1] + parts[2];
+    if (fork) {
+      float w = 0.f;
+      KIFMM_HIP(hipEventElapsedTime(&w, d->ev[1], d->ev[4]));
+      m2l_ms = w;
+    }
     h->timings[0] = a;
     h->timings[1] = m2l_ms;
     h->timings[2] = b - m2l_ms;

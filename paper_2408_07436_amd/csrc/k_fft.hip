@@ -16,6 +16,8 @@
 // 3. fft_inverse: complex inverse DFTs along x and y, then the c2r step along
 //    z (odd length: no Nyquist term), evaluated only at the check-surface
 //    lattice points.
+// The transforms are direct sums along each axis with the n x p twiddle
+// matrix Wm[k][j] = exp(-2 pi i (k j mod n) / n).
 #include "kernels.h"
 
 namespace kifmm {
@@ -26,40 +28,87 @@ template <typename T> struct C2T;
 template <> struct C2T<float> { using type = float2; };
 template <> struct C2T<double> { using type = double2; };
 
+// acc += a * w and acc += a * conj(w) as four FMAs each
 template <typename C2>
-__device__ inline C2 cmul(C2 a, C2 b) {
-  C2 r;
-  r.x = a.x * b.x - a.y * b.y;
-  r.y = a.x * b.y + a.y * b.x;
-  return r;
+__device__ inline void cmac(C2& acc, C2 a, C2 w) {
+  acc.x = fma(a.x, w.x, acc.x);
+  acc.x = fma(-a.y, w.y, acc.x);
+  acc.y = fma(a.x, w.y, acc.y);
+  acc.y = fma(a.y, w.x, acc.y);
 }
-// a * conj(b)
 template <typename C2>
-__device__ inline C2 cmulc(C2 a, C2 b) {
-  C2 r;
-  r.x = a.x * b.x + a.y * b.y;
-  r.y = a.y * b.x - a.x * b.y;
-  return r;
+__device__ inline void cmacc(C2& acc, C2 a, C2 w) {
+  acc.x = fma(a.x, w.x, acc.x);
+  acc.x = fma(a.y, w.y, acc.x);
+  acc.y = fma(a.y, w.x, acc.y);
+  acc.y = fma(-a.x, w.y, acc.y);
 }
 
-constexpr int kFftThreads = 256;
+// LDS layout of the separable transforms, per order P and complex width
+// (W = 2 dwords for FP32, 4 for FP64): `items` (row, child) boxes per
+// workgroup; the z-stage buffer a1[item][x][y][kz] and the x/y-stage buffer
+// a2[item][x][ky][kz] (complex units).  The strides are padded so that the
+// lanes of each stage hit distinct LDS banks as far as possible (chosen by
+// a bank model of the three stages' access patterns).
+template <int P, int W> struct FftLds;
+#define KIFMM_FFT_LDS(PP, WW, IT, A, B, C, D, E, F)                                   \
+  template <> struct FftLds<PP, WW> {                                                \
+    static constexpr int items = IT, s1y = A, s1x = B, s1i = C, s2k = D, s2x = E, s2i = F; \
+  };
+KIFMM_FFT_LDS(2, 2, 8, 3, 6, 12, 2, 8, 18)
+KIFMM_FFT_LDS(2, 4, 8, 3, 6, 12, 2, 6, 13)
+KIFMM_FFT_LDS(3, 2, 8, 4, 19, 57, 3, 19, 58)
+KIFMM_FFT_LDS(3, 4, 8, 4, 19, 57, 3, 19, 57)
+KIFMM_FFT_LDS(4, 2, 8, 5, 20, 80, 4, 28, 114)
+KIFMM_FFT_LDS(4, 4, 8, 5, 20, 80, 4, 28, 113)
+KIFMM_FFT_LDS(5, 2, 8, 5, 25, 125, 5, 53, 266)
+KIFMM_FFT_LDS(5, 4, 4, 6, 37, 185, 5, 45, 226)
+KIFMM_FFT_LDS(6, 2, 8, 7, 42, 252, 6, 70, 422)
+KIFMM_FFT_LDS(6, 4, 4, 7, 42, 252, 6, 70, 422)
+KIFMM_FFT_LDS(7, 2, 4, 7, 54, 383, 7, 103, 724)
+KIFMM_FFT_LDS(7, 4, 2, 7, 49, 343, 7, 95, 668)
+KIFMM_FFT_LDS(8, 2, 2, 9, 72, 576, 8, 120, 968)
+KIFMM_FFT_LDS(8, 4, 1, 9, 72, 576, 8, 120, 960)
+#undef KIFMM_FFT_LDS
 
-template <typename T, int P, int ITEMS>
-__global__ __launch_bounds__(kFftThreads) void fft_forward_kernel(
+template <typename T, int P> struct FftCfg {
+  using L = FftLds<P, (int)sizeof(T) / 2>;
+  static constexpr int items = L::items;
+  // one thread per line of the z and y stages
+  static constexpr int threads = (items * P * P + 63) / 64 * 64;
+};
+
+// Forward transforms of `items` boxes per workgroup in three stages, each
+// thread transforming whole lines so that the twiddle matrix
+// Wm[k][j] = exp(-2 pi i (k j mod n) / n) (n x p) is read at wave-uniform
+// addresses:
+//   z: a1[x][y][kz] = sum_z d(x, y, z) Wm[kz][z]        (real input, kz < p)
+//   y: a2[x][ky][kz] = sum_y a1[x][y][kz] Wm[ky][y]     (ky < n)
+//   x: Qhat[f][row][child] = sum_x a2[x][ky][kz] Wm[kx][x], f = (kx n + ky) p + kz.
+// Box item g is child g % 8 of row g / 8 (row = cluster * nvec + v).
+template <typename T, int P>
+__global__ __launch_bounds__((FftCfg<T, P>::threads)) void fft_forward_kernel(
     const double* __restrict__ M, const int32_t* __restrict__ child, int64_t n_rows, int nvec,
-    const int16_t* __restrict__ lat2surf, const typename C2T<T>::type* __restrict__ tw,
+    const int16_t* __restrict__ lat2surf, const typename C2T<T>::type* __restrict__ Wm,
     typename C2T<T>::type* __restrict__ Qhat) {
   using C2 = typename C2T<T>::type;
+  using L = typename FftCfg<T, P>::L;
   constexpr int N = 2 * P - 1, H = P, NS = 6 * (P - 1) * (P - 1) + 2;
-  __shared__ C2 w[N];
+  constexpr int IT = FftCfg<T, P>::items, TH = FftCfg<T, P>::threads;
+  __shared__ C2 a1[IT * L::s1i];
+  __shared__ C2 a2[IT * L::s2i];
   __shared__ int16_t l2s[P * P * P];
-  __shared__ T sv[ITEMS][NS];
-  __shared__ C2 a1[ITEMS][P][P][H];
+  T* sv = reinterpret_cast<T*>(a2);  // densities; read before a2 is written
+  static_assert(IT * NS * sizeof(T) <= IT * L::s2i * sizeof(C2), "density staging fits in a2");
   const int tid = threadIdx.x;
-  const int64_t g0 = (int64_t)blockIdx.x * ITEMS;  // first (row, child) item
-  for (int t = tid; t < N; t += kFftThreads) w[t] = tw[t];
-  for (int t = tid; t < P * P * P; t += kFftThreads) l2s[t] = lat2surf[t];
-  for (int idx = tid; idx < ITEMS * NS; idx += kFftThreads) {
+  // consecutive rows on one XCD, so the two 64-byte halves of a 128-byte
+  // line of Qhat meet in the same L2
+  const int64_t nwg = (n_rows * 8 + IT - 1) / IT, per_xcd = (nwg + 7) / 8;
+  const int64_t wg = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (wg >= nwg) return;
+  const int64_t g0 = wg * IT;
+  for (int t = tid; t < P * P * P; t += TH) l2s[t] = lat2surf[t];
+  for (int idx = tid; idx < IT * NS; idx += TH) {
     const int it = idx / NS, s = idx % NS;
     const int64_t g = g0 + it, row = g / 8;
     double val = 0.0;
@@ -69,83 +118,91 @@ __global__ __launch_bounds__(kFftThreads) void fft_forward_kernel(
       const int32_t box = child[c * 8 + (g % 8)];
       if (box >= 0) val = M[((int64_t)box * nvec + v) * NS + s];
     }
-    sv[it][s] = (T)val;
+    sv[idx] = (T)val;
   }
   __syncthreads();
-  // z: real -> complex, kz in [0, p)
-  for (int idx = tid; idx < ITEMS * P * P * H; idx += kFftThreads) {
-    const int it = idx / (P * P * H);
-    const int rem = idx % (P * P * H);
-    const int x = rem / (P * H), y = (rem / H) % P, kz = rem % H;
-    C2 acc;
-    acc.x = T(0);
-    acc.y = T(0);
+  for (int idx = tid; idx < IT * P * P; idx += TH) {
+    const int it = idx / (P * P), x = (idx / P) % P, y = idx % P;
+    T dz[P];
 #pragma unroll
     for (int z = 0; z < P; ++z) {
-      const int s = l2s[(x * P + y) * P + z];
-      if (s >= 0) {
-        const T d = sv[it][s];
-        const C2 wz = w[(kz * z) % N];
-        acc.x += d * wz.x;
-        acc.y += d * wz.y;
-      }
+      const int sidx = l2s[(x * P + y) * P + z];
+      const T dv = sv[it * NS + (sidx < 0 ? 0 : sidx)];
+      dz[z] = sidx < 0 ? T(0) : dv;
     }
-    a1[it][x][y][kz] = acc;
+#pragma unroll
+    for (int kz = 0; kz < H; ++kz) {
+      C2 acc;  // Wm[kz][0] = 1
+      acc.x = dz[0];
+      acc.y = T(0);
+#pragma unroll
+      for (int z = 1; z < P; ++z) {
+        const C2 wv = Wm[kz * P + z];
+        acc.x = fma(dz[z], wv.x, acc.x);
+        acc.y = fma(dz[z], wv.y, acc.y);
+      }
+      a1[it * L::s1i + x * L::s1x + y * L::s1y + kz] = acc;
+    }
   }
   __syncthreads();
-  // y then x; each task owns one (ky, kz) column of one item
-  for (int idx = tid; idx < ITEMS * N * H; idx += kFftThreads) {
-    const int it = idx % ITEMS, col = idx / ITEMS;
+  for (int idx = tid; idx < IT * P * H; idx += TH) {
+    const int it = idx / (P * H), x = (idx / H) % P, kz = idx % H;
+    C2 in[P];
+#pragma unroll
+    for (int y = 0; y < P; ++y) in[y] = a1[it * L::s1i + x * L::s1x + y * L::s1y + kz];
+#pragma unroll
+    for (int ky = 0; ky < N; ++ky) {
+      C2 acc = in[0];  // Wm[ky][0] = 1
+#pragma unroll
+      for (int y = 1; y < P; ++y) cmac(acc, in[y], Wm[ky * P + y]);
+      a2[it * L::s2i + x * L::s2x + ky * L::s2k + kz] = acc;
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < IT * N * H; idx += TH) {
+    const int it = idx % IT, col = idx / IT;
     const int ky = col / H, kz = col % H;
     const int64_t g = g0 + it, row = g / 8;
     if (row >= n_rows) continue;
-    C2 cx[P];
+    C2 in[P];
 #pragma unroll
-    for (int x = 0; x < P; ++x) {
-      C2 acc;
-      acc.x = T(0);
-      acc.y = T(0);
-#pragma unroll
-      for (int y = 0; y < P; ++y) {
-        const C2 t = cmul(a1[it][x][y][kz], w[(ky * y) % N]);
-        acc.x += t.x;
-        acc.y += t.y;
-      }
-      cx[x] = acc;
-    }
+    for (int x = 0; x < P; ++x) in[x] = a2[it * L::s2i + x * L::s2x + ky * L::s2k + kz];
 #pragma unroll
     for (int kx = 0; kx < N; ++kx) {
-      C2 acc;
-      acc.x = T(0);
-      acc.y = T(0);
+      C2 acc = in[0];  // Wm[kx][0] = 1
 #pragma unroll
-      for (int x = 0; x < P; ++x) {
-        const C2 t = cmul(cx[x], w[(kx * x) % N]);
-        acc.x += t.x;
-        acc.y += t.y;
-      }
+      for (int x = 1; x < P; ++x) cmac(acc, in[x], Wm[kx * P + x]);
       const int64_t f = ((int64_t)kx * N + ky) * H + kz;
       Qhat[(f * n_rows + row) * 8 + (g % 8)] = acc;
     }
   }
 }
 
+// Inverse transforms, one (row, child) box per item: complex inverse DFTs
+// along x (only x < p kept) and y (y < p), then the complex-to-real step
+// along z (odd length: no Nyquist term) at the check-surface points, scaled.
+// Twiddles conj(Wm[k][j]); one output per task in the y and z stages.
+constexpr int kInvThreads = 256;
+template <typename C2>
+__device__ inline C2 cmulc(C2 a, C2 b) {  // a * conj(b)
+  C2 r;
+  r.x = a.x * b.x + a.y * b.y;
+  r.y = a.y * b.x - a.x * b.y;
+  return r;
+}
 template <typename T, int P, int ITEMS>
-__global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(
+__global__ __launch_bounds__(kInvThreads) void fft_inverse_kernel(
     const typename C2T<T>::type* __restrict__ Phat, const int32_t* __restrict__ child,
     int64_t n_rows, int nvec, const int16_t* __restrict__ surf_lat,
-    const typename C2T<T>::type* __restrict__ tw, double scale, double* __restrict__ out) {
+    const typename C2T<T>::type* __restrict__ Wm, double scale, double* __restrict__ out) {
   using C2 = typename C2T<T>::type;
   constexpr int N = 2 * P - 1, H = P, NS = 6 * (P - 1) * (P - 1) + 2;
-  __shared__ C2 w[N];
   __shared__ C2 b2[ITEMS][P][N][H];
   __shared__ C2 b1[ITEMS][P][P][H];
   const int tid = threadIdx.x;
   const int64_t g0 = (int64_t)blockIdx.x * ITEMS;
-  for (int t = tid; t < N; t += kFftThreads) w[t] = tw[t];
-  __syncthreads();
   // x: complex inverse, only x in [0, p) is kept
-  for (int idx = tid; idx < ITEMS * N * H; idx += kFftThreads) {
+  for (int idx = tid; idx < ITEMS * N * H; idx += kInvThreads) {
     const int it = idx % ITEMS, col = idx / ITEMS;
     const int ky = col / H, kz = col % H;
     const int64_t g = g0 + it, row = g / 8;
@@ -167,7 +224,7 @@ __global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(
       acc.y = T(0);
 #pragma unroll
       for (int kx = 0; kx < N; ++kx) {
-        const C2 t = cmulc(v[kx], w[(kx * x) % N]);
+        const C2 t = cmulc(v[kx], Wm[kx * P + x]);
         acc.x += t.x;
         acc.y += t.y;
       }
@@ -176,7 +233,7 @@ __global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(
   }
   __syncthreads();
   // y: complex inverse, y in [0, p)
-  for (int idx = tid; idx < ITEMS * P * P * H; idx += kFftThreads) {
+  for (int idx = tid; idx < ITEMS * P * P * H; idx += kInvThreads) {
     const int it = idx / (P * P * H);
     const int rem = idx % (P * P * H);
     const int x = rem / (P * H), y = (rem / H) % P, kz = rem % H;
@@ -185,7 +242,7 @@ __global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(
     acc.y = T(0);
 #pragma unroll
     for (int ky = 0; ky < N; ++ky) {
-      const C2 t = cmulc(b2[it][x][ky][kz], w[(ky * y) % N]);
+      const C2 t = cmulc(b2[it][x][ky][kz], Wm[ky * P + y]);
       acc.x += t.x;
       acc.y += t.y;
     }
@@ -193,7 +250,7 @@ __global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(
   }
   __syncthreads();
   // z: complex -> real on the check-surface points only
-  for (int idx = tid; idx < ITEMS * NS; idx += kFftThreads) {
+  for (int idx = tid; idx < ITEMS * NS; idx += kInvThreads) {
     const int it = idx / NS, s = idx % NS;
     const int64_t g = g0 + it, row = g / 8;
     if (row >= n_rows) continue;
@@ -205,7 +262,7 @@ __global__ __launch_bounds__(kFftThreads) void fft_inverse_kernel(
     T val = b1[it][x][y][0].x;
     T acc = T(0);
 #pragma unroll
-    for (int kz = 1; kz < H; ++kz) acc += cmulc(b1[it][x][y][kz], w[(kz * z) % N]).x;
+    for (int kz = 1; kz < H; ++kz) acc += cmulc(b1[it][x][y][kz], Wm[kz * P + z]).x;
     val += T(2) * acc;
     out[((int64_t)box * nvec + v) * NS + s] = scale * (double)val;
   }
@@ -460,43 +517,43 @@ __global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_kernel(
   }
 }
 
-template <typename T, int P, int ITEMS>
+template <typename T, int P>
 hipError_t fwd_launch(const double* M, const int32_t* child, int64_t n_rows, int nvec,
-                      const int16_t* lat2surf, const void* tw, void* Qhat, hipStream_t s) {
+                      const int16_t* lat2surf, const void* wm, void* Qhat, hipStream_t s) {
   using C2 = typename C2T<T>::type;
-  const int64_t items = n_rows * 8;
-  const unsigned grid = (unsigned)((items + ITEMS - 1) / ITEMS);
-  fft_forward_kernel<T, P, ITEMS><<<grid, kFftThreads, 0, s>>>(M, child, n_rows, nvec, lat2surf,
-                                                             (const C2*)tw, (C2*)Qhat);
+  constexpr int IT = FftCfg<T, P>::items;
+  const unsigned grid = (unsigned)(8 * (((n_rows * 8 + IT - 1) / IT + 7) / 8));
+  fft_forward_kernel<T, P><<<grid, FftCfg<T, P>::threads, 0, s>>>(M, child, n_rows, nvec, lat2surf,
+                                                                (const C2*)wm, (C2*)Qhat);
   return hipGetLastError();
 }
 
-template <typename T, int P, int ITEMS>
-hipError_t inv_launch(const void* Phat, const int32_t* child, int64_t n_rows, int nvec,
-                      const int16_t* surf_lat, const void* tw, double scale, double* out,
-                      hipStream_t s) {
-  using C2 = typename C2T<T>::type;
-  const int64_t items = n_rows * 8;
-  const unsigned grid = (unsigned)((items + ITEMS - 1) / ITEMS);
-  fft_inverse_kernel<T, P, ITEMS><<<grid, kFftThreads, 0, s>>>((const C2*)Phat, child, n_rows, nvec,
-                                                             surf_lat, (const C2*)tw, scale, out);
-  return hipGetLastError();
-}
-
-// items per workgroup, sized so the LDS stays within 64 KiB
-template <typename T, int P> struct Items {
+// inverse items per workgroup, sized so the LDS stays within 48 KiB
+template <typename T, int P> struct InvItems {
   static constexpr int bytes = sizeof(T) * 2;
-  static constexpr int per = P * (2 * P - 1) * P * bytes + P * P * P * bytes;  // inverse
+  static constexpr int per = P * (2 * P - 1) * P * bytes + P * P * P * bytes;
   static constexpr int raw = 49152 / per;
   static constexpr int value = raw >= 16 ? 16 : raw >= 8 ? 8 : raw >= 4 ? 4 : raw >= 2 ? 2 : 1;
 };
 
+template <typename T, int P>
+hipError_t inv_launch(const void* Phat, const int32_t* child, int64_t n_rows, int nvec,
+                      const int16_t* surf_lat, const void* wm, double scale, double* out,
+                      hipStream_t s) {
+  using C2 = typename C2T<T>::type;
+  constexpr int IT = InvItems<T, P>::value;
+  const unsigned grid = (unsigned)((n_rows * 8 + IT - 1) / IT);
+  fft_inverse_kernel<T, P, IT><<<grid, kInvThreads, 0, s>>>((const C2*)Phat, child, n_rows, nvec,
+                                                          surf_lat, (const C2*)wm, scale, out);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t fwd_dispatch(int p, const double* M, const int32_t* child, int64_t n_rows, int nvec,
-                        const int16_t* l2s, const void* tw, void* Q, hipStream_t s) {
+                        const int16_t* l2s, const void* wm, void* Q, hipStream_t s) {
   switch (p) {
 #define KIFMM_FWD(PP) \
-  case PP: return fwd_launch<T, PP, Items<T, PP>::value>(M, child, n_rows, nvec, l2s, tw, Q, s);
+  case PP: return fwd_launch<T, PP>(M, child, n_rows, nvec, l2s, wm, Q, s);
     KIFMM_FWD(2) KIFMM_FWD(3) KIFMM_FWD(4) KIFMM_FWD(5) KIFMM_FWD(6) KIFMM_FWD(7) KIFMM_FWD(8)
 #undef KIFMM_FWD
     default: return hipErrorInvalidValue;
@@ -505,10 +562,10 @@ hipError_t fwd_dispatch(int p, const double* M, const int32_t* child, int64_t n_
 
 template <typename T>
 hipError_t inv_dispatch(int p, const void* Ph, const int32_t* child, int64_t n_rows, int nvec,
-                        const int16_t* sl, const void* tw, double scale, double* out, hipStream_t s) {
+                        const int16_t* l2s, const void* wm, double scale, double* out, hipStream_t s) {
   switch (p) {
 #define KIFMM_INV(PP) \
-  case PP: return inv_launch<T, PP, Items<T, PP>::value>(Ph, child, n_rows, nvec, sl, tw, scale, out, s);
+  case PP: return inv_launch<T, PP>(Ph, child, n_rows, nvec, l2s, wm, scale, out, s);
     KIFMM_INV(2) KIFMM_INV(3) KIFMM_INV(4) KIFMM_INV(5) KIFMM_INV(6) KIFMM_INV(7) KIFMM_INV(8)
 #undef KIFMM_INV
     default: return hipErrorInvalidValue;
@@ -519,20 +576,20 @@ hipError_t inv_dispatch(int p, const void* Ph, const int32_t* child, int64_t n_r
 
 hipError_t launch_fft_forward(int p, bool fp64, const double* M, const int32_t* child,
                               int64_t n_clusters, int nvec, const int16_t* lat2surf,
-                              const void* twiddle, void* Qhat, hipStream_t stream) {
+                              const void* wm, void* Qhat, hipStream_t stream) {
   const int64_t n_rows = n_clusters * nvec;
   if (n_rows == 0) return hipSuccess;
-  return fp64 ? fwd_dispatch<double>(p, M, child, n_rows, nvec, lat2surf, twiddle, Qhat, stream)
-              : fwd_dispatch<float>(p, M, child, n_rows, nvec, lat2surf, twiddle, Qhat, stream);
+  return fp64 ? fwd_dispatch<double>(p, M, child, n_rows, nvec, lat2surf, wm, Qhat, stream)
+              : fwd_dispatch<float>(p, M, child, n_rows, nvec, lat2surf, wm, Qhat, stream);
 }
 
 hipError_t launch_fft_inverse(int p, bool fp64, const void* Phat, const int32_t* child,
                               int64_t n_clusters, int nvec, const int16_t* surf_lat,
-                              const void* twiddle, double scale, double* out, hipStream_t stream) {
+                              const void* wm, double scale, double* out, hipStream_t stream) {
   const int64_t n_rows = n_clusters * nvec;
   if (n_rows == 0) return hipSuccess;
-  return fp64 ? inv_dispatch<double>(p, Phat, child, n_rows, nvec, surf_lat, twiddle, scale, out, stream)
-              : inv_dispatch<float>(p, Phat, child, n_rows, nvec, surf_lat, twiddle, scale, out, stream);
+  return fp64 ? inv_dispatch<double>(p, Phat, child, n_rows, nvec, surf_lat, wm, scale, out, stream)
+              : inv_dispatch<float>(p, Phat, child, n_rows, nvec, surf_lat, wm, scale, out, stream);
 }
 
 hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,

@@ -49,9 +49,12 @@ hipError_t launch_gemm64(const Gemm64& g, hipStream_t stream);
 // ---- FFT-M2L (Appendix A.1) ----------------------------------------------
 // Forward: densities M[box][v][ns] (FP64) of the children of each cluster
 // -> spectra Qhat[f][row][8] (complex, T), row = cluster * nvec + v.
+// lat2surf[(x p + y) p + z] is the surface index of a lattice point or -1;
+// wm is the twiddle matrix Wm[k][j] = exp(-2 pi i (k j mod n) / n), n x p
+// complex T.
 hipError_t launch_fft_forward(int p, bool fp64, const double* M, const int32_t* child,
                               int64_t n_clusters, int nvec, const int16_t* lat2surf,
-                              const void* twiddle, void* Qhat, hipStream_t stream);
+                              const void* wm, void* Qhat, hipStream_t stream);
 // Hadamard products by sibling cluster: Phat[f][row][i] = sum_d sum_j
 // Khat[f][d][i][j] Qhat[f][halo[d][c] * nvec + v][j], row = c * nvec + v.
 // Qhat holds n_clusters + 1 clusters per frequency, the last one zero;
@@ -64,9 +67,10 @@ hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
                            const int32_t* blk_src, const int32_t* blk_list, const uint32_t* slots,
                            int64_t n_clusters, int nvec, void* Phat, hipStream_t stream);
 // Inverse: spectra -> check potentials out[box][v][s] = scale * phi (FP64).
+// surf_lat[3 s + k] is lattice coordinate k of surface point s.
 hipError_t launch_fft_inverse(int p, bool fp64, const void* Phat, const int32_t* child,
                               int64_t n_clusters, int nvec, const int16_t* surf_lat,
-                              const void* twiddle, double scale, double* out, hipStream_t stream);
+                              const void* wm, double scale, double* out, hipStream_t stream);
 
 // ---- BLAS-M2L (Section 3.2) -----------------------------------------------
 // Fused per-level compressed M2L: out[box][v][0:k] = scale * sum over the
