@@ -11,8 +11,10 @@ order.  Inputs are resident in device memory before the timed region.
 The headline value is the M2L time per evaluate of the mixed-precision run
 (FP32 complex transforms and Hadamard products, FP64 local accumulation);
 the same path in FP64 is timed beside it.  The JSON line also carries the
-roofline of the dominant kernel, measured live with HIP events on the
-evaluate stream, and the FP64 CPU oracle timed on a bounded sample.
+roofline of the dominant kernel, measured live with HIP events (the leaf
+level's M2L kernels on their own through single-level stage calls, since the
+levels of an evaluate overlap), and the FP64 CPU oracle timed on a bounded
+sample.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -74,6 +76,42 @@ def m2l_work(f, depth, order, nvec, prec):
         had_bytes += 2 * spec + kern
         m2l_bytes += 2 * c["boxes"] * ns * 8 * nvec + 4 * spec + kern
     return had_flops, had_bytes, m2l_bytes
+
+
+def leaf_level_m2l(torch, f, w, reps):
+    """The leaf level's M2L on its own: one event-timed stage call at a time
+    (forward transform, Hadamard, inverse) on synthetic FP64 densities."""
+    lev = w.depth
+    ns = 6 * (w.order - 1) ** 2 + 2
+    g = torch.Generator(device="cuda")
+    g.manual_seed(w.order * 1000 + lev)
+    mult = torch.randn((f.num_boxes(lev), w.nvec, ns), dtype=torch.float64, device="cuda", generator=g)
+    out = torch.empty_like(mult)
+    for _ in range(3):
+        f.stage_m2l(lev, mult, out)
+    f.set_timing(True)
+    acc = np.zeros(3)
+    for _ in range(reps):
+        f.stage_m2l(lev, mult, out)
+        t = f.timings()
+        acc += (t["m2l_first"], t["m2l_main"], t["m2l_last"])
+    f.set_timing(False)
+    torch.cuda.synchronize()
+    return dict(zip(("fft_forward", "hadamard", "fft_inverse"), acc / reps))
+
+
+def leaf_level_work(f, w, prec):
+    """Algorithmic flops / HBM bytes of the leaf level's M2L kernels."""
+    n = 2 * w.order - 1
+    F = n * n * (n // 2 + 1)
+    ns = 6 * (w.order - 1) ** 2 + 2
+    cb = 8 if prec == "fp32" else 16
+    c = f.m2l_counts(w.depth)
+    spec = c["clusters"] * 8 * F * cb * w.nvec        # spectra of one side
+    dens = c["boxes"] * ns * 8 * w.nvec               # FP64 densities / check potentials
+    return {"hadamard_flops": 8.0 * 64 * F * c["cluster_pairs"] * w.nvec,
+            "hadamard_bytes": 2 * spec + 26 * 64 * F * cb,
+            "fft_forward_bytes": dens + spec, "fft_inverse_bytes": spec + dens}
 
 
 def p2p_work(pts, depth):
@@ -327,40 +365,55 @@ def main():
 
     had_flops, had_bytes, m2l_bytes = m2l_work(mix["f"], w.depth, w.order, w.nvec, "fp32")
     tm = mix["tm"]
-    n_launch = tm["m2l_levels"]
-    had_avg_s = tm["m2l_main"] / n_launch * 1e-3
+    # the leaf level's M2L kernels timed on their own (levels overlap inside
+    # an evaluate, so per-kernel times come from single-level stage calls)
+    lk = leaf_level_m2l(torch, mix["f"], w, args.steps)
+    lw = leaf_level_work(mix["f"], w, "fp32")
+    log(f"  leaf-level M2L kernels (level {w.depth}, alone): fwd {lk['fft_forward']:.4f} "
+        f"had {lk['hadamard']:.4f} inv {lk['fft_inverse']:.4f} ms")
     interactions = p2p_work(w.points, w.depth)
-    kernels = {
-        "hadamard": tm["m2l_main"],
-        "fft_forward": tm["m2l_first"],
-        "fft_inverse": tm["m2l_last"],
-        "leaf_eval": tm["leaves"],
-    }
+    kernels = dict(lk, leaf_eval=tm["leaves"])
     dominant = max(kernels, key=kernels.get)
-    roof_had = {"kernel": "hadamard_kernel<float> (v_mfma_f32_16x16x4f32)", "bound": "mfma",
-                "achieved": had_flops / n_launch / had_avg_s / 1e12, "peak": PEAK_MFMA["fp32"] / 1e12,
+    had_s = lk["hadamard"] * 1e-3
+    roof_had = {"kernel": "hadamard_block_kernel (v_mfma_f32_16x16x4f32), leaf level", "bound": "mfma",
+                "achieved": lw["hadamard_flops"] / had_s / 1e12, "peak": PEAK_MFMA["fp32"] / 1e12,
                 "unit": "TFLOP/s",
                 "traffic": measured_traffic("paper_2408_07436_amd/csrc/k_fft.hip",
                                             "hadamard_f32_uniform1M_p6_traffic.json"),
-                "algorithmic_bytes": round(had_bytes / n_launch),
-                "per_launch": f"{had_flops / n_launch / 1e9:.2f} GFLOP (8 flops x 64 pairs x F per "
-                              f"cluster pair, averaged over {n_launch} level launches), "
-                              f"avg {had_avg_s * 1e3:.4f} ms"}
+                "algorithmic_bytes": round(lw["hadamard_bytes"]),
+                "per_launch": f"{lw['hadamard_flops'] / 1e9:.2f} GFLOP (8 flops x 64 pairs x F per "
+                              f"cluster pair at level {w.depth}), avg {lk['hadamard']:.4f} ms"}
     roof_had["frac"] = roof_had["achieved"] / roof_had["peak"]
+    fwd_s, inv_s = lk["fft_forward"] * 1e-3, lk["fft_inverse"] * 1e-3
+    roof_fwd = {"kernel": "fft_forward_kernel<float, 6>, leaf level", "bound": "hbm",
+                "achieved": lw["fft_forward_bytes"] / fwd_s / 1e9, "peak": PEAK_HBM / 1e9,
+                "unit": "GB/s", "traffic": None,
+                "per_launch": f"{lw['fft_forward_bytes'] / 1e6:.1f} MB (FP64 densities in, FP32 "
+                              f"spectra out), avg {lk['fft_forward']:.4f} ms"}
+    roof_inv = {"kernel": "fft_inverse_kernel<float, 6>, leaf level", "bound": "hbm",
+                "achieved": lw["fft_inverse_bytes"] / inv_s / 1e9, "peak": PEAK_HBM / 1e9,
+                "unit": "GB/s", "traffic": None,
+                "per_launch": f"{lw['fft_inverse_bytes'] / 1e6:.1f} MB (FP32 products in, FP64 "
+                              f"check potentials out), avg {lk['fft_inverse']:.4f} ms"}
+    for r in (roof_fwd, roof_inv):
+        r["frac"] = r["achieved"] / r["peak"]
     leaf_s = tm["leaves"] * 1e-3
     # 11 flops per interaction: 3 differences, r^2 (1 mul + 2 fma), one fma
     # accumulate; the reciprocal square root is counted as one operation
     p2p_flops = 12.0 * interactions
-    roof_leaf = {"kernel": "leaf_eval_kernel<float> (L2P FP64 + P2P FP32)", "bound": "alu",
+    roof_leaf = {"kernel": "leaf_eval_kernel<float, float, 1> (L2P FP64 + P2P FP32)", "bound": "alu",
                  "achieved": p2p_flops / leaf_s / 1e12, "peak": PEAK_VALU_NOPK["fp32"] / 1e12,
-                 "unit": "TFLOP/s", "traffic": None,
+                 "unit": "TFLOP/s",
+                 "traffic": measured_traffic("paper_2408_07436_amd/csrc/k_leaf.hip",
+                                             "leaf_eval_f32_uniform1M_p6_traffic.json"),
                  "per_launch": f"{interactions:.3e} P2P interactions x 12 operations "
                                f"(11 flops + rsqrt), avg {tm['leaves']:.4f} ms"}
     roof_leaf["frac"] = roof_leaf["achieved"] / roof_leaf["peak"]
-    roofline = roof_had if dominant in ("hadamard", "fft_forward", "fft_inverse") else roof_leaf
-    for r in (roof_had, roof_leaf):
+    roofs = {"hadamard": roof_had, "fft_forward": roof_fwd, "fft_inverse": roof_inv, "leaf_eval": roof_leaf}
+    for r in roofs.values():
         for k in ("achieved", "peak", "frac"):
             r[k] = round(r[k], 4)
+    roofline = roofs[dominant]
 
     m2l_ms = tm["m2l"]
     line = {
@@ -389,7 +442,8 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in tm.items() if k != "m2l_levels"},
         "stage_ms_fp64": {k: round(v, 4) for k, v in ref["tm"].items() if k != "m2l_levels"},
         "roofline": roofline,
-        "roofline_other": roof_leaf if roofline is roof_had else roof_had,
+        "roofline_other": [r for k, r in roofs.items() if k != dominant],
+        "leaf_level_m2l_kernel_ms": {k: round(v, 4) for k, v in lk.items()},
         "paper_context": "FFT-M2L FP64, N=1e6, P=6, depth 5: T_M2L 813 ms on Apple M1 Pro "
                          "(8 cores); 240 ms on AMD 3790X at depth 4 (32 cores) - CPU context only",
         "setup_s": {"fp32": round(mix["setup_s"], 2), "fp64": round(ref["setup_s"], 2)},

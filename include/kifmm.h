@@ -181,17 +181,21 @@ kifmm_status kifmm_operator(const kifmm_handle* h, int32_t which, double* out, i
 kifmm_status kifmm_stage(kifmm_handle* h, int32_t stage, int32_t level, const void* in_dev,
                          void* out_dev, int32_t n_vec, void* hip_stream);
 
-/* Enable (1) or disable (0) timing of evaluate with HIP events recorded on
- * the evaluate stream between kernels.  A timed evaluate synchronises the
- * stream before it returns. */
+/* Enable (1) or disable (0) timing of evaluate and stage with HIP events
+ * recorded between kernels.  A timed call synchronises before it returns. */
 kifmm_status kifmm_set_timing(kifmm_handle* h, int32_t on);
-/* Milliseconds of the last timed evaluate (cap >= 5; more entries are
- * filled when cap allows): [0] upward (P2M + M2M), [1] M2L (all levels),
- * [2] rest of the downward pass (L2L + pseudo-inverses), [3] leaves
- * (L2P + P2P), [4] total, [5] M2L first kernel summed over levels (FFT:
- * forward transform; BLAS/dense: compression), [6] M2L main kernel (FFT:
- * Hadamard; BLAS/dense: per-transfer-vector products), [7] M2L last kernel
- * (FFT: inverse transform; BLAS: decompression), [8] number of M2L levels. */
+/* Milliseconds of the last timed evaluate or stage (cap >= 5; more entries
+ * are filled when cap allows): [0] upward (P2M + M2M), [1] M2L (all levels;
+ * FFT-M2L runs the levels concurrently and this is the wall time from the
+ * end of the upward pass to the last level's end), [2] rest of the downward
+ * pass (L2L + pseudo-inverses), [3] leaves (L2P + P2P), [4] total, [5] M2L
+ * first kernel summed over levels (FFT: forward transform; BLAS/dense:
+ * compression), [6] M2L main kernel (FFT: Hadamard; BLAS/dense:
+ * per-transfer-vector products), [7] M2L last kernel (FFT: inverse
+ * transform; BLAS: decompression), [8] number of M2L levels.  [5..7] are
+ * each kernel's own start-to-end times and overlap when levels run
+ * concurrently.  After a timed stage: [1] = [4] = the level's M2L, [5..7]
+ * its three kernels, [8] = 1, the rest 0. */
 kifmm_status kifmm_timings(const kifmm_handle* h, double* ms, int32_t cap);
 
 /* Work counts of one M2L level (>= 2), valid after set_points: [0] target

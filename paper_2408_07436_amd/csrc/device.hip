@@ -758,7 +758,22 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
 kifmm_status device_stage(kifmm_handle* h, int level, const void* in, void* out, int nvec,
                           hipStream_t s) {
   KIFMM_TRY(device_ready(h, nvec));
-  return m2l_level(h, level, (const double*)in, (double*)out, nvec, s, false);
+  DeviceState* d = h->dev;
+  const bool timed = h->timing;
+  KIFMM_TRY(m2l_level(h, level, (const double*)in, (double*)out, nvec, s, timed));
+  if (timed) {
+    // this level's kernel phases; the stream is synchronised first
+    hipEvent_t* mark = &d->lev_ev[4 * level];
+    KIFMM_HIP(hipEventSynchronize(mark[3]));
+    float ph[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < 3; ++k) KIFMM_HIP(hipEventElapsedTime(&ph[k], mark[k], mark[k + 1]));
+    for (double& t : h->timings) t = 0.0;
+    h->timings[1] = (double)ph[0] + ph[1] + ph[2];
+    h->timings[4] = h->timings[1];
+    for (int k = 0; k < 3; ++k) h->timings[5 + k] = ph[k];
+    h->timings[8] = 1;
+  }
+  return KIFMM_OK;
 }
 
 }  // namespace kifmm
