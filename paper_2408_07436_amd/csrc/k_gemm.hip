@@ -31,19 +31,31 @@ constexpr int kBN = 64;            // data columns per workgroup (16 per wave)
 constexpr int kBK = 16;
 constexpr int kALoads = kBK * kBM / 256;  // operator values per thread per K slice
 
-__device__ inline void col_split(int64_t col, int nvec, int64_t& b, int& v) {
+// n / f.d and n % f.d for n < 2^32
+__device__ inline uint32_t fdiv(uint32_t n, const FastDiv& f, uint32_t& r) {
+  uint32_t q = __umulhi(n, f.m);
+  r = n - q * f.d;
+  if (r >= f.d) {
+    ++q;
+    r -= f.d;
+  }
+  return q;
+}
+
+__device__ inline void col_split(int64_t col, int nvec, const FastDiv& fv, int64_t& b, int& v) {
   if (nvec == 1) {
     b = col;
     v = 0;
   } else {
-    b = (int64_t)((uint32_t)col / (uint32_t)nvec);
-    v = (int)(col - b * nvec);
+    uint32_t r;
+    b = (int64_t)fdiv((uint32_t)col, fv, r);
+    v = (int)r;
   }
 }
 
 // blockIdx.z selects the K range [kz0, kz1) of a split product; with
 // `partial` set the raw sums go to partial[z][col][m] (m < M) instead of C.
-__global__ __launch_bounds__(256) void gemm64_kernel(Gemm64 g, int kchunk, double* partial) {
+__global__ __launch_bounds__(256, 2) void gemm64_kernel(Gemm64 g, int kchunk, double* partial) {
   __shared__ double As[kBK][kBM + 2];  // operator, k-major
   __shared__ double Bs[kBK][kBN + 2];  // data columns, k-major
   const int tid = threadIdx.x;
@@ -65,7 +77,7 @@ __global__ __launch_bounds__(256) void gemm64_kernel(Gemm64 g, int kchunk, doubl
   const bool col_ok = mycol < ncols;
   int64_t cb_box = 0;
   int cb_v = 0;
-  if (col_ok) col_split(mycol, g.nvec, cb_box, cb_v);
+  if (col_ok) col_split(mycol, g.nvec, g.div_nvec, cb_box, cb_v);
   const int32_t* bmap_row = g.bmap ? g.bmap + cb_box * g.nsegk : nullptr;
   const double* bcol = g.B + (int64_t)cb_v * g.b_vec;
   const double* bdirect = g.B + cb_box * g.b_box + (int64_t)cb_v * g.b_vec;
@@ -90,8 +102,9 @@ __global__ __launch_bounds__(256) void gemm64_kernel(Gemm64 g, int kchunk, doubl
         } else {
           int seg = 0, kk2 = k;
           if (g.nsegk != 1) {
-            seg = k / g.ks;
-            kk2 = k - seg * g.ks;
+            uint32_t r;
+            seg = (int)fdiv((uint32_t)k, g.div_ks, r);
+            kk2 = (int)r;
           }
           const int64_t bb = bmap_row ? (int64_t)bmap_row[seg] : cb_box;
           if (bb >= 0) val = bcol[bb * g.b_box + kk2];
@@ -138,22 +151,30 @@ __global__ __launch_bounds__(256) void gemm64_kernel(Gemm64 g, int kchunk, doubl
     }
     int64_t b;
     int v;
-    col_split(col, g.nvec, b, v);
+    col_split(col, g.nvec, g.div_nvec, b, v);
+    // destinations of the column's kMT entries first, then (accumulating)
+    // all their old values in flight together, then the stores
+    double* dst[kMT];
 #pragma unroll
     for (int j = 0; j < kMT; ++j) {
       const int m = m0 + 16 * j + l16;
+      dst[j] = nullptr;
       if (m >= g.M) continue;
       int seg = 0, mm = m;
       if (g.nsegm != 1) {
-        seg = m / g.ms;
-        mm = m - seg * g.ms;
+        uint32_t r;
+        seg = (int)fdiv((uint32_t)m, g.div_ms, r);
+        mm = (int)r;
       }
       const int64_t cb = g.cmap ? (int64_t)g.cmap[b * g.nsegm + seg] : b;
-      if (cb < 0) continue;
-      double* dst = &g.C[cb * g.c_box + (int64_t)v * g.c_vec + mm];
-      const double val = g.alpha * acc[j][e];
-      *dst = g.accumulate ? *dst + val : val;
+      if (cb >= 0) dst[j] = &g.C[cb * g.c_box + (int64_t)v * g.c_vec + mm];
     }
+    double old[kMT];
+#pragma unroll
+    for (int j = 0; j < kMT; ++j) old[j] = (g.accumulate && dst[j]) ? *dst[j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kMT; ++j)
+      if (dst[j]) *dst[j] = old[j] + g.alpha * acc[j][e];
   }
 }
 
@@ -161,20 +182,22 @@ __global__ __launch_bounds__(256) void gemm64_kernel(Gemm64 g, int kchunk, doubl
 __global__ __launch_bounds__(256) void gemm64_reduce_kernel(Gemm64 g, int nsplit,
                                                             const double* __restrict__ partial) {
   const int64_t ncols = g.nbox * g.nvec;
-  const int64_t total = ncols * g.M;
+  const int64_t total = ncols * g.M;  // < 2^32 (checked by the launcher)
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= total) return;
-  const int64_t col = i / g.M;
-  const int m = (int)(i - col * g.M);
+  uint32_t mr;
+  const int64_t col = fdiv((uint32_t)i, g.div_M, mr);
+  const int m = (int)mr;
   double sum = 0.0;
   for (int z = 0; z < nsplit; ++z) sum += partial[(int64_t)z * total + i];
   int64_t b;
   int v;
-  col_split(col, g.nvec, b, v);
+  col_split(col, g.nvec, g.div_nvec, b, v);
   int seg = 0, mm = m;
   if (g.nsegm != 1) {
-    seg = m / g.ms;
-    mm = m - seg * g.ms;
+    uint32_t r;
+    seg = (int)fdiv((uint32_t)m, g.div_ms, r);
+    mm = (int)r;
   }
   const int64_t cb = g.cmap ? (int64_t)g.cmap[b * g.nsegm + seg] : b;
   if (cb < 0) return;
@@ -183,18 +206,31 @@ __global__ __launch_bounds__(256) void gemm64_reduce_kernel(Gemm64 g, int nsplit
   *dst = g.accumulate ? *dst + val : val;
 }
 
+FastDiv make_div(int d) {
+  FastDiv f;
+  f.d = (uint32_t)d;
+  f.m = d == 1 ? 0xffffffffu : (uint32_t)((uint64_t(1) << 32) / (uint64_t)d);
+  return f;
+}
+
 }  // namespace
 
-hipError_t launch_gemm64(const Gemm64& g, hipStream_t stream) {
+hipError_t launch_gemm64(const Gemm64& g0, hipStream_t stream) {
+  Gemm64 g = g0;
   const int64_t ncols = g.nbox * g.nvec;
   if (ncols == 0 || g.M == 0) return hipSuccess;
-  if (ncols >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  if (ncols >= ((int64_t)1 << 31) || g.ks < 1 || g.ms < 1 || g.nvec < 1) return hipErrorInvalidValue;
+  g.div_ks = make_div(g.ks);
+  g.div_ms = make_div(g.ms);
+  g.div_nvec = make_div(g.nvec);
+  g.div_M = make_div(g.M);
   const int64_t gx = (ncols + kBN - 1) / kBN, gy = (g.M + kBM - 1) / kBM;
   // split K when the grid cannot fill the chip, within the workspace
   const int64_t slices = (g.K + kBK - 1) / kBK;
   int64_t split = 1;
   const int64_t target = 512;
-  if (g.work && gx * gy < target && slices >= 4) {
+  // (the reduction indexes (column, row) pairs in 32 bits)
+  if (g.work && gx * gy < target && slices >= 4 && ncols * g.M < ((int64_t)1 << 32)) {
     split = std::min<int64_t>((target + gx * gy - 1) / (gx * gy), slices / 2);
     const int64_t cap = g.work_elems / (ncols * g.M);
     split = std::max<int64_t>(1, std::min(split, cap));

@@ -37,12 +37,18 @@ hipError_t launch_leaf_eval(const double* tgt_xyz, const double* src_xyz, const 
 // cb = cmap ? cmap[b * nsegm + m / ms] : b  (cb < 0 is skipped).
 // Small grids split K over workgroups when a workspace is given: partials
 // of work_elems doubles at most, summed in a fixed order.
+// Division by a fixed divisor d >= 1 of numerators below 2^32: multiply-high
+// by floor(2^32 / d) and one correction step (set by the launcher).
+struct FastDiv {
+  uint32_t d = 1, m = 0xffffffffu;
+};
 struct Gemm64 {
   const double* A; int M; int K; int lda; double alpha;
   const double* B; int ks; int nsegk; const int32_t* bmap; int64_t b_box; int b_vec;
   double* C; int ms; int nsegm; const int32_t* cmap; int64_t c_box; int c_vec;
   int64_t nbox; int nvec; int accumulate;
   double* work = nullptr; int64_t work_elems = 0;
+  FastDiv div_ks, div_ms, div_nvec, div_M;  // filled by launch_gemm64
 };
 hipError_t launch_gemm64(const Gemm64& g, hipStream_t stream);
 
