@@ -58,6 +58,9 @@ struct DeviceState {
   int16_t* surf_lat = nullptr;
   double *up_V = nullptr, *up_Ut = nullptr, *down_V = nullptr, *down_Ut = nullptr;
   double *m2m = nullptr, *l2l = nullptr;
+  // composite operators of the reduced-precision modes (one GEMM per
+  // pseudo-inverse, pseudo-inverses folded into M2M / L2L)
+  double *up_P = nullptr, *down_P = nullptr, *m2m_c = nullptr, *l2l_c = nullptr;
   void* khat = nullptr;
   void* twiddle = nullptr;
   double* Ublas = nullptr;   // ns x k
@@ -383,6 +386,12 @@ kifmm_status upload_all(kifmm_handle* h) {
   KIFMM_TRY(upload(d, &d->down_Ut, op.down_Ut.data(), op.down_Ut.size()));
   KIFMM_TRY(upload(d, &d->m2m, op.m2m.data(), op.m2m.size()));
   KIFMM_TRY(upload(d, &d->l2l, op.l2l.data(), op.l2l.size()));
+  if (!d->fp64) {
+    KIFMM_TRY(upload(d, &d->up_P, op.up_P.data(), op.up_P.size()));
+    KIFMM_TRY(upload(d, &d->down_P, op.down_P.data(), op.down_P.size()));
+    KIFMM_TRY(upload(d, &d->m2m_c, op.m2m_c.data(), op.m2m_c.size()));
+    KIFMM_TRY(upload(d, &d->l2l_c, op.l2l_c.data(), op.l2l_c.size()));
+  }
 
   d->lv.resize(depth + 1);
   for (int l = 0; l <= depth; ++l) {
@@ -673,9 +682,25 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
   const DevLevel& leaf = d->lv[depth];
   KIFMM_LAUNCH(launch_p2m(d->src_xyz, d->qs, d->fp64, t.n_src, d->src_start, d->src_end,
                           d->leaf_centers, leaf.n, d->surf, op.ao * 0.5 * leaf.w, ns, nvec, d->phi, s));
-  KIFMM_TRY(pinv_apply(h, d->up_V, d->up_Ut, op.r_up, leaf.w, d->phi, d->mult[depth], leaf.n, nvec, s));
+  // FP64: two-factor pseudo-inverses after each M2M (Section 2.1.1); the
+  // reduced-precision modes apply the composite operators (M2M with the
+  // parent's pseudo-inverse folded in: the width scalings cancel)
+  const bool composite = !d->fp64;
+  if (composite) {
+    Gemm64 g{d->up_P, ns, ns, ns, leaf.w, d->phi, ns, 1, nullptr, (int64_t)nvec * ns, ns,
+             d->mult[depth], ns, 1, nullptr, (int64_t)nvec * ns, ns, leaf.n, nvec, 0};
+    KIFMM_LAUNCH(gemm(d, g, s));
+  } else {
+    KIFMM_TRY(pinv_apply(h, d->up_V, d->up_Ut, op.r_up, leaf.w, d->phi, d->mult[depth], leaf.n, nvec, s));
+  }
   for (int l = depth - 1; l >= 2; --l) {
     const DevLevel& D = d->lv[l];
+    if (composite) {
+      Gemm64 g{d->m2m_c, ns, 8 * ns, 8 * ns, 1.0, d->mult[l + 1], ns, 8, D.child,
+               (int64_t)nvec * ns, ns, d->mult[l], ns, 1, nullptr, (int64_t)nvec * ns, ns, D.n, nvec, 0};
+      KIFMM_LAUNCH(gemm(d, g, s));
+      continue;
+    }
     Gemm64 g{d->m2m, ns, 8 * ns, 8 * ns, 1.0 / D.w, d->mult[l + 1], ns, 8, D.child,
              (int64_t)nvec * ns, ns, d->phi, ns, 1, nullptr, (int64_t)nvec * ns, ns, D.n, nvec, 0};
     KIFMM_LAUNCH(gemm(d, g, s));
@@ -706,6 +731,20 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
     const DevLevel& D = d->lv[l];
     double* chk = fft ? D.chk : d->phi;
     if (!fork) KIFMM_TRY(m2l_level(h, l, d->mult[l], chk, nvec, s, timed));
+    if (composite) {
+      // local = w down_P chk + (w / w_parent) [down_P L_o] local_parent
+      Gemm64 g1{d->down_P, ns, ns, ns, D.w, chk, ns, 1, nullptr, (int64_t)nvec * ns, ns,
+                d->local[l], ns, 1, nullptr, (int64_t)nvec * ns, ns, D.n, nvec, 0};
+      KIFMM_LAUNCH(gemm(d, g1, s));
+      if (l >= 3) {
+        const DevLevel& P = d->lv[l - 1];
+        Gemm64 g2{d->l2l_c, 8 * ns, ns, ns, D.w / P.w, d->local[l - 1], ns, 1, nullptr,
+                  (int64_t)nvec * ns, ns, d->local[l], ns, 8, P.child, (int64_t)nvec * ns, ns,
+                  P.n, nvec, 1};
+        KIFMM_LAUNCH(gemm(d, g2, s));
+      }
+      continue;
+    }
     if (l >= 3) {
       const DevLevel& P = d->lv[l - 1];
       Gemm64 g{d->l2l, 8 * ns, ns, ns, 1.0 / P.w, d->local[l - 1], ns, 1, nullptr,

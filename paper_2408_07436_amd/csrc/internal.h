@@ -90,6 +90,10 @@ struct Operators {
   std::vector<double> m2m;
   // L2L: [8 ns] x [ns] = [L_0; ..; L_7] for a parent of width 1
   std::vector<double> l2l;
+  // composite forms for the reduced-precision modes: up_P = up_V up_Ut,
+  // down_P = down_V down_Ut (ns x ns), m2m_c = up_P m2m (ns x 8 ns),
+  // l2l_c = [down_P L_0; ..; down_P L_7] (8 ns x ns)
+  std::vector<double> up_P, down_P, m2m_c, l2l_c;
   // FFT: kernel spectra of the unit box, [316][F] complex (re, im)
   std::vector<double> spectra;
   // BLAS / dense M2L of the unit box

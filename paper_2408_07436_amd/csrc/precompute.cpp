@@ -140,6 +140,29 @@ kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg) {
     }
   }
 
+  // composite operators (products accumulated in extended precision)
+  {
+    auto matmul = [](const double* A, const double* B, int m, int k, int n, int lda, int ldb,
+                     double* C, int ldc) {
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < n; ++j) {
+          long double acc = 0.0L;
+          for (int t = 0; t < k; ++t) acc += (long double)A[(size_t)i * lda + t] * B[(size_t)t * ldb + j];
+          C[(size_t)i * ldc + j] = (double)acc;
+        }
+    };
+    op.up_P.assign((size_t)ns * ns, 0.0);
+    op.down_P.assign((size_t)ns * ns, 0.0);
+    matmul(op.up_V.data(), op.up_Ut.data(), ns, op.r_up, ns, op.r_up, ns, op.up_P.data(), ns);
+    matmul(op.down_V.data(), op.down_Ut.data(), ns, op.r_down, ns, op.r_down, ns, op.down_P.data(), ns);
+    op.m2m_c.assign((size_t)ns * 8 * ns, 0.0);
+    matmul(op.up_P.data(), op.m2m.data(), ns, ns, 8 * ns, ns, 8 * ns, op.m2m_c.data(), 8 * ns);
+    op.l2l_c.assign((size_t)8 * ns * ns, 0.0);
+    for (int o = 0; o < 8; ++o)
+      matmul(op.down_P.data(), &op.l2l[(size_t)o * ns * ns], ns, ns, ns, ns, ns,
+             &op.l2l_c[(size_t)o * ns * ns], ns);
+  }
+
   if (cfg.m2l == KIFMM_M2L_FFT) {
     // kernel sequences G[m] = K(c_tau - c_sigma + h m) on the (2p-1)^3 grid
     const int n = op.n;
