@@ -357,9 +357,10 @@ def main():
         f, out, ms_step, tm, setup_s = run_precision(K, torch, w, prec, args.steps, args.warmup)
         err = direct_error(torch, w, out)
         res[prec] = dict(f=f, out=out, ms_step=ms_step, tm=tm, setup_s=setup_s, err=err)
-        log(f"  {prec}: step {ms_step:.3f} ms, m2l {tm['m2l']:.3f} ms "
-            f"(fwd {tm['m2l_first']:.3f} had {tm['m2l_main']:.3f} inv {tm['m2l_last']:.3f}), "
-            f"leaves {tm['leaves']:.3f} ms, err vs direct {err:.2e}")
+        log(f"  {prec}: step {ms_step:.3f} ms; phases: upward {tm['upward']:.3f}, m2l {tm['m2l']:.3f} "
+            f"(kernel sums fwd {tm['m2l_first']:.3f} had {tm['m2l_main']:.3f} inv {tm['m2l_last']:.3f}), "
+            f"downward {tm['downward']:.3f}, near field {tm['near_field']:.3f}, far field "
+            f"{tm['far_field']:.3f} ms; err vs direct {err:.2e}")
     mix, ref = res["fp32"], res["fp64"]
     rel_mix_vs_fp64 = float(torch.linalg.norm(mix["out"].double() - ref["out"]) / torch.linalg.norm(ref["out"]))
 
@@ -372,7 +373,7 @@ def main():
     log(f"  leaf-level M2L kernels (level {w.depth}, alone): fwd {lk['fft_forward']:.4f} "
         f"had {lk['hadamard']:.4f} inv {lk['fft_inverse']:.4f} ms")
     interactions = p2p_work(w.points, w.depth)
-    kernels = dict(lk, leaf_eval=tm["leaves"])
+    kernels = dict(lk, near_field=tm["near_field"])
     dominant = max(kernels, key=kernels.get)
     had_s = lk["hadamard"] * 1e-3
     roof_had = {"kernel": "hadamard_block_kernel (v_mfma_f32_16x16x4f32), leaf level", "bound": "mfma",
@@ -397,19 +398,19 @@ def main():
                               f"check potentials out), avg {lk['fft_inverse']:.4f} ms"}
     for r in (roof_fwd, roof_inv):
         r["frac"] = r["achieved"] / r["peak"]
-    leaf_s = tm["leaves"] * 1e-3
+    near_s = tm["near_field"] * 1e-3
     # 11 flops per interaction: 3 differences, r^2 (1 mul + 2 fma), one fma
     # accumulate; the reciprocal square root is counted as one operation
     p2p_flops = 12.0 * interactions
-    roof_leaf = {"kernel": "leaf_eval_kernel<float, float, 1> (L2P FP64 + P2P FP32)", "bound": "alu",
-                 "achieved": p2p_flops / leaf_s / 1e12, "peak": PEAK_VALU_NOPK["fp32"] / 1e12,
+    roof_leaf = {"kernel": "leaf_eval_kernel<float, float, 1, 1> (near field, P2P FP32)", "bound": "alu",
+                 "achieved": p2p_flops / near_s / 1e12, "peak": PEAK_VALU_NOPK["fp32"] / 1e12,
                  "unit": "TFLOP/s",
                  "traffic": measured_traffic("paper_2408_07436_amd/csrc/k_leaf.hip",
                                              "leaf_eval_f32_uniform1M_p6_traffic.json"),
                  "per_launch": f"{interactions:.3e} P2P interactions x 12 operations "
-                               f"(11 flops + rsqrt), avg {tm['leaves']:.4f} ms"}
+                               f"(11 flops + rsqrt), avg {tm['near_field']:.4f} ms"}
     roof_leaf["frac"] = roof_leaf["achieved"] / roof_leaf["peak"]
-    roofs = {"hadamard": roof_had, "fft_forward": roof_fwd, "fft_inverse": roof_inv, "leaf_eval": roof_leaf}
+    roofs = {"hadamard": roof_had, "fft_forward": roof_fwd, "fft_inverse": roof_inv, "near_field": roof_leaf}
     for r in roofs.values():
         for k in ("achieved", "peak", "frac"):
             r[k] = round(r[k], 4)

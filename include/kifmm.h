@@ -185,17 +185,21 @@ kifmm_status kifmm_stage(kifmm_handle* h, int32_t stage, int32_t level, const vo
  * recorded between kernels.  A timed call synchronises before it returns. */
 kifmm_status kifmm_set_timing(kifmm_handle* h, int32_t on);
 /* Milliseconds of the last timed evaluate or stage (cap >= 5; more entries
- * are filled when cap allows): [0] upward (P2M + M2M), [1] M2L (all levels;
- * FFT-M2L runs the levels concurrently and this is the wall time from the
- * end of the upward pass to the last level's end), [2] rest of the downward
- * pass (L2L + pseudo-inverses), [3] leaves (L2P + P2P), [4] total, [5] M2L
- * first kernel summed over levels (FFT: forward transform; BLAS/dense:
- * compression), [6] M2L main kernel (FFT: Hadamard; BLAS/dense:
+ * are filled when cap allows, up to 11).  An untimed FFT-M2L evaluate runs
+ * as a dependency graph over several streams (near field beside the FMM
+ * passes, coarse levels beside the leaf level); a timed one runs the
+ * phases one after another (the M2L levels still concurrently) so that each
+ * phase is measured on its own: [0] upward (P2M + M2M), [1] M2L (all
+ * levels; FFT: wall time of the concurrent levels), [2] rest of the
+ * downward pass (L2L + pseudo-inverses), [3] leaves (L2P + P2P), [4] total,
+ * [5] M2L first kernel summed over levels (FFT: forward transform;
+ * BLAS/dense: compression), [6] M2L main kernel (FFT: Hadamard; BLAS/dense:
  * per-transfer-vector products), [7] M2L last kernel (FFT: inverse
- * transform; BLAS: decompression), [8] number of M2L levels.  [5..7] are
- * each kernel's own start-to-end times and overlap when levels run
- * concurrently.  After a timed stage: [1] = [4] = the level's M2L, [5..7]
- * its three kernels, [8] = 1, the rest 0. */
+ * transform; BLAS: decompression), [8] number of M2L levels, [9] near-field
+ * pass (P2P) and [10] far-field pass (L2P) of FFT evaluates (0 otherwise).
+ * [5..7] are each kernel's own start-to-end times and overlap when levels
+ * run concurrently.  After a timed stage: [1] = [4] = the level's M2L,
+ * [5..7] its three kernels, [8] = 1, the rest 0. */
 kifmm_status kifmm_timings(const kifmm_handle* h, double* ms, int32_t cap);
 
 /* Work counts of one M2L level (>= 2), valid after set_points: [0] target

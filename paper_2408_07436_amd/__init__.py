@@ -238,10 +238,11 @@ class KiFMM:
         _check(lib().kifmm_set_timing(self._h, 1 if on else 0))
 
     def timings(self) -> dict:
-        ms = np.zeros(9, dtype=np.float64)
-        _check(lib().kifmm_timings(self._h, _ptr(ms, ctypes.c_double), 9))
+        ms = np.zeros(11, dtype=np.float64)
+        _check(lib().kifmm_timings(self._h, _ptr(ms, ctypes.c_double), 11))
         return dict(upward=ms[0], m2l=ms[1], downward=ms[2], leaves=ms[3], total=ms[4],
-                    m2l_first=ms[5], m2l_main=ms[6], m2l_last=ms[7], m2l_levels=int(ms[8]))
+                    m2l_first=ms[5], m2l_main=ms[6], m2l_last=ms[7], m2l_levels=int(ms[8]),
+                    near_field=ms[9], far_field=ms[10])
 
     def m2l_counts(self, level: int) -> dict:
         c = np.zeros(4, dtype=np.int64)

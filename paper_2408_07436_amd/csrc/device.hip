@@ -84,11 +84,15 @@ struct DeviceState {
   double* tmp2 = nullptr;
   double* gemm_ws = nullptr;  // split-K partials
   int64_t gemm_ws_elems = 0;
-  // FFT-M2L levels below the leaves run on side streams forked from the
-  // evaluate stream after the upward pass and joined before the downward pass
-  std::vector<hipStream_t> side;   // [depth + 1], levels 2 .. depth - 1
-  hipEvent_t fork_ev = nullptr;
-  std::vector<hipEvent_t> join_ev;  // [depth + 1]
+  // FFT-M2L evaluates run as a dependency graph: the leaf level's M2L on
+  // the evaluate stream, the coarse levels' M2M and downward work on a
+  // coarse stream, and each coarse level's M2L on a side stream
+  hipStream_t coarse = nullptr;
+  std::vector<hipStream_t> side;    // [depth + 1]: M2L of coarse level l
+  hipEvent_t fork_ev = nullptr;     // leaf multipoles ready
+  hipEvent_t down_ev = nullptr;     // coarse locals ready
+  std::vector<hipEvent_t> up_ev;    // [depth + 1] multipoles of coarse level l ready
+  std::vector<hipEvent_t> join_ev;  // [depth + 1] M2L of coarse level l done
   std::vector<void*> work_allocs;
   hipEvent_t ev[6] = {};
   std::vector<hipEvent_t> lev_ev;  // [level][4] marks around the M2L kernels
@@ -475,13 +479,17 @@ kifmm_status upload_all(kifmm_handle* h) {
   for (auto& e : d->lev_ev) KIFMM_HIP(hipEventCreate(&e));
   d->events = true;
   if (h->cfg.m2l == KIFMM_M2L_FFT) {
-    KIFMM_HIP(hipEventCreateWithFlags(&d->fork_ev, hipEventDisableTiming));
+    KIFMM_HIP(hipStreamCreateWithFlags(&d->coarse, hipStreamNonBlocking));
     d->side.assign(depth + 1, nullptr);
+    d->up_ev.assign(depth + 1, nullptr);
     d->join_ev.assign(depth + 1, nullptr);
     for (int l = 2; l < depth; ++l) {
       KIFMM_HIP(hipStreamCreateWithFlags(&d->side[l], hipStreamNonBlocking));
+      KIFMM_HIP(hipEventCreateWithFlags(&d->up_ev[l], hipEventDisableTiming));
       KIFMM_HIP(hipEventCreateWithFlags(&d->join_ev[l], hipEventDisableTiming));
     }
+    KIFMM_HIP(hipEventCreateWithFlags(&d->fork_ev, hipEventDisableTiming));
+    KIFMM_HIP(hipEventCreateWithFlags(&d->down_ev, hipEventDisableTiming));
   }
   return KIFMM_OK;
 }
@@ -640,10 +648,14 @@ void destroy_device(DeviceState* d) {
   for (auto& e : d->lev_ev)
     if (e) hipEventDestroy(e);
   if (d->fork_ev) hipEventDestroy(d->fork_ev);
+  if (d->down_ev) hipEventDestroy(d->down_ev);
+  for (auto& e : d->up_ev)
+    if (e) hipEventDestroy(e);
   for (auto& e : d->join_ev)
     if (e) hipEventDestroy(e);
   for (auto& st : d->side)
     if (st) hipStreamDestroy(st);
+  if (d->coarse) hipStreamDestroy(d->coarse);
   for (void* p : d->work_allocs) hipFree(p);
   for (void* p : d->allocs) hipFree(p);
   delete d;
@@ -677,11 +689,32 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
   const bool timed = h->timing;
   if (timed) KIFMM_HIP(hipEventRecord(d->ev[0], s));
 
+  const bool fft = h->cfg.m2l == KIFMM_M2L_FFT;
+  // Schedules: `graph` (FFT, untimed) runs the FMM passes as a dependency
+  // graph over several streams; `phased` (FFT, timed) runs the phases one
+  // after another with the M2L levels concurrent and the leaf work as two
+  // kernels (near field, then far field), so each phase and kernel is timed
+  // on its own; `serial` (other M2L forms, and under stream capture, where
+  // the multi-stream graph is not recorded) runs everything back to back on
+  // s.  graph and serial use the fused leaf kernel.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  KIFMM_HIP(hipStreamIsCapturing(s, &cap));
+  const bool fork = fft && cap == hipStreamCaptureStatusNone;
+  const bool graph = fork && !timed, phased = fork && timed;
+  const DevLevel& leaf = d->lv[depth];
+  const double ar_leaf = op.ao * 0.5 * leaf.w;
+  auto leaf_pass = [&](int mode, hipStream_t st) -> kifmm_status {
+    KIFMM_LAUNCH(launch_leaf_eval(d->tgt_xyz, d->src_xyz, d->src_xyz_f, d->qs, d->fp64, t.n_src,
+                                  d->tgt_start, d->tgt_end, d->src_start, d->src_end, d->near_offs,
+                                  d->near_src, d->leaf_centers, leaf.n, d->surf, ar_leaf, ns,
+                                  d->local[depth], d->tgt_perm, phi, ldphi, nvec, mode, st));
+    return KIFMM_OK;
+  };
+
   KIFMM_LAUNCH(launch_gather(q, ldq, d->src_perm, t.n_src, nvec, d->fp64, d->qs, s));
   // upward pass
-  const DevLevel& leaf = d->lv[depth];
   KIFMM_LAUNCH(launch_p2m(d->src_xyz, d->qs, d->fp64, t.n_src, d->src_start, d->src_end,
-                          d->leaf_centers, leaf.n, d->surf, op.ao * 0.5 * leaf.w, ns, nvec, d->phi, s));
+                          d->leaf_centers, leaf.n, d->surf, ar_leaf, ns, nvec, d->phi, s));
   // FP64: two-factor pseudo-inverses after each M2M (Section 2.1.1); the
   // reduced-precision modes apply the composite operators (M2M with the
   // parent's pseudo-inverse folded in: the width scalings cancel)
@@ -693,30 +726,78 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
   } else {
     KIFMM_TRY(pinv_apply(h, d->up_V, d->up_Ut, op.r_up, leaf.w, d->phi, d->mult[depth], leaf.n, nvec, s));
   }
-  for (int l = depth - 1; l >= 2; --l) {
+  // M2M into level l from level l + 1 (FP64: then the two-factor pinv)
+  auto m2m_level = [&](int l, hipStream_t st) -> kifmm_status {
     const DevLevel& D = d->lv[l];
     if (composite) {
       Gemm64 g{d->m2m_c, ns, 8 * ns, 8 * ns, 1.0, d->mult[l + 1], ns, 8, D.child,
                (int64_t)nvec * ns, ns, d->mult[l], ns, 1, nullptr, (int64_t)nvec * ns, ns, D.n, nvec, 0};
-      KIFMM_LAUNCH(gemm(d, g, s));
-      continue;
+      KIFMM_LAUNCH(gemm(d, g, st));
+      return KIFMM_OK;
     }
     Gemm64 g{d->m2m, ns, 8 * ns, 8 * ns, 1.0 / D.w, d->mult[l + 1], ns, 8, D.child,
              (int64_t)nvec * ns, ns, d->phi, ns, 1, nullptr, (int64_t)nvec * ns, ns, D.n, nvec, 0};
-    KIFMM_LAUNCH(gemm(d, g, s));
-    KIFMM_TRY(pinv_apply(h, d->up_V, d->up_Ut, op.r_up, D.w, d->phi, d->mult[l], D.n, nvec, s));
+    KIFMM_LAUNCH(gemm(d, g, st));
+    return pinv_apply(h, d->up_V, d->up_Ut, op.r_up, D.w, d->phi, d->mult[l], D.n, nvec, st);
+  };
+  // locals of level l from its M2L check potentials chk and the parent's
+  // locals: L2L (l >= 3) and the down pseudo-inverse
+  auto down_level = [&](int l, double* chk, hipStream_t st) -> kifmm_status {
+    const DevLevel& D = d->lv[l];
+    if (composite) {
+      // local = w down_P chk + (w / w_parent) [down_P L_o] local_parent
+      Gemm64 g1{d->down_P, ns, ns, ns, D.w, chk, ns, 1, nullptr, (int64_t)nvec * ns, ns,
+                d->local[l], ns, 1, nullptr, (int64_t)nvec * ns, ns, D.n, nvec, 0};
+      KIFMM_LAUNCH(gemm(d, g1, st));
+      if (l >= 3) {
+        const DevLevel& P = d->lv[l - 1];
+        Gemm64 g2{d->l2l_c, 8 * ns, ns, ns, D.w / P.w, d->local[l - 1], ns, 1, nullptr,
+                  (int64_t)nvec * ns, ns, d->local[l], ns, 8, P.child, (int64_t)nvec * ns, ns,
+                  P.n, nvec, 1};
+        KIFMM_LAUNCH(gemm(d, g2, st));
+      }
+      return KIFMM_OK;
+    }
+    if (l >= 3) {
+      const DevLevel& P = d->lv[l - 1];
+      Gemm64 g{d->l2l, 8 * ns, ns, ns, 1.0 / P.w, d->local[l - 1], ns, 1, nullptr,
+               (int64_t)nvec * ns, ns, chk, ns, 8, P.child, (int64_t)nvec * ns, ns, P.n, nvec, 1};
+      KIFMM_LAUNCH(gemm(d, g, st));
+    }
+    return pinv_apply(h, d->down_V, d->down_Ut, op.r_down, D.w, chk, d->local[l], D.n, nvec, st);
+  };
+
+  if (graph) {
+    // Each level's M2L needs only that level's multipoles.  The leaf level's
+    // M2L (the critical path) starts on s as soon as the leaf multipoles
+    // exist; the coarse stream runs the M2M chain, each coarse level's M2L
+    // runs on its side stream once its multipoles exist, and the coarse
+    // stream then walks the coarse downward pass as their M2L complete; s
+    // finishes the leaf level's downward step after the coarse locals.
+    if (timed) KIFMM_HIP(hipEventRecord(d->ev[1], s));
+    KIFMM_HIP(hipEventRecord(d->fork_ev, s));
+    KIFMM_TRY(m2l_level(h, depth, d->mult[depth], d->lv[depth].chk, nvec, s, timed));
+    KIFMM_HIP(hipStreamWaitEvent(d->coarse, d->fork_ev, 0));
+    for (int l = depth - 1; l >= 2; --l) {
+      KIFMM_TRY(m2m_level(l, d->coarse));
+      KIFMM_HIP(hipEventRecord(d->up_ev[l], d->coarse));
+      KIFMM_HIP(hipStreamWaitEvent(d->side[l], d->up_ev[l], 0));
+      KIFMM_TRY(m2l_level(h, l, d->mult[l], d->lv[l].chk, nvec, d->side[l], timed));
+      KIFMM_HIP(hipEventRecord(d->join_ev[l], d->side[l]));
+    }
+    for (int l = 2; l < depth; ++l) {
+      KIFMM_HIP(hipStreamWaitEvent(d->coarse, d->join_ev[l], 0));
+      KIFMM_TRY(down_level(l, d->lv[l].chk, d->coarse));
+    }
+    KIFMM_HIP(hipEventRecord(d->down_ev, d->coarse));
+    KIFMM_HIP(hipStreamWaitEvent(s, d->down_ev, 0));
+    KIFMM_TRY(down_level(depth, d->lv[depth].chk, s));
+    return leaf_pass(0, s);
   }
+  for (int l = depth - 1; l >= 2; --l) KIFMM_TRY(m2m_level(l, s));
   if (timed) KIFMM_HIP(hipEventRecord(d->ev[1], s));
-  // downward pass
-  const bool fft = h->cfg.m2l == KIFMM_M2L_FFT;
-  // under stream capture (batches) the levels run back to back on s: the
-  // side-stream fork is not recorded into graphs
-  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-  KIFMM_HIP(hipStreamIsCapturing(s, &cap));
-  const bool fork = fft && cap == hipStreamCaptureStatusNone;
-  if (fork) {
-    // M2L of every level needs only the upward pass: the levels below the
-    // leaves run on side streams while the leaf level runs on s
+  if (phased) {
+    // M2L of all levels, concurrently: the coarse levels on side streams
     KIFMM_HIP(hipEventRecord(d->fork_ev, s));
     for (int l = 2; l < depth; ++l) {
       KIFMM_HIP(hipStreamWaitEvent(d->side[l], d->fork_ev, 0));
@@ -725,39 +806,23 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
     }
     KIFMM_TRY(m2l_level(h, depth, d->mult[depth], d->lv[depth].chk, nvec, s, timed));
     for (int l = 2; l < depth; ++l) KIFMM_HIP(hipStreamWaitEvent(s, d->join_ev[l], 0));
-    if (timed) KIFMM_HIP(hipEventRecord(d->ev[4], s));
-  }
-  for (int l = 2; l <= depth; ++l) {
-    const DevLevel& D = d->lv[l];
-    double* chk = fft ? D.chk : d->phi;
-    if (!fork) KIFMM_TRY(m2l_level(h, l, d->mult[l], chk, nvec, s, timed));
-    if (composite) {
-      // local = w down_P chk + (w / w_parent) [down_P L_o] local_parent
-      Gemm64 g1{d->down_P, ns, ns, ns, D.w, chk, ns, 1, nullptr, (int64_t)nvec * ns, ns,
-                d->local[l], ns, 1, nullptr, (int64_t)nvec * ns, ns, D.n, nvec, 0};
-      KIFMM_LAUNCH(gemm(d, g1, s));
-      if (l >= 3) {
-        const DevLevel& P = d->lv[l - 1];
-        Gemm64 g2{d->l2l_c, 8 * ns, ns, ns, D.w / P.w, d->local[l - 1], ns, 1, nullptr,
-                  (int64_t)nvec * ns, ns, d->local[l], ns, 8, P.child, (int64_t)nvec * ns, ns,
-                  P.n, nvec, 1};
-        KIFMM_LAUNCH(gemm(d, g2, s));
-      }
-      continue;
+    KIFMM_HIP(hipEventRecord(d->ev[4], s));
+    for (int l = 2; l <= depth; ++l) KIFMM_TRY(down_level(l, d->lv[l].chk, s));
+  } else {
+    for (int l = 2; l <= depth; ++l) {
+      double* chk = fft ? d->lv[l].chk : d->phi;
+      KIFMM_TRY(m2l_level(h, l, d->mult[l], chk, nvec, s, timed));
+      KIFMM_TRY(down_level(l, chk, s));
     }
-    if (l >= 3) {
-      const DevLevel& P = d->lv[l - 1];
-      Gemm64 g{d->l2l, 8 * ns, ns, ns, 1.0 / P.w, d->local[l - 1], ns, 1, nullptr,
-               (int64_t)nvec * ns, ns, chk, ns, 8, P.child, (int64_t)nvec * ns, ns, P.n, nvec, 1};
-      KIFMM_LAUNCH(gemm(d, g, s));
-    }
-    KIFMM_TRY(pinv_apply(h, d->down_V, d->down_Ut, op.r_down, D.w, chk, d->local[l], D.n, nvec, s));
   }
   if (timed) KIFMM_HIP(hipEventRecord(d->ev[2], s));
-  KIFMM_LAUNCH(launch_leaf_eval(d->tgt_xyz, d->src_xyz, d->src_xyz_f, d->qs, d->fp64, t.n_src,
-                                d->tgt_start, d->tgt_end, d->src_start, d->src_end, d->near_offs,
-                                d->near_src, d->leaf_centers, leaf.n, d->surf, op.ao * 0.5 * leaf.w, ns,
-                                d->local[depth], d->tgt_perm, phi, ldphi, nvec, s));
+  if (phased) {
+    KIFMM_TRY(leaf_pass(1, s));
+    KIFMM_HIP(hipEventRecord(d->ev[5], s));
+    KIFMM_TRY(leaf_pass(2, s));
+  } else {
+    KIFMM_TRY(leaf_pass(0, s));
+  }
   if (timed) {
     KIFMM_HIP(hipEventRecord(d->ev[3], s));
     KIFMM_HIP(hipEventSynchronize(d->ev[3]));
@@ -773,13 +838,19 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
         KIFMM_HIP(hipEventElapsedTime(&ms, d->lev_ev[4 * l + k], d->lev_ev[4 * l + k + 1]));
         parts[k] += ms;
       }
-    // FFT: wall time from the fork to the join (levels overlap); otherwise
+    // phased: the M2L is the wall time of the concurrent levels; serial:
     // the levels run back to back and their kernel phases add up
     double m2l_ms = parts[0] + parts[1] + parts[2];
-    if (fork) {
-      float w = 0.f;
+    if (phased) {
+      float w = 0.f, nf = 0.f, ff = 0.f;
       KIFMM_HIP(hipEventElapsedTime(&w, d->ev[1], d->ev[4]));
+      KIFMM_HIP(hipEventElapsedTime(&nf, d->ev[2], d->ev[5]));
+      KIFMM_HIP(hipEventElapsedTime(&ff, d->ev[5], d->ev[3]));
       m2l_ms = w;
+      h->timings[9] = nf;
+      h->timings[10] = ff;
+    } else {
+      h->timings[9] = h->timings[10] = 0.0;
     }
     h->timings[0] = a;
     h->timings[1] = m2l_ms;

@@ -120,5 +120,5 @@ struct kifmm_handle {
   bool has_points = false;
   kifmm::DeviceState* dev = nullptr;
   bool timing = false;
-  double timings[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double timings[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 };

@@ -101,79 +101,101 @@ __global__ __launch_bounds__((FftCfg<T, P>::threads)) void fft_forward_kernel(
   T* sv = reinterpret_cast<T*>(a2);  // densities; read before a2 is written
   static_assert(IT * NS * sizeof(T) <= IT * L::s2i * sizeof(C2), "density staging fits in a2");
   const int tid = threadIdx.x;
-  // consecutive rows on one XCD, so the two 64-byte halves of a 128-byte
-  // line of Qhat meet in the same L2
-  const int64_t nwg = (n_rows * 8 + IT - 1) / IT, per_xcd = (nwg + 7) / 8;
+  // Persistent workgroups: iteration i loads the densities of item group
+  // i nwg + wg into registers while group (i - 1) nwg + wg is transformed.
+  // Logical workgroups are numbered per XCD, so at each iteration an XCD
+  // works on consecutive rows and the two 64-byte halves of a 128-byte line
+  // of Qhat meet in the same L2.
+  constexpr int KL = (IT * NS + TH - 1) / TH;
+  const int64_t n_groups = (n_rows * 8 + IT - 1) / IT;
+  const int64_t nwg = gridDim.x, per_xcd = nwg / 8;  // grid: a multiple of 8
   const int64_t wg = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (wg >= nwg) return;
-  const int64_t g0 = wg * IT;
   for (int t = tid; t < P * P * P; t += TH) l2s[t] = lat2surf[t];
-  for (int idx = tid; idx < IT * NS; idx += TH) {
-    const int it = idx / NS, s = idx % NS;
-    const int64_t g = g0 + it, row = g / 8;
-    double val = 0.0;
-    if (row < n_rows) {
-      const int64_t c = row / nvec;
-      const int v = (int)(row - c * nvec);
-      const int32_t box = child[c * 8 + (g % 8)];
-      if (box >= 0) val = M[((int64_t)box * nvec + v) * NS + s];
-    }
-    sv[idx] = (T)val;
-  }
-  __syncthreads();
-  for (int idx = tid; idx < IT * P * P; idx += TH) {
-    const int it = idx / (P * P), x = (idx / P) % P, y = idx % P;
-    T dz[P];
+  double pre[KL];
+  for (int64_t i = 0;; ++i) {
+    const int64_t gl = i * nwg + wg, gc = gl - nwg;
+    if (gc >= n_groups) break;
+    if (i > 0) {
+      __syncthreads();  // the previous group is done with a2, which holds sv
 #pragma unroll
-    for (int z = 0; z < P; ++z) {
-      const int sidx = l2s[(x * P + y) * P + z];
-      const T dv = sv[it * NS + (sidx < 0 ? 0 : sidx)];
-      dz[z] = sidx < 0 ? T(0) : dv;
-    }
-#pragma unroll
-    for (int kz = 0; kz < H; ++kz) {
-      C2 acc;  // Wm[kz][0] = 1
-      acc.x = dz[0];
-      acc.y = T(0);
-#pragma unroll
-      for (int z = 1; z < P; ++z) {
-        const C2 wv = Wm[kz * P + z];
-        acc.x = fma(dz[z], wv.x, acc.x);
-        acc.y = fma(dz[z], wv.y, acc.y);
+      for (int k = 0; k < KL; ++k) {
+        const int idx = tid + TH * k;
+        if (idx < IT * NS) sv[idx] = (T)pre[k];
       }
-      a1[it * L::s1i + x * L::s1x + y * L::s1y + kz] = acc;
     }
-  }
-  __syncthreads();
-  for (int idx = tid; idx < IT * P * H; idx += TH) {
-    const int it = idx / (P * H), x = (idx / H) % P, kz = idx % H;
-    C2 in[P];
+    if (gl < n_groups) {
 #pragma unroll
-    for (int y = 0; y < P; ++y) in[y] = a1[it * L::s1i + x * L::s1x + y * L::s1y + kz];
-#pragma unroll
-    for (int ky = 0; ky < N; ++ky) {
-      C2 acc = in[0];  // Wm[ky][0] = 1
-#pragma unroll
-      for (int y = 1; y < P; ++y) cmac(acc, in[y], Wm[ky * P + y]);
-      a2[it * L::s2i + x * L::s2x + ky * L::s2k + kz] = acc;
+      for (int k = 0; k < KL; ++k) {
+        const int idx = tid + TH * k;
+        const int it = idx / NS, s = idx % NS;
+        const int64_t g = gl * IT + it, row = g / 8;
+        double val = 0.0;
+        if (idx < IT * NS && row < n_rows) {
+          const int64_t c = row / nvec;
+          const int v = (int)(row - c * nvec);
+          const int32_t box = child[c * 8 + (g % 8)];
+          if (box >= 0) val = M[((int64_t)box * nvec + v) * NS + s];
+        }
+        pre[k] = val;
+      }
     }
-  }
-  __syncthreads();
-  for (int idx = tid; idx < IT * N * H; idx += TH) {
-    const int it = idx % IT, col = idx / IT;
-    const int ky = col / H, kz = col % H;
-    const int64_t g = g0 + it, row = g / 8;
-    if (row >= n_rows) continue;
-    C2 in[P];
+    if (i == 0) continue;
+    const int64_t g0 = gc * IT;
+    __syncthreads();  // sv holds group gc
+    for (int idx = tid; idx < IT * P * P; idx += TH) {
+      const int it = idx / (P * P), x = (idx / P) % P, y = idx % P;
+      T dz[P];
 #pragma unroll
-    for (int x = 0; x < P; ++x) in[x] = a2[it * L::s2i + x * L::s2x + ky * L::s2k + kz];
+      for (int z = 0; z < P; ++z) {
+        const int sidx = l2s[(x * P + y) * P + z];
+        const T dv = sv[it * NS + (sidx < 0 ? 0 : sidx)];
+        dz[z] = sidx < 0 ? T(0) : dv;
+      }
 #pragma unroll
-    for (int kx = 0; kx < N; ++kx) {
-      C2 acc = in[0];  // Wm[kx][0] = 1
+      for (int kz = 0; kz < H; ++kz) {
+        C2 acc;  // Wm[kz][0] = 1
+        acc.x = dz[0];
+        acc.y = T(0);
 #pragma unroll
-      for (int x = 1; x < P; ++x) cmac(acc, in[x], Wm[kx * P + x]);
-      const int64_t f = ((int64_t)kx * N + ky) * H + kz;
-      Qhat[(f * n_rows + row) * 8 + (g % 8)] = acc;
+        for (int z = 1; z < P; ++z) {
+          const C2 wv = Wm[kz * P + z];
+          acc.x = fma(dz[z], wv.x, acc.x);
+          acc.y = fma(dz[z], wv.y, acc.y);
+        }
+        a1[it * L::s1i + x * L::s1x + y * L::s1y + kz] = acc;
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < IT * P * H; idx += TH) {
+      const int it = idx / (P * H), x = (idx / H) % P, kz = idx % H;
+      C2 in[P];
+#pragma unroll
+      for (int y = 0; y < P; ++y) in[y] = a1[it * L::s1i + x * L::s1x + y * L::s1y + kz];
+#pragma unroll
+      for (int ky = 0; ky < N; ++ky) {
+        C2 acc = in[0];  // Wm[ky][0] = 1
+#pragma unroll
+        for (int y = 1; y < P; ++y) cmac(acc, in[y], Wm[ky * P + y]);
+        a2[it * L::s2i + x * L::s2x + ky * L::s2k + kz] = acc;
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < IT * N * H; idx += TH) {
+      const int it = idx % IT, col = idx / IT;
+      const int ky = col / H, kz = col % H;
+      const int64_t g = g0 + it, row = g / 8;
+      if (row >= n_rows) continue;
+      C2 in[P];
+#pragma unroll
+      for (int x = 0; x < P; ++x) in[x] = a2[it * L::s2i + x * L::s2x + ky * L::s2k + kz];
+#pragma unroll
+      for (int kx = 0; kx < N; ++kx) {
+        C2 acc = in[0];  // Wm[kx][0] = 1
+#pragma unroll
+        for (int x = 1; x < P; ++x) cmac(acc, in[x], Wm[kx * P + x]);
+        const int64_t f = ((int64_t)kx * N + ky) * H + kz;
+        Qhat[(f * n_rows + row) * 8 + (g % 8)] = acc;
+      }
     }
   }
 }
@@ -517,14 +539,32 @@ __global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_kernel(
   }
 }
 
+// Workgroups resident on the whole device for a kernel (occupancy x CUs).
+template <typename K>
+int64_t resident_wgs(K kernel, int threads) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      cus < 1 || per_cu < 1)
+    return 0;
+  return (int64_t)cus * per_cu;
+}
+
 template <typename T, int P>
 hipError_t fwd_launch(const double* M, const int32_t* child, int64_t n_rows, int nvec,
                       const int16_t* lat2surf, const void* wm, void* Qhat, hipStream_t s) {
   using C2 = typename C2T<T>::type;
-  constexpr int IT = FftCfg<T, P>::items;
-  const unsigned grid = (unsigned)(8 * (((n_rows * 8 + IT - 1) / IT + 7) / 8));
-  fft_forward_kernel<T, P><<<grid, FftCfg<T, P>::threads, 0, s>>>(M, child, n_rows, nvec, lat2surf,
-                                                                (const C2*)wm, (C2*)Qhat);
+  constexpr int IT = FftCfg<T, P>::items, TH = FftCfg<T, P>::threads;
+  static const int64_t resident = resident_wgs(fft_forward_kernel<T, P>, TH);
+  if (resident < 1) return hipErrorInvalidValue;
+  // enough persistent workgroups to fill the device once, each taking an
+  // equal number of item groups; a multiple of 8 for the XCD numbering
+  const int64_t n_groups = (n_rows * 8 + IT - 1) / IT;
+  const int64_t rounds = (n_groups + resident - 1) / resident;
+  const int64_t nwg = ((n_groups + rounds - 1) / rounds + 7) / 8 * 8;
+  fft_forward_kernel<T, P><<<(unsigned)nwg, TH, 0, s>>>(M, child, n_rows, nvec, lat2surf,
+                                                        (const C2*)wm, (C2*)Qhat);
   return hipGetLastError();
 }
 

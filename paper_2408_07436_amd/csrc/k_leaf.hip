@@ -155,8 +155,11 @@ template <> struct Vec4<double> { using type = double4; };
 // The near-field sources (up to 27 leaves, each a contiguous run in Morton
 // order) are located by binary search over the run offsets.  L2P runs in
 // FP64 from the leaf's downward-equivalent densities; P2P runs in T.  NV
-// charge vectors are handled per pass.
-template <typename T, typename TQ, int NV>
+// charge vectors are handled per pass.  MODE 0 does both; MODE 1 only the
+// near field, storing its raw sums (in T, before the 1/(4 pi) factor);
+// MODE 2 adds the far field to those stored sums and finishes, so 1 then 2
+// gives exactly the result of 0.
+template <typename T, typename TQ, int NV, int MODE>
 __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
     const double* __restrict__ txyz, const T* __restrict__ sxyz, const TQ* __restrict__ qs,
     int64_t n_src, const int32_t* __restrict__ tstart, const int32_t* __restrict__ tend,
@@ -224,7 +227,7 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
         ap0[v] = ap1[v] = T(0);
       }
       // L2P: the leaf's downward-equivalent surface as sources (FP64)
-      for (int c0 = 0; c0 < ns; c0 += kL2PChunk) {
+      for (int c0 = 0; c0 < (MODE == 1 ? 0 : ns); c0 += kL2PChunk) {
         const int cn = min(kL2PChunk, ns - c0);
         const int cnp = (cn + 2 * L - 1) / (2 * L) * (2 * L);  // zero densities pad
         __syncthreads();
@@ -265,7 +268,7 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
       }
       // P2P over the near field
       const T xt0 = (T)x0, yt0 = (T)y0, zt0 = (T)z0, xt1 = (T)x1, yt1 = (T)y1, zt1 = (T)z1;
-      for (int c0 = 0; c0 < total; c0 += kLeafChunk) {
+      for (int c0 = 0; c0 < (MODE == 2 ? 0 : total); c0 += kLeafChunk) {
         const int cn = min(kLeafChunk, total - c0);
         const int cnp = (cn + 2 * L - 1) / (2 * L) * (2 * L);  // zero charges pad
         __syncthreads();
@@ -322,24 +325,31 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           if (vb + v >= nvec) continue;
-          if (act0)
-            phi[(int64_t)(vb + v) * ldphi + tperm[t0 + ti0]] = (TQ)(kInv4Pi * (al0[v] + (double)ap0[v]));
-          if (act1)
-            phi[(int64_t)(vb + v) * ldphi + tperm[t0 + ti1]] = (TQ)(kInv4Pi * (al1[v] + (double)ap1[v]));
+          TQ* o0 = act0 ? &phi[(int64_t)(vb + v) * ldphi + tperm[t0 + ti0]] : nullptr;
+          TQ* o1 = act1 ? &phi[(int64_t)(vb + v) * ldphi + tperm[t0 + ti1]] : nullptr;
+          if (MODE == 1) {
+            if (o0) *o0 = (TQ)ap0[v];
+            if (o1) *o1 = (TQ)ap1[v];
+          } else {
+            const double n0 = MODE == 2 ? (o0 ? (double)*o0 : 0.0) : (double)ap0[v];
+            const double n1 = MODE == 2 ? (o1 ? (double)*o1 : 0.0) : (double)ap1[v];
+            if (o0) *o0 = (TQ)(kInv4Pi * (al0[v] + n0));
+            if (o1) *o1 = (TQ)(kInv4Pi * (al1[v] + n1));
+          }
         }
       }
     }
   }
 }
 
-template <typename T, typename TQ>
+template <typename T, typename TQ, int MODE>
 hipError_t leaf_launch(int nvec, unsigned grid, hipStream_t stream, const double* txyz, const T* sxyz,
                        const TQ* qs, int64_t n_src, const int32_t* tstart, const int32_t* tend,
                        const int32_t* sstart, const int32_t* send, const int64_t* near_offs,
                        const int32_t* near_src, const double* centers, const double* surf, double ar,
                        int ns, const double* local, const int64_t* tgt_perm, TQ* phi, int64_t ldphi) {
 #define KIFMM_LEAF(NVV)                                                                       \
-  leaf_eval_kernel<T, TQ, NVV><<<grid, kLeafThreads, 0, stream>>>(                            \
+  leaf_eval_kernel<T, TQ, NVV, MODE><<<grid, kLeafThreads, 0, stream>>>(                      \
       txyz, sxyz, qs, n_src, tstart, tend, sstart, send, near_offs, near_src, centers, surf, ar, \
       ns, local, tgt_perm, phi, ldphi, nvec)
   if (nvec == 1)
@@ -352,6 +362,25 @@ hipError_t leaf_launch(int nvec, unsigned grid, hipStream_t stream, const double
     KIFMM_LEAF(8);
 #undef KIFMM_LEAF
   return hipGetLastError();
+}
+
+template <typename T, typename TQ>
+hipError_t leaf_mode(int mode, int nvec, unsigned grid, hipStream_t stream, const double* txyz,
+                     const T* sxyz, const TQ* qs, int64_t n_src, const int32_t* tstart,
+                     const int32_t* tend, const int32_t* sstart, const int32_t* send,
+                     const int64_t* near_offs, const int32_t* near_src, const double* centers,
+                     const double* surf, double ar, int ns, const double* local,
+                     const int64_t* tgt_perm, TQ* phi, int64_t ldphi) {
+  switch (mode) {
+#define KIFMM_MODE(M)                                                                        \
+  case M:                                                                                    \
+    return leaf_launch<T, TQ, M>(nvec, grid, stream, txyz, sxyz, qs, n_src, tstart, tend, sstart, \
+                                 send, near_offs, near_src, centers, surf, ar, ns, local,     \
+                                 tgt_perm, phi, ldphi);
+    KIFMM_MODE(0) KIFMM_MODE(1) KIFMM_MODE(2)
+#undef KIFMM_MODE
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
@@ -384,17 +413,17 @@ hipError_t launch_leaf_eval(const double* tgt_xyz, const double* src_xyz, const 
                             const int64_t* near_offs, const int32_t* near_src,
                             const double* centers, int64_t n_leaf, const double* surf, double ar,
                             int ns, const double* local, const int64_t* tgt_perm, void* phi,
-                            int64_t ldphi, int nvec, hipStream_t stream) {
+                            int64_t ldphi, int nvec, int mode, hipStream_t stream) {
   if (n_leaf == 0) return hipSuccess;
   if (fp64)
-    return leaf_launch<double, double>(nvec, (unsigned)n_leaf, stream, tgt_xyz, src_xyz,
-                                       (const double*)qs, n_src, tstart, tend, sstart, send,
-                                       near_offs, near_src, centers, surf, ar, ns, local, tgt_perm,
-                                       (double*)phi, ldphi);
-  return leaf_launch<float, float>(nvec, (unsigned)n_leaf, stream, tgt_xyz, src_xyz_f,
-                                   (const float*)qs, n_src, tstart, tend, sstart, send, near_offs,
-                                   near_src, centers, surf, ar, ns, local, tgt_perm, (float*)phi,
-                                   ldphi);
+    return leaf_mode<double, double>(mode, nvec, (unsigned)n_leaf, stream, tgt_xyz, src_xyz,
+                                     (const double*)qs, n_src, tstart, tend, sstart, send,
+                                     near_offs, near_src, centers, surf, ar, ns, local, tgt_perm,
+                                     (double*)phi, ldphi);
+  return leaf_mode<float, float>(mode, nvec, (unsigned)n_leaf, stream, tgt_xyz, src_xyz_f,
+                                 (const float*)qs, n_src, tstart, tend, sstart, send, near_offs,
+                                 near_src, centers, surf, ar, ns, local, tgt_perm, (float*)phi,
+                                 ldphi);
 }
 
 }  // namespace kifmm

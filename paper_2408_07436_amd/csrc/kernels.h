@@ -20,14 +20,16 @@ hipError_t launch_p2m(const double* src_xyz, const void* qs, bool q_fp64, int64_
                       hipStream_t stream);
 
 // Leaf evaluation: L2P (FP64) + P2P over the near field (precision of the
-// charges), written to the caller's target order.
+// charges), written to the caller's target order.  mode 0: both; mode 1:
+// the near field only, phi receives its raw sums (no 1/(4 pi)); mode 2: the
+// far field added to the raw sums in phi, finished - 1 then 2 equals 0.
 hipError_t launch_leaf_eval(const double* tgt_xyz, const double* src_xyz, const float* src_xyz_f,
                             const void* qs, bool fp64, int64_t n_src, const int32_t* tstart,
                             const int32_t* tend, const int32_t* sstart, const int32_t* send,
                             const int64_t* near_offs, const int32_t* near_src,
                             const double* centers, int64_t n_leaf, const double* surf, double ar,
                             int ns, const double* local, const int64_t* tgt_perm, void* phi,
-                            int64_t ldphi, int nvec, hipStream_t stream);
+                            int64_t ldphi, int nvec, int mode, hipStream_t stream);
 
 // FP64 GEMM with gathered columns: C(:, col) = alpha * A * B(:, col) (+ C).
 // Columns are (box, v) pairs, col = box * nvec + v.  B's row k of column

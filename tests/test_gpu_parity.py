@@ -173,3 +173,31 @@ def test_blas_full_size_sampled(prec, gate):
     say(f"  rel err vs oracle (projected operator) {e:.3e}")
     assert e <= gate
     assert np.all(np.isfinite(got))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_schedules_agree_bitwise(prec):
+    """The untimed FFT evaluate (multi-stream dependency graph, near field split
+    from the far field) and the timed one (phases back to back) give identical
+    potentials, and the timed one fills every phase time."""
+    pts = workloads.uniform_cube(40000, 81)
+    q = workloads.charges(40000, 2, 82, "upm1")
+    say(f"case: schedules fft 40k depth 4 p5 {prec} nvec 2")
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    f = K.KiFMM(5, 4, m2l="fft", prec=prec).set_points(pts).precompute()
+    qt = torch.as_tensor(q, dtype=dt, device="cuda")
+    a = f.evaluate(qt).clone()
+    f.set_timing(True)
+    b = f.evaluate(qt).clone()
+    tm = f.timings()
+    f.set_timing(False)
+    c = f.evaluate(qt).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, c)
+    for k in ("upward", "m2l", "downward", "leaves", "total", "near_field", "far_field"):
+        assert tm[k] > 0.0, k
+    assert tm["m2l_levels"] == 3
+    ref = fmm.KiFMM(pts, pts, 4, 5).evaluate(q)
+    e = kernel.rel_l2(a.double().cpu().numpy(), ref)
+    say(f"  rel err vs oracle {e:.3e}")
+    assert e <= (FP64_GATE if prec == "fp64" else FP32_GATE)
