@@ -22,13 +22,13 @@ struct DevLevel {
   double* chk = nullptr;
   // FFT-M2L source blocks: the clusters of one aligned 4 x 4 x 4 cube of
   // level l-1 (consecutive in Morton order) share one list of at most 216
-  // source clusters with LDS slots; slots[c] holds, per direction, the slot
-  // of cluster c's neighbour (26 bytes in 7 words)
+  // source clusters with LDS slots; slots[c] holds, per direction, the LDS
+  // byte offset of cluster c's neighbour's row (26 x 16 bits in 13 words)
   int64_t hb_n = 0;
   int32_t* hb_tgt = nullptr;    // [hb_n + 1] first cluster of each block
   int32_t* hb_src = nullptr;    // [hb_n + 1] offsets into hb_list
   int32_t* hb_list = nullptr;   // cluster << 8 | slot (the empty cluster n_{l-1} included)
-  uint32_t* hb_slots = nullptr; // [n_{l-1}][7]
+  uint32_t* hb_slots = nullptr; // [n_{l-1}][13]: 26 LDS byte offsets (16 bits each)
   // BLAS / dense M2L: target tiles of one octant class and, per tile, the
   // transfer vectors present with the source box of every tile slot
   int64_t ntiles = 0;
@@ -291,7 +291,7 @@ static kifmm_status build_source_blocks(DeviceState* d, DevLevel& D, const Level
                                         const std::vector<int32_t>& halo) {
   const int64_t nc = up.n;
   std::vector<int32_t> tgt, src, list;
-  std::vector<uint32_t> slots((size_t)nc * 7, 0u);
+  std::vector<uint32_t> slots((size_t)nc * 13, 0u);
   int64_t c = 0;
   while (c < nc) {
     const uint64_t bk = up.keys[c] >> 6;
@@ -326,7 +326,7 @@ static kifmm_status build_source_blocks(DeviceState* d, DevLevel& D, const Level
       for (int dd = 0; dd < kNumDirections; ++dd) {
         const int32_t s = halo[(size_t)dd * nc + i];
         const size_t k = (size_t)(std::lower_bound(u.begin(), u.end(), s) - u.begin());
-        slots[(size_t)i * 7 + dd / 4] |= (uint32_t)slot_of[k] << (8 * (dd % 4));
+        slots[(size_t)i * 13 + dd / 2] |= (uint32_t)(slot_of[k] * kHadRowBytes) << (16 * (dd % 2));
       }
     for (size_t k = 0; k < u.size(); ++k) list.push_back((int32_t)((uint32_t)u[k] << 8 | (uint32_t)slot_of[k]));
     c = e;

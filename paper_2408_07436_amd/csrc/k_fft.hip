@@ -421,6 +421,7 @@ __global__ __launch_bounds__(kHadThreads) void hadamard_gather_kernel(
 }
 
 constexpr int kHadSrcMax = 216;  // source slots of one 4 x 4 x 4 block: its 6 x 6 x 6 shell
+static_assert(kHadRowBytes % 16 == 0 && kHadRowBytes >= 64, "LDS row of 16 floats");
 constexpr int kHadStage = (kHadSrcMax * 4 + kHadThreads - 1) / kHadThreads;
 
 // Block form (FP32).  Workgroup = one frequency x a run of (block, charge
@@ -443,15 +444,15 @@ __global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_kernel(
     const int32_t* __restrict__ blk_list, const uint32_t* __restrict__ slots, int64_t n_items,
     int nvec, int64_t n_rows, int items_per_wg, int n_groups, int64_t total_wgs,
     float* __restrict__ Phat) {
-  constexpr int kRow = 5;  // LDS row stride in float4: 16 reals + padding
+  constexpr int kRow = kHadRowBytes / 16;  // LDS row stride in float4: 16 reals + padding
   __shared__ float4 As[2][kHadSrcMax * kRow + 1];  // + one discard entry
   const int64_t b = blockIdx.x;
   const int64_t per_xcd = (total_wgs + 7) / 8;
   const int64_t logical = (b % 8) * per_xcd + b / 8;  // consecutive work per XCD
   if (logical >= total_wgs) return;
   const int64_t f = logical / n_groups;
-  const int64_t item0 = (logical % n_groups) * items_per_wg;
-  const int64_t item1 = min(item0 + items_per_wg, n_items);
+  const int item0 = (int)((logical % n_groups) * items_per_wg);
+  const int item1 = (int)min((int64_t)item0 + items_per_wg, n_items);
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int rl = lane % 16, g = lane / 16;
@@ -465,76 +466,93 @@ __global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_kernel(
     B[d] = (rl & 1) ? float4{k.y, k.x, k.w, k.z} : float4{k.x, -k.y, k.z, -k.w};
   }
   // this frequency's spectra (n_rows + nvec rows: the empty cluster last)
+  // and products, addressed with 32-bit byte offsets from these bases
   const char* qf = reinterpret_cast<const char*>(Qhat + f * (n_rows + nvec) * 16);
-  float* pf = Phat + f * n_rows * 16;
+  char* pf = reinterpret_cast<char*>(Phat + f * n_rows * 16);
   const int tr0 = wave * 16;  // this wave's tile of the block's targets
+  const uint32_t row_bytes = 64u * (uint32_t)nvec;  // one cluster's rows
   // staging registers: four 16-byte pieces per thread (216 rows x 4 pieces
-  // over 256 threads), named rather than an array so they stay in VGPRs
+  // over 256 threads), named rather than an array so they stay in VGPRs;
+  // piece k is row (tid + 256 k) / 4, quarter tid % 4
   static_assert(kHadStage == 4, "staging pieces per thread");
+  const uint32_t part_bytes = 16u * (uint32_t)(tid & 3);
   float4 stg0, stg1, stg2, stg3;
-  int sl0 = 0, sl1 = 0, sl2 = 0, sl3 = 0;
-  uint32_t w[7], wn[7];
+  uint32_t sl0 = 0, sl1 = 0, sl2 = 0, sl3 = 0;
+  uint32_t w[13];  // 26 LDS byte offsets (16 bits each) of the lane's target
   int buf = 0;
+  // (block, vector) of the next item to load, and of the item whose rows
+  // sit in the staging registers
+  int lblk = item0 / nvec, lv = item0 - lblk * nvec;
+  int pblk = lblk, pv = lv;
   // iteration `it` issues the loads of item it (into registers) and then
   // computes item it - 1, whose rows the previous iteration loaded
-  for (int64_t it = item0; it <= item1; ++it) {
+  for (int it = item0; it <= item1; ++it) {
+    const int blk = pblk, v = pv;  // item it - 1
     if (it > item0) {
-      As[buf][sl0] = stg0;
-      As[buf][sl1] = stg1;
-      As[buf][sl2] = stg2;
-      As[buf][sl3] = stg3;
-#pragma unroll
-      for (int k = 0; k < 7; ++k) w[k] = wn[k];
+      char* ab = reinterpret_cast<char*>(As[buf]);
+      *reinterpret_cast<float4*>(ab + sl0) = stg0;
+      *reinterpret_cast<float4*>(ab + sl1) = stg1;
+      *reinterpret_cast<float4*>(ab + sl2) = stg2;
+      *reinterpret_cast<float4*>(ab + sl3) = stg3;
       __syncthreads();  // As[buf] complete; As[buf ^ 1] free for the next item
     }
     if (it < item1) {
-      const int64_t blk = it / nvec;
-      const uint32_t v = (uint32_t)(it - blk * nvec);
-      const int s0 = blk_src[blk], ns = blk_src[blk + 1] - s0;
-      const int t0 = blk_tgt[blk], nt = blk_tgt[blk + 1] - t0;
-      // piece k of this thread: row (tid + 256 k) / 4, quarter tid % 4;
-      // threads past the list read its first entry into the discard entry
-      auto piece = [&](int k, float4& st, int& slot) __attribute__((always_inline)) {
-        const int idx = tid + kHadThreads * k, r = idx >> 2, part = idx & 3;
-        const int32_t e = blk_list[s0 + (r < ns ? r : 0)];
-        const uint32_t src = (uint32_t)e >> 8;
-        const uint32_t off = ((src * (uint32_t)nvec + v) * 16 + 4 * part) * 4u;
-        st = *reinterpret_cast<const float4*>(qf + off);
-        slot = r < ns ? (e & 255) * kRow + part : kHadSrcMax * kRow;
+      const int s0 = blk_src[lblk], ns = blk_src[lblk + 1] - s0;
+      const int t0 = blk_tgt[lblk], nt = blk_tgt[lblk + 1] - t0;
+      const int32_t* lst = blk_list + s0;
+      const uint32_t vb = (uint32_t)lv * 64u + part_bytes;
+      auto piece = [&](int k, float4& st, uint32_t& sl) __attribute__((always_inline)) {
+        const int r = (tid + kHadThreads * k) >> 2;
+        const int32_t e = lst[r < ns ? r : 0];  // past the list: first entry, discarded
+        st = *reinterpret_cast<const float4*>(qf + (((uint32_t)e >> 8) * row_bytes + vb));
+        sl = r < ns ? (uint32_t)(e & 255) * kHadRowBytes + part_bytes : kHadSrcMax * kHadRowBytes;
       };
       piece(0, stg0, sl0);
       piece(1, stg1, sl1);
       piece(2, stg2, sl2);
       piece(3, stg3, sl3);
-      const int tr = min(tr0 + rl, nt - 1);
-#pragma unroll
-      for (int k = 0; k < 7; ++k) wn[k] = slots[(int64_t)(t0 + tr) * 7 + k];
+      pblk = lblk;
+      pv = lv;
+      if (++lv == nvec) {
+        lv = 0;
+        ++lblk;
+      }
     }
-    if (it == item0) continue;
-    const int64_t item = it - 1;
-    const int64_t blk = item / nvec;
-    const int v = (int)(item - blk * nvec);
-    const int t0 = blk_tgt[blk], nt = blk_tgt[blk + 1] - t0;
-    const int cur = buf;
-    buf ^= 1;
-    if (tr0 >= nt) continue;
-    // two accumulators (even / odd directions) so consecutive MFMAs are
-    // independent
     v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+    int t0 = 0, nt = 0;
+    if (it > item0) {
+      t0 = blk_tgt[blk];
+      nt = blk_tgt[blk + 1] - t0;
+      const char* ab = reinterpret_cast<const char*>(As[buf]) + 16 * g;
+      buf ^= 1;
+      if (tr0 < nt) {
+        // two accumulators (even / odd directions) so consecutive MFMAs are
+        // independent
 #pragma unroll
-    for (int d = 0; d < 26; ++d) {
-      const uint32_t slot = (w[d / 4] >> (8 * (d % 4))) & 0xffu;
-      const float4 a = As[cur][slot * kRow + g];
-      v4f& acc = (d & 1) ? acc1 : acc0;
-      acc = mfma16(a.x, B[d].x, acc);
-      acc = mfma16(a.y, B[d].y, acc);
-      acc = mfma16(a.z, B[d].z, acc);
-      acc = mfma16(a.w, B[d].w, acc);
+        for (int d = 0; d < 26; ++d) {
+          const uint32_t off = (d & 1) ? (w[d / 2] >> 16) : (w[d / 2] & 0xffffu);
+          const float4 a = *reinterpret_cast<const float4*>(ab + off);
+          v4f& acc = (d & 1) ? acc1 : acc0;
+          acc = mfma16(a.x, B[d].x, acc);
+          acc = mfma16(a.y, B[d].y, acc);
+          acc = mfma16(a.z, B[d].z, acc);
+          acc = mfma16(a.w, B[d].w, acc);
+        }
+      }
     }
+    // the LDS offsets of the item just loaded, for the next iteration
+    if (it < item1) {
+      const int nt0 = blk_tgt[pblk], ntn = blk_tgt[pblk + 1] - nt0;
+      const uint32_t* sw = slots + (int64_t)nt0 * 13 + (uint32_t)min(tr0 + rl, ntn - 1) * 13u;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int to = tr0 + out_row(0.f, g, i);
-      if (to < nt) pf[((int64_t)(t0 + to) * nvec + v) * 16 + rl] = acc0[i] + acc1[i];
+      for (int k = 0; k < 13; ++k) w[k] = sw[k];
+    }
+    if (it > item0 && tr0 < nt) {
+      // row tr0 + 4 g + i of the tile: cluster t0 + that row, vector v
+      const uint32_t o0 = ((uint32_t)(t0 + tr0 + 4 * g) * nvec + v) * 64u + 4u * rl;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (tr0 + 4 * g + i < nt) *reinterpret_cast<float*>(pf + o0 + i * row_bytes) = acc0[i] + acc1[i];
     }
   }
 }

@@ -55,6 +55,9 @@ struct Gemm64 {
 hipError_t launch_gemm64(const Gemm64& g, hipStream_t stream);
 
 // ---- FFT-M2L (Appendix A.1) ----------------------------------------------
+// LDS row stride of the FP32 block-form Hadamard: 16 floats + 16 bytes of
+// padding; the slot table holds byte offsets slot * kHadRowBytes.
+constexpr int kHadRowBytes = 80;
 // Forward: densities M[box][v][ns] (FP64) of the children of each cluster
 // -> spectra Qhat[f][row][8] (complex, T), row = cluster * nvec + v.
 // lat2surf[(x p + y) p + z] is the surface index of a lattice point or -1;
@@ -69,7 +72,8 @@ hipError_t launch_fft_forward(int p, bool fp64, const double* M, const int32_t* 
 // absent neighbours name it.  FP64 gathers through halo; FP32 stages
 // source blocks: block b covers clusters [blk_tgt[b], blk_tgt[b + 1]), its
 // sources are blk_list[blk_src[b] ...] packed as cluster << 8 | slot, and
-// byte d of slots[c] (7 words per cluster) is the slot of halo[d][c].
+// 16-bit entry d of slots[c] (13 words per cluster) is slot(halo[d][c]) *
+// kHadRowBytes.
 hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
                            const int32_t* halo, int64_t n_blocks, const int32_t* blk_tgt,
                            const int32_t* blk_src, const int32_t* blk_list, const uint32_t* slots,
