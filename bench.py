@@ -300,7 +300,7 @@ def run_batch(K, torch, launches):
     return out
 
 
-def cpu_baseline(w, budget_boxes=2048):
+def cpu_baseline(w, budget_boxes=32768):
     """FP64 oracle dense M2L timed on a bounded sample of target boxes."""
     from oracle import fmm
     try:

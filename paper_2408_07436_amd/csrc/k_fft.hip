@@ -222,7 +222,12 @@ __global__ __launch_bounds__(kInvThreads) void fft_inverse_kernel(
   __shared__ C2 b2[ITEMS][P][N][H];
   __shared__ C2 b1[ITEMS][P][P][H];
   const int tid = threadIdx.x;
-  const int64_t g0 = (int64_t)blockIdx.x * ITEMS;
+  // consecutive rows on one XCD, so the two 64-byte halves of a 128-byte
+  // line of Phat are fetched once, into the same L2
+  const int64_t nwg = (n_rows * 8 + ITEMS - 1) / ITEMS, per_xcd = (nwg + 7) / 8;
+  const int64_t wg = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (wg >= nwg) return;
+  const int64_t g0 = wg * ITEMS;
   // x: complex inverse, only x in [0, p) is kept
   for (int idx = tid; idx < ITEMS * N * H; idx += kInvThreads) {
     const int it = idx % ITEMS, col = idx / ITEMS;
@@ -600,7 +605,7 @@ hipError_t inv_launch(const void* Phat, const int32_t* child, int64_t n_rows, in
                       hipStream_t s) {
   using C2 = typename C2T<T>::type;
   constexpr int IT = InvItems<T, P>::value;
-  const unsigned grid = (unsigned)((n_rows * 8 + IT - 1) / IT);
+  const unsigned grid = (unsigned)(8 * (((n_rows * 8 + IT - 1) / IT + 7) / 8));
   fft_inverse_kernel<T, P, IT><<<grid, kInvThreads, 0, s>>>((const C2*)Phat, child, n_rows, nvec,
                                                           surf_lat, (const C2*)wm, scale, out);
   return hipGetLastError();

@@ -167,7 +167,7 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
     const int64_t* __restrict__ noffs, const int32_t* __restrict__ nsrc,
     const double* __restrict__ centers, const double* __restrict__ surf, double ar, int ns,
     const double* __restrict__ local, const int64_t* __restrict__ tperm, TQ* __restrict__ phi,
-    int64_t ldphi, int nvec) {
+    int64_t ldphi, int nvec, int64_t n_leaf) {
   using T4 = typename Vec4<T>::type;
   constexpr int NX = NV > 1 ? NV - 1 : 1;
   __shared__ double4 ls[kL2PChunk];
@@ -178,7 +178,11 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
   __shared__ int32_t nb_pref[28];
   __shared__ int32_t n_nb;
 
-  const int64_t leaf = blockIdx.x;
+  // consecutive leaves (which share most near-field sources) on one XCD;
+  // the grid is 8 ceil(n_leaf / 8) workgroups
+  const int64_t per_xcd = (n_leaf + 7) / 8;
+  const int64_t leaf = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (leaf >= n_leaf) return;
   const int t0 = tstart[leaf], t1 = tend[leaf];
   const int nt = t1 - t0;
   if (nt == 0) return;
@@ -343,15 +347,16 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
 }
 
 template <typename T, typename TQ, int MODE>
-hipError_t leaf_launch(int nvec, unsigned grid, hipStream_t stream, const double* txyz, const T* sxyz,
+hipError_t leaf_launch(int nvec, int64_t n_leaf, hipStream_t stream, const double* txyz, const T* sxyz,
                        const TQ* qs, int64_t n_src, const int32_t* tstart, const int32_t* tend,
                        const int32_t* sstart, const int32_t* send, const int64_t* near_offs,
                        const int32_t* near_src, const double* centers, const double* surf, double ar,
                        int ns, const double* local, const int64_t* tgt_perm, TQ* phi, int64_t ldphi) {
 #define KIFMM_LEAF(NVV)                                                                       \
-  leaf_eval_kernel<T, TQ, NVV, MODE><<<grid, kLeafThreads, 0, stream>>>(                      \
+  leaf_eval_kernel<T, TQ, NVV, MODE><<<(unsigned)(8 * ((n_leaf + 7) / 8)), kLeafThreads, 0,  \
+                                       stream>>>(                                             \
       txyz, sxyz, qs, n_src, tstart, tend, sstart, send, near_offs, near_src, centers, surf, ar, \
-      ns, local, tgt_perm, phi, ldphi, nvec)
+      ns, local, tgt_perm, phi, ldphi, nvec, n_leaf)
   if (nvec == 1)
     KIFMM_LEAF(1);
   else if (nvec == 2)
@@ -365,7 +370,7 @@ hipError_t leaf_launch(int nvec, unsigned grid, hipStream_t stream, const double
 }
 
 template <typename T, typename TQ>
-hipError_t leaf_mode(int mode, int nvec, unsigned grid, hipStream_t stream, const double* txyz,
+hipError_t leaf_mode(int mode, int nvec, int64_t n_leaf, hipStream_t stream, const double* txyz,
                      const T* sxyz, const TQ* qs, int64_t n_src, const int32_t* tstart,
                      const int32_t* tend, const int32_t* sstart, const int32_t* send,
                      const int64_t* near_offs, const int32_t* near_src, const double* centers,
@@ -374,7 +379,7 @@ hipError_t leaf_mode(int mode, int nvec, unsigned grid, hipStream_t stream, cons
   switch (mode) {
 #define KIFMM_MODE(M)                                                                        \
   case M:                                                                                    \
-    return leaf_launch<T, TQ, M>(nvec, grid, stream, txyz, sxyz, qs, n_src, tstart, tend, sstart, \
+    return leaf_launch<T, TQ, M>(nvec, n_leaf, stream, txyz, sxyz, qs, n_src, tstart, tend, sstart, \
                                  send, near_offs, near_src, centers, surf, ar, ns, local,     \
                                  tgt_perm, phi, ldphi);
     KIFMM_MODE(0) KIFMM_MODE(1) KIFMM_MODE(2)
@@ -416,11 +421,11 @@ hipError_t launch_leaf_eval(const double* tgt_xyz, const double* src_xyz, const 
                             int64_t ldphi, int nvec, int mode, hipStream_t stream) {
   if (n_leaf == 0) return hipSuccess;
   if (fp64)
-    return leaf_mode<double, double>(mode, nvec, (unsigned)n_leaf, stream, tgt_xyz, src_xyz,
+    return leaf_mode<double, double>(mode, nvec, n_leaf, stream, tgt_xyz, src_xyz,
                                      (const double*)qs, n_src, tstart, tend, sstart, send,
                                      near_offs, near_src, centers, surf, ar, ns, local, tgt_perm,
                                      (double*)phi, ldphi);
-  return leaf_mode<float, float>(mode, nvec, (unsigned)n_leaf, stream, tgt_xyz, src_xyz_f,
+  return leaf_mode<float, float>(mode, nvec, n_leaf, stream, tgt_xyz, src_xyz_f,
                                  (const float*)qs, n_src, tstart, tend, sstart, send, near_offs,
                                  near_src, centers, surf, ar, ns, local, tgt_perm, (float*)phi,
                                  ldphi);
