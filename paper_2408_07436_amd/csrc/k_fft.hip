@@ -28,6 +28,27 @@ template <typename T> struct C2T;
 template <> struct C2T<float> { using type = float2; };
 template <> struct C2T<double> { using type = double2; };
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ inline v4f mfma16(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// accumulator row of element i of lane group g (measured lane layouts)
+__device__ inline int out_row(float, int g, int i) { return 4 * g + i; }
+__device__ inline int out_row(double, int g, int i) { return g + 4 * i; }
+// Row r of an A operand whose product row out_row(g, i) is to hold logical
+// row 4 g + i (so each lane's four outputs are consecutive logical rows)
+__device__ inline int a_row(float, int r) { return r; }
+__device__ inline int a_row(double, int r) { return 4 * (r % 4) + r / 4; }
+
+template <typename T> struct V4T;
+template <> struct V4T<float> { using type = v4f; };
+template <> struct V4T<double> { using type = v4d; };
+
 // acc += a * w and acc += a * conj(w) as four FMAs each
 template <typename C2>
 __device__ inline void cmac(C2& acc, C2 a, C2 w) {
@@ -78,13 +99,15 @@ template <typename T, int P> struct FftCfg {
   static constexpr int threads = (items * P * P + 63) / 64 * 64;
 };
 
-// Forward transforms of `items` boxes per workgroup in three stages, each
-// thread transforming whole lines so that the twiddle matrix
-// Wm[k][j] = exp(-2 pi i (k j mod n) / n) (n x p) is read at wave-uniform
-// addresses:
-//   z: a1[x][y][kz] = sum_z d(x, y, z) Wm[kz][z]        (real input, kz < p)
+// Forward transforms of `items` boxes per workgroup in three stages, with
+// the twiddle matrix Wm[k][j] = exp(-2 pi i (k j mod n) / n) (n x p):
+//   z: a1[x][y][kz] = sum_z d(x, y, z) Wm[kz][z]        (real input, kz < p;
+//      VALU, one thread per line, twiddles at wave-uniform addresses)
 //   y: a2[x][ky][kz] = sum_y a1[x][y][kz] Wm[ky][y]     (ky < n)
 //   x: Qhat[f][row][child] = sum_x a2[x][ky][kz] Wm[kx][x], f = (kx n + ky) p + kz.
+// The y and x stages are real products on MFMA: the 2n x 2p real form of Wm
+// (held in registers) times 16-column tiles of the lines' real and
+// imaginary parts.
 // Box item g is child g % 8 of row g / 8 (row = cluster * nvec + v).
 template <typename T, int P>
 __global__ __launch_bounds__((FftCfg<T, P>::threads)) void fft_forward_kernel(
@@ -98,50 +121,85 @@ __global__ __launch_bounds__((FftCfg<T, P>::threads)) void fft_forward_kernel(
   __shared__ C2 a1[IT * L::s1i];
   __shared__ C2 a2[IT * L::s2i];
   __shared__ int16_t l2s[P * P * P];
-  T* sv = reinterpret_cast<T*>(a2);  // densities; read before a2 is written
-  static_assert(IT * NS * sizeof(T) <= IT * L::s2i * sizeof(C2), "density staging fits in a2");
+  __shared__ T sv[IT * NS];  // densities of the group being transformed
+  static_assert(IT <= 8 && 8 % IT == 0, "an item group lies within one row");
   const int tid = threadIdx.x;
-  // Persistent workgroups: iteration i loads the densities of item group
-  // i nwg + wg into registers while group (i - 1) nwg + wg is transformed.
-  // Logical workgroups are numbered per XCD, so at each iteration an XCD
-  // works on consecutive rows and the two 64-byte halves of a 128-byte line
-  // of Qhat meet in the same L2.
+  // Persistent workgroups: while group gc is transformed, the densities of
+  // group gc + nwg are loaded into registers (issued before the z stage,
+  // written to sv after the y stage).  The group's eight child box indices
+  // are read with scalar loads, so no vector-memory wait (which would also
+  // wait for the previous group's spectrum stores) sits between them and
+  // the density loads.  Logical workgroups are numbered per XCD, so at each
+  // iteration an XCD works on consecutive rows and the two 64-byte halves
+  // of a 128-byte line of Qhat meet in the same L2.
   constexpr int KL = (IT * NS + TH - 1) / TH;
   const int64_t n_groups = (n_rows * 8 + IT - 1) / IT;
   const int64_t nwg = gridDim.x, per_xcd = nwg / 8;  // grid: a multiple of 8
   const int64_t wg = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   for (int t = tid; t < P * P * P; t += TH) l2s[t] = lat2surf[t];
+  // MFMA operand A of the y and x stages: the real form of Wm, rows
+  // (k, re/im), columns (j, re/im); lane (lc, lg) holds row lc, column lg of
+  // each 16 x 4 block, rows ordered so that lane (lc, g) of a product holds
+  // the real and imaginary parts of outputs k = 8 mt + 2 g and 8 mt + 2 g + 1
+  using V4 = typename V4T<T>::type;
+  constexpr int MT = (2 * N + 15) / 16, KS = (2 * P + 3) / 4, NW = TH / 64;
+  const int wave = tid / 64, lc = tid % 16, lg = (tid % 64) / 16;
+  T Ar[MT][KS];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int m = 16 * mt + a_row(T(0), lc), k = 4 * ks + lg;
+      T val = T(0);
+      if (m < 2 * N && k < 2 * P) {
+        const C2 w = Wm[(m >> 1) * P + (k >> 1)];
+        val = (m & 1) ? ((k & 1) ? w.x : w.y) : ((k & 1) ? -w.y : w.x);
+      }
+      Ar[mt][ks] = val;
+    }
+  const T* a1f = reinterpret_cast<const T*>(a1);
+  const T* a2f = reinterpret_cast<const T*>(a2);
+  // densities of group gl into pre (box indices of absent children read
+  // box 0; their values are masked when written to sv)
   double pre[KL];
-  for (int64_t i = 0;; ++i) {
-    const int64_t gl = i * nwg + wg, gc = gl - nwg;
-    if (gc >= n_groups) break;
-    if (i > 0) {
-      __syncthreads();  // the previous group is done with a2, which holds sv
+  uint32_t okm = 0;
+  auto load_group = [&](int64_t gl) __attribute__((always_inline)) {
+    const int64_t g0 = gl * IT;
+    const uint32_t row = (uint32_t)(g0 / 8), c = row / (uint32_t)nvec;
+    const int v = (int)(row - c * (uint32_t)nvec);
+    int32_t cb[8];
 #pragma unroll
-      for (int k = 0; k < KL; ++k) {
-        const int idx = tid + TH * k;
-        if (idx < IT * NS) sv[idx] = (T)pre[k];
-      }
-    }
-    if (gl < n_groups) {
+    for (int j = 0; j < 8; ++j) cb[j] = child[(int64_t)c * 8 + j];  // uniform: scalar loads
+    okm = 0;
 #pragma unroll
-      for (int k = 0; k < KL; ++k) {
-        const int idx = tid + TH * k;
-        const int it = idx / NS, s = idx % NS;
-        const int64_t g = gl * IT + it, row = g / 8;
-        double val = 0.0;
-        if (idx < IT * NS && row < n_rows) {
-          const int64_t c = row / nvec;
-          const int v = (int)(row - c * nvec);
-          const int32_t box = child[c * 8 + (g % 8)];
-          if (box >= 0) val = M[((int64_t)box * nvec + v) * NS + s];
-        }
-        pre[k] = val;
-      }
+    for (int k = 0; k < KL; ++k) {
+      const int idx = tid + TH * k;
+      const int it = idx < IT * NS ? idx / NS : 0, sidx = idx - it * NS;
+      int32_t box = cb[0];
+#pragma unroll
+      for (int j = 1; j < 8; ++j)
+        if ((int)(g0 % 8) + it == j) box = cb[j];
+      const bool ok = idx < IT * NS && box >= 0;
+      okm |= (uint32_t)ok << k;
+      pre[k] = M[((int64_t)(ok ? box : 0) * nvec + v) * NS + (ok ? sidx : 0)];
     }
-    if (i == 0) continue;
-    const int64_t g0 = gc * IT;
-    __syncthreads();  // sv holds group gc
+  };
+  auto store_group = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+      const int idx = tid + TH * k;
+      if (idx < IT * NS) sv[idx] = (okm >> k) & 1 ? (T)pre[k] : T(0);
+    }
+  };
+  if (wg >= n_groups) return;
+  load_group(wg);
+  store_group();
+  __syncthreads();
+  for (int64_t gc = wg; gc < n_groups; gc += nwg) {
+    // past the last group the current one is loaded again (unused), so the
+    // loads and their stores to sv stay unconditional
+    const int64_t gn = gc + nwg, g0 = gc * IT;
+    load_group(gn < n_groups ? gn : gc);
     for (int idx = tid; idx < IT * P * P; idx += TH) {
       const int it = idx / (P * P), x = (idx / P) % P, y = idx % P;
       T dz[P];
@@ -166,35 +224,72 @@ __global__ __launch_bounds__((FftCfg<T, P>::threads)) void fft_forward_kernel(
       }
     }
     __syncthreads();
-    for (int idx = tid; idx < IT * P * H; idx += TH) {
-      const int it = idx / (P * H), x = (idx / H) % P, kz = idx % H;
-      C2 in[P];
+    // y stage on MFMA: a2[(ky, re/im)][col] = Ar x a1[(y, re/im)][col],
+    // col = (item, x, kz), kz fastest
+    {
+      constexpr int NC = IT * P * H, NT = (NC + 15) / 16;
+      for (int t = wave; t < NT; t += NW) {
+        const int col = 16 * t + lc;
+        const bool ok = col < NC;
+        const int cc = ok ? col : 0;
+        const int kz = cc % H, x = (cc / H) % P, it = cc / (H * P);
+        const int b1 = 2 * (it * L::s1i + x * L::s1x + kz);
+        V4 acc[MT];
 #pragma unroll
-      for (int y = 0; y < P; ++y) in[y] = a1[it * L::s1i + x * L::s1x + y * L::s1y + kz];
+        for (int mt = 0; mt < MT; ++mt) acc[mt] = V4{T(0), T(0), T(0), T(0)};
 #pragma unroll
-      for (int ky = 0; ky < N; ++ky) {
-        C2 acc = in[0];  // Wm[ky][0] = 1
+        for (int ks = 0; ks < KS; ++ks) {
+          const int k = 4 * ks + lg;  // (y, re/im)
+          const T bv = a1f[b1 + (k < 2 * P ? (k >> 1) * 2 * L::s1y + (k & 1) : 0)];
+          const T b = (ok && k < 2 * P) ? bv : T(0);
 #pragma unroll
-        for (int y = 1; y < P; ++y) cmac(acc, in[y], Wm[ky * P + y]);
-        a2[it * L::s2i + x * L::s2x + ky * L::s2k + kz] = acc;
+          for (int mt = 0; mt < MT; ++mt) acc[mt] = mfma16(Ar[mt][ks], b, acc[mt]);
+        }
+        C2* o2 = a2 + it * L::s2i + x * L::s2x + kz;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int ky = 8 * mt + 2 * lg + h;
+            if (ok && ky < N) o2[ky * L::s2k] = C2{acc[mt][2 * h], acc[mt][2 * h + 1]};
+          }
       }
     }
+    store_group();  // the z stage is done with sv
     __syncthreads();
-    for (int idx = tid; idx < IT * N * H; idx += TH) {
-      const int it = idx % IT, col = idx / IT;
-      const int ky = col / H, kz = col % H;
-      const int64_t g = g0 + it, row = g / 8;
-      if (row >= n_rows) continue;
-      C2 in[P];
+    // x stage on MFMA: Qhat(f, row, child) = Ar x a2[(x, re/im)][col],
+    // col = (ky, kz, item), item fastest, f = (kx n + ky) p + kz
+    {
+      constexpr int NC = IT * N * H, NT = (NC + 15) / 16;
+      for (int t = wave; t < NT; t += NW) {
+        const int col = 16 * t + lc;
+        const bool ok = col < NC;
+        const int cc = ok ? col : 0;
+        const int it = cc % IT, rest = cc / IT;
+        const int kz = rest % H, ky = rest / H;
+        const int64_t g = g0 + it, row = g / 8;
+        const int b2 = 2 * (it * L::s2i + ky * L::s2k + kz);
+        V4 acc[MT];
 #pragma unroll
-      for (int x = 0; x < P; ++x) in[x] = a2[it * L::s2i + x * L::s2x + ky * L::s2k + kz];
+        for (int mt = 0; mt < MT; ++mt) acc[mt] = V4{T(0), T(0), T(0), T(0)};
 #pragma unroll
-      for (int kx = 0; kx < N; ++kx) {
-        C2 acc = in[0];  // Wm[kx][0] = 1
+        for (int ks = 0; ks < KS; ++ks) {
+          const int k = 4 * ks + lg;  // (x, re/im)
+          const T bv = a2f[b2 + (k < 2 * P ? (k >> 1) * 2 * L::s2x + (k & 1) : 0)];
+          const T b = (ok && k < 2 * P) ? bv : T(0);
 #pragma unroll
-        for (int x = 1; x < P; ++x) cmac(acc, in[x], Wm[kx * P + x]);
-        const int64_t f = ((int64_t)kx * N + ky) * H + kz;
-        Qhat[(f * n_rows + row) * 8 + (g % 8)] = acc;
+          for (int mt = 0; mt < MT; ++mt) acc[mt] = mfma16(Ar[mt][ks], b, acc[mt]);
+        }
+        if (ok && row < n_rows) {
+          C2* qrow = Qhat + row * 8 + (g % 8) + ((int64_t)ky * H + kz) * n_rows * 8;
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int kx = 8 * mt + 2 * lg + h;
+              if (kx < N) qrow[(int64_t)kx * N * H * n_rows * 8] = C2{acc[mt][2 * h], acc[mt][2 * h + 1]};
+            }
+        }
       }
     }
   }
@@ -203,7 +298,10 @@ __global__ __launch_bounds__((FftCfg<T, P>::threads)) void fft_forward_kernel(
 // Inverse transforms, one (row, child) box per item: complex inverse DFTs
 // along x (only x < p kept) and y (y < p), then the complex-to-real step
 // along z (odd length: no Nyquist term) at the check-surface points, scaled.
-// Twiddles conj(Wm[k][j]); one output per task in the y and z stages.
+// Twiddles conj(Wm[k][j]): at wave-uniform addresses (scalar registers) in
+// the x stage, from an LDS copy in the y and z stages, which take one output
+// per task.  The row's child boxes and the surface-lattice table are read
+// once per workgroup, so the output stores wait on no vector-memory load.
 constexpr int kInvThreads = 256;
 template <typename C2>
 __device__ inline C2 cmulc(C2 a, C2 b) {  // a * conj(b)
@@ -221,6 +319,9 @@ __global__ __launch_bounds__(kInvThreads) void fft_inverse_kernel(
   constexpr int N = 2 * P - 1, H = P, NS = 6 * (P - 1) * (P - 1) + 2;
   __shared__ C2 b2[ITEMS][P][N][H];
   __shared__ C2 b1[ITEMS][P][P][H];
+  __shared__ int16_t sl[3 * NS];
+  __shared__ C2 wl[N * P];  // twiddles read at lane-varying indices
+  static_assert(ITEMS <= 8 && 8 % ITEMS == 0, "a workgroup's items lie within one row");
   const int tid = threadIdx.x;
   // consecutive rows on one XCD, so the two 64-byte halves of a 128-byte
   // line of Phat are fetched once, into the same L2
@@ -228,6 +329,15 @@ __global__ __launch_bounds__(kInvThreads) void fft_inverse_kernel(
   const int64_t wg = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (wg >= nwg) return;
   const int64_t g0 = wg * ITEMS;
+  for (int t = tid; t < 3 * NS; t += kInvThreads) sl[t] = surf_lat[t];
+  for (int t = tid; t < N * P; t += kInvThreads) wl[t] = Wm[t];
+  // the row's child boxes, read with scalar loads (uniform addresses), so
+  // the output stores need no vector-memory wait between them
+  const uint32_t row0 = (uint32_t)(g0 / 8), c0 = row0 / (uint32_t)nvec;
+  const int v0 = (int)(row0 - c0 * (uint32_t)nvec);
+  int32_t cb[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) cb[j] = child[(int64_t)c0 * 8 + j];
   // x: complex inverse, only x in [0, p) is kept
   for (int idx = tid; idx < ITEMS * N * H; idx += kInvThreads) {
     const int it = idx % ITEMS, col = idx / ITEMS;
@@ -244,7 +354,8 @@ __global__ __launch_bounds__(kInvThreads) void fft_inverse_kernel(
         v[kx].y = T(0);
       }
     }
-#pragma unroll
+    // x not unrolled: each x takes its n twiddles into scalar registers
+#pragma unroll 1
     for (int x = 0; x < P; ++x) {
       C2 acc;
       acc.x = T(0);
@@ -269,7 +380,7 @@ __global__ __launch_bounds__(kInvThreads) void fft_inverse_kernel(
     acc.y = T(0);
 #pragma unroll
     for (int ky = 0; ky < N; ++ky) {
-      const C2 t = cmulc(b2[it][x][ky][kz], Wm[ky * P + y]);
+      const C2 t = cmulc(b2[it][x][ky][kz], wl[ky * P + y]);
       acc.x += t.x;
       acc.y += t.y;
     }
@@ -279,40 +390,23 @@ __global__ __launch_bounds__(kInvThreads) void fft_inverse_kernel(
   // z: complex -> real on the check-surface points only
   for (int idx = tid; idx < ITEMS * NS; idx += kInvThreads) {
     const int it = idx / NS, s = idx % NS;
-    const int64_t g = g0 + it, row = g / 8;
-    if (row >= n_rows) continue;
-    const int64_t c = row / nvec;
-    const int v = (int)(row - c * nvec);
-    const int32_t box = child[c * 8 + (g % 8)];
+    const int ch = (int)(g0 % 8) + it;
+    int32_t box = cb[0];
+#pragma unroll
+    for (int j = 1; j < 8; ++j)
+      if (ch == j) box = cb[j];
     if (box < 0) continue;
-    const int x = surf_lat[3 * s], y = surf_lat[3 * s + 1], z = surf_lat[3 * s + 2];
+    const int x = sl[3 * s], y = sl[3 * s + 1], z = sl[3 * s + 2];
     T val = b1[it][x][y][0].x;
     T acc = T(0);
 #pragma unroll
-    for (int kz = 1; kz < H; ++kz) acc += cmulc(b1[it][x][y][kz], Wm[kz * P + z]).x;
+    for (int kz = 1; kz < H; ++kz) acc += cmulc(b1[it][x][y][kz], wl[kz * P + z]).x;
     val += T(2) * acc;
-    out[((int64_t)box * nvec + v) * NS + s] = scale * (double)val;
+    out[((int64_t)box * nvec + v0) * NS + s] = scale * (double)val;
   }
 }
 
 // ---- Hadamard products on MFMA ---------------------------------------------
-
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-__device__ inline v4f mfma16(float a, float b, v4f c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-__device__ inline v4d mfma16(double a, double b, v4d c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-// accumulator row of element i of lane group g (measured lane layouts)
-__device__ inline int out_row(float, int g, int i) { return 4 * g + i; }
-__device__ inline int out_row(double, int g, int i) { return g + 4 * i; }
-
-template <typename T> struct V4T;
-template <> struct V4T<float> { using type = v4f; };
-template <> struct V4T<double> { using type = v4d; };
 
 constexpr int kHadThreads = 256;
 
@@ -580,7 +674,7 @@ hipError_t fwd_launch(const double* M, const int32_t* child, int64_t n_rows, int
   using C2 = typename C2T<T>::type;
   constexpr int IT = FftCfg<T, P>::items, TH = FftCfg<T, P>::threads;
   static const int64_t resident = resident_wgs(fft_forward_kernel<T, P>, TH);
-  if (resident < 1) return hipErrorInvalidValue;
+  if (resident < 1 || n_rows >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
   // enough persistent workgroups to fill the device once, each taking an
   // equal number of item groups; a multiple of 8 for the XCD numbering
   const int64_t n_groups = (n_rows * 8 + IT - 1) / IT;
@@ -596,7 +690,7 @@ template <typename T, int P> struct InvItems {
   static constexpr int bytes = sizeof(T) * 2;
   static constexpr int per = P * (2 * P - 1) * P * bytes + P * P * P * bytes;
   static constexpr int raw = 49152 / per;
-  static constexpr int value = raw >= 16 ? 16 : raw >= 8 ? 8 : raw >= 4 ? 4 : raw >= 2 ? 2 : 1;
+  static constexpr int value = raw >= 8 ? 8 : raw >= 4 ? 4 : raw >= 2 ? 2 : 1;
 };
 
 template <typename T, int P>
@@ -605,6 +699,7 @@ hipError_t inv_launch(const void* Phat, const int32_t* child, int64_t n_rows, in
                       hipStream_t s) {
   using C2 = typename C2T<T>::type;
   constexpr int IT = InvItems<T, P>::value;
+  if (n_rows >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)(8 * (((n_rows * 8 + IT - 1) / IT + 7) / 8));
   fft_inverse_kernel<T, P, IT><<<grid, kInvThreads, 0, s>>>((const C2*)Phat, child, n_rows, nvec,
                                                           surf_lat, (const C2*)wm, scale, out);
