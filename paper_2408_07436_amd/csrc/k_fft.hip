@@ -540,21 +540,37 @@ constexpr int kHadStage = (kHadSrcMax * 4 + kHadThreads - 1) / kHadThreads;
 __global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_kernel(
     const float2* __restrict__ Khat, const float* __restrict__ Qhat,
     const int32_t* __restrict__ blk_tgt, const int32_t* __restrict__ blk_src,
-    const int32_t* __restrict__ blk_list, const uint32_t* __restrict__ slots, int64_t n_items,
-    int nvec, int64_t n_rows, int items_per_wg, int n_groups, int64_t total_wgs,
-    float* __restrict__ Phat) {
+    const int32_t* __restrict__ blk_list, const uint32_t* __restrict__ slots, int n_items,
+    int nvec, int64_t n_rows, int64_t total_items, int64_t n_wgs, float* __restrict__ Phat) {
   constexpr int kRow = kHadRowBytes / 16;  // LDS row stride in float4: 16 reals + padding
   __shared__ float4 As[2][kHadSrcMax * kRow + 1];  // + one discard entry
   const int64_t b = blockIdx.x;
-  const int64_t per_xcd = (total_wgs + 7) / 8;
+  const int64_t per_xcd = gridDim.x / 8;  // grid: a multiple of 8
   const int64_t logical = (b % 8) * per_xcd + b / 8;  // consecutive work per XCD
-  if (logical >= total_wgs) return;
-  const int64_t f = logical / n_groups;
-  const int item0 = (int)((logical % n_groups) * items_per_wg);
-  const int item1 = (int)min((int64_t)item0 + items_per_wg, n_items);
+  if (logical >= n_wgs) return;
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int rl = lane % 16, g = lane / 16;
+  const int tr0 = wave * 16;  // this wave's tile of the block's targets
+  const uint32_t row_bytes = 64u * (uint32_t)nvec;  // one cluster's rows
+  // staging registers: four 16-byte pieces per thread (216 rows x 4 pieces
+  // over 256 threads), named rather than an array so they stay in VGPRs;
+  // piece k is row (tid + 256 k) / 4, quarter tid % 4
+  static_assert(kHadStage == 4, "staging pieces per thread");
+  const uint32_t part_bytes = 16u * (uint32_t)(tid & 3);
+  float4 stg0, stg1, stg2, stg3;
+  uint32_t sl0 = 0, sl1 = 0, sl2 = 0, sl3 = 0;
+  uint32_t w[13];  // 26 LDS byte offsets (16 bits each) of the lane's target
+  int buf = 0;
+  // Persistent workgroups: this one takes an equal run [q0, q1) of the
+  // frequency-major (frequency, block, vector) items, in segments of one
+  // frequency each (at most a few per run).
+  const int64_t q0 = logical * total_items / n_wgs, q1 = (logical + 1) * total_items / n_wgs;
+  for (int64_t seg = q0; seg < q1;) {
+  const int64_t f = seg / n_items;
+  const int item0 = (int)(seg - f * n_items);
+  const int item1 = (int)(min(q1, (f + 1) * n_items) - f * n_items);
+  seg = f * n_items + item1;
   // B operand: lane (n, g) multiplies inputs 2g, 2g + 1 (real, imaginary
   // parts) into output n / 2, real part for even n and imaginary for odd n
   float4 B[26];
@@ -568,17 +584,6 @@ __global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_kernel(
   // and products, addressed with 32-bit byte offsets from these bases
   const char* qf = reinterpret_cast<const char*>(Qhat + f * (n_rows + nvec) * 16);
   char* pf = reinterpret_cast<char*>(Phat + f * n_rows * 16);
-  const int tr0 = wave * 16;  // this wave's tile of the block's targets
-  const uint32_t row_bytes = 64u * (uint32_t)nvec;  // one cluster's rows
-  // staging registers: four 16-byte pieces per thread (216 rows x 4 pieces
-  // over 256 threads), named rather than an array so they stay in VGPRs;
-  // piece k is row (tid + 256 k) / 4, quarter tid % 4
-  static_assert(kHadStage == 4, "staging pieces per thread");
-  const uint32_t part_bytes = 16u * (uint32_t)(tid & 3);
-  float4 stg0, stg1, stg2, stg3;
-  uint32_t sl0 = 0, sl1 = 0, sl2 = 0, sl3 = 0;
-  uint32_t w[13];  // 26 LDS byte offsets (16 bits each) of the lane's target
-  int buf = 0;
   // (block, vector) of the next item to load, and of the item whose rows
   // sit in the staging registers
   int lblk = item0 / nvec, lv = item0 - lblk * nvec;
@@ -597,7 +602,6 @@ __global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_kernel(
     }
     if (it < item1) {
       const int s0 = blk_src[lblk], ns = blk_src[lblk + 1] - s0;
-      const int t0 = blk_tgt[lblk], nt = blk_tgt[lblk + 1] - t0;
       const int32_t* lst = blk_list + s0;
       const uint32_t vb = (uint32_t)lv * 64u + part_bytes;
       auto piece = [&](int k, float4& st, uint32_t& sl) __attribute__((always_inline)) {
@@ -653,6 +657,7 @@ __global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_kernel(
       for (int i = 0; i < 4; ++i)
         if (tr0 + 4 * g + i < nt) *reinterpret_cast<float*>(pf + o0 + i * row_bytes) = acc0[i] + acc1[i];
     }
+  }
   }
 }
 
@@ -771,14 +776,17 @@ hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
         total, (double*)Phat);
     return hipGetLastError();
   }
+  // persistent workgroups, one device-full, each taking an equal run of the
+  // frequency-major items (the B operand is loaded once per frequency in a run)
+  static const int64_t resident = resident_wgs(hadamard_block_kernel, kHadThreads);
   const int64_t n_items = n_blocks * nvec;
-  const int ipw = n_items >= 64 ? 8 : n_items >= 16 ? 4 : 1;
-  const int n_groups = (int)((n_items + ipw - 1) / ipw);
-  const int64_t total = (int64_t)F * n_groups;
-  const unsigned grid = (unsigned)(8 * ((total + 7) / 8));
+  if (resident < 8 || n_items >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+  const int64_t total = (int64_t)F * n_items;
+  const int64_t n_wgs = min(total, resident / 8 * 8);
+  const unsigned grid = (unsigned)(8 * ((n_wgs + 7) / 8));
   hadamard_block_kernel<<<grid, kHadThreads, 0, stream>>>(
-      (const float2*)Khat, (const float*)Qhat, blk_tgt, blk_src, blk_list, slots, n_items, nvec,
-      n_rows, ipw, n_groups, total, (float*)Phat);
+      (const float2*)Khat, (const float*)Qhat, blk_tgt, blk_src, blk_list, slots, (int)n_items,
+      nvec, n_rows, total, n_wgs, (float*)Phat);
   return hipGetLastError();
 }
 
