@@ -201,6 +201,8 @@ def run_blas(K, torch, steps, warmup):
             out["kt_mean"] = round(float(kt.mean()), 2)
         q = torch.as_tensor(w.q, dtype=dt, device="cuda")
         phi = torch.empty((w.nvec, w.n), dtype=dt, device="cuda")
+        tune_ms = f.autotune(q, phi, reps=2)
+        tuning = f.tuning()
         for _ in range(warmup):
             f.evaluate(q, phi)
         torch.cuda.synchronize()
@@ -226,9 +228,12 @@ def run_blas(K, torch, steps, warmup):
                      "fused_kernel_ms": round(tm["m2l_main"], 3), "ms_per_step": round(ms_step, 3),
                      "fused_tflops": round(flops / main_s / 1e12, 2),
                      "fused_frac_of_peak": round(flops / main_s / peak, 4),
-                     "rel_err_vs_fp64_run": rel, "setup_s": round(setup_s, 2)}
+                     "rel_err_vs_fp64_run": rel, "setup_s": round(setup_s, 2),
+                     "autotuned_tile_boxes": tuning["blas_tile"],
+                     "autotune_best_ms": round(tune_ms, 3)}
         log(f"  blas {prec}: step {ms_step:.2f} ms, m2l {tm['m2l']:.2f} ms (fused {tm['m2l_main']:.2f}), "
-            f"{flops / main_s / 1e12:.1f} TFLOP/s, rel vs fp64 {rel:.2e}")
+            f"{flops / main_s / 1e12:.1f} TFLOP/s, rel vs fp64 {rel:.2e}, autotuned tile "
+            f"{tuning['blas_tile']} boxes")
         del f, q, phi
         torch.cuda.empty_cache()
     out["algorithmic_gflop"] = round(flops / 1e9, 1)
@@ -255,8 +260,9 @@ def run_batch(K, torch, launches):
         total_pts += sp["n"]
     setup_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    b = K.Batch(items)
+    b = K.Batch(items, autotune=True, reps=3)
     capture_s = time.perf_counter() - t0
+    kept = sorted({f.tuning()["hadamard"] for f, _, _ in items})
     s = torch.cuda.current_stream()
     for _ in range(5):
         b.launch()
@@ -292,9 +298,11 @@ def run_batch(K, torch, launches):
            "problems_per_s": round(len(items) / (p50 * 1e-3), 1),
            "points_per_s": round(total_pts / (p50 * 1e-3), 1),
            "eager_sequential_ms": round(eager_ms, 3),
-           "setup_s": round(setup_s, 2), "capture_s": round(capture_s, 2),
+           "setup_s": round(setup_s, 2), "autotune_and_capture_s": round(capture_s, 2),
+           "autotuned_hadamard_form": kept, "autotune_best_ms": round(b.best_ms, 3),
            "precision": "fp32 M2L, fp64 local accumulation", "m2l": "fft"}
-    log(f"  batch: p50 {p50:.2f} ms, p99 {out['latency_ms_p99']:.2f} ms, eager sequential {eager_ms:.2f} ms")
+    log(f"  batch: p50 {p50:.2f} ms, p99 {out['latency_ms_p99']:.2f} ms, eager sequential {eager_ms:.2f} ms, "
+        f"autotuned Hadamard form {kept}")
     del items
     torch.cuda.empty_cache()
     return out

@@ -208,6 +208,46 @@ kifmm_status kifmm_timings(const kifmm_handle* h, double* ms, int32_t cap);
  * halos.  cap >= 4. */
 kifmm_status kifmm_m2l_counts(const kifmm_handle* h, int32_t level, int64_t* counts, int32_t cap);
 
+/* ---- autotuning ---------------------------------------------------------- */
+
+/* Knobs of the evaluate's schedule and tile shapes (int32; 0 = built-in
+ * default).  No setting changes results: every one gives bit-identical
+ * potentials.
+ *   [KIFMM_TUNE_BLAS_TILE] BLAS / dense M2L: target boxes per tile.  A tile's
+ *       MFMA columns are its boxes x n_vec, at most 128; larger values are
+ *       clamped to 128 / n_vec.  0 = 128 / n_vec.  Range 0..128.
+ *   [KIFMM_TUNE_SCHEDULE] FFT-M2L evaluates that are not timed and not under
+ *       stream capture: 0 = the FMM passes as a dependency graph over several
+ *       streams (the M2L of each level beside the others), 1 = every pass
+ *       back to back on the caller's stream.
+ *   [KIFMM_TUNE_HADAMARD] FP32 FFT-M2L Hadamard: 0 = persistent workgroups,
+ *       one device-full, each over one contiguous run of the frequency-major
+ *       (frequency, block, vector) items; 1 = one workgroup per unit of 8
+ *       consecutive items. */
+enum {
+  KIFMM_TUNE_BLAS_TILE = 0,
+  KIFMM_TUNE_SCHEDULE = 1,
+  KIFMM_TUNE_HADAMARD = 2,
+  KIFMM_TUNE_COUNT = 3
+};
+/* Current knob values into knobs[0 .. KIFMM_TUNE_COUNT); cap >= KIFMM_TUNE_COUNT.
+ * Host only. */
+kifmm_status kifmm_get_tuning(const kifmm_handle* h, int32_t* knobs, int32_t cap);
+/* Set the first n knobs (n <= KIFMM_TUNE_COUNT); EINVAL (nothing changed) if a
+ * value is out of range.  Host only; takes effect at the next evaluate. */
+kifmm_status kifmm_set_tuning(kifmm_handle* h, const int32_t* knobs, int32_t n);
+/* Autotuner: times every candidate setting that applies to the handle's M2L
+ * form and precision (FFT: schedule x Hadamard form for FP32, schedule for
+ * FP64; BLAS / dense: four tile widths) with one warm-up and `reps` (1..100)
+ * evaluates of the given charges (arguments as in kifmm_evaluate), keeps
+ * the setting with the smallest median evaluate time, and writes that time
+ * to *best_ms (if not NULL).  phi_dev holds the last evaluate's potentials.
+ * Runs untimed whatever kifmm_set_timing says; synchronises hip_stream.
+ * EINVAL: bad arguments or a capturing stream; ESTATE: as evaluate. */
+kifmm_status kifmm_autotune(kifmm_handle* h, const void* q_dev, int64_t ldq, int32_t n_vec,
+                            void* phi_dev, int64_t ldphi, void* hip_stream, int32_t reps,
+                            double* best_ms);
+
 /* ---- batches of independent problems ------------------------------------ */
 
 /* A batch replays the evaluates of n independent, precomputed handles with
@@ -226,6 +266,20 @@ typedef struct kifmm_batch kifmm_batch;
 kifmm_status kifmm_batch_create(kifmm_handle* const* handles, int32_t n, const void* const* q_dev,
                                 const int64_t* ldq, const int32_t* n_vec, void* const* phi_dev,
                                 const int64_t* ldphi, void* hip_stream, kifmm_batch** out);
+/* Autotuned batch: for each candidate knob setting that applies to the
+ * batch's handles (FP32 FFT-M2L: both Hadamard forms; BLAS / dense: tile
+ * widths (128 / n_vec[i]) >> k, k = 0..3), sets the knobs of every handle,
+ * builds the batch as kifmm_batch_create does, times one warm-up and `reps`
+ * (1..100) launches on hip_stream, and destroys it; then builds the batch
+ * with the fastest setting into *out, leaves that setting in the handles and
+ * writes its median launch time to *best_ms (if not NULL).  Arguments and
+ * errors as kifmm_batch_create; EINVAL also for reps out of range.  On an
+ * error every handle's knobs are restored. */
+kifmm_status kifmm_batch_autotune(kifmm_handle* const* handles, int32_t n,
+                                  const void* const* q_dev, const int64_t* ldq,
+                                  const int32_t* n_vec, void* const* phi_dev,
+                                  const int64_t* ldphi, void* hip_stream, int32_t reps,
+                                  kifmm_batch** out, double* best_ms);
 /* Launch the recorded graph on hip_stream (asynchronous). */
 kifmm_status kifmm_batch_launch(kifmm_batch* batch, void* hip_stream);
 /* Destroy the graph and its capture streams (not the handles). */

@@ -25,9 +25,11 @@ EXPORTS = [
     "kifmm_config_default", "kifmm_create", "kifmm_set_points", "kifmm_precompute",
     "kifmm_evaluate", "kifmm_destroy", "kifmm_last_error", "kifmm_num_boxes", "kifmm_box_keys",
     "kifmm_point_perm", "kifmm_interactions", "kifmm_near", "kifmm_operator", "kifmm_stage",
-    "kifmm_set_timing", "kifmm_timings", "kifmm_m2l_counts", "kifmm_batch_create",
+    "kifmm_set_timing", "kifmm_timings", "kifmm_m2l_counts", "kifmm_get_tuning",
+    "kifmm_set_tuning", "kifmm_autotune", "kifmm_batch_create", "kifmm_batch_autotune",
     "kifmm_batch_launch", "kifmm_batch_destroy",
 ]
+TUNE_KNOBS = ("blas_tile", "schedule", "hadamard")
 
 
 class KifmmError(RuntimeError):
@@ -84,9 +86,15 @@ def lib() -> ctypes.CDLL:
     L.kifmm_set_timing.argtypes = [vp, i32]
     L.kifmm_timings.argtypes = [vp, dp, i32]
     L.kifmm_m2l_counts.argtypes = [vp, i32, ctypes.POINTER(i64), i32]
+    L.kifmm_get_tuning.argtypes = [vp, ctypes.POINTER(i32), i32]
+    L.kifmm_set_tuning.argtypes = [vp, ctypes.POINTER(i32), i32]
+    L.kifmm_autotune.argtypes = [vp, vp, i64, i32, vp, i64, vp, i32, dp]
     L.kifmm_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(i64),
                                      ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(i64), vp,
                                      ctypes.POINTER(vp)]
+    L.kifmm_batch_autotune.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp),
+                                       ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(vp),
+                                       ctypes.POINTER(i64), vp, i32, ctypes.POINTER(vp), dp]
     L.kifmm_batch_launch.argtypes = [vp, vp]
     L.kifmm_batch_destroy.argtypes = [vp]
     for name in EXPORTS:
@@ -244,6 +252,39 @@ class KiFMM:
                     m2l_first=ms[5], m2l_main=ms[6], m2l_last=ms[7], m2l_levels=int(ms[8]),
                     near_field=ms[9], far_field=ms[10])
 
+    # ---- autotuning -------------------------------------------------------
+    def tuning(self) -> dict:
+        k = np.zeros(len(TUNE_KNOBS), dtype=np.int32)
+        _check(lib().kifmm_get_tuning(self._h, _ptr(k, ctypes.c_int32), len(TUNE_KNOBS)))
+        return {n: int(v) for n, v in zip(TUNE_KNOBS, k)}
+
+    def set_tuning(self, **knobs):
+        cur = self.tuning()
+        for n, v in knobs.items():
+            if n not in cur:
+                raise KeyError(n)
+            cur[n] = int(v)
+        k = np.array([cur[n] for n in TUNE_KNOBS], dtype=np.int32)
+        _check(lib().kifmm_set_tuning(self._h, _ptr(k, ctypes.c_int32), len(TUNE_KNOBS)))
+
+    def autotune(self, q, out=None, stream=None, reps: int = 3) -> float:
+        """Time the candidate knob settings on charges ``q`` and keep the fastest; returns its
+        median evaluate time in ms (``out`` receives the potentials)."""
+        import torch
+        if q.dim() == 1:
+            q = q[None]
+        assert q.is_cuda and q.dtype == self.dtype and q.stride(1) == 1
+        nvec = q.shape[0]
+        if out is None:
+            out = torch.empty((nvec, self.n_tgt), dtype=self.dtype, device=q.device)
+        assert out.is_cuda and out.dtype == self.dtype and out.stride(1) == 1
+        s = torch.cuda.current_stream(q.device) if stream is None else stream
+        best = ctypes.c_double(0.0)
+        _check(lib().kifmm_autotune(self._h, q.data_ptr(), q.stride(0), nvec, out.data_ptr(),
+                                    out.stride(0), ctypes.c_void_p(s.cuda_stream), reps,
+                                    ctypes.byref(best)))
+        return best.value
+
     def m2l_counts(self, level: int) -> dict:
         c = np.zeros(4, dtype=np.int64)
         _check(lib().kifmm_m2l_counts(self._h, level, _ptr(c, ctypes.c_int64), 4))
@@ -257,7 +298,10 @@ class Batch:
     and phi (nvec, n_tgt) that stay alive as long as the batch.
     """
 
-    def __init__(self, items, stream=None):
+    def __init__(self, items, stream=None, autotune: bool = False, reps: int = 3):
+        """With ``autotune`` the knob settings that apply to the handles are timed as whole
+        batches (kifmm_batch_autotune) and the fastest is kept; ``best_ms`` is its median
+        launch time (None without autotuning)."""
         import torch
         n = len(items)
         self._items = items
@@ -271,8 +315,16 @@ class Batch:
             assert q.is_cuda and p.is_cuda and q.dtype == f.dtype and p.dtype == f.dtype
         s = torch.cuda.current_stream() if stream is None else stream
         b = ctypes.c_void_p()
-        _check(lib().kifmm_batch_create(hs, n, qs, ldq, nv, ps, ldp, ctypes.c_void_p(s.cuda_stream),
-                                        ctypes.byref(b)))
+        self.best_ms = None
+        if autotune:
+            best = ctypes.c_double(0.0)
+            _check(lib().kifmm_batch_autotune(hs, n, qs, ldq, nv, ps, ldp,
+                                              ctypes.c_void_p(s.cuda_stream), reps, ctypes.byref(b),
+                                              ctypes.byref(best)))
+            self.best_ms = best.value
+        else:
+            _check(lib().kifmm_batch_create(hs, n, qs, ldq, nv, ps, ldp,
+                                            ctypes.c_void_p(s.cuda_stream), ctypes.byref(b)))
         self._b = b
 
     def launch(self, stream=None):

@@ -25,6 +25,8 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
                              int64_t ldphi, hipStream_t s);
 kifmm_status device_stage(kifmm_handle* h, int level, const void* in, void* out, int nvec,
                           hipStream_t s);
+kifmm_status device_autotune(kifmm_handle* h, const void* q, int64_t ldq, int nvec, void* phi,
+                             int64_t ldphi, hipStream_t s, int reps, double* best_ms);
 
 }  // namespace kifmm
 
@@ -289,6 +291,37 @@ kifmm_status kifmm_timings(const kifmm_handle* h, double* ms, int32_t cap) {
   if (cap < 5) return fail(KIFMM_EINVAL, "capacity too small");
   for (int i = 0; i < cap && i < 11; ++i) ms[i] = h->timings[i];
   return KIFMM_OK;
+}
+
+kifmm_status kifmm_get_tuning(const kifmm_handle* h, int32_t* knobs, int32_t cap) {
+  if (!h || !knobs) return fail(KIFMM_EINVAL, "null argument");
+  if (cap < KIFMM_TUNE_COUNT) return fail(KIFMM_EINVAL, "capacity too small");
+  for (int i = 0; i < KIFMM_TUNE_COUNT; ++i) knobs[i] = h->tune[i];
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_set_tuning(kifmm_handle* h, const int32_t* knobs, int32_t n) {
+  if (!h || !knobs) return fail(KIFMM_EINVAL, "null argument");
+  if (n < 0 || n > KIFMM_TUNE_COUNT) return fail(KIFMM_EINVAL, "bad knob count");
+  static const int32_t hi[KIFMM_TUNE_COUNT] = {128, 1, 1};
+  for (int i = 0; i < n; ++i)
+    if (knobs[i] < 0 || knobs[i] > hi[i]) return fail(KIFMM_EINVAL, "knob value out of range");
+  for (int i = 0; i < n; ++i) h->tune[i] = knobs[i];
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_autotune(kifmm_handle* h, const void* q_dev, int64_t ldq, int32_t n_vec,
+                            void* phi_dev, int64_t ldphi, void* hip_stream, int32_t reps,
+                            double* best_ms) {
+  if (!h) return fail(KIFMM_EINVAL, "null handle");
+  if (!h->has_points) return fail(KIFMM_ESTATE, "autotune before set_points");
+  if (!h->op.ready) return fail(KIFMM_ESTATE, "autotune before precompute");
+  if (!q_dev || !phi_dev) return fail(KIFMM_EINVAL, "null buffer");
+  if (n_vec < 1 || ldq < h->tree.n_src || ldphi < h->tree.n_tgt)
+    return fail(KIFMM_EINVAL, "bad n_vec or leading dimension");
+  if (reps < 1 || reps > 100) return fail(KIFMM_EINVAL, "reps out of range");
+  return kifmm::device_autotune(h, q_dev, ldq, n_vec, phi_dev, ldphi, (hipStream_t)hip_stream,
+                                reps, best_ms);
 }
 
 kifmm_status kifmm_m2l_counts(const kifmm_handle* h, int32_t level, int64_t* counts, int32_t cap) {

@@ -1,4 +1,6 @@
 // Batches of independent kiFMM problems replayed as one HIP graph.
+#include <algorithm>
+#include <array>
 #include <set>
 #include <vector>
 
@@ -123,6 +125,97 @@ kifmm_status kifmm_batch_create(kifmm_handle* const* handles, int32_t n, const v
     return fail(KIFMM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
   }
   *out = b;
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_batch_autotune(kifmm_handle* const* handles, int32_t n,
+                                  const void* const* q_dev, const int64_t* ldq,
+                                  const int32_t* n_vec, void* const* phi_dev,
+                                  const int64_t* ldphi, void* hip_stream, int32_t reps,
+                                  kifmm_batch** out, double* best_ms) {
+  if (!handles || !n_vec || !out || n < 1) return fail(KIFMM_EINVAL, "bad batch arguments");
+  if (reps < 1 || reps > 100) return fail(KIFMM_EINVAL, "reps out of range");
+  *out = nullptr;
+  for (int i = 0; i < n; ++i)
+    if (!handles[i] || n_vec[i] < 1) return fail(KIFMM_EINVAL, "bad batch entry");
+  bool fft32 = false, tiled = false;
+  for (int i = 0; i < n; ++i) {
+    const kifmm_config& c = handles[i]->cfg;
+    if (c.m2l == KIFMM_M2L_FFT && c.prec != KIFMM_FP64) fft32 = true;
+    if (c.m2l != KIFMM_M2L_FFT) tiled = true;
+  }
+  // candidates: (Hadamard form, BLAS tile shift): the tile width of problem
+  // i is (128 / n_vec[i]) >> shift; the schedule knob does not apply under
+  // capture
+  std::vector<std::array<int, 2>> cand;
+  for (int form = 0; form < (fft32 ? 2 : 1); ++form)
+    for (int shift = 0; shift < (tiled ? 4 : 1); ++shift) cand.push_back({form, shift});
+  using Knobs = std::array<int32_t, KIFMM_TUNE_COUNT>;
+  std::vector<Knobs> saved((size_t)n);
+  for (int i = 0; i < n; ++i) std::copy(handles[i]->tune, handles[i]->tune + KIFMM_TUNE_COUNT, saved[i].begin());
+  auto apply = [&](const std::array<int, 2>& c) {
+    for (int i = 0; i < n; ++i) {
+      kifmm_handle* h = handles[i];
+      std::copy(saved[i].begin(), saved[i].end(), h->tune);
+      if (h->cfg.m2l == KIFMM_M2L_FFT) {
+        if (h->cfg.prec != KIFMM_FP64) h->tune[KIFMM_TUNE_HADAMARD] = c[0];
+      } else {
+        h->tune[KIFMM_TUNE_BLAS_TILE] = std::max(1, (128 / n_vec[i]) >> c[1]);
+      }
+    }
+  };
+  auto restore = [&]() {
+    for (int i = 0; i < n; ++i) std::copy(saved[i].begin(), saved[i].end(), handles[i]->tune);
+  };
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  auto cleanup = [&]() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  };
+  if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) {
+    cleanup();
+    return fail(KIFMM_EDEVICE, "event creation failed");
+  }
+  double best = 0.0;
+  size_t chosen = 0;
+  for (size_t k = 0; k < cand.size(); ++k) {
+    apply(cand[k]);
+    kifmm_batch* b = nullptr;
+    kifmm_status st = kifmm_batch_create(handles, n, q_dev, ldq, n_vec, phi_dev, ldphi, hip_stream, &b);
+    std::vector<float> t((size_t)reps);
+    hipError_t e = hipSuccess;
+    if (st == KIFMM_OK) {
+      e = hipGraphLaunch(b->exec, s);  // warm-up
+      for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        e = hipEventRecord(ev[0], s);
+        if (e == hipSuccess) e = hipGraphLaunch(b->exec, s);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t[(size_t)r], ev[0], ev[1]);
+      }
+      kifmm_batch_destroy(b);
+    }
+    if (st != KIFMM_OK || e != hipSuccess) {
+      restore();
+      cleanup();
+      return st != KIFMM_OK ? st : fail(KIFMM_EDEVICE, std::string("batch autotune: ") + hipGetErrorString(e));
+    }
+    std::sort(t.begin(), t.end());
+    const double med = t[(size_t)reps / 2];
+    if (k == 0 || med < best) {
+      best = med;
+      chosen = k;
+    }
+  }
+  cleanup();
+  apply(cand[chosen]);
+  const kifmm_status st = kifmm_batch_create(handles, n, q_dev, ldq, n_vec, phi_dev, ldphi, hip_stream, out);
+  if (st != KIFMM_OK) {
+    restore();
+    return st;
+  }
+  if (best_ms) *best_ms = best;
   return KIFMM_OK;
 }
 

@@ -1,6 +1,7 @@
 // Device state and the evaluate pipeline of the kiFMM (Section 2: upward
 // pass P2M + M2M, downward pass M2L + L2L per level, then L2P + P2P).
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -497,7 +498,8 @@ kifmm_status upload_all(kifmm_handle* h) {
 kifmm_status ensure_work(kifmm_handle* h, int nvec) {
   DeviceState* d = h->dev;
   if (h->cfg.m2l != KIFMM_M2L_FFT) {
-    const int TB = std::max(1, 128 / nvec);
+    const int tb_max = std::max(1, 128 / nvec), knob = h->tune[KIFMM_TUNE_BLAS_TILE];
+    const int TB = knob > 0 ? std::min(knob, tb_max) : tb_max;
     if (TB != d->tile_tb) KIFMM_TRY(build_blas_tiles(h, d, TB));
   }
   if (nvec <= d->nvec_cap) return KIFMM_OK;
@@ -587,7 +589,8 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
                                     d->twiddle, D.Qhat, s));
     if (mark) KIFMM_HIP(hipEventRecord(mark[1], s));
     KIFMM_LAUNCH(launch_hadamard(d->fp64, op.F, d->khat, D.Qhat, D.halo, D.hb_n, D.hb_tgt,
-                                 D.hb_src, D.hb_list, D.hb_slots, nc, nvec, D.Phat, s));
+                                 D.hb_src, D.hb_list, D.hb_slots, nc, nvec,
+                                 h->tune[KIFMM_TUNE_HADAMARD] == 1, D.Phat, s));
     if (mark) KIFMM_HIP(hipEventRecord(mark[2], s));
     const double scale = 1.0 / ((double)op.n * op.n * op.n * D.w);  // 1 / (n^3 w)
     KIFMM_LAUNCH(launch_fft_inverse(op.p, d->fp64, D.Phat, child, nc, nvec, d->surf_lat,
@@ -700,7 +703,8 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   KIFMM_HIP(hipStreamIsCapturing(s, &cap));
   const bool fork = fft && cap == hipStreamCaptureStatusNone;
-  const bool graph = fork && !timed, phased = fork && timed;
+  const bool graph = fork && !timed && h->tune[KIFMM_TUNE_SCHEDULE] == 0;
+  const bool phased = fork && timed;
   const DevLevel& leaf = d->lv[depth];
   const double ar_leaf = op.ao * 0.5 * leaf.w;
   auto leaf_pass = [&](int mode, hipStream_t st) -> kifmm_status {
@@ -883,6 +887,77 @@ kifmm_status device_stage(kifmm_handle* h, int level, const void* in, void* out,
     for (int k = 0; k < 3; ++k) h->timings[5 + k] = ph[k];
     h->timings[8] = 1;
   }
+  return KIFMM_OK;
+}
+
+// Autotuner: each candidate knob setting that applies to the handle's M2L
+// form and precision is timed with one warm-up and `reps` untimed evaluates
+// (HIP events on s); the setting with the smallest median is kept.
+kifmm_status device_autotune(kifmm_handle* h, const void* q, int64_t ldq, int nvec, void* phi,
+                             int64_t ldphi, hipStream_t s, int reps, double* best_ms) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  KIFMM_HIP(hipStreamIsCapturing(s, &cap));
+  if (cap != hipStreamCaptureStatusNone) return fail(KIFMM_EINVAL, "autotune on a capturing stream");
+  using Knobs = std::array<int32_t, KIFMM_TUNE_COUNT>;
+  Knobs base;
+  std::copy(h->tune, h->tune + KIFMM_TUNE_COUNT, base.begin());
+  std::vector<Knobs> cand;
+  if (h->cfg.m2l == KIFMM_M2L_FFT) {
+    const int forms = h->cfg.prec == KIFMM_FP64 ? 1 : 2;  // FP64 uses the gather form only
+    for (int sched = 0; sched < 2; ++sched)
+      for (int form = 0; form < forms; ++form) {
+        Knobs c = base;
+        c[KIFMM_TUNE_SCHEDULE] = sched;
+        c[KIFMM_TUNE_HADAMARD] = form;
+        cand.push_back(c);
+      }
+  } else {
+    const int tb_max = std::max(1, 128 / nvec);
+    int last = -1;
+    for (int k = 0; k < 4; ++k) {
+      const int tb = std::max(1, tb_max >> k);
+      if (tb == last) continue;
+      last = tb;
+      Knobs c = base;
+      c[KIFMM_TUNE_BLAS_TILE] = tb;
+      cand.push_back(c);
+    }
+  }
+  struct Restore {  // events and the timing switch, on every exit
+    kifmm_handle* h;
+    bool timing;
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Restore() {
+      h->timing = timing;
+      for (hipEvent_t ev : e)
+        if (ev) (void)hipEventDestroy(ev);
+    }
+  } guard{h, h->timing};
+  h->timing = false;
+  KIFMM_HIP(hipEventCreate(&guard.e[0]));
+  KIFMM_HIP(hipEventCreate(&guard.e[1]));
+  double best = 0.0;
+  Knobs chosen = base;
+  for (size_t i = 0; i < cand.size(); ++i) {
+    std::copy(cand[i].begin(), cand[i].end(), h->tune);
+    KIFMM_TRY(device_evaluate(h, q, ldq, nvec, phi, ldphi, s));
+    std::vector<float> t((size_t)reps);
+    for (int r = 0; r < reps; ++r) {
+      KIFMM_HIP(hipEventRecord(guard.e[0], s));
+      KIFMM_TRY(device_evaluate(h, q, ldq, nvec, phi, ldphi, s));
+      KIFMM_HIP(hipEventRecord(guard.e[1], s));
+      KIFMM_HIP(hipEventSynchronize(guard.e[1]));
+      KIFMM_HIP(hipEventElapsedTime(&t[(size_t)r], guard.e[0], guard.e[1]));
+    }
+    std::sort(t.begin(), t.end());
+    const double med = t[(size_t)reps / 2];
+    if (i == 0 || med < best) {
+      best = med;
+      chosen = cand[i];
+    }
+  }
+  std::copy(chosen.begin(), chosen.end(), h->tune);
+  if (best_ms) *best_ms = best;
   return KIFMM_OK;
 }
 

@@ -121,4 +121,5 @@ struct kifmm_handle {
   kifmm::DeviceState* dev = nullptr;
   bool timing = false;
   double timings[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  int32_t tune[KIFMM_TUNE_COUNT] = {0, 0, 0};  // autotuning knobs (kifmm.h)
 };

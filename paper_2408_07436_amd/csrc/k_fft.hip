@@ -541,7 +541,8 @@ __global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_kernel(
     const float2* __restrict__ Khat, const float* __restrict__ Qhat,
     const int32_t* __restrict__ blk_tgt, const int32_t* __restrict__ blk_src,
     const int32_t* __restrict__ blk_list, const uint32_t* __restrict__ slots, int n_items,
-    int nvec, int64_t n_rows, int64_t total_items, int64_t n_wgs, float* __restrict__ Phat) {
+    int nvec, int64_t n_rows, int64_t total_items, int64_t unit_len, int64_t n_units,
+    int64_t n_wgs, float* __restrict__ Phat) {
   constexpr int kRow = kHadRowBytes / 16;  // LDS row stride in float4: 16 reals + padding
   __shared__ float4 As[2][kHadSrcMax * kRow + 1];  // + one discard entry
   const int64_t b = blockIdx.x;
@@ -562,10 +563,12 @@ __global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_kernel(
   uint32_t sl0 = 0, sl1 = 0, sl2 = 0, sl3 = 0;
   uint32_t w[13];  // 26 LDS byte offsets (16 bits each) of the lane's target
   int buf = 0;
-  // Persistent workgroups: this one takes an equal run [q0, q1) of the
-  // frequency-major (frequency, block, vector) items, in segments of one
-  // frequency each (at most a few per run).
-  const int64_t q0 = logical * total_items / n_wgs, q1 = (logical + 1) * total_items / n_wgs;
+  // Units of unit_len consecutive frequency-major (frequency, block, vector)
+  // items: this workgroup takes units logical, logical + n_wgs, ..., each in
+  // segments of one frequency.  Persistent form: one unit per workgroup, a
+  // device-full of workgroups; unit form: 8-item units, one per workgroup.
+  for (int64_t unit = logical; unit < n_units; unit += n_wgs) {
+  const int64_t q0 = unit * unit_len, q1 = min(q0 + unit_len, total_items);
   for (int64_t seg = q0; seg < q1;) {
   const int64_t f = seg / n_items;
   const int item0 = (int)(seg - f * n_items);
@@ -657,6 +660,7 @@ __global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_kernel(
       for (int i = 0; i < 4; ++i)
         if (tr0 + 4 * g + i < nt) *reinterpret_cast<float*>(pf + o0 + i * row_bytes) = acc0[i] + acc1[i];
     }
+  }
   }
   }
 }
@@ -758,7 +762,8 @@ hipError_t launch_fft_inverse(int p, bool fp64, const void* Phat, const int32_t*
 hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
                            const int32_t* halo, int64_t n_blocks, const int32_t* blk_tgt,
                            const int32_t* blk_src, const int32_t* blk_list, const uint32_t* slots,
-                           int64_t n_clusters, int nvec, void* Phat, hipStream_t stream) {
+                           int64_t n_clusters, int nvec, bool units, void* Phat,
+                           hipStream_t stream) {
   const int64_t n_rows = n_clusters * nvec;
   if (n_rows == 0) return hipSuccess;
   // 24-bit cluster indices and 32-bit byte offsets within one frequency
@@ -776,17 +781,27 @@ hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
         total, (double*)Phat);
     return hipGetLastError();
   }
-  // persistent workgroups, one device-full, each taking an equal run of the
-  // frequency-major items (the B operand is loaded once per frequency in a run)
+  // persistent form: a device-full of workgroups, each taking one run of
+  // the frequency-major items (the B operand is loaded once per frequency in
+  // a run); unit form: one workgroup per 8 items
   static const int64_t resident = resident_wgs(hadamard_block_kernel, kHadThreads);
   const int64_t n_items = n_blocks * nvec;
   if (resident < 8 || n_items >= (int64_t(1) << 31)) return hipErrorInvalidValue;
   const int64_t total = (int64_t)F * n_items;
-  const int64_t n_wgs = min(total, resident / 8 * 8);
+  int64_t unit_len, n_units, n_wgs;
+  if (units) {
+    unit_len = 8;
+    n_units = (total + unit_len - 1) / unit_len;
+    n_wgs = n_units;
+  } else {
+    n_wgs = min(total, resident / 8 * 8);
+    unit_len = (total + n_wgs - 1) / n_wgs;
+    n_units = (total + unit_len - 1) / unit_len;
+  }
   const unsigned grid = (unsigned)(8 * ((n_wgs + 7) / 8));
   hadamard_block_kernel<<<grid, kHadThreads, 0, stream>>>(
       (const float2*)Khat, (const float*)Qhat, blk_tgt, blk_src, blk_list, slots, (int)n_items,
-      nvec, n_rows, total, n_wgs, (float*)Phat);
+      nvec, n_rows, total, unit_len, n_units, n_wgs, (float*)Phat);
   return hipGetLastError();
 }
 

@@ -73,11 +73,14 @@ hipError_t launch_fft_forward(int p, bool fp64, const double* M, const int32_t* 
 // source blocks: block b covers clusters [blk_tgt[b], blk_tgt[b + 1]), its
 // sources are blk_list[blk_src[b] ...] packed as cluster << 8 | slot, and
 // 16-bit entry d of slots[c] (13 words per cluster) is slot(halo[d][c]) *
-// kHadRowBytes.
+// kHadRowBytes.  FP32 work split: units = false gives persistent
+// workgroups over contiguous runs of the frequency-major (frequency, block,
+// vector) items, true one workgroup per unit of 8 items.
 hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
                            const int32_t* halo, int64_t n_blocks, const int32_t* blk_tgt,
                            const int32_t* blk_src, const int32_t* blk_list, const uint32_t* slots,
-                           int64_t n_clusters, int nvec, void* Phat, hipStream_t stream);
+                           int64_t n_clusters, int nvec, bool units, void* Phat,
+                           hipStream_t stream);
 // Inverse: spectra -> check potentials out[box][v][s] = scale * phi (FP64).
 // surf_lat[3 s + k] is lattice coordinate k of surface point s.
 hipError_t launch_fft_inverse(int p, bool fp64, const void* Phat, const int32_t* child,

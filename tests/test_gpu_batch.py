@@ -77,3 +77,38 @@ def test_batch_rejects_repeated_handle():
     with pytest.raises(K.KifmmError) as e:
         K.Batch([(f, qt, phi), (f, qt, phi)])
     assert e.value.code == 1
+
+
+def test_batch_autotune_keeps_results():
+    """The batch autotuner times whole-batch candidates (Hadamard form, tile
+    widths), keeps one, and the kept batch replays the eager results bit for
+    bit (knob settings do not change results)."""
+    items, eager = [], []
+    for i, spec in enumerate(PROBLEMS):
+        f, _, _, qt = build(i, *spec)
+        ref = f.evaluate(qt).clone()
+        items.append((f, qt, torch.full_like(ref, float("nan"))))
+        eager.append(ref)
+    torch.cuda.synchronize()
+    say(f"case: batch autotune over {len(items)} problems")
+    b = K.Batch(items, autotune=True, reps=2)
+    say(f"  kept {[f.tuning() for f, _, _ in items]}, {b.best_ms:.3f} ms")
+    assert b.best_ms > 0.0
+    for i, ((f, _, _), spec) in enumerate(zip(items, PROBLEMS)):
+        t = f.tuning()
+        m2l, prec, nvec = spec[3], spec[4], spec[5]
+        if m2l == "fft":
+            assert t["blas_tile"] == 0
+            assert t["hadamard"] in ((0, 1) if prec != "fp64" else (0,))
+        else:
+            assert t["blas_tile"] in [max(1, (128 // nvec) >> k) for k in range(4)]
+    for rep in range(2):
+        for _, _, phi in items:
+            phi.fill_(float("nan"))
+        b.launch()
+        torch.cuda.synchronize()
+        for i, (_, _, phi) in enumerate(items):
+            assert torch.equal(phi, eager[i]), f"replay {rep} problem {i}"
+    b.close()
+    for i, (f, qt, _) in enumerate(items):
+        assert torch.equal(f.evaluate(qt), eager[i]), f"eager with kept knobs, problem {i}"

@@ -201,3 +201,48 @@ def test_schedules_agree_bitwise(prec):
     e = kernel.rel_l2(a.double().cpu().numpy(), ref)
     say(f"  rel err vs oracle {e:.3e}")
     assert e <= (FP64_GATE if prec == "fp64" else FP32_GATE)
+
+
+@pytest.mark.parametrize("m2l,prec", [("fft", "fp32"), ("fft", "fp64"), ("blas", "fp32")])
+def test_tuning_settings_agree_and_autotune(m2l, prec):
+    """Every knob setting the autotuner tries gives potentials bit-identical to
+    the defaults (schedule, Hadamard work split, BLAS tile width); the
+    autotuner keeps one of them, reports a positive time, and its result
+    still matches the oracle."""
+    pts = workloads.uniform_cube(30000, 91)
+    q = workloads.charges(30000, 3, 92, "upm1")
+    depth, order = (4, 5) if m2l == "fft" else (3, 5)
+    say(f"case: tuning {m2l} {prec} 30k depth {depth} p{order} nvec 3")
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    kw = dict(svd_rel_tol=1e-6, svd_rel_tol_dir=1e-6) if m2l == "blas" else {}
+    f = K.KiFMM(order, depth, m2l=m2l, prec=prec, **kw).set_points(pts).precompute()
+    qt = torch.as_tensor(q, dtype=dt, device="cuda")
+    a = f.evaluate(qt).clone()
+    if m2l == "fft":
+        settings = [dict(schedule=s, hadamard=h) for s in (0, 1) for h in (0, 1)]
+    else:
+        settings = [dict(blas_tile=t) for t in (42, 21, 10, 5, 1)]
+    for st in settings:
+        f.set_tuning(**st)
+        b = f.evaluate(qt)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), st
+    f.set_tuning(blas_tile=0, schedule=0, hadamard=0)
+    best = f.autotune(qt, reps=2)
+    tuned = f.tuning()
+    say(f"  autotune kept {tuned}, {best:.3f} ms")
+    assert best > 0.0
+    if m2l == "fft":
+        assert tuned["schedule"] in (0, 1) and tuned["hadamard"] in (0, 1)
+        if prec == "fp64":
+            assert tuned["hadamard"] == 0
+    else:
+        assert tuned["blas_tile"] in (42, 21, 10, 5)
+    c = f.evaluate(qt)
+    torch.cuda.synchronize()
+    assert torch.equal(a, c)
+    if m2l == "fft":
+        ref = fmm.KiFMM(pts, pts, depth, order).evaluate(q)
+        e = kernel.rel_l2(c.double().cpu().numpy(), ref)
+        say(f"  rel err vs oracle {e:.3e}")
+        assert e <= (FP64_GATE if prec == "fp64" else FP32_GATE)
