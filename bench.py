@@ -241,6 +241,27 @@ def run_blas(K, torch, steps, warmup):
     return out
 
 
+def run_scale(K, torch, steps, warmup):
+    """The paper's larger problem size: 8,000,000 uniform points, depth 6, p = 6,
+    FFT-M2L, mixed and FP64, with the error against the FP64 direct sum."""
+    import workloads
+    w = workloads.config(6)
+    out = {"workload": w.name, "n_points": w.n, "depth": w.depth, "order": w.order, "n_vec": w.nvec}
+    for prec in ("fp32", "fp64"):
+        f, phi, ms_step, tm, setup_s = run_precision(K, torch, w, prec, steps, warmup)
+        err = direct_error(torch, w, phi)
+        out[prec] = {"ms_per_step": round(ms_step, 3), "m2l_ms": round(tm["m2l"], 3),
+                     "near_field_ms": round(tm["near_field"], 3), "setup_s": round(setup_s, 2),
+                     "rel_err_vs_direct": err}
+        log(f"  8M {prec}: step {ms_step:.2f} ms, m2l {tm['m2l']:.3f} ms, near field "
+            f"{tm['near_field']:.3f} ms, err vs direct {err:.2e}")
+        del f, phi
+        torch.cuda.empty_cache()
+    out["m2l_speedup_mixed_vs_fp64"] = round(out["fp64"]["m2l_ms"] / out["fp32"]["m2l_ms"], 3)
+    out["error_targets"] = 1000
+    return out
+
+
 def run_batch(K, torch, launches):
     """128 independent problems (log-uniform sizes 1e4..2e5, depth 3-4,
     p in {4,5,6}, 1-8 vectors), FFT-M2L in FP32 with FP64 local
@@ -347,6 +368,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-blas", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-scale", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the FMM here is a single-GPU build "
@@ -462,8 +484,11 @@ def main():
     if not args.no_batch:
         log("batched serving workload: 128 problems, one graph launch")
         line["batch_128"] = run_batch(K, torch, 200)
+    if not args.no_scale:
+        log("scale workload: 8M uniform points, depth 6, p = 6")
+        line["scale_8M"] = run_scale(K, torch, max(1, min(args.steps, 5)), 1)
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle dense M2L on a bounded sample")
+        log("cpu baseline: oracle dense M2L of every level")
         line["cpu_baseline"] = cpu_baseline(w)
     else:
         line["cpu_baseline"] = None

@@ -45,7 +45,6 @@ struct DeviceState {
   std::vector<void*> allocs;
   // points and leaves
   double* src_xyz = nullptr;
-  float* src_xyz_f = nullptr;
   double* tgt_xyz = nullptr;
   int64_t* src_perm = nullptr;
   int64_t* tgt_perm = nullptr;
@@ -355,10 +354,6 @@ kifmm_status upload_all(kifmm_handle* h) {
 
   KIFMM_TRY(upload(d, &d->src_xyz, t.src_sorted.data(), t.src_sorted.size()));
   KIFMM_TRY(upload(d, &d->tgt_xyz, t.tgt_sorted.data(), t.tgt_sorted.size()));
-  {
-    std::vector<float> f(t.src_sorted.begin(), t.src_sorted.end());
-    KIFMM_TRY(upload(d, &d->src_xyz_f, f.data(), f.size()));
-  }
   KIFMM_TRY(upload(d, &d->src_perm, t.src_perm.data(), t.src_perm.size()));
   KIFMM_TRY(upload(d, &d->tgt_perm, t.tgt_perm.data(), t.tgt_perm.size()));
   KIFMM_TRY(upload(d, &d->src_start, t.src_start.data(), t.src_start.size()));
@@ -708,7 +703,7 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
   const DevLevel& leaf = d->lv[depth];
   const double ar_leaf = op.ao * 0.5 * leaf.w;
   auto leaf_pass = [&](int mode, hipStream_t st) -> kifmm_status {
-    KIFMM_LAUNCH(launch_leaf_eval(d->tgt_xyz, d->src_xyz, d->src_xyz_f, d->qs, d->fp64, t.n_src,
+    KIFMM_LAUNCH(launch_leaf_eval(d->tgt_xyz, d->src_xyz, leaf.w, d->qs, d->fp64, t.n_src,
                                   d->tgt_start, d->tgt_end, d->src_start, d->src_end, d->near_offs,
                                   d->near_src, d->leaf_centers, leaf.n, d->surf, ar_leaf, ns,
                                   d->local[depth], d->tgt_perm, phi, ldphi, nvec, mode, st));

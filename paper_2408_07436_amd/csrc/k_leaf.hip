@@ -154,25 +154,35 @@ template <> struct Vec4<double> { using type = double4; };
 // occupancy), split the staged sources and reduce with cross-lane shuffles.
 // The near-field sources (up to 27 leaves, each a contiguous run in Morton
 // order) are located by binary search over the run offsets.  L2P runs in
-// FP64 from the leaf's downward-equivalent densities; P2P runs in T.  NV
+// FP64 from the leaf's downward-equivalent densities; P2P runs in T, in the
+// frame of the target leaf's center (offsets of at most 1.5 leaf widths w,
+// formed in FP64).  In FP32 each offset is split as hi + lo (hi its FP32
+// rounding, lo the FP32 rounding of the remainder); pairs are evaluated
+// from the hi parts, whose rounding (at most about 1e-7 w) bounds the
+// relative error of r by 5e-6 for r >= w / 16.  The rare pairs closer than
+// that (r^2 < tau2) are evaluated again from the difference of the hi
+// parts plus the difference of the lo parts, which carries the pair's
+// separation to FP32 relative accuracy.  NV
 // charge vectors are handled per pass.  MODE 0 does both; MODE 1 only the
 // near field, storing its raw sums (in T, before the 1/(4 pi) factor);
 // MODE 2 adds the far field to those stored sums and finishes, so 1 then 2
 // gives exactly the result of 0.
 template <typename T, typename TQ, int NV, int MODE>
 __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
-    const double* __restrict__ txyz, const T* __restrict__ sxyz, const TQ* __restrict__ qs,
+    const double* __restrict__ txyz, const double* __restrict__ sxyz, const TQ* __restrict__ qs,
     int64_t n_src, const int32_t* __restrict__ tstart, const int32_t* __restrict__ tend,
     const int32_t* __restrict__ sstart, const int32_t* __restrict__ send,
     const int64_t* __restrict__ noffs, const int32_t* __restrict__ nsrc,
     const double* __restrict__ centers, const double* __restrict__ surf, double ar, int ns,
     const double* __restrict__ local, const int64_t* __restrict__ tperm, TQ* __restrict__ phi,
-    int64_t ldphi, int nvec, int64_t n_leaf) {
+    int64_t ldphi, int nvec, int64_t n_leaf, T tau2) {
   using T4 = typename Vec4<T>::type;
   constexpr int NX = NV > 1 ? NV - 1 : 1;
   __shared__ double4 ls[kL2PChunk];
   __shared__ double lq[NX][kL2PChunk];
+  constexpr bool kSplit = sizeof(T) == 4;  // FP32: hi + lo offsets
   __shared__ T4 ps[kLeafChunk];
+  __shared__ float4 pl[kSplit ? kLeafChunk : 1];  // lo parts of the staged offsets
   __shared__ T pq[NX][kLeafChunk];
   __shared__ int32_t nb_first[27];
   __shared__ int32_t nb_pref[28];
@@ -271,13 +281,19 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
         }
       }
       // P2P over the near field
-      const T xt0 = (T)x0, yt0 = (T)y0, zt0 = (T)z0, xt1 = (T)x1, yt1 = (T)y1, zt1 = (T)z1;
+      const T xt0 = (T)(x0 - cx), yt0 = (T)(y0 - cy), zt0 = (T)(z0 - cz);
+      const T xt1 = (T)(x1 - cx), yt1 = (T)(y1 - cy), zt1 = (T)(z1 - cz);
+      const float xl0 = (float)((x0 - cx) - (double)xt0), yl0 = (float)((y0 - cy) - (double)yt0),
+                  zl0 = (float)((z0 - cz) - (double)zt0);
+      const float xl1 = (float)((x1 - cx) - (double)xt1), yl1 = (float)((y1 - cy) - (double)yt1),
+                  zl1 = (float)((z1 - cz) - (double)zt1);
       for (int c0 = 0; c0 < (MODE == 2 ? 0 : total); c0 += kLeafChunk) {
         const int cn = min(kLeafChunk, total - c0);
         const int cnp = (cn + 2 * L - 1) / (2 * L) * (2 * L);  // zero charges pad
         __syncthreads();
         for (int t = cn + threadIdx.x; t < cnp; t += kLeafThreads) {
           ps[t] = T4{T(0), T(0), T(0), T(0)};
+          if constexpr (kSplit) pl[t] = float4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int v = 1; v < NV; ++v) pq[v - 1][t] = T(0);
         }
@@ -290,7 +306,11 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
           }
           const int64_t si = (int64_t)nb_first[lo] + (g - nb_pref[lo]);
           const T q0 = vb < nvec ? (T)qs[(int64_t)vb * n_src + si] : T(0);
-          ps[t] = T4{sxyz[3 * si], sxyz[3 * si + 1], sxyz[3 * si + 2], q0};
+          const double ox = sxyz[3 * si] - cx, oy = sxyz[3 * si + 1] - cy, oz = sxyz[3 * si + 2] - cz;
+          ps[t] = T4{(T)ox, (T)oy, (T)oz, q0};
+          if constexpr (kSplit)
+            pl[t] = float4{(float)(ox - (double)(T)ox), (float)(oy - (double)(T)oy),
+                           (float)(oz - (double)(T)oz), 0.f};
 #pragma unroll
           for (int v = 1; v < NV; ++v)
             pq[v - 1][t] = vb + v < nvec ? (T)qs[(int64_t)(vb + v) * n_src + si] : T(0);
@@ -300,8 +320,17 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
           const T4 src = ps[s];
           const T dx0 = xt0 - src.x, dy0 = yt0 - src.y, dz0 = zt0 - src.z;
           const T dx1 = xt1 - src.x, dy1 = yt1 - src.y, dz1 = zt1 - src.z;
-          const T r0 = inv_r(dx0 * dx0 + dy0 * dy0 + dz0 * dz0);
-          const T r1 = inv_r(dx1 * dx1 + dy1 * dy1 + dz1 * dz1);
+          const T q0 = dx0 * dx0 + dy0 * dy0 + dz0 * dz0, q1 = dx1 * dx1 + dy1 * dy1 + dz1 * dz1;
+          T r0 = inv_r(q0), r1 = inv_r(q1);
+          if constexpr (kSplit) {
+            if (q0 < tau2 || q1 < tau2) {  // rare: a pair closer than w / 16
+              const float4 sl = pl[s];
+              const float fx0 = dx0 + (xl0 - sl.x), fy0 = dy0 + (yl0 - sl.y), fz0 = dz0 + (zl0 - sl.z);
+              const float fx1 = dx1 + (xl1 - sl.x), fy1 = dy1 + (yl1 - sl.y), fz1 = dz1 + (zl1 - sl.z);
+              if (q0 < tau2) r0 = inv_r(fx0 * fx0 + fy0 * fy0 + fz0 * fz0);
+              if (q1 < tau2) r1 = inv_r(fx1 * fx1 + fy1 * fy1 + fz1 * fz1);
+            }
+          }
           ap0[0] += r0 * src.w;
           ap1[0] += r1 * src.w;
 #pragma unroll
@@ -347,7 +376,8 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
 }
 
 template <typename T, typename TQ, int MODE>
-hipError_t leaf_launch(int nvec, int64_t n_leaf, hipStream_t stream, const double* txyz, const T* sxyz,
+hipError_t leaf_launch(int nvec, int64_t n_leaf, hipStream_t stream, const double* txyz,
+                       const double* sxyz, double tau2,
                        const TQ* qs, int64_t n_src, const int32_t* tstart, const int32_t* tend,
                        const int32_t* sstart, const int32_t* send, const int64_t* near_offs,
                        const int32_t* near_src, const double* centers, const double* surf, double ar,
@@ -355,8 +385,9 @@ hipError_t leaf_launch(int nvec, int64_t n_leaf, hipStream_t stream, const doubl
 #define KIFMM_LEAF(NVV)                                                                       \
   leaf_eval_kernel<T, TQ, NVV, MODE><<<(unsigned)(8 * ((n_leaf + 7) / 8)), kLeafThreads, 0,  \
                                        stream>>>(                                             \
-      txyz, sxyz, qs, n_src, tstart, tend, sstart, send, near_offs, near_src, centers, surf, ar, \
-      ns, local, tgt_perm, phi, ldphi, nvec, n_leaf)
+      txyz, sxyz, qs, n_src, tstart, tend, sstart, send, near_offs, near_src, centers, \
+      surf, ar, \
+      ns, local, tgt_perm, phi, ldphi, nvec, n_leaf, (T)tau2)
   if (nvec == 1)
     KIFMM_LEAF(1);
   else if (nvec == 2)
@@ -371,7 +402,8 @@ hipError_t leaf_launch(int nvec, int64_t n_leaf, hipStream_t stream, const doubl
 
 template <typename T, typename TQ>
 hipError_t leaf_mode(int mode, int nvec, int64_t n_leaf, hipStream_t stream, const double* txyz,
-                     const T* sxyz, const TQ* qs, int64_t n_src, const int32_t* tstart,
+                     const double* sxyz, double tau2, const TQ* qs, int64_t n_src,
+                     const int32_t* tstart,
                      const int32_t* tend, const int32_t* sstart, const int32_t* send,
                      const int64_t* near_offs, const int32_t* near_src, const double* centers,
                      const double* surf, double ar, int ns, const double* local,
@@ -379,7 +411,8 @@ hipError_t leaf_mode(int mode, int nvec, int64_t n_leaf, hipStream_t stream, con
   switch (mode) {
 #define KIFMM_MODE(M)                                                                        \
   case M:                                                                                    \
-    return leaf_launch<T, TQ, M>(nvec, n_leaf, stream, txyz, sxyz, qs, n_src, tstart, tend, sstart, \
+    return leaf_launch<T, TQ, M>(nvec, n_leaf, stream, txyz, sxyz, tau2, qs, n_src, tstart,       \
+                                 tend, sstart, \
                                  send, near_offs, near_src, centers, surf, ar, ns, local,     \
                                  tgt_perm, phi, ldphi);
     KIFMM_MODE(0) KIFMM_MODE(1) KIFMM_MODE(2)
@@ -412,7 +445,7 @@ hipError_t launch_p2m(const double* src_xyz, const void* qs, bool q_fp64, int64_
                            end, centers, surf, ar, ns, phi);
 }
 
-hipError_t launch_leaf_eval(const double* tgt_xyz, const double* src_xyz, const float* src_xyz_f,
+hipError_t launch_leaf_eval(const double* tgt_xyz, const double* src_xyz, double leaf_w,
                             const void* qs, bool fp64, int64_t n_src, const int32_t* tstart,
                             const int32_t* tend, const int32_t* sstart, const int32_t* send,
                             const int64_t* near_offs, const int32_t* near_src,
@@ -420,12 +453,13 @@ hipError_t launch_leaf_eval(const double* tgt_xyz, const double* src_xyz, const 
                             int ns, const double* local, const int64_t* tgt_perm, void* phi,
                             int64_t ldphi, int nvec, int mode, hipStream_t stream) {
   if (n_leaf == 0) return hipSuccess;
+  const double tau2 = (leaf_w / 16) * (leaf_w / 16);  // FP32: pairs refined below w / 16
   if (fp64)
-    return leaf_mode<double, double>(mode, nvec, n_leaf, stream, tgt_xyz, src_xyz,
+    return leaf_mode<double, double>(mode, nvec, n_leaf, stream, tgt_xyz, src_xyz, tau2,
                                      (const double*)qs, n_src, tstart, tend, sstart, send,
                                      near_offs, near_src, centers, surf, ar, ns, local, tgt_perm,
                                      (double*)phi, ldphi);
-  return leaf_mode<float, float>(mode, nvec, n_leaf, stream, tgt_xyz, src_xyz_f,
+  return leaf_mode<float, float>(mode, nvec, n_leaf, stream, tgt_xyz, src_xyz, tau2,
                                  (const float*)qs, n_src, tstart, tend, sstart, send, near_offs,
                                  near_src, centers, surf, ar, ns, local, tgt_perm, (float*)phi,
                                  ldphi);

@@ -23,7 +23,9 @@ hipError_t launch_p2m(const double* src_xyz, const void* qs, bool q_fp64, int64_
 // charges), written to the caller's target order.  mode 0: both; mode 1:
 // the near field only, phi receives its raw sums (no 1/(4 pi)); mode 2: the
 // far field added to the raw sums in phi, finished - 1 then 2 equals 0.
-hipError_t launch_leaf_eval(const double* tgt_xyz, const double* src_xyz, const float* src_xyz_f,
+// src_xyz: sorted sources (FP64); leaf_w: the leaf width (the FP32 near
+// field refines pairs closer than leaf_w / 16).
+hipError_t launch_leaf_eval(const double* tgt_xyz, const double* src_xyz, double leaf_w,
                             const void* qs, bool fp64, int64_t n_src, const int32_t* tstart,
                             const int32_t* tend, const int32_t* sstart, const int32_t* send,
                             const int64_t* near_offs, const int32_t* near_src,

@@ -96,6 +96,8 @@ def config(c: int, n: int | None = None, nvec: int | None = None,
        depth 5, p=6, 32 vectors in [-1,1).
     4: 4,000,000 points on the unit sphere in [-1,1]^3, depth 6, p=6,
        64 standard-normal vectors.
+    6: 8,000,000 uniform points, depth 6, p=6, FFT-M2L, 1 vector in [0,1)
+       (the paper's larger problem size, for runs at scale).
     """
     if c == 1:
         n = 20_000 if n is None else n
@@ -126,6 +128,13 @@ def config(c: int, n: int | None = None, nvec: int | None = None,
         q = charges(n, nv, SEED_CHARGES + c, "normal")
         return Workload("sphere-4M-d6-p6-64rhs", pts, q, 6 if depth is None else depth,
                         6, (-1.0, -1.0, -1.0), 2.0, "fft")
+    if c == 6:
+        n = 8_000_000 if n is None else n
+        nv = 1 if nvec is None else nvec
+        pts = uniform_cube(n, SEED_POINTS + c)
+        q = charges(n, nv, SEED_CHARGES + c, "u01")
+        return Workload("uniform-8M-d6-p6-fft", pts, q, 6 if depth is None else depth,
+                        6, (0.0, 0.0, 0.0), 1.0, "fft")
     raise ValueError(f"unknown workload {c}")
 
 
