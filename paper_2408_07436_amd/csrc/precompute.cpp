@@ -9,11 +9,30 @@
 // of width w equals the unit-box operator divided by w (pseudo-inverses are
 // multiplied by w); the device code applies that scale per level.
 #include <cmath>
+#include <algorithm>
+#include <atomic>
 #include <complex>
+#include <thread>
 
 #include "internal.h"
 
 namespace kifmm {
+
+namespace {
+// Runs f(i) for i in [0, n) on up to 16 host threads (independent items).
+template <typename F>
+void parallel_for(int n, F f) {
+  const int nt = std::max(1, std::min({n, 16, (int)std::thread::hardware_concurrency()}));
+  std::atomic<int> next{0};
+  auto work = [&]() {
+    for (int i = next++; i < n; i = next++) f(i);
+  };
+  std::vector<std::thread> pool;
+  for (int k = 1; k < nt; ++k) pool.emplace_back(work);
+  work();
+  for (auto& th : pool) th.join();
+}
+}  // namespace
 
 namespace {
 
@@ -192,12 +211,12 @@ kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg) {
     // surface around t), both on the inner surface
     const auto dc = place(op, op.ai, 0.5, zero);
     std::vector<std::vector<double>> Kt(kNumTransfer, std::vector<double>((size_t)ns * ns));
-    for (int it = 0; it < kNumTransfer; ++it) {
+    parallel_for(kNumTransfer, [&](int it) {
       int t[3];
       transfer_vector(it, t);
       const double c[3] = {(double)t[0], (double)t[1], (double)t[2]};
       kernel_block(dc, place(op, op.ai, 0.5, c), ns, ns, Kt[it].data(), ns);
-    }
+    });
     op.Ubar.assign(kNumTransfer, {});
     op.Vbarp.assign(kNumTransfer, {});
     op.kt.assign(kNumTransfer, 0);
@@ -233,8 +252,10 @@ kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg) {
       for (int i = 0; i < ns; ++i)
         for (int j = 0; j < k; ++j) op.U[(size_t)i * k + j] = Uf[(size_t)i * r0 + j];
       op.recompressed = cfg.svd_rel_tol_dir >= 0;
-      std::vector<double> tmp((size_t)ns * k), C((size_t)k * k);
-      for (int it = 0; it < kNumTransfer; ++it) {
+      // the transfer vectors are independent: one host thread each at a time
+      std::atomic<bool> svd_failed{false};
+      parallel_for(kNumTransfer, [&](int it) {
+        std::vector<double> tmp((size_t)ns * k), C((size_t)k * k);
         // C_t = U^T K_t U
         for (int i = 0; i < ns; ++i)
           for (int j = 0; j < k; ++j) {
@@ -251,10 +272,13 @@ kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg) {
         if (!op.recompressed) {
           op.kt[it] = k;
           op.Vbarp[it] = C;  // applied directly
-          continue;
+          return;
         }
         std::vector<double> cu, cs, cv;
-        if (!svd(C.data(), k, k, cu, cs, cv)) return fail(KIFMM_ENUMERIC, "SVD of C_t did not converge");
+        if (!svd(C.data(), k, k, cu, cs, cv)) {
+          svd_failed = true;
+          return;
+        }
         int r = 0;
         while (r < k && cs[r] > cfg.svd_rel_tol_dir * cs[0]) ++r;
         if (r == 0) r = 1;
@@ -266,7 +290,8 @@ kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg) {
             op.Ubar[it][(size_t)i * r + j] = cu[(size_t)i * k + j];
             op.Vbarp[it][(size_t)i * r + j] = cv[(size_t)i * k + j] * cs[j];
           }
-      }
+      });
+      if (svd_failed) return fail(KIFMM_ENUMERIC, "SVD of C_t did not converge");
     }
   }
   op.ready = true;
