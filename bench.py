@@ -439,7 +439,40 @@ def main():
                  "per_launch": f"{interactions:.3e} P2P interactions x 12 operations "
                                f"(11 flops + rsqrt), avg {tm['near_field']:.4f} ms"}
     roof_leaf["frac"] = roof_leaf["achieved"] / roof_leaf["peak"]
-    roofs = {"hadamard": roof_had, "fft_forward": roof_fwd, "fft_inverse": roof_inv, "near_field": roof_leaf}
+    # the passes around the M2L (mixed run): P2M and L2P on the FP64 VALU
+    # (12 operations per surface-point / point pair, as for P2P), the
+    # composite-operator GEMMs of the upward and downward passes on FP64 MFMA
+    ns = 6 * (w.order - 1) ** 2 + 2
+    nb = [mix["f"].num_boxes(lev) for lev in range(w.depth + 1)]
+    up_flops = 2.0 * ns * ns * nb[w.depth] * w.nvec + sum(
+        2.0 * ns * 8 * ns * nb[lev] * w.nvec for lev in range(2, w.depth))
+    down_flops = sum(2.0 * ns * ns * nb[lev] * w.nvec for lev in range(2, w.depth + 1)) + sum(
+        2.0 * 8 * ns * ns * nb[lev - 1] * w.nvec for lev in range(3, w.depth + 1))
+    surf_pairs = float(ns) * w.n
+    roof_p2m = {"kernel": "p2m_kernel (FP64, leaf check potentials)", "bound": "alu",
+                "achieved": 12.0 * surf_pairs / (tm["p2m"] * 1e-3) / 1e12,
+                "peak": PEAK_VALU_NOPK["fp64"] / 1e12, "unit": "TFLOP/s", "traffic": None,
+                "per_launch": f"{surf_pairs:.3e} (check point, source) pairs x 12 operations, "
+                              f"avg {tm['p2m']:.4f} ms"}
+    roof_l2p = {"kernel": "leaf_eval_kernel<float, float, 1, 2> (far field, L2P FP64)", "bound": "alu",
+                "achieved": 12.0 * surf_pairs / (tm["far_field"] * 1e-3) / 1e12,
+                "peak": PEAK_VALU_NOPK["fp64"] / 1e12, "unit": "TFLOP/s", "traffic": None,
+                "per_launch": f"{surf_pairs:.3e} (target, equivalent point) pairs x 12 operations, "
+                              f"avg {tm['far_field']:.4f} ms"}
+    up_gemm_ms = tm["upward"] - tm["p2m"]
+    roof_up = {"kernel": "gemm64_kernel, upward pass (leaf pseudo-inverse, M2M with it folded in)",
+               "bound": "mfma", "achieved": up_flops / (up_gemm_ms * 1e-3) / 1e12,
+               "peak": PEAK_MFMA["fp64"] / 1e12, "unit": "TFLOP/s", "traffic": None,
+               "per_launch": f"{up_flops / 1e9:.2f} GFLOP per evaluate, {up_gemm_ms:.4f} ms "
+                             f"(upward phase minus P2M, includes the charge gather)"}
+    roof_down = {"kernel": "gemm64_kernel, downward pass (down pseudo-inverse, L2L with it folded in)",
+                 "bound": "mfma", "achieved": down_flops / (tm["downward"] * 1e-3) / 1e12,
+                 "peak": PEAK_MFMA["fp64"] / 1e12, "unit": "TFLOP/s", "traffic": None,
+                 "per_launch": f"{down_flops / 1e9:.2f} GFLOP per evaluate, {tm['downward']:.4f} ms"}
+    for r in (roof_p2m, roof_l2p, roof_up, roof_down):
+        r["frac"] = r["achieved"] / r["peak"]
+    roofs = {"hadamard": roof_had, "fft_forward": roof_fwd, "fft_inverse": roof_inv, "near_field": roof_leaf,
+             "p2m": roof_p2m, "far_field": roof_l2p, "upward_gemm": roof_up, "downward_gemm": roof_down}
     for r in roofs.values():
         for k in ("achieved", "peak", "frac"):
             r[k] = round(r[k], 4)

@@ -185,7 +185,7 @@ kifmm_status kifmm_stage(kifmm_handle* h, int32_t stage, int32_t level, const vo
  * recorded between kernels.  A timed call synchronises before it returns. */
 kifmm_status kifmm_set_timing(kifmm_handle* h, int32_t on);
 /* Milliseconds of the last timed evaluate or stage (cap >= 5; more entries
- * are filled when cap allows, up to 11).  An untimed FFT-M2L evaluate runs
+ * are filled when cap allows, up to 12).  An untimed FFT-M2L evaluate runs
  * as a dependency graph over several streams (near field beside the FMM
  * passes, coarse levels beside the leaf level); a timed one runs the
  * phases one after another (the M2L levels still concurrently) so that each
@@ -196,7 +196,8 @@ kifmm_status kifmm_set_timing(kifmm_handle* h, int32_t on);
  * BLAS/dense: compression), [6] M2L main kernel (FFT: Hadamard; BLAS/dense:
  * per-transfer-vector products), [7] M2L last kernel (FFT: inverse
  * transform; BLAS: decompression), [8] number of M2L levels, [9] near-field
- * pass (P2P) and [10] far-field pass (L2P) of FFT evaluates (0 otherwise).
+ * pass (P2P) and [10] far-field pass (L2P) of FFT evaluates (0 otherwise),
+ * [11] the P2M kernel (leaf check potentials, part of [0]).
  * [5..7] are each kernel's own start-to-end times and overlap when levels
  * run concurrently.  After a timed stage: [1] = [4] = the level's M2L,
  * [5..7] its three kernels, [8] = 1, the rest 0. */

@@ -246,11 +246,11 @@ class KiFMM:
         _check(lib().kifmm_set_timing(self._h, 1 if on else 0))
 
     def timings(self) -> dict:
-        ms = np.zeros(11, dtype=np.float64)
-        _check(lib().kifmm_timings(self._h, _ptr(ms, ctypes.c_double), 11))
+        ms = np.zeros(12, dtype=np.float64)
+        _check(lib().kifmm_timings(self._h, _ptr(ms, ctypes.c_double), 12))
         return dict(upward=ms[0], m2l=ms[1], downward=ms[2], leaves=ms[3], total=ms[4],
                     m2l_first=ms[5], m2l_main=ms[6], m2l_last=ms[7], m2l_levels=int(ms[8]),
-                    near_field=ms[9], far_field=ms[10])
+                    near_field=ms[9], far_field=ms[10], p2m=ms[11])
 
     # ---- autotuning -------------------------------------------------------
     def tuning(self) -> dict:

@@ -289,7 +289,7 @@ kifmm_status kifmm_set_timing(kifmm_handle* h, int32_t on) {
 kifmm_status kifmm_timings(const kifmm_handle* h, double* ms, int32_t cap) {
   if (!h || !ms) return fail(KIFMM_EINVAL, "null argument");
   if (cap < 5) return fail(KIFMM_EINVAL, "capacity too small");
-  for (int i = 0; i < cap && i < 11; ++i) ms[i] = h->timings[i];
+  for (int i = 0; i < cap && i < 12; ++i) ms[i] = h->timings[i];
   return KIFMM_OK;
 }
 

@@ -94,7 +94,7 @@ struct DeviceState {
   std::vector<hipEvent_t> up_ev;    // [depth + 1] multipoles of coarse level l ready
   std::vector<hipEvent_t> join_ev;  // [depth + 1] M2L of coarse level l done
   std::vector<void*> work_allocs;
-  hipEvent_t ev[6] = {};
+  hipEvent_t ev[8] = {};
   std::vector<hipEvent_t> lev_ev;  // [level][4] marks around the M2L kernels
   bool events = false;
 };
@@ -470,7 +470,7 @@ kifmm_status upload_all(kifmm_handle* h) {
     KIFMM_TRY(upload(d, &d->UblasT, Ut.data(), Ut.size()));
     KIFMM_TRY(pack_blas_operators(h, d));
   }
-  for (int e = 0; e < 6; ++e) KIFMM_HIP(hipEventCreate(&d->ev[e]));
+  for (int e = 0; e < 8; ++e) KIFMM_HIP(hipEventCreate(&d->ev[e]));
   d->lev_ev.assign(4 * (depth + 1), nullptr);
   for (auto& e : d->lev_ev) KIFMM_HIP(hipEventCreate(&e));
   d->events = true;
@@ -712,8 +712,10 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
 
   KIFMM_LAUNCH(launch_gather(q, ldq, d->src_perm, t.n_src, nvec, d->fp64, d->qs, s));
   // upward pass
+  if (timed) KIFMM_HIP(hipEventRecord(d->ev[6], s));
   KIFMM_LAUNCH(launch_p2m(d->src_xyz, d->qs, d->fp64, t.n_src, d->src_start, d->src_end,
                           d->leaf_centers, leaf.n, d->surf, ar_leaf, ns, nvec, d->phi, s));
+  if (timed) KIFMM_HIP(hipEventRecord(d->ev[7], s));
   // FP64: two-factor pseudo-inverses after each M2M (Section 2.1.1); the
   // reduced-precision modes apply the composite operators (M2M with the
   // parent's pseudo-inverse folded in: the width scalings cancel)
@@ -851,6 +853,9 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
     } else {
       h->timings[9] = h->timings[10] = 0.0;
     }
+    float p2m = 0.f;
+    KIFMM_HIP(hipEventElapsedTime(&p2m, d->ev[6], d->ev[7]));
+    h->timings[11] = p2m;
     h->timings[0] = a;
     h->timings[1] = m2l_ms;
     h->timings[2] = b - m2l_ms;

@@ -120,6 +120,6 @@ struct kifmm_handle {
   bool has_points = false;
   kifmm::DeviceState* dev = nullptr;
   bool timing = false;
-  double timings[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double timings[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   int32_t tune[KIFMM_TUNE_COUNT] = {0, 0, 0};  // autotuning knobs (kifmm.h)
 };
