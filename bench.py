@@ -262,6 +262,36 @@ def run_scale(K, torch, steps, warmup):
     return out
 
 
+def run_resetup(K, torch, w, reps=3):
+    """Moving points: the tree rebuilt on the host (kifmm_set_points) against the
+    device re-setup (kifmm_update_points: binning and a stable radix sort on the GPU)
+    for new positions of the same workload size."""
+    import workloads
+    t0 = time.perf_counter()
+    f = K.KiFMM(w.order, w.depth, m2l="fft", prec="fp32").set_points(w.points)
+    host_ms = (time.perf_counter() - t0) * 1e3
+    f.precompute()
+    q = torch.as_tensor(w.q, dtype=torch.float32, device="cuda")
+    f.evaluate(q)
+    moved = [torch.as_tensor(workloads.uniform_cube(w.n, 9000 + r), device="cuda") for r in range(reps)]
+    torch.cuda.synchronize()
+    dev = []
+    for r in range(reps):
+        t0 = time.perf_counter()
+        f.update_points(moved[r])
+        torch.cuda.synchronize()
+        dev.append((time.perf_counter() - t0) * 1e3)
+    f.evaluate(q)
+    torch.cuda.synchronize()
+    out = {"n_points": w.n, "depth": w.depth, "host_set_points_ms": round(host_ms, 2),
+           "device_update_points_ms": round(float(np.median(dev)), 3)}
+    log(f"  re-setup of {w.n} moved points: host tree build {host_ms:.1f} ms, device update "
+        f"{out['device_update_points_ms']:.2f} ms")
+    del f, q, moved
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_batch(K, torch, launches):
     """128 independent problems (log-uniform sizes 1e4..2e5, depth 3-4,
     p in {4,5,6}, 1-8 vectors), FFT-M2L in FP32 with FP64 local
@@ -511,6 +541,8 @@ def main():
                          "(8 cores); 240 ms on AMD 3790X at depth 4 (32 cores) - CPU context only",
         "setup_s": {"fp32": round(mix["setup_s"], 2), "fp64": round(ref["setup_s"], 2)},
     }
+    log("moving points: host tree build vs device re-setup")
+    line["resetup_1M"] = run_resetup(K, torch, w)
     if not args.no_blas:
         log("blas-m2l workload: 32 vectors, fp64 / fp32 / bf16x3")
         line["blas_32rhs"] = run_blas(K, torch, max(1, min(args.steps, 3)), 1)

@@ -209,6 +209,23 @@ kifmm_status kifmm_timings(const kifmm_handle* h, double* ms, int32_t cap);
  * halos.  cap >= 4. */
 kifmm_status kifmm_m2l_counts(const kifmm_handle* h, int32_t level, int64_t* counts, int32_t cap);
 
+/* ---- moving points --------------------------------------------------------- */
+
+/* Re-setup for points that move between evaluates, on the device: the new
+ * positions src_dev[n_src][3] and tgt_dev[n_tgt][3] (device memory, FP64,
+ * row-major, the counts of kifmm_set_points; tgt_dev may equal src_dev; they
+ * must not be buffers the library returned) are binned into the current
+ * tree's leaves and sorted on the GPU, stably by leaf and then by index (the
+ * order kifmm_set_points produces).  The box set, the lists and the
+ * operators are kept, so the potentials equal those after kifmm_set_points
+ * with the same positions whenever that call would build the same box set
+ * (every leaf keeps at least one point).  The buffers are read on
+ * hip_stream; the call synchronises it.  ESTATE: no points or operators
+ * yet, or some point falls outside every current leaf - then nothing has
+ * changed and kifmm_set_points is needed.  EINVAL: null arguments. */
+kifmm_status kifmm_update_points(kifmm_handle* h, const void* src_dev, const void* tgt_dev,
+                                 void* hip_stream);
+
 /* ---- autotuning ---------------------------------------------------------- */
 
 /* Knobs of the evaluate's schedule and tile shapes (int32; 0 = built-in

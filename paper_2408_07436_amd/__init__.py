@@ -26,7 +26,7 @@ EXPORTS = [
     "kifmm_evaluate", "kifmm_destroy", "kifmm_last_error", "kifmm_num_boxes", "kifmm_box_keys",
     "kifmm_point_perm", "kifmm_interactions", "kifmm_near", "kifmm_operator", "kifmm_stage",
     "kifmm_set_timing", "kifmm_timings", "kifmm_m2l_counts", "kifmm_get_tuning",
-    "kifmm_set_tuning", "kifmm_autotune", "kifmm_batch_create", "kifmm_batch_autotune",
+    "kifmm_set_tuning", "kifmm_autotune", "kifmm_update_points", "kifmm_batch_create", "kifmm_batch_autotune",
     "kifmm_batch_launch", "kifmm_batch_destroy",
 ]
 TUNE_KNOBS = ("blas_tile", "schedule", "hadamard")
@@ -86,6 +86,7 @@ def lib() -> ctypes.CDLL:
     L.kifmm_set_timing.argtypes = [vp, i32]
     L.kifmm_timings.argtypes = [vp, dp, i32]
     L.kifmm_m2l_counts.argtypes = [vp, i32, ctypes.POINTER(i64), i32]
+    L.kifmm_update_points.argtypes = [vp, vp, vp, vp]
     L.kifmm_get_tuning.argtypes = [vp, ctypes.POINTER(i32), i32]
     L.kifmm_set_tuning.argtypes = [vp, ctypes.POINTER(i32), i32]
     L.kifmm_autotune.argtypes = [vp, vp, i64, i32, vp, i64, vp, i32, dp]
@@ -251,6 +252,18 @@ class KiFMM:
         return dict(upward=ms[0], m2l=ms[1], downward=ms[2], leaves=ms[3], total=ms[4],
                     m2l_first=ms[5], m2l_main=ms[6], m2l_last=ms[7], m2l_levels=int(ms[8]),
                     near_field=ms[9], far_field=ms[10], p2m=ms[11])
+
+    def update_points(self, sources, targets=None, stream=None):
+        """Move the points on the device (kifmm_update_points): ``sources``
+        (and ``targets``, default the sources) are FP64 device tensors (n, 3)."""
+        import torch
+        tgt = sources if targets is None else targets
+        for a in (sources, tgt):
+            assert a.is_cuda and a.dtype == torch.float64 and a.is_contiguous() and a.shape[1] == 3
+        s = torch.cuda.current_stream(sources.device) if stream is None else stream
+        _check(lib().kifmm_update_points(self._h, sources.data_ptr(), tgt.data_ptr(),
+                                         ctypes.c_void_p(s.cuda_stream)))
+        return self
 
     # ---- autotuning -------------------------------------------------------
     def tuning(self) -> dict:

@@ -27,6 +27,9 @@ kifmm_status device_stage(kifmm_handle* h, int level, const void* in, void* out,
                           hipStream_t s);
 kifmm_status device_autotune(kifmm_handle* h, const void* q, int64_t ldq, int nvec, void* phi,
                              int64_t ldphi, hipStream_t s, int reps, double* best_ms);
+kifmm_status device_update_points(kifmm_handle* h, const double* src, const double* tgt,
+                                  hipStream_t s);
+kifmm_status refresh_host_points(kifmm_handle* h);
 
 }  // namespace kifmm
 
@@ -85,6 +88,7 @@ kifmm_status kifmm_set_points(kifmm_handle* h, const double* src, int64_t n_src,
     h->dev = nullptr;
   }
   h->has_points = false;
+  h->points_on_device = false;
   kifmm_status st = kifmm::build_tree(h->tree, h->cfg.depth, h->cfg.origin, h->cfg.width, src, n_src,
                                       tgt, n_tgt);
   if (st != KIFMM_OK) return st;
@@ -162,6 +166,9 @@ kifmm_status kifmm_point_perm(const kifmm_handle* h, int32_t which, int64_t* per
   if (!h || !perm) return fail(KIFMM_EINVAL, "null argument");
   if (!h->has_points) return fail(KIFMM_ESTATE, "no points set");
   if (which != 0 && which != 1) return fail(KIFMM_EINVAL, "which must be 0 or 1");
+  // after device updates the host copy is refreshed from the device
+  kifmm_status st = kifmm::refresh_host_points(const_cast<kifmm_handle*>(h));
+  if (st != KIFMM_OK) return st;
   const auto& p = which == 0 ? h->tree.src_perm : h->tree.tgt_perm;
   if (cap < (int64_t)p.size()) return fail(KIFMM_EINVAL, "capacity too small");
   std::memcpy(perm, p.data(), p.size() * sizeof(int64_t));
@@ -291,6 +298,15 @@ kifmm_status kifmm_timings(const kifmm_handle* h, double* ms, int32_t cap) {
   if (cap < 5) return fail(KIFMM_EINVAL, "capacity too small");
   for (int i = 0; i < cap && i < 12; ++i) ms[i] = h->timings[i];
   return KIFMM_OK;
+}
+
+kifmm_status kifmm_update_points(kifmm_handle* h, const void* src_dev, const void* tgt_dev,
+                                 void* hip_stream) {
+  if (!h || !src_dev || !tgt_dev) return fail(KIFMM_EINVAL, "null argument");
+  if (!h->has_points) return fail(KIFMM_ESTATE, "update_points before set_points");
+  if (!h->op.ready) return fail(KIFMM_ESTATE, "update_points before precompute");
+  return kifmm::device_update_points(h, (const double*)src_dev, (const double*)tgt_dev,
+                                     (hipStream_t)hip_stream);
 }
 
 kifmm_status kifmm_get_tuning(const kifmm_handle* h, int32_t* knobs, int32_t cap) {

@@ -47,6 +47,12 @@ struct DeviceState {
   double* src_xyz = nullptr;
   double* tgt_xyz = nullptr;
   int64_t* src_perm = nullptr;
+  // re-setup for moving points: leaf keys of the tree, scratch (lazy)
+  uint64_t* leaf_keys = nullptr;
+  int32_t* setup_scratch = nullptr;
+  int32_t* leaf_src = nullptr;
+  int32_t* leaf_tgt = nullptr;
+  int32_t* bad_flag = nullptr;
   int64_t* tgt_perm = nullptr;
   int32_t *src_start = nullptr, *src_end = nullptr, *tgt_start = nullptr, *tgt_end = nullptr;
   int64_t* near_offs = nullptr;
@@ -362,6 +368,7 @@ kifmm_status upload_all(kifmm_handle* h) {
   KIFMM_TRY(upload(d, &d->tgt_end, t.tgt_end.data(), t.tgt_end.size()));
   KIFMM_TRY(upload(d, &d->near_offs, t.near_offs.data(), t.near_offs.size()));
   KIFMM_TRY(upload(d, &d->near_src, t.near_src.data(), t.near_src.size()));
+  KIFMM_TRY(upload(d, &d->leaf_keys, t.levels[depth].keys.data(), t.levels[depth].keys.size()));
   {
     const Level& L = t.levels[depth];
     const double w = t.width / std::ldexp(1.0, depth);
@@ -958,6 +965,71 @@ kifmm_status device_autotune(kifmm_handle* h, const void* q, int64_t ldq, int nv
   }
   std::copy(chosen.begin(), chosen.end(), h->tune);
   if (best_ms) *best_ms = best;
+  return KIFMM_OK;
+}
+
+// Moving points: bin the new positions into the current leaves and sort
+// them on the device; the box set, lists and operators stay.  Nothing is
+// changed unless every point falls into a current leaf.
+kifmm_status device_update_points(kifmm_handle* h, const double* src, const double* tgt,
+                                  hipStream_t s) {
+  if (!h->dev) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0)
+      return fail(KIFMM_EDEVICE, "no HIP device available");
+    if (h->cfg.device < 0 || h->cfg.device >= count)
+      return fail(KIFMM_EINVAL, "device ordinal out of range");
+    kifmm_status st = upload_all(h);
+    if (st != KIFMM_OK) {
+      destroy_device(h->dev);
+      h->dev = nullptr;
+      return st;
+    }
+  }
+  DeviceState* d = h->dev;
+  KIFMM_HIP(hipSetDevice(d->device));
+  const Tree& t = h->tree;
+  const Level& L = t.levels[t.depth];
+  const int64_t nmax = std::max(t.n_src, t.n_tgt);
+  if (!d->setup_scratch) {
+    KIFMM_TRY(dalloc(d, &d->setup_scratch, sort_scratch_ints(nmax, L.n)));
+    KIFMM_TRY(dalloc(d, &d->leaf_src, (size_t)t.n_src));
+    KIFMM_TRY(dalloc(d, &d->leaf_tgt, (size_t)t.n_tgt));
+    KIFMM_TRY(dalloc(d, &d->bad_flag, 1));
+  }
+  KIFMM_HIP(hipMemsetAsync(d->bad_flag, 0, sizeof(int32_t), s));
+  KIFMM_LAUNCH(launch_point_leaf(src, t.n_src, d->leaf_keys, L.n, t.depth, t.origin, t.width,
+                                 d->leaf_src, d->bad_flag, s));
+  KIFMM_LAUNCH(launch_point_leaf(tgt, t.n_tgt, d->leaf_keys, L.n, t.depth, t.origin, t.width,
+                                 d->leaf_tgt, d->bad_flag, s));
+  int32_t bad = 0;
+  KIFMM_HIP(hipMemcpyAsync(&bad, d->bad_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  KIFMM_HIP(hipStreamSynchronize(s));
+  if (bad) return fail(KIFMM_ESTATE, "a point lies outside the current leaves; call kifmm_set_points");
+  KIFMM_LAUNCH(launch_sort_by_leaf(src, d->leaf_src, t.n_src, L.n, d->setup_scratch, d->src_perm,
+                                   d->src_xyz, d->src_start, d->src_end, s));
+  KIFMM_LAUNCH(launch_sort_by_leaf(tgt, d->leaf_tgt, t.n_tgt, L.n, d->setup_scratch, d->tgt_perm,
+                                   d->tgt_xyz, d->tgt_start, d->tgt_end, s));
+  h->points_on_device = true;
+  return KIFMM_OK;
+}
+
+// The device's point order back into the host tree (after device updates).
+kifmm_status refresh_host_points(kifmm_handle* h) {
+  if (!h->points_on_device || !h->dev) return KIFMM_OK;
+  DeviceState* d = h->dev;
+  Tree& t = h->tree;
+  KIFMM_HIP(hipSetDevice(d->device));
+  KIFMM_HIP(hipDeviceSynchronize());
+  KIFMM_HIP(hipMemcpy(t.src_perm.data(), d->src_perm, t.src_perm.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+  KIFMM_HIP(hipMemcpy(t.tgt_perm.data(), d->tgt_perm, t.tgt_perm.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+  KIFMM_HIP(hipMemcpy(t.src_sorted.data(), d->src_xyz, t.src_sorted.size() * sizeof(double), hipMemcpyDeviceToHost));
+  KIFMM_HIP(hipMemcpy(t.tgt_sorted.data(), d->tgt_xyz, t.tgt_sorted.size() * sizeof(double), hipMemcpyDeviceToHost));
+  KIFMM_HIP(hipMemcpy(t.src_start.data(), d->src_start, t.src_start.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  KIFMM_HIP(hipMemcpy(t.src_end.data(), d->src_end, t.src_end.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  KIFMM_HIP(hipMemcpy(t.tgt_start.data(), d->tgt_start, t.tgt_start.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  KIFMM_HIP(hipMemcpy(t.tgt_end.data(), d->tgt_end, t.tgt_end.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  h->points_on_device = false;
   return KIFMM_OK;
 }
 

@@ -122,4 +122,5 @@ struct kifmm_handle {
   bool timing = false;
   double timings[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   int32_t tune[KIFMM_TUNE_COUNT] = {0, 0, 0};  // autotuning knobs (kifmm.h)
+  bool points_on_device = false;  // host copies of the point order are stale
 };

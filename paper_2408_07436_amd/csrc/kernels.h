@@ -33,6 +33,22 @@ hipError_t launch_leaf_eval(const double* tgt_xyz, const double* src_xyz, double
                             int ns, const double* local, const int64_t* tgt_perm, void* phi,
                             int64_t ldphi, int nvec, int mode, hipStream_t stream);
 
+// ---- device re-setup for moving points -------------------------------------
+// leaf[i] = index of point i's leaf in the sorted leaf keys of the given
+// depth, or -1 (and *bad = 1) if the point is outside the domain cube or its
+// leaf is not among the keys.
+hipError_t launch_point_leaf(const double* pts, int64_t n, const uint64_t* leaf_keys,
+                             int64_t n_leaf, int depth, const double origin[3], double width,
+                             int32_t* leaf, int32_t* bad, hipStream_t s);
+// int32 scratch entries launch_sort_by_leaf needs for n points and n_leaf leaves.
+size_t sort_scratch_ints(int64_t n, int64_t n_leaf);
+// Stable sort of pts[n][3] by leaf (every leaf[i] in [0, n_leaf)): perm[i]
+// = original index at sorted position i, sorted[n][3], and per leaf the
+// range [start, end) of its points.  pts must not alias the outputs.
+hipError_t launch_sort_by_leaf(const double* pts, const int32_t* leaf, int64_t n, int64_t n_leaf,
+                               int32_t* scratch, int64_t* perm, double* sorted, int32_t* start,
+                               int32_t* end, hipStream_t s);
+
 // FP64 GEMM with gathered columns: C(:, col) = alpha * A * B(:, col) (+ C).
 // Columns are (box, v) pairs, col = box * nvec + v.  B's row k of column
 // (b, v) lives at B[bb * b_box + v * b_vec + k % ks] with

@@ -168,3 +168,15 @@ def test_tuning_knobs_host():
     rc = lib.kifmm_autotune(f._h, ctypes.c_void_p(1), 499, 1, ctypes.c_void_p(1), 500, None, 3,
                             ctypes.byref(best))
     assert rc == 1
+
+
+def test_update_points_argument_errors():
+    """Refused before any device use: null buffers, no points, no operators."""
+    lib = K.lib()
+    f = K.KiFMM(4, 3)
+    one = ctypes.c_void_p(1)
+    assert lib.kifmm_update_points(f._h, None, one, None) == 1
+    assert lib.kifmm_update_points(f._h, one, one, None) == 2
+    f.set_points(workloads.uniform_cube(500, 60))
+    assert lib.kifmm_update_points(f._h, one, one, None) == 2
+    assert b"precompute" in lib.kifmm_last_error()
