@@ -76,6 +76,7 @@ struct DeviceState {
   bool two_stage = false;
   int64_t* op_off = nullptr;
   int32_t* ktp = nullptr;
+  int ktp_max = 0;
   void* op_hi = nullptr;
   void* op_lo = nullptr;
   int tile_tb = 0;            // target boxes per tile of the current tiles
@@ -210,6 +211,7 @@ kifmm_status pack_blas_operators(kifmm_handle* h, DeviceState* d) {
   }
   KIFMM_TRY(upload(d, &d->op_off, off.data(), off.size()));
   KIFMM_TRY(upload(d, &d->ktp, ktp.data(), ktp.size()));
+  d->ktp_max = *std::max_element(ktp.begin(), ktp.end());
   if (mode == 0) {
     double* p;
     KIFMM_TRY(upload(d, &p, packed.data(), packed.size()));
@@ -627,6 +629,7 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
   b.tl_src = D.tl_src;
   b.op_off = d->op_off;
   b.ktp = d->ktp;
+  b.ktp_max = d->ktp_max;
   b.op_hi = d->op_hi;
   b.op_lo = d->op_lo;
   b.out = dense ? out : d->tmp2;

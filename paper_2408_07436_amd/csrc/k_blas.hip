@@ -78,10 +78,13 @@ __device__ inline ColInfo columns(const BlasM2L& a, int wave, int l16) {
 }
 
 // ---- FP32 / FP64 -----------------------------------------------------------
-template <typename T, bool TWO>
-__global__ __launch_bounds__(256) void blas_m2l_kernel(BlasM2L a) {
+// RB / KB: accumulator row blocks (k_pad / 16) and Xi row blocks (k_t pad
+// / 16) the instance holds registers for; the launcher takes the smallest
+// instance that covers the operators, so FP64 fits two waves per SIMD.
+template <typename T, bool TWO, int RB, int KB>
+__global__ __launch_bounds__(256, (sizeof(T) == 8 ? (RB > 8 ? 1 : 2) : (RB > 8 ? 2 : 3))) void blas_m2l_kernel(BlasM2L a) {
   using V4 = typename std::conditional<sizeof(T) == 4, v4f, v4d>::type;
-  constexpr int kMaxKB = 3;  // Xi row blocks: k_t pad <= 48
+  constexpr int kMaxKB = KB;
   const int tile = blockIdx.x;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int l16 = lane % 16, g4 = lane / 16;
@@ -89,9 +92,9 @@ __global__ __launch_bounds__(256) void blas_m2l_kernel(BlasM2L a) {
   const T* q = static_cast<const T*>(a.q);
   const T* ops = static_cast<const T*>(a.op_hi);
   const ColInfo ci = columns(a, wave, l16);
-  V4 acc[kMaxRB][2];
+  V4 acc[RB][2];
 #pragma unroll
-  for (int rb = 0; rb < kMaxRB; ++rb)
+  for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) acc[rb][ct] = V4{T(0), T(0), T(0), T(0)};
 
@@ -136,7 +139,7 @@ __global__ __launch_bounds__(256) void blas_m2l_kernel(BlasM2L a) {
         }
       }
 #pragma unroll
-      for (int rb = 0; rb < kMaxRB; ++rb) {
+      for (int rb = 0; rb < RB; ++rb) {
         if (rb < nrb) {
 #pragma unroll
           for (int rx = 0; rx < kMaxKB; ++rx) {
@@ -162,7 +165,7 @@ __global__ __launch_bounds__(256) void blas_m2l_kernel(BlasM2L a) {
         for (int ct = 0; ct < 2; ++ct)
           bq[ct] = qp[ct] ? ld4(qp[ct] + kb + 4 * g4) : V4{T(0), T(0), T(0), T(0)};
 #pragma unroll
-        for (int rb = 0; rb < kMaxRB; ++rb) {
+        for (int rb = 0; rb < RB; ++rb) {
           if (rb < nrb) {
             const V4 ac = ld4(Vt + (int64_t)(rb * 16 + l16) * a.kp + kb + 4 * g4);
 #pragma unroll
@@ -186,7 +189,7 @@ __global__ __launch_bounds__(256) void blas_m2l_kernel(BlasM2L a) {
     if (box < 0) continue;
     double* dst = a.out + ((int64_t)box * a.nvec + ci.v[ct]) * a.k;
 #pragma unroll
-    for (int rb = 0; rb < kMaxRB; ++rb) {
+    for (int rb = 0; rb < RB; ++rb) {
       if (rb < nrb) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -202,6 +205,7 @@ __global__ __launch_bounds__(256) void blas_m2l_kernel(BlasM2L a) {
 // ---- BF16 x 3 ----------------------------------------------------------------
 template <bool TWO>
 __global__ __launch_bounds__(256) void blas_m2l_bf16_kernel(BlasM2L a) {
+  constexpr int RB = kMaxRB;
   constexpr int kMaxKB = 4;  // Xi row blocks: k_t pad <= 64
   const int tile = blockIdx.x;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -211,9 +215,9 @@ __global__ __launch_bounds__(256) void blas_m2l_bf16_kernel(BlasM2L a) {
   const __bf16* oph = static_cast<const __bf16*>(a.op_hi);
   const __bf16* opl = static_cast<const __bf16*>(a.op_lo);
   const ColInfo ci = columns(a, wave, l16);
-  v4f acc[kMaxRB][2];
+  v4f acc[RB][2];
 #pragma unroll
-  for (int rb = 0; rb < kMaxRB; ++rb)
+  for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) acc[rb][ct] = v4f{0.f, 0.f, 0.f, 0.f};
 
@@ -285,7 +289,7 @@ __global__ __launch_bounds__(256) void blas_m2l_bf16_kernel(BlasM2L a) {
           split8(x, xh[j][ct], xl[j][ct]);
         }
 #pragma unroll
-      for (int rb = 0; rb < kMaxRB; ++rb) {
+      for (int rb = 0; rb < RB; ++rb) {
         if (rb < nrb) {
 #pragma unroll
           for (int j = 0; j < kMaxKB / 2; ++j) {
@@ -322,7 +326,7 @@ __global__ __launch_bounds__(256) void blas_m2l_bf16_kernel(BlasM2L a) {
           split8(x, bh[ct], bl[ct]);
         }
 #pragma unroll
-        for (int rb = 0; rb < kMaxRB; ++rb) {
+        for (int rb = 0; rb < RB; ++rb) {
           if (rb < nrb) {
             const int64_t o = off + (int64_t)(rb * 16 + l16) * a.kp + kb + 8 * g4;
             const v8bf ah = ld8bf(oph + o), al = ld8bf(opl + o);
@@ -344,7 +348,7 @@ __global__ __launch_bounds__(256) void blas_m2l_bf16_kernel(BlasM2L a) {
     if (box < 0) continue;
     double* dst = a.out + ((int64_t)box * a.nvec + ci.v[ct]) * a.k;
 #pragma unroll
-    for (int rb = 0; rb < kMaxRB; ++rb) {
+    for (int rb = 0; rb < RB; ++rb) {
       if (rb < nrb) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -373,12 +377,29 @@ hipError_t launch_blas_m2l(const BlasM2L& a, int mode, bool two_stage, hipStream
   if (a.ntiles == 0) return hipSuccess;
   if (a.kp > 16 * kMaxRB || a.C > 128) return hipErrorInvalidValue;
   const dim3 grid((unsigned)a.ntiles), block(256);
-  if (mode == 0) {
-    if (two_stage) blas_m2l_kernel<double, true><<<grid, block, 0, stream>>>(a);
-    else blas_m2l_kernel<double, false><<<grid, block, 0, stream>>>(a);
-  } else if (mode == 1) {
-    if (two_stage) blas_m2l_kernel<float, true><<<grid, block, 0, stream>>>(a);
-    else blas_m2l_kernel<float, false><<<grid, block, 0, stream>>>(a);
+  if (mode == 0 || mode == 1) {
+    if (two_stage && a.ktp_max > 48) return hipErrorInvalidValue;
+    const int nrb = a.kp / 16;
+    const int rb = nrb <= 4 ? 4 : nrb <= 8 ? 8 : 10;
+    const int kb = two_stage ? (a.ktp_max <= 16 ? 1 : a.ktp_max <= 32 ? 2 : 3) : 1;
+#define KIFMM_BLAS(TT, TW, RR, KK) blas_m2l_kernel<TT, TW, RR, KK><<<grid, block, 0, stream>>>(a)
+#define KIFMM_BLAS_KB(TT, RR)                 \
+  if (!two_stage) KIFMM_BLAS(TT, false, RR, 1); \
+  else if (kb == 1) KIFMM_BLAS(TT, true, RR, 1); \
+  else if (kb == 2) KIFMM_BLAS(TT, true, RR, 2); \
+  else KIFMM_BLAS(TT, true, RR, 3);
+#define KIFMM_BLAS_RB(TT)                     \
+  if (rb == 4) { KIFMM_BLAS_KB(TT, 4) }       \
+  else if (rb == 8) { KIFMM_BLAS_KB(TT, 8) }  \
+  else { KIFMM_BLAS_KB(TT, 10) }
+    if (mode == 0) {
+      KIFMM_BLAS_RB(double)
+    } else {
+      KIFMM_BLAS_RB(float)
+    }
+#undef KIFMM_BLAS_RB
+#undef KIFMM_BLAS_KB
+#undef KIFMM_BLAS
   } else {
     if (two_stage) blas_m2l_bf16_kernel<true><<<grid, block, 0, stream>>>(a);
     else blas_m2l_bf16_kernel<false><<<grid, block, 0, stream>>>(a);
