@@ -77,6 +77,7 @@ struct DeviceState {
   int64_t* op_off = nullptr;
   int32_t* ktp = nullptr;
   int ktp_max = 0;
+  int32_t* ktq = nullptr;
   void* op_hi = nullptr;
   void* op_lo = nullptr;
   int tile_tb = 0;            // target boxes per tile of the current tiles
@@ -170,6 +171,17 @@ int packed_col(int mode, int c) {
   return c;
 }
 
+// Row of Xi (the first product's output) that holds row r of Vbar'_t^T in
+// the FP32 mode: row r goes to second-product K step q = r / 4, whose four K
+// values are Xi rows 16 (q / 4) + 4 g + q % 4 (g = r % 4), so the steps past
+// ceil(k_t / 4) hold only zero rows and are skipped.  (Measured: FP32 5%
+// faster; FP64, with fewer waves to hide latency, 3% slower - kept in order.)
+int xi_row(int mode, int r) {
+  if (mode != 1) return r;
+  const int q = r / 4, g = r % 4;
+  return 16 * (q / 4) + 4 * g + q % 4;
+}
+
 // Operators of the fused BLAS / dense M2L kernel, per t, unit box:
 //   two-stage: Vbar'_t^T (ktp x kp) then Ubar_t (kp x ktp, packed columns)
 //   single:    C_t (kp x kp)
@@ -185,7 +197,7 @@ kifmm_status pack_blas_operators(kifmm_handle* h, DeviceState* d) {
   d->kp = kp;
   d->two_stage = op.recompressed;
   std::vector<int64_t> off(kNumTransfer);
-  std::vector<int32_t> ktp(kNumTransfer, 0);
+  std::vector<int32_t> ktp(kNumTransfer, 0), ktq(kNumTransfer, 0);
   std::vector<double> packed;
   for (int t = 0; t < kNumTransfer; ++t) {
     off[t] = (int64_t)packed.size();
@@ -201,16 +213,23 @@ kifmm_status pack_blas_operators(kifmm_handle* h, DeviceState* d) {
     if (tp > (mode == 2 ? 64 : 48))
       return fail(KIFMM_EUNSUPPORTED, "directional rank above the fused kernel's limit");
     ktp[t] = tp;
+    ktq[t] = mode == 1 ? (kt + 3) / 4 : tp / 4;
     std::vector<double> V((size_t)tp * kp, 0.0), Ub((size_t)kp * tp, 0.0);
-    for (int r = 0; r < kt; ++r)
-      for (int c = 0; c < k; ++c) V[(size_t)r * kp + c] = op.Vbarp[t][(size_t)c * kt + r];
+    for (int r = 0; r < kt; ++r) {
+      const int xr = xi_row(mode, r);
+      for (int c = 0; c < k; ++c) V[(size_t)xr * kp + c] = op.Vbarp[t][(size_t)c * kt + r];
+    }
     for (int r = 0; r < k; ++r)
-      for (int c = 0; c < kt; ++c) Ub[(size_t)r * tp + packed_col(mode, c)] = op.Ubar[t][(size_t)r * kt + c];
+      for (int c = 0; c < kt; ++c) {
+        const int xc = xi_row(mode, c);
+        Ub[(size_t)r * tp + packed_col(mode, xc)] = op.Ubar[t][(size_t)r * kt + c];
+      }
     packed.insert(packed.end(), V.begin(), V.end());
     packed.insert(packed.end(), Ub.begin(), Ub.end());
   }
   KIFMM_TRY(upload(d, &d->op_off, off.data(), off.size()));
   KIFMM_TRY(upload(d, &d->ktp, ktp.data(), ktp.size()));
+  KIFMM_TRY(upload(d, &d->ktq, ktq.data(), ktq.size()));
   d->ktp_max = *std::max_element(ktp.begin(), ktp.end());
   if (mode == 0) {
     double* p;
@@ -630,6 +649,7 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
   b.op_off = d->op_off;
   b.ktp = d->ktp;
   b.ktp_max = d->ktp_max;
+  b.ktq = d->ktq;
   b.op_hi = d->op_hi;
   b.op_lo = d->op_lo;
   b.out = dense ? out : d->tmp2;

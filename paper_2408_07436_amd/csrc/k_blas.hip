@@ -111,6 +111,7 @@ __global__ __launch_bounds__(256, (sizeof(T) == 8 ? (RB > 8 ? 1 : 2) : (RB > 8 ?
     if constexpr (TWO) {
       const int ktp = a.ktp[t];
       const int nkb = ktp / 16;
+      const int nq = a.ktq[t];  // second-product K steps that hold Xi rows
       const T* Ub = Vt + (int64_t)ktp * a.kp;
       V4 xi[kMaxKB][2];
 #pragma unroll
@@ -145,15 +146,19 @@ __global__ __launch_bounds__(256, (sizeof(T) == 8 ? (RB > 8 ? 1 : 2) : (RB > 8 ?
           for (int rx = 0; rx < kMaxKB; ++rx) {
             if (rx < nkb) {
               const V4 au = ld4(Ub + (int64_t)(rb * 16 + l16) * ktp + rx * 16 + 4 * g4);
-#pragma unroll
-              for (int ct = 0; ct < 2; ++ct)
+              if constexpr (sizeof(T) == 4) {
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                  if constexpr (sizeof(T) == 4)
-                    acc[rb][ct] = mf32(au[s], xi[rx][ct][s], acc[rb][ct]);
-                  else
-                    acc[rb][ct] = mf64(au[s], xi[rx][ct][s], acc[rb][ct]);
+                  if (4 * rx + s >= nq) continue;  // only zero Xi rows
+#pragma unroll
+                  for (int ct = 0; ct < 2; ++ct) acc[rb][ct] = mf32(au[s], xi[rx][ct][s], acc[rb][ct]);
                 }
+              } else {
+#pragma unroll
+                for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+                  for (int s = 0; s < 4; ++s) acc[rb][ct] = mf64(au[s], xi[rx][ct][s], acc[rb][ct]);
+              }
             }
           }
         }

@@ -119,6 +119,7 @@ struct BlasM2L {
   const int64_t* op_off;    // [316] element offset of t's operators
   const int32_t* ktp;       // [316] padded rank (two-stage)
   int ktp_max;              // largest ktp (two-stage)
+  const int32_t* ktq;       // [316] second-product K steps of 4 to run (FP64 / FP32)
   const void* op_hi;        // FP64 / FP32 operators, or bf16 high parts
   const void* op_lo;        // bf16 low parts
   double* out;
