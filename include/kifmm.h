@@ -261,6 +261,7 @@ kifmm_status kifmm_set_tuning(kifmm_handle* h, const int32_t* knobs, int32_t n);
  * the setting with the smallest median evaluate time, and writes that time
  * to *best_ms (if not NULL).  phi_dev holds the last evaluate's potentials.
  * Runs untimed whatever kifmm_set_timing says; synchronises hip_stream.
+ * On an error the knobs are left as they were.
  * EINVAL: bad arguments or a capturing stream; ESTATE: as evaluate. */
 kifmm_status kifmm_autotune(kifmm_handle* h, const void* q_dev, int64_t ldq, int32_t n_vec,
                             void* phi_dev, int64_t ldphi, void* hip_stream, int32_t reps,

@@ -953,16 +953,19 @@ kifmm_status device_autotune(kifmm_handle* h, const void* q, int64_t ldq, int nv
       cand.push_back(c);
     }
   }
-  struct Restore {  // events and the timing switch, on every exit
+  struct Restore {  // events, the timing switch and (on errors) the knobs
     kifmm_handle* h;
     bool timing;
+    Knobs knobs;
+    bool done = false;
     hipEvent_t e[2] = {nullptr, nullptr};
     ~Restore() {
       h->timing = timing;
+      if (!done) std::copy(knobs.begin(), knobs.end(), h->tune);
       for (hipEvent_t ev : e)
         if (ev) (void)hipEventDestroy(ev);
     }
-  } guard{h, h->timing};
+  } guard{h, h->timing, base};
   h->timing = false;
   KIFMM_HIP(hipEventCreate(&guard.e[0]));
   KIFMM_HIP(hipEventCreate(&guard.e[1]));
@@ -987,6 +990,7 @@ kifmm_status device_autotune(kifmm_handle* h, const void* q, int64_t ldq, int nv
     }
   }
   std::copy(chosen.begin(), chosen.end(), h->tune);
+  guard.done = true;
   if (best_ms) *best_ms = best;
   return KIFMM_OK;
 }
