@@ -399,6 +399,7 @@ def main():
     ap.add_argument("--no-blas", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-scale", action="store_true")
+    ap.add_argument("--no-resetup", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the FMM here is a single-GPU build "
@@ -541,8 +542,9 @@ def main():
                          "(8 cores); 240 ms on AMD 3790X at depth 4 (32 cores) - CPU context only",
         "setup_s": {"fp32": round(mix["setup_s"], 2), "fp64": round(ref["setup_s"], 2)},
     }
-    log("moving points: host tree build vs device re-setup")
-    line["resetup_1M"] = run_resetup(K, torch, w)
+    if not args.no_resetup:
+        log("moving points: host tree build vs device re-setup")
+        line["resetup_1M"] = run_resetup(K, torch, w)
     if not args.no_blas:
         log("blas-m2l workload: 32 vectors, fp64 / fp32 / bf16x3")
         line["blas_32rhs"] = run_blas(K, torch, max(1, min(args.steps, 3)), 1)
