@@ -22,14 +22,15 @@ struct DevLevel {
   void* Phat = nullptr;
   double* chk = nullptr;
   // FFT-M2L source blocks: the clusters of one aligned 4 x 4 x 4 cube of
-  // level l-1 (consecutive in Morton order) share one list of at most 216
-  // source clusters with LDS slots; slots[c] holds, per direction, the LDS
-  // byte offset of cluster c's neighbour's row (26 x 16 bits in 13 words)
+  // level l-1 (consecutive in Morton order) share one list of the at most
+  // 216 source clusters of the cube's 6 x 6 x 6 shell, each at the slot of
+  // its shell position; tbase[c] is (slot(c) - kHadSlotBias) * kHadRowBytes
   int64_t hb_n = 0;
   int32_t* hb_tgt = nullptr;    // [hb_n + 1] first cluster of each block
   int32_t* hb_src = nullptr;    // [hb_n + 1] offsets into hb_list
-  int32_t* hb_list = nullptr;   // cluster << 8 | slot (the empty cluster n_{l-1} included)
-  uint32_t* hb_slots = nullptr; // [n_{l-1}][13]: 26 LDS byte offsets (16 bits each)
+  int32_t* hb_list = nullptr;   // cluster << 8 | slot (the empty cluster n_{l-1} included);
+                                // entry 0 is the empty cluster at slot 255
+  int32_t* hb_tbase = nullptr;  // [n_{l-1}] LDS byte offset of the cluster's own slot, biased
   // BLAS / dense M2L: target tiles of one octant class and, per tile, the
   // transfer vectors present with the source box of every tile slot
   int64_t ntiles = 0;
@@ -309,53 +310,53 @@ kifmm_status build_blas_tiles(kifmm_handle* h, DeviceState* d, int TB) {
 }
 
 // Source blocks of one FFT-M2L level (see DevLevel): clusters grouped by
-// Morton key >> 6 (aligned 4 x 4 x 4 cubes); each block lists the distinct
-// clusters its members' halos reach, each with a slot 8 r + the parity class
-// (x & 1) + 2 (y & 1) + 4 (z & 1) of its position, r counting within the
-// class, so the clusters of any aligned 2 x 2 x 2 cube get distinct slots
-// modulo 8.  The empty cluster (index nc) takes a free slot.
+// Morton key >> 6 (aligned 4 x 4 x 4 cubes).  A block's sources sit at fixed
+// slots, their positions in the 6 x 6 x 6 shell around the cube
+// (slot = x + 6 y + 36 z, shell coordinates 0..5), so the cluster in
+// direction D of a member at slot s is at slot s + D_x + 6 D_y + 36 D_z and
+// the kernel needs one base offset per member, not a table per direction.
+// The list names every slot some member's halo reaches, with the empty
+// cluster (index nc, zero spectra) where no cluster is present.
 static kifmm_status build_source_blocks(DeviceState* d, DevLevel& D, const Level& up,
                                         const std::vector<int32_t>& halo) {
   const int64_t nc = up.n;
-  std::vector<int32_t> tgt, src, list;
-  std::vector<uint32_t> slots((size_t)nc * 13, 0u);
+  std::vector<int32_t> tgt, src, list, tbase((size_t)nc, 0);
+  int doff[kNumDirections];
+  for (int dd = 0; dd < kNumDirections; ++dd) {
+    int v[3];
+    direction_vector(dd, v);
+    doff[dd] = v[0] + kHadShell * v[1] + kHadShell * kHadShell * v[2];
+  }
+  std::vector<int32_t> at(kHadSrcSlots);
+  // entry 0: the empty cluster at slot 255, taken by staging lanes past a
+  // block's list (their LDS writes land in a discard area)
+  list.push_back((int32_t)((uint32_t)nc << 8 | 255u));
   int64_t c = 0;
   while (c < nc) {
     const uint64_t bk = up.keys[c] >> 6;
     int64_t e = c;
     while (e < nc && (up.keys[e] >> 6) == bk) ++e;
-    std::vector<int32_t> u;
-    u.reserve((size_t)(e - c) * kNumDirections);
-    for (int64_t i = c; i < e; ++i)
-      for (int dd = 0; dd < kNumDirections; ++dd) u.push_back(halo[(size_t)dd * nc + i]);
-    std::sort(u.begin(), u.end());
-    u.erase(std::unique(u.begin(), u.end()), u.end());
-    int count[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    std::vector<int32_t> slot_of(u.size(), -1);
-    for (size_t k = 0; k < u.size(); ++k) {
-      if (u[k] == nc) continue;
-      const int32_t* an = &up.anchor[3 * (size_t)u[k]];
-      const int par = (an[0] & 1) + 2 * (an[1] & 1) + 4 * (an[2] & 1);
-      slot_of[k] = 8 * count[par]++ + par;
+    std::fill(at.begin(), at.end(), -1);
+    const int32_t* a0 = &up.anchor[3 * (size_t)c];
+    for (int64_t i = c; i < e; ++i) {
+      const int32_t* an = &up.anchor[3 * (size_t)i];
+      if ((an[0] >> 2) != (a0[0] >> 2) || (an[1] >> 2) != (a0[1] >> 2) || (an[2] >> 2) != (a0[2] >> 2))
+        return fail(KIFMM_ENUMERIC, "FFT-M2L source block is not an aligned 4 x 4 x 4 cube");
+      const int own = ((an[0] & 3) + 1) + kHadShell * ((an[1] & 3) + 1) +
+                      kHadShell * kHadShell * ((an[2] & 3) + 1);
+      tbase[(size_t)i] = (own - kHadSlotBias) * kHadRowBytes;
+      for (int dd = 0; dd < kNumDirections; ++dd) {
+        const int slot = own + doff[dd];
+        const int32_t s = halo[(size_t)dd * nc + i];
+        if (at[(size_t)slot] >= 0 && at[(size_t)slot] != s)
+          return fail(KIFMM_ENUMERIC, "FFT-M2L halo disagrees with the cluster positions");
+        at[(size_t)slot] = s;
+      }
     }
-    for (size_t k = 0; k < u.size(); ++k) {
-      if (u[k] != nc) continue;
-      int par = 0;
-      while (par < 8 && count[par] >= 27) ++par;
-      if (par == 8) return fail(KIFMM_ENUMERIC, "FFT-M2L source block has no free slot");
-      slot_of[k] = 8 * count[par]++ + par;
-    }
-    for (int par = 0; par < 8; ++par)
-      if (count[par] > 27) return fail(KIFMM_ENUMERIC, "FFT-M2L source block exceeds 216 slots");
     tgt.push_back((int32_t)c);
     src.push_back((int32_t)list.size());
-    for (int64_t i = c; i < e; ++i)
-      for (int dd = 0; dd < kNumDirections; ++dd) {
-        const int32_t s = halo[(size_t)dd * nc + i];
-        const size_t k = (size_t)(std::lower_bound(u.begin(), u.end(), s) - u.begin());
-        slots[(size_t)i * 13 + dd / 2] |= (uint32_t)(slot_of[k] * kHadRowBytes) << (16 * (dd % 2));
-      }
-    for (size_t k = 0; k < u.size(); ++k) list.push_back((int32_t)((uint32_t)u[k] << 8 | (uint32_t)slot_of[k]));
+    for (int slot = 0; slot < kHadSrcSlots; ++slot)
+      if (at[(size_t)slot] >= 0) list.push_back((int32_t)((uint32_t)at[(size_t)slot] << 8 | (uint32_t)slot));
     c = e;
   }
   D.hb_n = (int64_t)tgt.size();
@@ -364,7 +365,7 @@ static kifmm_status build_source_blocks(DeviceState* d, DevLevel& D, const Level
   KIFMM_TRY(upload(d, &D.hb_tgt, tgt.data(), tgt.size()));
   KIFMM_TRY(upload(d, &D.hb_src, src.data(), src.size()));
   KIFMM_TRY(upload(d, &D.hb_list, list.data(), list.size()));
-  KIFMM_TRY(upload(d, &D.hb_slots, slots.data(), slots.size()));
+  KIFMM_TRY(upload(d, &D.hb_tbase, tbase.data(), tbase.size()));
   return KIFMM_OK;
 }
 
@@ -612,7 +613,7 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
                                     d->twiddle, D.Qhat, s));
     if (mark) KIFMM_HIP(hipEventRecord(mark[1], s));
     KIFMM_LAUNCH(launch_hadamard(d->fp64, op.F, d->khat, D.Qhat, D.halo, D.hb_n, D.hb_tgt,
-                                 D.hb_src, D.hb_list, D.hb_slots, nc, nvec,
+                                 D.hb_src, D.hb_list, D.hb_tbase, nc, nvec,
                                  h->tune[KIFMM_TUNE_HADAMARD] == 1, D.Phat, s));
     if (mark) KIFMM_HIP(hipEventRecord(mark[2], s));
     const double scale = 1.0 / ((double)op.n * op.n * op.n * D.w);  // 1 / (n^3 w)

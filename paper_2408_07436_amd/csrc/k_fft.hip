@@ -519,32 +519,48 @@ __global__ __launch_bounds__(kHadThreads) void hadamard_gather_kernel(
   }
 }
 
-constexpr int kHadSrcMax = 216;  // source slots of one 4 x 4 x 4 block: its 6 x 6 x 6 shell
+constexpr int kHadSrcMax = kHadSrcSlots;  // source slots of one 4 x 4 x 4 block: its 6 x 6 x 6 shell
 static_assert(kHadRowBytes % 16 == 0 && kHadRowBytes >= 64, "LDS row of 16 floats");
 constexpr int kHadStage = (kHadSrcMax * 4 + kHadThreads - 1) / kHadThreads;
+constexpr int kHadDiscard = kHadSrcMax * kHadRowBytes;  // LDS bytes past the slots
+
+// Byte offset, relative to a cluster's biased base, of its neighbour in
+// direction d (the 26 offsets of {-1, 0, 1}^3 \ {0} in lexicographic order,
+// x slowest): a compile-time constant once the direction loop is unrolled.
+__host__ __device__ constexpr int had_dir_bytes(int d) {
+  return (kHadSlotBias + ((d < 13 ? d : d + 1) / 9 - 1) +
+          kHadShell * ((d < 13 ? d : d + 1) / 3 % 3 - 1) +
+          kHadShell * kHadShell * ((d < 13 ? d : d + 1) % 3 - 1)) *
+         kHadRowBytes;
+}
+static_assert(had_dir_bytes(0) == 0 && had_dir_bytes(25) == 2 * kHadSlotBias * kHadRowBytes,
+              "direction offsets span the shell");
 
 // Block form (FP32).  Workgroup = one frequency x a run of (block, charge
 // vector) items.  Each lane holds the frequency's B operand for all 26
 // directions in registers (the 416 x 16 real form of the 26 x 8 x 8 complex
 // kernel coefficients, in its operand order).  Per item the spectra of the
 // block's source clusters (at most 216 rows of 16 reals) are staged in LDS
-// - the next item's rows are loaded into registers while the current one
-// computes - and each wave takes one 16-cluster tile of the block's (at
-// most 64) target clusters, reading its A operands at the slots of the
-// clusters' 26 neighbours.  A source slot is 8 x rank + the parity class of
-// the source's position, so the eight clusters of an aligned 2 x 2 x 2 cube
-// (eight consecutive lanes) always read distinct LDS banks.  Every source
-// spectrum crosses the cache hierarchy once per block, and the VALU work per
-// MFMA stays small (on gfx950 the VALU does not co-issue with the MFMA of the
-// same wave).
+// at the slots of their shell positions - the next item's rows are loaded
+// into registers while the current one computes, and the list entries that
+// address them one item earlier still, so no load waits on another inside
+// an item - and each wave takes one 16-cluster tile of the block's (at most
+// 64) target clusters.  A lane's A operand for direction d is read at its
+// cluster's base offset plus a constant, so the eight clusters of an
+// aligned 2 x 2 x 2 cube (eight consecutive lanes) read distinct LDS banks,
+// and the read for the next direction is issued before the current
+// direction's MFMAs.  Every source spectrum crosses the cache hierarchy
+// once per block, and the VALU work per MFMA stays small (on gfx950 the
+// VALU does not co-issue with the MFMA of the same wave).
 __global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_kernel(
     const float2* __restrict__ Khat, const float* __restrict__ Qhat,
     const int32_t* __restrict__ blk_tgt, const int32_t* __restrict__ blk_src,
-    const int32_t* __restrict__ blk_list, const uint32_t* __restrict__ slots, int n_items,
+    const int32_t* __restrict__ blk_list, const int32_t* __restrict__ tbase, int n_items,
     int nvec, int64_t n_rows, int64_t total_items, int64_t unit_len, int64_t n_units,
     int64_t n_wgs, float* __restrict__ Phat) {
   constexpr int kRow = kHadRowBytes / 16;  // LDS row stride in float4: 16 reals + padding
-  __shared__ float4 As[2][kHadSrcMax * kRow + 1];  // + one discard entry
+  constexpr int kBuf = kHadSrcMax * kRow + 4;  // + a 64-byte discard area
+  __shared__ float4 As[2 * kBuf];
   const int64_t b = blockIdx.x;
   const int64_t per_xcd = gridDim.x / 8;  // grid: a multiple of 8
   const int64_t logical = (b % 8) * per_xcd + b / 8;  // consecutive work per XCD
@@ -556,12 +572,26 @@ __global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_kernel(
   const uint32_t row_bytes = 64u * (uint32_t)nvec;  // one cluster's rows
   // staging registers: four 16-byte pieces per thread (216 rows x 4 pieces
   // over 256 threads), named rather than an array so they stay in VGPRs;
-  // piece k is row (tid + 256 k) / 4, quarter tid % 4
+  // piece k is row (tid + 256 k) / 4, quarter tid % 4.  A piece past the
+  // block's list takes the list's first entry, the empty cluster at slot
+  // 255, whose LDS offset is clamped into the discard area.
   static_assert(kHadStage == 4, "staging pieces per thread");
   const uint32_t part_bytes = 16u * (uint32_t)(tid & 3);
   float4 stg0, stg1, stg2, stg3;
-  uint32_t sl0 = 0, sl1 = 0, sl2 = 0, sl3 = 0;
-  uint32_t w[13];  // 26 LDS byte offsets (16 bits each) of the lane's target
+  // list entries of two consecutive items (sets a and b alternate between
+  // steps, so no loaded register is copied) and the lane's target base of
+  // two consecutive items
+  uint32_t ea0 = 0, ea1 = 0, ea2 = 0, ea3 = 0;
+  uint32_t eb0 = 0, eb1 = 0, eb2 = 0, eb3 = 0;
+  uint32_t tba = 0, tbb = 0;
+  float res0 = 0.f, res1 = 0.f, res2 = 0.f, res3 = 0.f;  // products of the last item computed
+  auto entry = [&](int s0, int ns, int k) __attribute__((always_inline)) {
+    const int r = (tid + kHadThreads * k) >> 2;
+    return (uint32_t)blk_list[r < ns ? s0 + r : 0];
+  };
+  auto lds_slot = [&](uint32_t e) __attribute__((always_inline)) {
+    return min((e & 255u) * (uint32_t)kHadRowBytes, (uint32_t)kHadDiscard) + part_bytes;
+  };
   int buf = 0;
   // Units of unit_len consecutive frequency-major (frequency, block, vector)
   // items: this workgroup takes units logical, logical + n_wgs, ..., each in
@@ -587,79 +617,121 @@ __global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_kernel(
   // and products, addressed with 32-bit byte offsets from these bases
   const char* qf = reinterpret_cast<const char*>(Qhat + f * (n_rows + nvec) * 16);
   char* pf = reinterpret_cast<char*>(Phat + f * n_rows * 16);
-  // (block, vector) of the next item to load, and of the item whose rows
-  // sit in the staging registers
-  int lblk = item0 / nvec, lv = item0 - lblk * nvec;
-  int pblk = lblk, pv = lv;
-  // iteration `it` issues the loads of item it (into registers) and then
-  // computes item it - 1, whose rows the previous iteration loaded
-  for (int it = item0; it <= item1; ++it) {
-    const int blk = pblk, v = pv;  // item it - 1
-    if (it > item0) {
-      char* ab = reinterpret_cast<char*>(As[buf]);
-      *reinterpret_cast<float4*>(ab + sl0) = stg0;
-      *reinterpret_cast<float4*>(ab + sl1) = stg1;
-      *reinterpret_cast<float4*>(ab + sl2) = stg2;
-      *reinterpret_cast<float4*>(ab + sl3) = stg3;
-      __syncthreads();  // As[buf] complete; As[buf ^ 1] free for the next item
+  // Software pipeline over the segment's items, one step per item plus two:
+  // step `it` (1) writes the rows of item it - 1 to LDS and stores the
+  // products of item it - 2, (2) issues every global load of item it (rows,
+  // target base) and the list entries of item it + 1, and (3) computes item
+  // it - 1.  A step's loads are consumed only after the next step's single
+  // wait at its top, which the MFMA work of (3) covers, so no wait inside a
+  // step (gfx9 counts loads and stores in one in-order counter) falls on a
+  // load or store issued in the same step.  Block bounds are read one step
+  // ahead as well.
+  int lblk = item0 / nvec, lv = item0 - lblk * nvec;  // item it
+  int cv = 0, ct0 = 0, cnt = 0;  // item it - 1: vector, first cluster, count
+  int sv = 0, st0 = 0, snt = 0;  // item it - 2
+  // bounds kept as loaded (differences taken at their use, a step later,
+  // so that no scalar load is waited for in the step that issues it)
+  int nt0 = blk_tgt[lblk], nt1 = blk_tgt[lblk + 1];  // clusters of item it's block
+  int es0, es1;  // list range of item it + 1
+  {
+    const int s0 = blk_src[lblk], ns = blk_src[lblk + 1] - s0;
+    ea0 = entry(s0, ns, 0);
+    ea1 = entry(s0, ns, 1);
+    ea2 = entry(s0, ns, 2);
+    ea3 = entry(s0, ns, 3);
+    const int b1 = (lv + 1 == nvec) ? lblk + 1 : lblk;
+    const int bb = min(b1, (int)(((int64_t)n_items - 1) / nvec));
+    es0 = blk_src[bb];
+    es1 = blk_src[bb + 1];
+  }
+  auto step = [&](int it, uint32_t& w0, uint32_t& w1, uint32_t& w2, uint32_t& w3, uint32_t u0,
+                  uint32_t u1, uint32_t u2, uint32_t u3, uint32_t tbc, uint32_t& tbn)
+                  __attribute__((always_inline)) {
+    __builtin_amdgcn_s_waitcnt(0);  // the previous step's loads and stores
+    const bool write = it > item0 && it <= item1;  // rows of item it - 1 staged
+    if (write) {
+      char* ab = reinterpret_cast<char*>(As + buf * kBuf);
+      *reinterpret_cast<float4*>(ab + lds_slot(w0)) = stg0;
+      *reinterpret_cast<float4*>(ab + lds_slot(w1)) = stg1;
+      *reinterpret_cast<float4*>(ab + lds_slot(w2)) = stg2;
+      *reinterpret_cast<float4*>(ab + lds_slot(w3)) = stg3;
     }
+    if (it >= item0 + 2 && tr0 < snt) {
+      // row tr0 + 4 g + i of the tile: cluster st0 + that row, vector sv
+      const uint32_t o0 = ((uint32_t)(st0 + tr0 + 4 * g) * nvec + sv) * 64u + 4u * rl;
+      const int rr = tr0 + 4 * g;
+      if (rr + 0 < snt) *reinterpret_cast<float*>(pf + o0) = res0;
+      if (rr + 1 < snt) *reinterpret_cast<float*>(pf + o0 + row_bytes) = res1;
+      if (rr + 2 < snt) *reinterpret_cast<float*>(pf + o0 + 2 * row_bytes) = res2;
+      if (rr + 3 < snt) *reinterpret_cast<float*>(pf + o0 + 3 * row_bytes) = res3;
+    }
+    if (write) __syncthreads();  // this buffer complete; the other one free for the next item
+    sv = cv;
+    st0 = ct0;
+    snt = cnt;
     if (it < item1) {
-      const int s0 = blk_src[lblk], ns = blk_src[lblk + 1] - s0;
-      const int32_t* lst = blk_list + s0;
       const uint32_t vb = (uint32_t)lv * 64u + part_bytes;
-      auto piece = [&](int k, float4& st, uint32_t& sl) __attribute__((always_inline)) {
-        const int r = (tid + kHadThreads * k) >> 2;
-        const int32_t e = lst[r < ns ? r : 0];  // past the list: first entry, discarded
-        st = *reinterpret_cast<const float4*>(qf + (((uint32_t)e >> 8) * row_bytes + vb));
-        sl = r < ns ? (uint32_t)(e & 255) * kHadRowBytes + part_bytes : kHadSrcMax * kHadRowBytes;
-      };
-      piece(0, stg0, sl0);
-      piece(1, stg1, sl1);
-      piece(2, stg2, sl2);
-      piece(3, stg3, sl3);
-      pblk = lblk;
-      pv = lv;
-      if (++lv == nvec) {
-        lv = 0;
-        ++lblk;
+      stg0 = *reinterpret_cast<const float4*>(qf + ((u0 >> 8) * row_bytes + vb));
+      stg1 = *reinterpret_cast<const float4*>(qf + ((u1 >> 8) * row_bytes + vb));
+      stg2 = *reinterpret_cast<const float4*>(qf + ((u2 >> 8) * row_bytes + vb));
+      stg3 = *reinterpret_cast<const float4*>(qf + ((u3 >> 8) * row_bytes + vb));
+      tbn = (uint32_t)tbase[nt0 + min(tr0 + rl, nt1 - nt0 - 1)];
+      if (it + 1 < item1) {
+        w0 = entry(es0, es1 - es0, 0);
+        w1 = entry(es0, es1 - es0, 1);
+        w2 = entry(es0, es1 - es0, 2);
+        w3 = entry(es0, es1 - es0, 3);
       }
     }
-    v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
-    int t0 = 0, nt = 0;
-    if (it > item0) {
-      t0 = blk_tgt[blk];
-      nt = blk_tgt[blk + 1] - t0;
-      const char* ab = reinterpret_cast<const char*>(As[buf]) + 16 * g;
-      buf ^= 1;
-      if (tr0 < nt) {
-        // two accumulators (even / odd directions) so consecutive MFMAs are
-        // independent
+    // item it becomes item it - 1 of the next step; advance to item it + 1
+    const int pnt0 = nt0, pnt1 = nt1, plv = lv;
+    if (++lv == nvec) {
+      lv = 0;
+      ++lblk;
+    }
+    if (it + 1 < item1) {
+      nt0 = blk_tgt[lblk];
+      nt1 = blk_tgt[lblk + 1];
+    }
+    if (it + 2 < item1) {
+      const int b2 = (lv + 1 == nvec) ? lblk + 1 : lblk;  // block of item it + 2
+      es0 = blk_src[b2];
+      es1 = blk_src[b2 + 1];
+    }
+    if (write && tr0 < cnt) {
+      // two accumulators so consecutive MFMAs are independent: K slices x
+      // and y (real and imaginary parts of source children 0, 2, 4, 6) into
+      // one, z and w (children 1, 3, 5, 7) into the other, so each holds
+      // whole complex products and their sum cancels no more than the
+      // products themselves; the next direction's A operand is in flight
+      // while the current one's MFMAs issue
+      const char* ab = reinterpret_cast<const char*>(As + buf * kBuf) + tbc + 16 * g;
+      v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+      float4 an = *reinterpret_cast<const float4*>(ab + had_dir_bytes(0));
 #pragma unroll
-        for (int d = 0; d < 26; ++d) {
-          const uint32_t off = (d & 1) ? (w[d / 2] >> 16) : (w[d / 2] & 0xffffu);
-          const float4 a = *reinterpret_cast<const float4*>(ab + off);
-          v4f& acc = (d & 1) ? acc1 : acc0;
-          acc = mfma16(a.x, B[d].x, acc);
-          acc = mfma16(a.y, B[d].y, acc);
-          acc = mfma16(a.z, B[d].z, acc);
-          acc = mfma16(a.w, B[d].w, acc);
-        }
+      for (int d = 0; d < 26; ++d) {
+        const float4 a = an;
+        if (d + 1 < 26) an = *reinterpret_cast<const float4*>(ab + had_dir_bytes(d + 1));
+        // keep the read above the MFMAs (the scheduler would sink it)
+        __builtin_amdgcn_sched_barrier(0);
+        acc0 = mfma16(a.x, B[d].x, acc0);
+        acc1 = mfma16(a.z, B[d].z, acc1);
+        acc0 = mfma16(a.y, B[d].y, acc0);
+        acc1 = mfma16(a.w, B[d].w, acc1);
       }
+      res0 = acc0[0] + acc1[0];
+      res1 = acc0[1] + acc1[1];
+      res2 = acc0[2] + acc1[2];
+      res3 = acc0[3] + acc1[3];
     }
-    // the LDS offsets of the item just loaded, for the next iteration
-    if (it < item1) {
-      const int nt0 = blk_tgt[pblk], ntn = blk_tgt[pblk + 1] - nt0;
-      const uint32_t* sw = slots + (int64_t)nt0 * 13 + (uint32_t)min(tr0 + rl, ntn - 1) * 13u;
-#pragma unroll
-      for (int k = 0; k < 13; ++k) w[k] = sw[k];
-    }
-    if (it > item0 && tr0 < nt) {
-      // row tr0 + 4 g + i of the tile: cluster t0 + that row, vector v
-      const uint32_t o0 = ((uint32_t)(t0 + tr0 + 4 * g) * nvec + v) * 64u + 4u * rl;
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        if (tr0 + 4 * g + i < nt) *reinterpret_cast<float*>(pf + o0 + i * row_bytes) = acc0[i] + acc1[i];
-    }
+    if (write) buf ^= 1;
+    cv = plv;
+    ct0 = pnt0;
+    cnt = it < item1 ? pnt1 - pnt0 : 0;
+  };
+  for (int it = item0; it <= item1 + 1; it += 2) {
+    step(it, eb0, eb1, eb2, eb3, ea0, ea1, ea2, ea3, tbb, tba);
+    if (it + 1 <= item1 + 1) step(it + 1, ea0, ea1, ea2, ea3, eb0, eb1, eb2, eb3, tba, tbb);
   }
   }
   }
@@ -761,7 +833,7 @@ hipError_t launch_fft_inverse(int p, bool fp64, const void* Phat, const int32_t*
 
 hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
                            const int32_t* halo, int64_t n_blocks, const int32_t* blk_tgt,
-                           const int32_t* blk_src, const int32_t* blk_list, const uint32_t* slots,
+                           const int32_t* blk_src, const int32_t* blk_list, const int32_t* tbase,
                            int64_t n_clusters, int nvec, bool units, void* Phat,
                            hipStream_t stream) {
   const int64_t n_rows = n_clusters * nvec;
@@ -800,7 +872,7 @@ hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
   }
   const unsigned grid = (unsigned)(8 * ((n_wgs + 7) / 8));
   hadamard_block_kernel<<<grid, kHadThreads, 0, stream>>>(
-      (const float2*)Khat, (const float*)Qhat, blk_tgt, blk_src, blk_list, slots, (int)n_items,
+      (const float2*)Khat, (const float*)Qhat, blk_tgt, blk_src, blk_list, tbase, (int)n_items,
       nvec, n_rows, total, unit_len, n_units, n_wgs, (float*)Phat);
   return hipGetLastError();
 }

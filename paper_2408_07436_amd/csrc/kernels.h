@@ -73,9 +73,18 @@ struct Gemm64 {
 hipError_t launch_gemm64(const Gemm64& g, hipStream_t stream);
 
 // ---- FFT-M2L (Appendix A.1) ----------------------------------------------
-// LDS row stride of the FP32 block-form Hadamard: 16 floats + 16 bytes of
-// padding; the slot table holds byte offsets slot * kHadRowBytes.
+// FP32 block-form Hadamard: a block's sources are staged in LDS at the slots
+// of their positions in the 6 x 6 x 6 shell around the block's aligned
+// 4 x 4 x 4 cube (slot = x + 6 y + 36 z); an LDS row is 16 floats + 16
+// bytes of padding, so eight clusters of an aligned 2 x 2 x 2 cube (slots
+// congruent to 0, 1, 6, 7, 36, 37, 42, 43 plus a constant) fall on distinct
+// 16-byte bank groups modulo 128 bytes.  Member slots run from 43 (shell
+// position (1, 1, 1)) to 172, and the per-cluster base offsets are biased
+// by kHadSlotBias slots so that every direction's offset is non-negative.
 constexpr int kHadRowBytes = 80;
+constexpr int kHadShell = 6;
+constexpr int kHadSrcSlots = kHadShell * kHadShell * kHadShell;
+constexpr int kHadSlotBias = 1 + kHadShell + kHadShell * kHadShell;
 // Forward: densities M[box][v][ns] (FP64) of the children of each cluster
 // -> spectra Qhat[f][row][8] (complex, T), row = cluster * nvec + v.
 // lat2surf[(x p + y) p + z] is the surface index of a lattice point or -1;
@@ -89,14 +98,16 @@ hipError_t launch_fft_forward(int p, bool fp64, const double* M, const int32_t* 
 // Qhat holds n_clusters + 1 clusters per frequency, the last one zero;
 // absent neighbours name it.  FP64 gathers through halo; FP32 stages
 // source blocks: block b covers clusters [blk_tgt[b], blk_tgt[b + 1]), its
-// sources are blk_list[blk_src[b] ...] packed as cluster << 8 | slot, and
-// 16-bit entry d of slots[c] (13 words per cluster) is slot(halo[d][c]) *
-// kHadRowBytes.  FP32 work split: units = false gives persistent
+// sources are blk_list[blk_src[b] ...] packed as cluster << 8 | slot
+// (blk_list[0] = n_clusters << 8 | 255, the empty cluster at a discard slot), and
+// tbase[c] = (slot(c) - kHadSlotBias) * kHadRowBytes, so the neighbour in
+// direction D of cluster c sits at byte tbase[c] + (kHadSlotBias + D_x +
+// 6 D_y + 36 D_z) * kHadRowBytes.  FP32 work split: units = false gives persistent
 // workgroups over contiguous runs of the frequency-major (frequency, block,
 // vector) items, true one workgroup per unit of 8 items.
 hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
                            const int32_t* halo, int64_t n_blocks, const int32_t* blk_tgt,
-                           const int32_t* blk_src, const int32_t* blk_list, const uint32_t* slots,
+                           const int32_t* blk_src, const int32_t* blk_list, const int32_t* tbase,
                            int64_t n_clusters, int nvec, bool units, void* Phat,
                            hipStream_t stream);
 // Inverse: spectra -> check potentials out[box][v][s] = scale * phi (FP64).
