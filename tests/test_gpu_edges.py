@@ -1,0 +1,78 @@
+"""Degenerate and ragged inputs through the C ABI against the oracle: one
+point (its own potential is exactly zero, the self term being excluded), two
+and nine points at depths 2 and 3 (levels with a single box, halos that are
+all absent), all points in one corner of the domain (a heavily pruned tree
+whose FFT-M2L source blocks are partly filled), two far-apart clusters, and
+zero charges (exactly zero potentials).  Gates as in the parity tests: FP64
+relative L2 <= 1e-10, FP32 / mixed <= 1e-5."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import fmm, kernel
+
+from gpu_util import evaluate, say
+
+K = pytest.importorskip("paper_2408_07436_amd")
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GATE = {"fp64": 1e-10, "fp32": 1e-5}
+MODES = [("fft", "fp64"), ("fft", "fp32"), ("blas", "fp64"), ("blas", "fp32")]
+
+
+def corner(n, seed):
+    rng = np.random.default_rng(seed)
+    return 0.2 * rng.random((n, 3)) + 0.001
+
+
+def two_clusters(n, seed):
+    rng = np.random.default_rng(seed)
+    h = n // 2
+    return np.concatenate([0.1 * rng.random((h, 3)) + 0.02, 0.1 * rng.random((n - h, 3)) + 0.85])
+
+
+@pytest.mark.parametrize("m2l,prec", MODES)
+def test_single_point_has_zero_potential(m2l, prec):
+    pts = workloads.uniform_cube(1, 901)
+    q = workloads.charges(1, 2, 911, "normal")
+    say(f"case: one point depth 2 p4 {m2l} {prec}")
+    got, _ = evaluate(K, pts, q, 2, 4, m2l, prec)
+    say(f"  potentials {got.ravel()}")
+    assert np.all(got == 0.0)
+
+
+@pytest.mark.parametrize("m2l,prec", MODES)
+@pytest.mark.parametrize("n,depth", [(2, 2), (9, 3)])
+def test_few_points(m2l, prec, n, depth):
+    pts = workloads.uniform_cube(n, 900 + n)
+    q = workloads.charges(n, 2, 910 + n, "normal")
+    say(f"case: {n} points depth {depth} p4 {m2l} {prec}")
+    got, _ = evaluate(K, pts, q, depth, 4, m2l, prec)
+    ref = fmm.KiFMM(pts, pts, depth, 4).evaluate(q)
+    e = kernel.rel_l2(got, ref)
+    say(f"  rel err vs oracle {e:.3e}")
+    assert e <= GATE[prec]
+
+
+@pytest.mark.parametrize("m2l,prec", MODES)
+@pytest.mark.parametrize("shape", ["corner", "two_clusters"])
+def test_pruned_trees(m2l, prec, shape):
+    n = 6000
+    pts = corner(n, 921) if shape == "corner" else two_clusters(n, 922)
+    q = workloads.charges(n, 1, 923, "normal")
+    say(f"case: {shape} {n} points depth 5 p4 {m2l} {prec}")
+    got, _ = evaluate(K, pts, q, 5, 4, m2l, prec)
+    ref = fmm.KiFMM(pts, pts, 5, 4).evaluate(q)
+    e = kernel.rel_l2(got, ref)
+    say(f"  rel err vs oracle {e:.3e}")
+    assert e <= GATE[prec]
+
+
+@pytest.mark.parametrize("m2l,prec", MODES)
+def test_zero_charges_give_zero(m2l, prec):
+    pts = workloads.uniform_cube(5000, 931)
+    q = np.zeros((3, 5000))
+    say(f"case: zero charges 5000 points depth 4 p4 {m2l} {prec}")
+    got, _ = evaluate(K, pts, q, 4, 4, m2l, prec)
+    assert np.all(got == 0.0)
