@@ -119,6 +119,33 @@ kifmm_status kifmm_set_points(kifmm_handle* h, const double* src, int64_t n_src,
  * ENUMERIC: an SVD did not converge. */
 kifmm_status kifmm_precompute(kifmm_handle* h);
 
+/* Compression of K_fat = [K_1 .. K_316] (n_s x 316 n_s) for BLAS-M2L
+ * (Section 3.1).
+ *   KIFMM_SVD_DETERMINISTIC (default) - host SVD: Householder QR of K_fat^T,
+ *     then a Jacobi SVD of the triangular factor.
+ *   KIFMM_SVD_RANDOMIZED - the one-shot randomized SVD the paper uses for
+ *     setup (Section 3.1, after Halko, Martinsson and Tropp): no power
+ *     iterations, only oversampling and a rank estimate.  With l = rank +
+ *     oversample (at most n_s): Omega (316 n_s x l) of standard normal
+ *     numbers (Philox4x32-10 keyed by `seed`, counter = pair index,
+ *     Box-Muller), Y = K_fat Omega, Q an orthonormal basis of Y, B = Q^T
+ *     K_fat, the SVD of B from the eigen-decomposition of B B^T, and the
+ *     left vectors Q times those of B.  The three products with the long
+ *     dimension run on the handle's device (FP64 MFMA); the factorizations of
+ *     the small matrices on the host.  The basis keeps at most `rank`
+ *     vectors (those above svd_rel_tol, as in the deterministic mode); rank
+ *     0 selects ceil(n_s / 2), the paper's rank estimate for the Laplace
+ *     kernel.  Forming B B^T squares the singular values, so those below
+ *     about 1e-8 sigma_0 are not resolved.
+ * Applies to BLAS-M2L only (other forms ignore it).  Call before
+ * kifmm_precompute.  Operators are cached per configuration and SVD setting.
+ * EINVAL: null handle, unknown mode, rank < 0 or oversample < 0.
+ * ESTATE: after kifmm_precompute.  At precompute: ENOMEM / EDEVICE if the
+ * device buffers (about 4 x 8 n_s x 316 n_s bytes + 64 MiB) or products fail. */
+typedef enum { KIFMM_SVD_DETERMINISTIC = 0, KIFMM_SVD_RANDOMIZED = 1 } kifmm_svd;
+kifmm_status kifmm_set_svd(kifmm_handle* h, int32_t mode, int32_t rank, int32_t oversample,
+                           uint64_t seed);
+
 /* Evaluate potentials on the device, asynchronously on hip_stream (a
  * hipStream_t; NULL = default stream).  q_dev holds n_vec charge vectors,
  * column-major [n_vec][ldq] in the caller's source order; phi_dev receives

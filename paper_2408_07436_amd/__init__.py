@@ -27,7 +27,7 @@ EXPORTS = [
     "kifmm_point_perm", "kifmm_interactions", "kifmm_near", "kifmm_operator", "kifmm_stage",
     "kifmm_set_timing", "kifmm_timings", "kifmm_m2l_counts", "kifmm_get_tuning",
     "kifmm_set_tuning", "kifmm_autotune", "kifmm_update_points", "kifmm_batch_create", "kifmm_batch_autotune",
-    "kifmm_batch_launch", "kifmm_batch_destroy",
+    "kifmm_batch_launch", "kifmm_batch_destroy", "kifmm_set_svd",
 ]
 TUNE_KNOBS = ("blas_tile", "schedule", "hadamard")
 
@@ -89,6 +89,7 @@ def lib() -> ctypes.CDLL:
     L.kifmm_update_points.argtypes = [vp, vp, vp, vp]
     L.kifmm_get_tuning.argtypes = [vp, ctypes.POINTER(i32), i32]
     L.kifmm_set_tuning.argtypes = [vp, ctypes.POINTER(i32), i32]
+    L.kifmm_set_svd.argtypes = [vp, i32, i32, i32, ctypes.c_uint64]
     L.kifmm_autotune.argtypes = [vp, vp, i64, i32, vp, i64, vp, i32, dp]
     L.kifmm_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), ctypes.POINTER(i64),
                                      ctypes.POINTER(i32), ctypes.POINTER(vp), ctypes.POINTER(i64), vp,
@@ -163,6 +164,14 @@ class KiFMM:
         _check(lib().kifmm_set_points(self._h, _ptr(s, ctypes.c_double), s.shape[0],
                                       _ptr(t, ctypes.c_double), t.shape[0]))
         self.n_src, self.n_tgt = s.shape[0], t.shape[0]
+        return self
+
+    def set_svd(self, mode: str = "randomized", rank: int = 0, oversample: int = 10, seed: int = 0):
+        """Compression of K_fat for BLAS-M2L: "deterministic" (host SVD) or "randomized"
+        (one-shot randomized SVD on the device; ``rank`` 0 = ceil(n_s / 2)).  Before
+        ``precompute``."""
+        modes = {"deterministic": 0, "randomized": 1}
+        _check(lib().kifmm_set_svd(self._h, modes[mode], int(rank), int(oversample), int(seed)))
         return self
 
     def precompute(self):

@@ -105,12 +105,15 @@ kifmm_status kifmm_precompute(kifmm_handle* h) {
   }
   // operators depend only on the configuration (Section 5.1): one FP64
   // precomputation per distinct configuration and process
-  using Key = std::tuple<int, int, double, double, double, double>;
+  using Key = std::tuple<int, int, double, double, double, double, int, int, int, uint64_t>;
   static std::mutex mu;
   static std::map<Key, kifmm::Operators> cache;
   const kifmm_config& c = h->cfg;
-  const Key key{c.order, c.m2l, c.m2l == KIFMM_M2L_BLAS ? c.svd_rel_tol : 0.0,
-                c.m2l == KIFMM_M2L_BLAS ? c.svd_rel_tol_dir : 0.0, c.alpha_inner, c.alpha_outer};
+  const bool blas = c.m2l == KIFMM_M2L_BLAS;
+  const bool rnd = blas && h->svd.mode == KIFMM_SVD_RANDOMIZED;
+  const Key key{c.order, c.m2l, blas ? c.svd_rel_tol : 0.0, blas ? c.svd_rel_tol_dir : 0.0,
+                c.alpha_inner, c.alpha_outer, rnd ? 1 : 0, rnd ? h->svd.rank : 0,
+                rnd ? h->svd.oversample : 0, rnd ? h->svd.seed : 0};
   {
     std::lock_guard<std::mutex> lock(mu);
     auto it = cache.find(key);
@@ -119,10 +122,26 @@ kifmm_status kifmm_precompute(kifmm_handle* h) {
       return KIFMM_OK;
     }
   }
-  kifmm_status st = kifmm::precompute_operators(h->op, h->cfg);
+  kifmm::SvdOptions svd = h->svd;
+  svd.device = c.device;
+  kifmm_status st = kifmm::precompute_operators(h->op, h->cfg, svd);
   if (st != KIFMM_OK) return st;
   std::lock_guard<std::mutex> lock(mu);
   cache.emplace(key, h->op);
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_set_svd(kifmm_handle* h, int32_t mode, int32_t rank, int32_t oversample,
+                           uint64_t seed) {
+  if (!h) return fail(KIFMM_EINVAL, "null handle");
+  if (mode != KIFMM_SVD_DETERMINISTIC && mode != KIFMM_SVD_RANDOMIZED)
+    return fail(KIFMM_EINVAL, "unknown SVD mode");
+  if (rank < 0 || oversample < 0) return fail(KIFMM_EINVAL, "negative rank or oversampling");
+  if (h->op.ready) return fail(KIFMM_ESTATE, "the SVD is chosen before kifmm_precompute");
+  h->svd.mode = mode;
+  h->svd.rank = rank;
+  h->svd.oversample = oversample;
+  h->svd.seed = seed;
   return KIFMM_OK;
 }
 

@@ -105,7 +105,23 @@ struct Operators {
   bool ready = false;
 };
 
-kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg);
+// Compression of K_fat for BLAS-M2L (Section 3.1): the deterministic host
+// SVD or the one-shot randomized SVD on the device (kifmm_set_svd).
+struct SvdOptions {
+  int mode = KIFMM_SVD_DETERMINISTIC;
+  int rank = 0;  // target rank; 0 = ceil(ns / 2)
+  int oversample = 10;
+  uint64_t seed = 0;
+  int device = 0;
+};
+// Leading left singular vectors U (m x r, row-major, r = the target rank)
+// and values s of A (m x n, row-major) by a one-shot randomized SVD: the
+// products with the long dimension on the device, the small
+// factorizations on the host.
+kifmm_status rsvd_left_device(const double* A, int m, int n, const SvdOptions& o,
+                              std::vector<double>& U, std::vector<double>& s);
+
+kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg, const SvdOptions& svd);
 
 // ---- device side -------------------------------------------------------------
 struct DeviceState;  // defined in device.hip
@@ -123,4 +139,5 @@ struct kifmm_handle {
   double timings[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   int32_t tune[KIFMM_TUNE_COUNT] = {0, 0, 0};  // autotuning knobs (kifmm.h)
   bool points_on_device = false;  // host copies of the point order are stale
+  kifmm::SvdOptions svd;          // K_fat compression (BLAS-M2L)
 };

@@ -109,7 +109,7 @@ void rdft3(const std::vector<double>& g, int n, std::vector<std::complex<double>
 
 }  // namespace
 
-kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg) {
+kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg, const SvdOptions& svd_opt) {
   op = Operators();
   const int p = cfg.order;
   op.p = p;
@@ -238,8 +238,12 @@ kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg) {
           std::copy(&Kt[it][(size_t)i * ns], &Kt[it][(size_t)i * ns] + ns,
                     &Kfat[((size_t)i * kNumTransfer + it) * ns]);
       std::vector<double> Uf, sf;
-      if (!svd_left_wide(Kfat.data(), ns, kNumTransfer * ns, Uf, sf))
+      if (svd_opt.mode == KIFMM_SVD_RANDOMIZED) {
+        const kifmm_status st = rsvd_left_device(Kfat.data(), ns, kNumTransfer * ns, svd_opt, Uf, sf);
+        if (st != KIFMM_OK) return st;
+      } else if (!svd_left_wide(Kfat.data(), ns, kNumTransfer * ns, Uf, sf)) {
         return fail(KIFMM_ENUMERIC, "SVD of K_fat did not converge");
+      }
       const int r0 = (int)sf.size();
       int k = 0;
       if (cfg.svd_rel_tol > 0) {

@@ -180,3 +180,18 @@ def test_update_points_argument_errors():
     f.set_points(workloads.uniform_cube(500, 60))
     assert lib.kifmm_update_points(f._h, one, one, None) == 2
     assert b"precompute" in lib.kifmm_last_error()
+
+
+def test_set_svd_argument_and_state_errors():
+    """The K_fat compression is chosen before precompute; bad modes and sizes are refused."""
+    lib = K.lib()
+    f = K.KiFMM(4, 3, m2l="blas", svd_rel_tol=1e-6)
+    assert lib.kifmm_set_svd(None, 1, 0, 10, 0) == 1
+    assert lib.kifmm_set_svd(f._h, 2, 0, 10, 0) == 1
+    assert lib.kifmm_set_svd(f._h, 1, -1, 10, 0) == 1
+    assert lib.kifmm_set_svd(f._h, 1, 0, -1, 0) == 1
+    assert lib.kifmm_set_svd(f._h, 0, 0, 0, 0) == 0
+    f.set_points(workloads.uniform_cube(500, 61))
+    f.precompute()  # deterministic: host only
+    assert lib.kifmm_set_svd(f._h, 1, 0, 10, 0) == 2
+    assert b"precompute" in lib.kifmm_last_error()
