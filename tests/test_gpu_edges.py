@@ -2,9 +2,10 @@
 point (its own potential is exactly zero, the self term being excluded), two
 and nine points at depths 2 and 3 (levels with a single box, halos that are
 all absent), all points in one corner of the domain (a heavily pruned tree
-whose FFT-M2L source blocks are partly filled), two far-apart clusters, and
-zero charges (exactly zero potentials).  Gates as in the parity tests: FP64
-relative L2 <= 1e-10, FP32 / mixed <= 1e-5."""
+whose FFT-M2L source blocks are partly filled), two far-apart clusters, zero
+charges (exactly zero potentials), and FFT-M2L at orders 2, 7 and 8 (the
+smallest and largest built).  Gates as in the parity tests: FP64 relative L2
+<= 1e-10, FP32 / mixed <= 1e-5 end to end, 1e-12 / 1e-6 per M2L stage."""
 import numpy as np
 import pytest
 
@@ -76,3 +77,37 @@ def test_zero_charges_give_zero(m2l, prec):
     say(f"case: zero charges 5000 points depth 4 p4 {m2l} {prec}")
     got, _ = evaluate(K, pts, q, 4, 4, m2l, prec)
     assert np.all(got == 0.0)
+
+
+@pytest.mark.parametrize("p", [2, 7, 8])
+@pytest.mark.parametrize("prec,gate", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_fft_extreme_orders_stage(p, prec, gate):
+    """FFT-M2L at the smallest and the largest orders the library builds (grids
+    of 3 and 15 points per axis): one level at a time, in check-potential space."""
+    pts = workloads.sphere_surface(8000, 990 + p)
+    ora = fmm.KiFMM(pts, pts, 4, p, origin=(-1, -1, -1), width=2.0)
+    f = K.KiFMM(p, 4, m2l="fft", prec=prec, origin=(-1, -1, -1), width=2.0).set_points(pts).precompute()
+    rng = np.random.default_rng(991)
+    for lev in (2, 3, 4):
+        nb = len(ora.tree.levels[lev])
+        mult = rng.standard_normal((nb, 2, ora.ns))
+        say(f"case: fft stage p{p} {prec} level {lev} boxes {nb}")
+        out = f.stage_m2l(lev, torch.as_tensor(mult, device="cuda"))
+        torch.cuda.synchronize()
+        ref = ora.m2l_level(lev, mult.transpose(0, 2, 1)).transpose(0, 2, 1)
+        e = kernel.rel_l2(out.cpu().numpy(), ref)
+        say(f"  rel err {e:.3e}")
+        assert e <= gate
+
+
+@pytest.mark.parametrize("p", [2, 8])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fft_extreme_orders_end_to_end(p, prec):
+    pts = workloads.sphere_surface(8000, 992 + p)
+    q = workloads.charges(8000, 1, 993 + p, "normal")
+    say(f"case: fft end to end p{p} {prec} sphere 8000 depth 4")
+    got, _ = evaluate(K, pts, q, 4, p, "fft", prec, origin=(-1, -1, -1), width=2.0)
+    ref = fmm.KiFMM(pts, pts, 4, p, origin=(-1, -1, -1), width=2.0).evaluate(q)
+    e = kernel.rel_l2(got, ref)
+    say(f"  rel err vs oracle {e:.3e}")
+    assert e <= GATE[prec]
