@@ -60,6 +60,16 @@ __device__ inline void split8(const float* x, v8bf& hi, v8bf& lo) {
   }
 }
 
+// Tiles in consecutive runs per XCD: workgroup b runs on XCD b % 8, and
+// neighbouring tiles (consecutive boxes of one octant class) gather many of
+// the same source columns, which then meet in that XCD's L2.  The grid is a
+// multiple of 8; -1 past the last tile.
+__device__ inline int xcd_tile(int64_t ntiles) {
+  const int64_t b = blockIdx.x, per_xcd = gridDim.x / 8;
+  const int64_t t = (b % 8) * per_xcd + b / 8;
+  return t < ntiles ? (int)t : -1;
+}
+
 struct ColInfo {
   int slot[2], v[2];
   bool ok[2];
@@ -85,7 +95,8 @@ template <typename T, bool TWO, int RB, int KB>
 __global__ __launch_bounds__(256, (sizeof(T) == 8 ? (RB > 8 ? 1 : 2) : (RB > 8 ? 2 : 3))) void blas_m2l_kernel(BlasM2L a) {
   using V4 = typename std::conditional<sizeof(T) == 4, v4f, v4d>::type;
   constexpr int kMaxKB = KB;
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile(a.ntiles);
+  if (tile < 0) return;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int l16 = lane % 16, g4 = lane / 16;
   const int nrb = a.kp / 16;
@@ -212,7 +223,8 @@ template <bool TWO>
 __global__ __launch_bounds__(256) void blas_m2l_bf16_kernel(BlasM2L a) {
   constexpr int RB = kMaxRB;
   constexpr int kMaxKB = 4;  // Xi row blocks: k_t pad <= 64
-  const int tile = blockIdx.x;
+  const int tile = xcd_tile(a.ntiles);
+  if (tile < 0) return;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int l16 = lane % 16, g4 = lane / 16;
   const int nrb = a.kp / 16;
@@ -381,7 +393,7 @@ __global__ void pad_convert_kernel(const double* __restrict__ in, int k, int64_t
 hipError_t launch_blas_m2l(const BlasM2L& a, int mode, bool two_stage, hipStream_t stream) {
   if (a.ntiles == 0) return hipSuccess;
   if (a.kp > 16 * kMaxRB || a.C > 128) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)a.ntiles), block(256);
+  const dim3 grid((unsigned)(8 * ((a.ntiles + 7) / 8))), block(256);
   if (mode == 0 || mode == 1) {
     if (two_stage && a.ktp_max > 48) return hipErrorInvalidValue;
     const int nrb = a.kp / 16;
