@@ -28,10 +28,12 @@ from .surfaces import ALPHA_INNER, surface
 from .tree import TRANSFER_VECTORS
 
 
-def m2l_matrices(p: int, half_width: float, alpha: float = ALPHA_INNER) -> list[np.ndarray]:
+def m2l_matrices(p: int, half_width: float, alpha: float = ALPHA_INNER,
+                 check_order: int | None = None) -> list[np.ndarray]:
     """K_t for the 316 transfer vectors at a level with box half-width r:
-    target check surface around 0, source equivalent surface around t * 2r."""
-    x = surface(p, alpha, half_width)
+    target check surface (order check_order, default p) around 0, source
+    equivalent surface (order p) around t * 2r; n_c x n_e each."""
+    x = surface(p if check_order is None else check_order, alpha, half_width)
     out = []
     for t in TRANSFER_VECTORS:
         y = surface(p, alpha, half_width, center=t * 2.0 * half_width)
@@ -72,5 +74,5 @@ def compress(ks: list[np.ndarray], tol: float, tol_dir: float) -> dict:
 
 
 def applied_operator(comp: dict, it: int) -> np.ndarray:
-    """Dense n_s x n_s operator U Ubar_t Vbar'_t^T S^T for transfer index it."""
+    """Dense n_c x n_e operator U Ubar_t Vbar'_t^T S^T for transfer index it."""
     return comp["U"] @ comp["Ubar"][it] @ comp["Vbarp"][it].T @ comp["S"].T

@@ -27,6 +27,14 @@ sum is accumulated per target in ascending transfer-vector index.
 ``m2l`` selects how each M2L matrix is applied: "dense" (the definition),
 "fft" (the convolution of Appendix A.1, through ``fft_m2l``) or "blas" (the
 compressed operator of Section 3.1, through ``blas_m2l``).
+
+``check_order`` (P_c) sets the order of both check surfaces, ``order`` (P_e)
+that of both equivalent surfaces.  The BLAS form may take P_c > P_e (more
+check than equivalent points, often the more stable fit; Section 5.1, and
+the P_e / P_c columns of the BLAS-M2L parameter table in Section 4), which
+the convolution form cannot: its surfaces must be discretised alike.
+Check-side arrays then have n_c = 6 (P_c - 1)^2 + 2 rows and
+equivalent-side arrays n_e = 6 (P_e - 1)^2 + 2.
 """
 
 from __future__ import annotations
@@ -51,12 +59,19 @@ class KiFMM:
     def __init__(self, sources, targets, depth: int, order: int,
                  origin=(0.0, 0.0, 0.0), width: float = 1.0, m2l: str = "dense",
                  svd_rel_tol: float = 0.0, svd_rel_tol_dir: float = -1.0,
-                 alpha_inner: float = ALPHA_INNER, alpha_outer: float = ALPHA_OUTER):
+                 alpha_inner: float = ALPHA_INNER, alpha_outer: float = ALPHA_OUTER,
+                 check_order: int | None = None):
         if order < 2:
             raise ValueError("expansion order must be >= 2")
         self.tree = Tree(sources, targets, depth, origin, width)
         self.p = int(order)
-        self.ns = n_surface(self.p)
+        self.pc = self.p if check_order is None else int(check_order)
+        if self.pc < self.p:
+            raise ValueError("check order must be >= the expansion order")
+        if m2l == "fft" and self.pc != self.p:
+            raise ValueError("the convolution form needs equal check and equivalent orders")
+        self.ns = n_surface(self.p)     # equivalent surfaces (n_e)
+        self.nc = n_surface(self.pc)    # check surfaces (n_c)
         self.m2l = m2l
         self.tol = svd_rel_tol
         self.tol_dir = svd_rel_tol_dir
@@ -73,38 +88,38 @@ class KiFMM:
 
     def up_pinv(self, level: int):
         r = self.r(level)
-        return pinv_factors(kernel_matrix(surface(self.p, self.ao, r), surface(self.p, self.ai, r)))
+        return pinv_factors(kernel_matrix(surface(self.pc, self.ao, r), surface(self.p, self.ai, r)))
 
     def down_pinv(self, level: int):
         r = self.r(level)
-        return pinv_factors(kernel_matrix(surface(self.p, self.ai, r), surface(self.p, self.ao, r)))
+        return pinv_factors(kernel_matrix(surface(self.pc, self.ai, r), surface(self.p, self.ao, r)))
 
     def m2m_matrix(self, level: int, octant: int) -> np.ndarray:
         """K(UC of a parent at ``level``, UE of its child in ``octant``)."""
         rp, rc = self.r(level), self.r(level + 1)
         c = _octant_offset(octant) * self.w(level + 1)
-        return kernel_matrix(surface(self.p, self.ao, rp), surface(self.p, self.ai, rc, c))
+        return kernel_matrix(surface(self.pc, self.ao, rp), surface(self.p, self.ai, rc, c))
 
     def l2l_matrix(self, level: int, octant: int) -> np.ndarray:
         """K(DC of a child at ``level`` in ``octant``, DE of its parent)."""
         rc, rp = self.r(level), self.r(level - 1)
         c = _octant_offset(octant) * self.w(level)
-        return kernel_matrix(surface(self.p, self.ai, rc, c), surface(self.p, self.ao, rp))
+        return kernel_matrix(surface(self.pc, self.ai, rc, c), surface(self.p, self.ao, rp))
 
     def m2l_matrix(self, level: int, it: int) -> np.ndarray:
         """K(DC_tau, UE_sigma) for sigma = tau + t (anchors), t = TRANSFER_VECTORS[it]."""
         r = self.r(level)
         t = TRANSFER_VECTORS[it].astype(np.float64) * self.w(level)
-        return kernel_matrix(surface(self.p, self.ai, r), surface(self.p, self.ai, r, t))
+        return kernel_matrix(surface(self.pc, self.ai, r), surface(self.p, self.ai, r, t))
 
     def compression(self, level: int) -> dict:
         if level not in self._comp:
-            ks = blas_m2l.m2l_matrices(self.p, self.r(level), self.ai)
+            ks = blas_m2l.m2l_matrices(self.p, self.r(level), self.ai, check_order=self.pc)
             self._comp[level] = blas_m2l.compress(ks, self.tol, self.tol_dir)
         return self._comp[level]
 
     def m2l_apply(self, level: int, it: int, q: np.ndarray) -> np.ndarray:
-        """Check potentials (m, n_s, nvec) of source densities q (m, n_s, nvec)."""
+        """Check potentials (m, n_c, nvec) of source densities q (m, n_e, nvec)."""
         if self.m2l == "dense":
             return np.einsum("ij,mjv->miv", self.m2l_matrix(level, it), q, optimize=True)
         if self.m2l == "blas":
@@ -131,11 +146,11 @@ class KiFMM:
         ys = tr.sources[tr.src_perm]
         leaves = tr.levels[d]
         centers = tr.center(d, np.arange(len(leaves)))
-        phi = np.zeros((len(leaves), self.ns, nvec))
+        phi = np.zeros((len(leaves), self.nc, nvec))
         for i in range(len(leaves)):
             s, e = tr.src_start[i], tr.src_end[i]
             if e > s:
-                uc = surface(self.p, self.ao, self.r(d), centers[i])
+                uc = surface(self.pc, self.ao, self.r(d), centers[i])
                 phi[i] = kernel_matrix(uc, ys[s:e]) @ qs[:, s:e].T
         mult = [None] * (d + 1)
         mult[d] = self._apply_pinv(self.up_pinv(d), phi)
@@ -143,7 +158,7 @@ class KiFMM:
             child_keys = tr.levels[lev + 1]
             parent = tr.index_of(lev, child_keys >> np.uint64(3))
             octant = (child_keys & np.uint64(7)).astype(np.int64)
-            phi = np.zeros((len(tr.levels[lev]), self.ns, nvec))
+            phi = np.zeros((len(tr.levels[lev]), self.nc, nvec))
             for o in range(8):
                 sel = np.nonzero(octant == o)[0]
                 if sel.size:
@@ -154,15 +169,17 @@ class KiFMM:
         return mult
 
     def _apply_pinv(self, factors, phi: np.ndarray) -> np.ndarray:
-        m, ns, nvec = phi.shape
-        flat = phi.transpose(1, 0, 2).reshape(ns, m * nvec)
-        return pinv_apply(factors, flat).reshape(ns, m, nvec).transpose(1, 0, 2).copy()
+        """Equivalent densities (m, n_e, nvec) of check potentials (m, n_c, nvec)."""
+        m, nc, nvec = phi.shape
+        flat = phi.transpose(1, 0, 2).reshape(nc, m * nvec)
+        out = pinv_apply(factors, flat)
+        return out.reshape(out.shape[0], m, nvec).transpose(1, 0, 2).copy()
 
     def m2l_level(self, level: int, mult: np.ndarray, targets: np.ndarray | None = None) -> np.ndarray:
         """M2L check potentials at ``level`` for the boxes ``targets`` (all if None).
 
         ``mult`` holds the upward-equivalent densities of every box at the
-        level; the result has shape (len(targets), n_s, nvec).
+        level; the result has shape (len(targets), n_c, nvec).
         """
         tr = self.tree
         offs, src, ti = tr.interactions(level)
@@ -174,7 +191,7 @@ class KiFMM:
         pos[targets] = np.arange(len(targets))
         keep = pos[tg] >= 0
         tg, src, ti = pos[tg[keep]], src[keep], ti[keep]
-        out = np.zeros((len(targets), self.ns, mult.shape[2]))
+        out = np.zeros((len(targets), self.nc, mult.shape[2]))
         for it in range(len(TRANSFER_VECTORS)):
             sel = np.nonzero(ti == it)[0]
             if sel.size:

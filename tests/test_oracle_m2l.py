@@ -130,3 +130,24 @@ def test_probe_ranks_p6():
     assert comp["k"] == kthin
     assert 80 <= comp["k"] <= 152
     assert 5 <= comp["kt"].min() and comp["kt"].max() <= comp["k"]
+
+
+def test_check_order_above_expansion_order():
+    """P_c > P_e (Section 5.1; the P_e / P_c columns of Section 4's BLAS-M2L
+    parameter table): the full-rank BLAS form still equals the dense M2L with
+    rectangular n_c x n_e matrices, and more check points never make the fit
+    worse against the direct sum."""
+    pts = workloads.uniform_cube(3000, 5)
+    q = workloads.charges(3000, 2, 6, "normal")
+    direct = kernel.direct(pts, q, pts)
+    errs = []
+    for pc in (4, 5, 6):
+        dense = fmm.KiFMM(pts, pts, 3, 4, check_order=pc).evaluate(q)
+        blas = fmm.KiFMM(pts, pts, 3, 4, m2l="blas", check_order=pc).evaluate(q)
+        assert kernel.rel_l2(blas, dense) < 1e-13
+        errs.append(kernel.rel_l2(dense, direct))
+    assert errs[0] > errs[1] > errs[2]
+    with pytest.raises(ValueError):
+        fmm.KiFMM(pts, pts, 3, 4, m2l="fft", check_order=5)
+    with pytest.raises(ValueError):
+        fmm.KiFMM(pts, pts, 3, 4, check_order=3)
