@@ -96,6 +96,13 @@ typedef struct {
   double alpha_outer;       /* 0 selects 2.95 */
   double origin[3];         /* lower corner of the domain cube */
   double width;             /* side of the domain cube; <= 0 selects the tight cube */
+  int32_t check_order;      /* P_c, order of both check surfaces; 0 = order.  Above order
+                               (more check than equivalent points, Section 5.1; the P_e and
+                               P_c columns of Section 4's BLAS-M2L parameter table) for
+                               KIFMM_M2L_BLAS only: the convolution form needs equal
+                               orders.  Check-side arrays then have n_c = 6 (P_c - 1)^2 + 2
+                               points, equivalent-side ones n_s = 6 (P_e - 1)^2 + 2, and the
+                               compressed rank k is at most n_s. */
 } kifmm_config;
 
 /* Fill *cfg with defaults: p = 6, depth = 4, FFT, FP64, tolerances 0 / -1,
@@ -103,7 +110,8 @@ typedef struct {
 void kifmm_config_default(kifmm_config* cfg);
 
 /* Create a handle.  Validates the config (EINVAL: order < 2, depth outside
- * 2..16, unknown m2l/prec; EUNSUPPORTED: BF16X3 with FFT).  *out receives
+ * 2..16, unknown m2l/prec, 0 < check_order < order; EUNSUPPORTED: BF16X3 with
+ * FFT, check_order > order without BLAS-M2L).  *out receives
  * the handle, owned by the caller until kifmm_destroy. */
 kifmm_status kifmm_create(const kifmm_config* cfg, kifmm_handle** out);
 
@@ -190,10 +198,11 @@ kifmm_status kifmm_near(const kifmm_handle* h, int64_t* offs, int64_t* src, int6
  *     to wrap; the paper pads to 2p), kernel value K(c_tau - c_sigma + h m)
  *     at index m mod n for m in [-(p-1), p-1]^3, densities at their lattice
  *     positions;
- *   5 KIFMM_OP_BLAS_U: U (n_s x k, row-major), 6 KIFMM_OP_BLAS_RANKS: k then
+ *   5 KIFMM_OP_BLAS_U: U (n_c x k, row-major), 6 KIFMM_OP_BLAS_RANKS: k then
  *     k_t for the 316 transfer vectors (as doubles), 7 KIFMM_OP_BLAS_APPLIED:
- *     the applied operator U Ubar_t Vbar'_t^T S^T of every t, [316][n_s][n_s],
- *     for the unit box.
+ *     the applied operator U Ubar_t Vbar'_t^T S^T of every t, [316][n_c][n_s],
+ *     for the unit box (n_c = n_s unless check_order > order).  The pseudo-
+ *     inverse factors are V (n_s x r) and Ut (r x n_c).
  * *n receives the element count; out may be NULL to query it. */
 kifmm_status kifmm_operator(const kifmm_handle* h, int32_t which, double* out, int64_t cap,
                             int64_t* n);
@@ -202,8 +211,9 @@ kifmm_status kifmm_operator(const kifmm_handle* h, int32_t which, double* out, i
 
 /* Run one M2L level on caller device buffers, asynchronously:
  * in_dev = upward-equivalent densities [n_boxes(level)][n_vec][n_s] (double,
- * boxes in key order), out_dev = M2L check potentials, same layout (double,
- * overwritten).  Uses the configured M2L form and precision.  stage must be
+ * boxes in key order), out_dev = M2L check potentials
+ * [n_boxes(level)][n_vec][n_c] (double, overwritten; n_c = n_s unless
+ * check_order > order).  Uses the configured M2L form and precision.  stage must be
  * KIFMM_STAGE_M2L (0). */
 kifmm_status kifmm_stage(kifmm_handle* h, int32_t stage, int32_t level, const void* in_dev,
                          void* out_dev, int32_t n_vec, void* hip_stream);

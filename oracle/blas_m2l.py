@@ -11,7 +11,9 @@ the first k_t singular triplets of each C_t: C_t ~ Ubar_t Vbar'_t^T with
 Vbar'_t = Vbar_t Sigmabar_t.
 
 Threshold reading (the paper's "singular value threshold" is not defined
-further): k = #{sigma_i(K_fat) > tol * sigma_0(K_fat)}, and k_t =
+further): k = #{sigma_i(K_fat) > tol * sigma_0(K_fat)}, capped at n_e (the
+right vectors K_thin has) when check surfaces are finer than equivalent ones,
+since C_t is k x k for one k, and k_t =
 #{sigma_i(C_t) > tol_dir * sigma_0(C_t)}; tol = 0 keeps full rank and
 tol_dir < 0 skips recompression.  The operator the method applies,
 U Ubar_t Vbar'_t^T S^T, does not depend on the signs or bases the SVD routine
@@ -53,7 +55,9 @@ def compress(ks: list[np.ndarray], tol: float, tol_dir: float) -> dict:
     kthin = np.vstack(ks)
     u, sfat, _ = np.linalg.svd(kfat, full_matrices=False)
     _, sthin, st = np.linalg.svd(kthin, full_matrices=False)
-    k = _rank(sfat, tol)
+    # one rank k for both sides (C_t is k x k), at most the number of right
+    # vectors K_thin has (n_e, below n_c when the check order is the higher)
+    k = min(_rank(sfat, tol), st.shape[0])
     uk = u[:, :k]
     sk = st[:k].T
     ubar, vbarp, kts = [], [], []

@@ -52,6 +52,7 @@ class Config(ctypes.Structure):
         ("alpha_outer", ctypes.c_double),
         ("origin", ctypes.c_double * 3),
         ("width", ctypes.c_double),
+        ("check_order", ctypes.c_int32),
     ]
 
 
@@ -125,7 +126,7 @@ class KiFMM:
     def __init__(self, order: int, depth: int, m2l: str = "fft", prec: str = "fp64",
                  origin=(0.0, 0.0, 0.0), width: float = 1.0, svd_rel_tol: float = 0.0,
                  svd_rel_tol_dir: float = -1.0, device: int = 0, alpha_inner: float = 1.05,
-                 alpha_outer: float = 2.95):
+                 alpha_outer: float = 2.95, check_order: int = 0):
         L = lib()
         cfg = Config()
         L.kifmm_config_default(ctypes.byref(cfg))
@@ -136,10 +137,14 @@ class KiFMM:
         cfg.alpha_inner, cfg.alpha_outer = alpha_inner, alpha_outer
         cfg.origin[:] = list(origin)
         cfg.width = width
+        cfg.check_order = check_order
         h = ctypes.c_void_p()
         _check(L.kifmm_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
         self.order, self.depth, self.m2l, self.prec = order, depth, m2l, prec
+        self.check_order = check_order if check_order > 0 else order
+        self.n_equiv = 6 * (order - 1) ** 2 + 2              # points of an equivalent surface
+        self.n_check = 6 * (self.check_order - 1) ** 2 + 2  # points of a check surface
         self.n_src = self.n_tgt = 0
 
     def close(self):
@@ -194,11 +199,15 @@ class KiFMM:
         return out
 
     def stage_m2l(self, level: int, mult, out=None, stream=None):
-        """M2L check potentials of one level for densities ``mult`` (n_boxes, nvec, n_s), FP64."""
+        """M2L check potentials (n_boxes, nvec, n_check) of one level for equivalent
+        densities ``mult`` (n_boxes, nvec, n_equiv), FP64."""
         import torch
         assert mult.is_cuda and mult.dtype == torch.float64 and mult.is_contiguous()
+        assert mult.shape[2] == self.n_equiv
         if out is None:
-            out = torch.empty_like(mult)
+            out = torch.empty((mult.shape[0], mult.shape[1], self.n_check), dtype=torch.float64,
+                              device=mult.device)
+        assert out.shape == (mult.shape[0], mult.shape[1], self.n_check) and out.is_contiguous()
         s = torch.cuda.current_stream(mult.device) if stream is None else stream
         _check(lib().kifmm_stage(self._h, 0, level, mult.data_ptr(), out.data_ptr(), mult.shape[1],
                                  ctypes.c_void_p(s.cuda_stream)))

@@ -51,6 +51,7 @@ void kifmm_config_default(kifmm_config* cfg) {
   cfg->alpha_inner = 1.05;
   cfg->alpha_outer = 2.95;
   cfg->width = 1.0;
+  cfg->check_order = 0;
 }
 
 const char* kifmm_last_error(void) { return kifmm::g_last_error.c_str(); }
@@ -69,6 +70,10 @@ kifmm_status kifmm_create(const kifmm_config* cfg, kifmm_handle** out) {
     return fail(KIFMM_EUNSUPPORTED, "FFT M2L is built for orders 2..8");
   if (cfg->m2l == KIFMM_M2L_FFT && cfg->prec == KIFMM_BF16X3)
     return fail(KIFMM_EUNSUPPORTED, "bf16 split precision applies to the BLAS and dense M2L only");
+  if (cfg->check_order != 0 && cfg->check_order < cfg->order)
+    return fail(KIFMM_EINVAL, "check_order must be 0 or >= order");
+  if (cfg->check_order > cfg->order && cfg->m2l != KIFMM_M2L_BLAS)
+    return fail(KIFMM_EUNSUPPORTED, "a check order above the expansion order needs BLAS-M2L");
   auto* h = new (std::nothrow) kifmm_handle();
   if (!h) return fail(KIFMM_ENOMEM, "out of host memory");
   h->cfg = *cfg;
@@ -111,7 +116,8 @@ kifmm_status kifmm_precompute(kifmm_handle* h) {
   const kifmm_config& c = h->cfg;
   const bool blas = c.m2l == KIFMM_M2L_BLAS;
   const bool rnd = blas && h->svd.mode == KIFMM_SVD_RANDOMIZED;
-  const Key key{c.order, c.m2l, blas ? c.svd_rel_tol : 0.0, blas ? c.svd_rel_tol_dir : 0.0,
+  const int pc = c.check_order > 0 ? c.check_order : c.order;
+  const Key key{c.order * 64 + pc, c.m2l, blas ? c.svd_rel_tol : 0.0, blas ? c.svd_rel_tol_dir : 0.0,
                 c.alpha_inner, c.alpha_outer, rnd ? 1 : 0, rnd ? h->svd.rank : 0,
                 rnd ? h->svd.oversample : 0, rnd ? h->svd.seed : 0};
   {
@@ -253,9 +259,9 @@ kifmm_status kifmm_operator(const kifmm_handle* h, int32_t which, double* out, i
       break;
     case 7: {
       if (h->cfg.m2l == KIFMM_M2L_FFT) return fail(KIFMM_EINVAL, "no BLAS operators in this mode");
-      const int ns = op.ns, k = op.k;
-      buf.assign((size_t)kifmm::kNumTransfer * ns * ns, 0.0);
-      std::vector<double> C((size_t)k * k), UC((size_t)ns * k);
+      const int ns = op.ns, nc = op.nc, k = op.k;
+      buf.assign((size_t)kifmm::kNumTransfer * nc * ns, 0.0);
+      std::vector<double> C((size_t)k * k), UC((size_t)nc * k);
       for (int it = 0; it < kifmm::kNumTransfer; ++it) {
         if (!op.recompressed) {
           C = op.Vbarp[it];
@@ -269,17 +275,17 @@ kifmm_status kifmm_operator(const kifmm_handle* h, int32_t which, double* out, i
               C[(size_t)i * k + j] = acc;
             }
         }
-        for (int i = 0; i < ns; ++i)
+        for (int i = 0; i < nc; ++i)
           for (int j = 0; j < k; ++j) {
             double acc = 0;
             for (int l = 0; l < k; ++l) acc += op.U[(size_t)i * k + l] * C[(size_t)l * k + j];
             UC[(size_t)i * k + j] = acc;
           }
-        double* dst = &buf[(size_t)it * ns * ns];
-        for (int i = 0; i < ns; ++i)
+        double* dst = &buf[(size_t)it * nc * ns];
+        for (int i = 0; i < nc; ++i)
           for (int j = 0; j < ns; ++j) {
             double acc = 0;
-            for (int l = 0; l < k; ++l) acc += UC[(size_t)i * k + l] * op.U[(size_t)j * k + l];
+            for (int l = 0; l < k; ++l) acc += UC[(size_t)i * k + l] * op.S[(size_t)j * k + l];
             dst[(size_t)i * ns + j] = acc;
           }
       }

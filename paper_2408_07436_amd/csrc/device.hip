@@ -60,7 +60,8 @@ struct DeviceState {
   int32_t* near_src = nullptr;
   double* leaf_centers = nullptr;
   // operators
-  double* surf = nullptr;
+  double* surf = nullptr;    // [ns][3] equivalent-surface offsets
+  double* surf_c = nullptr;  // [nc][3] check-surface offsets
   int16_t* lat2surf = nullptr;
   int16_t* surf_lat = nullptr;
   double *up_V = nullptr, *up_Ut = nullptr, *down_V = nullptr, *down_Ut = nullptr;
@@ -70,8 +71,8 @@ struct DeviceState {
   double *up_P = nullptr, *down_P = nullptr, *m2m_c = nullptr, *l2l_c = nullptr;
   void* khat = nullptr;
   void* twiddle = nullptr;
-  double* Ublas = nullptr;   // ns x k
-  double* UblasT = nullptr;  // k x ns
+  double* Ublas = nullptr;   // nc x k: decompression
+  double* SblasT = nullptr;  // k x ns: compression
   // packed per-t M2L operators of the fused kernel (see pack_blas_operators)
   int blas_mode = 0, kp = 0;
   bool two_stage = false;
@@ -401,6 +402,7 @@ kifmm_status upload_all(kifmm_handle* h) {
   }
 
   KIFMM_TRY(upload(d, &d->surf, op.surf.data(), op.surf.size()));
+  KIFMM_TRY(upload(d, &d->surf_c, op.surf_c.data(), op.surf_c.size()));
   {
     std::vector<int16_t> sl(op.lattice.begin(), op.lattice.end());
     KIFMM_TRY(upload(d, &d->surf_lat, sl.data(), sl.size()));
@@ -492,11 +494,11 @@ kifmm_status upload_all(kifmm_handle* h) {
     }
   } else {
     const int k = op.k;
-    std::vector<double> Ut((size_t)k * ns);
+    std::vector<double> St((size_t)k * ns);
     for (int i = 0; i < ns; ++i)
-      for (int j = 0; j < k; ++j) Ut[(size_t)j * ns + i] = op.U[(size_t)i * k + j];
+      for (int j = 0; j < k; ++j) St[(size_t)j * ns + i] = op.S[(size_t)i * k + j];
     KIFMM_TRY(upload(d, &d->Ublas, op.U.data(), op.U.size()));
-    KIFMM_TRY(upload(d, &d->UblasT, Ut.data(), Ut.size()));
+    KIFMM_TRY(upload(d, &d->SblasT, St.data(), St.size()));
     KIFMM_TRY(pack_blas_operators(h, d));
   }
   for (int e = 0; e < 8; ++e) KIFMM_HIP(hipEventCreate(&d->ev[e]));
@@ -548,8 +550,10 @@ kifmm_status ensure_work(kifmm_handle* h, int nvec) {
     KIFMM_TRY(dalloc(d, &d->mult[l], (size_t)t.levels[l].n * nvec * ns, true));
     KIFMM_TRY(dalloc(d, &d->local[l], (size_t)t.levels[l].n * nvec * ns, true));
   }
-  const size_t kmax = std::max<size_t>(ns, (size_t)std::max(op.k, 1));
-  KIFMM_TRY(dalloc(d, &d->phi, (size_t)maxn * nvec * ns, true));
+  // check potentials have nc >= ns entries per box and vector
+  const size_t ncs = std::max<size_t>(ns, (size_t)op.nc);
+  const size_t kmax = std::max<size_t>(ncs, (size_t)std::max(op.k, 1));
+  KIFMM_TRY(dalloc(d, &d->phi, (size_t)maxn * nvec * ncs, true));
   KIFMM_TRY(dalloc(d, &d->tmp, (size_t)maxn * nvec * kmax, true));
   KIFMM_TRY(dalloc(d, &d->tmp2, (size_t)maxn * nvec * kmax, true));
   d->gemm_ws_elems = (int64_t)8 << 20;  // 64 MiB of split-K partials
@@ -582,12 +586,13 @@ hipError_t gemm(DeviceState* d, Gemm64 g, hipStream_t s) {
   return launch_gemm64(g, s);
 }
 
-// Apply a unit-box pseudo-inverse V (Ut phi) scaled by the box width w.
+// Apply a unit-box pseudo-inverse V (Ut phi) scaled by the box width w:
+// check potentials [box][v][nc] -> equivalent densities [box][v][ns].
 kifmm_status pinv_apply(kifmm_handle* h, const double* V, const double* Ut, int r, double w,
                         const double* in, double* out, int64_t nbox, int nvec, hipStream_t s) {
   DeviceState* d = h->dev;
-  const int ns = h->op.ns;
-  Gemm64 g1{Ut, r, ns, ns, w, in, ns, 1, nullptr, (int64_t)nvec * ns, ns,
+  const int ns = h->op.ns, nc = h->op.nc;  // equivalent-side and check-side points
+  Gemm64 g1{Ut, r, nc, nc, w, in, nc, 1, nullptr, (int64_t)nvec * nc, nc,
             d->tmp, r, 1, nullptr, (int64_t)nvec * r, r, nbox, nvec, 0};
   KIFMM_LAUNCH(gemm(d, g1, s));
   Gemm64 g2{V, ns, r, r, 1.0, d->tmp, r, 1, nullptr, (int64_t)nvec * r, r,
@@ -596,13 +601,14 @@ kifmm_status pinv_apply(kifmm_handle* h, const double* V, const double* Ut, int 
   return KIFMM_OK;
 }
 
-// M2L check potentials of one level: out[box][v][ns] (overwritten)
+// M2L check potentials of one level: in[box][v][ns] equivalent densities,
+// out[box][v][nc] check potentials (overwritten)
 kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, int nvec,
                        hipStream_t s, bool timed) {
   DeviceState* d = h->dev;
   const Operators& op = h->op;
   const DevLevel& D = d->lv[l];
-  const int ns = op.ns;
+  const int ns = op.ns, ncp = op.nc;
   hipEvent_t* mark = timed ? &d->lev_ev[4 * l] : nullptr;
   if (mark) KIFMM_HIP(hipEventRecord(mark[0], s));
   if (h->cfg.m2l == KIFMM_M2L_FFT) {
@@ -627,8 +633,8 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
   const bool dense = h->cfg.m2l == KIFMM_M2L_DENSE;
   const double* qsrc = in;
   if (!dense) {
-    // compressed multipoles  Q~ = S^T Q  (S = U)
-    Gemm64 g{d->UblasT, k, ns, ns, 1.0, in, ns, 1, nullptr, (int64_t)nvec * ns, ns,
+    // compressed multipoles  Q~ = S^T Q
+    Gemm64 g{d->SblasT, k, ns, ns, 1.0, in, ns, 1, nullptr, (int64_t)nvec * ns, ns,
              d->tmp, k, 1, nullptr, (int64_t)nvec * k, k, D.n, nvec, 0};
     KIFMM_LAUNCH(gemm(d, g, s));
     qsrc = d->tmp;
@@ -659,8 +665,8 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
   if (mark) KIFMM_HIP(hipEventRecord(mark[2], s));
   if (!dense) {
     // check potentials  Phi = U Phi~
-    Gemm64 g{d->Ublas, ns, k, k, 1.0, d->tmp2, k, 1, nullptr, (int64_t)nvec * k, k,
-             out, ns, 1, nullptr, (int64_t)nvec * ns, ns, D.n, nvec, 0};
+    Gemm64 g{d->Ublas, ncp, k, k, 1.0, d->tmp2, k, 1, nullptr, (int64_t)nvec * k, k,
+             out, ncp, 1, nullptr, (int64_t)nvec * ncp, ncp, D.n, nvec, 0};
     KIFMM_LAUNCH(gemm(d, g, s));
   }
   if (mark) KIFMM_HIP(hipEventRecord(mark[3], s));
@@ -714,7 +720,7 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
   DeviceState* d = h->dev;
   const Tree& t = h->tree;
   const Operators& op = h->op;
-  const int depth = t.depth, ns = op.ns;
+  const int depth = t.depth, ns = op.ns, nc = op.nc;  // equivalent / check points
   const bool timed = h->timing;
   if (timed) KIFMM_HIP(hipEventRecord(d->ev[0], s));
 
@@ -745,14 +751,14 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
   // upward pass
   if (timed) KIFMM_HIP(hipEventRecord(d->ev[6], s));
   KIFMM_LAUNCH(launch_p2m(d->src_xyz, d->qs, d->fp64, t.n_src, d->src_start, d->src_end,
-                          d->leaf_centers, leaf.n, d->surf, ar_leaf, ns, nvec, d->phi, s));
+                          d->leaf_centers, leaf.n, d->surf_c, ar_leaf, nc, nvec, d->phi, s));
   if (timed) KIFMM_HIP(hipEventRecord(d->ev[7], s));
   // FP64: two-factor pseudo-inverses after each M2M (Section 2.1.1); the
   // reduced-precision modes apply the composite operators (M2M with the
   // parent's pseudo-inverse folded in: the width scalings cancel)
   const bool composite = !d->fp64;
   if (composite) {
-    Gemm64 g{d->up_P, ns, ns, ns, leaf.w, d->phi, ns, 1, nullptr, (int64_t)nvec * ns, ns,
+    Gemm64 g{d->up_P, ns, nc, nc, leaf.w, d->phi, nc, 1, nullptr, (int64_t)nvec * nc, nc,
              d->mult[depth], ns, 1, nullptr, (int64_t)nvec * ns, ns, leaf.n, nvec, 0};
     KIFMM_LAUNCH(gemm(d, g, s));
   } else {
@@ -767,8 +773,8 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
       KIFMM_LAUNCH(gemm(d, g, st));
       return KIFMM_OK;
     }
-    Gemm64 g{d->m2m, ns, 8 * ns, 8 * ns, 1.0 / D.w, d->mult[l + 1], ns, 8, D.child,
-             (int64_t)nvec * ns, ns, d->phi, ns, 1, nullptr, (int64_t)nvec * ns, ns, D.n, nvec, 0};
+    Gemm64 g{d->m2m, nc, 8 * ns, 8 * ns, 1.0 / D.w, d->mult[l + 1], ns, 8, D.child,
+             (int64_t)nvec * ns, ns, d->phi, nc, 1, nullptr, (int64_t)nvec * nc, nc, D.n, nvec, 0};
     KIFMM_LAUNCH(gemm(d, g, st));
     return pinv_apply(h, d->up_V, d->up_Ut, op.r_up, D.w, d->phi, d->mult[l], D.n, nvec, st);
   };
@@ -778,7 +784,7 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
     const DevLevel& D = d->lv[l];
     if (composite) {
       // local = w down_P chk + (w / w_parent) [down_P L_o] local_parent
-      Gemm64 g1{d->down_P, ns, ns, ns, D.w, chk, ns, 1, nullptr, (int64_t)nvec * ns, ns,
+      Gemm64 g1{d->down_P, ns, nc, nc, D.w, chk, nc, 1, nullptr, (int64_t)nvec * nc, nc,
                 d->local[l], ns, 1, nullptr, (int64_t)nvec * ns, ns, D.n, nvec, 0};
       KIFMM_LAUNCH(gemm(d, g1, st));
       if (l >= 3) {
@@ -792,8 +798,8 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
     }
     if (l >= 3) {
       const DevLevel& P = d->lv[l - 1];
-      Gemm64 g{d->l2l, 8 * ns, ns, ns, 1.0 / P.w, d->local[l - 1], ns, 1, nullptr,
-               (int64_t)nvec * ns, ns, chk, ns, 8, P.child, (int64_t)nvec * ns, ns, P.n, nvec, 1};
+      Gemm64 g{d->l2l, 8 * nc, ns, ns, 1.0 / P.w, d->local[l - 1], ns, 1, nullptr,
+               (int64_t)nvec * ns, ns, chk, nc, 8, P.child, (int64_t)nvec * nc, nc, P.n, nvec, 1};
       KIFMM_LAUNCH(gemm(d, g, st));
     }
     return pinv_apply(h, d->down_V, d->down_Ut, op.r_down, D.w, chk, d->local[l], D.n, nvec, st);

@@ -79,26 +79,33 @@ bool svd_left_wide(const double* A, int m, int n, std::vector<double>& U, std::v
 
 // ---- operators ------------------------------------------------------------
 struct Operators {
-  int p = 0, ns = 0, F = 0, n = 0;  // order, surface points, spectrum length, grid size 2p-1
+  // equivalent surfaces of order p (ns = n_e points), check surfaces of order
+  // pc >= p (nc = n_c points; pc = p except for BLAS-M2L with a finer check
+  // surface); spectrum length and grid size 2p-1 of the FFT form
+  int p = 0, ns = 0, F = 0, n = 0;
+  int pc = 0, nc = 0;
   double ai = 1.05, ao = 2.95;
   std::vector<double> surf;         // [ns][3] unit offsets -1 + 2 i/(p-1)
   std::vector<int32_t> lattice;     // [ns][3] integer positions
-  // pseudo-inverses of the unit box (width 1), V (ns x r) and Ut (r x ns)
+  std::vector<double> surf_c;       // [nc][3] check-surface offsets -1 + 2 i/(pc-1)
+  // pseudo-inverses of K(check, equivalent) of the unit box (width 1),
+  // V (ns x r) and Ut (r x nc)
   int r_up = 0, r_down = 0;
   std::vector<double> up_V, up_Ut, down_V, down_Ut;
-  // M2M: [ns] x [8 ns] = [K_0 .. K_7] for a parent of width 1
+  // M2M: [nc] x [8 ns] = [K_0 .. K_7] for a parent of width 1
   std::vector<double> m2m;
-  // L2L: [8 ns] x [ns] = [L_0; ..; L_7] for a parent of width 1
+  // L2L: [8 nc] x [ns] = [L_0; ..; L_7] for a parent of width 1
   std::vector<double> l2l;
   // composite forms for the reduced-precision modes: up_P = up_V up_Ut,
-  // down_P = down_V down_Ut (ns x ns), m2m_c = up_P m2m (ns x 8 ns),
+  // down_P = down_V down_Ut (ns x nc), m2m_c = up_P m2m (ns x 8 ns),
   // l2l_c = [down_P L_0; ..; down_P L_7] (8 ns x ns)
   std::vector<double> up_P, down_P, m2m_c, l2l_c;
   // FFT: kernel spectra of the unit box, [316][F] complex (re, im)
   std::vector<double> spectra;
-  // BLAS / dense M2L of the unit box
+  // BLAS / dense M2L of the unit box: K_t ~ U C_t S^T
   int k = 0;                         // compressed rank (= ns for dense)
-  std::vector<double> U;             // ns x k (row-major)
+  std::vector<double> U;             // nc x k (row-major): decompression
+  std::vector<double> S;             // ns x k (row-major): compression (= U when nc = ns)
   std::vector<int> kt;               // per t rank (k when not recompressed)
   std::vector<std::vector<double>> Ubar, Vbarp;  // per t: k x kt (row-major)
   bool recompressed = false;

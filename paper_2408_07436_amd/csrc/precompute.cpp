@@ -44,13 +44,38 @@ double lap(const double* x, const double* y) {
   return r == 0.0 ? 0.0 : kInv4Pi / r;
 }
 
-// points c + alpha * r * s_i
-std::vector<double> place(const Operators& op, double alpha, double r, const double c[3]) {
-  std::vector<double> pts((size_t)op.ns * 3);
+// points c + alpha * r * s_i of a surface given by its unit offsets
+std::vector<double> place_on(const std::vector<double>& surf, double alpha, double r, const double c[3]) {
+  std::vector<double> pts(surf.size());
   const double ar = alpha * r;
-  for (int i = 0; i < op.ns; ++i)
-    for (int k = 0; k < 3; ++k) pts[3 * i + k] = c[k] + ar * op.surf[3 * i + k];
+  for (size_t i = 0; i < surf.size() / 3; ++i)
+    for (int k = 0; k < 3; ++k) pts[3 * i + k] = c[k] + ar * surf[3 * i + k];
   return pts;
+}
+// equivalent surface (order p) and check surface (order pc)
+std::vector<double> place(const Operators& op, double alpha, double r, const double c[3]) {
+  return place_on(op.surf, alpha, r, c);
+}
+std::vector<double> place_c(const Operators& op, double alpha, double r, const double c[3]) {
+  return place_on(op.surf_c, alpha, r, c);
+}
+
+// boundary points of the q x q x q lattice, i_x slowest: unit offsets
+// -1 + 2 i / (q - 1) and (optionally) the integer positions
+void lattice_surface(int q, std::vector<double>& surf, std::vector<int32_t>* lattice) {
+  surf.clear();
+  if (lattice) lattice->clear();
+  for (int ix = 0; ix < q; ++ix)
+    for (int iy = 0; iy < q; ++iy)
+      for (int iz = 0; iz < q; ++iz) {
+        const bool bnd = ix == 0 || iy == 0 || iz == 0 || ix == q - 1 || iy == q - 1 || iz == q - 1;
+        if (!bnd) continue;
+        const int id[3] = {ix, iy, iz};
+        for (int k = 0; k < 3; ++k) {
+          if (lattice) lattice->push_back(id[k]);
+          surf.push_back(-1.0 + 2.0 * id[k] / (q - 1));
+        }
+      }
 }
 
 void kernel_block(const std::vector<double>& x, const std::vector<double>& y, int nx, int ny,
@@ -112,50 +137,51 @@ void rdft3(const std::vector<double>& g, int n, std::vector<std::complex<double>
 kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg, const SvdOptions& svd_opt) {
   op = Operators();
   const int p = cfg.order;
+  const int pc = cfg.check_order > 0 ? cfg.check_order : p;
+  if (pc < p) return fail(KIFMM_EINVAL, "check order below the expansion order");
+  if (pc != p && cfg.m2l != KIFMM_M2L_BLAS)
+    return fail(KIFMM_EUNSUPPORTED, "a check order above the expansion order needs BLAS-M2L");
   op.p = p;
+  op.pc = pc;
   op.ai = cfg.alpha_inner > 0 ? cfg.alpha_inner : 1.05;
   op.ao = cfg.alpha_outer > 0 ? cfg.alpha_outer : 2.95;
-  for (int ix = 0; ix < p; ++ix)
-    for (int iy = 0; iy < p; ++iy)
-      for (int iz = 0; iz < p; ++iz) {
-        const bool bnd = ix == 0 || iy == 0 || iz == 0 || ix == p - 1 || iy == p - 1 || iz == p - 1;
-        if (!bnd) continue;
-        const int id[3] = {ix, iy, iz};
-        for (int k = 0; k < 3; ++k) {
-          op.lattice.push_back(id[k]);
-          op.surf.push_back(-1.0 + 2.0 * id[k] / (p - 1));
-        }
-      }
+  lattice_surface(p, op.surf, &op.lattice);
   op.ns = (int)op.lattice.size() / 3;
+  if (pc == p)
+    op.surf_c = op.surf;
+  else
+    lattice_surface(pc, op.surf_c, nullptr);
+  op.nc = (int)op.surf_c.size() / 3;
   // convolution grid of 2p - 1 points per axis: the offsets of check and
   // equivalent lattice points span 2p - 1 values, so the circular
   // convolution does not wrap (the paper pads to 2p)
   op.n = 2 * p - 1;
   op.F = op.n * op.n * (op.n / 2 + 1);
-  const int ns = op.ns;
+  const int ns = op.ns, nc = op.nc;
   const double zero[3] = {0, 0, 0};
 
-  // pseudo-inverses of the unit box: up K(UC, UE), down K(DC, DE)
+  // pseudo-inverses of the unit box: up K(UC, UE), down K(DC, DE) (nc x ns)
   {
-    std::vector<double> K((size_t)ns * ns);
-    kernel_block(place(op, op.ao, 0.5, zero), place(op, op.ai, 0.5, zero), ns, ns, K.data(), ns);
-    kifmm_status st = pinv(K, ns, ns, op.r_up, op.up_V, op.up_Ut);
+    std::vector<double> K((size_t)nc * ns);
+    kernel_block(place_c(op, op.ao, 0.5, zero), place(op, op.ai, 0.5, zero), nc, ns, K.data(), ns);
+    kifmm_status st = pinv(K, nc, ns, op.r_up, op.up_V, op.up_Ut);
     if (st != KIFMM_OK) return st;
-    kernel_block(place(op, op.ai, 0.5, zero), place(op, op.ao, 0.5, zero), ns, ns, K.data(), ns);
-    st = pinv(K, ns, ns, op.r_down, op.down_V, op.down_Ut);
+    kernel_block(place_c(op, op.ai, 0.5, zero), place(op, op.ao, 0.5, zero), nc, ns, K.data(), ns);
+    st = pinv(K, nc, ns, op.r_down, op.down_V, op.down_Ut);
     if (st != KIFMM_OK) return st;
   }
-  // M2M [K_0 .. K_7] and L2L [L_0; ..; L_7] for a parent of width 1
-  op.m2m.assign((size_t)ns * 8 * ns, 0.0);
-  op.l2l.assign((size_t)8 * ns * ns, 0.0);
+  // M2M [K_0 .. K_7] (nc x 8 ns) and L2L [L_0; ..; L_7] (8 nc x ns) for a
+  // parent of width 1
+  op.m2m.assign((size_t)nc * 8 * ns, 0.0);
+  op.l2l.assign((size_t)8 * nc * ns, 0.0);
   {
-    const auto uc = place(op, op.ao, 0.5, zero);
+    const auto uc = place_c(op, op.ao, 0.5, zero);
     const auto de = place(op, op.ao, 0.5, zero);
     for (int o = 0; o < 8; ++o) {
       const double c[3] = {(((o >> 0) & 1) - 0.5) * 0.5, (((o >> 1) & 1) - 0.5) * 0.5,
                            (((o >> 2) & 1) - 0.5) * 0.5};
-      kernel_block(uc, place(op, op.ai, 0.25, c), ns, ns, &op.m2m[(size_t)o * ns], 8 * ns);
-      kernel_block(place(op, op.ai, 0.25, c), de, ns, ns, &op.l2l[(size_t)o * ns * ns], ns);
+      kernel_block(uc, place(op, op.ai, 0.25, c), nc, ns, &op.m2m[(size_t)o * ns], 8 * ns);
+      kernel_block(place_c(op, op.ai, 0.25, c), de, nc, ns, &op.l2l[(size_t)o * nc * ns], ns);
     }
   }
 
@@ -170,15 +196,15 @@ kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg, const 
           C[(size_t)i * ldc + j] = (double)acc;
         }
     };
-    op.up_P.assign((size_t)ns * ns, 0.0);
-    op.down_P.assign((size_t)ns * ns, 0.0);
-    matmul(op.up_V.data(), op.up_Ut.data(), ns, op.r_up, ns, op.r_up, ns, op.up_P.data(), ns);
-    matmul(op.down_V.data(), op.down_Ut.data(), ns, op.r_down, ns, op.r_down, ns, op.down_P.data(), ns);
+    op.up_P.assign((size_t)ns * nc, 0.0);
+    op.down_P.assign((size_t)ns * nc, 0.0);
+    matmul(op.up_V.data(), op.up_Ut.data(), ns, op.r_up, nc, op.r_up, nc, op.up_P.data(), nc);
+    matmul(op.down_V.data(), op.down_Ut.data(), ns, op.r_down, nc, op.r_down, nc, op.down_P.data(), nc);
     op.m2m_c.assign((size_t)ns * 8 * ns, 0.0);
-    matmul(op.up_P.data(), op.m2m.data(), ns, ns, 8 * ns, ns, 8 * ns, op.m2m_c.data(), 8 * ns);
+    matmul(op.up_P.data(), op.m2m.data(), ns, nc, 8 * ns, nc, 8 * ns, op.m2m_c.data(), 8 * ns);
     op.l2l_c.assign((size_t)8 * ns * ns, 0.0);
     for (int o = 0; o < 8; ++o)
-      matmul(op.down_P.data(), &op.l2l[(size_t)o * ns * ns], ns, ns, ns, ns, ns,
+      matmul(op.down_P.data(), &op.l2l[(size_t)o * nc * ns], ns, nc, ns, nc, ns,
              &op.l2l_c[(size_t)o * ns * ns], ns);
   }
 
@@ -208,14 +234,14 @@ kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg, const 
     }
   } else {
     // M2L matrices K_t of the unit box (check surface around 0, equivalent
-    // surface around t), both on the inner surface
-    const auto dc = place(op, op.ai, 0.5, zero);
-    std::vector<std::vector<double>> Kt(kNumTransfer, std::vector<double>((size_t)ns * ns));
+    // surface around t), both on the inner surface; nc x ns
+    const auto dc = place_c(op, op.ai, 0.5, zero);
+    std::vector<std::vector<double>> Kt(kNumTransfer, std::vector<double>((size_t)nc * ns));
     parallel_for(kNumTransfer, [&](int it) {
       int t[3];
       transfer_vector(it, t);
       const double c[3] = {(double)t[0], (double)t[1], (double)t[2]};
-      kernel_block(dc, place(op, op.ai, 0.5, c), ns, ns, Kt[it].data(), ns);
+      kernel_block(dc, place(op, op.ai, 0.5, c), nc, ns, Kt[it].data(), ns);
     });
     op.Ubar.assign(kNumTransfer, {});
     op.Vbarp.assign(kNumTransfer, {});
@@ -224,26 +250,31 @@ kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg, const 
       op.k = ns;
       op.U.assign((size_t)ns * ns, 0.0);
       for (int i = 0; i < ns; ++i) op.U[(size_t)i * ns + i] = 1.0;
+      op.S = op.U;
       for (int it = 0; it < kNumTransfer; ++it) {
         op.kt[it] = ns;
         op.Vbarp[it] = Kt[it];  // applied directly as C_t = K_t
       }
       op.recompressed = false;
     } else {
-      // K_fat = [K_1 .. K_T]; K_t^T = K_{-t} makes K_thin's right vectors equal
-      // K_fat's left vectors, so S = U (Section 3.1, symmetric kernels)
-      std::vector<double> Kfat((size_t)ns * kNumTransfer * ns);
-      for (int i = 0; i < ns; ++i)
+      // K_fat = [K_1 .. K_T] (nc x T ns): its left vectors give U.  With
+      // nc = ns, K_t^T = K_{-t} makes K_thin's right vectors equal K_fat's
+      // left vectors, so S = U (Section 3.1, symmetric kernels); otherwise S
+      // comes from the left vectors of K_thin^T = [K_1^T .. K_T^T] (ns x T nc).
+      auto left = [&](const std::vector<double>& A, int m, int n, std::vector<double>& Uo,
+                      std::vector<double>& so) -> kifmm_status {
+        if (svd_opt.mode == KIFMM_SVD_RANDOMIZED) return rsvd_left_device(A.data(), m, n, svd_opt, Uo, so);
+        if (!svd_left_wide(A.data(), m, n, Uo, so)) return fail(KIFMM_ENUMERIC, "SVD of K_fat / K_thin did not converge");
+        return KIFMM_OK;
+      };
+      std::vector<double> Kfat((size_t)nc * kNumTransfer * ns);
+      for (int i = 0; i < nc; ++i)
         for (int it = 0; it < kNumTransfer; ++it)
           std::copy(&Kt[it][(size_t)i * ns], &Kt[it][(size_t)i * ns] + ns,
                     &Kfat[((size_t)i * kNumTransfer + it) * ns]);
       std::vector<double> Uf, sf;
-      if (svd_opt.mode == KIFMM_SVD_RANDOMIZED) {
-        const kifmm_status st = rsvd_left_device(Kfat.data(), ns, kNumTransfer * ns, svd_opt, Uf, sf);
-        if (st != KIFMM_OK) return st;
-      } else if (!svd_left_wide(Kfat.data(), ns, kNumTransfer * ns, Uf, sf)) {
-        return fail(KIFMM_ENUMERIC, "SVD of K_fat did not converge");
-      }
+      kifmm_status st = left(Kfat, nc, kNumTransfer * ns, Uf, sf);
+      if (st != KIFMM_OK) return st;
       const int r0 = (int)sf.size();
       int k = 0;
       if (cfg.svd_rel_tol > 0) {
@@ -251,26 +282,43 @@ kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg, const 
       } else {
         while (k < r0 && sf[k] > 0.0) ++k;
       }
+      std::vector<double> Sf;
+      int rs = r0;
+      if (nc == ns) {
+        Sf = Uf;
+      } else {
+        std::vector<double> KthinT((size_t)ns * kNumTransfer * nc), ss;
+        for (int it = 0; it < kNumTransfer; ++it)
+          for (int i = 0; i < nc; ++i)
+            for (int j = 0; j < ns; ++j) KthinT[((size_t)j * kNumTransfer + it) * nc + i] = Kt[it][(size_t)i * ns + j];
+        st = left(KthinT, ns, kNumTransfer * nc, Sf, ss);
+        if (st != KIFMM_OK) return st;
+        rs = (int)ss.size();
+        k = std::min(k, rs);
+      }
       op.k = k;
-      op.U.assign((size_t)ns * k, 0.0);
-      for (int i = 0; i < ns; ++i)
+      op.U.assign((size_t)nc * k, 0.0);
+      for (int i = 0; i < nc; ++i)
         for (int j = 0; j < k; ++j) op.U[(size_t)i * k + j] = Uf[(size_t)i * r0 + j];
+      op.S.assign((size_t)ns * k, 0.0);
+      for (int i = 0; i < ns; ++i)
+        for (int j = 0; j < k; ++j) op.S[(size_t)i * k + j] = Sf[(size_t)i * rs + j];
       op.recompressed = cfg.svd_rel_tol_dir >= 0;
       // the transfer vectors are independent: one host thread each at a time
       std::atomic<bool> svd_failed{false};
       parallel_for(kNumTransfer, [&](int it) {
-        std::vector<double> tmp((size_t)ns * k), C((size_t)k * k);
-        // C_t = U^T K_t U
-        for (int i = 0; i < ns; ++i)
+        std::vector<double> tmp((size_t)nc * k), C((size_t)k * k);
+        // C_t = U^T K_t S
+        for (int i = 0; i < nc; ++i)
           for (int j = 0; j < k; ++j) {
             double acc = 0;
-            for (int l = 0; l < ns; ++l) acc += Kt[it][(size_t)i * ns + l] * op.U[(size_t)l * k + j];
+            for (int l = 0; l < ns; ++l) acc += Kt[it][(size_t)i * ns + l] * op.S[(size_t)l * k + j];
             tmp[(size_t)i * k + j] = acc;
           }
         for (int i = 0; i < k; ++i)
           for (int j = 0; j < k; ++j) {
             double acc = 0;
-            for (int l = 0; l < ns; ++l) acc += op.U[(size_t)l * k + i] * tmp[(size_t)l * k + j];
+            for (int l = 0; l < nc; ++l) acc += op.U[(size_t)l * k + i] * tmp[(size_t)l * k + j];
             C[(size_t)i * k + j] = acc;
           }
         if (!op.recompressed) {

@@ -195,3 +195,32 @@ def test_set_svd_argument_and_state_errors():
     f.precompute()  # deterministic: host only
     assert lib.kifmm_set_svd(f._h, 1, 0, 10, 0) == 2
     assert b"precompute" in lib.kifmm_last_error()
+
+
+@pytest.mark.parametrize("tol,tol_dir", [(1e-6, 1e-6), (1e-6, -1.0)])
+def test_blas_operators_with_finer_check_surface_match_oracle(tol, tol_dir):
+    """P_c = 5 check points over P_e = 4 equivalent points: the library's ranks and
+    applied n_c x n_e operators equal the oracle's projected ones (host precompute)."""
+    p, pc = 4, 5
+    f = K.KiFMM(p, 3, m2l="blas", svd_rel_tol=tol, svd_rel_tol_dir=tol_dir, check_order=pc)
+    f.set_points(workloads.uniform_cube(100, 58)).precompute()
+    ne, nc = surfaces.n_surface(p), surfaces.n_surface(pc)
+    comp = blas_m2l.compress(blas_m2l.m2l_matrices(p, 0.5, check_order=pc), tol, tol_dir)
+    ranks = f.operator(K.OP_BLAS_RANKS)
+    assert int(ranks[0]) == comp["k"] and comp["k"] <= ne
+    assert np.array_equal(ranks[1:].astype(int), comp["kt"])
+    app = f.operator(K.OP_BLAS_APPLIED).reshape(316, nc, ne)
+    for it in range(316):
+        ref = blas_m2l.applied_operator(comp, it)
+        assert np.abs(app[it] - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert f.operator(K.OP_UP_UT).size == f.operator(K.OP_UP_V).size // ne * nc
+
+
+def test_check_order_validation():
+    with pytest.raises(K.KifmmError) as e:
+        K.KiFMM(4, 3, m2l="blas", check_order=3)
+    assert e.value.code == 1
+    for m2l in ("fft", "dense"):
+        with pytest.raises(K.KifmmError) as e:
+            K.KiFMM(4, 3, m2l=m2l, check_order=5)
+        assert e.value.code == 5
