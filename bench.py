@@ -266,6 +266,38 @@ def run_blas(K, torch, steps, warmup):
     return out
 
 
+def run_check_order(K, torch, w, steps):
+    """BLAS-M2L (FP64, SVD tolerances 1e-6 / 1e-6) on the main workload with check
+    surfaces of the expansion order and of one order more: setup, M2L time and the
+    error against the FP64 direct sum."""
+    out = {"workload": w.name + " (BLAS-M2L FP64, tol 1e-6 / 1e-6)", "order": w.order}
+    q = torch.as_tensor(w.q, dtype=torch.float64, device="cuda")
+    for pc in (w.order, w.order + 1):
+        f = K.KiFMM(w.order, w.depth, m2l="blas", prec="fp64", svd_rel_tol=1e-6, svd_rel_tol_dir=1e-6,
+                    check_order=pc).set_points(w.points)
+        t0 = time.perf_counter()
+        f.precompute()
+        pre_s = time.perf_counter() - t0
+        phi = torch.empty((w.nvec, w.n), dtype=torch.float64, device="cuda")
+        f.evaluate(q, phi)
+        f.set_timing(True)
+        m2l = 0.0
+        for _ in range(steps):
+            f.evaluate(q, phi)
+            m2l += f.timings()["m2l"]
+        f.set_timing(False)
+        torch.cuda.synchronize()
+        err = direct_error(torch, w, phi)
+        out[f"check_order_{pc}"] = {"n_check": 6 * (pc - 1) ** 2 + 2, "precompute_s": round(pre_s, 2),
+                                    "k": int(f.operator(K.OP_BLAS_RANKS)[0]),
+                                    "m2l_ms": round(m2l / steps, 3), "rel_err_vs_direct": err}
+        log(f"  blas fp64 check order {pc}: m2l {m2l / steps:.3f} ms, err vs direct {err:.2e}, "
+            f"precompute {pre_s:.2f} s")
+        del f, phi
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_scale(K, torch, steps, warmup):
     """The paper's larger problem size: 8,000,000 uniform points, depth 6, p = 6,
     FFT-M2L, mixed and FP64, with the error against the FP64 direct sum."""
@@ -425,6 +457,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-scale", action="store_true")
     ap.add_argument("--no-resetup", action="store_true")
+    ap.add_argument("--no-check-order", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the FMM here is a single-GPU build "
@@ -570,6 +603,9 @@ def main():
     if not args.no_resetup:
         log("moving points: host tree build vs device re-setup")
         line["resetup_1M"] = run_resetup(K, torch, w)
+    if not args.no_check_order:
+        log("blas-m2l with a finer check surface: check order p and p + 1")
+        line["check_order_blas"] = run_check_order(K, torch, w, max(1, min(args.steps, 3)))
     if not args.no_blas:
         log("blas-m2l workload: 32 vectors, fp64 / fp32 / bf16x3")
         line["blas_32rhs"] = run_blas(K, torch, max(1, min(args.steps, 3)), 1)
