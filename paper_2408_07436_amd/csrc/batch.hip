@@ -25,10 +25,11 @@ namespace {
 
 void release(kifmm_batch* b) {
   if (!b) return;
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
-  for (auto e : b->events) hipEventDestroy(e);
-  for (auto s : b->streams) hipStreamDestroy(s);
+  // teardown: nothing to do about a failure here
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (auto e : b->events) (void)hipEventDestroy(e);
+  for (auto s : b->streams) (void)hipStreamDestroy(s);
   delete b;
 }
 
@@ -228,7 +229,7 @@ kifmm_status kifmm_batch_launch(kifmm_batch* b, void* hip_stream) {
 
 kifmm_status kifmm_batch_destroy(kifmm_batch* b) {
   if (!b) return KIFMM_OK;
-  hipSetDevice(b->device);
+  (void)hipSetDevice(b->device);
   release(b);
   return KIFMM_OK;
 }

@@ -268,7 +268,7 @@ kifmm_status build_blas_tiles(kifmm_handle* h, DeviceState* d, int TB) {
     DevLevel& D = d->lv[l];
     for (void* p : {(void*)D.tile_box, (void*)D.tl_offs, (void*)D.tl_t, (void*)D.tl_src}) {
       if (!p) continue;
-      hipFree(p);
+      (void)hipFree(p);
       d->allocs.erase(std::remove(d->allocs.begin(), d->allocs.end(), p), d->allocs.end());
     }
     std::vector<int32_t> tile_box, tl_t, tl_src;
@@ -529,7 +529,7 @@ kifmm_status ensure_work(kifmm_handle* h, int nvec) {
     if (TB != d->tile_tb) KIFMM_TRY(build_blas_tiles(h, d, TB));
   }
   if (nvec <= d->nvec_cap) return KIFMM_OK;
-  for (void* p : d->work_allocs) hipFree(p);
+  for (void* p : d->work_allocs) (void)hipFree(p);
   d->work_allocs.clear();
   d->nvec_cap = 0;
   const Tree& t = h->tree;
@@ -677,22 +677,23 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
 
 void destroy_device(DeviceState* d) {
   if (!d) return;
-  hipSetDevice(d->device);
+  // teardown: failures are ignored
+  (void)hipSetDevice(d->device);
   if (d->events)
-    for (auto& e : d->ev) hipEventDestroy(e);
+    for (auto& e : d->ev) (void)hipEventDestroy(e);
   for (auto& e : d->lev_ev)
-    if (e) hipEventDestroy(e);
-  if (d->fork_ev) hipEventDestroy(d->fork_ev);
-  if (d->down_ev) hipEventDestroy(d->down_ev);
+    if (e) (void)hipEventDestroy(e);
+  if (d->fork_ev) (void)hipEventDestroy(d->fork_ev);
+  if (d->down_ev) (void)hipEventDestroy(d->down_ev);
   for (auto& e : d->up_ev)
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
   for (auto& e : d->join_ev)
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
   for (auto& st : d->side)
-    if (st) hipStreamDestroy(st);
-  if (d->coarse) hipStreamDestroy(d->coarse);
-  for (void* p : d->work_allocs) hipFree(p);
-  for (void* p : d->allocs) hipFree(p);
+    if (st) (void)hipStreamDestroy(st);
+  if (d->coarse) (void)hipStreamDestroy(d->coarse);
+  for (void* p : d->work_allocs) (void)hipFree(p);
+  for (void* p : d->allocs) (void)hipFree(p);
   delete d;
 }
 
