@@ -83,3 +83,27 @@ def test_randomized_svd_default_rank_and_seed_reproducible():
     # rank n_s / 2 truncates K_fat at sigma_76 / sigma_0; the FMM's own p = 6
     # error against the direct sum is ~5e-7, so the compression stays below 1e-4
     assert ea < 1e-4 and ec < 1e-4
+
+
+def test_randomized_svd_with_finer_check_surface():
+    """With P_c > P_e both K_fat (for U) and K_thin^T (for S) are sketched.  The rank
+    is capped at n_e = 56, well inside K_fat's slowly decaying spectrum (no gap at the
+    cut), so both compressions sit at their truncation error against the uncompressed
+    FMM, and the sketch's stays within twice the deterministic one's."""
+    p, pc = 4, 5
+    pts = workloads.uniform_cube(20000, 955)
+    q = workloads.charges(20000, 2, 956, "normal")
+    tol = 1e-6
+    out = {}
+    for mode in ("deterministic", "randomized"):
+        f = K.KiFMM(p, 4, m2l="blas", prec="fp64", svd_rel_tol=tol, svd_rel_tol_dir=-1.0, check_order=pc)
+        if mode == "randomized":
+            f.set_svd("randomized", rank=56, oversample=10, seed=3)
+        f.set_points(pts).precompute()
+        qd = torch.as_tensor(q, dtype=torch.float64, device="cuda")
+        out[mode] = f.evaluate(qd).cpu().numpy()
+        torch.cuda.synchronize()
+    ref = fmm.KiFMM(pts, pts, 4, p, check_order=pc).evaluate(q)
+    e_det, e_rnd = kernel.rel_l2(out["deterministic"], ref), kernel.rel_l2(out["randomized"], ref)
+    say(f"case: rsvd with P_e {p} P_c {pc}: vs uncompressed oracle det {e_det:.3e} rnd {e_rnd:.3e}")
+    assert e_rnd <= 2 * e_det
