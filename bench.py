@@ -267,13 +267,14 @@ def run_blas(K, torch, steps, warmup):
 
 
 def run_check_order(K, torch, w, steps):
-    """BLAS-M2L (FP64, SVD tolerances 1e-6 / 1e-6) on the main workload with check
-    surfaces of the expansion order and of one order more: setup, M2L time and the
-    error against the FP64 direct sum."""
-    out = {"workload": w.name + " (BLAS-M2L FP64, tol 1e-6 / 1e-6)", "order": w.order}
+    """BLAS-M2L (FP64, SVD tolerance 1e-6, no directional recompression: a configuration
+    no other section precomputes, so both setups are timed uncached) on the main
+    workload with check surfaces of the expansion order and of one order more: setup,
+    M2L time and the error against the FP64 direct sum."""
+    out = {"workload": w.name + " (BLAS-M2L FP64, tol 1e-6, no recompression)", "order": w.order}
     q = torch.as_tensor(w.q, dtype=torch.float64, device="cuda")
     for pc in (w.order, w.order + 1):
-        f = K.KiFMM(w.order, w.depth, m2l="blas", prec="fp64", svd_rel_tol=1e-6, svd_rel_tol_dir=1e-6,
+        f = K.KiFMM(w.order, w.depth, m2l="blas", prec="fp64", svd_rel_tol=1e-6, svd_rel_tol_dir=-1.0,
                     check_order=pc).set_points(w.points)
         t0 = time.perf_counter()
         f.precompute()
