@@ -297,11 +297,14 @@ __global__ __launch_bounds__((FftCfg<T, P>::threads)) void fft_forward_kernel(
 
 // Inverse transforms, one (row, child) box per item: complex inverse DFTs
 // along x (only x < p kept) and y (y < p), then the complex-to-real step
-// along z (odd length: no Nyquist term) at the check-surface points, scaled.
-// Twiddles conj(Wm[k][j]): at wave-uniform addresses (scalar registers) in
-// the x stage, from an LDS copy in the y and z stages, which take one output
-// per task.  The row's child boxes and the surface-lattice table are read
-// once per workgroup, so the output stores wait on no vector-memory load.
+// along z (odd length: no Nyquist term) at the p^3 lattice points, and the
+// check-surface points of those, scaled, stored in surface order.  Each
+// stage takes one line per task: the line's inputs in registers, and the
+// outputs one at a time (loop not unrolled) with that output's twiddles
+// conj(Wm[k][j]) at wave-uniform addresses (scalar registers), so the LDS
+// carries each intermediate value once in and once out.  The row's child
+// boxes and the surface-lattice table are read once per workgroup, so the
+// output stores wait on no vector-memory load.
 constexpr int kInvThreads = 256;
 template <typename C2>
 __device__ inline C2 cmulc(C2 a, C2 b) {  // a * conj(b)
@@ -320,7 +323,9 @@ __global__ __launch_bounds__(kInvThreads) void fft_inverse_kernel(
   __shared__ C2 b2[ITEMS][P][N][H];
   __shared__ C2 b1[ITEMS][P][P][H];
   __shared__ int16_t sl[3 * NS];
-  __shared__ C2 wl[N * P];  // twiddles read at lane-varying indices
+  // real lattice values of the z stage, in b2 (free after the y stage)
+  static_assert(sizeof(T) * P * P * P <= sizeof(C2) * P * N * H, "lattice fits in b2");
+  T* zb = reinterpret_cast<T*>(&b2[0][0][0][0]);
   static_assert(ITEMS <= 8 && 8 % ITEMS == 0, "a workgroup's items lie within one row");
   const int tid = threadIdx.x;
   // consecutive rows on one XCD, so the two 64-byte halves of a 128-byte
@@ -330,7 +335,6 @@ __global__ __launch_bounds__(kInvThreads) void fft_inverse_kernel(
   if (wg >= nwg) return;
   const int64_t g0 = wg * ITEMS;
   for (int t = tid; t < 3 * NS; t += kInvThreads) sl[t] = surf_lat[t];
-  for (int t = tid; t < N * P; t += kInvThreads) wl[t] = Wm[t];
   // the row's child boxes, read with scalar loads (uniform addresses), so
   // the output stores need no vector-memory wait between them
   const uint32_t row0 = (uint32_t)(g0 / 8), c0 = row0 / (uint32_t)nvec;
@@ -370,24 +374,43 @@ __global__ __launch_bounds__(kInvThreads) void fft_inverse_kernel(
     }
   }
   __syncthreads();
-  // y: complex inverse, y in [0, p)
-  for (int idx = tid; idx < ITEMS * P * P * H; idx += kInvThreads) {
-    const int it = idx / (P * P * H);
-    const int rem = idx % (P * P * H);
-    const int x = rem / (P * H), y = (rem / H) % P, kz = rem % H;
-    C2 acc;
-    acc.x = T(0);
-    acc.y = T(0);
+  // y: complex inverse, y in [0, p); one task per (item, x, kz) line
+  for (int idx = tid; idx < ITEMS * P * H; idx += kInvThreads) {
+    const int it = idx / (P * H), x = (idx / H) % P, kz = idx % H;
+    C2 v[N];
 #pragma unroll
-    for (int ky = 0; ky < N; ++ky) {
-      const C2 t = cmulc(b2[it][x][ky][kz], wl[ky * P + y]);
-      acc.x += t.x;
-      acc.y += t.y;
+    for (int ky = 0; ky < N; ++ky) v[ky] = b2[it][x][ky][kz];
+#pragma unroll 1
+    for (int y = 0; y < P; ++y) {
+      C2 acc;
+      acc.x = T(0);
+      acc.y = T(0);
+#pragma unroll
+      for (int ky = 0; ky < N; ++ky) {
+        const C2 t = cmulc(v[ky], Wm[ky * P + y]);
+        acc.x += t.x;
+        acc.y += t.y;
+      }
+      b1[it][x][y][kz] = acc;
     }
-    b1[it][x][y][kz] = acc;
   }
   __syncthreads();
-  // z: complex -> real on the check-surface points only
+  // z: complex -> real at every lattice point; one task per (item, x, y) line
+  for (int idx = tid; idx < ITEMS * P * P; idx += kInvThreads) {
+    const int it = idx / (P * P), x = (idx / P) % P, y = idx % P;
+    C2 v[H];
+#pragma unroll
+    for (int kz = 0; kz < H; ++kz) v[kz] = b1[it][x][y][kz];
+#pragma unroll 1
+    for (int z = 0; z < P; ++z) {
+      T acc = T(0);
+#pragma unroll
+      for (int kz = 1; kz < H; ++kz) acc += cmulc(v[kz], Wm[kz * P + z]).x;
+      zb[((it * P + x) * P + y) * P + z] = v[0].x + T(2) * acc;
+    }
+  }
+  __syncthreads();
+  // the check-surface points, scaled
   for (int idx = tid; idx < ITEMS * NS; idx += kInvThreads) {
     const int it = idx / NS, s = idx % NS;
     const int ch = (int)(g0 % 8) + it;
@@ -397,12 +420,7 @@ __global__ __launch_bounds__(kInvThreads) void fft_inverse_kernel(
       if (ch == j) box = cb[j];
     if (box < 0) continue;
     const int x = sl[3 * s], y = sl[3 * s + 1], z = sl[3 * s + 2];
-    T val = b1[it][x][y][0].x;
-    T acc = T(0);
-#pragma unroll
-    for (int kz = 1; kz < H; ++kz) acc += cmulc(b1[it][x][y][kz], wl[kz * P + z]).x;
-    val += T(2) * acc;
-    out[((int64_t)box * nvec + v0) * NS + s] = scale * (double)val;
+    out[((int64_t)box * nvec + v0) * NS + s] = scale * (double)zb[((it * P + x) * P + y) * P + z];
   }
 }
 

@@ -4,9 +4,9 @@
 //
 // The operators have few rows (n_s = 152 at p = 6, or 8 n_s for L2L) and the
 // data has many columns (boxes x charge vectors), so a workgroup owns 64
-// data columns and a block of 160 operator rows: each of its four waves
-// computes 16 data columns x 160 rows on v_mfma_f64_16x16x4f64 (ten 16 x 16
-// accumulator tiles).  The product runs in transposed form - data columns
+// data columns and a block of 80 operator rows: each of its four waves
+// computes 16 data columns x 80 rows on v_mfma_f64_16x16x4f64 (five 16 x 16
+// accumulator tiles), which leaves registers for four workgroups per CU.  The product runs in transposed form - data columns
 // are the MFMA rows - so the sixteen lanes holding one accumulator row store
 // sixteen consecutive entries of one output column.  K is staged through LDS
 // sixteen at a time, with the next slice's global loads issued before the
@@ -25,8 +25,8 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int kMT = 10;            // 16-row MFMA tiles per wave along the operator rows
-constexpr int kBM = 16 * kMT;      // 160 operator rows per workgroup
+constexpr int kMT = 5;             // 16-row MFMA tiles per wave along the operator rows
+constexpr int kBM = 16 * kMT;      // 80 operator rows per workgroup
 constexpr int kBN = 64;            // data columns per workgroup (16 per wave)
 constexpr int kBK = 16;
 constexpr int kALoads = kBK * kBM / 256;  // operator values per thread per K slice
@@ -55,7 +55,7 @@ __device__ inline void col_split(int64_t col, int nvec, const FastDiv& fv, int64
 
 // blockIdx.z selects the K range [kz0, kz1) of a split product; with
 // `partial` set the raw sums go to partial[z][col][m] (m < M) instead of C.
-__global__ __launch_bounds__(256, 2) void gemm64_kernel(Gemm64 g, int kchunk, double* partial) {
+__global__ __launch_bounds__(256, 4) void gemm64_kernel(Gemm64 g, int kchunk, double* partial) {
   __shared__ double As[kBK][kBM + 2];  // operator, k-major
   __shared__ double Bs[kBK][kBN + 2];  // data columns, k-major
   const int tid = threadIdx.x;
@@ -188,8 +188,17 @@ __global__ __launch_bounds__(256) void gemm64_reduce_kernel(Gemm64 g, int nsplit
   uint32_t mr;
   const int64_t col = fdiv((uint32_t)i, g.div_M, mr);
   const int m = (int)mr;
+  // eight partials in flight at a time, summed in order z = 0, 1, ...
   double sum = 0.0;
-  for (int z = 0; z < nsplit; ++z) sum += partial[(int64_t)z * total + i];
+  int z = 0;
+  for (; z + 8 <= nsplit; z += 8) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = partial[(int64_t)(z + u) * total + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sum += t[u];
+  }
+  for (; z < nsplit; ++z) sum += partial[(int64_t)z * total + i];
   int64_t b;
   int v;
   col_split(col, g.nvec, g.div_nvec, b, v);
