@@ -101,6 +101,10 @@ struct DeviceState {
   std::vector<hipStream_t> side;    // [depth + 1]: M2L of coarse level l
   hipEvent_t fork_ev = nullptr;     // leaf multipoles ready
   hipEvent_t down_ev = nullptr;     // coarse locals ready
+  // the near field runs on its own stream from the sorted charges on
+  hipStream_t nearst = nullptr;
+  hipEvent_t near_fork_ev = nullptr;  // sorted charges ready
+  hipEvent_t near_ev = nullptr;       // near-field sums stored
   std::vector<hipEvent_t> up_ev;    // [depth + 1] multipoles of coarse level l ready
   std::vector<hipEvent_t> join_ev;  // [depth + 1] M2L of coarse level l done
   std::vector<void*> work_allocs;
@@ -517,6 +521,9 @@ kifmm_status upload_all(kifmm_handle* h) {
     }
     KIFMM_HIP(hipEventCreateWithFlags(&d->fork_ev, hipEventDisableTiming));
     KIFMM_HIP(hipEventCreateWithFlags(&d->down_ev, hipEventDisableTiming));
+    KIFMM_HIP(hipStreamCreateWithFlags(&d->nearst, hipStreamNonBlocking));
+    KIFMM_HIP(hipEventCreateWithFlags(&d->near_fork_ev, hipEventDisableTiming));
+    KIFMM_HIP(hipEventCreateWithFlags(&d->near_ev, hipEventDisableTiming));
   }
   return KIFMM_OK;
 }
@@ -685,6 +692,9 @@ void destroy_device(DeviceState* d) {
     if (e) (void)hipEventDestroy(e);
   if (d->fork_ev) (void)hipEventDestroy(d->fork_ev);
   if (d->down_ev) (void)hipEventDestroy(d->down_ev);
+  if (d->near_fork_ev) (void)hipEventDestroy(d->near_fork_ev);
+  if (d->near_ev) (void)hipEventDestroy(d->near_ev);
+  if (d->nearst) (void)hipStreamDestroy(d->nearst);
   for (auto& e : d->up_ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& e : d->join_ev)
@@ -732,7 +742,8 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
   // kernels (near field, then far field), so each phase and kernel is timed
   // on its own; `serial` (other M2L forms, and under stream capture, where
   // the multi-stream graph is not recorded) runs everything back to back on
-  // s.  graph and serial use the fused leaf kernel.
+  // s.  graph runs the near field on a stream of its own from the start and
+  // the far field last; serial uses the fused leaf kernel.
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   KIFMM_HIP(hipStreamIsCapturing(s, &cap));
   const bool fork = fft && cap == hipStreamCaptureStatusNone;
@@ -749,6 +760,16 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
   };
 
   KIFMM_LAUNCH(launch_gather(q, ldq, d->src_perm, t.n_src, nvec, d->fp64, d->qs, s));
+  if (graph) {
+    // The near field needs only the sorted charges: it runs on its own
+    // stream, concurrently with the upward, M2L and downward passes, and
+    // stores its raw sums, which the far-field kernel completes at the end
+    // (near then far gives exactly the fused kernel's result).
+    KIFMM_HIP(hipEventRecord(d->near_fork_ev, s));
+    KIFMM_HIP(hipStreamWaitEvent(d->nearst, d->near_fork_ev, 0));
+    KIFMM_TRY(leaf_pass(1, d->nearst));
+    KIFMM_HIP(hipEventRecord(d->near_ev, d->nearst));
+  }
   // upward pass
   if (timed) KIFMM_HIP(hipEventRecord(d->ev[6], s));
   KIFMM_LAUNCH(launch_p2m(d->src_xyz, d->qs, d->fp64, t.n_src, d->src_start, d->src_end,
@@ -831,7 +852,8 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
     KIFMM_HIP(hipEventRecord(d->down_ev, d->coarse));
     KIFMM_HIP(hipStreamWaitEvent(s, d->down_ev, 0));
     KIFMM_TRY(down_level(depth, d->lv[depth].chk, s));
-    return leaf_pass(0, s);
+    KIFMM_HIP(hipStreamWaitEvent(s, d->near_ev, 0));
+    return leaf_pass(2, s);
   }
   for (int l = depth - 1; l >= 2; --l) KIFMM_TRY(m2m_level(l, s));
   if (timed) KIFMM_HIP(hipEventRecord(d->ev[1], s));
