@@ -461,8 +461,8 @@ def main():
     ap.add_argument("--no-check-order", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the FMM here is a single-GPU build "
-              "(see DESIGN.md for how the path would shard); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the FMM here is a single-GPU build; "
+              "use --gpus 1", file=sys.stderr)
         return 2
     import torch
     import paper_2408_07436_amd as K
