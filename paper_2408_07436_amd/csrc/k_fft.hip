@@ -305,7 +305,7 @@ __global__ __launch_bounds__((FftCfg<T, P>::threads)) void fft_forward_kernel(
 // carries each intermediate value once in and once out.  The row's child
 // boxes and the surface-lattice table are read once per workgroup, so the
 // output stores wait on no vector-memory load.
-constexpr int kInvThreads = 256;
+constexpr int kInvThreads = 512;  // with 8 boxes per workgroup: each y / z line in one pass
 template <typename C2>
 __device__ inline C2 cmulc(C2 a, C2 b) {  // a * conj(b)
   C2 r;
