@@ -95,8 +95,11 @@ KIFMM_FFT_LDS(8, 4, 1, 9, 72, 576, 8, 120, 960)
 template <typename T, int P> struct FftCfg {
   using L = FftLds<P, (int)sizeof(T) / 2>;
   static constexpr int items = L::items;
-  // one thread per line of the z and y stages
-  static constexpr int threads = (items * P * P + 63) / 64 * 64;
+  // one thread per line of the z stage, and at least seven waves: the MFMA
+  // stages then spread over more waves and the persistent grid holds fewer,
+  // larger workgroups, which runs faster beside the coarse levels' M2L
+  static constexpr int lines = (items * P * P + 63) / 64 * 64;
+  static constexpr int threads = lines > 448 ? lines : 448;
 };
 
 // Forward transforms of `items` boxes per workgroup in three stages, with
