@@ -507,12 +507,16 @@ def main():
     fwd_s, inv_s = lk["fft_forward"] * 1e-3, lk["fft_inverse"] * 1e-3
     roof_fwd = {"kernel": "fft_forward_kernel<float, 6>, leaf level", "bound": "hbm",
                 "achieved": lw["fft_forward_bytes"] / fwd_s / 1e9, "peak": PEAK_HBM / 1e9,
-                "unit": "GB/s", "traffic": None,
+                "unit": "GB/s",
+                "traffic": measured_traffic("paper_2408_07436_amd/csrc/k_fft.hip",
+                                            "fft_forward_f32_uniform1M_p6_traffic.json"),
                 "per_launch": f"{lw['fft_forward_bytes'] / 1e6:.1f} MB (FP64 densities in, FP32 "
                               f"spectra out), avg {lk['fft_forward']:.4f} ms"}
     roof_inv = {"kernel": "fft_inverse_kernel<float, 6>, leaf level", "bound": "hbm",
                 "achieved": lw["fft_inverse_bytes"] / inv_s / 1e9, "peak": PEAK_HBM / 1e9,
-                "unit": "GB/s", "traffic": None,
+                "unit": "GB/s",
+                "traffic": measured_traffic("paper_2408_07436_amd/csrc/k_fft.hip",
+                                            "fft_inverse_f32_uniform1M_p6_traffic.json"),
                 "per_launch": f"{lw['fft_inverse_bytes'] / 1e6:.1f} MB (FP32 products in, FP64 "
                               f"check potentials out), avg {lk['fft_inverse']:.4f} ms"}
     for r in (roof_fwd, roof_inv):
