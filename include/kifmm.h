@@ -39,7 +39,15 @@
  *     the lattice boundary, i_x slowest; 6(p-1)^2 + 2 points (Appendix A.3).
  *     Upward-equivalent and downward-check surfaces use alpha_inner,
  *     upward-check and downward-equivalent surfaces alpha_outer.
- *   - K(x, y) = 0 when x and y are bitwise equal.
+ *   - Self term (the paper takes sources equal to targets, Section 4, and
+ *     does not say what K is at r = 0): K(x, y) = 0 for coincident points.
+ *     The kernels zero a pair when |x - y|^2, formed in the working
+ *     precision, is below that precision's smallest normal number; bitwise-
+ *     equal points always are.  Distinct points are zeroed only when their
+ *     separation is below what the working precision resolves: about
+ *     1.5e-154 in FP64, and in the FP32 near field (which forms separations
+ *     from FP64 offsets to the target leaf's centre) about 1e-16 times the
+ *     domain width.
  *   - Pseudo-inverses keep singular values > max(M,N) * 2^-52 * sigma_0 and
  *     are applied as two FP64 factors V (Sigma^-1 U^T) (Section 2.1.1).
  *   - The M2L and L2L check potentials of a box are summed before its
@@ -106,25 +114,35 @@ typedef struct {
 } kifmm_config;
 
 /* Fill *cfg with defaults: p = 6, depth = 4, FFT, FP64, tolerances 0 / -1,
- * alpha 1.05 / 2.95, origin 0, width 1, device 0. */
+ * alpha 1.05 / 2.95, origin 0, width 1, device 0.  The parameters are those
+ * of the paper's runtime tables (expansion order P, tree depth, M2L form,
+ * precision; Section 4). */
 void kifmm_config_default(kifmm_config* cfg);
 
-/* Create a handle.  Validates the config (EINVAL: order < 2, depth outside
- * 2..16, unknown m2l/prec, 0 < check_order < order; EUNSUPPORTED: BF16X3 with
- * FFT, check_order > order without BLAS-M2L).  *out receives
- * the handle, owned by the caller until kifmm_destroy. */
+/* Create a handle for one FMM configuration: the parameters of Section 4's
+ * setup (order, depth, M2L form of Section 2.2 / 3 / Appendix A, precision),
+ * nothing computed yet.  Validates the config (EINVAL: order < 2, depth
+ * outside 2..16, unknown m2l/prec, 0 < check_order < order; EUNSUPPORTED:
+ * BF16X3 with FFT, FFT with order > 8, check_order > order without
+ * BLAS-M2L).  *out receives the handle, owned by the caller until
+ * kifmm_destroy. */
 kifmm_status kifmm_create(const kifmm_config* cfg, kifmm_handle** out);
 
 /* Build the tree and all lists from host positions src[n_src][3] and
- * tgt[n_tgt][3] (row-major doubles; copied).  tgt may equal src.
- * EINVAL: null pointers, n <= 0, or a point outside the domain cube. */
+ * tgt[n_tgt][3] (row-major doubles; copied): the uniform octree with
+ * empty branches pruned, near fields and interaction lists of Section 2
+ * and the transfer-vector index of Section 3.1.  tgt may equal src.
+ * EINVAL: null pointers, n <= 0, or a point outside the domain cube.
+ * ESTATE: a batch holds the handle. */
 kifmm_status kifmm_set_points(kifmm_handle* h, const double* src, int64_t n_src,
                               const double* tgt, int64_t n_tgt);
 
 /* Compute all operators in FP64 on the host: pseudo-inverse factors, M2M
  * and L2L kernel matrices, and the M2L operators of the selected form.
- * Depends only on the configuration (Section 5.1).  Idempotent.
- * ENUMERIC: an SVD did not converge. */
+ * Depends only on the configuration (Section 5.1): pseudo-inverses of
+ * Section 2.1.1, kernel spectra of Appendix A.1 or the compressed
+ * operators of Section 3.1.  Idempotent.
+ * ENUMERIC: an SVD did not converge; ESTATE: a batch holds the handle. */
 kifmm_status kifmm_precompute(kifmm_handle* h);
 
 /* Compression of K_fat = [K_1 .. K_316] (n_s x 316 n_s) for BLAS-M2L
@@ -154,23 +172,34 @@ typedef enum { KIFMM_SVD_DETERMINISTIC = 0, KIFMM_SVD_RANDOMIZED = 1 } kifmm_svd
 kifmm_status kifmm_set_svd(kifmm_handle* h, int32_t mode, int32_t rank, int32_t oversample,
                            uint64_t seed);
 
-/* Evaluate potentials on the device, asynchronously on hip_stream (a
- * hipStream_t; NULL = default stream).  q_dev holds n_vec charge vectors,
+/* Evaluate potentials phi_i = sum_j K(x_i, y_j) q_j (Section 1) with the
+ * FMM passes of Section 2 (upward P2M / M2M, downward M2L / L2L, leaf L2P
+ * and P2P), for n_vec charge vectors through the same launches (the
+ * multiple right-hand sides of Section 3.2), asynchronously on hip_stream
+ * (a hipStream_t; NULL = default stream).  q_dev holds n_vec charge vectors,
  * column-major [n_vec][ldq] in the caller's source order; phi_dev receives
  * [n_vec][ldphi] in the caller's target order (overwritten).  Element type
  * is double for KIFMM_FP64 and float otherwise; both are device pointers
  * owned by the caller.  ldq >= n_src, ldphi >= n_tgt, n_vec >= 1.
- * ESTATE: called before set_points / precompute.  EDEVICE: HIP error. */
+ * ESTATE: called before set_points / precompute, or a batch holds the
+ * handle and this call needs more vectors than the batch's (or other knobs).
+ * EUNSUPPORTED: n_vec above a kernel limit (BLAS / dense: 128; FFT: the
+ * spectra of a level, clusters x n_vec x 128 bytes, must stay below 4 GiB),
+ * checked before anything is enqueued.  EDEVICE: HIP error. */
 kifmm_status kifmm_evaluate(kifmm_handle* h, const void* q_dev, int64_t ldq, int32_t n_vec,
                             void* phi_dev, int64_t ldphi, void* hip_stream);
 
-/* Release the handle and all device memory it owns.  NULL is accepted. */
+/* Release the handle and all device memory it owns.  NULL is accepted.
+ * ESTATE (nothing released): a batch holds the handle. */
 kifmm_status kifmm_destroy(kifmm_handle* h);
 
-/* Message of the last failed call on this thread ("" if none). */
+/* Message of the last failed call on this thread ("" if none); the
+ * library's own error report, not a passage of the paper. */
 const char* kifmm_last_error(void);
 
-/* ---- introspection (host only, valid after set_points) ---------------- */
+/* ---- introspection (host only, valid after set_points) ----------------
+ * The tree and lists of Section 2 (boxes, near fields, interaction lists)
+ * and the operators of Sections 2.1.1, 3.1 and Appendix A.1, for checks. */
 
 /* Number of boxes at a level (0..depth). */
 kifmm_status kifmm_num_boxes(const kifmm_handle* h, int32_t level, int64_t* n);
@@ -209,17 +238,23 @@ kifmm_status kifmm_operator(const kifmm_handle* h, int32_t which, double* out, i
 
 /* ---- stages and timings (device) ---------------------------------------- */
 
-/* Run one M2L level on caller device buffers, asynchronously:
+/* The M2L of one level (Section 2.2: check potentials of every target box
+ * from the multipoles of its interaction list; in the configured form,
+ * Appendix A.1 or Section 3.2) on caller device buffers, asynchronously:
  * in_dev = upward-equivalent densities [n_boxes(level)][n_vec][n_s] (double,
  * boxes in key order), out_dev = M2L check potentials
  * [n_boxes(level)][n_vec][n_c] (double, overwritten; n_c = n_s unless
  * check_order > order).  Uses the configured M2L form and precision.  stage must be
- * KIFMM_STAGE_M2L (0). */
+ * KIFMM_STAGE_M2L (0).  The buffers must hold every box of the level
+ * (kifmm_num_boxes); the call cannot check their size.  EINVAL: level
+ * outside 2..depth, null buffers; EUNSUPPORTED: as kifmm_evaluate. */
 kifmm_status kifmm_stage(kifmm_handle* h, int32_t stage, int32_t level, const void* in_dev,
                          void* out_dev, int32_t n_vec, void* hip_stream);
 
 /* Enable (1) or disable (0) timing of evaluate and stage with HIP events
- * recorded between kernels.  A timed call synchronises before it returns. */
+ * recorded between kernels (the per-phase times T_FMM, T_M2L, T_P2P the
+ * paper reports in Section 4's runtime tables).  A timed call synchronises
+ * before it returns. */
 kifmm_status kifmm_set_timing(kifmm_handle* h, int32_t on);
 /* Milliseconds of the last timed evaluate or stage (cap >= 5; more entries
  * are filled when cap allows, up to 12).  An untimed FFT-M2L evaluate runs
@@ -240,7 +275,8 @@ kifmm_status kifmm_set_timing(kifmm_handle* h, int32_t on);
  * [5..7] its three kernels, [8] = 1, the rest 0. */
 kifmm_status kifmm_timings(const kifmm_handle* h, double* ms, int32_t cap);
 
-/* Work counts of one M2L level (>= 2), valid after set_points: [0] target
+/* Work counts of one M2L level (>= 2; the M2L pairs of Section 2.2 and the
+ * sibling-cluster pairs of Appendix A.2), valid after set_points: [0] target
  * boxes, [1] M2L box pairs, [2] sibling clusters (boxes of level-1),
  * [3] (target cluster, existing source cluster) pairs over the 26-cluster
  * halos.  cap >= 4. */
@@ -248,7 +284,9 @@ kifmm_status kifmm_m2l_counts(const kifmm_handle* h, int32_t level, int64_t* cou
 
 /* ---- moving points --------------------------------------------------------- */
 
-/* Re-setup for points that move between evaluates, on the device: the new
+/* Re-setup for points that move between evaluates (the dynamic-particle
+ * setting of Section 5.1, where the tree and maps are rebuilt each step;
+ * Tables 5-6 list that setup cost), on the device: the new
  * positions src_dev[n_src][3] and tgt_dev[n_tgt][3] (device memory, FP64,
  * row-major, the counts of kifmm_set_points; tgt_dev may equal src_dev; they
  * must not be buffers the library returned) are binned into the current
@@ -259,15 +297,18 @@ kifmm_status kifmm_m2l_counts(const kifmm_handle* h, int32_t level, int64_t* cou
  * (every leaf keeps at least one point).  The buffers are read on
  * hip_stream; the call synchronises it.  ESTATE: no points or operators
  * yet, or some point falls outside every current leaf - then nothing has
- * changed and kifmm_set_points is needed.  EINVAL: null arguments. */
+ * changed and kifmm_set_points is needed; a batch holds the handle.
+ * EINVAL: null arguments. */
 kifmm_status kifmm_update_points(kifmm_handle* h, const void* src_dev, const void* tgt_dev,
                                  void* hip_stream);
 
 /* ---- autotuning ---------------------------------------------------------- */
 
 /* Knobs of the evaluate's schedule and tile shapes (int32; 0 = built-in
- * default).  No setting changes results: every one gives bit-identical
- * potentials.
+ * default).  The paper tunes its CPU kernels by hand (the batch size of
+ * Appendix A.2, the parameter search of Section 4); these knobs are this
+ * library's own launch shapes.  No setting changes results: every one
+ * gives bit-identical potentials.
  *   [KIFMM_TUNE_BLAS_TILE] BLAS / dense M2L: target boxes per tile.  A tile's
  *       MFMA columns are its boxes x n_vec, at most 128; larger values are
  *       clamped to 128 / n_vec.  0 = 128 / n_vec.  Range 0..128.
@@ -289,7 +330,8 @@ enum {
  * Host only. */
 kifmm_status kifmm_get_tuning(const kifmm_handle* h, int32_t* knobs, int32_t cap);
 /* Set the first n knobs (n <= KIFMM_TUNE_COUNT); EINVAL (nothing changed) if a
- * value is out of range.  Host only; takes effect at the next evaluate. */
+ * value is out of range; ESTATE if a batch holds the handle and a value
+ * changes.  Host only; takes effect at the next evaluate. */
 kifmm_status kifmm_set_tuning(kifmm_handle* h, const int32_t* knobs, int32_t n);
 /* Autotuner: times every candidate setting that applies to the handle's M2L
  * form and precision (FFT: schedule x Hadamard form for FP32, schedule for
@@ -299,7 +341,8 @@ kifmm_status kifmm_set_tuning(kifmm_handle* h, const int32_t* knobs, int32_t n);
  * to *best_ms (if not NULL).  phi_dev holds the last evaluate's potentials.
  * Runs untimed whatever kifmm_set_timing says; synchronises hip_stream.
  * On an error the knobs are left as they were.
- * EINVAL: bad arguments or a capturing stream; ESTATE: as evaluate. */
+ * EINVAL: bad arguments or a capturing stream; ESTATE: as evaluate, or a
+ * batch holds the handle. */
 kifmm_status kifmm_autotune(kifmm_handle* h, const void* q_dev, int64_t ldq, int32_t n_vec,
                             void* phi_dev, int64_t ldphi, void* hip_stream, int32_t reps,
                             double* best_ms);

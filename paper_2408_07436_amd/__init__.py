@@ -189,10 +189,12 @@ class KiFMM:
         if q.dim() == 1:
             q = q[None]
         assert q.is_cuda and q.dtype == self.dtype and q.stride(1) == 1
+        assert q.dim() == 2 and q.shape[1] == self.n_src, "charges must be (nvec, n_src)"
         nvec = q.shape[0]
         if out is None:
             out = torch.empty((nvec, self.n_tgt), dtype=self.dtype, device=q.device)
         assert out.is_cuda and out.dtype == self.dtype and out.stride(1) == 1
+        assert tuple(out.shape) == (nvec, self.n_tgt), "potentials must be (nvec, n_tgt)"
         s = torch.cuda.current_stream(q.device) if stream is None else stream
         _check(lib().kifmm_evaluate(self._h, q.data_ptr(), q.stride(0), nvec, out.data_ptr(),
                                     out.stride(0), ctypes.c_void_p(s.cuda_stream)))
@@ -203,7 +205,8 @@ class KiFMM:
         densities ``mult`` (n_boxes, nvec, n_equiv), FP64."""
         import torch
         assert mult.is_cuda and mult.dtype == torch.float64 and mult.is_contiguous()
-        assert mult.shape[2] == self.n_equiv
+        assert mult.dim() == 3 and mult.shape[2] == self.n_equiv
+        assert mult.shape[0] == self.num_boxes(level), "densities must cover every box of the level"
         if out is None:
             out = torch.empty((mult.shape[0], mult.shape[1], self.n_check), dtype=torch.float64,
                               device=mult.device)
@@ -305,10 +308,12 @@ class KiFMM:
         if q.dim() == 1:
             q = q[None]
         assert q.is_cuda and q.dtype == self.dtype and q.stride(1) == 1
+        assert q.dim() == 2 and q.shape[1] == self.n_src, "charges must be (nvec, n_src)"
         nvec = q.shape[0]
         if out is None:
             out = torch.empty((nvec, self.n_tgt), dtype=self.dtype, device=q.device)
         assert out.is_cuda and out.dtype == self.dtype and out.stride(1) == 1
+        assert tuple(out.shape) == (nvec, self.n_tgt), "potentials must be (nvec, n_tgt)"
         s = torch.cuda.current_stream(q.device) if stream is None else stream
         best = ctypes.c_double(0.0)
         _check(lib().kifmm_autotune(self._h, q.data_ptr(), q.stride(0), nvec, out.data_ptr(),
@@ -344,6 +349,8 @@ class Batch:
         nv = (ctypes.c_int32 * n)(*[q.shape[0] for _, q, _ in items])
         for f, q, p in items:
             assert q.is_cuda and p.is_cuda and q.dtype == f.dtype and p.dtype == f.dtype
+            assert q.dim() == 2 and q.shape[1] == f.n_src and q.stride(1) == 1
+            assert tuple(p.shape) == (q.shape[0], f.n_tgt) and p.stride(1) == 1
         s = torch.cuda.current_stream() if stream is None else stream
         b = ctypes.c_void_p()
         self.best_ms = None

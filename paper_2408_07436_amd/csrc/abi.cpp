@@ -88,6 +88,7 @@ kifmm_status kifmm_set_points(kifmm_handle* h, const double* src, int64_t n_src,
   if (!h || !src || !tgt) return fail(KIFMM_EINVAL, "null argument");
   if (n_src <= 0 || n_tgt <= 0) return fail(KIFMM_EINVAL, "point counts must be positive");
   if (n_src > INT32_MAX || n_tgt > INT32_MAX) return fail(KIFMM_EINVAL, "too many points");
+  if (h->batches > 0) return fail(KIFMM_ESTATE, "a batch holds this handle");
   if (h->dev) {
     kifmm::destroy_device(h->dev);
     h->dev = nullptr;
@@ -104,6 +105,7 @@ kifmm_status kifmm_set_points(kifmm_handle* h, const double* src, int64_t n_src,
 kifmm_status kifmm_precompute(kifmm_handle* h) {
   if (!h) return fail(KIFMM_EINVAL, "null handle");
   if (h->op.ready) return KIFMM_OK;
+  if (h->batches > 0) return fail(KIFMM_ESTATE, "a batch holds this handle");
   if (h->dev) {
     kifmm::destroy_device(h->dev);
     h->dev = nullptr;
@@ -144,6 +146,7 @@ kifmm_status kifmm_set_svd(kifmm_handle* h, int32_t mode, int32_t rank, int32_t 
     return fail(KIFMM_EINVAL, "unknown SVD mode");
   if (rank < 0 || oversample < 0) return fail(KIFMM_EINVAL, "negative rank or oversampling");
   if (h->op.ready) return fail(KIFMM_ESTATE, "the SVD is chosen before kifmm_precompute");
+  if (h->batches > 0) return fail(KIFMM_ESTATE, "a batch holds this handle");
   h->svd.mode = mode;
   h->svd.rank = rank;
   h->svd.oversample = oversample;
@@ -164,6 +167,7 @@ kifmm_status kifmm_evaluate(kifmm_handle* h, const void* q_dev, int64_t ldq, int
 
 kifmm_status kifmm_destroy(kifmm_handle* h) {
   if (!h) return KIFMM_OK;
+  if (h->batches > 0) return fail(KIFMM_ESTATE, "a batch holds this handle; destroy the batch first");
   kifmm::destroy_device(h->dev);
   delete h;
   return KIFMM_OK;
@@ -330,6 +334,7 @@ kifmm_status kifmm_update_points(kifmm_handle* h, const void* src_dev, const voi
   if (!h || !src_dev || !tgt_dev) return fail(KIFMM_EINVAL, "null argument");
   if (!h->has_points) return fail(KIFMM_ESTATE, "update_points before set_points");
   if (!h->op.ready) return fail(KIFMM_ESTATE, "update_points before precompute");
+  if (h->batches > 0) return fail(KIFMM_ESTATE, "a batch holds this handle");
   return kifmm::device_update_points(h, (const double*)src_dev, (const double*)tgt_dev,
                                      (hipStream_t)hip_stream);
 }
@@ -347,6 +352,9 @@ kifmm_status kifmm_set_tuning(kifmm_handle* h, const int32_t* knobs, int32_t n) 
   static const int32_t hi[KIFMM_TUNE_COUNT] = {128, 1, 1};
   for (int i = 0; i < n; ++i)
     if (knobs[i] < 0 || knobs[i] > hi[i]) return fail(KIFMM_EINVAL, "knob value out of range");
+  if (h->batches > 0)
+    for (int i = 0; i < n; ++i)
+      if (knobs[i] != h->tune[i]) return fail(KIFMM_ESTATE, "a batch holds this handle");
   for (int i = 0; i < n; ++i) h->tune[i] = knobs[i];
   return KIFMM_OK;
 }
@@ -361,6 +369,7 @@ kifmm_status kifmm_autotune(kifmm_handle* h, const void* q_dev, int64_t ldq, int
   if (n_vec < 1 || ldq < h->tree.n_src || ldphi < h->tree.n_tgt)
     return fail(KIFMM_EINVAL, "bad n_vec or leading dimension");
   if (reps < 1 || reps > 100) return fail(KIFMM_EINVAL, "reps out of range");
+  if (h->batches > 0) return fail(KIFMM_ESTATE, "a batch holds this handle");
   return kifmm::device_autotune(h, q_dev, ldq, n_vec, phi_dev, ldphi, (hipStream_t)hip_stream,
                                 reps, best_ms);
 }

@@ -14,6 +14,7 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
 using kifmm::fail;
 
 struct kifmm_batch {
+  std::vector<kifmm_handle*> handles;  // each holds one count in handle->batches
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;
   hipGraph_t graph = nullptr;
@@ -25,6 +26,7 @@ namespace {
 
 void release(kifmm_batch* b) {
   if (!b) return;
+  for (kifmm_handle* h : b->handles) --h->batches;
   // teardown: nothing to do about a failure here
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -125,6 +127,8 @@ kifmm_status kifmm_batch_create(kifmm_handle* const* handles, int32_t n, const v
     release(b);
     return fail(KIFMM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
   }
+  b->handles.assign(handles, handles + n);
+  for (kifmm_handle* h : b->handles) ++h->batches;
   *out = b;
   return KIFMM_OK;
 }
@@ -139,6 +143,8 @@ kifmm_status kifmm_batch_autotune(kifmm_handle* const* handles, int32_t n,
   *out = nullptr;
   for (int i = 0; i < n; ++i)
     if (!handles[i] || n_vec[i] < 1) return fail(KIFMM_EINVAL, "bad batch entry");
+  for (int i = 0; i < n; ++i)
+    if (handles[i]->batches > 0) return fail(KIFMM_ESTATE, "a batch already holds a handle");
   bool fft32 = false, tiled = false;
   for (int i = 0; i < n; ++i) {
     const kifmm_config& c = handles[i]->cfg;

@@ -533,9 +533,15 @@ kifmm_status ensure_work(kifmm_handle* h, int nvec) {
   if (h->cfg.m2l != KIFMM_M2L_FFT) {
     const int tb_max = std::max(1, 128 / nvec), knob = h->tune[KIFMM_TUNE_BLAS_TILE];
     const int TB = knob > 0 ? std::min(knob, tb_max) : tb_max;
-    if (TB != d->tile_tb) KIFMM_TRY(build_blas_tiles(h, d, TB));
+    if (TB != d->tile_tb) {
+      if (h->batches > 0)
+        return fail(KIFMM_ESTATE, "a batch holds this handle: its BLAS tiles cannot be rebuilt");
+      KIFMM_TRY(build_blas_tiles(h, d, TB));
+    }
   }
   if (nvec <= d->nvec_cap) return KIFMM_OK;
+  if (h->batches > 0)
+    return fail(KIFMM_ESTATE, "a batch holds this handle: more vectors than its buffers hold");
   for (void* p : d->work_allocs) (void)hipFree(p);
   d->work_allocs.clear();
   d->nvec_cap = 0;
@@ -707,7 +713,29 @@ void destroy_device(DeviceState* d) {
   delete d;
 }
 
+// Size limits of the kernels, checked before anything is enqueued: the fused
+// BLAS / dense kernel holds at most 128 columns (boxes x vectors) per tile;
+// the FFT-M2L kernels index clusters with 24 bits, one frequency's spectra
+// with 32-bit byte offsets and rows (cluster x vector) with 31 bits.
+kifmm_status check_limits(const kifmm_handle* h, int nvec) {
+  if (nvec < 1) return fail(KIFMM_EINVAL, "n_vec must be >= 1");
+  if (h->cfg.m2l != KIFMM_M2L_FFT) {
+    if (nvec > 128) return fail(KIFMM_EUNSUPPORTED, "BLAS / dense M2L takes at most 128 vectors per call");
+    return KIFMM_OK;
+  }
+  const int64_t cb = h->cfg.prec == KIFMM_FP64 ? 8 : 4;
+  for (int l = 2; l <= h->tree.depth; ++l) {
+    const int64_t nc = h->tree.levels[l - 1].n;
+    if (nc + 1 >= (int64_t(1) << 23) || (nc + 1) * nvec * 16 * cb >= (int64_t(1) << 32) ||
+        (nc + 1) * nvec * 8 >= (int64_t(1) << 31))
+      return fail(KIFMM_EUNSUPPORTED, "FFT-M2L level too large for this many vectors "
+                                      "(clusters x vectors x 128 bytes must stay below 4 GiB)");
+  }
+  return KIFMM_OK;
+}
+
 kifmm_status device_ready(kifmm_handle* h, int nvec) {
+  KIFMM_TRY(check_limits(h, nvec));
   if (!h->dev) {
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count == 0)
@@ -955,6 +983,7 @@ kifmm_status device_stage(kifmm_handle* h, int level, const void* in, void* out,
 // (HIP events on s); the setting with the smallest median is kept.
 kifmm_status device_autotune(kifmm_handle* h, const void* q, int64_t ldq, int nvec, void* phi,
                              int64_t ldphi, hipStream_t s, int reps, double* best_ms) {
+  KIFMM_TRY(check_limits(h, nvec));
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   KIFMM_HIP(hipStreamIsCapturing(s, &cap));
   if (cap != hipStreamCaptureStatusNone) return fail(KIFMM_EINVAL, "autotune on a capturing stream");

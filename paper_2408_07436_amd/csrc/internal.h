@@ -147,4 +147,7 @@ struct kifmm_handle {
   int32_t tune[KIFMM_TUNE_COUNT] = {0, 0, 0};  // autotuning knobs (kifmm.h)
   bool points_on_device = false;  // host copies of the point order are stale
   kifmm::SvdOptions svd;          // K_fat compression (BLAS-M2L)
+  // batches alive that hold this handle: their launches read the handle's
+  // device buffers by address, so nothing may free or rebuild them meanwhile
+  int32_t batches = 0;
 };

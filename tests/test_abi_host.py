@@ -224,3 +224,34 @@ def test_check_order_validation():
         with pytest.raises(K.KifmmError) as e:
             K.KiFMM(4, 3, m2l=m2l, check_order=5)
         assert e.value.code == 5
+
+
+def test_vector_limits_refused_before_device_use():
+    """Vector counts beyond a kernel's limit are refused with EUNSUPPORTED before
+    anything is enqueued (no device is touched here)."""
+    lib = K.lib()
+    one = ctypes.c_void_p(1)
+    f = K.KiFMM(4, 3, m2l="blas", prec="fp32", svd_rel_tol=1e-6, svd_rel_tol_dir=1e-6)
+    f.set_points(workloads.uniform_cube(500, 62)).precompute()
+    assert lib.kifmm_evaluate(f._h, one, 500, 129, one, 500, None) == 5
+    assert b"128" in lib.kifmm_last_error()
+    assert lib.kifmm_stage(f._h, 0, 3, one, one, 129, None) == 5
+    best = ctypes.c_double(0.0)
+    assert lib.kifmm_autotune(f._h, one, 500, 129, one, 500, None, 2, ctypes.byref(best)) == 5
+    # FFT: a level's spectra (clusters x vectors x 128 bytes in FP32) stay below 4 GiB
+    g = K.KiFMM(4, 3, m2l="fft", prec="fp32").set_points(workloads.uniform_cube(500, 63)).precompute()
+    nvec = (1 << 26) // (g.num_boxes(2) + 1) + 1
+    assert lib.kifmm_evaluate(g._h, one, 500, nvec, one, 500, None) == 5
+    assert b"4 GiB" in lib.kifmm_last_error()
+
+
+def test_binding_checks_shapes_before_calls():
+    """The binding refuses tensors whose shapes do not cover the problem (the C
+    entry points take raw pointers and cannot see sizes)."""
+    torch = pytest.importorskip("torch")
+    f = K.KiFMM(4, 3, m2l="fft", prec="fp64").set_points(workloads.uniform_cube(500, 64)).precompute()
+    nb = f.num_boxes(3)
+    with pytest.raises(AssertionError):
+        f.stage_m2l(3, torch.zeros((nb - 1, 1, f.n_equiv), dtype=torch.float64))
+    with pytest.raises(AssertionError):
+        f.evaluate(torch.zeros((1, 499), dtype=torch.float64))

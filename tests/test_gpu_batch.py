@@ -7,7 +7,7 @@ import pytest
 import workloads
 from oracle import fmm, kernel
 
-from gpu_util import say
+from gpu_util import E2E_GATES, check_parity, say
 
 K = pytest.importorskip("paper_2408_07436_amd")
 torch = pytest.importorskip("torch")
@@ -63,12 +63,13 @@ def test_batch_graph_replays_match_eager():
     for i, (_, _, phi) in enumerate(items):
         assert torch.equal(phi, 2.0 * eager[i]), f"scaled charges problem {i}"
     b.close()
-    # one problem against the oracle
-    pts, q = hosts[2]
-    ref = fmm.KiFMM(pts, pts, 4, 6).evaluate(q)
-    e = kernel.rel_l2(eager[2].cpu().numpy().astype(np.float64), ref)
-    say(f"  problem 2 rel err vs oracle {e:.3e}")
-    assert e <= 1e-5
+    # every problem against the oracle (the replays equal the eager results)
+    for i, (n, depth, p, m2l, prec, nvec) in enumerate(PROBLEMS):
+        pts, q = hosts[i]
+        kw = dict(m2l="blas", svd_rel_tol=1e-6, svd_rel_tol_dir=1e-6) if m2l == "blas" else {}
+        ref = fmm.KiFMM(pts, pts, depth, p, **kw).evaluate(q)
+        check_parity(eager[i].cpu().numpy().astype(np.float64), ref, E2E_GATES[prec],
+                     what=f"problem {i} ({m2l} {prec}) vs oracle")
 
 
 def test_batch_rejects_repeated_handle():

@@ -10,7 +10,7 @@ import pytest
 import workloads
 from oracle import fmm, kernel
 
-from gpu_util import evaluate, say
+from gpu_util import E2E_GATES, check_parity, evaluate, say
 
 K = pytest.importorskip("paper_2408_07436_amd")
 torch = pytest.importorskip("torch")
@@ -24,56 +24,49 @@ DIRECT_GATE = 1e-5
 @pytest.fixture(scope="module")
 def sphere4m():
     w = workloads.config(4)
-    s = workloads.sample_indices(w.n, 16, workloads.SEED_SAMPLES + 4)
+    s = workloads.sample_indices(w.n, 64, workloads.SEED_SAMPLES + 4)
     return w, s
 
 
 def test_sphere_4M_64rhs_fft_sampled(sphere4m):
     w, s = sphere4m
-    say(f"case: {w.name} fft fp32/fp64, 64 vectors at 16 sampled targets")
+    say(f"case: {w.name} fft fp32/fp64, 64 vectors at 64 sampled targets")
     ref = fmm.KiFMM(w.points, w.points, w.depth, w.order, origin=w.origin,
                     width=w.width).evaluate(w.q, s)
     res = {}
     for prec, gate in (("fp32", FP32_GATE), ("fp64", FP64_GATE)):
         got, _ = evaluate(K, w.points, w.q, w.depth, w.order, "fft", prec, origin=w.origin,
                           width=w.width)
-        e = kernel.rel_l2(got[:, s], ref)
-        say(f"  fft {prec} rel err vs oracle {e:.3e}")
-        assert e <= gate
+        check_parity(got[:, s], ref, E2E_GATES[prec], what=f"fft {prec} vs oracle")
         assert np.all(np.isfinite(got))
         res[prec] = got
-    e = kernel.rel_l2(res["fp32"], res["fp64"])
-    say(f"  fft mixed vs fp64 (every target and vector) {e:.3e}")
-    assert e <= FP32_GATE
+    check_parity(res["fp32"], res["fp64"], E2E_GATES["fp32"],
+                 what="fft mixed vs fp64 (every target and vector)")
 
 
 def test_sphere_4M_64rhs_blas_sampled(sphere4m):
     w, s = sphere4m
-    say(f"case: {w.name} blas tol 1e-6/1e-6 fp32/fp64, 64 vectors at 16 sampled targets")
+    say(f"case: {w.name} blas tol 1e-6/1e-6 fp32/fp64, 64 vectors at 64 sampled targets")
     ref = fmm.KiFMM(w.points, w.points, w.depth, w.order, origin=w.origin, width=w.width,
                     m2l="blas", svd_rel_tol=1e-6, svd_rel_tol_dir=1e-6).evaluate(w.q, s)
     for prec, gate in (("fp32", FP32_GATE), ("fp64", FP64_GATE)):
         got, _ = evaluate(K, w.points, w.q, w.depth, w.order, "blas", prec, origin=w.origin,
                           width=w.width, tol=1e-6, tol_dir=1e-6)
-        e = kernel.rel_l2(got[:, s], ref)
-        say(f"  blas {prec} rel err vs oracle (projected operator) {e:.3e}")
-        assert e <= gate
+        check_parity(got[:, s], ref, E2E_GATES[prec], what=f"blas {prec} vs oracle (projected operator)")
         assert np.all(np.isfinite(got))
 
 
 def test_uniform_8M_fft_vs_direct_sampled():
     w = workloads.config(6)
-    s = workloads.sample_indices(w.n, 32, workloads.SEED_SAMPLES + 6)
-    say(f"case: {w.name} fft fp32/fp64 vs the direct sum at 32 sampled targets")
-    ref = kernel.direct(w.points, w.q, w.points[s])
+    s = workloads.sample_indices(w.n, 100, workloads.SEED_SAMPLES + 6)
+    say(f"case: {w.name} fft fp32/fp64 vs the direct sum at 100 sampled targets")
+    # 16 targets at a time keep the (targets x sources x 3) differences near 3 GB
+    ref = np.concatenate([kernel.direct(w.points, w.q, w.points[s[i:i + 16]])
+                          for i in range(0, len(s), 16)], axis=1)
     res = {}
     for prec in ("fp32", "fp64"):
         got, _ = evaluate(K, w.points, w.q, w.depth, w.order, "fft", prec)
-        e = kernel.rel_l2(got[:, s], ref)
-        say(f"  fft {prec} rel err vs direct {e:.3e}")
-        assert e <= DIRECT_GATE
+        check_parity(got[:, s], ref, (DIRECT_GATE, DIRECT_GATE), what=f"fft {prec} vs direct")
         assert np.all(np.isfinite(got))
         res[prec] = got
-    e = kernel.rel_l2(res["fp32"], res["fp64"])
-    say(f"  fft mixed vs fp64 (every target) {e:.3e}")
-    assert e <= FP32_GATE
+    check_parity(res["fp32"], res["fp64"], E2E_GATES["fp32"], what="fft mixed vs fp64 (every target)")
