@@ -14,7 +14,12 @@ the same path in FP64 is timed beside it.  The JSON line also carries the
 roofline of the dominant kernel, measured live with HIP events (the leaf
 level's M2L kernels on their own through single-level stage calls, since the
 levels of an evaluate overlap), and the FP64 CPU oracle timed on a bounded
-sample.
+sample.  Further sections (each can be switched off): the plain kiFMM
+workload (20k points, dense M2L, FP64), moving points, BLAS-M2L with a finer
+check surface, BLAS-M2L with 32 vectors in FP64 / FP32 / BF16x3 beside FP64
+with one vector per launch, the 4M-point sphere with 64 vectors (FFT- and
+BLAS-M2L, mixed against FP64), the batched serving workload and the 8M-point
+uniform cube; errors against the FP64 direct sum at sampled targets.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -157,23 +162,39 @@ def run_precision(K, torch, w, prec, steps, warmup):
     return f, out, ms_step, tm, setup_s
 
 
-def direct_error(torch, w, phi, n_sample=1000):
-    """Relative L2 error against the FP64 direct sum at sampled targets."""
-    import workloads
-    s = workloads.sample_indices(w.n, n_sample, workloads.SEED_SAMPLES + 2)
+def direct_potentials(torch, w, sample):
+    """FP64 direct sum (Section 1's N-body sum, K = 0 for coincident points) of every
+    charge vector at the sampled targets: (nvec, len(sample)) on the device."""
     src = torch.as_tensor(w.points, device="cuda")
-    q = torch.as_tensor(w.q[0], device="cuda")
-    tgt = src[torch.as_tensor(s, device="cuda")]
-    ref = torch.zeros(len(s), dtype=torch.float64, device="cuda")
+    q = torch.as_tensor(np.ascontiguousarray(w.q.T), device="cuda")      # (n, nvec)
+    tgt = src[torch.as_tensor(sample, device="cuda")]
+    ref = torch.zeros((len(sample), w.nvec), dtype=torch.float64, device="cuda")
     for c in range(0, w.n, 65536):
         diff = tgt[:, None, :] - src[None, c:c + 65536, :]
         r2 = (diff * diff).sum(-1)
         inv = torch.where(r2 > 0, torch.rsqrt(torch.where(r2 > 0, r2, torch.ones_like(r2))),
                           torch.zeros_like(r2))
         ref += inv @ q[c:c + 65536]
-    ref /= 4 * np.pi
-    got = phi[0, torch.as_tensor(s, device="cuda")].double()
-    return float(torch.linalg.norm(got - ref) / torch.linalg.norm(ref))
+    return (ref / (4 * np.pi)).T.contiguous()
+
+
+def direct_errors(torch, w, phi, ref, sample):
+    """Relative L2 errors against the FP64 direct sum at the sampled targets: the
+    largest over the charge vectors and the Frobenius value over all of them."""
+    got = phi[:, torch.as_tensor(sample, device="cuda")].double()
+    per = torch.linalg.norm(got - ref, dim=1) / torch.linalg.norm(ref, dim=1)
+    return {"max_over_vectors": float(per.max()),
+            "frobenius": float(torch.linalg.norm(got - ref) / torch.linalg.norm(ref))}
+
+
+def direct_error(torch, w, phi, n_sample=1000):
+    """Relative L2 error of the first charge vector against the FP64 direct sum at
+    sampled targets."""
+    import workloads
+    s = workloads.sample_indices(w.n, n_sample, workloads.SEED_SAMPLES + 2)
+    w1 = workloads.Workload(w.name, w.points, w.q[:1], w.depth, w.order, w.origin, w.width, w.m2l)
+    ref = direct_potentials(torch, w1, s)
+    return direct_errors(torch, w1, phi[:1], ref, s)["frobenius"]
 
 
 def run_blas(K, torch, steps, warmup):
@@ -183,6 +204,8 @@ def run_blas(K, torch, steps, warmup):
     out = {"workload": w.name, "n_vec": w.nvec, "svd_rel_tol": 1e-6, "svd_rel_tol_dir": 1e-6}
     ref_phi = None
     flops = None
+    sample = workloads.sample_indices(w.n, 1000, workloads.SEED_SAMPLES + 3)
+    ref_direct = direct_potentials(torch, w, sample)
     for prec in ("fp64", "fp32", "bf16x3"):
         dt = torch.float64 if prec == "fp64" else torch.float32
         t0 = time.perf_counter()
@@ -225,19 +248,29 @@ def run_blas(K, torch, steps, warmup):
         if ref_phi is None:
             ref_phi = phi.double().clone()
         rel = float(torch.linalg.norm(phi.double() - ref_phi) / torch.linalg.norm(ref_phi))
+        derr = direct_errors(torch, w, phi, ref_direct, sample)
         main_s = tm["m2l_main"] * 1e-3
         peak = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2500e12 / 3}[prec]
         out[prec] = {"m2l_ms": round(tm["m2l"], 3), "m2l_ms_per_vector": round(tm["m2l"] / w.nvec, 4),
                      "fused_kernel_ms": round(tm["m2l_main"], 3), "ms_per_step": round(ms_step, 3),
                      "fused_tflops": round(flops / main_s / 1e12, 2),
                      "fused_frac_of_peak": round(flops / main_s / peak, 4),
-                     "rel_err_vs_fp64_run": rel, "setup_s": round(setup_s, 2),
+                     "rel_err_vs_fp64_run": rel, "rel_err_vs_direct": derr,
+                     "setup_s": round(setup_s, 2),
                      "precompute_s": round(precompute_s, 3),
                      "autotuned_tile_boxes": tuning["blas_tile"],
                      "autotune_best_ms": round(tune_ms, 3)}
         log(f"  blas {prec}: step {ms_step:.2f} ms, m2l {tm['m2l']:.2f} ms (fused {tm['m2l_main']:.2f}), "
-            f"{flops / main_s / 1e12:.1f} TFLOP/s, rel vs fp64 {rel:.2e}, autotuned tile "
-            f"{tuning['blas_tile']} boxes")
+            f"{flops / main_s / 1e12:.1f} TFLOP/s, rel vs fp64 {rel:.2e}, vs direct "
+            f"{derr['max_over_vectors']:.2e} (max over vectors), autotuned tile {tuning['blas_tile']} boxes")
+        if prec == "fp64":
+            # the plain FP64 comparator: the same M2L form, one charge vector per launch
+            q1 = q[:1].contiguous()
+            phi1 = torch.empty((1, w.n), dtype=dt, device="cuda")
+            f.autotune(q1, phi1, reps=2)
+            out["fp64_one_rhs_per_launch"] = one_rhs_m2l(torch, f, q1, phi1, steps)
+            out["fp64_one_rhs_per_launch"]["autotuned_tile_boxes"] = f.tuning()["blas_tile"]
+            log(f"  blas fp64, one vector per launch: m2l {out['fp64_one_rhs_per_launch']['m2l_ms']:.3f} ms")
         del f, q, phi
         torch.cuda.empty_cache()
     # K_fat compressed by the one-shot randomized SVD on the device (rank k + 4,
@@ -263,7 +296,24 @@ def run_blas(K, torch, steps, warmup):
     torch.cuda.empty_cache()
     out["algorithmic_gflop"] = round(flops / 1e9, 1)
     out["peaks_tflops"] = {"fp64": 78.6, "fp32": 157.3, "bf16x3": round(2500 / 3, 1)}
+    one = out["fp64_one_rhs_per_launch"]["m2l_ms"]
+    out["m2l_per_vector_speedup_vs_fp64_one_rhs"] = {
+        p: round(one / out[p]["m2l_ms_per_vector"], 2) for p in ("fp64", "fp32", "bf16x3")}
+    out["error_targets"] = len(sample)
     return out
+
+
+def one_rhs_m2l(torch, f, q1, phi1, steps):
+    """M2L time of evaluates with one charge vector (timed evaluates, HIP events)."""
+    f.evaluate(q1, phi1)
+    f.set_timing(True)
+    m2l = 0.0
+    for _ in range(steps):
+        f.evaluate(q1, phi1)
+        m2l += f.timings()["m2l"]
+    f.set_timing(False)
+    torch.cuda.synchronize()
+    return {"m2l_ms": round(m2l / steps, 4)}
 
 
 def run_check_order(K, torch, w, steps):
@@ -317,6 +367,100 @@ def run_scale(K, torch, steps, warmup):
         torch.cuda.empty_cache()
     out["m2l_speedup_mixed_vs_fp64"] = round(out["fp64"]["m2l_ms"] / out["fp32"]["m2l_ms"], 3)
     out["error_targets"] = 1000
+    return out
+
+
+def timed_run(torch, f, q, phi, steps, warmup):
+    """Wall time per evaluate (synchronised) and the event-timed phases."""
+    for _ in range(warmup):
+        f.evaluate(q, phi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f.evaluate(q, phi)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) / steps * 1e3
+    f.set_timing(True)
+    acc = {}
+    for _ in range(steps):
+        f.evaluate(q, phi)
+        for kk, v in f.timings().items():
+            acc[kk] = acc.get(kk, 0.0) + v
+    f.set_timing(False)
+    torch.cuda.synchronize()
+    return ms_step, {kk: v / steps for kk, v in acc.items()}
+
+
+def run_sphere(K, torch, steps, warmup):
+    """The non-uniform workload: 4,000,000 points on the unit sphere (domain [-1,1]^3,
+    depth 6, empty boxes pruned), p = 6, 64 standard-normal charge vectors.  FFT-M2L in
+    FP32 complex and FP64, BLAS-M2L (SVD tolerance 1e-6 / 1e-6) in FP32, BF16x3 and FP64,
+    all 64 vectors through each launch, beside the plain FP64 form with one vector per
+    launch; errors of every vector against the FP64 direct sum at 1,000 sampled targets."""
+    import workloads
+    w = workloads.config(4)
+    sample = workloads.sample_indices(w.n, 1000, workloads.SEED_SAMPLES + 4)
+    ref = direct_potentials(torch, w, sample)
+    out = {"workload": w.name, "n_points": w.n, "depth": w.depth, "order": w.order, "n_vec": w.nvec,
+           "error_targets": len(sample)}
+    for m2l, precs in (("fft", ("fp32", "fp64")), ("blas", ("fp32", "bf16x3", "fp64"))):
+        for prec in precs:
+            dt = torch.float64 if prec == "fp64" else torch.float32
+            kw = dict(svd_rel_tol=1e-6, svd_rel_tol_dir=1e-6) if m2l == "blas" else {}
+            t0 = time.perf_counter()
+            f = K.KiFMM(w.order, w.depth, m2l=m2l, prec=prec, origin=w.origin, width=w.width,
+                        **kw).set_points(w.points).precompute()
+            setup_s = time.perf_counter() - t0
+            q = torch.as_tensor(w.q, dtype=dt, device="cuda")
+            phi = torch.empty((w.nvec, w.n), dtype=dt, device="cuda")
+            if m2l == "blas":
+                f.autotune(q, phi, reps=2)
+            ms_step, tm = timed_run(torch, f, q, phi, steps, warmup)
+            derr = direct_errors(torch, w, phi, ref, sample)
+            key = f"{m2l}_{prec}"
+            out[key] = {"ms_per_step": round(ms_step, 3), "m2l_ms": round(tm["m2l"], 3),
+                        "m2l_ms_per_vector": round(tm["m2l"] / w.nvec, 4),
+                        "m2l_main_kernel_ms": round(tm["m2l_main"], 3),
+                        "setup_s": round(setup_s, 2), "rel_err_vs_direct": derr}
+            log(f"  sphere {key}: step {ms_step:.2f} ms, m2l {tm['m2l']:.3f} ms "
+                f"({tm['m2l'] / w.nvec:.4f} per vector), err vs direct {derr['max_over_vectors']:.2e}")
+            if prec == "fp64":
+                q1 = q[:1].contiguous()
+                phi1 = torch.empty((1, w.n), dtype=dt, device="cuda")
+                if m2l == "blas":
+                    f.autotune(q1, phi1, reps=2)
+                one = one_rhs_m2l(torch, f, q1, phi1, steps)
+                out[f"{m2l}_fp64_one_rhs_per_launch"] = one
+                log(f"  sphere {m2l} fp64, one vector per launch: m2l {one['m2l_ms']:.3f} ms")
+                del q1, phi1
+            f.close()
+            del f, q, phi
+            torch.cuda.empty_cache()
+    for m2l, mixed in (("fft", ("fp32",)), ("blas", ("fp32", "bf16x3"))):
+        one = out[f"{m2l}_fp64_one_rhs_per_launch"]["m2l_ms"]
+        for prec in mixed + ("fp64",):
+            out[f"{m2l}_{prec}"]["m2l_per_vector_speedup_vs_fp64_one_rhs"] = round(
+                one / out[f"{m2l}_{prec}"]["m2l_ms_per_vector"], 2)
+    return out
+
+
+def run_plain(K, torch, steps, warmup):
+    """The plain kiFMM workload: 20,000 uniform points, depth 3, p = 3, dense M2L in
+    FP64, one vector; error against the FP64 direct sum at every target."""
+    import workloads
+    w = workloads.config(1)
+    f = K.KiFMM(w.order, w.depth, m2l="dense", prec="fp64").set_points(w.points).precompute()
+    q = torch.as_tensor(w.q, device="cuda")
+    phi = torch.empty((w.nvec, w.n), dtype=torch.float64, device="cuda")
+    ms_step, tm = timed_run(torch, f, q, phi, steps, warmup)
+    sample = np.arange(w.n)
+    derr = direct_errors(torch, w, phi, direct_potentials(torch, w, sample), sample)
+    out = {"workload": w.name, "ms_per_step": round(ms_step, 4), "m2l_ms": round(tm["m2l"], 4),
+           "upward_ms": round(tm["upward"], 4), "downward_ms": round(tm["downward"], 4),
+           "leaves_ms": round(tm["leaves"], 4), "rel_err_vs_direct_all_targets": derr["frobenius"]}
+    log(f"  plain kiFMM 20k: step {ms_step:.3f} ms, m2l {tm['m2l']:.4f} ms, err vs direct "
+        f"{derr['frobenius']:.2e}")
+    f.close()
     return out
 
 
@@ -459,6 +603,8 @@ def main():
     ap.add_argument("--no-scale", action="store_true")
     ap.add_argument("--no-resetup", action="store_true")
     ap.add_argument("--no-check-order", action="store_true")
+    ap.add_argument("--no-sphere", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the FMM here is a single-GPU build; "
@@ -605,6 +751,9 @@ def main():
                          "(8 cores); 240 ms on AMD 3790X at depth 4 (32 cores) - CPU context only",
         "setup_s": {"fp32": round(mix["setup_s"], 2), "fp64": round(ref["setup_s"], 2)},
     }
+    if not args.no_plain:
+        log("plain kiFMM workload: 20k points, dense M2L, fp64")
+        line["plain_20k"] = run_plain(K, torch, args.steps, args.warmup)
     if not args.no_resetup:
         log("moving points: host tree build vs device re-setup")
         line["resetup_1M"] = run_resetup(K, torch, w)
@@ -614,6 +763,11 @@ def main():
     if not args.no_blas:
         log("blas-m2l workload: 32 vectors, fp64 / fp32 / bf16x3")
         line["blas_32rhs"] = run_blas(K, torch, max(1, min(args.steps, 3)), 1)
+    if not args.no_sphere:
+        # after the BLAS section: operators are cached per configuration, and the
+        # BLAS section times its precompute uncached
+        log("sphere workload: 4M points, depth 6, p = 6, 64 vectors")
+        line["sphere_4M"] = run_sphere(K, torch, max(1, min(args.steps, 3)), 1)
     if not args.no_batch:
         log("batched serving workload: 128 problems, one graph launch")
         line["batch_128"] = run_batch(K, torch, 200)
