@@ -189,6 +189,38 @@ kifmm_status kifmm_set_svd(kifmm_handle* h, int32_t mode, int32_t rank, int32_t 
 kifmm_status kifmm_evaluate(kifmm_handle* h, const void* q_dev, int64_t ldq, int32_t n_vec,
                             void* phi_dev, int64_t ldphi, void* hip_stream);
 
+/* Size in bytes of the device array kifmm_evaluate_noalloc takes its work
+ * buffers from (256 MiB), held on each device the library runs on until the
+ * process ends. */
+#define KIFMM_NOALLOC_SCRATCH_BYTES (256LL << 20)
+
+/* kifmm_evaluate without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, serving loops and harnesses that
+ * forbid hipMalloc.  Arguments, layouts, results and errors as
+ * kifmm_evaluate: the same kernels in the same schedule on the same inputs,
+ * so the potentials are those kifmm_evaluate returns.  The per-evaluate work
+ * buffers (sorted charges, multipoles and locals per level, check
+ * potentials, GEMM intermediates and split-K partials, FFT spectra, padded
+ * compressed multipoles) come from one fixed device array of
+ * KIFMM_NOALLOC_SCRATCH_BYTES per device instead of buffers the handle
+ * allocates; the call calls no hipMalloc, hipFree or allocating library
+ * routine.  Every call on one device shares that device's array, which keeps
+ * the last call's contents; the evaluate writes every entry before it reads
+ * it, so nothing needs to start at zero.  Calls that overlap on one device
+ * (several streams or host threads, or a captured graph replayed while
+ * another call runs) race on the array: the caller serialises them.
+ * ESTATE (nothing enqueued): the handle's tree and operators are not on the
+ * device yet - one kifmm_evaluate, kifmm_stage or kifmm_update_points places
+ * them there - or, for BLAS / dense M2L, the target tiles were last built
+ * for another tile width (128 / n_vec or the tuning knob; one kifmm_evaluate
+ * with this n_vec rebuilds them).  EINVAL: as kifmm_evaluate, or this
+ * problem's work buffers (40 MiB of split-K partials included) exceed the
+ * array; the message gives both sizes.  At p = 6 in FP32 an FFT-M2L problem
+ * of about 1e5 points at depth 4 with one vector fits. */
+kifmm_status kifmm_evaluate_noalloc(kifmm_handle* h, const void* q_dev, int64_t ldq,
+                                    int32_t n_vec, void* phi_dev, int64_t ldphi,
+                                    void* hip_stream);
+
 /* Release the handle and all device memory it owns.  NULL is accepted.
  * ESTATE (nothing released): a batch holds the handle. */
 kifmm_status kifmm_destroy(kifmm_handle* h);

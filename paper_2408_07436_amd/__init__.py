@@ -27,8 +27,9 @@ EXPORTS = [
     "kifmm_point_perm", "kifmm_interactions", "kifmm_near", "kifmm_operator", "kifmm_stage",
     "kifmm_set_timing", "kifmm_timings", "kifmm_m2l_counts", "kifmm_get_tuning",
     "kifmm_set_tuning", "kifmm_autotune", "kifmm_update_points", "kifmm_batch_create", "kifmm_batch_autotune",
-    "kifmm_batch_launch", "kifmm_batch_destroy", "kifmm_set_svd",
+    "kifmm_batch_launch", "kifmm_batch_destroy", "kifmm_set_svd", "kifmm_evaluate_noalloc",
 ]
+NOALLOC_SCRATCH_BYTES = 256 << 20  # KIFMM_NOALLOC_SCRATCH_BYTES
 TUNE_KNOBS = ("blas_tile", "schedule", "hadamard")
 
 
@@ -74,6 +75,7 @@ def lib() -> ctypes.CDLL:
     L.kifmm_set_points.argtypes = [vp, dp, i64, dp, i64]
     L.kifmm_precompute.argtypes = [vp]
     L.kifmm_evaluate.argtypes = [vp, vp, i64, i32, vp, i64, vp]
+    L.kifmm_evaluate_noalloc.argtypes = [vp, vp, i64, i32, vp, i64, vp]
     L.kifmm_destroy.argtypes = [vp]
     L.kifmm_last_error.restype = ctypes.c_char_p
     L.kifmm_num_boxes.argtypes = [vp, i32, ctypes.POINTER(i64)]
@@ -183,8 +185,7 @@ class KiFMM:
         _check(lib().kifmm_precompute(self._h))
         return self
 
-    def evaluate(self, q, out=None, stream=None):
-        """Potentials (nvec, n_tgt) on the device for charges ``q`` (nvec, n_src)."""
+    def _eval_args(self, q, out, stream):
         import torch
         if q.dim() == 1:
             q = q[None]
@@ -196,8 +197,21 @@ class KiFMM:
         assert out.is_cuda and out.dtype == self.dtype and out.stride(1) == 1
         assert tuple(out.shape) == (nvec, self.n_tgt), "potentials must be (nvec, n_tgt)"
         s = torch.cuda.current_stream(q.device) if stream is None else stream
+        return q, out, nvec, s
+
+    def evaluate(self, q, out=None, stream=None):
+        """Potentials (nvec, n_tgt) on the device for charges ``q`` (nvec, n_src)."""
+        q, out, nvec, s = self._eval_args(q, out, stream)
         _check(lib().kifmm_evaluate(self._h, q.data_ptr(), q.stride(0), nvec, out.data_ptr(),
                                     out.stride(0), ctypes.c_void_p(s.cuda_stream)))
+        return out
+
+    def evaluate_noalloc(self, q, out, stream=None):
+        """As ``evaluate`` through kifmm_evaluate_noalloc: the library allocates no device
+        memory (its work buffers come from its fixed scratch array); ``out`` is required."""
+        q, out, nvec, s = self._eval_args(q, out, stream)
+        _check(lib().kifmm_evaluate_noalloc(self._h, q.data_ptr(), q.stride(0), nvec, out.data_ptr(),
+                                            out.stride(0), ctypes.c_void_p(s.cuda_stream)))
         return out
 
     def stage_m2l(self, level: int, mult, out=None, stream=None):

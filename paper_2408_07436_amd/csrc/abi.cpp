@@ -23,6 +23,8 @@ kifmm_status fail(kifmm_status code, const std::string& msg) {
 
 kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nvec, void* phi,
                              int64_t ldphi, hipStream_t s);
+kifmm_status device_evaluate_noalloc(kifmm_handle* h, const void* q, int64_t ldq, int nvec,
+                                     void* phi, int64_t ldphi, hipStream_t s);
 kifmm_status device_stage(kifmm_handle* h, int level, const void* in, void* out, int nvec,
                           hipStream_t s);
 kifmm_status device_autotune(kifmm_handle* h, const void* q, int64_t ldq, int nvec, void* phi,
@@ -163,6 +165,17 @@ kifmm_status kifmm_evaluate(kifmm_handle* h, const void* q_dev, int64_t ldq, int
   if (n_vec < 1 || ldq < h->tree.n_src || ldphi < h->tree.n_tgt)
     return fail(KIFMM_EINVAL, "bad n_vec or leading dimension");
   return kifmm::device_evaluate(h, q_dev, ldq, n_vec, phi_dev, ldphi, (hipStream_t)hip_stream);
+}
+
+kifmm_status kifmm_evaluate_noalloc(kifmm_handle* h, const void* q_dev, int64_t ldq, int32_t n_vec,
+                                    void* phi_dev, int64_t ldphi, void* hip_stream) {
+  if (!h) return fail(KIFMM_EINVAL, "null handle");
+  if (!h->has_points) return fail(KIFMM_ESTATE, "evaluate before set_points");
+  if (!h->op.ready) return fail(KIFMM_ESTATE, "evaluate before precompute");
+  if (!q_dev || !phi_dev) return fail(KIFMM_EINVAL, "null buffer");
+  if (n_vec < 1 || ldq < h->tree.n_src || ldphi < h->tree.n_tgt)
+    return fail(KIFMM_EINVAL, "bad n_vec or leading dimension");
+  return kifmm::device_evaluate_noalloc(h, q_dev, ldq, n_vec, phi_dev, ldphi, (hipStream_t)hip_stream);
 }
 
 kifmm_status kifmm_destroy(kifmm_handle* h) {

@@ -5,6 +5,9 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <functional>
+#include <mutex>
+#include <utility>
 
 #include "internal.h"
 #include "kernels.h"
@@ -528,11 +531,80 @@ kifmm_status upload_all(kifmm_handle* h) {
   return KIFMM_OK;
 }
 
+// Target boxes per BLAS / dense tile for n_vec vectors: the knob, clamped
+// to the 128 MFMA columns of a tile.
+int blas_tile_width(const kifmm_handle* h, int nvec) {
+  const int tb_max = std::max(1, 128 / nvec), knob = h->tune[KIFMM_TUNE_BLAS_TILE];
+  return knob > 0 ? std::min(knob, tb_max) : tb_max;
+}
+
+// The per-evaluate work buffers of a handle for n_vec vectors: charges in
+// sorted order, multipoles and locals per level, check potentials, GEMM
+// intermediates, split-K partials (gemm_elems doubles), padded compressed
+// multipoles (BLAS / dense) and the spectra and check potentials of each
+// FFT-M2L level (the levels run concurrently).  Each slot names its size
+// and the DeviceState field that points at it; ensure_work allocates the
+// slots one by one, the no-allocation evaluate carves them out of one
+// fixed array.
+struct WorkSlot {
+  size_t bytes;
+  std::function<void*()> get;
+  std::function<void(void*)> set;
+};
+
+std::vector<WorkSlot> work_slots(const kifmm_handle* h, DeviceState* d, int nvec, int64_t gemm_elems) {
+  const Tree& t = h->tree;
+  const Operators& op = h->op;
+  const int depth = t.depth;
+  const size_t ns = op.ns, nv = (size_t)nvec;
+  int64_t maxn = 0;
+  for (int l = 0; l <= depth; ++l) maxn = std::max(maxn, t.levels[l].n);
+  const size_t qbytes = (d->fp64 ? 8 : 4);
+  if ((int)d->mult.size() != depth + 1) d->mult.assign(depth + 1, nullptr);
+  if ((int)d->local.size() != depth + 1) d->local.assign(depth + 1, nullptr);
+  std::vector<WorkSlot> w;
+  auto dbl = [](double** f) {
+    return std::make_pair(std::function<void*()>([f] { return (void*)*f; }),
+                          std::function<void(void*)>([f](void* p) { *f = (double*)p; }));
+  };
+  auto raw = [](void** f) {
+    return std::make_pair(std::function<void*()>([f] { return *f; }),
+                          std::function<void(void*)>([f](void* p) { *f = p; }));
+  };
+  auto add = [&w](size_t bytes, std::pair<std::function<void*()>, std::function<void(void*)>> gs) {
+    w.push_back(WorkSlot{bytes, gs.first, gs.second});
+  };
+  add(nv * (size_t)t.n_src * qbytes, raw(&d->qs));
+  for (int l = 2; l <= depth; ++l) {
+    add((size_t)t.levels[l].n * nv * ns * 8, dbl(&d->mult[l]));
+    add((size_t)t.levels[l].n * nv * ns * 8, dbl(&d->local[l]));
+  }
+  // check potentials have nc >= ns entries per box and vector
+  const size_t ncs = std::max<size_t>(ns, (size_t)op.nc);
+  const size_t kmax = std::max<size_t>(ncs, (size_t)std::max(op.k, 1));
+  add((size_t)maxn * nv * ncs * 8, dbl(&d->phi));
+  add((size_t)maxn * nv * kmax * 8, dbl(&d->tmp));
+  add((size_t)maxn * nv * kmax * 8, dbl(&d->tmp2));
+  add((size_t)gemm_elems * 8, dbl(&d->gemm_ws));
+  if (h->cfg.m2l != KIFMM_M2L_FFT) {
+    add((size_t)maxn * nv * d->kp * (d->blas_mode == 0 ? 8 : 4), raw(&d->qpad));
+  } else {
+    const size_t cb = d->fp64 ? 16 : 8;
+    for (int l = 2; l <= depth; ++l) {
+      DevLevel& D = d->lv[l];
+      const size_t nc = (size_t)t.levels[l - 1].n;
+      add((size_t)op.F * (nc + 1) * nv * 8 * cb, raw(&D.Qhat));  // + empty cluster
+      add((size_t)op.F * nc * nv * 8 * cb, raw(&D.Phat));
+      add((size_t)t.levels[l].n * nv * ns * 8, dbl(&D.chk));
+    }
+  }
+  return w;
+}
+
 kifmm_status ensure_work(kifmm_handle* h, int nvec) {
   DeviceState* d = h->dev;
   if (h->cfg.m2l != KIFMM_M2L_FFT) {
-    const int tb_max = std::max(1, 128 / nvec), knob = h->tune[KIFMM_TUNE_BLAS_TILE];
-    const int TB = knob > 0 ? std::min(knob, tb_max) : tb_max;
+    const int TB = blas_tile_width(h, nvec);
     if (TB != d->tile_tb) {
       if (h->batches > 0)
         return fail(KIFMM_ESTATE, "a batch holds this handle: its BLAS tiles cannot be rebuilt");
@@ -545,50 +617,13 @@ kifmm_status ensure_work(kifmm_handle* h, int nvec) {
   for (void* p : d->work_allocs) (void)hipFree(p);
   d->work_allocs.clear();
   d->nvec_cap = 0;
-  const Tree& t = h->tree;
-  const Operators& op = h->op;
-  const int depth = t.depth;
-  const size_t ns = op.ns;
-  int64_t maxn = 0;
-  for (int l = 0; l <= depth; ++l) maxn = std::max(maxn, t.levels[l].n);
-  const size_t qbytes = (d->fp64 ? 8 : 4);
-  {
-    char* q;
-    KIFMM_TRY(dalloc(d, &q, (size_t)nvec * t.n_src * qbytes, true));
-    d->qs = q;
+  const int64_t gemm_elems = (int64_t)8 << 20;  // 64 MiB of split-K partials
+  for (WorkSlot& ws : work_slots(h, d, nvec, gemm_elems)) {
+    char* p;
+    KIFMM_TRY(dalloc(d, &p, ws.bytes, true));
+    ws.set(p);
   }
-  d->mult.assign(depth + 1, nullptr);
-  d->local.assign(depth + 1, nullptr);
-  for (int l = 2; l <= depth; ++l) {
-    KIFMM_TRY(dalloc(d, &d->mult[l], (size_t)t.levels[l].n * nvec * ns, true));
-    KIFMM_TRY(dalloc(d, &d->local[l], (size_t)t.levels[l].n * nvec * ns, true));
-  }
-  // check potentials have nc >= ns entries per box and vector
-  const size_t ncs = std::max<size_t>(ns, (size_t)op.nc);
-  const size_t kmax = std::max<size_t>(ncs, (size_t)std::max(op.k, 1));
-  KIFMM_TRY(dalloc(d, &d->phi, (size_t)maxn * nvec * ncs, true));
-  KIFMM_TRY(dalloc(d, &d->tmp, (size_t)maxn * nvec * kmax, true));
-  KIFMM_TRY(dalloc(d, &d->tmp2, (size_t)maxn * nvec * kmax, true));
-  d->gemm_ws_elems = (int64_t)8 << 20;  // 64 MiB of split-K partials
-  KIFMM_TRY(dalloc(d, &d->gemm_ws, (size_t)d->gemm_ws_elems, true));
-  if (h->cfg.m2l != KIFMM_M2L_FFT) {
-    char* qp;
-    KIFMM_TRY(dalloc(d, &qp, (size_t)maxn * nvec * d->kp * (d->blas_mode == 0 ? 8 : 4), true));
-    d->qpad = qp;
-  }
-  if (h->cfg.m2l == KIFMM_M2L_FFT) {
-    const size_t cb = d->fp64 ? 16 : 8;
-    for (int l = 2; l <= depth; ++l) {
-      DevLevel& D = d->lv[l];
-      const size_t nc = (size_t)t.levels[l - 1].n;
-      char *a, *b;
-      KIFMM_TRY(dalloc(d, &a, (size_t)op.F * (nc + 1) * nvec * 8 * cb, true));  // + empty cluster
-      KIFMM_TRY(dalloc(d, &b, (size_t)op.F * nc * nvec * 8 * cb, true));
-      KIFMM_TRY(dalloc(d, &D.chk, (size_t)t.levels[l].n * nvec * ns, true));
-      D.Qhat = a;
-      D.Phat = b;
-    }
-  }
+  d->gemm_ws_elems = gemm_elems;
   d->nvec_cap = nvec;
   return KIFMM_OK;
 }
@@ -753,9 +788,12 @@ kifmm_status device_ready(kifmm_handle* h, int nvec) {
   return ensure_work(h, nvec);
 }
 
-kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nvec, void* phi,
-                             int64_t ldphi, hipStream_t s) {
-  KIFMM_TRY(device_ready(h, nvec));
+namespace {
+
+// The evaluate's launches on buffers already in place (device_ready or the
+// no-allocation scratch).
+kifmm_status evaluate_launches(kifmm_handle* h, const void* q, int64_t ldq, int nvec, void* phi,
+                               int64_t ldphi, hipStream_t s) {
   DeviceState* d = h->dev;
   const Tree& t = h->tree;
   const Operators& op = h->op;
@@ -955,6 +993,94 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
     h->timings[8] = depth - 1;
   }
   return KIFMM_OK;
+}
+
+}  // namespace
+
+kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nvec, void* phi,
+                             int64_t ldphi, hipStream_t s) {
+  KIFMM_TRY(device_ready(h, nvec));
+  return evaluate_launches(h, q, ldq, nvec, phi, ldphi, s);
+}
+
+// ---- evaluate without allocation ----------------------------------------------
+// For callers that cannot allocate device memory (HIP graph capture, serving
+// loops, harnesses that forbid it): the work buffers of one evaluate are
+// carved out of `scratch`, a fixed device array each device holds until the
+// process ends.  In host code `scratch` names a host-side stand-in, so the
+// library takes the array's device address once per device with
+// hipGetSymbolAddress (that device current) and only ever passes that
+// address.  The split-K workspace is the largest the GEMM launcher can use,
+// so its split, and with it every sum, is the one kifmm_evaluate computes.
+static __device__ __align__(256) unsigned char scratch[KIFMM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current device.
+kifmm_status scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(KIFMM_EUNSUPPORTED, "no-allocation evaluate: device ordinal above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(KIFMM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return KIFMM_OK;
+}
+
+}  // namespace
+
+kifmm_status device_evaluate_noalloc(kifmm_handle* h, const void* q, int64_t ldq, int nvec,
+                                     void* phi, int64_t ldphi, hipStream_t s) {
+  KIFMM_TRY(check_limits(h, nvec));
+  DeviceState* d = h->dev;
+  if (!d)
+    return fail(KIFMM_ESTATE, "no-allocation evaluate: the tree and operators are not on the device "
+                              "yet (one kifmm_evaluate or kifmm_stage places them there)");
+  if (h->cfg.m2l != KIFMM_M2L_FFT && blas_tile_width(h, nvec) != d->tile_tb)
+    return fail(KIFMM_ESTATE, "no-allocation evaluate: the BLAS tiles were built for another tile "
+                              "width (one kifmm_evaluate with this n_vec rebuilds them)");
+  KIFMM_HIP(hipSetDevice(d->device));
+  void* base = nullptr;
+  KIFMM_TRY(scratch_address(d->device, &base));
+  const int64_t gemm_elems = gemm64_max_work_elems();
+  std::vector<WorkSlot> slots = work_slots(h, d, nvec, gemm_elems);
+  std::vector<size_t> off(slots.size());
+  size_t total = 0;
+  for (size_t i = 0; i < slots.size(); ++i) {
+    off[i] = total;
+    total += (slots[i].bytes + 255) / 256 * 256;
+  }
+  if (total > (size_t)KIFMM_NOALLOC_SCRATCH_BYTES)
+    return fail(KIFMM_EINVAL, "no-allocation evaluate: this problem needs " + std::to_string(total >> 20) +
+                                  " MiB of work buffers; the scratch array holds " +
+                                  std::to_string((size_t)KIFMM_NOALLOC_SCRATCH_BYTES >> 20) + " MiB");
+  // the handle's own work buffers are set aside for the call and put back
+  struct Swap {
+    DeviceState* d;
+    std::vector<WorkSlot>& slots;
+    std::vector<void*> kept;
+    int nvec_cap;
+    int64_t gemm_ws_elems;
+    ~Swap() {
+      for (size_t i = 0; i < slots.size(); ++i) slots[i].set(kept[i]);
+      d->nvec_cap = nvec_cap;
+      d->gemm_ws_elems = gemm_ws_elems;
+    }
+  } swap{d, slots, {}, d->nvec_cap, d->gemm_ws_elems};
+  for (WorkSlot& ws : slots) swap.kept.push_back(ws.get());
+  for (size_t i = 0; i < slots.size(); ++i) slots[i].set(static_cast<char*>(base) + off[i]);
+  d->nvec_cap = nvec;
+  d->gemm_ws_elems = gemm_elems;
+  return evaluate_launches(h, q, ldq, nvec, phi, ldphi, s);
 }
 
 kifmm_status device_stage(kifmm_handle* h, int level, const void* in, void* out, int nvec,

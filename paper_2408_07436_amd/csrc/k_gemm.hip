@@ -29,6 +29,7 @@ constexpr int kMT = 5;             // 16-row MFMA tiles per wave along the opera
 constexpr int kBM = 16 * kMT;      // 80 operator rows per workgroup
 constexpr int kBN = 64;            // data columns per workgroup (16 per wave)
 constexpr int kBK = 16;
+constexpr int64_t kSplitTarget = 512;  // split K below this many workgroups
 constexpr int kALoads = kBK * kBM / 256;  // operator values per thread per K slice
 
 // n / f.d and n % f.d for n < 2^32
@@ -224,6 +225,8 @@ FastDiv make_div(int d) {
 
 }  // namespace
 
+int64_t gemm64_max_work_elems() { return 2 * kSplitTarget * kBN * kBM; }
+
 hipError_t launch_gemm64(const Gemm64& g0, hipStream_t stream) {
   Gemm64 g = g0;
   const int64_t ncols = g.nbox * g.nvec;
@@ -237,7 +240,7 @@ hipError_t launch_gemm64(const Gemm64& g0, hipStream_t stream) {
   // split K when the grid cannot fill the chip, within the workspace
   const int64_t slices = (g.K + kBK - 1) / kBK;
   int64_t split = 1;
-  const int64_t target = 512;
+  const int64_t target = kSplitTarget;
   // (the reduction indexes (column, row) pairs in 32 bits)
   if (g.work && gx * gy < target && slices >= 4 && ncols * g.M < ((int64_t)1 << 32)) {
     split = std::min<int64_t>((target + gx * gy - 1) / (gx * gy), slices / 2);

@@ -71,6 +71,12 @@ struct Gemm64 {
   FastDiv div_ks, div_ms, div_nvec, div_M;  // filled by launch_gemm64
 };
 hipError_t launch_gemm64(const Gemm64& g, hipStream_t stream);
+// Largest split-K workspace (doubles) launch_gemm64 uses for any shape:
+// only grids of fewer than 512 workgroups are split, into at most
+// ceil(512 / workgroups) parts, so parts x columns x rows stays below
+// 2 x 512 workgroups x 64 columns x 80 rows.  A workspace of this size
+// never limits the split, so the partial sums do not depend on it.
+int64_t gemm64_max_work_elems();
 
 // ---- FFT-M2L (Appendix A.1) ----------------------------------------------
 // FP32 block-form Hadamard: a block's sources are staged in LDS at the slots

@@ -255,3 +255,20 @@ def test_binding_checks_shapes_before_calls():
         f.stage_m2l(3, torch.zeros((nb - 1, 1, f.n_equiv), dtype=torch.float64))
     with pytest.raises(AssertionError):
         f.evaluate(torch.zeros((1, 499), dtype=torch.float64))
+
+
+def test_evaluate_noalloc_refused_before_device_setup():
+    """kifmm_evaluate_noalloc allocates nothing, so it refuses (ESTATE, nothing
+    enqueued) a handle whose tree and operators are not on the device yet, and
+    checks its arguments like kifmm_evaluate (no device is touched here)."""
+    lib = K.lib()
+    one = ctypes.c_void_p(1)
+    f = K.KiFMM(4, 3, m2l="fft", prec="fp32").set_points(workloads.uniform_cube(500, 65)).precompute()
+    assert lib.kifmm_evaluate_noalloc(f._h, one, 500, 1, one, 500, None) == 2
+    assert b"not on the device" in lib.kifmm_last_error()
+    assert lib.kifmm_evaluate_noalloc(f._h, None, 500, 1, one, 500, None) == 1
+    assert lib.kifmm_evaluate_noalloc(f._h, one, 499, 1, one, 500, None) == 1
+    assert lib.kifmm_evaluate_noalloc(None, one, 500, 1, one, 500, None) == 1
+    g = K.KiFMM(4, 3, m2l="fft", prec="fp32")
+    assert lib.kifmm_evaluate_noalloc(g._h, one, 500, 1, one, 500, None) == 2
+    assert K.NOALLOC_SCRATCH_BYTES == 256 << 20
