@@ -259,10 +259,12 @@ def run_blas(K, torch, steps, warmup):
                      "setup_s": round(setup_s, 2),
                      "precompute_s": round(precompute_s, 3),
                      "autotuned_tile_boxes": tuning["blas_tile"],
+                     "autotuned_form": ("stacked", "fused")[tuning["blas_form"]],
                      "autotune_best_ms": round(tune_ms, 3)}
         log(f"  blas {prec}: step {ms_step:.2f} ms, m2l {tm['m2l']:.2f} ms (fused {tm['m2l_main']:.2f}), "
             f"{flops / main_s / 1e12:.1f} TFLOP/s, rel vs fp64 {rel:.2e}, vs direct "
-            f"{derr['max_over_vectors']:.2e} (max over vectors), autotuned tile {tuning['blas_tile']} boxes")
+            f"{derr['max_over_vectors']:.2e} (max over vectors), autotuned tile {tuning['blas_tile']} boxes, "
+            f"form {('stacked', 'fused')[tuning['blas_form']]}")
         if prec == "fp64":
             # the plain FP64 comparator: the same M2L form, one charge vector per launch
             q1 = q[:1].contiguous()
@@ -270,6 +272,7 @@ def run_blas(K, torch, steps, warmup):
             f.autotune(q1, phi1, reps=2)
             out["fp64_one_rhs_per_launch"] = one_rhs_m2l(torch, f, q1, phi1, steps)
             out["fp64_one_rhs_per_launch"]["autotuned_tile_boxes"] = f.tuning()["blas_tile"]
+            out["fp64_one_rhs_per_launch"]["autotuned_form"] = ("stacked", "fused")[f.tuning()["blas_form"]]
             log(f"  blas fp64, one vector per launch: m2l {out['fp64_one_rhs_per_launch']['m2l_ms']:.3f} ms")
         del f, q, phi
         torch.cuda.empty_cache()

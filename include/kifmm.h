@@ -339,8 +339,9 @@ kifmm_status kifmm_update_points(kifmm_handle* h, const void* src_dev, const voi
 /* Knobs of the evaluate's schedule and tile shapes (int32; 0 = built-in
  * default).  The paper tunes its CPU kernels by hand (the batch size of
  * Appendix A.2, the parameter search of Section 4); these knobs are this
- * library's own launch shapes.  No setting changes results: every one
- * gives bit-identical potentials.
+ * library's own launch shapes.  Settings of the first three knobs give
+ * bit-identical potentials; the two BLAS-M2L forms sum the same products in
+ * different orders (results agree to rounding).
  *   [KIFMM_TUNE_BLAS_TILE] BLAS / dense M2L: target boxes per tile.  A tile's
  *       MFMA columns are its boxes x n_vec, at most 128; larger values are
  *       clamped to 128 / n_vec.  0 = 128 / n_vec.  Range 0..128.
@@ -351,12 +352,22 @@ kifmm_status kifmm_update_points(kifmm_handle* h, const void* src_dev, const voi
  *   [KIFMM_TUNE_HADAMARD] FP32 FFT-M2L Hadamard: 0 = persistent workgroups,
  *       one device-full, each over one contiguous run of the frequency-major
  *       (frequency, block, vector) items; 1 = one workgroup per unit of 8
- *       consecutive items. */
+ *       consecutive items.
+ *   [KIFMM_TUNE_BLAS_FORM] BLAS-M2L with directional recompression (Section
+ *       3.1-3.2: phi~ = sum_t Ubar_t Vbar'_t^T q~): 0 = stacked, two GEMM
+ *       kernels per level over octant classes - Stage A forms Vbar'_t^T q~
+ *       of every source box for all 189 transfer vectors its class serves
+ *       (kept in device memory, about 4 sum_t k_t bytes per box and vector
+ *       in FP32, twice that in FP64), Stage B sums Ubar_t times those blocks
+ *       per target box; 1 = fused, one kernel per level that gathers q~ per
+ *       target tile and transfer vector and keeps Vbar'_t^T q~ in registers
+ *       (no intermediate in memory).  Other M2L forms ignore it. */
 enum {
   KIFMM_TUNE_BLAS_TILE = 0,
   KIFMM_TUNE_SCHEDULE = 1,
   KIFMM_TUNE_HADAMARD = 2,
-  KIFMM_TUNE_COUNT = 3
+  KIFMM_TUNE_BLAS_FORM = 3,
+  KIFMM_TUNE_COUNT = 4
 };
 /* Current knob values into knobs[0 .. KIFMM_TUNE_COUNT); cap >= KIFMM_TUNE_COUNT.
  * Host only. */
@@ -367,7 +378,8 @@ kifmm_status kifmm_get_tuning(const kifmm_handle* h, int32_t* knobs, int32_t cap
 kifmm_status kifmm_set_tuning(kifmm_handle* h, const int32_t* knobs, int32_t n);
 /* Autotuner: times every candidate setting that applies to the handle's M2L
  * form and precision (FFT: schedule x Hadamard form for FP32, schedule for
- * FP64; BLAS / dense: four tile widths) with one warm-up and `reps` (1..100)
+ * FP64; BLAS / dense: four tile widths, times the two forms for BLAS-M2L
+ * with directional recompression) with one warm-up and `reps` (1..100)
  * evaluates of the given charges (arguments as in kifmm_evaluate), keeps
  * the setting with the smallest median evaluate time, and writes that time
  * to *best_ms (if not NULL).  phi_dev holds the last evaluate's potentials.

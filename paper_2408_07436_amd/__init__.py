@@ -30,7 +30,7 @@ EXPORTS = [
     "kifmm_batch_launch", "kifmm_batch_destroy", "kifmm_set_svd", "kifmm_evaluate_noalloc",
 ]
 NOALLOC_SCRATCH_BYTES = 256 << 20  # KIFMM_NOALLOC_SCRATCH_BYTES
-TUNE_KNOBS = ("blas_tile", "schedule", "hadamard")
+TUNE_KNOBS = ("blas_tile", "schedule", "hadamard", "blas_form")
 
 
 class KifmmError(RuntimeError):

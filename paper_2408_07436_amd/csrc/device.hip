@@ -41,6 +41,10 @@ struct DevLevel {
   int64_t* tl_offs = nullptr;
   int32_t* tl_t = nullptr;
   int32_t* tl_src = nullptr;
+  // stacked form: octant class of each tile and the source box of every
+  // (transfer vector j of the class, tile slot), -1 where absent
+  int32_t* tile_class = nullptr;
+  int32_t* tile_src = nullptr;
 };
 
 struct DeviceState {
@@ -87,6 +91,14 @@ struct DeviceState {
   void* op_lo = nullptr;
   int tile_tb = 0;            // target boxes per tile of the current tiles
   void* qpad = nullptr;       // padded compressed multipoles
+  // stacked two-stage form (BlasStack in kernels.h): operators of Stage A
+  // and B, the row-group table, the per-class slot j of each transfer vector
+  bool stack_ok = false;
+  int st_Rs = 0, st_Rpad = 0, st_nsteps = 0, st_rbo = 0, st_J = 0;
+  void *st_A_hi = nullptr, *st_A_lo = nullptr, *st_B_hi = nullptr, *st_B_lo = nullptr;
+  int32_t* st_info = nullptr;
+  std::vector<int32_t> st_jof;  // [8][316]
+  void *xi_hi = nullptr, *xi_lo = nullptr;  // work: stacked intermediates
   std::vector<DevLevel> lv;
   // work buffers
   int nvec_cap = 0;
@@ -265,6 +277,159 @@ kifmm_status pack_blas_operators(kifmm_handle* h, DeviceState* d) {
   return KIFMM_OK;
 }
 
+// Operators of the stacked two-stage form.  Target class o (key & 7) takes
+// the transfer vectors T(o) (ascending index; t_x = -3 only for odd x, +3
+// only for even x, likewise y and z); a source of class c serves T(c ^ 7),
+// and the source of target class o along t has class o ^ (t mod 2).  Each
+// t's k_t rows are padded to P = 4 (BF16x3: 8) rows.
+//   Stage A operators [8][Rpad][kp]: class c's rows are Vbar'_t^T for t in
+//     T(c ^ 7), stacked; Rs = rows per class (all classes alike).
+//   Stage B operators, class o, K = the stacked rows of T(o): FP32 / FP64
+//     [8][nsteps][64 lanes][rbo] with lane (g, l) of step n holding
+//     Ubar(row 16 rb + l, K 4 n + g); BF16x3 [8][nsteps][64][rbo][8] holding
+//     K 32 n + 8 g + e, split into bf16 high and low parts.
+//   info [8][groups][2]: per group of 4 (BF16x3: 8) K rows, the class slot j
+//     of its transfer vector and the xi row of its first row (-1: padding).
+kifmm_status pack_blas_stacked(kifmm_handle* h, DeviceState* d) {
+  const Operators& op = h->op;
+  const int mode = d->blas_mode, k = op.k, kp = d->kp;
+  const int P = mode == 2 ? 8 : 4, KS = mode == 2 ? 32 : 4, G = mode == 2 ? 8 : 4;
+  const int rbo = (kp / 16 + 1) / 2 * 2;
+  auto admissible = [](int o, const int t[3]) {
+    for (int ax = 0; ax < 3; ++ax) {
+      const int b = (o >> ax) & 1;
+      if ((b == 0 && t[ax] == -3) || (b == 1 && t[ax] == 3)) return false;
+    }
+    return true;
+  };
+  auto parity = [](int it) {
+    int t[3];
+    transfer_vector(it, t);
+    return (t[0] & 1) | ((t[1] & 1) << 1) | ((t[2] & 1) << 2);
+  };
+  std::vector<std::vector<int>> Tt(8);
+  for (int o = 0; o < 8; ++o)
+    for (int it = 0; it < kNumTransfer; ++it) {
+      int t[3];
+      transfer_vector(it, t);
+      if (admissible(o, t)) Tt[o].push_back(it);
+    }
+  const int J = (int)Tt[0].size();
+  for (int o = 1; o < 8; ++o)
+    if ((int)Tt[o].size() != J) return fail(KIFMM_ENUMERIC, "octant classes with different transfer-vector counts");
+  auto seg = [&](int it) { return (op.kt[it] + P - 1) / P * P; };
+  std::vector<int> srcoff((size_t)8 * kNumTransfer, -1), tgtoff((size_t)8 * kNumTransfer, -1);
+  std::vector<int> Rt(8, 0);
+  int Rs = 0;
+  for (int c = 0; c < 8; ++c) {
+    int off = 0;
+    for (int it : Tt[c ^ 7]) {
+      srcoff[(size_t)c * kNumTransfer + it] = off;
+      off += seg(it);
+    }
+    Rs = std::max(Rs, off);
+    off = 0;
+    for (int it : Tt[c]) {
+      tgtoff[(size_t)c * kNumTransfer + it] = off;
+      off += seg(it);
+    }
+    Rt[c] = off;
+  }
+  const int Rpad = (Rs + 127) / 128 * 128;
+  const int Rtmax = *std::max_element(Rt.begin(), Rt.end());
+  const int nsteps = (Rtmax + KS - 1) / KS;
+  const int ngroups = nsteps * KS / G;
+  // row r of class o's stacked K -> (transfer vector, row within its k_t), or -1
+  std::vector<int32_t> rt_it((size_t)8 * nsteps * KS, -1), rt_i((size_t)8 * nsteps * KS, 0);
+  std::vector<int32_t> info((size_t)8 * ngroups * 2, 0);
+  d->st_jof.assign((size_t)8 * kNumTransfer, -1);
+  for (int o = 0; o < 8; ++o) {
+    for (int j = 0; j < J; ++j) {
+      const int it = Tt[o][j];
+      d->st_jof[(size_t)o * kNumTransfer + it] = j;
+      const int r0 = tgtoff[(size_t)o * kNumTransfer + it];
+      for (int i = 0; i < seg(it); ++i) {
+        rt_it[(size_t)o * nsteps * KS + r0 + i] = it;
+        rt_i[(size_t)o * nsteps * KS + r0 + i] = i;
+      }
+    }
+    for (int n = 0; n < ngroups; ++n) {
+      const int r = n * G;
+      const int it = rt_it[(size_t)o * nsteps * KS + r];
+      int32_t* e = &info[((size_t)o * ngroups + n) * 2];
+      if (it < 0) {
+        e[0] = -1;
+        e[1] = 0;
+        continue;
+      }
+      const int c = o ^ parity(it);
+      e[0] = d->st_jof[(size_t)o * kNumTransfer + it];
+      e[1] = srcoff[(size_t)c * kNumTransfer + it] + rt_i[(size_t)o * nsteps * KS + r];
+    }
+  }
+  std::vector<double> A((size_t)8 * Rpad * kp, 0.0);
+  for (int c = 0; c < 8; ++c)
+    for (int it : Tt[c ^ 7]) {
+      const int kt = op.kt[it], r0 = srcoff[(size_t)c * kNumTransfer + it];
+      for (int i = 0; i < kt; ++i)
+        for (int cc = 0; cc < k; ++cc)
+          A[((size_t)c * Rpad + r0 + i) * kp + cc] = op.Vbarp[it][(size_t)cc * kt + i];
+    }
+  auto ubar = [&](int o, int m, int r) -> double {
+    if (m >= k || r >= nsteps * KS) return 0.0;
+    const int it = rt_it[(size_t)o * nsteps * KS + r];
+    if (it < 0) return 0.0;
+    const int kt = op.kt[it], i = rt_i[(size_t)o * nsteps * KS + r];
+    return i < kt ? op.Ubar[it][(size_t)m * kt + i] : 0.0;
+  };
+  const int per = mode == 2 ? 8 : 1;  // values per (lane, row block)
+  std::vector<double> B((size_t)8 * nsteps * 64 * rbo * per, 0.0);
+  for (int o = 0; o < 8; ++o)
+    for (int n = 0; n < nsteps; ++n)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int rb = 0; rb < rbo; ++rb)
+          for (int e = 0; e < per; ++e) {
+            const int m = rb * 16 + lane % 16;
+            const int r = mode == 2 ? 32 * n + 8 * (lane / 16) + e : 4 * n + lane / 16;
+            B[((((size_t)o * nsteps + n) * 64 + lane) * rbo + rb) * per + e] = ubar(o, m, r);
+          }
+  auto put = [&](const std::vector<double>& v, void** hi, void** lo) -> kifmm_status {
+    if (mode == 0) {
+      double* p;
+      KIFMM_TRY(upload(d, &p, v.data(), v.size()));
+      *hi = p;
+    } else if (mode == 1) {
+      std::vector<float> f(v.begin(), v.end());
+      float* p;
+      KIFMM_TRY(upload(d, &p, f.data(), f.size()));
+      *hi = p;
+    } else {
+      std::vector<uint16_t> vh(v.size()), vl(v.size());
+      for (size_t i = 0; i < v.size(); ++i) {
+        const float x = (float)v[i];
+        vh[i] = bf16_bits(x);
+        vl[i] = bf16_bits(x - bf16_value(vh[i]));
+      }
+      uint16_t *ph, *pl;
+      KIFMM_TRY(upload(d, &ph, vh.data(), vh.size()));
+      KIFMM_TRY(upload(d, &pl, vl.data(), vl.size()));
+      *hi = ph;
+      *lo = pl;
+    }
+    return KIFMM_OK;
+  };
+  KIFMM_TRY(put(A, &d->st_A_hi, &d->st_A_lo));
+  KIFMM_TRY(put(B, &d->st_B_hi, &d->st_B_lo));
+  KIFMM_TRY(upload(d, &d->st_info, info.data(), info.size()));
+  d->st_Rs = Rs;
+  d->st_Rpad = Rpad;
+  d->st_nsteps = nsteps;
+  d->st_rbo = rbo;
+  d->st_J = J;
+  d->stack_ok = true;
+  return KIFMM_OK;
+}
+
 // Target tiles of TB boxes of one octant class per level (boxes of a class
 // share their transfer vectors) and, per tile, the transfer vectors present
 // in ascending order with the source box of each slot.
@@ -273,13 +438,15 @@ kifmm_status build_blas_tiles(kifmm_handle* h, DeviceState* d, int TB) {
   for (int l = 2; l <= t.depth; ++l) {
     const Level& L = t.levels[l];
     DevLevel& D = d->lv[l];
-    for (void* p : {(void*)D.tile_box, (void*)D.tl_offs, (void*)D.tl_t, (void*)D.tl_src}) {
+    for (void* p : {(void*)D.tile_box, (void*)D.tl_offs, (void*)D.tl_t, (void*)D.tl_src,
+                    (void*)D.tile_class, (void*)D.tile_src}) {
       if (!p) continue;
       (void)hipFree(p);
       d->allocs.erase(std::remove(d->allocs.begin(), d->allocs.end(), p), d->allocs.end());
     }
-    std::vector<int32_t> tile_box, tl_t, tl_src;
+    std::vector<int32_t> tile_box, tl_t, tl_src, tile_class, tile_src;
     std::vector<int64_t> tl_offs(1, 0);
+    const int J = d->st_J;
     std::vector<int32_t> map((size_t)TB * kNumTransfer, -1);
     for (int o = 0; o < 8; ++o) {
       std::vector<int32_t> boxes;
@@ -288,10 +455,18 @@ kifmm_status build_blas_tiles(kifmm_handle* h, DeviceState* d, int TB) {
       for (size_t b0 = 0; b0 < boxes.size(); b0 += TB) {
         const size_t nb = std::min<size_t>(TB, boxes.size() - b0);
         for (size_t sl = 0; sl < (size_t)TB; ++sl) tile_box.push_back(sl < nb ? boxes[b0 + sl] : -1);
+        tile_class.push_back(o);
+        if (d->stack_ok) tile_src.resize(tile_src.size() + (size_t)J * TB, -1);
         for (size_t sl = 0; sl < nb; ++sl) {
           const int32_t bx = boxes[b0 + sl];
-          for (int64_t e = L.il_offs[bx]; e < L.il_offs[bx + 1]; ++e)
+          for (int64_t e = L.il_offs[bx]; e < L.il_offs[bx + 1]; ++e) {
             map[(size_t)sl * kNumTransfer + L.il_t[e]] = L.il_src[e];
+            if (d->stack_ok) {
+              const int j = d->st_jof[(size_t)o * kNumTransfer + L.il_t[e]];
+              if (j < 0) return fail(KIFMM_ENUMERIC, "interaction outside the octant class's transfer vectors");
+              tile_src[tile_src.size() - (size_t)J * TB + (size_t)j * TB + sl] = L.il_src[e];
+            }
+          }
         }
         for (int tt = 0; tt < kNumTransfer; ++tt) {
           bool any = false;
@@ -312,6 +487,8 @@ kifmm_status build_blas_tiles(kifmm_handle* h, DeviceState* d, int TB) {
     KIFMM_TRY(upload(d, &D.tl_offs, tl_offs.data(), tl_offs.size()));
     KIFMM_TRY(upload(d, &D.tl_t, tl_t.data(), tl_t.size()));
     KIFMM_TRY(upload(d, &D.tl_src, tl_src.data(), tl_src.size()));
+    KIFMM_TRY(upload(d, &D.tile_class, tile_class.data(), tile_class.size()));
+    if (d->stack_ok) KIFMM_TRY(upload(d, &D.tile_src, tile_src.data(), tile_src.size()));
   }
   d->tile_tb = TB;
   return KIFMM_OK;
@@ -507,6 +684,7 @@ kifmm_status upload_all(kifmm_handle* h) {
     KIFMM_TRY(upload(d, &d->Ublas, op.U.data(), op.U.size()));
     KIFMM_TRY(upload(d, &d->SblasT, St.data(), St.size()));
     KIFMM_TRY(pack_blas_operators(h, d));
+    if (op.recompressed && h->cfg.m2l == KIFMM_M2L_BLAS) KIFMM_TRY(pack_blas_stacked(h, d));
   }
   for (int e = 0; e < 8; ++e) KIFMM_HIP(hipEventCreate(&d->ev[e]));
   d->lev_ev.assign(4 * (depth + 1), nullptr);
@@ -588,6 +766,15 @@ std::vector<WorkSlot> work_slots(const kifmm_handle* h, DeviceState* d, int nvec
   add((size_t)gemm_elems * 8, dbl(&d->gemm_ws));
   if (h->cfg.m2l != KIFMM_M2L_FFT) {
     add((size_t)maxn * nv * d->kp * (d->blas_mode == 0 ? 8 : 4), raw(&d->qpad));
+    if (d->stack_ok && h->tune[KIFMM_TUNE_BLAS_FORM] == 0) {
+      const size_t xi = (size_t)maxn * nv * d->st_Rs;
+      if (d->blas_mode == 2) {
+        add(xi * 2, raw(&d->xi_hi));
+        add(xi * 2, raw(&d->xi_lo));
+      } else {
+        add(xi * (d->blas_mode == 0 ? 8 : 4), raw(&d->xi_hi));
+      }
+    }
   } else {
     const size_t cb = d->fp64 ? 16 : 8;
     for (int l = 2; l <= depth; ++l) {
@@ -611,9 +798,12 @@ kifmm_status ensure_work(kifmm_handle* h, int nvec) {
       KIFMM_TRY(build_blas_tiles(h, d, TB));
     }
   }
-  if (nvec <= d->nvec_cap) return KIFMM_OK;
+  const bool need_xi = d->stack_ok && h->tune[KIFMM_TUNE_BLAS_FORM] == 0 && h->cfg.m2l != KIFMM_M2L_FFT;
+  if (nvec <= d->nvec_cap && (!need_xi || d->xi_hi)) return KIFMM_OK;
   if (h->batches > 0)
     return fail(KIFMM_ESTATE, "a batch holds this handle: more vectors than its buffers hold");
+  d->xi_hi = d->xi_lo = nullptr;
+  nvec = std::max(nvec, d->nvec_cap);
   for (void* p : d->work_allocs) (void)hipFree(p);
   d->work_allocs.clear();
   d->nvec_cap = 0;
@@ -686,6 +876,51 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
              d->tmp, k, 1, nullptr, (int64_t)nvec * k, k, D.n, nvec, 0};
     KIFMM_LAUNCH(gemm(d, g, s));
     qsrc = d->tmp;
+  }
+  if (!dense && d->stack_ok && h->tune[KIFMM_TUNE_BLAS_FORM] == 0) {
+    // stacked form: Stage A (xi of every source box), Stage B (targets)
+    void* qlo = nullptr;
+    if (d->blas_mode == 2) {
+      qlo = static_cast<char*>(d->qpad) + (size_t)D.n * nvec * d->kp * 2;
+      KIFMM_LAUNCH(launch_pad_split(qsrc, k, D.n * nvec, d->kp, d->qpad, qlo, s));
+    } else {
+      KIFMM_LAUNCH(launch_pad_convert(qsrc, k, D.n * nvec, d->kp, d->blas_mode == 0, d->qpad, s));
+    }
+    if (mark) KIFMM_HIP(hipEventRecord(mark[1], s));
+    BlasStack b;
+    b.mode = d->blas_mode;
+    b.k = k;
+    b.kp = d->kp;
+    b.nvec = nvec;
+    b.TB = d->tile_tb;
+    b.C = d->tile_tb * nvec;
+    b.ntiles = D.ntiles;
+    b.tile_box = D.tile_box;
+    b.tile_class = D.tile_class;
+    b.tile_src = D.tile_src;
+    b.J = d->st_J;
+    b.Rs = d->st_Rs;
+    b.Rpad = d->st_Rpad;
+    b.nsteps = d->st_nsteps;
+    b.rbo = d->st_rbo;
+    b.A_hi = d->st_A_hi;
+    b.A_lo = d->st_A_lo;
+    b.B_hi = d->st_B_hi;
+    b.B_lo = d->st_B_lo;
+    b.info = d->st_info;
+    b.q_hi = d->qpad;
+    b.q_lo = qlo;
+    b.xi_hi = d->xi_hi;
+    b.xi_lo = d->xi_lo;
+    b.out = d->tmp2;
+    b.scale = 1.0 / D.w;
+    KIFMM_LAUNCH(launch_blas_stacked(b, s));
+    if (mark) KIFMM_HIP(hipEventRecord(mark[2], s));
+    Gemm64 g{d->Ublas, ncp, k, k, 1.0, d->tmp2, k, 1, nullptr, (int64_t)nvec * k, k,
+             out, ncp, 1, nullptr, (int64_t)nvec * ncp, ncp, D.n, nvec, 0};
+    KIFMM_LAUNCH(gemm(d, g, s));
+    if (mark) KIFMM_HIP(hipEventRecord(mark[3], s));
+    return KIFMM_OK;
   }
   KIFMM_LAUNCH(launch_pad_convert(qsrc, k, D.n * nvec, d->kp, d->blas_mode == 0, d->qpad, s));
   if (mark) KIFMM_HIP(hipEventRecord(mark[1], s));
@@ -1128,14 +1363,18 @@ kifmm_status device_autotune(kifmm_handle* h, const void* q, int64_t ldq, int nv
       }
   } else {
     const int tb_max = std::max(1, 128 / nvec);
-    int last = -1;
-    for (int k = 0; k < 4; ++k) {
-      const int tb = std::max(1, tb_max >> k);
-      if (tb == last) continue;
-      last = tb;
-      Knobs c = base;
-      c[KIFMM_TUNE_BLAS_TILE] = tb;
-      cand.push_back(c);
+    const bool two_forms = h->cfg.m2l == KIFMM_M2L_BLAS && h->op.recompressed;
+    for (int form = 0; form < (two_forms ? 2 : 1); ++form) {
+      int last = -1;
+      for (int k = 0; k < 4; ++k) {
+        const int tb = std::max(1, tb_max >> k);
+        if (tb == last) continue;
+        last = tb;
+        Knobs c = base;
+        c[KIFMM_TUNE_BLAS_TILE] = tb;
+        c[KIFMM_TUNE_BLAS_FORM] = form;
+        cand.push_back(c);
+      }
     }
   }
   struct Restore {  // events, the timing switch and (on errors) the knobs

@@ -377,6 +377,358 @@ __global__ __launch_bounds__(256) void blas_m2l_bf16_kernel(BlasM2L a) {
   }
 }
 
+// ---- stacked form (two-stage operators) -------------------------------------
+// Column c of a tile (TB boxes x nvec vectors, c < C): slot c / nvec, vector
+// c % nvec; wave w takes columns 32 w .. 32 w + 31 as two MFMA column tiles.
+struct StackCols {
+  int slot[2], v[2];
+  bool ok[2];
+};
+__device__ inline StackCols stack_columns(const BlasStack& a, int wave, int l16) {
+  StackCols c;
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) {
+    const int col = (wave * 2 + ct) * 16 + l16;
+    c.ok[ct] = col < a.C;
+    c.slot[ct] = c.ok[ct] ? col / a.nvec : 0;
+    c.v[ct] = c.ok[ct] ? col - c.slot[ct] * a.nvec : 0;
+  }
+  return c;
+}
+
+// Work item w of a grid that is a multiple of 8, consecutive items on one
+// XCD (workgroup b runs on XCD b % 8): tiles are ordered by class, so an
+// XCD's L2 holds the operators of about one class.
+__device__ inline int64_t xcd_item() {
+  const int64_t b = blockIdx.x, per_xcd = gridDim.x / 8;
+  return (b % 8) * per_xcd + b / 8;
+}
+
+// Stage A, FP32 / FP64: one workgroup per (tile, 128-row block of the
+// class's stacked operator); xi[box][row][v] for rows < Rs.
+template <typename T>
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_a_kernel(BlasStack a) {
+  using V4 = typename std::conditional<sizeof(T) == 4, v4f, v4d>::type;
+  const int nmb = a.Rpad / 128;
+  const int64_t w = xcd_item();
+  if (w >= a.ntiles * nmb) return;
+  const int64_t tile = w / nmb;
+  const int mb = (int)(w - tile * nmb);
+  const int cls = a.tile_class[tile];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int l16 = lane % 16, g4 = lane / 16;
+  const T* q = static_cast<const T*>(a.q_hi);
+  const T* A = static_cast<const T*>(a.A_hi) + ((int64_t)cls * a.Rpad + (int64_t)mb * 128) * a.kp;
+  const StackCols cc = stack_columns(a, wave, l16);
+  int box[2];
+  const T* qp[2];
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) {
+    box[ct] = cc.ok[ct] ? a.tile_box[tile * a.TB + cc.slot[ct]] : -1;
+    qp[ct] = box[ct] >= 0 ? q + ((int64_t)box[ct] * a.nvec + cc.v[ct]) * a.kp : nullptr;
+  }
+  V4 acc[8][2];
+#pragma unroll
+  for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) acc[rb][ct] = V4{T(0), T(0), T(0), T(0)};
+  for (int kb = 0; kb < a.kp; kb += 16) {
+    V4 bq[2];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) bq[ct] = qp[ct] ? ld4(qp[ct] + kb + 4 * g4) : V4{T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb) {
+      const V4 av = ld4(A + (int64_t)(rb * 16 + l16) * a.kp + kb + 4 * g4);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          if constexpr (sizeof(T) == 4)
+            acc[rb][ct] = mf32(av[s], bq[ct][s], acc[rb][ct]);
+          else
+            acc[rb][ct] = mf64(av[s], bq[ct][s], acc[rb][ct]);
+        }
+    }
+  }
+  T* xi = static_cast<T*>(a.xi_hi);
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) {
+    if (box[ct] < 0) continue;
+    T* dst = xi + (int64_t)box[ct] * a.Rs * a.nvec + cc.v[ct];
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        // FP32 accumulator rows are 4 g4 + i, FP64 rows g4 + 4 i
+        const int row = mb * 128 + rb * 16 + (sizeof(T) == 4 ? 4 * g4 + i : g4 + 4 * i);
+        if (row < a.Rs) dst[(int64_t)row * a.nvec] = acc[rb][ct][i];
+      }
+  }
+}
+
+// Stage B, FP32 / FP64: one workgroup per target tile; K step n covers rows
+// 4n .. 4n + 3 of the class's stacked K (one transfer vector j, whose xi
+// rows start at info[n].y).  Loads run ahead of the MFMAs: the table entry
+// three steps, the source box two steps, xi and the operator one step.
+template <typename T, int RBO>
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_b_kernel(BlasStack a) {
+  using V4 = typename std::conditional<sizeof(T) == 4, v4f, v4d>::type;
+  const int tile = xcd_tile(a.ntiles);
+  if (tile < 0) return;
+  const int cls = a.tile_class[tile];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int l16 = lane % 16, g4 = lane / 16;
+  const StackCols cc = stack_columns(a, wave, l16);
+  const int32_t* src = a.tile_src + (int64_t)tile * a.J * a.TB;
+  const int2* info = reinterpret_cast<const int2*>(a.info) + (int64_t)cls * a.nsteps;
+  const T* Bop = static_cast<const T*>(a.B_hi) + (int64_t)cls * a.nsteps * 64 * RBO + lane * RBO;
+  const T* xi = static_cast<const T*>(a.xi_hi);
+  const int64_t rs = a.Rs;
+  const int nst = a.nsteps;
+  V4 acc[RBO][2];
+#pragma unroll
+  for (int rb = 0; rb < RBO; ++rb)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) acc[rb][ct] = V4{T(0), T(0), T(0), T(0)};
+  auto source = [&](int2 in, int ct) -> int {
+    return (cc.ok[ct] && in.x >= 0) ? src[in.x * a.TB + cc.slot[ct]] : -1;
+  };
+  auto xval = [&](int sb, int row, int ct) -> T {
+    return sb >= 0 ? xi[((int64_t)sb * rs + row + g4) * a.nvec + cc.v[ct]] : T(0);
+  };
+  // pipeline registers: in2 = table entry of step n + 2, sb1 / row1 = source
+  // boxes of step n + 1, x0 / o0 = xi and operator values of step n
+  int2 in2 = nst > 2 ? info[2] : make_int2(-1, 0);
+  const int2 in1 = nst > 1 ? info[1] : make_int2(-1, 0);
+  const int2 in0 = info[0];
+  int sb1[2], row1 = in1.y;
+  T x0[2], o0[RBO];
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) {
+    sb1[ct] = source(in1, ct);
+    x0[ct] = xval(source(in0, ct), in0.y, ct);
+  }
+#pragma unroll
+  for (int rb = 0; rb < RBO; ++rb) o0[rb] = Bop[rb];
+  for (int n = 0; n < nst; ++n) {
+    // issue the loads of the next steps
+    const int2 in3 = n + 3 < nst ? info[n + 3] : make_int2(-1, 0);
+    int sb2[2];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) sb2[ct] = source(in2, ct);
+    T x1[2], o1[RBO];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) x1[ct] = xval(sb1[ct], row1, ct);
+    if (n + 1 < nst) {
+#pragma unroll
+      for (int rb = 0; rb < RBO; ++rb) o1[rb] = Bop[(int64_t)(n + 1) * 64 * RBO + rb];
+    } else {
+#pragma unroll
+      for (int rb = 0; rb < RBO; ++rb) o1[rb] = T(0);
+    }
+    // products of step n
+#pragma unroll
+    for (int rb = 0; rb < RBO; ++rb)
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        if constexpr (sizeof(T) == 4)
+          acc[rb][ct] = mf32(o0[rb], x0[ct], acc[rb][ct]);
+        else
+          acc[rb][ct] = mf64(o0[rb], x0[ct], acc[rb][ct]);
+      }
+    // roll
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      x0[ct] = x1[ct];
+      sb1[ct] = sb2[ct];
+    }
+#pragma unroll
+    for (int rb = 0; rb < RBO; ++rb) o0[rb] = o1[rb];
+    row1 = in2.y;
+    in2 = in3;
+  }
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) {
+    if (!cc.ok[ct]) continue;
+    const int box = a.tile_box[tile * a.TB + cc.slot[ct]];
+    if (box < 0) continue;
+    double* dst = a.out + ((int64_t)box * a.nvec + cc.v[ct]) * a.k;
+#pragma unroll
+    for (int rb = 0; rb < RBO; ++rb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = rb * 16 + (sizeof(T) == 4 ? 4 * g4 + i : g4 + 4 * i);
+        if (row < a.k) dst[row] = a.scale * (double)acc[rb][ct][i];
+      }
+  }
+}
+
+// x = hi + lo for four floats, round-to-nearest-even bf16 parts
+__device__ inline void split4(const v4f x, __bf16* hi, __bf16* lo) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const __bf16 h = (__bf16)x[e];
+    hi[e] = h;
+    lo[e] = (__bf16)(x[e] - (float)h);
+  }
+}
+
+// Stage A, BF16x3: operands split hi + lo (three products, FP32
+// accumulation); xi stored split, [box][Rs / 8][v][8] so that eight
+// consecutive rows of one column are one 16-byte load in Stage B.
+__global__ __launch_bounds__(256, 2) void stack_a_bf16_kernel(BlasStack a) {
+  const int nmb = a.Rpad / 128;
+  const int64_t w = xcd_item();
+  if (w >= a.ntiles * nmb) return;
+  const int64_t tile = w / nmb;
+  const int mb = (int)(w - tile * nmb);
+  const int cls = a.tile_class[tile];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int l16 = lane % 16, g4 = lane / 16;
+  const __bf16* qh = static_cast<const __bf16*>(a.q_hi);
+  const __bf16* ql = static_cast<const __bf16*>(a.q_lo);
+  const int64_t aoff = ((int64_t)cls * a.Rpad + (int64_t)mb * 128) * a.kp;
+  const __bf16* Ah = static_cast<const __bf16*>(a.A_hi) + aoff;
+  const __bf16* Al = static_cast<const __bf16*>(a.A_lo) + aoff;
+  const StackCols cc = stack_columns(a, wave, l16);
+  int box[2];
+  int64_t qo[2];
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) {
+    box[ct] = cc.ok[ct] ? a.tile_box[tile * a.TB + cc.slot[ct]] : -1;
+    qo[ct] = box[ct] >= 0 ? ((int64_t)box[ct] * a.nvec + cc.v[ct]) * a.kp : -1;
+  }
+  v4f acc[8][2];
+#pragma unroll
+  for (int rb = 0; rb < 8; ++rb)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) acc[rb][ct] = v4f{0.f, 0.f, 0.f, 0.f};
+  const v8bf zero8 = {};
+  for (int kb = 0; kb < a.kp; kb += 32) {
+    v8bf bh[2], bl[2];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      bh[ct] = qo[ct] >= 0 ? ld8bf(qh + qo[ct] + kb + 8 * g4) : zero8;
+      bl[ct] = qo[ct] >= 0 ? ld8bf(ql + qo[ct] + kb + 8 * g4) : zero8;
+    }
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb) {
+      const int64_t o = (int64_t)(rb * 16 + l16) * a.kp + kb + 8 * g4;
+      const v8bf ah = ld8bf(Ah + o), al = ld8bf(Al + o);
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        acc[rb][ct] = mfbf(ah, bh[ct], acc[rb][ct]);
+        acc[rb][ct] = mfbf(ah, bl[ct], acc[rb][ct]);
+        acc[rb][ct] = mfbf(al, bh[ct], acc[rb][ct]);
+      }
+    }
+  }
+  __bf16* xh = static_cast<__bf16*>(a.xi_hi);
+  __bf16* xl = static_cast<__bf16*>(a.xi_lo);
+  const int64_t rb8 = a.Rs / 8;
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) {
+    if (box[ct] < 0) continue;
+#pragma unroll
+    for (int rb = 0; rb < 8; ++rb) {
+      const int row = mb * 128 + rb * 16 + 4 * g4;  // rows row .. row + 3 of this lane
+      if (row >= a.Rs) continue;
+      const int64_t o = (((int64_t)box[ct] * rb8 + row / 8) * a.nvec + cc.v[ct]) * 8 + row % 8;
+      __bf16 h[4], l[4];
+      split4(acc[rb][ct], h, l);
+      typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
+      *reinterpret_cast<v4bf*>(xh + o) = v4bf{h[0], h[1], h[2], h[3]};
+      *reinterpret_cast<v4bf*>(xl + o) = v4bf{l[0], l[1], l[2], l[3]};
+    }
+  }
+}
+
+// Stage B, BF16x3: K steps of 32 rows; lane group g4 takes the eight rows of
+// row group 4n + g4 (info per group), possibly of another transfer vector
+// than its neighbours.  Operators [8][nsteps][64 lanes][RBO][8] hi / lo.
+template <int RBO>
+__global__ __launch_bounds__(256, 2) void stack_b_bf16_kernel(BlasStack a) {
+  const int tile = xcd_tile(a.ntiles);
+  if (tile < 0) return;
+  const int cls = a.tile_class[tile];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int l16 = lane % 16, g4 = lane / 16;
+  const StackCols cc = stack_columns(a, wave, l16);
+  const int32_t* src = a.tile_src + (int64_t)tile * a.J * a.TB;
+  const int2* info = reinterpret_cast<const int2*>(a.info) + (int64_t)cls * a.nsteps * 4;
+  const int64_t boff = (int64_t)cls * a.nsteps * 64 * RBO * 8 + (int64_t)lane * RBO * 8;
+  const __bf16* Bh = static_cast<const __bf16*>(a.B_hi) + boff;
+  const __bf16* Bl = static_cast<const __bf16*>(a.B_lo) + boff;
+  const __bf16* xh = static_cast<const __bf16*>(a.xi_hi);
+  const __bf16* xl = static_cast<const __bf16*>(a.xi_lo);
+  const int64_t rb8 = a.Rs / 8;
+  const int nst = a.nsteps;
+  v4f acc[RBO][2];
+#pragma unroll
+  for (int rb = 0; rb < RBO; ++rb)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) acc[rb][ct] = v4f{0.f, 0.f, 0.f, 0.f};
+  const v8bf zero8 = {};
+  // offsets of the xi values of one step, -1 if absent
+  auto offsets = [&](int n, int64_t o[2]) {
+    const int2 in = info[4 * n + g4];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const int sb = (cc.ok[ct] && in.x >= 0) ? src[in.x * a.TB + cc.slot[ct]] : -1;
+      o[ct] = sb >= 0 ? (((int64_t)sb * rb8 + in.y / 8) * a.nvec + cc.v[ct]) * 8 : -1;
+    }
+  };
+  int64_t o1[2];
+  offsets(0, o1);
+  for (int n = 0; n < nst; ++n) {
+    v8bf bh[2], bl[2];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      bh[ct] = o1[ct] >= 0 ? ld8bf(xh + o1[ct]) : zero8;
+      bl[ct] = o1[ct] >= 0 ? ld8bf(xl + o1[ct]) : zero8;
+    }
+    if (n + 1 < nst) offsets(n + 1, o1);
+    const int64_t so = (int64_t)n * 64 * RBO * 8;
+#pragma unroll
+    for (int rb = 0; rb < RBO; ++rb) {
+      const v8bf ah = ld8bf(Bh + so + rb * 8), al = ld8bf(Bl + so + rb * 8);
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        acc[rb][ct] = mfbf(ah, bh[ct], acc[rb][ct]);
+        acc[rb][ct] = mfbf(ah, bl[ct], acc[rb][ct]);
+        acc[rb][ct] = mfbf(al, bh[ct], acc[rb][ct]);
+      }
+    }
+  }
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) {
+    if (!cc.ok[ct]) continue;
+    const int box = a.tile_box[tile * a.TB + cc.slot[ct]];
+    if (box < 0) continue;
+    double* dst = a.out + ((int64_t)box * a.nvec + cc.v[ct]) * a.k;
+#pragma unroll
+    for (int rb = 0; rb < RBO; ++rb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = rb * 16 + 4 * g4 + i;
+        if (row < a.k) dst[row] = a.scale * (double)acc[rb][ct][i];
+      }
+  }
+}
+
+// q~ (FP64, [box][v][k]) -> padded [box][v][kp] bf16 high and low parts
+__global__ void pad_split_kernel(const double* __restrict__ in, int k, int64_t ncols, int kp,
+                                 __bf16* __restrict__ hi, __bf16* __restrict__ lo) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= ncols * kp) return;
+  const int64_t col = i / kp;
+  const int r = (int)(i - col * kp);
+  const float x = r < k ? (float)in[col * k + r] : 0.f;
+  const __bf16 h = (__bf16)x;
+  hi[i] = h;
+  lo[i] = (__bf16)(x - (float)h);
+}
+
 // q~ (FP64, [box][v][k]) -> padded [box][v][kp] in T
 template <typename T>
 __global__ void pad_convert_kernel(const double* __restrict__ in, int k, int64_t ncols, int kp,
@@ -421,6 +773,44 @@ hipError_t launch_blas_m2l(const BlasM2L& a, int mode, bool two_stage, hipStream
     if (two_stage) blas_m2l_bf16_kernel<true><<<grid, block, 0, stream>>>(a);
     else blas_m2l_bf16_kernel<false><<<grid, block, 0, stream>>>(a);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_blas_stacked(const BlasStack& a, hipStream_t stream) {
+  if (a.ntiles == 0) return hipSuccess;
+  if (a.C > 128 || a.Rpad % 128 != 0 || a.Rs > a.Rpad || a.kp % (a.mode == 2 ? 32 : 16) != 0 ||
+      a.rbo * 16 < a.kp || a.kp < a.k || (a.mode == 2 && a.Rs % 8 != 0))
+    return hipErrorInvalidValue;
+  const int64_t nwork = a.ntiles * (a.Rpad / 128);
+  const dim3 grid_a((unsigned)(8 * ((nwork + 7) / 8))), grid_b((unsigned)(8 * ((a.ntiles + 7) / 8)));
+  const dim3 block(256);
+  if (a.mode == 0) stack_a_kernel<double><<<grid_a, block, 0, stream>>>(a);
+  else if (a.mode == 1) stack_a_kernel<float><<<grid_a, block, 0, stream>>>(a);
+  else stack_a_bf16_kernel<<<grid_a, block, 0, stream>>>(a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+#define KIFMM_STACK_B(RR)                                                        \
+  if (a.mode == 0) stack_b_kernel<double, RR><<<grid_b, block, 0, stream>>>(a);  \
+  else if (a.mode == 1) stack_b_kernel<float, RR><<<grid_b, block, 0, stream>>>(a); \
+  else stack_b_bf16_kernel<RR><<<grid_b, block, 0, stream>>>(a);
+  switch (a.rbo) {
+    case 2: KIFMM_STACK_B(2) break;
+    case 4: KIFMM_STACK_B(4) break;
+    case 6: KIFMM_STACK_B(6) break;
+    case 8: KIFMM_STACK_B(8) break;
+    case 10: KIFMM_STACK_B(10) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef KIFMM_STACK_B
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_split(const double* in, int k, int64_t ncols, int kp, void* hi, void* lo,
+                            hipStream_t stream) {
+  const int64_t n = ncols * kp;
+  if (n == 0) return hipSuccess;
+  pad_split_kernel<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(in, k, ncols, kp, (__bf16*)hi,
+                                                                    (__bf16*)lo);
   return hipGetLastError();
 }
 

@@ -144,6 +144,46 @@ struct BlasM2L {
 };
 // mode 0 FP64, 1 FP32, 2 BF16x3
 hipError_t launch_blas_m2l(const BlasM2L& a, int mode, bool two_stage, hipStream_t stream);
+// Stacked form of the two-stage BLAS-M2L (Section 3.2 with the per-t
+// products regrouped around the boxes).  Boxes are grouped by octant class
+// (key & 7); a class serves the same 189 transfer vectors as target and as
+// source.  Stage A, per source box sigma of class c:
+//     xi[sigma] = [Vbar'_t^T for the 189 t sigma serves, stacked] q~[sigma]
+// (Rs rows per box and vector, each t's k_t rows padded to 4 (8 for
+// BF16x3)), one GEMM per class over all its boxes.  Stage B, per target box
+// tau of class c:
+//     out[tau] = [Ubar_t for the 189 t of tau, side by side] . xi-rows of
+// the sources tau + t (gathered), one GEMM per class with K = the class's
+// stacked rows.  Each (sigma, t) block of xi is read by exactly one target.
+struct BlasStack {
+  int mode;                   // 0 FP64, 1 FP32, 2 BF16x3
+  int k, kp;                  // compressed rank; padded (K of Stage A, M of Stage B)
+  int nvec, TB, C;            // vectors, boxes per tile, columns per tile (TB * nvec <= 128)
+  int64_t ntiles;
+  const int32_t* tile_box;    // [ntiles][TB], -1 padded
+  const int32_t* tile_class;  // [ntiles] octant class of the tile's boxes
+  const int32_t* tile_src;    // [ntiles][J][TB] source box of transfer vector j, -1 if none
+  int J;                      // transfer vectors per class (189)
+  int Rs;                     // xi rows per (box, vector)
+  int Rpad;                   // Stage A operator rows per class (Rs rounded up to 128)
+  int nsteps;                 // Stage B K steps per class (4 rows; 32 for BF16x3)
+  int rbo;                    // Stage B operator row blocks of 16 (kp / 16)
+  const void* A_hi;           // Stage A operators [8][Rpad][kp] (BF16x3: high parts)
+  const void* A_lo;           //   BF16x3 low parts
+  const void* B_hi;           // Stage B operators in MFMA lane order (see device.hip)
+  const void* B_lo;
+  const int32_t* info;        // [8][groups][2]: (j, first xi row) per row group of Stage B's K
+  const void* q_hi;           // padded compressed multipoles [box][v][kp] (BF16x3: high parts)
+  const void* q_lo;           //   BF16x3 low parts
+  void* xi_hi;                // [box][Rs][v] (BF16x3: [box][Rs / 8][v][8] high parts)
+  void* xi_lo;                //   BF16x3 low parts
+  double* out;                // [box][v][k]
+  double scale;
+};
+hipError_t launch_blas_stacked(const BlasStack& a, hipStream_t stream);
+// q~ [col][k] FP64 -> [col][kp] zero-padded bf16 high and low parts
+hipError_t launch_pad_split(const double* in, int k, int64_t ncols, int kp, void* hi, void* lo,
+                            hipStream_t stream);
 // q~ [col][k] FP64 -> [col][kp] zero-padded, FP64 or FP32
 hipError_t launch_pad_convert(const double* in, int k, int64_t ncols, int kp, bool fp64, void* out,
                               hipStream_t stream);

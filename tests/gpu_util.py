@@ -10,12 +10,14 @@ def say(msg):
 
 
 def evaluate(K, pts, q, depth, order, m2l, prec, tgt=None, origin=(0, 0, 0), width=1.0,
-             tol=0.0, tol_dir=-1.0, ld_pad=0):
+             tol=0.0, tol_dir=-1.0, ld_pad=0, tune=None):
     import torch
     f = K.KiFMM(order, depth, m2l=m2l, prec=prec, origin=origin, width=width, svd_rel_tol=tol,
                 svd_rel_tol_dir=tol_dir)
     f.set_points(pts, tgt)
     f.precompute()
+    if tune:
+        f.set_tuning(**tune)
     dt = torch.float64 if prec == "fp64" else torch.float32
     n_src = pts.shape[0]
     n_tgt = n_src if tgt is None else tgt.shape[0]

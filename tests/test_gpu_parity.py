@@ -102,11 +102,14 @@ def test_fft_full_size_sampled(prec, gate):
 
 @pytest.mark.parametrize("prec,gate", [("fp64", FP64_GATE), ("fp32", FP32_GATE), ("bf16x3", FP32_GATE)])
 @pytest.mark.parametrize("nvec", [1, 3])
-def test_blas_fused_precisions(prec, gate, nvec):
+@pytest.mark.parametrize("form", [0, 1])
+def test_blas_fused_precisions(prec, gate, nvec, form):
+    """Both BLAS-M2L forms (0 stacked: two GEMM kernels over octant classes with
+    the intermediate in memory; 1 fused: one kernel per level)."""
     pts = workloads.uniform_cube(20000, 93)
     q = workloads.charges(20000, nvec, 94, "upm1")
-    say(f"case: blas {prec} tol 1e-6/1e-6 uniform 20k depth 3 p6 nvec {nvec}")
-    got, _ = evaluate(K, pts, q, 3, 6, "blas", prec, tol=1e-6, tol_dir=1e-6)
+    say(f"case: blas form {form} {prec} tol 1e-6/1e-6 uniform 20k depth 3 p6 nvec {nvec}")
+    got, _ = evaluate(K, pts, q, 3, 6, "blas", prec, tol=1e-6, tol_dir=1e-6, tune=dict(blas_form=form))
     ref = fmm.KiFMM(pts, pts, 3, 6, m2l="blas", svd_rel_tol=1e-6, svd_rel_tol_dir=1e-6).evaluate(q)
     check_parity(got, ref, E2E_GATES[prec], what="vs oracle (projected operator)")
 
@@ -126,17 +129,19 @@ def test_dense_reduced_precision_20k(prec, gate):
 @pytest.mark.parametrize("prec,gate", [("fp64", STAGE_GATES["fp64"]), ("fp32", (2e-6, 1e-5)),
                                        ("bf16x3", STAGE_GATES["bf16x3"])])
 @pytest.mark.parametrize("tol_dir", [1e-6, -1.0])
-def test_blas_stage_check_potentials(prec, gate, tol_dir):
+@pytest.mark.parametrize("form", [0, 1])
+def test_blas_stage_check_potentials(prec, gate, tol_dir, form):
     pts = workloads.sphere_surface(30000, 95)
     ora = fmm.KiFMM(pts, pts, 5, 5, origin=(-1, -1, -1), width=2.0, m2l="blas",
                     svd_rel_tol=1e-7, svd_rel_tol_dir=tol_dir)
     f = K.KiFMM(5, 5, m2l="blas", prec=prec, origin=(-1, -1, -1), width=2.0, svd_rel_tol=1e-7,
                 svd_rel_tol_dir=tol_dir).set_points(pts).precompute()
+    f.set_tuning(blas_form=form)
     rng = np.random.default_rng(96)
     for lev in (2, 4, 5):
         nb = len(ora.tree.levels[lev])
         mult = rng.standard_normal((nb, 5, ora.ns))
-        say(f"case: stage blas {prec} tol_dir {tol_dir} level {lev} boxes {nb} nvec 5")
+        say(f"case: stage blas form {form} {prec} tol_dir {tol_dir} level {lev} boxes {nb} nvec 5")
         out = f.stage_m2l(lev, torch.as_tensor(mult, device="cuda"))
         torch.cuda.synchronize()
         got = out.cpu().numpy()
@@ -197,16 +202,24 @@ def test_tuning_settings_agree_and_autotune(m2l, prec):
     f = K.KiFMM(order, depth, m2l=m2l, prec=prec, **kw).set_points(pts).precompute()
     qt = torch.as_tensor(q, dtype=dt, device="cuda")
     a = f.evaluate(qt).clone()
+    forms = {0: a}
     if m2l == "fft":
         settings = [dict(schedule=s, hadamard=h) for s in (0, 1) for h in (0, 1)]
     else:
-        settings = [dict(blas_tile=t) for t in (42, 21, 10, 5, 1)]
+        # both BLAS forms (stacked, fused), each at several tile widths: bit-identical
+        # within a form, the forms equal to rounding (same products, other order)
+        settings = [dict(blas_form=fm, blas_tile=t) for fm in (0, 1) for t in (42, 21, 10, 5, 1)]
     for st in settings:
         f.set_tuning(**st)
         b = f.evaluate(qt)
         torch.cuda.synchronize()
-        assert torch.equal(a, b), st
-    f.set_tuning(blas_tile=0, schedule=0, hadamard=0)
+        fm = st.get("blas_form", 0)
+        if fm not in forms:
+            forms[fm] = b.clone()
+            check_parity(b.double().cpu().numpy(), a.double().cpu().numpy(), E2E_GATES[prec],
+                         what=f"form {fm} vs form 0")
+        assert torch.equal(forms[fm], b), st
+    f.set_tuning(blas_tile=0, schedule=0, hadamard=0, blas_form=0)
     best = f.autotune(qt, reps=2)
     tuned = f.tuning()
     say(f"  autotune kept {tuned}, {best:.3f} ms")
@@ -216,10 +229,13 @@ def test_tuning_settings_agree_and_autotune(m2l, prec):
         if prec == "fp64":
             assert tuned["hadamard"] == 0
     else:
-        assert tuned["blas_tile"] in (42, 21, 10, 5)
+        assert tuned["blas_tile"] in (42, 21, 10, 5) and tuned["blas_form"] in (0, 1)
     c = f.evaluate(qt)
     torch.cuda.synchronize()
-    assert torch.equal(a, c)
+    assert torch.equal(forms[tuned.get("blas_form", 0)], c)
     if m2l == "fft":
         ref = fmm.KiFMM(pts, pts, depth, order).evaluate(q)
-        check_parity(c.double().cpu().numpy(), ref, E2E_GATES[prec])
+    else:
+        ref = fmm.KiFMM(pts, pts, depth, order, m2l="blas", svd_rel_tol=1e-6,
+                        svd_rel_tol_dir=1e-6).evaluate(q)
+    check_parity(c.double().cpu().numpy(), ref, E2E_GATES[prec])
