@@ -40,7 +40,21 @@ sys.path.insert(0, ROOT)
 METRIC = "M2L ms & GB/s, Laplace 1M pts p=6: mixed/batched vs FP64, rel err ≤1e-5"
 PEAK_HBM = 8.0e12           # bytes/s
 PEAK_MFMA = {"fp32": 157.3e12, "fp64": 78.6e12}
-PEAK_VALU_NOPK = {"fp32": 78.6e12, "fp64": 78.6e12}  # packed FP32 disabled in every build
+# Issue-slot model of the point kernels (bound "alu"): a SIMD issues one wave64
+# VALU instruction per 4 cycles (16 lanes a cycle), a transcendental one
+# (v_rsq_f32 / v_rsq_f64) per 16 cycles; 256 CUs x 4 SIMDs at 2.4 GHz.  VALU
+# instructions per interaction, counted in the inner loops of this build's
+# gfx950 assembly: near field (FP32 P2P) 42 + 4 v_rsq_f32 per 2 sources x 2
+# targets; P2M (FP64) 48 + 3 v_rsq_f64 per source x 3 check points; L2P
+# (FP64) 67 + 4 v_rsq_f64 per 2 equivalent points x 2 targets.
+SIMDS, CLOCK_HZ = 256 * 4, 2.4e9
+VALU_PER_PAIR = {"near_field": (42 / 4, 1.0), "p2m": (48 / 3, 1.0), "far_field": (67 / 4, 1.0)}
+
+
+def pair_peak(kind):
+    """Interactions per second at full VALU issue (the issue-slot model above)."""
+    v, t = VALU_PER_PAIR[kind]
+    return SIMDS * CLOCK_HZ * 64 / (4 * v + 16 * t)
 
 
 def log(msg):
@@ -518,7 +532,7 @@ def run_batch(K, torch, launches):
     t0 = time.perf_counter()
     b = K.Batch(items, autotune=True, reps=3)
     capture_s = time.perf_counter() - t0
-    kept = sorted({f.tuning()["hadamard"] for f, _, _ in items})
+    info = b.info()
     s = torch.cuda.current_stream()
     for _ in range(5):
         b.launch()
@@ -555,10 +569,11 @@ def run_batch(K, torch, launches):
            "points_per_s": round(total_pts / (p50 * 1e-3), 1),
            "eager_sequential_ms": round(eager_ms, 3),
            "setup_s": round(setup_s, 2), "autotune_and_capture_s": round(capture_s, 2),
-           "autotuned_hadamard_form": kept, "autotune_best_ms": round(b.best_ms, 3),
+           "launches_per_replay": info["launches"], "grouped_launches": info["grouped"],
+           "autotune_best_ms": round(b.best_ms, 3),
            "precision": "fp32 M2L, fp64 local accumulation", "m2l": "fft"}
     log(f"  batch: p50 {p50:.2f} ms, p99 {out['latency_ms_p99']:.2f} ms, eager sequential {eager_ms:.2f} ms, "
-        f"autotuned Hadamard form {kept}")
+        f"{info['launches']} launches per replay ({info['grouped']} grouped)")
     del items
     torch.cuda.empty_cache()
     return out
@@ -671,20 +686,19 @@ def main():
     for r in (roof_fwd, roof_inv):
         r["frac"] = r["achieved"] / r["peak"]
     near_s = tm["near_field"] * 1e-3
-    # 11 flops per interaction: 3 differences, r^2 (1 mul + 2 fma), one fma
-    # accumulate; the reciprocal square root is counted as one operation
-    p2p_flops = 12.0 * interactions
+    # interactions per second against the issue-slot peak (VALU_PER_PAIR)
     roof_leaf = {"kernel": "leaf_eval_kernel<float, float, 1, 1> (near field, P2P FP32)", "bound": "alu",
-                 "achieved": p2p_flops / near_s / 1e12, "peak": PEAK_VALU_NOPK["fp32"] / 1e12,
-                 "unit": "TFLOP/s",
+                 "achieved": interactions / near_s / 1e9, "peak": pair_peak("near_field") / 1e9,
+                 "unit": "Ginteractions/s",
                  "traffic": measured_traffic("paper_2408_07436_amd/csrc/k_leaf.hip",
                                              "leaf_eval_f32_uniform1M_p6_traffic.json"),
-                 "per_launch": f"{interactions:.3e} P2P interactions x 12 operations "
-                               f"(11 flops + rsqrt), avg {tm['near_field']:.4f} ms"}
+                 "per_launch": f"{interactions:.3e} P2P interactions, avg {tm['near_field']:.4f} ms; peak: "
+                               f"{VALU_PER_PAIR['near_field'][0]} VALU + 1 v_rsq_f32 per interaction at "
+                               f"full issue"}
     roof_leaf["frac"] = roof_leaf["achieved"] / roof_leaf["peak"]
     # the passes around the M2L (mixed run): P2M and L2P on the FP64 VALU
-    # (12 operations per surface-point / point pair, as for P2P), the
-    # composite-operator GEMMs of the upward and downward passes on FP64 MFMA
+    # (issue-slot model, as for P2P), the composite-operator GEMMs of the
+    # upward and downward passes on FP64 MFMA
     ns = 6 * (w.order - 1) ** 2 + 2
     nb = [mix["f"].num_boxes(lev) for lev in range(w.depth + 1)]
     up_flops = 2.0 * ns * ns * nb[w.depth] * w.nvec + sum(
@@ -693,15 +707,16 @@ def main():
         2.0 * 8 * ns * ns * nb[lev - 1] * w.nvec for lev in range(3, w.depth + 1))
     surf_pairs = float(ns) * w.n
     roof_p2m = {"kernel": "p2m_kernel (FP64, leaf check potentials)", "bound": "alu",
-                "achieved": 12.0 * surf_pairs / (tm["p2m"] * 1e-3) / 1e12,
-                "peak": PEAK_VALU_NOPK["fp64"] / 1e12, "unit": "TFLOP/s", "traffic": None,
-                "per_launch": f"{surf_pairs:.3e} (check point, source) pairs x 12 operations, "
-                              f"avg {tm['p2m']:.4f} ms"}
+                "achieved": surf_pairs / (tm["p2m"] * 1e-3) / 1e9,
+                "peak": pair_peak("p2m") / 1e9, "unit": "Ginteractions/s", "traffic": None,
+                "per_launch": f"{surf_pairs:.3e} (check point, source) pairs, avg {tm['p2m']:.4f} ms; "
+                              f"peak: {VALU_PER_PAIR['p2m'][0]} VALU + 1 v_rsq_f64 per pair"}
     roof_l2p = {"kernel": "leaf_eval_kernel<float, float, 1, 2> (far field, L2P FP64)", "bound": "alu",
-                "achieved": 12.0 * surf_pairs / (tm["far_field"] * 1e-3) / 1e12,
-                "peak": PEAK_VALU_NOPK["fp64"] / 1e12, "unit": "TFLOP/s", "traffic": None,
-                "per_launch": f"{surf_pairs:.3e} (target, equivalent point) pairs x 12 operations, "
-                              f"avg {tm['far_field']:.4f} ms"}
+                "achieved": surf_pairs / (tm["far_field"] * 1e-3) / 1e9,
+                "peak": pair_peak("far_field") / 1e9, "unit": "Ginteractions/s", "traffic": None,
+                "per_launch": f"{surf_pairs:.3e} (target, equivalent point) pairs, avg "
+                              f"{tm['far_field']:.4f} ms; peak: {VALU_PER_PAIR['far_field'][0]} VALU + "
+                              f"1 v_rsq_f64 per pair"}
     up_gemm_ms = tm["upward"] - tm["p2m"]
     roof_up = {"kernel": "gemm64_kernel, upward pass (leaf pseudo-inverse, M2M with it folded in)",
                "bound": "mfma", "achieved": up_flops / (up_gemm_ms * 1e-3) / 1e12,

@@ -393,25 +393,38 @@ kifmm_status kifmm_autotune(kifmm_handle* h, const void* q_dev, int64_t ldq, int
 
 /* ---- batches of independent problems ------------------------------------ */
 
-/* A batch replays the evaluates of n independent, precomputed handles with
- * one graph launch (many problems of uneven sizes served together).
- * kifmm_batch_create runs every evaluate once eagerly on hip_stream (which
- * finishes all lazy device setup), then records them into one HIP graph:
- * problem i is captured on its own forked stream, so the problems are
- * independent branches of the graph.  The device buffers q_dev[i] /
- * phi_dev[i] (layout and types as in kifmm_evaluate, n_vec[i] vectors,
- * leading dimensions ldq[i] / ldphi[i]) are captured by address: they must
- * stay valid, and a launch reads the charges they hold at that time.  A
- * handle may appear at most once; handles must not be evaluated or changed
- * while a batch that holds them is alive.  EINVAL: bad arguments or a
- * repeated handle; ESTATE: a handle without points or operators. */
+/* A batch evaluates n independent, precomputed handles (many problems of
+ * uneven sizes, orders, depths and vector counts, served together; the
+ * multiple right-hand sides of Section 3.2 within each) with one graph
+ * launch of grouped launches.  kifmm_batch_create runs every evaluate once
+ * eagerly on hip_stream (which finishes all lazy device setup), records each
+ * problem's serial schedule (charge gather, P2M, pseudo-inverses, M2M by
+ * level, M2L of every level, downward steps by level, leaf evaluation), and
+ * merges the launches of equal stage, kernel and instance across the
+ * problems into one launch each: workgroup b of such a launch runs the part
+ * of one problem's kernel that workgroup b - offset of that problem's own
+ * launch would run, so every problem's potentials are those of its own
+ * serial evaluate (the FP32 FFT-M2L Hadamard step of a grouped launch runs
+ * one workgroup per frequency over all its items; every work split gives
+ * the same potentials).  The grouped launches, a few dozen
+ * for a batch of any size, are captured into one HIP graph.  The device
+ * buffers q_dev[i] / phi_dev[i] (layout and types as in kifmm_evaluate,
+ * n_vec[i] vectors, leading dimensions ldq[i] / ldphi[i]) are the ones
+ * kifmm_batch_launch uses; kifmm_batch_evaluate takes others per launch.
+ * A handle may appear at most once.  While a batch holds a handle, calls
+ * that would free or rebuild its device buffers (more vectors, other tile
+ * knobs, set_points, precompute, update_points, destroy) return ESTATE.
+ * EINVAL: bad arguments or a repeated handle; ESTATE: a handle without
+ * points or operators; ENOMEM / EDEVICE: the job buffer or the capture. */
 typedef struct kifmm_batch kifmm_batch;
 kifmm_status kifmm_batch_create(kifmm_handle* const* handles, int32_t n, const void* const* q_dev,
                                 const int64_t* ldq, const int32_t* n_vec, void* const* phi_dev,
                                 const int64_t* ldphi, void* hip_stream, kifmm_batch** out);
 /* Autotuned batch: for each candidate knob setting that applies to the
- * batch's handles (FP32 FFT-M2L: both Hadamard forms; BLAS / dense: tile
- * widths (128 / n_vec[i]) >> k, k = 0..3), sets the knobs of every handle,
+ * batch's handles (BLAS / dense: tile widths (128 / n_vec[i]) >> k,
+ * k = 0..3, times the two BLAS-M2L forms where directional recompression
+ * is on; a batch of FFT-M2L problems has one setting, since the schedule
+ * and Hadamard knobs do not apply to grouped launches), sets the knobs of every handle,
  * builds the batch as kifmm_batch_create does, times one warm-up and `reps`
  * (1..100) launches on hip_stream, and destroys it; then builds the batch
  * with the fastest setting into *out, leaves that setting in the handles and
@@ -423,8 +436,22 @@ kifmm_status kifmm_batch_autotune(kifmm_handle* const* handles, int32_t n,
                                   const int32_t* n_vec, void* const* phi_dev,
                                   const int64_t* ldphi, void* hip_stream, int32_t reps,
                                   kifmm_batch** out, double* best_ms);
-/* Launch the recorded graph on hip_stream (asynchronous). */
+/* Launch the recorded graph on hip_stream (asynchronous), with the charge
+ * and potential buffers given at creation (their current contents). */
 kifmm_status kifmm_batch_launch(kifmm_batch* batch, void* hip_stream);
+/* Launch the graph on hip_stream with other buffers: q_dev[i] / phi_dev[i]
+ * replace problem i's charge and potential buffers (same types, vector
+ * counts and leading dimensions as at creation; device pointers owned by
+ * the caller).  The buffer addresses are copied into the batch's device
+ * job table on hip_stream, ordered after earlier launches on that stream:
+ * launches of one batch on several streams at once race.  EINVAL: null
+ * arguments. */
+kifmm_status kifmm_batch_evaluate(kifmm_batch* batch, const void* const* q_dev,
+                                  void* const* phi_dev, void* hip_stream);
+/* info[0] problems, info[1] launches per replay, info[2] of which grouped
+ * (the rest are kernels without a grouped form, such as the BLAS-M2L
+ * kernels, one per problem and stage).  cap >= 3. */
+kifmm_status kifmm_batch_info(const kifmm_batch* batch, int64_t* info, int32_t cap);
 /* Destroy the graph and its capture streams (not the handles). */
 kifmm_status kifmm_batch_destroy(kifmm_batch* batch);
 

@@ -28,6 +28,7 @@ EXPORTS = [
     "kifmm_set_timing", "kifmm_timings", "kifmm_m2l_counts", "kifmm_get_tuning",
     "kifmm_set_tuning", "kifmm_autotune", "kifmm_update_points", "kifmm_batch_create", "kifmm_batch_autotune",
     "kifmm_batch_launch", "kifmm_batch_destroy", "kifmm_set_svd", "kifmm_evaluate_noalloc",
+    "kifmm_batch_evaluate", "kifmm_batch_info",
 ]
 NOALLOC_SCRATCH_BYTES = 256 << 20  # KIFMM_NOALLOC_SCRATCH_BYTES
 TUNE_KNOBS = ("blas_tile", "schedule", "hadamard", "blas_form")
@@ -101,6 +102,8 @@ def lib() -> ctypes.CDLL:
                                        ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(vp),
                                        ctypes.POINTER(i64), vp, i32, ctypes.POINTER(vp), dp]
     L.kifmm_batch_launch.argtypes = [vp, vp]
+    L.kifmm_batch_evaluate.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    L.kifmm_batch_info.argtypes = [vp, ctypes.POINTER(i64), i32]
     L.kifmm_batch_destroy.argtypes = [vp]
     for name in EXPORTS:
         if name not in ("kifmm_config_default", "kifmm_last_error"):
@@ -383,6 +386,27 @@ class Batch:
         import torch
         s = torch.cuda.current_stream() if stream is None else stream
         _check(lib().kifmm_batch_launch(self._b, ctypes.c_void_p(s.cuda_stream)))
+
+    def evaluate(self, qs, phis, stream=None):
+        """Launch with other charge / potential tensors (kifmm_batch_evaluate): one
+        (q, phi) per problem, shapes and dtypes as at creation."""
+        import torch
+        n = len(self._items)
+        assert len(qs) == n and len(phis) == n
+        for (f, q0, p0), q, p in zip(self._items, qs, phis):
+            assert q.is_cuda and p.is_cuda and q.dtype == f.dtype and p.dtype == f.dtype
+            assert q.shape == q0.shape and q.stride() == q0.stride()
+            assert p.shape == p0.shape and p.stride() == p0.stride()
+        qa = (ctypes.c_void_p * n)(*[q.data_ptr() for q in qs])
+        pa = (ctypes.c_void_p * n)(*[p.data_ptr() for p in phis])
+        s = torch.cuda.current_stream() if stream is None else stream
+        _check(lib().kifmm_batch_evaluate(self._b, qa, pa, ctypes.c_void_p(s.cuda_stream)))
+
+    def info(self) -> dict:
+        """Problems, launches per replay, and how many of those are grouped."""
+        a = np.zeros(3, dtype=np.int64)
+        _check(lib().kifmm_batch_info(self._b, _ptr(a, ctypes.c_int64), 3))
+        return dict(problems=int(a[0]), launches=int(a[1]), grouped=int(a[2]))
 
     def close(self):
         if getattr(self, "_b", None) is not None and self._b.value:

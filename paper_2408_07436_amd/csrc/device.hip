@@ -6,7 +6,9 @@
 #include <complex>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <utility>
 
 #include "internal.h"
@@ -126,6 +128,13 @@ struct DeviceState {
   hipEvent_t ev[8] = {};
   std::vector<hipEvent_t> lev_ev;  // [level][4] marks around the M2L kernels
   bool events = false;
+  // key of the shared FFT-M2L kernel spectra and twiddles (khat, twiddle)
+  // when this handle holds a reference to them
+  bool fft_shared = false;
+  std::tuple<int, int, int, uint64_t> fft_key{};
+  // set while a batch records this handle's serial schedule (nothing is
+  // enqueued then; see LaunchSink)
+  LaunchSink* sink = nullptr;
 };
 
 namespace {
@@ -554,6 +563,33 @@ static kifmm_status build_source_blocks(DeviceState* d, DevLevel& D, const Level
   return KIFMM_OK;
 }
 
+// FFT-M2L kernel spectra and twiddles depend only on the order, the radius
+// of the (coincident) upward-equivalent and downward-check surfaces and the
+// precision - the unit box's; a level's width is a scale of the inverse
+// transform - so the handles on one device share one copy (reference
+// counted): many problems with equal orders, as in a batch, read the same
+// operator data from L2 instead of one copy each.
+struct SharedFft {
+  int64_t refs = 0;
+  void* khat = nullptr;
+  void* twiddle = nullptr;
+};
+std::mutex g_fft_mu;
+std::map<std::tuple<int, int, int, uint64_t>, SharedFft> g_fft;
+
+void release_shared_fft(DeviceState* d) {
+  if (!d->fft_shared) return;
+  std::lock_guard<std::mutex> lock(g_fft_mu);
+  auto it = g_fft.find(d->fft_key);
+  if (it != g_fft.end() && --it->second.refs == 0) {
+    // teardown: failures are ignored
+    (void)hipFree(it->second.khat);
+    (void)hipFree(it->second.twiddle);
+    g_fft.erase(it);
+  }
+  d->fft_shared = false;
+}
+
 kifmm_status upload_all(kifmm_handle* h) {
   const Tree& t = h->tree;
   const Operators& op = h->op;
@@ -633,48 +669,78 @@ kifmm_status upload_all(kifmm_handle* h) {
 
   if (h->cfg.m2l == KIFMM_M2L_FFT) {
     const int n = op.n, F = op.F;
-    // twiddle matrix Wm[k][j] = exp(-2 pi i (k j mod n) / n), k < n, j < p
-    std::vector<double> tw(2 * (size_t)n * op.p);
-    for (int k = 0; k < n; ++k)
-      for (int j = 0; j < op.p; ++j) {
-        const int m = (k * j) % n;
-        tw[2 * ((size_t)k * op.p + j)] = std::cos(2.0 * M_PI * m / n);
-        tw[2 * ((size_t)k * op.p + j) + 1] = -std::sin(2.0 * M_PI * m / n);
-      }
-    // kernel spectra in sibling-cluster frequency order [f][26][8 i][8 j]
-    std::vector<double> kh((size_t)F * 26 * 64 * 2, 0.0);
-    for (int dd = 0; dd < 26; ++dd) {
-      int D[3];
-      direction_vector(dd, D);
-      for (int i = 0; i < 8; ++i)
-        for (int j = 0; j < 8; ++j) {
-          const int tx = 2 * D[0] + (j & 1) - (i & 1);
-          const int ty = 2 * D[1] + ((j >> 1) & 1) - ((i >> 1) & 1);
-          const int tz = 2 * D[2] + ((j >> 2) & 1) - ((i >> 2) & 1);
-          const int it = transfer_index(tx, ty, tz);
-          if (it < 0) continue;  // adjacent pair: zero kernel
-          for (int f = 0; f < F; ++f) {
-            const size_t o = ((((size_t)f * 26 + dd) * 8 + i) * 8 + j) * 2;
-            kh[o] = op.spectra[((size_t)it * F + f) * 2];
-            kh[o + 1] = op.spectra[((size_t)it * F + f) * 2 + 1];
-          }
-        }
-    }
-    if (d->fp64) {
-      double* p1;
-      double* p2;
-      KIFMM_TRY(upload(d, &p1, tw.data(), tw.size()));
-      KIFMM_TRY(upload(d, &p2, kh.data(), kh.size()));
-      d->twiddle = p1;
-      d->khat = p2;
+    uint64_t ai_bits;
+    std::memcpy(&ai_bits, &op.ai, sizeof ai_bits);
+    const auto key = std::make_tuple(d->device, op.p, d->fp64 ? 1 : 0, ai_bits);
+    std::lock_guard<std::mutex> lock(g_fft_mu);
+    auto found = g_fft.find(key);
+    if (found != g_fft.end()) {
+      ++found->second.refs;
+      d->khat = found->second.khat;
+      d->twiddle = found->second.twiddle;
+      d->fft_key = key;
+      d->fft_shared = true;
     } else {
-      std::vector<float> twf(tw.begin(), tw.end()), khf(kh.begin(), kh.end());
-      float* p1;
-      float* p2;
-      KIFMM_TRY(upload(d, &p1, twf.data(), twf.size()));
-      KIFMM_TRY(upload(d, &p2, khf.data(), khf.size()));
-      d->twiddle = p1;
-      d->khat = p2;
+      // twiddle matrix Wm[k][j] = exp(-2 pi i (k j mod n) / n), k < n, j < p
+      std::vector<double> tw(2 * (size_t)n * op.p);
+      for (int k = 0; k < n; ++k)
+        for (int j = 0; j < op.p; ++j) {
+          const int m = (k * j) % n;
+          tw[2 * ((size_t)k * op.p + j)] = std::cos(2.0 * M_PI * m / n);
+          tw[2 * ((size_t)k * op.p + j) + 1] = -std::sin(2.0 * M_PI * m / n);
+        }
+      // kernel spectra in sibling-cluster frequency order [f][26][8 i][8 j]
+      std::vector<double> kh((size_t)F * 26 * 64 * 2, 0.0);
+      for (int dd = 0; dd < 26; ++dd) {
+        int D[3];
+        direction_vector(dd, D);
+        for (int i = 0; i < 8; ++i)
+          for (int j = 0; j < 8; ++j) {
+            const int tx = 2 * D[0] + (j & 1) - (i & 1);
+            const int ty = 2 * D[1] + ((j >> 1) & 1) - ((i >> 1) & 1);
+            const int tz = 2 * D[2] + ((j >> 2) & 1) - ((i >> 2) & 1);
+            const int it = transfer_index(tx, ty, tz);
+            if (it < 0) continue;  // adjacent pair: zero kernel
+            for (int f = 0; f < F; ++f) {
+              const size_t o = ((((size_t)f * 26 + dd) * 8 + i) * 8 + j) * 2;
+              kh[o] = op.spectra[((size_t)it * F + f) * 2];
+              kh[o + 1] = op.spectra[((size_t)it * F + f) * 2 + 1];
+            }
+          }
+      }
+      // the shared copy is allocated outside the handle's own allocations
+      auto put = [](const void* host, size_t bytes, void** dev) -> kifmm_status {
+        *dev = nullptr;
+        hipError_t e = hipMalloc(dev, bytes);
+        if (e != hipSuccess) return fail(KIFMM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        e = hipMemcpy(*dev, host, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+          (void)hipFree(*dev);
+          *dev = nullptr;
+          return fail(KIFMM_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+        }
+        return KIFMM_OK;
+      };
+      SharedFft sh;
+      kifmm_status st;
+      if (d->fp64) {
+        st = put(tw.data(), tw.size() * sizeof(double), &sh.twiddle);
+        if (st == KIFMM_OK) st = put(kh.data(), kh.size() * sizeof(double), &sh.khat);
+      } else {
+        std::vector<float> twf(tw.begin(), tw.end()), khf(kh.begin(), kh.end());
+        st = put(twf.data(), twf.size() * sizeof(float), &sh.twiddle);
+        if (st == KIFMM_OK) st = put(khf.data(), khf.size() * sizeof(float), &sh.khat);
+      }
+      if (st != KIFMM_OK) {
+        if (sh.twiddle) (void)hipFree(sh.twiddle);
+        return st;
+      }
+      sh.refs = 1;
+      g_fft[key] = sh;
+      d->khat = sh.khat;
+      d->twiddle = sh.twiddle;
+      d->fft_key = key;
+      d->fft_shared = true;
     }
   } else {
     const int k = op.k;
@@ -818,10 +884,74 @@ kifmm_status ensure_work(kifmm_handle* h, int nvec) {
   return KIFMM_OK;
 }
 
+// Launches of the evaluate: enqueued at once, or recorded into d->sink as
+// jobs of grouped launches (the grouped forward takes one item group per
+// workgroup and the FP32 Hadamard one workgroup per frequency; both compute
+// every item as the launches here do).
 hipError_t gemm(DeviceState* d, Gemm64 g, hipStream_t s) {
   g.work = d->gemm_ws;
   g.work_elems = d->gemm_ws_elems;
-  return launch_gemm64(g, s);
+  if (!d->sink) return launch_gemm64(g, s);
+  GemmJob j;
+  const hipError_t e = plan_gemm64(g, j);
+  if (e != hipSuccess || j.split == 0) return e;
+  d->sink->add(kFamGemm, 0, j, gemm64_job_blocks(j));
+  if (j.split > 1) d->sink->add(kFamGemmReduce, 0, j, gemm64_reduce_blocks(j));
+  return hipSuccess;
+}
+
+hipError_t run_fft_forward(DeviceState* d, int p, const double* M, const int32_t* child, int64_t ncl,
+                           int nvec, void* Qhat, hipStream_t s) {
+  if (!d->sink) return launch_fft_forward(p, d->fp64, M, child, ncl, nvec, d->lat2surf, d->twiddle, Qhat, s);
+  FwdArgs a;
+  int inst;
+  int64_t blocks;
+  const hipError_t e = plan_fft_forward(p, d->fp64, M, child, ncl, nvec, d->lat2surf, d->twiddle, Qhat,
+                                        false, a, inst, blocks);
+  if (e == hipSuccess && blocks > 0) d->sink->add(kFamFwd, inst, a, blocks);
+  return e;
+}
+
+hipError_t run_hadamard(DeviceState* d, int F, const DevLevel& D, int64_t ncl, int nvec, bool units,
+                        hipStream_t s) {
+  if (!d->sink)
+    return launch_hadamard(d->fp64, F, d->khat, D.Qhat, D.halo, D.hb_n, D.hb_tgt, D.hb_src, D.hb_list,
+                           D.hb_tbase, ncl, nvec, units, D.Phat, s);
+  HadBlockArgs ab;
+  HadGatherArgs ag;
+  int64_t blocks;
+  const hipError_t e = plan_hadamard(d->fp64, F, d->khat, D.Qhat, D.halo, D.hb_n, D.hb_tgt, D.hb_src,
+                                     D.hb_list, D.hb_tbase, ncl, nvec, 2, D.Phat, ab, ag, blocks);
+  if (e != hipSuccess || blocks == 0) return e;
+  if (d->fp64)
+    d->sink->add(kFamHad, 1, ag, blocks);
+  else
+    d->sink->add(kFamHad, 0, ab, blocks);
+  return hipSuccess;
+}
+
+hipError_t run_fft_inverse(DeviceState* d, int p, const void* Phat, const int32_t* child, int64_t ncl,
+                           int nvec, double scale, double* out, hipStream_t s) {
+  if (!d->sink)
+    return launch_fft_inverse(p, d->fp64, Phat, child, ncl, nvec, d->surf_lat, d->twiddle, scale, out, s);
+  InvArgs a;
+  int inst;
+  int64_t blocks;
+  const hipError_t e = plan_fft_inverse(p, d->fp64, Phat, child, ncl, nvec, d->surf_lat, d->twiddle,
+                                        scale, out, a, inst, blocks);
+  if (e == hipSuccess && blocks > 0) d->sink->add(kFamInv, inst, a, blocks);
+  return e;
+}
+
+// a launch without a grouped form: enqueued at once or recorded as is
+hipError_t run_single(DeviceState* d, std::function<hipError_t(hipStream_t)> f, hipStream_t s) {
+  if (!d->sink) return f(s);
+  d->sink->add_single(std::move(f));
+  return hipSuccess;
+}
+
+void stage_mark(DeviceState* d, int phase, int level) {
+  if (d->sink) d->sink->stage(phase, level);
 }
 
 // Apply a unit-box pseudo-inverse V (Ut phi) scaled by the box width w:
@@ -853,16 +983,12 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
     const int64_t nc = d->lv[l - 1].n;
     const int32_t* child = d->lv[l - 1].child;
     // spectra of the nc clusters and of the empty cluster behind them
-    KIFMM_LAUNCH(launch_fft_forward(op.p, d->fp64, in, child, nc + 1, nvec, d->lat2surf,
-                                    d->twiddle, D.Qhat, s));
+    KIFMM_LAUNCH(run_fft_forward(d, op.p, in, child, nc + 1, nvec, D.Qhat, s));
     if (mark) KIFMM_HIP(hipEventRecord(mark[1], s));
-    KIFMM_LAUNCH(launch_hadamard(d->fp64, op.F, d->khat, D.Qhat, D.halo, D.hb_n, D.hb_tgt,
-                                 D.hb_src, D.hb_list, D.hb_tbase, nc, nvec,
-                                 h->tune[KIFMM_TUNE_HADAMARD] == 1, D.Phat, s));
+    KIFMM_LAUNCH(run_hadamard(d, op.F, D, nc, nvec, h->tune[KIFMM_TUNE_HADAMARD] == 1, s));
     if (mark) KIFMM_HIP(hipEventRecord(mark[2], s));
     const double scale = 1.0 / ((double)op.n * op.n * op.n * D.w);  // 1 / (n^3 w)
-    KIFMM_LAUNCH(launch_fft_inverse(op.p, d->fp64, D.Phat, child, nc, nvec, d->surf_lat,
-                                    d->twiddle, scale, out, s));
+    KIFMM_LAUNCH(run_fft_inverse(d, op.p, D.Phat, child, nc, nvec, scale, out, s));
     if (mark) KIFMM_HIP(hipEventRecord(mark[3], s));
     return KIFMM_OK;
   }
@@ -882,9 +1008,16 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
     void* qlo = nullptr;
     if (d->blas_mode == 2) {
       qlo = static_cast<char*>(d->qpad) + (size_t)D.n * nvec * d->kp * 2;
-      KIFMM_LAUNCH(launch_pad_split(qsrc, k, D.n * nvec, d->kp, d->qpad, qlo, s));
+      void* qhi = d->qpad;
+      const int kp = d->kp;
+      const int64_t ncols = D.n * nvec;
+      KIFMM_LAUNCH(run_single(d, [=](hipStream_t st) { return launch_pad_split(qsrc, k, ncols, kp, qhi, qlo, st); }, s));
     } else {
-      KIFMM_LAUNCH(launch_pad_convert(qsrc, k, D.n * nvec, d->kp, d->blas_mode == 0, d->qpad, s));
+      void* qp = d->qpad;
+      const int kp = d->kp;
+      const bool f64 = d->blas_mode == 0;
+      const int64_t ncols = D.n * nvec;
+      KIFMM_LAUNCH(run_single(d, [=](hipStream_t st) { return launch_pad_convert(qsrc, k, ncols, kp, f64, qp, st); }, s));
     }
     if (mark) KIFMM_HIP(hipEventRecord(mark[1], s));
     BlasStack b;
@@ -914,7 +1047,20 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
     b.xi_lo = d->xi_lo;
     b.out = d->tmp2;
     b.scale = 1.0 / D.w;
-    KIFMM_LAUNCH(launch_blas_stacked(b, s));
+    // levels with few tiles split Stage B's K steps over up to 16 workgroups
+    // per tile; the partial sums go to tmp (free once the compressed
+    // multipoles are padded), which holds maxn x n_vec x max(n_s, n_c, k)
+    if (D.ntiles > 0 && D.ntiles < 1024) {
+      int64_t maxn = 0;
+      for (const Level& L : h->tree.levels) maxn = std::max(maxn, L.n);
+      const int64_t kmax = std::max<int64_t>(std::max(op.ns, op.nc), k);
+      const int64_t want = std::min<int64_t>(16, (2048 + D.ntiles - 1) / D.ntiles);
+      const int64_t fits = (maxn * kmax) / std::max<int64_t>(1, D.n * (int64_t)k);
+      b.ksplit = (int)std::max<int64_t>(1, std::min(want, fits));
+    }
+    b.n_boxes = D.n;
+    b.partial = d->tmp;
+    KIFMM_LAUNCH(run_single(d, [=](hipStream_t st) { return launch_blas_stacked(b, st); }, s));
     if (mark) KIFMM_HIP(hipEventRecord(mark[2], s));
     Gemm64 g{d->Ublas, ncp, k, k, 1.0, d->tmp2, k, 1, nullptr, (int64_t)nvec * k, k,
              out, ncp, 1, nullptr, (int64_t)nvec * ncp, ncp, D.n, nvec, 0};
@@ -922,7 +1068,13 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
     if (mark) KIFMM_HIP(hipEventRecord(mark[3], s));
     return KIFMM_OK;
   }
-  KIFMM_LAUNCH(launch_pad_convert(qsrc, k, D.n * nvec, d->kp, d->blas_mode == 0, d->qpad, s));
+  {
+    void* qp = d->qpad;
+    const int kp = d->kp;
+    const bool f64 = d->blas_mode == 0;
+    const int64_t ncols = D.n * nvec;
+    KIFMM_LAUNCH(run_single(d, [=](hipStream_t st) { return launch_pad_convert(qsrc, k, ncols, kp, f64, qp, st); }, s));
+  }
   if (mark) KIFMM_HIP(hipEventRecord(mark[1], s));
   BlasM2L b;
   b.q = d->qpad;
@@ -944,7 +1096,11 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
   b.op_lo = d->op_lo;
   b.out = dense ? out : d->tmp2;
   b.scale = 1.0 / D.w;
-  KIFMM_LAUNCH(launch_blas_m2l(b, d->blas_mode, d->two_stage, s));
+  {
+    const int mode = d->blas_mode;
+    const bool two = d->two_stage;
+    KIFMM_LAUNCH(run_single(d, [=](hipStream_t st) { return launch_blas_m2l(b, mode, two, st); }, s));
+  }
   if (mark) KIFMM_HIP(hipEventRecord(mark[2], s));
   if (!dense) {
     // check potentials  Phi = U Phi~
@@ -962,6 +1118,7 @@ void destroy_device(DeviceState* d) {
   if (!d) return;
   // teardown: failures are ignored
   (void)hipSetDevice(d->device);
+  release_shared_fft(d);
   if (d->events)
     for (auto& e : d->ev) (void)hipEventDestroy(e);
   for (auto& e : d->lev_ev)
@@ -1047,12 +1204,25 @@ kifmm_status evaluate_launches(kifmm_handle* h, const void* q, int64_t ldq, int 
   // the far field last; serial uses the fused leaf kernel.
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   KIFMM_HIP(hipStreamIsCapturing(s, &cap));
-  const bool fork = fft && cap == hipStreamCaptureStatusNone;
+  // (a batch recording the schedule takes the serial one, untimed)
+  const bool fork = fft && cap == hipStreamCaptureStatusNone && !d->sink;
   const bool graph = fork && !timed && h->tune[KIFMM_TUNE_SCHEDULE] == 0;
   const bool phased = fork && timed;
   const DevLevel& leaf = d->lv[depth];
   const double ar_leaf = op.ao * 0.5 * leaf.w;
   auto leaf_pass = [&](int mode, hipStream_t st) -> kifmm_status {
+    if (d->sink) {
+      LeafArgs a;
+      int inst;
+      int64_t blocks;
+      plan_leaf_eval(d->tgt_xyz, d->src_xyz, leaf.w, d->qs, d->fp64, t.n_src, d->tgt_start, d->tgt_end,
+                     d->src_start, d->src_end, d->near_offs, d->near_src, d->leaf_centers, leaf.n,
+                     d->surf, ar_leaf, ns, d->local[depth], d->tgt_perm, phi, ldphi, nvec, mode, a,
+                     inst, blocks);
+      if (inst < 0) return fail(KIFMM_EINVAL, "bad leaf-pass mode");
+      if (blocks > 0) d->sink->add(kFamLeaf, inst, a, blocks);
+      return KIFMM_OK;
+    }
     KIFMM_LAUNCH(launch_leaf_eval(d->tgt_xyz, d->src_xyz, leaf.w, d->qs, d->fp64, t.n_src,
                                   d->tgt_start, d->tgt_end, d->src_start, d->src_end, d->near_offs,
                                   d->near_src, d->leaf_centers, leaf.n, d->surf, ar_leaf, ns,
@@ -1060,7 +1230,20 @@ kifmm_status evaluate_launches(kifmm_handle* h, const void* q, int64_t ldq, int 
     return KIFMM_OK;
   };
 
-  KIFMM_LAUNCH(launch_gather(q, ldq, d->src_perm, t.n_src, nvec, d->fp64, d->qs, s));
+  stage_mark(d, 0, 0);
+  if (d->sink) {
+    GatherArgs a{q, ldq, d->src_perm, t.n_src, nvec, d->qs};
+    d->sink->add(kFamGather, d->fp64 ? 1 : 0, a, (t.n_src + 255) / 256 * nvec);
+    // the near field on a branch of its own from the sorted charges on (its
+    // raw sums, completed by the far field at the end: near then far gives
+    // the fused kernel's result bit for bit)
+    d->sink->side = true;
+    stage_mark(d, 7, 0);
+    KIFMM_TRY(leaf_pass(1, s));
+    d->sink->side = false;
+  } else {
+    KIFMM_LAUNCH(launch_gather(q, ldq, d->src_perm, t.n_src, nvec, d->fp64, d->qs, s));
+  }
   if (graph) {
     // The near field needs only the sorted charges: it runs on its own
     // stream, concurrently with the upward, M2L and downward passes, and
@@ -1073,8 +1256,19 @@ kifmm_status evaluate_launches(kifmm_handle* h, const void* q, int64_t ldq, int 
   }
   // upward pass
   if (timed) KIFMM_HIP(hipEventRecord(d->ev[6], s));
-  KIFMM_LAUNCH(launch_p2m(d->src_xyz, d->qs, d->fp64, t.n_src, d->src_start, d->src_end,
-                          d->leaf_centers, leaf.n, d->surf_c, ar_leaf, nc, nvec, d->phi, s));
+  stage_mark(d, 1, 0);
+  if (d->sink) {
+    P2MArgs a;
+    int inst;
+    int64_t blocks;
+    plan_p2m(d->src_xyz, d->qs, d->fp64, t.n_src, d->src_start, d->src_end, d->leaf_centers, leaf.n,
+             d->surf_c, ar_leaf, nc, nvec, d->phi, a, inst, blocks);
+    if (blocks > 0) d->sink->add(kFamP2M, inst, a, blocks);
+  } else {
+    KIFMM_LAUNCH(launch_p2m(d->src_xyz, d->qs, d->fp64, t.n_src, d->src_start, d->src_end,
+                            d->leaf_centers, leaf.n, d->surf_c, ar_leaf, nc, nvec, d->phi, s));
+  }
+  stage_mark(d, 2, 0);
   if (timed) KIFMM_HIP(hipEventRecord(d->ev[7], s));
   // FP64: two-factor pseudo-inverses after each M2M (Section 2.1.1); the
   // reduced-precision modes apply the composite operators (M2M with the
@@ -1156,7 +1350,10 @@ kifmm_status evaluate_launches(kifmm_handle* h, const void* q, int64_t ldq, int 
     KIFMM_HIP(hipStreamWaitEvent(s, d->near_ev, 0));
     return leaf_pass(2, s);
   }
-  for (int l = depth - 1; l >= 2; --l) KIFMM_TRY(m2m_level(l, s));
+  for (int l = depth - 1; l >= 2; --l) {
+    stage_mark(d, 3, 20 - l);
+    KIFMM_TRY(m2m_level(l, s));
+  }
   if (timed) KIFMM_HIP(hipEventRecord(d->ev[1], s));
   if (phased) {
     // M2L of all levels, concurrently: the coarse levels on side streams
@@ -1172,8 +1369,13 @@ kifmm_status evaluate_launches(kifmm_handle* h, const void* q, int64_t ldq, int 
     for (int l = 2; l <= depth; ++l) KIFMM_TRY(down_level(l, d->lv[l].chk, s));
   } else {
     for (int l = 2; l <= depth; ++l) {
+      // recorded: the FFT-M2L of all levels in one stage (each level has
+      // its own buffers); other forms share phi and tmp buffers across
+      // levels, so their M2L stays in the level's downward stage
       double* chk = fft ? d->lv[l].chk : d->phi;
+      stage_mark(d, fft ? 4 : 5, fft ? 0 : l);
       KIFMM_TRY(m2l_level(h, l, d->mult[l], chk, nvec, s, timed));
+      if (fft) stage_mark(d, 5, l);
       KIFMM_TRY(down_level(l, chk, s));
     }
   }
@@ -1183,7 +1385,8 @@ kifmm_status evaluate_launches(kifmm_handle* h, const void* q, int64_t ldq, int 
     KIFMM_HIP(hipEventRecord(d->ev[5], s));
     KIFMM_TRY(leaf_pass(2, s));
   } else {
-    KIFMM_TRY(leaf_pass(0, s));
+    stage_mark(d, 6, 0);
+    KIFMM_TRY(leaf_pass(d->sink ? 2 : 0, s));
   }
   if (timed) {
     KIFMM_HIP(hipEventRecord(d->ev[3], s));
@@ -1236,6 +1439,24 @@ kifmm_status device_evaluate(kifmm_handle* h, const void* q, int64_t ldq, int nv
                              int64_t ldphi, hipStream_t s) {
   KIFMM_TRY(device_ready(h, nvec));
   return evaluate_launches(h, q, ldq, nvec, phi, ldphi, s);
+}
+
+// Record one evaluate's serial schedule into sink (nothing is enqueued):
+// the device state, work buffers and tiles must already exist (a previous
+// evaluate with the same vector count and knobs).
+kifmm_status device_record(kifmm_handle* h, const void* q, int64_t ldq, int nvec, void* phi,
+                           int64_t ldphi, LaunchSink* sink, hipStream_t s) {
+  DeviceState* d = h->dev;
+  if (!d || nvec > d->nvec_cap) return fail(KIFMM_ESTATE, "recording before the device buffers exist");
+  if (h->cfg.m2l != KIFMM_M2L_FFT && blas_tile_width(h, nvec) != d->tile_tb)
+    return fail(KIFMM_ESTATE, "recording with BLAS tiles of another width");
+  const bool timing = h->timing;
+  h->timing = false;
+  d->sink = sink;
+  const kifmm_status st = evaluate_launches(h, q, ldq, nvec, phi, ldphi, s);
+  d->sink = nullptr;
+  h->timing = timing;
+  return st;
 }
 
 // ---- evaluate without allocation ----------------------------------------------

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -129,6 +131,65 @@ kifmm_status rsvd_left_device(const double* A, int m, int n, const SvdOptions& o
                               std::vector<double>& U, std::vector<double>& s);
 
 kifmm_status precompute_operators(Operators& op, const kifmm_config& cfg, const SvdOptions& svd);
+
+// ---- recorded launches -----------------------------------------------------
+// A batch (batch.hip) runs the serial evaluate schedule of many problems as
+// grouped launches (kernels.h): with a sink set, the evaluate records every
+// launch instead of enqueuing it, with a stage key that orders the launches
+// of one problem; launches of several problems with equal keys, kernel
+// family and instance are independent and become one grouped launch.
+enum LaunchFamily {
+  kFamGather = 0, kFamP2M, kFamGemm, kFamGemmReduce, kFamFwd, kFamHad, kFamInv, kFamLeaf,
+  kFamSingle  // no grouped form: the recorded launch itself
+};
+struct LaunchRec {
+  int64_t key = 0;
+  int family = 0, inst = 0, problem = 0;
+  bool side = false;                              // on the near-field branch
+  int64_t blocks = 0;
+  std::vector<uint8_t> args;                      // the job's argument struct
+  std::function<hipError_t(hipStream_t)> single;  // kFamSingle
+};
+struct LaunchSink {
+  std::vector<LaunchRec> recs;
+  int problem = 0;
+  int64_t phase = 0, level = 0, step = 0;
+  // launches recorded while set form a branch beside the others (the near
+  // field, which needs only the sorted charges: stage 0 before it, the far
+  // field of stage 6 after it)
+  bool side = false;
+  // stages: 0 charge gather, 1 P2M, 2 leaf pseudo-inverse, 3 M2M (level
+  // key 20 - l), 4 FFT-M2L of every level, 5 M2L of other forms and the
+  // downward step of level l, 6 leaf evaluation; steps count launches
+  void stage(int64_t ph, int64_t lv) {
+    phase = ph;
+    level = lv;
+    step = 0;
+  }
+  int64_t next_key() { return (phase * 64 + level) * 4096 + step++; }
+  template <typename A>
+  void add(int family, int inst, const A& a, int64_t blocks) {
+    LaunchRec r;
+    r.key = next_key();
+    r.family = family;
+    r.inst = inst;
+    r.problem = problem;
+    r.side = side;
+    r.blocks = blocks;
+    r.args.resize(sizeof(A));
+    std::memcpy(r.args.data(), &a, sizeof(A));
+    recs.push_back(std::move(r));
+  }
+  void add_single(std::function<hipError_t(hipStream_t)> f) {
+    LaunchRec r;
+    r.key = next_key();
+    r.family = kFamSingle;
+    r.problem = problem;
+    r.side = side;
+    r.single = std::move(f);
+    recs.push_back(std::move(r));
+  }
+};
 
 // ---- device side -------------------------------------------------------------
 struct DeviceState;  // defined in device.hip

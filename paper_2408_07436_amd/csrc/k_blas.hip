@@ -470,11 +470,35 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_a_kernel(Bl
 // 4n .. 4n + 3 of the class's stacked K (one transfer vector j, whose xi
 // rows start at info[n].y).  Loads run ahead of the MFMAs: the table entry
 // three steps, the source box two steps, xi and the operator one step.
+// Work item of Stage B: (tile, part of its K steps), consecutive items per
+// XCD; the part's steps [n0, n1).
+struct StackPart {
+  int64_t tile;
+  int part, n0, n1;
+};
+__device__ inline bool stack_part(const BlasStack& a, int nst, StackPart& p) {
+  const int64_t w = xcd_item();
+  if (w >= a.ntiles * a.ksplit) return false;
+  p.tile = w / a.ksplit;
+  p.part = (int)(w - p.tile * a.ksplit);
+  p.n0 = (int)((int64_t)nst * p.part / a.ksplit);
+  p.n1 = (int)((int64_t)nst * (p.part + 1) / a.ksplit);
+  return true;
+}
+
+// Stage B's result for one column: the scaled sum (one part), or the raw
+// partial sum of this part (several parts; the reduction scales).
+__device__ inline double* stack_dst(const BlasStack& a, const StackPart& p, int box, int v) {
+  if (a.ksplit == 1) return a.out + ((int64_t)box * a.nvec + v) * a.k;
+  return a.partial + (((int64_t)p.part * a.n_boxes + box) * a.nvec + v) * a.k;
+}
+
 template <typename T, int RBO>
 __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_b_kernel(BlasStack a) {
   using V4 = typename std::conditional<sizeof(T) == 4, v4f, v4d>::type;
-  const int tile = xcd_tile(a.ntiles);
-  if (tile < 0) return;
+  StackPart sp;
+  if (!stack_part(a, a.nsteps, sp)) return;
+  const int64_t tile = sp.tile;
   const int cls = a.tile_class[tile];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int l16 = lane % 16, g4 = lane / 16;
@@ -484,7 +508,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_b_kernel(Bl
   const T* Bop = static_cast<const T*>(a.B_hi) + (int64_t)cls * a.nsteps * 64 * RBO + lane * RBO;
   const T* xi = static_cast<const T*>(a.xi_hi);
   const int64_t rs = a.Rs;
-  const int nst = a.nsteps;
+  const int nb = sp.n0, nst = sp.n1;  // steps of this part
   V4 acc[RBO][2];
 #pragma unroll
   for (int rb = 0; rb < RBO; ++rb)
@@ -498,9 +522,9 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_b_kernel(Bl
   };
   // pipeline registers: in2 = table entry of step n + 2, sb1 / row1 = source
   // boxes of step n + 1, x0 / o0 = xi and operator values of step n
-  int2 in2 = nst > 2 ? info[2] : make_int2(-1, 0);
-  const int2 in1 = nst > 1 ? info[1] : make_int2(-1, 0);
-  const int2 in0 = info[0];
+  int2 in2 = nb + 2 < nst ? info[nb + 2] : make_int2(-1, 0);
+  const int2 in1 = nb + 1 < nst ? info[nb + 1] : make_int2(-1, 0);
+  const int2 in0 = nb < nst ? info[nb] : make_int2(-1, 0);
   int sb1[2], row1 = in1.y;
   T x0[2], o0[RBO];
 #pragma unroll
@@ -509,8 +533,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_b_kernel(Bl
     x0[ct] = xval(source(in0, ct), in0.y, ct);
   }
 #pragma unroll
-  for (int rb = 0; rb < RBO; ++rb) o0[rb] = Bop[rb];
-  for (int n = 0; n < nst; ++n) {
+  for (int rb = 0; rb < RBO; ++rb) o0[rb] = nb < nst ? Bop[(int64_t)nb * 64 * RBO + rb] : T(0);
+  for (int n = nb; n < nst; ++n) {
     // issue the loads of the next steps
     const int2 in3 = n + 3 < nst ? info[n + 3] : make_int2(-1, 0);
     int sb2[2];
@@ -547,20 +571,31 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_b_kernel(Bl
     row1 = in2.y;
     in2 = in3;
   }
+  const double scale = a.ksplit == 1 ? a.scale : 1.0;
 #pragma unroll
   for (int ct = 0; ct < 2; ++ct) {
     if (!cc.ok[ct]) continue;
     const int box = a.tile_box[tile * a.TB + cc.slot[ct]];
     if (box < 0) continue;
-    double* dst = a.out + ((int64_t)box * a.nvec + cc.v[ct]) * a.k;
+    double* dst = stack_dst(a, sp, box, cc.v[ct]);
 #pragma unroll
     for (int rb = 0; rb < RBO; ++rb)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = rb * 16 + (sizeof(T) == 4 ? 4 * g4 + i : g4 + 4 * i);
-        if (row < a.k) dst[row] = a.scale * (double)acc[rb][ct][i];
+        if (row < a.k) dst[row] = scale * (double)acc[rb][ct][i];
       }
   }
+}
+
+// out = scale * (sum of the ksplit partial sums, in order)
+__global__ void stack_reduce_kernel(BlasStack a) {
+  const int64_t total = a.n_boxes * a.nvec * a.k;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  double sum = 0.0;
+  for (int p = 0; p < a.ksplit; ++p) sum += a.partial[(int64_t)p * total + i];
+  a.out[i] = a.scale * sum;
 }
 
 // x = hi + lo for four floats, round-to-nearest-even bf16 parts
@@ -648,8 +683,9 @@ __global__ __launch_bounds__(256, 2) void stack_a_bf16_kernel(BlasStack a) {
 // than its neighbours.  Operators [8][nsteps][64 lanes][RBO][8] hi / lo.
 template <int RBO>
 __global__ __launch_bounds__(256, 2) void stack_b_bf16_kernel(BlasStack a) {
-  const int tile = xcd_tile(a.ntiles);
-  if (tile < 0) return;
+  StackPart sp;
+  if (!stack_part(a, a.nsteps, sp)) return;
+  const int64_t tile = sp.tile;
   const int cls = a.tile_class[tile];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int l16 = lane % 16, g4 = lane / 16;
@@ -662,7 +698,7 @@ __global__ __launch_bounds__(256, 2) void stack_b_bf16_kernel(BlasStack a) {
   const __bf16* xh = static_cast<const __bf16*>(a.xi_hi);
   const __bf16* xl = static_cast<const __bf16*>(a.xi_lo);
   const int64_t rb8 = a.Rs / 8;
-  const int nst = a.nsteps;
+  const int nb = sp.n0, nst = sp.n1;  // steps of this part
   v4f acc[RBO][2];
 #pragma unroll
   for (int rb = 0; rb < RBO; ++rb)
@@ -678,9 +714,9 @@ __global__ __launch_bounds__(256, 2) void stack_b_bf16_kernel(BlasStack a) {
       o[ct] = sb >= 0 ? (((int64_t)sb * rb8 + in.y / 8) * a.nvec + cc.v[ct]) * 8 : -1;
     }
   };
-  int64_t o1[2];
-  offsets(0, o1);
-  for (int n = 0; n < nst; ++n) {
+  int64_t o1[2] = {-1, -1};
+  if (nb < nst) offsets(nb, o1);
+  for (int n = nb; n < nst; ++n) {
     v8bf bh[2], bl[2];
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) {
@@ -700,18 +736,19 @@ __global__ __launch_bounds__(256, 2) void stack_b_bf16_kernel(BlasStack a) {
       }
     }
   }
+  const double scale = a.ksplit == 1 ? a.scale : 1.0;
 #pragma unroll
   for (int ct = 0; ct < 2; ++ct) {
     if (!cc.ok[ct]) continue;
     const int box = a.tile_box[tile * a.TB + cc.slot[ct]];
     if (box < 0) continue;
-    double* dst = a.out + ((int64_t)box * a.nvec + cc.v[ct]) * a.k;
+    double* dst = stack_dst(a, sp, box, cc.v[ct]);
 #pragma unroll
     for (int rb = 0; rb < RBO; ++rb)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int row = rb * 16 + 4 * g4 + i;
-        if (row < a.k) dst[row] = a.scale * (double)acc[rb][ct][i];
+        if (row < a.k) dst[row] = scale * (double)acc[rb][ct][i];
       }
   }
 }
@@ -781,8 +818,10 @@ hipError_t launch_blas_stacked(const BlasStack& a, hipStream_t stream) {
   if (a.C > 128 || a.Rpad % 128 != 0 || a.Rs > a.Rpad || a.kp % (a.mode == 2 ? 32 : 16) != 0 ||
       a.rbo * 16 < a.kp || a.kp < a.k || (a.mode == 2 && a.Rs % 8 != 0))
     return hipErrorInvalidValue;
+  if (a.ksplit < 1 || (a.ksplit > 1 && !a.partial)) return hipErrorInvalidValue;
   const int64_t nwork = a.ntiles * (a.Rpad / 128);
-  const dim3 grid_a((unsigned)(8 * ((nwork + 7) / 8))), grid_b((unsigned)(8 * ((a.ntiles + 7) / 8)));
+  const int64_t nb_items = a.ntiles * a.ksplit;
+  const dim3 grid_a((unsigned)(8 * ((nwork + 7) / 8))), grid_b((unsigned)(8 * ((nb_items + 7) / 8)));
   const dim3 block(256);
   if (a.mode == 0) stack_a_kernel<double><<<grid_a, block, 0, stream>>>(a);
   else if (a.mode == 1) stack_a_kernel<float><<<grid_a, block, 0, stream>>>(a);
@@ -802,6 +841,12 @@ hipError_t launch_blas_stacked(const BlasStack& a, hipStream_t stream) {
     default: return hipErrorInvalidValue;
   }
 #undef KIFMM_STACK_B
+  if (a.ksplit > 1) {
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t total = a.n_boxes * a.nvec * a.k;
+    stack_reduce_kernel<<<(unsigned)((total + 255) / 256), 256, 0, stream>>>(a);
+  }
   return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@
 //    lattice points.
 // The transforms are direct sums along each axis with the n x p twiddle
 // matrix Wm[k][j] = exp(-2 pi i (k j mod n) / n).
+#include "group.h"
 #include "kernels.h"
 
 namespace kifmm {
@@ -113,11 +114,15 @@ template <typename T, int P> struct FftCfg {
 // imaginary parts.
 // Box item g is child g % 8 of row g / 8 (row = cluster * nvec + v).
 template <typename T, int P>
-__global__ __launch_bounds__((FftCfg<T, P>::threads)) void fft_forward_kernel(
-    const double* __restrict__ M, const int32_t* __restrict__ child, int64_t n_rows, int nvec,
-    const int16_t* __restrict__ lat2surf, const typename C2T<T>::type* __restrict__ Wm,
-    typename C2T<T>::type* __restrict__ Qhat) {
+__device__ __forceinline__ void fft_forward_body(const FwdArgs& a, int64_t blk, int64_t nblk) {
   using C2 = typename C2T<T>::type;
+  const double* __restrict__ M = a.M;
+  const int32_t* __restrict__ child = a.child;
+  const int64_t n_rows = a.n_rows;
+  const int nvec = a.nvec;
+  const int16_t* __restrict__ lat2surf = a.lat2surf;
+  const C2* __restrict__ Wm = static_cast<const C2*>(a.wm);
+  C2* __restrict__ Qhat = static_cast<C2*>(a.Qhat);
   using L = typename FftCfg<T, P>::L;
   constexpr int N = 2 * P - 1, H = P, NS = 6 * (P - 1) * (P - 1) + 2;
   constexpr int IT = FftCfg<T, P>::items, TH = FftCfg<T, P>::threads;
@@ -137,8 +142,8 @@ __global__ __launch_bounds__((FftCfg<T, P>::threads)) void fft_forward_kernel(
   // of a 128-byte line of Qhat meet in the same L2.
   constexpr int KL = (IT * NS + TH - 1) / TH;
   const int64_t n_groups = (n_rows * 8 + IT - 1) / IT;
-  const int64_t nwg = gridDim.x, per_xcd = nwg / 8;  // grid: a multiple of 8
-  const int64_t wg = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  const int64_t nwg = nblk, per_xcd = nwg / 8;  // grid: a multiple of 8
+  const int64_t wg = (blk % 8) * per_xcd + blk / 8;
   for (int t = tid; t < P * P * P; t += TH) l2s[t] = lat2surf[t];
   // MFMA operand A of the y and x stages: the real form of Wm, rows
   // (k, re/im), columns (j, re/im); lane (lc, lg) holds row lc, column lg of
@@ -317,11 +322,16 @@ __device__ inline C2 cmulc(C2 a, C2 b) {  // a * conj(b)
   return r;
 }
 template <typename T, int P, int ITEMS>
-__global__ __launch_bounds__(kInvThreads) void fft_inverse_kernel(
-    const typename C2T<T>::type* __restrict__ Phat, const int32_t* __restrict__ child,
-    int64_t n_rows, int nvec, const int16_t* __restrict__ surf_lat,
-    const typename C2T<T>::type* __restrict__ Wm, double scale, double* __restrict__ out) {
+__device__ __forceinline__ void fft_inverse_body(const InvArgs& a, int64_t blk) {
   using C2 = typename C2T<T>::type;
+  const C2* __restrict__ Phat = static_cast<const C2*>(a.Phat);
+  const int32_t* __restrict__ child = a.child;
+  const int64_t n_rows = a.n_rows;
+  const int nvec = a.nvec;
+  const int16_t* __restrict__ surf_lat = a.surf_lat;
+  const C2* __restrict__ Wm = static_cast<const C2*>(a.wm);
+  const double scale = a.scale;
+  double* __restrict__ out = a.out;
   constexpr int N = 2 * P - 1, H = P, NS = 6 * (P - 1) * (P - 1) + 2;
   __shared__ C2 b2[ITEMS][P][N][H];
   __shared__ C2 b1[ITEMS][P][P][H];
@@ -334,7 +344,7 @@ __global__ __launch_bounds__(kInvThreads) void fft_inverse_kernel(
   // consecutive rows on one XCD, so the two 64-byte halves of a 128-byte
   // line of Phat are fetched once, into the same L2
   const int64_t nwg = (n_rows * 8 + ITEMS - 1) / ITEMS, per_xcd = (nwg + 7) / 8;
-  const int64_t wg = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  const int64_t wg = (blk % 8) * per_xcd + blk / 8;
   if (wg >= nwg) return;
   const int64_t g0 = wg * ITEMS;
   for (int t = tid; t < 3 * NS; t += kInvThreads) sl[t] = surf_lat[t];
@@ -457,16 +467,21 @@ __device__ inline double4 load4(const double* p) {
 // so the gather needs no masking and the VALU work per MFMA stays small
 // (on gfx950 the VALU does not co-issue with the MFMA of the same wave).
 template <typename T>
-__global__ __launch_bounds__(kHadThreads) void hadamard_gather_kernel(
-    const typename C2T<T>::type* __restrict__ Khat, const T* __restrict__ Qhat,
-    const int32_t* __restrict__ halo, int64_t n_c, int nvec, int64_t n_rows, int n_chunks,
-    int tiles_per_wave, int64_t total_blocks, T* __restrict__ Phat) {
+__device__ __forceinline__ void hadamard_gather_body(const HadGatherArgs& a, int64_t b) {
   using C2 = typename C2T<T>::type;
   using V4 = typename V4T<T>::type;
   using T4 = typename Vec4T<T>::type;
+  const C2* __restrict__ Khat = static_cast<const C2*>(a.Khat);
+  const T* __restrict__ Qhat = static_cast<const T*>(a.Qhat);
+  const int32_t* __restrict__ halo = a.halo;
+  const int64_t n_c = a.n_c;
+  const int nvec = a.nvec;
+  const int64_t n_rows = a.n_rows;
+  const int n_chunks = a.n_chunks, tiles_per_wave = a.tiles_per_wave;
+  const int64_t total_blocks = a.total_blocks;
+  T* __restrict__ Phat = static_cast<T*>(a.Phat);
   constexpr int DC = HadChunk<T>::value;
   __shared__ T4 Bl[26][64];
-  const int64_t b = blockIdx.x;
   const int64_t per_xcd = (total_blocks + 7) / 8;
   const int64_t logical = (b % 8) * per_xcd + b / 8;  // consecutive work per XCD
   if (logical >= total_blocks) return;
@@ -573,17 +588,21 @@ static_assert(had_dir_bytes(0) == 0 && had_dir_bytes(25) == 2 * kHadSlotBias * k
 // direction's MFMAs.  Every source spectrum crosses the cache hierarchy
 // once per block, and the VALU work per MFMA stays small (on gfx950 the
 // VALU does not co-issue with the MFMA of the same wave).
-__global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_kernel(
-    const float2* __restrict__ Khat, const float* __restrict__ Qhat,
-    const int32_t* __restrict__ blk_tgt, const int32_t* __restrict__ blk_src,
-    const int32_t* __restrict__ blk_list, const int32_t* __restrict__ tbase, int n_items,
-    int nvec, int64_t n_rows, int64_t total_items, int64_t unit_len, int64_t n_units,
-    int64_t n_wgs, float* __restrict__ Phat) {
+__device__ __forceinline__ void hadamard_block_body(const HadBlockArgs& a, int64_t b, int64_t nblk) {
+  const float2* __restrict__ Khat = static_cast<const float2*>(a.Khat);
+  const float* __restrict__ Qhat = static_cast<const float*>(a.Qhat);
+  const int32_t* __restrict__ blk_tgt = a.blk_tgt;
+  const int32_t* __restrict__ blk_src = a.blk_src;
+  const int32_t* __restrict__ blk_list = a.blk_list;
+  const int32_t* __restrict__ tbase = a.tbase;
+  const int n_items = a.n_items, nvec = a.nvec;
+  const int64_t n_rows = a.n_rows, total_items = a.total_items, unit_len = a.unit_len;
+  const int64_t n_units = a.n_units, n_wgs = a.n_wgs;
+  float* __restrict__ Phat = static_cast<float*>(a.Phat);
   constexpr int kRow = kHadRowBytes / 16;  // LDS row stride in float4: 16 reals + padding
   constexpr int kBuf = kHadSrcMax * kRow + 4;  // + a 64-byte discard area
   __shared__ float4 As[2 * kBuf];
-  const int64_t b = blockIdx.x;
-  const int64_t per_xcd = gridDim.x / 8;  // grid: a multiple of 8
+  const int64_t per_xcd = nblk / 8;  // grid: a multiple of 8
   const int64_t logical = (b % 8) * per_xcd + b / 8;  // consecutive work per XCD
   if (logical >= n_wgs) return;
   const int tid = threadIdx.x;
@@ -758,6 +777,58 @@ __global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_kernel(
   }
 }
 
+// ---- kernels: the bodies above as plain and as grouped launches ------------
+// (scalar parameters: with the arguments as one by-value struct the compiler
+// kept 120 instead of 66 VGPRs at p = 6, FP32)
+template <typename T, int P>
+__global__ __launch_bounds__((FftCfg<T, P>::threads)) void fft_forward_kernel(
+    const double* __restrict__ M, const int32_t* __restrict__ child, int64_t n_rows, int nvec,
+    const int16_t* __restrict__ lat2surf, const void* __restrict__ wm, void* __restrict__ Qhat) {
+  const FwdArgs a{M, child, n_rows, nvec, lat2surf, wm, Qhat};
+  fft_forward_body<T, P>(a, blockIdx.x, gridDim.x);
+}
+template <typename T, int P>
+__global__ __launch_bounds__((FftCfg<T, P>::threads)) void fft_forward_group_kernel(
+    const FwdArgs* __restrict__ jobs, const int64_t* __restrict__ pre, int nj) {
+  int64_t b;
+  const int j = group_job(pre, nj, b);
+  const FwdArgs a = jobs[j];
+  fft_forward_body<T, P>(a, b, pre[j + 1] - pre[j]);
+}
+template <typename T, int P, int IT>
+__global__ __launch_bounds__(kInvThreads) void fft_inverse_kernel(InvArgs a) {
+  fft_inverse_body<T, P, IT>(a, blockIdx.x);
+}
+template <typename T, int P, int IT>
+__global__ __launch_bounds__(kInvThreads) void fft_inverse_group_kernel(const InvArgs* __restrict__ jobs,
+                                                                        const int64_t* __restrict__ pre,
+                                                                        int nj) {
+  int64_t b;
+  const InvArgs a = jobs[group_job(pre, nj, b)];
+  fft_inverse_body<T, P, IT>(a, b);
+}
+template <typename T>
+__global__ __launch_bounds__(kHadThreads) void hadamard_gather_kernel(HadGatherArgs a) {
+  hadamard_gather_body<T>(a, blockIdx.x);
+}
+template <typename T>
+__global__ __launch_bounds__(kHadThreads) void hadamard_gather_group_kernel(
+    const HadGatherArgs* __restrict__ jobs, const int64_t* __restrict__ pre, int nj) {
+  int64_t b;
+  const HadGatherArgs a = jobs[group_job(pre, nj, b)];
+  hadamard_gather_body<T>(a, b);
+}
+__global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_kernel(HadBlockArgs a) {
+  hadamard_block_body(a, blockIdx.x, gridDim.x);
+}
+__global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_group_kernel(
+    const HadBlockArgs* __restrict__ jobs, const int64_t* __restrict__ pre, int nj) {
+  int64_t b;
+  const int j = group_job(pre, nj, b);
+  const HadBlockArgs a = jobs[j];
+  hadamard_block_body(a, b, pre[j + 1] - pre[j]);
+}
+
 // Workgroups resident on the whole device for a kernel (occupancy x CUs).
 template <typename K>
 int64_t resident_wgs(K kernel, int threads) {
@@ -770,21 +841,29 @@ int64_t resident_wgs(K kernel, int threads) {
   return (int64_t)cus * per_cu;
 }
 
+// Forward workgroups: persistent (enough to fill the device once, each an
+// equal number of item groups) or, for grouped launches, one item group per
+// workgroup; a multiple of 8 for the XCD numbering.  -1 on failure.
 template <typename T, int P>
-hipError_t fwd_launch(const double* M, const int32_t* child, int64_t n_rows, int nvec,
-                      const int16_t* lat2surf, const void* wm, void* Qhat, hipStream_t s) {
-  using C2 = typename C2T<T>::type;
+int64_t fwd_blocks(int64_t n_rows, bool persistent) {
   constexpr int IT = FftCfg<T, P>::items, TH = FftCfg<T, P>::threads;
-  static const int64_t resident = resident_wgs(fft_forward_kernel<T, P>, TH);
-  if (resident < 1 || n_rows >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-  // enough persistent workgroups to fill the device once, each taking an
-  // equal number of item groups; a multiple of 8 for the XCD numbering
   const int64_t n_groups = (n_rows * 8 + IT - 1) / IT;
+  if (!persistent) return (n_groups + 7) / 8 * 8;
+  static const int64_t resident = resident_wgs(fft_forward_kernel<T, P>, TH);
+  if (resident < 1) return -1;
   const int64_t rounds = (n_groups + resident - 1) / resident;
-  const int64_t nwg = ((n_groups + rounds - 1) / rounds + 7) / 8 * 8;
-  fft_forward_kernel<T, P><<<(unsigned)nwg, TH, 0, s>>>(M, child, n_rows, nvec, lat2surf,
-                                                        (const C2*)wm, (C2*)Qhat);
-  return hipGetLastError();
+  return ((n_groups + rounds - 1) / rounds + 7) / 8 * 8;
+}
+
+template <typename T, int P>
+void fwd_go(const FwdArgs* one, const FwdArgs* jobs, const int64_t* pre, int nj, int64_t blocks,
+            hipStream_t s) {
+  constexpr int TH = FftCfg<T, P>::threads;
+  if (!jobs)
+    fft_forward_kernel<T, P><<<(unsigned)blocks, TH, 0, s>>>(one->M, one->child, one->n_rows, one->nvec,
+                                                             one->lat2surf, one->wm, one->Qhat);
+  else
+    fft_forward_group_kernel<T, P><<<(unsigned)blocks, TH, 0, s>>>(jobs, pre, nj);
 }
 
 // inverse items per workgroup, sized so the LDS stays within 48 KiB
@@ -796,68 +875,173 @@ template <typename T, int P> struct InvItems {
 };
 
 template <typename T, int P>
-hipError_t inv_launch(const void* Phat, const int32_t* child, int64_t n_rows, int nvec,
-                      const int16_t* surf_lat, const void* wm, double scale, double* out,
-                      hipStream_t s) {
-  using C2 = typename C2T<T>::type;
+int64_t inv_blocks(int64_t n_rows) {
   constexpr int IT = InvItems<T, P>::value;
-  if (n_rows >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-  const unsigned grid = (unsigned)(8 * (((n_rows * 8 + IT - 1) / IT + 7) / 8));
-  fft_inverse_kernel<T, P, IT><<<grid, kInvThreads, 0, s>>>((const C2*)Phat, child, n_rows, nvec,
-                                                          surf_lat, (const C2*)wm, scale, out);
+  return 8 * (((n_rows * 8 + IT - 1) / IT + 7) / 8);
+}
+
+template <typename T, int P>
+void inv_go(const InvArgs* one, const InvArgs* jobs, const int64_t* pre, int nj, int64_t blocks,
+            hipStream_t s) {
+  constexpr int IT = InvItems<T, P>::value;
+  if (!jobs)
+    fft_inverse_kernel<T, P, IT><<<(unsigned)blocks, kInvThreads, 0, s>>>(*one);
+  else
+    fft_inverse_group_kernel<T, P, IT><<<(unsigned)blocks, kInvThreads, 0, s>>>(jobs, pre, nj);
+}
+
+// p = 2..8 as a template argument
+#define KIFMM_SWITCH_P(p, CALL)                                                                  \
+  switch (p) {                                                                                   \
+    case 2: { constexpr int PP = 2; CALL; } break;                                               \
+    case 3: { constexpr int PP = 3; CALL; } break;                                               \
+    case 4: { constexpr int PP = 4; CALL; } break;                                               \
+    case 5: { constexpr int PP = 5; CALL; } break;                                               \
+    case 6: { constexpr int PP = 6; CALL; } break;                                               \
+    case 7: { constexpr int PP = 7; CALL; } break;                                               \
+    case 8: { constexpr int PP = 8; CALL; } break;                                               \
+    default: return hipErrorInvalidValue;                                                        \
+  }
+
+hipError_t fwd_dispatch(int inst, const FwdArgs* one, const FwdArgs* jobs, const int64_t* pre, int nj,
+                        int64_t blocks, hipStream_t s) {
+  if (blocks == 0) return hipSuccess;
+  if (blocks < 0 || blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  const bool fp64 = inst >= 16;
+  if (fp64) {
+    KIFMM_SWITCH_P(inst % 16, (fwd_go<double, PP>(one, jobs, pre, nj, blocks, s)))
+  } else {
+    KIFMM_SWITCH_P(inst % 16, (fwd_go<float, PP>(one, jobs, pre, nj, blocks, s)))
+  }
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t fwd_dispatch(int p, const double* M, const int32_t* child, int64_t n_rows, int nvec,
-                        const int16_t* l2s, const void* wm, void* Q, hipStream_t s) {
-  switch (p) {
-#define KIFMM_FWD(PP) \
-  case PP: return fwd_launch<T, PP>(M, child, n_rows, nvec, l2s, wm, Q, s);
-    KIFMM_FWD(2) KIFMM_FWD(3) KIFMM_FWD(4) KIFMM_FWD(5) KIFMM_FWD(6) KIFMM_FWD(7) KIFMM_FWD(8)
-#undef KIFMM_FWD
-    default: return hipErrorInvalidValue;
+hipError_t inv_dispatch(int inst, const InvArgs* one, const InvArgs* jobs, const int64_t* pre, int nj,
+                        int64_t blocks, hipStream_t s) {
+  if (blocks == 0) return hipSuccess;
+  if (blocks < 0 || blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  const bool fp64 = inst >= 16;
+  if (fp64) {
+    KIFMM_SWITCH_P(inst % 16, (inv_go<double, PP>(one, jobs, pre, nj, blocks, s)))
+  } else {
+    KIFMM_SWITCH_P(inst % 16, (inv_go<float, PP>(one, jobs, pre, nj, blocks, s)))
   }
+  return hipGetLastError();
 }
 
-template <typename T>
-hipError_t inv_dispatch(int p, const void* Ph, const int32_t* child, int64_t n_rows, int nvec,
-                        const int16_t* l2s, const void* wm, double scale, double* out, hipStream_t s) {
-  switch (p) {
-#define KIFMM_INV(PP) \
-  case PP: return inv_launch<T, PP>(Ph, child, n_rows, nvec, l2s, wm, scale, out, s);
-    KIFMM_INV(2) KIFMM_INV(3) KIFMM_INV(4) KIFMM_INV(5) KIFMM_INV(6) KIFMM_INV(7) KIFMM_INV(8)
-#undef KIFMM_INV
-    default: return hipErrorInvalidValue;
+hipError_t had_dispatch(bool fp64, const void* one, const void* jobs, const int64_t* pre, int nj,
+                        int64_t blocks, hipStream_t s) {
+  if (blocks == 0) return hipSuccess;
+  if (blocks < 0 || blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  if (fp64) {
+    if (!jobs)
+      hadamard_gather_kernel<double><<<(unsigned)blocks, kHadThreads, 0, s>>>(
+          *static_cast<const HadGatherArgs*>(one));
+    else
+      hadamard_gather_group_kernel<double><<<(unsigned)blocks, kHadThreads, 0, s>>>(
+          static_cast<const HadGatherArgs*>(jobs), pre, nj);
+  } else {
+    if (!jobs)
+      hadamard_block_kernel<<<(unsigned)blocks, kHadThreads, 0, s>>>(*static_cast<const HadBlockArgs*>(one));
+    else
+      hadamard_block_group_kernel<<<(unsigned)blocks, kHadThreads, 0, s>>>(
+          static_cast<const HadBlockArgs*>(jobs), pre, nj);
   }
+  return hipGetLastError();
 }
 
 }  // namespace
 
+hipError_t plan_fft_forward(int p, bool fp64, const double* M, const int32_t* child, int64_t n_clusters,
+                            int nvec, const int16_t* lat2surf, const void* wm, void* Qhat,
+                            bool persistent, FwdArgs& a, int& inst, int64_t& blocks) {
+  const int64_t n_rows = n_clusters * nvec;
+  a = FwdArgs{M, child, n_rows, nvec, lat2surf, wm, Qhat};
+  inst = (fp64 ? 16 : 0) + p;
+  blocks = 0;
+  if (n_rows == 0) return hipSuccess;
+  if (p < 2 || p > 8 || n_rows >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  if (fp64) {
+    switch (p) {
+#define KIFMM_FB(PP) case PP: blocks = fwd_blocks<double, PP>(n_rows, persistent); break;
+      KIFMM_FB(2) KIFMM_FB(3) KIFMM_FB(4) KIFMM_FB(5) KIFMM_FB(6) KIFMM_FB(7) KIFMM_FB(8)
+#undef KIFMM_FB
+    }
+  } else {
+    switch (p) {
+#define KIFMM_FB(PP) case PP: blocks = fwd_blocks<float, PP>(n_rows, persistent); break;
+      KIFMM_FB(2) KIFMM_FB(3) KIFMM_FB(4) KIFMM_FB(5) KIFMM_FB(6) KIFMM_FB(7) KIFMM_FB(8)
+#undef KIFMM_FB
+    }
+  }
+  return blocks < 0 ? hipErrorInvalidValue : hipSuccess;
+}
+
 hipError_t launch_fft_forward(int p, bool fp64, const double* M, const int32_t* child,
                               int64_t n_clusters, int nvec, const int16_t* lat2surf,
                               const void* wm, void* Qhat, hipStream_t stream) {
+  FwdArgs a;
+  int inst;
+  int64_t blocks;
+  hipError_t e = plan_fft_forward(p, fp64, M, child, n_clusters, nvec, lat2surf, wm, Qhat, true, a, inst,
+                                  blocks);
+  if (e != hipSuccess) return e;
+  return fwd_dispatch(inst, &a, nullptr, nullptr, 0, blocks, stream);
+}
+
+hipError_t launch_fft_forward_group(int inst, const FwdArgs* jobs, const int64_t* pre, int nj,
+                                    int64_t blocks, hipStream_t stream) {
+  return fwd_dispatch(inst, nullptr, jobs, pre, nj, blocks, stream);
+}
+
+hipError_t plan_fft_inverse(int p, bool fp64, const void* Phat, const int32_t* child, int64_t n_clusters,
+                            int nvec, const int16_t* surf_lat, const void* wm, double scale, double* out,
+                            InvArgs& a, int& inst, int64_t& blocks) {
   const int64_t n_rows = n_clusters * nvec;
+  a = InvArgs{Phat, child, n_rows, nvec, surf_lat, wm, scale, out};
+  inst = (fp64 ? 16 : 0) + p;
+  blocks = 0;
   if (n_rows == 0) return hipSuccess;
-  return fp64 ? fwd_dispatch<double>(p, M, child, n_rows, nvec, lat2surf, wm, Qhat, stream)
-              : fwd_dispatch<float>(p, M, child, n_rows, nvec, lat2surf, wm, Qhat, stream);
+  if (p < 2 || p > 8 || n_rows >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  if (fp64) {
+    switch (p) {
+#define KIFMM_IB(PP) case PP: blocks = inv_blocks<double, PP>(n_rows); break;
+      KIFMM_IB(2) KIFMM_IB(3) KIFMM_IB(4) KIFMM_IB(5) KIFMM_IB(6) KIFMM_IB(7) KIFMM_IB(8)
+#undef KIFMM_IB
+    }
+  } else {
+    switch (p) {
+#define KIFMM_IB(PP) case PP: blocks = inv_blocks<float, PP>(n_rows); break;
+      KIFMM_IB(2) KIFMM_IB(3) KIFMM_IB(4) KIFMM_IB(5) KIFMM_IB(6) KIFMM_IB(7) KIFMM_IB(8)
+#undef KIFMM_IB
+    }
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_fft_inverse(int p, bool fp64, const void* Phat, const int32_t* child,
                               int64_t n_clusters, int nvec, const int16_t* surf_lat,
                               const void* wm, double scale, double* out, hipStream_t stream) {
-  const int64_t n_rows = n_clusters * nvec;
-  if (n_rows == 0) return hipSuccess;
-  return fp64 ? inv_dispatch<double>(p, Phat, child, n_rows, nvec, surf_lat, wm, scale, out, stream)
-              : inv_dispatch<float>(p, Phat, child, n_rows, nvec, surf_lat, wm, scale, out, stream);
+  InvArgs a;
+  int inst;
+  int64_t blocks;
+  hipError_t e = plan_fft_inverse(p, fp64, Phat, child, n_clusters, nvec, surf_lat, wm, scale, out, a,
+                                  inst, blocks);
+  if (e != hipSuccess) return e;
+  return inv_dispatch(inst, &a, nullptr, nullptr, 0, blocks, stream);
 }
 
-hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
-                           const int32_t* halo, int64_t n_blocks, const int32_t* blk_tgt,
-                           const int32_t* blk_src, const int32_t* blk_list, const int32_t* tbase,
-                           int64_t n_clusters, int nvec, bool units, void* Phat,
-                           hipStream_t stream) {
+hipError_t launch_fft_inverse_group(int inst, const InvArgs* jobs, const int64_t* pre, int nj,
+                                    int64_t blocks, hipStream_t stream) {
+  return inv_dispatch(inst, nullptr, jobs, pre, nj, blocks, stream);
+}
+
+hipError_t plan_hadamard(bool fp64, int F, const void* Khat, const void* Qhat, const int32_t* halo,
+                         int64_t n_blocks, const int32_t* blk_tgt, const int32_t* blk_src,
+                         const int32_t* blk_list, const int32_t* tbase, int64_t n_clusters, int nvec,
+                         int split, void* Phat, HadBlockArgs& ab, HadGatherArgs& ag, int64_t& blocks) {
   const int64_t n_rows = n_clusters * nvec;
+  blocks = 0;
   if (n_rows == 0) return hipSuccess;
   // 24-bit cluster indices and 32-bit byte offsets within one frequency
   if (n_clusters + 1 >= (int64_t(1) << 23) ||
@@ -868,22 +1052,21 @@ hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
     const int tpw = tiles >= 256 ? 8 : tiles >= 64 ? 4 : 1;
     const int n_chunks = (int)((tiles + 4 * tpw - 1) / (4 * tpw));
     const int64_t total = (int64_t)F * n_chunks;
-    const unsigned grid = (unsigned)(8 * ((total + 7) / 8));
-    hadamard_gather_kernel<double><<<grid, kHadThreads, 0, stream>>>(
-        (const double2*)Khat, (const double*)Qhat, halo, n_clusters, nvec, n_rows, n_chunks, tpw,
-        total, (double*)Phat);
-    return hipGetLastError();
+    ag = HadGatherArgs{Khat, Qhat, halo, n_clusters, nvec, n_rows, n_chunks, tpw, total, Phat};
+    blocks = 8 * ((total + 7) / 8);
+    return hipSuccess;
   }
-  // persistent form: a device-full of workgroups, each taking one run of
-  // the frequency-major items (the B operand is loaded once per frequency in
-  // a run); unit form: one workgroup per 8 items
+  // persistent form (split 0): a device-full of workgroups, each taking one
+  // run of the frequency-major items (the B operand is loaded once per
+  // frequency in a run); unit form (1): one workgroup per 8 items; frequency
+  // form (2): one workgroup per frequency, over all its items
   static const int64_t resident = resident_wgs(hadamard_block_kernel, kHadThreads);
   const int64_t n_items = n_blocks * nvec;
   if (resident < 8 || n_items >= (int64_t(1) << 31)) return hipErrorInvalidValue;
   const int64_t total = (int64_t)F * n_items;
   int64_t unit_len, n_units, n_wgs;
-  if (units) {
-    unit_len = 8;
+  if (split == 1 || split == 2) {
+    unit_len = split == 1 ? 8 : n_items;
     n_units = (total + unit_len - 1) / unit_len;
     n_wgs = n_units;
   } else {
@@ -891,11 +1074,30 @@ hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
     unit_len = (total + n_wgs - 1) / n_wgs;
     n_units = (total + unit_len - 1) / unit_len;
   }
-  const unsigned grid = (unsigned)(8 * ((n_wgs + 7) / 8));
-  hadamard_block_kernel<<<grid, kHadThreads, 0, stream>>>(
-      (const float2*)Khat, (const float*)Qhat, blk_tgt, blk_src, blk_list, tbase, (int)n_items,
-      nvec, n_rows, total, unit_len, n_units, n_wgs, (float*)Phat);
-  return hipGetLastError();
+  ab = HadBlockArgs{Khat, Qhat, blk_tgt, blk_src, blk_list, tbase, (int)n_items, nvec, n_rows, total,
+                    unit_len, n_units, n_wgs, Phat};
+  blocks = 8 * ((n_wgs + 7) / 8);
+  return hipSuccess;
+}
+
+hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
+                           const int32_t* halo, int64_t n_blocks, const int32_t* blk_tgt,
+                           const int32_t* blk_src, const int32_t* blk_list, const int32_t* tbase,
+                           int64_t n_clusters, int nvec, bool units, void* Phat,
+                           hipStream_t stream) {
+  HadBlockArgs ab;
+  HadGatherArgs ag;
+  int64_t blocks;
+  hipError_t e = plan_hadamard(fp64, F, Khat, Qhat, halo, n_blocks, blk_tgt, blk_src, blk_list, tbase,
+                               n_clusters, nvec, units ? 1 : 0, Phat, ab, ag, blocks);
+  if (e != hipSuccess) return e;
+  return had_dispatch(fp64, fp64 ? (const void*)&ag : (const void*)&ab, nullptr, nullptr, 0, blocks,
+                      stream);
+}
+
+hipError_t launch_hadamard_group(bool fp64, const void* jobs, const int64_t* pre, int nj, int64_t blocks,
+                                 hipStream_t stream) {
+  return had_dispatch(fp64, nullptr, jobs, pre, nj, blocks, stream);
 }
 
 }  // namespace kifmm

@@ -17,6 +17,7 @@
 // the partials in a fixed order (deterministic) and applies the scatter.
 #include <algorithm>
 
+#include "group.h"
 #include "kernels.h"
 
 namespace kifmm {
@@ -54,18 +55,20 @@ __device__ inline void col_split(int64_t col, int nvec, const FastDiv& fv, int64
   }
 }
 
-// blockIdx.z selects the K range [kz0, kz1) of a split product; with
-// `partial` set the raw sums go to partial[z][col][m] (m < M) instead of C.
-__global__ __launch_bounds__(256, 4) void gemm64_kernel(Gemm64 g, int kchunk, double* partial) {
+// Workgroup (bx, by, bz): data columns bx * 64.., operator rows by * 80..,
+// K range [bz * kchunk, ..) of a split product; with `partial` set the raw
+// sums go to partial[bz][col][m] (m < M) instead of C.
+__device__ __forceinline__ void gemm64_body(const Gemm64& g, int kchunk, double* partial, int64_t bx,
+                                            int by, int bz) {
   __shared__ double As[kBK][kBM + 2];  // operator, k-major
   __shared__ double Bs[kBK][kBN + 2];  // data columns, k-major
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int l16 = lane % 16, g4 = lane / 16;
-  const int m0 = blockIdx.y * kBM;
-  const int64_t n0 = (int64_t)blockIdx.x * kBN;
+  const int m0 = by * kBM;
+  const int64_t n0 = bx * kBN;
   const int64_t ncols = g.nbox * g.nvec;
-  const int kz0 = blockIdx.z * kchunk;
+  const int kz0 = bz * kchunk;
   const int kz1 = min(g.K, kz0 + kchunk);
   v4d acc[kMT];
 #pragma unroll
@@ -142,7 +145,7 @@ __global__ __launch_bounds__(256, 4) void gemm64_kernel(Gemm64 g, int kchunk, do
     const int64_t col = n0 + wave * 16 + g4 + 4 * e;
     if (col >= ncols) continue;
     if (partial) {
-      double* dst = partial + ((int64_t)blockIdx.z * ncols + col) * g.M;
+      double* dst = partial + ((int64_t)bz * ncols + col) * g.M;
 #pragma unroll
       for (int j = 0; j < kMT; ++j) {
         const int m = m0 + 16 * j + l16;
@@ -179,12 +182,29 @@ __global__ __launch_bounds__(256, 4) void gemm64_kernel(Gemm64 g, int kchunk, do
   }
 }
 
+__global__ __launch_bounds__(256, 4) void gemm64_kernel(Gemm64 g, int kchunk, double* partial) {
+  gemm64_body(g, kchunk, partial, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Grouped: workgroup b of job j (pre[j] <= b < pre[j + 1]) is workgroup
+// b - pre[j] of that job's gx x gy x split grid (x fastest).
+__global__ __launch_bounds__(256, 4) void gemm64_group_kernel(const GemmJob* __restrict__ jobs,
+                                                              const int64_t* __restrict__ pre, int nj) {
+  int64_t b;
+  const GemmJob j = jobs[group_job(pre, nj, b)];
+  const int64_t per_z = j.gx * j.gy;
+  const int bz = (int)(b / per_z);
+  const int64_t r = b - (int64_t)bz * per_z;
+  const int by = (int)(r / j.gx);
+  gemm64_body(j.g, j.kchunk, j.split > 1 ? j.g.work : nullptr, r - (int64_t)by * j.gx, by, bz);
+}
+
 // Sum the split-K partials in order z = 0, 1, ... and scatter like the GEMM.
-__global__ __launch_bounds__(256) void gemm64_reduce_kernel(Gemm64 g, int nsplit,
-                                                            const double* __restrict__ partial) {
+__device__ __forceinline__ void gemm64_reduce_body(const Gemm64& g, int nsplit,
+                                                   const double* __restrict__ partial, int64_t blk) {
   const int64_t ncols = g.nbox * g.nvec;
   const int64_t total = ncols * g.M;  // < 2^32 (checked by the launcher)
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = blk * 256 + threadIdx.x;
   if (i >= total) return;
   uint32_t mr;
   const int64_t col = fdiv((uint32_t)i, g.div_M, mr);
@@ -216,6 +236,20 @@ __global__ __launch_bounds__(256) void gemm64_reduce_kernel(Gemm64 g, int nsplit
   *dst = g.accumulate ? *dst + val : val;
 }
 
+__global__ __launch_bounds__(256) void gemm64_reduce_kernel(Gemm64 g, int nsplit,
+                                                            const double* __restrict__ partial) {
+  gemm64_reduce_body(g, nsplit, partial, blockIdx.x);
+}
+
+// Grouped reduction: jobs with split > 1 only; ceil(M x columns / 256)
+// workgroups each.
+__global__ __launch_bounds__(256) void gemm64_reduce_group_kernel(const GemmJob* __restrict__ jobs,
+                                                                  const int64_t* __restrict__ pre, int nj) {
+  int64_t b;
+  const GemmJob j = jobs[group_job(pre, nj, b)];
+  gemm64_reduce_body(j.g, j.split, j.g.work, b);
+}
+
 FastDiv make_div(int d) {
   FastDiv f;
   f.d = (uint32_t)d;
@@ -227,8 +261,10 @@ FastDiv make_div(int d) {
 
 int64_t gemm64_max_work_elems() { return 2 * kSplitTarget * kBN * kBM; }
 
-hipError_t launch_gemm64(const Gemm64& g0, hipStream_t stream) {
-  Gemm64 g = g0;
+hipError_t plan_gemm64(const Gemm64& g0, GemmJob& job) {
+  Gemm64& g = job.g;
+  g = g0;
+  job.gx = job.gy = job.split = job.kchunk = 0;
   const int64_t ncols = g.nbox * g.nvec;
   if (ncols == 0 || g.M == 0) return hipSuccess;
   if (ncols >= ((int64_t)1 << 31) || g.ks < 1 || g.ms < 1 || g.nvec < 1) return hipErrorInvalidValue;
@@ -249,16 +285,43 @@ hipError_t launch_gemm64(const Gemm64& g0, hipStream_t stream) {
   }
   const int kchunk = (int)(((slices + split - 1) / split) * kBK);
   split = (g.K + kchunk - 1) / kchunk;
-  dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)split);
-  if (split == 1) {
-    gemm64_kernel<<<grid, 256, 0, stream>>>(g, kchunk, nullptr);
+  job.gx = gx;
+  job.gy = (int)gy;
+  job.split = (int)split;
+  job.kchunk = kchunk;
+  return hipSuccess;
+}
+
+int64_t gemm64_job_blocks(const GemmJob& j) { return j.gx * j.gy * j.split; }
+int64_t gemm64_reduce_blocks(const GemmJob& j) {
+  return j.split > 1 ? (j.g.nbox * j.g.nvec * j.g.M + 255) / 256 : 0;
+}
+
+hipError_t launch_gemm64(const Gemm64& g0, hipStream_t stream) {
+  GemmJob job;
+  hipError_t e = plan_gemm64(g0, job);
+  if (e != hipSuccess || job.split == 0) return e;
+  const Gemm64& g = job.g;
+  dim3 grid((unsigned)job.gx, (unsigned)job.gy, (unsigned)job.split);
+  if (job.split == 1) {
+    gemm64_kernel<<<grid, 256, 0, stream>>>(g, job.kchunk, nullptr);
     return hipGetLastError();
   }
-  gemm64_kernel<<<grid, 256, 0, stream>>>(g, kchunk, g.work);
-  hipError_t e = hipGetLastError();
+  gemm64_kernel<<<grid, 256, 0, stream>>>(g, job.kchunk, g.work);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t total = ncols * g.M;
-  gemm64_reduce_kernel<<<(unsigned)((total + 255) / 256), 256, 0, stream>>>(g, (int)split, g.work);
+  gemm64_reduce_kernel<<<(unsigned)gemm64_reduce_blocks(job), 256, 0, stream>>>(g, job.split, g.work);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm64_group(const GemmJob* jobs, const int64_t* pre, int nj, int64_t blocks,
+                               bool reduce, hipStream_t stream) {
+  if (blocks == 0) return hipSuccess;
+  if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  if (reduce)
+    gemm64_reduce_group_kernel<<<(unsigned)blocks, 256, 0, stream>>>(jobs, pre, nj);
+  else
+    gemm64_group_kernel<<<(unsigned)blocks, 256, 0, stream>>>(jobs, pre, nj);
   return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 // precision count as coincident).
 #include <algorithm>
 
+#include "group.h"
 #include "kernels.h"
 
 namespace kifmm {
@@ -36,21 +37,41 @@ __global__ void gather_kernel(const TQ* __restrict__ q, int64_t ldq, const int64
   if (i < n) qs[v * n + i] = q[v * ldq + perm[i]];
 }
 
+// Grouped gather: a job's workgroups are (x, v) with x fastest, ceil(n / 256)
+// per vector.
+template <typename TQ>
+__global__ void gather_group_kernel(const GatherArgs* __restrict__ jobs, const int64_t* __restrict__ pre,
+                                    int nj) {
+  int64_t b;
+  const GatherArgs a = jobs[group_job(pre, nj, b)];
+  const int64_t nbx = (a.n + 255) / 256;
+  const int64_t v = b / nbx;
+  const int64_t i = (b - v * nbx) * 256 + threadIdx.x;
+  const TQ* __restrict__ q = static_cast<const TQ*>(a.q);
+  TQ* __restrict__ qs = static_cast<TQ*>(a.qs);
+  if (i < a.n) qs[v * a.n + i] = q[v * a.ldq + a.perm[i]];
+}
+
 constexpr int kP2MChunk = 64;  // sources staged per pass (one per lane)
 
 // One wave per leaf.  Each lane owns PPL upward-check points (lane + 64 j)
 // and NV charge vectors, so one staged source (x, y, z, q) serves PPL x NV
 // accumulations; the source loop is uniform across the wave.
 template <typename TQ, int PPL, int NV>
-__global__ __launch_bounds__(64) void p2m_kernel(
-    const double* __restrict__ xyz, const TQ* __restrict__ qs, int64_t n_src,
-    const int32_t* __restrict__ start, const int32_t* __restrict__ end,
-    const double* __restrict__ centers, const double* __restrict__ surf, double ar, int ns, int nvec,
-    double* __restrict__ phi) {
+__device__ __forceinline__ void p2m_body(const P2MArgs& a, int64_t leaf) {
+  const double* __restrict__ xyz = a.xyz;
+  const TQ* __restrict__ qs = static_cast<const TQ*>(a.qs);
+  const int64_t n_src = a.n_src;
+  const int32_t* __restrict__ start = a.start;
+  const int32_t* __restrict__ end = a.end;
+  const double* __restrict__ centers = a.centers;
+  const double* __restrict__ surf = a.surf;
+  const double ar = a.ar;
+  const int ns = a.ns, nvec = a.nvec;
+  double* __restrict__ phi = a.phi;
   constexpr int NX = NV > 1 ? NV - 1 : 1;
   __shared__ double4 sp[kP2MChunk];
   __shared__ double sq[NX][kP2MChunk];
-  const int64_t leaf = blockIdx.x;
   const int lane = threadIdx.x;
   const int s0 = start[leaf], s1 = end[leaf];
   const double cx = centers[3 * leaf], cy = centers[3 * leaf + 1], cz = centers[3 * leaf + 2];
@@ -105,37 +126,64 @@ __global__ __launch_bounds__(64) void p2m_kernel(
   }
 }
 
-template <typename TQ, int PPL>
-void p2m_launch_nv(int nvec, unsigned grid, hipStream_t stream, const double* xyz, const TQ* qs,
-                   int64_t n_src, const int32_t* start, const int32_t* end, const double* centers,
-                   const double* surf, double ar, int ns, double* phi) {
-#define KIFMM_P2M(NVV)                                                                   \
-  p2m_kernel<TQ, PPL, NVV><<<grid, 64, 0, stream>>>(xyz, qs, n_src, start, end, centers, \
-                                                     surf, ar, ns, nvec, phi)
-  if (nvec == 1)
-    KIFMM_P2M(1);
-  else if (nvec == 2)
-    KIFMM_P2M(2);
-  else if (nvec <= 4)
-    KIFMM_P2M(4);
+template <typename TQ, int PPL, int NV>
+__global__ __launch_bounds__(64) void p2m_kernel(P2MArgs a) {
+  p2m_body<TQ, PPL, NV>(a, blockIdx.x);
+}
+
+template <typename TQ, int PPL, int NV>
+__global__ __launch_bounds__(64) void p2m_group_kernel(const P2MArgs* __restrict__ jobs,
+                                                       const int64_t* __restrict__ pre, int nj) {
+  int64_t b;
+  const P2MArgs a = jobs[group_job(pre, nj, b)];
+  p2m_body<TQ, PPL, NV>(a, b);
+}
+
+// Instance of the P2M kernel: (TQ, check points per lane, vector block).
+int p2m_instance(bool q_fp64, int ns, int nvec) {
+  const int ppl = std::min(4, (ns + 63) / 64);
+  const int nv = nvec == 1 ? 0 : nvec == 2 ? 1 : nvec <= 4 ? 2 : 3;
+  return (q_fp64 ? 16 : 0) + (ppl - 1) * 4 + nv;
+}
+
+// One launch of instance `inst`: a plain launch of one job (jobs == nullptr,
+// `one` holds the arguments) or a grouped launch.
+template <typename TQ, int PPL, int NV>
+void p2m_go(const P2MArgs* one, const P2MArgs* jobs, const int64_t* pre, int nj, int64_t blocks,
+            hipStream_t s) {
+  if (!jobs)
+    p2m_kernel<TQ, PPL, NV><<<(unsigned)blocks, 64, 0, s>>>(*one);
   else
-    KIFMM_P2M(8);
-#undef KIFMM_P2M
+    p2m_group_kernel<TQ, PPL, NV><<<(unsigned)blocks, 64, 0, s>>>(jobs, pre, nj);
+}
+
+template <typename TQ, int PPL>
+void p2m_go_nv(int nv, const P2MArgs* one, const P2MArgs* jobs, const int64_t* pre, int nj,
+               int64_t blocks, hipStream_t s) {
+  if (nv == 0) p2m_go<TQ, PPL, 1>(one, jobs, pre, nj, blocks, s);
+  else if (nv == 1) p2m_go<TQ, PPL, 2>(one, jobs, pre, nj, blocks, s);
+  else if (nv == 2) p2m_go<TQ, PPL, 4>(one, jobs, pre, nj, blocks, s);
+  else p2m_go<TQ, PPL, 8>(one, jobs, pre, nj, blocks, s);
 }
 
 template <typename TQ>
-hipError_t p2m_launch(int nvec, unsigned grid, hipStream_t stream, const double* xyz, const TQ* qs,
-                      int64_t n_src, const int32_t* start, const int32_t* end,
-                      const double* centers, const double* surf, double ar, int ns, double* phi) {
-  const int ppl = std::min(4, (ns + 63) / 64);
-  if (ppl == 1)
-    p2m_launch_nv<TQ, 1>(nvec, grid, stream, xyz, qs, n_src, start, end, centers, surf, ar, ns, phi);
-  else if (ppl == 2)
-    p2m_launch_nv<TQ, 2>(nvec, grid, stream, xyz, qs, n_src, start, end, centers, surf, ar, ns, phi);
-  else if (ppl == 3)
-    p2m_launch_nv<TQ, 3>(nvec, grid, stream, xyz, qs, n_src, start, end, centers, surf, ar, ns, phi);
+void p2m_go_ppl(int ppl, int nv, const P2MArgs* one, const P2MArgs* jobs, const int64_t* pre, int nj,
+                int64_t blocks, hipStream_t s) {
+  if (ppl == 1) p2m_go_nv<TQ, 1>(nv, one, jobs, pre, nj, blocks, s);
+  else if (ppl == 2) p2m_go_nv<TQ, 2>(nv, one, jobs, pre, nj, blocks, s);
+  else if (ppl == 3) p2m_go_nv<TQ, 3>(nv, one, jobs, pre, nj, blocks, s);
+  else p2m_go_nv<TQ, 4>(nv, one, jobs, pre, nj, blocks, s);
+}
+
+hipError_t p2m_dispatch(int inst, const P2MArgs* one, const P2MArgs* jobs, const int64_t* pre, int nj,
+                        int64_t blocks, hipStream_t s) {
+  if (blocks == 0) return hipSuccess;
+  if (inst < 0 || inst >= 32 || blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  const int ppl = (inst % 16) / 4 + 1, nv = inst % 4;
+  if (inst >= 16)
+    p2m_go_ppl<double>(ppl, nv, one, jobs, pre, nj, blocks, s);
   else
-    p2m_launch_nv<TQ, 4>(nvec, grid, stream, xyz, qs, n_src, start, end, centers, surf, ar, ns, phi);
+    p2m_go_ppl<float>(ppl, nv, one, jobs, pre, nj, blocks, s);
   return hipGetLastError();
 }
 
@@ -168,14 +216,28 @@ template <> struct Vec4<double> { using type = double4; };
 // MODE 2 adds the far field to those stored sums and finishes, so 1 then 2
 // gives exactly the result of 0.
 template <typename T, typename TQ, int NV, int MODE>
-__global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
-    const double* __restrict__ txyz, const double* __restrict__ sxyz, const TQ* __restrict__ qs,
-    int64_t n_src, const int32_t* __restrict__ tstart, const int32_t* __restrict__ tend,
-    const int32_t* __restrict__ sstart, const int32_t* __restrict__ send,
-    const int64_t* __restrict__ noffs, const int32_t* __restrict__ nsrc,
-    const double* __restrict__ centers, const double* __restrict__ surf, double ar, int ns,
-    const double* __restrict__ local, const int64_t* __restrict__ tperm, TQ* __restrict__ phi,
-    int64_t ldphi, int nvec, int64_t n_leaf, T tau2) {
+__device__ __forceinline__ void leaf_eval_body(const LeafArgs& a, int64_t blk) {
+  const double* __restrict__ txyz = a.txyz;
+  const double* __restrict__ sxyz = a.sxyz;
+  const TQ* __restrict__ qs = static_cast<const TQ*>(a.qs);
+  const int64_t n_src = a.n_src;
+  const int32_t* __restrict__ tstart = a.tstart;
+  const int32_t* __restrict__ tend = a.tend;
+  const int32_t* __restrict__ sstart = a.sstart;
+  const int32_t* __restrict__ send = a.send;
+  const int64_t* __restrict__ noffs = a.near_offs;
+  const int32_t* __restrict__ nsrc = a.near_src;
+  const double* __restrict__ centers = a.centers;
+  const double* __restrict__ surf = a.surf;
+  const double ar = a.ar;
+  const int ns = a.ns;
+  const double* __restrict__ local = a.local;
+  const int64_t* __restrict__ tperm = a.tgt_perm;
+  TQ* __restrict__ phi = static_cast<TQ*>(a.phi);
+  const int64_t ldphi = a.ldphi;
+  const int nvec = a.nvec;
+  const int64_t n_leaf = a.n_leaf;
+  const T tau2 = (T)a.tau2;
   using T4 = typename Vec4<T>::type;
   constexpr int NX = NV > 1 ? NV - 1 : 1;
   __shared__ double4 ls[kL2PChunk];
@@ -191,7 +253,7 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
   // consecutive leaves (which share most near-field sources) on one XCD;
   // the grid is 8 ceil(n_leaf / 8) workgroups
   const int64_t per_xcd = (n_leaf + 7) / 8;
-  const int64_t leaf = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  const int64_t leaf = (blk % 8) * per_xcd + blk / 8;
   if (leaf >= n_leaf) return;
   const int t0 = tstart[leaf], t1 = tend[leaf];
   const int nt = t1 - t0;
@@ -375,50 +437,62 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(
   }
 }
 
-template <typename T, typename TQ, int MODE>
-hipError_t leaf_launch(int nvec, int64_t n_leaf, hipStream_t stream, const double* txyz,
-                       const double* sxyz, double tau2,
-                       const TQ* qs, int64_t n_src, const int32_t* tstart, const int32_t* tend,
-                       const int32_t* sstart, const int32_t* send, const int64_t* near_offs,
-                       const int32_t* near_src, const double* centers, const double* surf, double ar,
-                       int ns, const double* local, const int64_t* tgt_perm, TQ* phi, int64_t ldphi) {
-#define KIFMM_LEAF(NVV)                                                                       \
-  leaf_eval_kernel<T, TQ, NVV, MODE><<<(unsigned)(8 * ((n_leaf + 7) / 8)), kLeafThreads, 0,  \
-                                       stream>>>(                                             \
-      txyz, sxyz, qs, n_src, tstart, tend, sstart, send, near_offs, near_src, centers, \
-      surf, ar, \
-      ns, local, tgt_perm, phi, ldphi, nvec, n_leaf, (T)tau2)
-  if (nvec == 1)
-    KIFMM_LEAF(1);
-  else if (nvec == 2)
-    KIFMM_LEAF(2);
-  else if (nvec <= 4)
-    KIFMM_LEAF(4);
-  else
-    KIFMM_LEAF(8);
-#undef KIFMM_LEAF
-  return hipGetLastError();
+template <typename T, typename TQ, int NV, int MODE>
+__global__ __launch_bounds__(kLeafThreads) void leaf_eval_kernel(LeafArgs a) {
+  leaf_eval_body<T, TQ, NV, MODE>(a, blockIdx.x);
 }
 
-template <typename T, typename TQ>
-hipError_t leaf_mode(int mode, int nvec, int64_t n_leaf, hipStream_t stream, const double* txyz,
-                     const double* sxyz, double tau2, const TQ* qs, int64_t n_src,
-                     const int32_t* tstart,
-                     const int32_t* tend, const int32_t* sstart, const int32_t* send,
-                     const int64_t* near_offs, const int32_t* near_src, const double* centers,
-                     const double* surf, double ar, int ns, const double* local,
-                     const int64_t* tgt_perm, TQ* phi, int64_t ldphi) {
-  switch (mode) {
-#define KIFMM_MODE(M)                                                                        \
-  case M:                                                                                    \
-    return leaf_launch<T, TQ, M>(nvec, n_leaf, stream, txyz, sxyz, tau2, qs, n_src, tstart,       \
-                                 tend, sstart, \
-                                 send, near_offs, near_src, centers, surf, ar, ns, local,     \
-                                 tgt_perm, phi, ldphi);
-    KIFMM_MODE(0) KIFMM_MODE(1) KIFMM_MODE(2)
-#undef KIFMM_MODE
-    default: return hipErrorInvalidValue;
-  }
+template <typename T, typename TQ, int NV, int MODE>
+__global__ __launch_bounds__(kLeafThreads) void leaf_eval_group_kernel(const LeafArgs* __restrict__ jobs,
+                                                                      const int64_t* __restrict__ pre,
+                                                                      int nj) {
+  int64_t b;
+  const LeafArgs a = jobs[group_job(pre, nj, b)];
+  leaf_eval_body<T, TQ, NV, MODE>(a, b);
+}
+
+// Instance of the leaf kernel: (precision, mode, vector block).
+int leaf_instance(bool fp64, int mode, int nvec) {
+  const int nv = nvec == 1 ? 0 : nvec == 2 ? 1 : nvec <= 4 ? 2 : 3;
+  return (fp64 ? 12 : 0) + mode * 4 + nv;
+}
+
+template <typename T, int NV, int MODE>
+void leaf_go(const LeafArgs* one, const LeafArgs* jobs, const int64_t* pre, int nj, int64_t blocks,
+             hipStream_t s) {
+  if (!jobs)
+    leaf_eval_kernel<T, T, NV, MODE><<<(unsigned)blocks, kLeafThreads, 0, s>>>(*one);
+  else
+    leaf_eval_group_kernel<T, T, NV, MODE><<<(unsigned)blocks, kLeafThreads, 0, s>>>(jobs, pre, nj);
+}
+
+template <typename T, int MODE>
+void leaf_go_nv(int nv, const LeafArgs* one, const LeafArgs* jobs, const int64_t* pre, int nj,
+                int64_t blocks, hipStream_t s) {
+  if (nv == 0) leaf_go<T, 1, MODE>(one, jobs, pre, nj, blocks, s);
+  else if (nv == 1) leaf_go<T, 2, MODE>(one, jobs, pre, nj, blocks, s);
+  else if (nv == 2) leaf_go<T, 4, MODE>(one, jobs, pre, nj, blocks, s);
+  else leaf_go<T, 8, MODE>(one, jobs, pre, nj, blocks, s);
+}
+
+template <typename T>
+void leaf_go_mode(int mode, int nv, const LeafArgs* one, const LeafArgs* jobs, const int64_t* pre,
+                  int nj, int64_t blocks, hipStream_t s) {
+  if (mode == 0) leaf_go_nv<T, 0>(nv, one, jobs, pre, nj, blocks, s);
+  else if (mode == 1) leaf_go_nv<T, 1>(nv, one, jobs, pre, nj, blocks, s);
+  else leaf_go_nv<T, 2>(nv, one, jobs, pre, nj, blocks, s);
+}
+
+hipError_t leaf_dispatch(int inst, const LeafArgs* one, const LeafArgs* jobs, const int64_t* pre, int nj,
+                         int64_t blocks, hipStream_t s) {
+  if (blocks == 0) return hipSuccess;
+  if (inst < 0 || inst >= 24 || blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  const int mode = (inst % 12) / 4, nv = inst % 4;
+  if (inst >= 12)
+    leaf_go_mode<double>(mode, nv, one, jobs, pre, nj, blocks, s);
+  else
+    leaf_go_mode<float>(mode, nv, one, jobs, pre, nj, blocks, s);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -437,12 +511,39 @@ hipError_t launch_p2m(const double* src_xyz, const void* qs, bool q_fp64, int64_
                       const int32_t* start, const int32_t* end, const double* centers, int64_t n_leaf,
                       const double* surf, double ar, int ns, int nvec, double* phi,
                       hipStream_t stream) {
-  if (n_leaf == 0) return hipSuccess;
-  if (q_fp64)
-    return p2m_launch<double>(nvec, (unsigned)n_leaf, stream, src_xyz, (const double*)qs, n_src,
-                              start, end, centers, surf, ar, ns, phi);
-  return p2m_launch<float>(nvec, (unsigned)n_leaf, stream, src_xyz, (const float*)qs, n_src, start,
-                           end, centers, surf, ar, ns, phi);
+  P2MArgs a;
+  int inst;
+  int64_t blocks;
+  plan_p2m(src_xyz, qs, q_fp64, n_src, start, end, centers, n_leaf, surf, ar, ns, nvec, phi, a, inst,
+           blocks);
+  return p2m_dispatch(inst, &a, nullptr, nullptr, 0, blocks, stream);
+}
+
+void plan_p2m(const double* src_xyz, const void* qs, bool q_fp64, int64_t n_src, const int32_t* start,
+              const int32_t* end, const double* centers, int64_t n_leaf, const double* surf, double ar,
+              int ns, int nvec, double* phi, P2MArgs& a, int& inst, int64_t& blocks) {
+  a = P2MArgs{src_xyz, qs, n_src, start, end, centers, surf, ar, ns, nvec, phi, n_leaf};
+  inst = p2m_instance(q_fp64, ns, nvec);
+  blocks = n_leaf;
+}
+
+hipError_t launch_p2m_group(int inst, const P2MArgs* jobs, const int64_t* pre, int nj, int64_t blocks,
+                            hipStream_t stream) {
+  return p2m_dispatch(inst, nullptr, jobs, pre, nj, blocks, stream);
+}
+
+void plan_leaf_eval(const double* tgt_xyz, const double* src_xyz, double leaf_w, const void* qs,
+                    bool fp64, int64_t n_src, const int32_t* tstart, const int32_t* tend,
+                    const int32_t* sstart, const int32_t* send, const int64_t* near_offs,
+                    const int32_t* near_src, const double* centers, int64_t n_leaf,
+                    const double* surf, double ar, int ns, const double* local,
+                    const int64_t* tgt_perm, void* phi, int64_t ldphi, int nvec, int mode,
+                    LeafArgs& a, int& inst, int64_t& blocks) {
+  const double tau2 = (leaf_w / 16) * (leaf_w / 16);  // FP32: pairs refined below w / 16
+  a = LeafArgs{tgt_xyz, src_xyz, qs, n_src, tstart, tend, sstart, send, near_offs, near_src, centers,
+               surf, ar, ns, local, tgt_perm, phi, ldphi, nvec, n_leaf, tau2};
+  inst = (mode < 0 || mode > 2) ? -1 : leaf_instance(fp64, mode, nvec);
+  blocks = 8 * ((n_leaf + 7) / 8);
 }
 
 hipError_t launch_leaf_eval(const double* tgt_xyz, const double* src_xyz, double leaf_w,
@@ -453,16 +554,29 @@ hipError_t launch_leaf_eval(const double* tgt_xyz, const double* src_xyz, double
                             int ns, const double* local, const int64_t* tgt_perm, void* phi,
                             int64_t ldphi, int nvec, int mode, hipStream_t stream) {
   if (n_leaf == 0) return hipSuccess;
-  const double tau2 = (leaf_w / 16) * (leaf_w / 16);  // FP32: pairs refined below w / 16
+  LeafArgs a;
+  int inst;
+  int64_t blocks;
+  plan_leaf_eval(tgt_xyz, src_xyz, leaf_w, qs, fp64, n_src, tstart, tend, sstart, send, near_offs,
+                 near_src, centers, n_leaf, surf, ar, ns, local, tgt_perm, phi, ldphi, nvec, mode, a,
+                 inst, blocks);
+  return leaf_dispatch(inst, &a, nullptr, nullptr, 0, blocks, stream);
+}
+
+hipError_t launch_leaf_eval_group(int inst, const LeafArgs* jobs, const int64_t* pre, int nj,
+                                  int64_t blocks, hipStream_t stream) {
+  return leaf_dispatch(inst, nullptr, jobs, pre, nj, blocks, stream);
+}
+
+hipError_t launch_gather_group(bool fp64, const GatherArgs* jobs, const int64_t* pre, int nj,
+                               int64_t blocks, hipStream_t stream) {
+  if (blocks == 0) return hipSuccess;
+  if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
   if (fp64)
-    return leaf_mode<double, double>(mode, nvec, n_leaf, stream, tgt_xyz, src_xyz, tau2,
-                                     (const double*)qs, n_src, tstart, tend, sstart, send,
-                                     near_offs, near_src, centers, surf, ar, ns, local, tgt_perm,
-                                     (double*)phi, ldphi);
-  return leaf_mode<float, float>(mode, nvec, n_leaf, stream, tgt_xyz, src_xyz, tau2,
-                                 (const float*)qs, n_src, tstart, tend, sstart, send, near_offs,
-                                 near_src, centers, surf, ar, ns, local, tgt_perm, (float*)phi,
-                                 ldphi);
+    gather_group_kernel<double><<<(unsigned)blocks, 256, 0, stream>>>(jobs, pre, nj);
+  else
+    gather_group_kernel<float><<<(unsigned)blocks, 256, 0, stream>>>(jobs, pre, nj);
+  return hipGetLastError();
 }
 
 }  // namespace kifmm

@@ -33,6 +33,41 @@ hipError_t launch_leaf_eval(const double* tgt_xyz, const double* src_xyz, double
                             int ns, const double* local, const int64_t* tgt_perm, void* phi,
                             int64_t ldphi, int nvec, int mode, hipStream_t stream);
 
+// Grouped forms of the point kernels (see "grouped launches" below).
+struct GatherArgs {  // ceil(n / 256) x nvec workgroups
+  const void* q; int64_t ldq; const int64_t* perm; int64_t n; int nvec; void* qs;
+};
+hipError_t launch_gather_group(bool fp64, const GatherArgs* jobs, const int64_t* pre, int nj,
+                               int64_t blocks, hipStream_t stream);
+struct P2MArgs {  // one workgroup per leaf
+  const double* xyz; const void* qs; int64_t n_src; const int32_t* start; const int32_t* end;
+  const double* centers; const double* surf; double ar; int ns; int nvec; double* phi;
+  int64_t n_leaf;
+};
+// arguments, kernel instance (element type, check points per lane, vector
+// block) and workgroups of launch_p2m
+void plan_p2m(const double* src_xyz, const void* qs, bool q_fp64, int64_t n_src, const int32_t* start,
+              const int32_t* end, const double* centers, int64_t n_leaf, const double* surf, double ar,
+              int ns, int nvec, double* phi, P2MArgs& a, int& inst, int64_t& blocks);
+hipError_t launch_p2m_group(int inst, const P2MArgs* jobs, const int64_t* pre, int nj, int64_t blocks,
+                            hipStream_t stream);
+struct LeafArgs {  // 8 ceil(n_leaf / 8) workgroups (leaves placed by XCD)
+  const double* txyz; const double* sxyz; const void* qs; int64_t n_src; const int32_t* tstart;
+  const int32_t* tend; const int32_t* sstart; const int32_t* send; const int64_t* near_offs;
+  const int32_t* near_src; const double* centers; const double* surf; double ar; int ns;
+  const double* local; const int64_t* tgt_perm; void* phi; int64_t ldphi; int nvec; int64_t n_leaf;
+  double tau2;
+};
+void plan_leaf_eval(const double* tgt_xyz, const double* src_xyz, double leaf_w, const void* qs,
+                    bool fp64, int64_t n_src, const int32_t* tstart, const int32_t* tend,
+                    const int32_t* sstart, const int32_t* send, const int64_t* near_offs,
+                    const int32_t* near_src, const double* centers, int64_t n_leaf,
+                    const double* surf, double ar, int ns, const double* local,
+                    const int64_t* tgt_perm, void* phi, int64_t ldphi, int nvec, int mode,
+                    LeafArgs& a, int& inst, int64_t& blocks);
+hipError_t launch_leaf_eval_group(int inst, const LeafArgs* jobs, const int64_t* pre, int nj,
+                                  int64_t blocks, hipStream_t stream);
+
 // ---- device re-setup for moving points -------------------------------------
 // leaf[i] = index of point i's leaf in the sorted leaf keys of the given
 // depth, or -1 (and *bad = 1) if the point is outside the domain cube or its
@@ -71,6 +106,30 @@ struct Gemm64 {
   FastDiv div_ks, div_ms, div_nvec, div_M;  // filled by launch_gemm64
 };
 hipError_t launch_gemm64(const Gemm64& g, hipStream_t stream);
+
+// ---- grouped launches -------------------------------------------------------
+// One launch runs the same kernel for many independent jobs (the problems of
+// a batch): job j owns workgroups pre[j] .. pre[j + 1] - 1 of the grid (pre
+// is an exclusive prefix sum of the jobs' workgroup counts, in device
+// memory, as is the job array), and each workgroup runs exactly what the
+// job's own launch would have run in its place, so results are those of
+// separate launches.  Jobs whose kernels place work by XCD take multiples
+// of 8 workgroups.
+
+// A planned FP64 GEMM: the launch shape launch_gemm64 would use (gx column
+// blocks, gy row blocks, split K parts of kchunk each; split == 0: nothing to
+// do); the split-K partials go to g.work when split > 1.
+struct GemmJob {
+  Gemm64 g;
+  int64_t gx = 0;
+  int gy = 0, split = 0, kchunk = 0;
+};
+hipError_t plan_gemm64(const Gemm64& g, GemmJob& job);
+int64_t gemm64_job_blocks(const GemmJob& j);    // gx * gy * split
+int64_t gemm64_reduce_blocks(const GemmJob& j);  // 0 unless split > 1
+// reduce = false: the products; true: the split-K sums (jobs with split > 1)
+hipError_t launch_gemm64_group(const GemmJob* jobs, const int64_t* pre, int nj, int64_t blocks,
+                               bool reduce, hipStream_t stream);
 // Largest split-K workspace (doubles) launch_gemm64 uses for any shape:
 // only grids of fewer than 512 workgroups are split, into at most
 // ceil(512 / workgroups) parts, so parts x columns x rows stays below
@@ -121,6 +180,47 @@ hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
 hipError_t launch_fft_inverse(int p, bool fp64, const void* Phat, const int32_t* child,
                               int64_t n_clusters, int nvec, const int16_t* surf_lat,
                               const void* wm, double scale, double* out, hipStream_t stream);
+
+// Grouped forms of the FFT-M2L kernels: arguments, kernel instance
+// ((fp64 ? 16 : 0) + p) and workgroups of one launch.  A grouped forward
+// takes one item group per workgroup (persistent = false); the FP32
+// Hadamard of a grouped launch takes one workgroup per frequency (split 2).
+struct FwdArgs {
+  const double* M; const int32_t* child; int64_t n_rows; int nvec; const int16_t* lat2surf;
+  const void* wm; void* Qhat;
+};
+struct InvArgs {
+  const void* Phat; const int32_t* child; int64_t n_rows; int nvec; const int16_t* surf_lat;
+  const void* wm; double scale; double* out;
+};
+struct HadGatherArgs {  // FP64
+  const void* Khat; const void* Qhat; const int32_t* halo; int64_t n_c; int nvec; int64_t n_rows;
+  int n_chunks; int tiles_per_wave; int64_t total_blocks; void* Phat;
+};
+struct HadBlockArgs {  // FP32
+  const void* Khat; const void* Qhat; const int32_t* blk_tgt; const int32_t* blk_src;
+  const int32_t* blk_list; const int32_t* tbase; int n_items; int nvec; int64_t n_rows;
+  int64_t total_items; int64_t unit_len; int64_t n_units; int64_t n_wgs; void* Phat;
+};
+hipError_t plan_fft_forward(int p, bool fp64, const double* M, const int32_t* child, int64_t n_clusters,
+                            int nvec, const int16_t* lat2surf, const void* wm, void* Qhat,
+                            bool persistent, FwdArgs& a, int& inst, int64_t& blocks);
+hipError_t launch_fft_forward_group(int inst, const FwdArgs* jobs, const int64_t* pre, int nj,
+                                    int64_t blocks, hipStream_t stream);
+hipError_t plan_fft_inverse(int p, bool fp64, const void* Phat, const int32_t* child, int64_t n_clusters,
+                            int nvec, const int16_t* surf_lat, const void* wm, double scale, double* out,
+                            InvArgs& a, int& inst, int64_t& blocks);
+hipError_t launch_fft_inverse_group(int inst, const InvArgs* jobs, const int64_t* pre, int nj,
+                                    int64_t blocks, hipStream_t stream);
+// fills ab (FP32) or ag (FP64); FP32 work split: 0 persistent runs, 1
+// 8-item units, 2 one workgroup per frequency (all its items)
+hipError_t plan_hadamard(bool fp64, int F, const void* Khat, const void* Qhat, const int32_t* halo,
+                         int64_t n_blocks, const int32_t* blk_tgt, const int32_t* blk_src,
+                         const int32_t* blk_list, const int32_t* tbase, int64_t n_clusters, int nvec,
+                         int split, void* Phat, HadBlockArgs& ab, HadGatherArgs& ag, int64_t& blocks);
+// jobs: HadGatherArgs (fp64) or HadBlockArgs
+hipError_t launch_hadamard_group(bool fp64, const void* jobs, const int64_t* pre, int nj, int64_t blocks,
+                                 hipStream_t stream);
 
 // ---- BLAS-M2L (Section 3.2) -----------------------------------------------
 // Fused per-level compressed M2L: out[box][v][0:k] = scale * sum over the
@@ -179,6 +279,12 @@ struct BlasStack {
   void* xi_lo;                //   BF16x3 low parts
   double* out;                // [box][v][k]
   double scale;
+  // Stage B's K steps split over ksplit workgroups per tile (levels with
+  // few tiles): each writes its raw sums to partial[part][box][v][k], and a
+  // reduction adds the parts in order, scales and writes out
+  int ksplit = 1;
+  int64_t n_boxes = 0;        // boxes of the level (partial's box extent)
+  double* partial = nullptr;
 };
 hipError_t launch_blas_stacked(const BlasStack& a, hipStream_t stream);
 // q~ [col][k] FP64 -> [col][kp] zero-padded bf16 high and low parts
