@@ -317,20 +317,30 @@ kifmm_status kifmm_m2l_counts(const kifmm_handle* h, int32_t level, int64_t* cou
 /* ---- moving points --------------------------------------------------------- */
 
 /* Re-setup for points that move between evaluates (the dynamic-particle
- * setting of Section 5.1, where the tree and maps are rebuilt each step;
- * Tables 5-6 list that setup cost), on the device: the new
- * positions src_dev[n_src][3] and tgt_dev[n_tgt][3] (device memory, FP64,
- * row-major, the counts of kifmm_set_points; tgt_dev may equal src_dev; they
- * must not be buffers the library returned) are binned into the current
- * tree's leaves and sorted on the GPU, stably by leaf and then by index (the
- * order kifmm_set_points produces).  The box set, the lists and the
- * operators are kept, so the potentials equal those after kifmm_set_points
- * with the same positions whenever that call would build the same box set
- * (every leaf keeps at least one point).  The buffers are read on
- * hip_stream; the call synchronises it.  ESTATE: no points or operators
- * yet, or some point falls outside every current leaf - then nothing has
- * changed and kifmm_set_points is needed; a batch holds the handle.
- * EINVAL: null arguments. */
+ * setting of Section 5.1, where the locational encoding, the index pointers
+ * and the M2L maps are rebuilt each step; Tables 5-6 list that setup cost
+ * as Tree and Map Creation), on the device: the new positions
+ * src_dev[n_src][3] and tgt_dev[n_tgt][3] (device memory, FP64, row-major,
+ * the counts of kifmm_set_points; tgt_dev may equal src_dev; they must not
+ * be buffers the library returned) get their leaf codes in the handle's
+ * domain cube and are sorted on the GPU, stably by leaf (Morton order) and
+ * then by index.  If the leaves are those of the current tree, only the
+ * point order and the leaves' point ranges change.  Otherwise the tree is
+ * rebuilt on the device: the levels (ancestors of the non-empty leaves),
+ * parents and children, the near lists, the interaction lists with their
+ * transfer vectors (Section 2), the sibling-cluster halos and source blocks
+ * of FFT-M2L (Appendix A) and, at the next evaluate, the target tiles of
+ * BLAS / dense M2L with the transfer vectors present (Section 3.2, Step 1);
+ * the work buffers sized by box counts are reallocated.  Every structure,
+ * and so the potentials, equals that of kifmm_set_points with the same
+ * positions and the handle's domain cube (origin and width as resolved at
+ * set_points); box_keys, interactions, near and point_perm read the
+ * device's tree.  The operators are kept.  The buffers are read on
+ * hip_stream; the call synchronises the device.  ESTATE: no points or
+ * operators yet, a batch holds the handle, or some point lies outside the
+ * domain cube (then nothing has changed).  EINVAL: null arguments.
+ * ENOMEM / EDEVICE during a rebuild leave the handle without points
+ * (kifmm_set_points is needed). */
 kifmm_status kifmm_update_points(kifmm_handle* h, const void* src_dev, const void* tgt_dev,
                                  void* hip_stream);
 

@@ -293,11 +293,14 @@ class KiFMM:
 
     def update_points(self, sources, targets=None, stream=None):
         """Move the points on the device (kifmm_update_points): ``sources``
-        (and ``targets``, default the sources) are FP64 device tensors (n, 3)."""
+        (and ``targets``, default the sources) are FP64 device tensors (n, 3)
+        with the counts of set_points; the tree of the new positions over the
+        same domain cube is built on the device."""
         import torch
         tgt = sources if targets is None else targets
-        for a in (sources, tgt):
-            assert a.is_cuda and a.dtype == torch.float64 and a.is_contiguous() and a.shape[1] == 3
+        for a, n in ((sources, self.n_src), (tgt, self.n_tgt)):
+            assert a.is_cuda and a.dtype == torch.float64 and a.is_contiguous()
+            assert a.dim() == 2 and tuple(a.shape) == (n, 3), "points must be (n, 3) as in set_points"
         s = torch.cuda.current_stream(sources.device) if stream is None else stream
         _check(lib().kifmm_update_points(self._h, sources.data_ptr(), tgt.data_ptr(),
                                          ctypes.c_void_p(s.cuda_stream)))

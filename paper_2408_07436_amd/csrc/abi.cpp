@@ -31,7 +31,7 @@ kifmm_status device_autotune(kifmm_handle* h, const void* q, int64_t ldq, int nv
                              int64_t ldphi, hipStream_t s, int reps, double* best_ms);
 kifmm_status device_update_points(kifmm_handle* h, const double* src, const double* tgt,
                                   hipStream_t s);
-kifmm_status refresh_host_points(kifmm_handle* h);
+kifmm_status refresh_host_tree(kifmm_handle* h);
 
 }  // namespace kifmm
 
@@ -97,6 +97,7 @@ kifmm_status kifmm_set_points(kifmm_handle* h, const double* src, int64_t n_src,
   }
   h->has_points = false;
   h->points_on_device = false;
+  h->tree_on_device = false;
   kifmm_status st = kifmm::build_tree(h->tree, h->cfg.depth, h->cfg.origin, h->cfg.width, src, n_src,
                                       tgt, n_tgt);
   if (st != KIFMM_OK) return st;
@@ -198,6 +199,8 @@ kifmm_status kifmm_box_keys(const kifmm_handle* h, int32_t level, uint64_t* keys
   if (!h || !keys) return fail(KIFMM_EINVAL, "null argument");
   if (!h->has_points) return fail(KIFMM_ESTATE, "no points set");
   if (level < 0 || level > h->tree.depth) return fail(KIFMM_EINVAL, "level out of range");
+  kifmm_status st = kifmm::refresh_host_tree(const_cast<kifmm_handle*>(h));
+  if (st != KIFMM_OK) return st;
   const auto& k = h->tree.levels[level].keys;
   if (cap < (int64_t)k.size()) return fail(KIFMM_EINVAL, "capacity too small");
   std::memcpy(keys, k.data(), k.size() * sizeof(uint64_t));
@@ -209,7 +212,7 @@ kifmm_status kifmm_point_perm(const kifmm_handle* h, int32_t which, int64_t* per
   if (!h->has_points) return fail(KIFMM_ESTATE, "no points set");
   if (which != 0 && which != 1) return fail(KIFMM_EINVAL, "which must be 0 or 1");
   // after device updates the host copy is refreshed from the device
-  kifmm_status st = kifmm::refresh_host_points(const_cast<kifmm_handle*>(h));
+  kifmm_status st = kifmm::refresh_host_tree(const_cast<kifmm_handle*>(h));
   if (st != KIFMM_OK) return st;
   const auto& p = which == 0 ? h->tree.src_perm : h->tree.tgt_perm;
   if (cap < (int64_t)p.size()) return fail(KIFMM_EINVAL, "capacity too small");
@@ -222,6 +225,8 @@ kifmm_status kifmm_interactions(const kifmm_handle* h, int32_t level, int64_t* o
   if (!h || !n_pairs) return fail(KIFMM_EINVAL, "null argument");
   if (!h->has_points) return fail(KIFMM_ESTATE, "no points set");
   if (level < 2 || level > h->tree.depth) return fail(KIFMM_EINVAL, "level out of range");
+  kifmm_status st = kifmm::refresh_host_tree(const_cast<kifmm_handle*>(h));
+  if (st != KIFMM_OK) return st;
   const auto& L = h->tree.levels[level];
   *n_pairs = (int64_t)L.il_src.size();
   if (!offs && !src && !tidx) return KIFMM_OK;
@@ -239,6 +244,8 @@ kifmm_status kifmm_near(const kifmm_handle* h, int64_t* offs, int64_t* src, int6
                         int64_t* n_pairs) {
   if (!h || !n_pairs) return fail(KIFMM_EINVAL, "null argument");
   if (!h->has_points) return fail(KIFMM_ESTATE, "no points set");
+  kifmm_status st = kifmm::refresh_host_tree(const_cast<kifmm_handle*>(h));
+  if (st != KIFMM_OK) return st;
   *n_pairs = (int64_t)h->tree.near_src.size();
   if (!offs && !src) return KIFMM_OK;
   if (!offs || !src) return fail(KIFMM_EINVAL, "null array");
@@ -392,6 +399,8 @@ kifmm_status kifmm_m2l_counts(const kifmm_handle* h, int32_t level, int64_t* cou
   if (!h->has_points) return fail(KIFMM_ESTATE, "no points set");
   if (level < 2 || level > h->tree.depth) return fail(KIFMM_EINVAL, "level out of range");
   if (cap < 4) return fail(KIFMM_EINVAL, "capacity too small");
+  kifmm_status st = kifmm::refresh_host_tree(const_cast<kifmm_handle*>(h));
+  if (st != KIFMM_OK) return st;
   const auto& L = h->tree.levels[level];
   counts[0] = L.n;
   counts[1] = (int64_t)L.il_src.size();

@@ -47,6 +47,13 @@ struct DevLevel {
   // (transfer vector j of the class, tile slot), -1 where absent
   int32_t* tile_class = nullptr;
   int32_t* tile_src = nullptr;
+  // a tree built on the device (moving points): keys, parents and the
+  // interaction lists of the level (host layout of Level)
+  uint64_t* keys = nullptr;
+  int32_t* parent = nullptr;
+  int64_t* il_offs = nullptr;
+  int32_t* il_src = nullptr;
+  int16_t* il_t = nullptr;
 };
 
 struct DeviceState {
@@ -57,13 +64,20 @@ struct DeviceState {
   double* src_xyz = nullptr;
   double* tgt_xyz = nullptr;
   int64_t* src_perm = nullptr;
-  // re-setup for moving points: leaf keys of the tree, scratch (lazy)
+  // keys of the leaves (compared with the leaves of moved points)
   uint64_t* leaf_keys = nullptr;
-  int32_t* setup_scratch = nullptr;
-  int32_t* leaf_src = nullptr;
-  int32_t* leaf_tgt = nullptr;
-  int32_t* bad_flag = nullptr;
   int64_t* tgt_perm = nullptr;
+  // device tree build: scratch, totals, lookup tables (transfer index over
+  // (t + 3) in base 7, the 316 vectors as int8 triples, the stacked form's
+  // class slot of each transfer vector); tree_dev once the levels, lists
+  // and maps of the handle were built on the device
+  void* tree_scratch = nullptr;
+  size_t tree_scratch_bytes = 0;
+  int64_t* tree_totals = nullptr;  // [64]
+  int16_t* tmap = nullptr;
+  int8_t* tvec = nullptr;
+  int32_t* jof = nullptr;
+  bool tree_dev = false;
   int32_t *src_start = nullptr, *src_end = nullptr, *tgt_start = nullptr, *tgt_end = nullptr;
   int64_t* near_offs = nullptr;
   int32_t* near_src = nullptr;
@@ -147,6 +161,15 @@ kifmm_status dalloc(DeviceState* d, T** p, size_t count, bool work = false) {
   if (e != hipSuccess) return fail(KIFMM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
   (work ? d->work_allocs : d->allocs).push_back(*p);
   return KIFMM_OK;
+}
+
+// free one allocation of d->allocs (null is ignored) and clear the pointer
+template <typename T>
+void dfree(DeviceState* d, T** p) {
+  if (!*p) return;
+  (void)hipFree((void*)*p);
+  d->allocs.erase(std::remove(d->allocs.begin(), d->allocs.end(), (void*)*p), d->allocs.end());
+  *p = nullptr;
 }
 
 template <typename T>
@@ -442,7 +465,7 @@ kifmm_status pack_blas_stacked(kifmm_handle* h, DeviceState* d) {
 // Target tiles of TB boxes of one octant class per level (boxes of a class
 // share their transfer vectors) and, per tile, the transfer vectors present
 // in ascending order with the source box of each slot.
-kifmm_status build_blas_tiles(kifmm_handle* h, DeviceState* d, int TB) {
+kifmm_status build_blas_tiles_host(kifmm_handle* h, DeviceState* d, int TB) {
   const Tree& t = h->tree;
   for (int l = 2; l <= t.depth; ++l) {
     const Level& L = t.levels[l];
@@ -501,6 +524,111 @@ kifmm_status build_blas_tiles(kifmm_handle* h, DeviceState* d, int TB) {
   }
   d->tile_tb = TB;
   return KIFMM_OK;
+}
+
+// Lookup tables of the device tree build (once per device state).
+kifmm_status tree_tables(DeviceState* d) {
+  if (d->tmap) return KIFMM_OK;
+  std::vector<int16_t> tm(343, -1);
+  std::vector<int8_t> tv(3 * kNumTransfer);
+  for (int it = 0; it < kNumTransfer; ++it) {
+    int t[3];
+    transfer_vector(it, t);
+    tm[(t[0] + 3) * 49 + (t[1] + 3) * 7 + (t[2] + 3)] = (int16_t)it;
+    for (int k = 0; k < 3; ++k) tv[3 * it + k] = (int8_t)t[k];
+  }
+  KIFMM_TRY(upload(d, &d->tmap, tm.data(), tm.size()));
+  KIFMM_TRY(upload(d, &d->tvec, tv.data(), tv.size()));
+  if (d->stack_ok) KIFMM_TRY(upload(d, &d->jof, d->st_jof.data(), d->st_jof.size()));
+  KIFMM_TRY(dalloc(d, &d->tree_totals, 64));
+  return KIFMM_OK;
+}
+
+// The same tiles from a tree built on the device (keys of every level on
+// the device): boxes in stable octant-class order, TB per tile, and per tile
+// the transfer vectors whose source box exists for some slot.
+kifmm_status build_blas_tiles_device(kifmm_handle* h, DeviceState* d, int TB) {
+  const Tree& t = h->tree;
+  KIFMM_TRY(tree_tables(d));
+  const hipStream_t s = nullptr;
+  for (int l = 2; l <= t.depth; ++l) {
+    DevLevel& D = d->lv[l];
+    dfree(d, &D.tile_box);
+    dfree(d, &D.tl_offs);
+    dfree(d, &D.tl_t);
+    dfree(d, &D.tl_src);
+    dfree(d, &D.tile_class);
+    dfree(d, &D.tile_src);
+    D.ntiles = 0;
+    const int64_t n = D.n;
+    int32_t *scr = nullptr, *order = nullptr;
+    int64_t* present = nullptr;
+    auto release = [&] {
+      dfree(d, &scr);
+      dfree(d, &order);
+      dfree(d, &present);
+    };
+    kifmm_status st = dalloc(d, &scr, tree_classes_scratch_ints(n) + 8);
+    if (st == KIFMM_OK) st = dalloc(d, &order, (size_t)n);
+    if (st != KIFMM_OK) {
+      release();
+      return st;
+    }
+    int32_t* counts = scr + tree_classes_scratch_ints(n);
+    int32_t cls[8];
+    hipError_t e = tree_classes(D.keys, n, scr, order, counts, s);
+    if (e == hipSuccess) e = hipMemcpy(cls, counts, sizeof cls, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      release();
+      return fail(KIFMM_EDEVICE, std::string("tile classes: ") + hipGetErrorString(e));
+    }
+    TileClasses tc;
+    int32_t run = 0;
+    int64_t tiles = 0;
+    for (int o = 0; o < 8; ++o) {
+      tc.start[o] = run;
+      tc.count[o] = cls[o];
+      tc.first_tile[o] = tiles;
+      run += cls[o];
+      tiles += (cls[o] + TB - 1) / TB;
+    }
+    tc.first_tile[8] = tiles;
+    st = dalloc(d, &D.tile_box, (size_t)tiles * TB);
+    if (st == KIFMM_OK) st = dalloc(d, &D.tile_class, (size_t)tiles);
+    if (st == KIFMM_OK) st = dalloc(d, &D.tl_offs, (size_t)tiles + 1);
+    if (st == KIFMM_OK) st = dalloc(d, &present, (size_t)tiles * kNumTransfer + 1);
+    if (st != KIFMM_OK) {
+      release();
+      return st;
+    }
+    int64_t total = 0;
+    e = tree_tiles(D.keys, n, l, order, tc, TB, tiles, d->tvec, D.tile_box, D.tile_class, present,
+                   d->tree_totals, s);
+    if (e == hipSuccess) e = hipMemcpy(&total, d->tree_totals, sizeof total, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      release();
+      return fail(KIFMM_EDEVICE, std::string("tiles: ") + hipGetErrorString(e));
+    }
+    st = dalloc(d, &D.tl_t, (size_t)total);
+    if (st == KIFMM_OK) st = dalloc(d, &D.tl_src, (size_t)total * TB);
+    if (st == KIFMM_OK && d->stack_ok) st = dalloc(d, &D.tile_src, (size_t)tiles * d->st_J * TB);
+    if (st != KIFMM_OK) {
+      release();
+      return st;
+    }
+    e = tree_tiles_fill(D.keys, n, l, D.tile_box, D.tile_class, tiles, TB, d->tvec, present, D.tl_t,
+                        D.tl_src, D.tl_offs, d->jof, d->st_J, d->stack_ok ? D.tile_src : nullptr, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    release();
+    if (e != hipSuccess) return fail(KIFMM_EDEVICE, std::string("tile lists: ") + hipGetErrorString(e));
+    D.ntiles = tiles;
+  }
+  d->tile_tb = TB;
+  return KIFMM_OK;
+}
+
+kifmm_status build_blas_tiles(kifmm_handle* h, DeviceState* d, int TB) {
+  return d->tree_dev ? build_blas_tiles_device(h, d, TB) : build_blas_tiles_host(h, d, TB);
 }
 
 // Source blocks of one FFT-M2L level (see DevLevel): clusters grouped by
@@ -1640,9 +1768,155 @@ kifmm_status device_autotune(kifmm_handle* h, const void* q, int64_t ldq, int nv
   return KIFMM_OK;
 }
 
-// Moving points: bin the new positions into the current leaves and sort
-// them on the device; the box set, lists and operators stay.  Nothing is
-// changed unless every point falls into a current leaf.
+// Levels, lists and maps of a tree built on the device (the leaf set
+// changed): everything sized by box counts is reallocated and rebuilt from
+// the sorted codes in tb; n[l] = boxes of level l.
+kifmm_status rebuild_tree(kifmm_handle* h, const TreeBuild& tb, const std::vector<int64_t>& n,
+                          const double* src, const double* tgt, hipStream_t s) {
+  DeviceState* d = h->dev;
+  Tree& t = h->tree;
+  const int depth = t.depth;
+  const bool fft = h->cfg.m2l == KIFMM_M2L_FFT;
+  KIFMM_TRY(tree_tables(d));
+  // the old structures (an evaluate in flight on another stream still reads
+  // them: hipFree waits for the device)
+  KIFMM_HIP(hipDeviceSynchronize());
+  for (DevLevel& D : d->lv) {
+    dfree(d, &D.child);
+    dfree(d, &D.halo);
+    dfree(d, &D.hb_tgt);
+    dfree(d, &D.hb_src);
+    dfree(d, &D.hb_list);
+    dfree(d, &D.hb_tbase);
+    dfree(d, &D.tile_box);
+    dfree(d, &D.tl_offs);
+    dfree(d, &D.tl_t);
+    dfree(d, &D.tl_src);
+    dfree(d, &D.tile_class);
+    dfree(d, &D.tile_src);
+    dfree(d, &D.keys);
+    dfree(d, &D.parent);
+    dfree(d, &D.il_offs);
+    dfree(d, &D.il_src);
+    dfree(d, &D.il_t);
+    D.hb_n = 0;
+    D.ntiles = 0;
+  }
+  dfree(d, &d->src_start);
+  dfree(d, &d->src_end);
+  dfree(d, &d->tgt_start);
+  dfree(d, &d->tgt_end);
+  dfree(d, &d->near_offs);
+  dfree(d, &d->near_src);
+  dfree(d, &d->leaf_centers);
+  dfree(d, &d->leaf_keys);
+  for (void* p : d->work_allocs) (void)hipFree(p);
+  d->work_allocs.clear();
+  d->nvec_cap = 0;
+  d->xi_hi = d->xi_lo = nullptr;
+  d->tile_tb = 0;
+  // from here on the handle holds the new tree; its host arrays are filled
+  // from the device on demand (refresh_host_tree)
+  d->tree_dev = true;
+  h->tree_on_device = true;
+  h->points_on_device = true;
+  for (int l = 0; l <= depth; ++l) {
+    Level& L = t.levels[l];
+    L = Level();
+    L.n = n[l];
+    d->lv[l].n = n[l];
+  }
+  const int64_t nleaf = n[depth];
+  // levels: keys, parents, children
+  for (int l = 0; l <= depth; ++l) {
+    DevLevel& D = d->lv[l];
+    KIFMM_TRY(dalloc(d, &D.keys, (size_t)n[l]));
+    KIFMM_TRY(dalloc(d, &D.parent, (size_t)n[l]));
+    if (l < depth) KIFMM_TRY(dalloc(d, &D.child, (size_t)8 * n[l] + 8));
+  }
+  for (int l = 0; l <= depth; ++l)
+    KIFMM_LAUNCH(tree_level(tb.code[l], tb.parent[l], n[l], l, d->lv[l].keys, d->lv[l].parent,
+                            l > 0 ? d->lv[l - 1].child : nullptr, l > 0 ? n[l - 1] : 0, s));
+  // leaves: points, ranges, centres, keys
+  KIFMM_TRY(dalloc(d, &d->src_start, (size_t)nleaf));
+  KIFMM_TRY(dalloc(d, &d->src_end, (size_t)nleaf));
+  KIFMM_TRY(dalloc(d, &d->tgt_start, (size_t)nleaf));
+  KIFMM_TRY(dalloc(d, &d->tgt_end, (size_t)nleaf));
+  KIFMM_TRY(dalloc(d, &d->leaf_centers, (size_t)3 * nleaf));
+  KIFMM_TRY(dalloc(d, &d->leaf_keys, (size_t)nleaf));
+  KIFMM_TRY(dalloc(d, &d->near_offs, (size_t)nleaf + 1));
+  KIFMM_LAUNCH(tree_finish_points(src, tb.code_src, tb.order_src, t.n_src, tb.code[depth], nleaf,
+                                  d->src_perm, d->src_xyz, d->src_start, d->src_end, s));
+  KIFMM_LAUNCH(tree_finish_points(tgt, tb.code_tgt, tb.order_tgt, t.n_tgt, tb.code[depth], nleaf,
+                                  d->tgt_perm, d->tgt_xyz, d->tgt_start, d->tgt_end, s));
+  KIFMM_LAUNCH(tree_centers(d->lv[depth].keys, nleaf, depth, t.origin, t.width / std::ldexp(1.0, depth),
+                            d->leaf_centers, s));
+  KIFMM_HIP(hipMemcpyAsync(d->leaf_keys, d->lv[depth].keys, (size_t)nleaf * sizeof(uint64_t),
+                           hipMemcpyDeviceToDevice, s));
+  // counts of the lists and the FFT-M2L source blocks
+  int64_t nmax = 0;
+  for (int l = 0; l <= depth; ++l) nmax = std::max(nmax, n[l]);
+  int32_t* flag = nullptr;  // scratch of the block builds (freed at the end, or with the state)
+  KIFMM_TRY(dalloc(d, &flag, (size_t)nmax + 1));
+  int32_t* tot32 = reinterpret_cast<int32_t*>(d->tree_totals + 40);  // [2][17] int32 past the int64 totals
+  for (int l = 2; l <= depth; ++l) {
+    DevLevel& D = d->lv[l];
+    const DevLevel& U = d->lv[l - 1];
+    KIFMM_TRY(dalloc(d, &D.halo, (size_t)kNumDirections * n[l - 1]));
+    KIFMM_LAUNCH(tree_halo(U.keys, n[l - 1], l - 1, D.halo, s));
+    KIFMM_TRY(dalloc(d, &D.il_offs, (size_t)n[l] + 1));
+    KIFMM_LAUNCH(tree_interactions(D.keys, n[l], D.parent, U.keys, n[l - 1], U.child, l, d->tmap,
+                                   D.il_offs, d->tree_totals + l, nullptr, nullptr, s));
+    if (fft) {
+      KIFMM_TRY(dalloc(d, &D.hb_tgt, (size_t)n[l - 1] + 1));
+      KIFMM_TRY(dalloc(d, &D.hb_tbase, (size_t)n[l - 1]));
+      KIFMM_LAUNCH(tree_blocks(U.keys, n[l - 1], l - 1, flag, D.hb_tgt, D.hb_tbase, tot32 + l, s));
+    }
+  }
+  KIFMM_LAUNCH(tree_near(d->lv[depth].keys, nleaf, depth, d->near_offs, d->tree_totals + 20, nullptr, s));
+  int64_t tot[40];
+  KIFMM_HIP(hipMemcpyAsync(tot, d->tree_totals, sizeof tot, hipMemcpyDeviceToHost, s));
+  int32_t t32[34];
+  KIFMM_HIP(hipMemcpyAsync(t32, tot32, sizeof t32, hipMemcpyDeviceToHost, s));
+  KIFMM_HIP(hipStreamSynchronize(s));
+  // the lists and the block source counts
+  for (int l = 2; l <= depth; ++l) {
+    DevLevel& D = d->lv[l];
+    const DevLevel& U = d->lv[l - 1];
+    KIFMM_TRY(dalloc(d, &D.il_src, (size_t)tot[l]));
+    KIFMM_TRY(dalloc(d, &D.il_t, (size_t)tot[l]));
+    KIFMM_LAUNCH(tree_interactions(D.keys, n[l], D.parent, U.keys, n[l - 1], U.child, l, d->tmap,
+                                   D.il_offs, nullptr, D.il_src, D.il_t, s));
+    if (fft) {
+      D.hb_n = t32[l];
+      KIFMM_TRY(dalloc(d, &D.hb_src, (size_t)D.hb_n + 1));
+      KIFMM_LAUNCH(tree_block_lists(U.keys, n[l - 1], l - 1, D.hb_tgt, D.hb_n, flag, D.hb_src,
+                                    tot32 + 17 + l, nullptr, s));
+    }
+  }
+  KIFMM_TRY(dalloc(d, &d->near_src, (size_t)tot[20]));
+  KIFMM_LAUNCH(tree_near(d->lv[depth].keys, nleaf, depth, d->near_offs, nullptr, d->near_src, s));
+  if (fft) {
+    KIFMM_HIP(hipMemcpyAsync(t32, tot32, sizeof t32, hipMemcpyDeviceToHost, s));
+    KIFMM_HIP(hipStreamSynchronize(s));
+    for (int l = 2; l <= depth; ++l) {
+      DevLevel& D = d->lv[l];
+      KIFMM_TRY(dalloc(d, &D.hb_list, (size_t)1 + t32[17 + l]));
+      KIFMM_LAUNCH(tree_block_lists(d->lv[l - 1].keys, n[l - 1], l - 1, D.hb_tgt, D.hb_n, nullptr,
+                                    D.hb_src, nullptr, D.hb_list, s));
+    }
+  }
+  KIFMM_HIP(hipStreamSynchronize(s));
+  dfree(d, &flag);
+  return KIFMM_OK;
+}
+
+// Moving points (the dynamic-particle setting of Section 5.1): the tree of
+// the new positions over the handle's domain cube is built on the device.
+// When the leaves are those of the current tree only the point order and
+// the leaves' point ranges change; otherwise the levels, the near and
+// interaction lists and the M2L maps are rebuilt on the device.  Nothing
+// changes if a point lies outside the domain cube.
 kifmm_status device_update_points(kifmm_handle* h, const double* src, const double* tgt,
                                   hipStream_t s) {
   if (!h->dev) {
@@ -1661,47 +1935,100 @@ kifmm_status device_update_points(kifmm_handle* h, const double* src, const doub
   DeviceState* d = h->dev;
   KIFMM_HIP(hipSetDevice(d->device));
   const Tree& t = h->tree;
-  const Level& L = t.levels[t.depth];
-  const int64_t nmax = std::max(t.n_src, t.n_tgt);
-  if (!d->setup_scratch) {
-    KIFMM_TRY(dalloc(d, &d->setup_scratch, sort_scratch_ints(nmax, L.n)));
-    KIFMM_TRY(dalloc(d, &d->leaf_src, (size_t)t.n_src));
-    KIFMM_TRY(dalloc(d, &d->leaf_tgt, (size_t)t.n_tgt));
-    KIFMM_TRY(dalloc(d, &d->bad_flag, 1));
+  const int depth = t.depth;
+  const size_t need = tree_scratch_bytes(t.n_src, t.n_tgt, depth);
+  if (d->tree_scratch_bytes < need) {
+    dfree(d, &d->tree_scratch);
+    d->tree_scratch_bytes = 0;
+    char* p = nullptr;
+    KIFMM_TRY(dalloc(d, &p, need));
+    d->tree_scratch = p;
+    d->tree_scratch_bytes = need;
   }
-  KIFMM_HIP(hipMemsetAsync(d->bad_flag, 0, sizeof(int32_t), s));
-  KIFMM_LAUNCH(launch_point_leaf(src, t.n_src, d->leaf_keys, L.n, t.depth, t.origin, t.width,
-                                 d->leaf_src, d->bad_flag, s));
-  KIFMM_LAUNCH(launch_point_leaf(tgt, t.n_tgt, d->leaf_keys, L.n, t.depth, t.origin, t.width,
-                                 d->leaf_tgt, d->bad_flag, s));
-  int32_t bad = 0;
-  KIFMM_HIP(hipMemcpyAsync(&bad, d->bad_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  const int64_t n_old = d->lv[depth].n;
+  TreeBuild tb;
+  KIFMM_LAUNCH(tree_sort_and_levels(src, t.n_src, tgt, t.n_tgt, depth, t.origin, t.width, d->leaf_keys,
+                                    n_old, d->tree_scratch, tb, s));
+  int32_t cnt[2 + 17];
+  KIFMM_HIP(hipMemcpyAsync(cnt, tb.counts, sizeof cnt, hipMemcpyDeviceToHost, s));
   KIFMM_HIP(hipStreamSynchronize(s));
-  if (bad) return fail(KIFMM_ESTATE, "a point lies outside the current leaves; call kifmm_set_points");
-  KIFMM_LAUNCH(launch_sort_by_leaf(src, d->leaf_src, t.n_src, L.n, d->setup_scratch, d->src_perm,
-                                   d->src_xyz, d->src_start, d->src_end, s));
-  KIFMM_LAUNCH(launch_sort_by_leaf(tgt, d->leaf_tgt, t.n_tgt, L.n, d->setup_scratch, d->tgt_perm,
-                                   d->tgt_xyz, d->tgt_start, d->tgt_end, s));
+  if (cnt[0]) return fail(KIFMM_ESTATE, "a point lies outside the domain cube; call kifmm_set_points");
+  if (cnt[1]) {
+    std::vector<int64_t> n(depth + 1);
+    for (int l = 0; l <= depth; ++l) n[l] = cnt[2 + l];
+    const kifmm_status st = rebuild_tree(h, tb, n, src, tgt, s);
+    if (st != KIFMM_OK) {
+      // a partly rebuilt tree is not usable: the handle needs new points
+      destroy_device(h->dev);
+      h->dev = nullptr;
+      h->has_points = false;
+      h->points_on_device = false;
+      h->tree_on_device = false;
+    }
+    return st;
+  }
+  // the same leaves: new point order and ranges
+  KIFMM_LAUNCH(tree_finish_points(src, tb.code_src, tb.order_src, t.n_src, tb.code[depth], n_old,
+                                  d->src_perm, d->src_xyz, d->src_start, d->src_end, s));
+  KIFMM_LAUNCH(tree_finish_points(tgt, tb.code_tgt, tb.order_tgt, t.n_tgt, tb.code[depth], n_old,
+                                  d->tgt_perm, d->tgt_xyz, d->tgt_start, d->tgt_end, s));
+  KIFMM_HIP(hipStreamSynchronize(s));
   h->points_on_device = true;
   return KIFMM_OK;
 }
 
-// The device's point order back into the host tree (after device updates).
-kifmm_status refresh_host_points(kifmm_handle* h) {
-  if (!h->points_on_device || !h->dev) return KIFMM_OK;
+// The host tree from the device after device updates: the point order and
+// ranges, and after a rebuild the levels and lists too.
+kifmm_status refresh_host_tree(kifmm_handle* h) {
+  if ((!h->points_on_device && !h->tree_on_device) || !h->dev) return KIFMM_OK;
   DeviceState* d = h->dev;
   Tree& t = h->tree;
+  const int depth = t.depth;
   KIFMM_HIP(hipSetDevice(d->device));
   KIFMM_HIP(hipDeviceSynchronize());
-  KIFMM_HIP(hipMemcpy(t.src_perm.data(), d->src_perm, t.src_perm.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
-  KIFMM_HIP(hipMemcpy(t.tgt_perm.data(), d->tgt_perm, t.tgt_perm.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
-  KIFMM_HIP(hipMemcpy(t.src_sorted.data(), d->src_xyz, t.src_sorted.size() * sizeof(double), hipMemcpyDeviceToHost));
-  KIFMM_HIP(hipMemcpy(t.tgt_sorted.data(), d->tgt_xyz, t.tgt_sorted.size() * sizeof(double), hipMemcpyDeviceToHost));
-  KIFMM_HIP(hipMemcpy(t.src_start.data(), d->src_start, t.src_start.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-  KIFMM_HIP(hipMemcpy(t.src_end.data(), d->src_end, t.src_end.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-  KIFMM_HIP(hipMemcpy(t.tgt_start.data(), d->tgt_start, t.tgt_start.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-  KIFMM_HIP(hipMemcpy(t.tgt_end.data(), d->tgt_end, t.tgt_end.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  auto down = [](auto& v, const auto* p, size_t count) -> hipError_t {
+    v.resize(count);
+    return count ? hipMemcpy(v.data(), p, count * sizeof(v[0]), hipMemcpyDeviceToHost) : hipSuccess;
+  };
+  const size_t nleaf = (size_t)d->lv[depth].n;
+  KIFMM_HIP(down(t.src_perm, d->src_perm, (size_t)t.n_src));
+  KIFMM_HIP(down(t.tgt_perm, d->tgt_perm, (size_t)t.n_tgt));
+  KIFMM_HIP(down(t.src_sorted, d->src_xyz, (size_t)3 * t.n_src));
+  KIFMM_HIP(down(t.tgt_sorted, d->tgt_xyz, (size_t)3 * t.n_tgt));
+  KIFMM_HIP(down(t.src_start, d->src_start, nleaf));
+  KIFMM_HIP(down(t.src_end, d->src_end, nleaf));
+  KIFMM_HIP(down(t.tgt_start, d->tgt_start, nleaf));
+  KIFMM_HIP(down(t.tgt_end, d->tgt_end, nleaf));
+  if (h->tree_on_device) {
+    for (int l = 0; l <= depth; ++l) {
+      Level& L = t.levels[l];
+      const DevLevel& D = d->lv[l];
+      const size_t nl = (size_t)D.n;
+      KIFMM_HIP(down(L.keys, D.keys, nl));
+      KIFMM_HIP(down(L.parent, D.parent, nl));
+      L.anchor.resize(3 * nl);
+      for (size_t i = 0; i < nl; ++i) {
+        int32_t* a = &L.anchor[3 * i];
+        a[0] = a[1] = a[2] = 0;
+        for (int b = 0; b < l; ++b)
+          for (int k = 0; k < 3; ++k) a[k] |= (int32_t)((L.keys[i] >> (3 * b + k)) & 1) << b;
+      }
+      if (l < depth) KIFMM_HIP(down(L.child, D.child, 8 * nl));
+      if (l >= 2) {
+        KIFMM_HIP(down(L.il_offs, D.il_offs, nl + 1));
+        KIFMM_HIP(down(L.il_src, D.il_src, (size_t)L.il_offs[nl]));
+        KIFMM_HIP(down(L.il_t, D.il_t, (size_t)L.il_offs[nl]));
+        const int32_t nc = (int32_t)d->lv[l - 1].n;
+        KIFMM_HIP(down(L.halo, D.halo, (size_t)kNumDirections * nc));
+        for (int32_t& x : L.halo)
+          if (x == nc) x = -1;
+      }
+    }
+    KIFMM_HIP(down(t.near_offs, d->near_offs, nleaf + 1));
+    KIFMM_HIP(down(t.near_src, d->near_src, (size_t)t.near_offs[nleaf]));
+  }
   h->points_on_device = false;
+  h->tree_on_device = false;
   return KIFMM_OK;
 }
 

@@ -207,6 +207,7 @@ struct kifmm_handle {
   double timings[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   int32_t tune[KIFMM_TUNE_COUNT] = {0, 0, 0, 0};  // autotuning knobs (kifmm.h)
   bool points_on_device = false;  // host copies of the point order are stale
+  bool tree_on_device = false;    // host copies of the levels and lists are stale
   kifmm::SvdOptions svd;          // K_fat compression (BLAS-M2L)
   // batches alive that hold this handle: their launches read the handle's
   // device buffers by address, so nothing may free or rebuild them meanwhile

@@ -68,21 +68,84 @@ void plan_leaf_eval(const double* tgt_xyz, const double* src_xyz, double leaf_w,
 hipError_t launch_leaf_eval_group(int inst, const LeafArgs* jobs, const int64_t* pre, int nj,
                                   int64_t blocks, hipStream_t stream);
 
-// ---- device re-setup for moving points -------------------------------------
-// leaf[i] = index of point i's leaf in the sorted leaf keys of the given
-// depth, or -1 (and *bad = 1) if the point is outside the domain cube or its
-// leaf is not among the keys.
-hipError_t launch_point_leaf(const double* pts, int64_t n, const uint64_t* leaf_keys,
-                             int64_t n_leaf, int depth, const double origin[3], double width,
-                             int32_t* leaf, int32_t* bad, hipStream_t s);
-// int32 scratch entries launch_sort_by_leaf needs for n points and n_leaf leaves.
-size_t sort_scratch_ints(int64_t n, int64_t n_leaf);
-// Stable sort of pts[n][3] by leaf (every leaf[i] in [0, n_leaf)): perm[i]
-// = original index at sorted position i, sorted[n][3], and per leaf the
-// range [start, end) of its points.  pts must not alias the outputs.
-hipError_t launch_sort_by_leaf(const double* pts, const int32_t* leaf, int64_t n, int64_t n_leaf,
-                               int32_t* scratch, int64_t* perm, double* sorted, int32_t* start,
-                               int32_t* end, hipStream_t s);
+// ---- device re-setup for moving points (k_setup.hip) ------------------------
+// Codes are Morton codes without the sentinel bit; level keys carry it at
+// bit 3 l (the host tree's keys).  Every launcher enqueues on s.
+
+// Device results of tree_sort_and_levels (pointers into the scratch):
+// sorted leaf codes of the points with the original index of each sorted
+// position, the codes of every level's boxes and each box's parent index,
+// and counts[]: [0] 1 if a point lies outside the domain cube, [1] 1 if the
+// leaf set differs from the given old one, [2 + l] boxes of level l.
+struct TreeBuild {
+  const uint64_t* code_src = nullptr;
+  const int32_t* order_src = nullptr;
+  const uint64_t* code_tgt = nullptr;
+  const int32_t* order_tgt = nullptr;
+  const uint64_t* code[17] = {};
+  const int32_t* parent[17] = {};
+  int32_t* counts = nullptr;
+};
+// Bytes of scratch tree_sort_and_levels needs.
+size_t tree_scratch_bytes(int64_t n_src, int64_t n_tgt, int depth);
+// Leaf codes of the points (domain cube [origin, origin + width]^3, depth
+// levels), a stable sort by code (ties keep the input order), the leaves
+// (union of the source and target leaves) and their ancestors.
+hipError_t tree_sort_and_levels(const double* src, int64_t n_src, const double* tgt, int64_t n_tgt,
+                                int depth, const double origin[3], double width,
+                                const uint64_t* old_leaf_keys, int64_t n_old, void* scratch,
+                                TreeBuild& out, hipStream_t s);
+// perm / sorted points in code order and each leaf's range [start, end).
+hipError_t tree_finish_points(const double* pts, const uint64_t* code, const int32_t* order, int64_t n,
+                              const uint64_t* leaf_code, int64_t n_leaf, int64_t* perm, double* sorted,
+                              int32_t* start, int32_t* end, hipStream_t s);
+// Keys and parents of level `level` (n boxes) and, when child_up is given,
+// the children [8 n_up + 8] of level - 1 (an empty cluster past the end).
+hipError_t tree_level(const uint64_t* code, const int32_t* parent, int64_t n, int level,
+                      uint64_t* keys, int32_t* parent_out, int32_t* child_up, int64_t n_up,
+                      hipStream_t s);
+// Leaf centres origin + (anchor + 1/2) w.
+hipError_t tree_centers(const uint64_t* keys, int64_t n, int depth, const double origin[3], double w,
+                        double* c, hipStream_t s);
+// Sibling-cluster halos [26][n] of the boxes of `level` (n where absent).
+hipError_t tree_halo(const uint64_t* keys, int64_t n, int level, int32_t* halo, hipStream_t s);
+// Interaction lists of level `level` >= 2: with tidx == nullptr, offs[n + 1]
+// and *total; else src / tidx (transfer index, tmap over (t + 3) in base 7).
+hipError_t tree_interactions(const uint64_t* keys, int64_t n, const int32_t* parent,
+                             const uint64_t* keys_up, int64_t n_up, const int32_t* child_up, int level,
+                             const int16_t* tmap, int64_t* offs, int64_t* total, int32_t* src,
+                             int16_t* tidx, hipStream_t s);
+// Near fields of the leaves: with src == nullptr offs[n + 1] and *total, else src.
+hipError_t tree_near(const uint64_t* keys, int64_t n, int depth, int64_t* offs, int64_t* total,
+                     int32_t* src, hipStream_t s);
+// FFT-M2L source blocks over the clusters (boxes of `level`): block firsts
+// tgt[nblk + 1], tbase[n], counts[0] = nblk (flag: n ints of scratch).
+hipError_t tree_blocks(const uint64_t* keys, int64_t n, int level, int32_t* flag, int32_t* tgt,
+                       int32_t* tbase, int32_t* counts, hipStream_t s);
+// Block source lists: with list == nullptr src[nblk + 1] and *total (cnt:
+// nblk ints of scratch), else list[1 + total].
+hipError_t tree_block_lists(const uint64_t* keys, int64_t n, int level, const int32_t* tgt, int64_t nblk,
+                            int32_t* cnt, int32_t* src, int32_t* total, int32_t* list, hipStream_t s);
+// Boxes in stable octant-class order (order[n]) and counts[8] per class.
+size_t tree_classes_scratch_ints(int64_t n);
+hipError_t tree_classes(const uint64_t* keys, int64_t n, int32_t* scratch, int32_t* order,
+                        int32_t* counts, hipStream_t s);
+struct TileClasses {
+  int32_t start[8];       // first position of class o in the class order
+  int32_t count[8];       // boxes of class o
+  int64_t first_tile[9];  // first tile of class o; [8] = number of tiles
+};
+// BLAS / dense target tiles of TB boxes per class: tile_box, tile_class and
+// the offsets of the transfer vectors present (present[ntiles * 316 + 1],
+// exclusive positions, *total), tvec = the 316 vectors as int8 triples.
+hipError_t tree_tiles(const uint64_t* keys, int64_t n, int level, const int32_t* order,
+                      const TileClasses& tc, int TB, int64_t ntiles, const int8_t* tvec,
+                      int32_t* tile_box, int32_t* tile_class, int64_t* present, int64_t* total,
+                      hipStream_t s);
+hipError_t tree_tiles_fill(const uint64_t* keys, int64_t n, int level, const int32_t* tile_box,
+                           const int32_t* tile_class, int64_t ntiles, int TB, const int8_t* tvec,
+                           const int64_t* pos, int32_t* tl_t, int32_t* tl_src, int64_t* tl_offs,
+                           const int32_t* jof, int J, int32_t* tile_src, hipStream_t s);
 
 // FP64 GEMM with gathered columns: C(:, col) = alpha * A * B(:, col) (+ C).
 // Columns are (box, v) pairs, col = box * nvec + v.  B's row k of column
