@@ -74,6 +74,7 @@ struct DeviceState {
   void* tree_scratch = nullptr;
   size_t tree_scratch_bytes = 0;
   int64_t* tree_totals = nullptr;  // [64]
+  int64_t* tree_part = nullptr;    // [kTreeScanPart] prefix-sum partials
   int16_t* tmap = nullptr;
   int8_t* tvec = nullptr;
   int32_t* jof = nullptr;
@@ -541,6 +542,7 @@ kifmm_status tree_tables(DeviceState* d) {
   KIFMM_TRY(upload(d, &d->tvec, tv.data(), tv.size()));
   if (d->stack_ok) KIFMM_TRY(upload(d, &d->jof, d->st_jof.data(), d->st_jof.size()));
   KIFMM_TRY(dalloc(d, &d->tree_totals, 64));
+  KIFMM_TRY(dalloc(d, &d->tree_part, kTreeScanPart));
   return KIFMM_OK;
 }
 
@@ -576,7 +578,7 @@ kifmm_status build_blas_tiles_device(kifmm_handle* h, DeviceState* d, int TB) {
     }
     int32_t* counts = scr + tree_classes_scratch_ints(n);
     int32_t cls[8];
-    hipError_t e = tree_classes(D.keys, n, scr, order, counts, s);
+    hipError_t e = tree_classes(D.keys, n, scr, order, counts, d->tree_part, s);
     if (e == hipSuccess) e = hipMemcpy(cls, counts, sizeof cls, hipMemcpyDeviceToHost);
     if (e != hipSuccess) {
       release();
@@ -603,7 +605,7 @@ kifmm_status build_blas_tiles_device(kifmm_handle* h, DeviceState* d, int TB) {
     }
     int64_t total = 0;
     e = tree_tiles(D.keys, n, l, order, tc, TB, tiles, d->tvec, D.tile_box, D.tile_class, present,
-                   d->tree_totals, s);
+                   d->tree_totals, d->tree_part, s);
     if (e == hipSuccess) e = hipMemcpy(&total, d->tree_totals, sizeof total, hipMemcpyDeviceToHost);
     if (e != hipSuccess) {
       release();
@@ -1866,14 +1868,15 @@ kifmm_status rebuild_tree(kifmm_handle* h, const TreeBuild& tb, const std::vecto
     KIFMM_LAUNCH(tree_halo(U.keys, n[l - 1], l - 1, D.halo, s));
     KIFMM_TRY(dalloc(d, &D.il_offs, (size_t)n[l] + 1));
     KIFMM_LAUNCH(tree_interactions(D.keys, n[l], D.parent, U.keys, n[l - 1], U.child, l, d->tmap,
-                                   D.il_offs, d->tree_totals + l, nullptr, nullptr, s));
+                                   D.il_offs, d->tree_totals + l, nullptr, nullptr, d->tree_part, s));
     if (fft) {
       KIFMM_TRY(dalloc(d, &D.hb_tgt, (size_t)n[l - 1] + 1));
       KIFMM_TRY(dalloc(d, &D.hb_tbase, (size_t)n[l - 1]));
-      KIFMM_LAUNCH(tree_blocks(U.keys, n[l - 1], l - 1, flag, D.hb_tgt, D.hb_tbase, tot32 + l, s));
+      KIFMM_LAUNCH(tree_blocks(U.keys, n[l - 1], l - 1, flag, D.hb_tgt, D.hb_tbase, tot32 + l, d->tree_part, s));
     }
   }
-  KIFMM_LAUNCH(tree_near(d->lv[depth].keys, nleaf, depth, d->near_offs, d->tree_totals + 20, nullptr, s));
+  KIFMM_LAUNCH(tree_near(d->lv[depth].keys, nleaf, depth, d->near_offs, d->tree_totals + 20, nullptr,
+                         d->tree_part, s));
   int64_t tot[40];
   KIFMM_HIP(hipMemcpyAsync(tot, d->tree_totals, sizeof tot, hipMemcpyDeviceToHost, s));
   int32_t t32[34];
@@ -1886,16 +1889,17 @@ kifmm_status rebuild_tree(kifmm_handle* h, const TreeBuild& tb, const std::vecto
     KIFMM_TRY(dalloc(d, &D.il_src, (size_t)tot[l]));
     KIFMM_TRY(dalloc(d, &D.il_t, (size_t)tot[l]));
     KIFMM_LAUNCH(tree_interactions(D.keys, n[l], D.parent, U.keys, n[l - 1], U.child, l, d->tmap,
-                                   D.il_offs, nullptr, D.il_src, D.il_t, s));
+                                   D.il_offs, nullptr, D.il_src, D.il_t, d->tree_part, s));
     if (fft) {
       D.hb_n = t32[l];
       KIFMM_TRY(dalloc(d, &D.hb_src, (size_t)D.hb_n + 1));
       KIFMM_LAUNCH(tree_block_lists(U.keys, n[l - 1], l - 1, D.hb_tgt, D.hb_n, flag, D.hb_src,
-                                    tot32 + 17 + l, nullptr, s));
+                                    tot32 + 17 + l, nullptr, d->tree_part, s));
     }
   }
   KIFMM_TRY(dalloc(d, &d->near_src, (size_t)tot[20]));
-  KIFMM_LAUNCH(tree_near(d->lv[depth].keys, nleaf, depth, d->near_offs, nullptr, d->near_src, s));
+  KIFMM_LAUNCH(tree_near(d->lv[depth].keys, nleaf, depth, d->near_offs, nullptr, d->near_src,
+                         d->tree_part, s));
   if (fft) {
     KIFMM_HIP(hipMemcpyAsync(t32, tot32, sizeof t32, hipMemcpyDeviceToHost, s));
     KIFMM_HIP(hipStreamSynchronize(s));
@@ -1903,7 +1907,7 @@ kifmm_status rebuild_tree(kifmm_handle* h, const TreeBuild& tb, const std::vecto
       DevLevel& D = d->lv[l];
       KIFMM_TRY(dalloc(d, &D.hb_list, (size_t)1 + t32[17 + l]));
       KIFMM_LAUNCH(tree_block_lists(d->lv[l - 1].keys, n[l - 1], l - 1, D.hb_tgt, D.hb_n, nullptr,
-                                    D.hb_src, nullptr, D.hb_list, s));
+                                    D.hb_src, nullptr, D.hb_list, d->tree_part, s));
     }
   }
   KIFMM_HIP(hipStreamSynchronize(s));

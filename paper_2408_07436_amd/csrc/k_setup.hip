@@ -20,7 +20,6 @@ namespace {
 constexpr int kSortThreads = 256;  // one element per thread per sub-tile
 constexpr int kSortTiles = 8;      // sub-tiles per workgroup
 constexpr int kSortChunk = kSortThreads * kSortTiles;
-constexpr int kScanThreads = 1024;
 constexpr int kNumT = 316;         // transfer vectors of the M2L
 constexpr int kThreads = 256;
 
@@ -113,37 +112,119 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(
   hist[(int64_t)tid * nb + blockIdx.x] = h[tid];
 }
 
-// exclusive prefix sum of a[0, m) in place (one workgroup), m = *mdev when
-// given (at most m_cap); the sum goes to *total when given
+// ---- exclusive prefix sums over the whole device ------------------------------
+// a[0, m) in place, m = *mdev when given (at most m_cap), the sum to *total
+// when given.  G <= kScanGroups workgroups each take a contiguous run of
+// 1024-element tiles: per-workgroup sums (part[G]), one workgroup scans
+// them, then each workgroup rescans its run with its offset.
+
+constexpr int kScanTile = 4 * kThreads;  // 4 consecutive elements per thread
+constexpr int kScanGroups = kTreeScanPart;
+
 template <typename T>
-__global__ __launch_bounds__(kScanThreads) void scan_kernel(T* __restrict__ a, int64_t m_cap,
-                                                            const int32_t* __restrict__ mdev,
-                                                            T* __restrict__ total) {
-  __shared__ T part[kScanThreads];
-  const int tid = threadIdx.x;
+__device__ inline T wave_inclusive(T x, int lane) {
+  for (int d = 1; d < 64; d <<= 1) {
+    const T y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+// exclusive prefix of x over the workgroup (kThreads threads) and the total
+template <typename T>
+__device__ inline T block_exclusive(T x, T* wsum, T& total) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const T inc = wave_inclusive(x, lane);
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  T pre = 0;
+  total = 0;
+  for (int w = 0; w < kThreads / 64; ++w) {
+    if (w < wave) pre += wsum[w];
+    total += wsum[w];
+  }
+  __syncthreads();
+  return pre + inc - x;
+}
+
+__device__ inline void scan_range(int64_t m, int G, int g, int64_t& t0, int64_t& t1) {
+  const int64_t tiles = (m + kScanTile - 1) / kScanTile;
+  const int64_t per = (tiles + G - 1) / G;
+  t0 = min((int64_t)g * per, tiles);
+  t1 = min(t0 + per, tiles);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void scan_reduce_kernel(const T* __restrict__ a, int64_t m_cap,
+                                                               const int32_t* __restrict__ mdev,
+                                                               T* __restrict__ part, int G) {
+  __shared__ T wsum[kThreads / 64];
   const int64_t m = mdev ? min((int64_t)*mdev, m_cap) : m_cap;
-  const int64_t per = (m + kScanThreads - 1) / kScanThreads;
-  const int64_t lo = min((int64_t)tid * per, m), hi = min(lo + per, m);
+  int64_t t0, t1;
+  scan_range(m, G, blockIdx.x, t0, t1);
   T sum = 0;
-  for (int64_t i = lo; i < hi; ++i) sum += a[i];
-  part[tid] = sum;
-  __syncthreads();
-  if (tid == 0) {
-    T run = 0;
-    for (int k = 0; k < kScanThreads; ++k) {
-      const T v = part[k];
-      part[k] = run;
-      run += v;
+  for (int64_t t = t0; t < t1; ++t)
+    for (int k = 0; k < 4; ++k) {
+      const int64_t i = t * kScanTile + k * kThreads + threadIdx.x;
+      if (i < m) sum += a[i];
     }
-    if (total) *total = run;
-  }
+  T total;
+  (void)block_exclusive(sum, wsum, total);
+  if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanGroups) void scan_part_kernel(T* __restrict__ part, int G,
+                                                                T* __restrict__ total) {
+  __shared__ T wsum[kScanGroups / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const T x = tid < G ? part[tid] : T(0);
+  const T inc = wave_inclusive(x, lane);
+  if (lane == 63) wsum[wave] = inc;
   __syncthreads();
-  T run = part[tid];
-  for (int64_t i = lo; i < hi; ++i) {
-    const T v = a[i];
-    a[i] = run;
-    run += v;
+  T pre = 0, all = 0;
+  for (int w = 0; w < kScanGroups / 64; ++w) {
+    if (w < wave) pre += wsum[w];
+    all += wsum[w];
   }
+  if (tid < G) part[tid] = pre + inc - x;
+  if (tid == 0 && total) *total = all;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void scan_apply_kernel(T* __restrict__ a, int64_t m_cap,
+                                                              const int32_t* __restrict__ mdev,
+                                                              const T* __restrict__ part, int G) {
+  __shared__ T wsum[kThreads / 64];
+  const int64_t m = mdev ? min((int64_t)*mdev, m_cap) : m_cap;
+  int64_t t0, t1;
+  scan_range(m, G, blockIdx.x, t0, t1);
+  T carry = part[blockIdx.x];
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t base = t * kScanTile + 4 * (int64_t)threadIdx.x;
+    T v[4];
+    T sum = 0;
+    for (int k = 0; k < 4; ++k) {
+      v[k] = base + k < m ? a[base + k] : T(0);
+      sum += v[k];
+    }
+    T total;
+    T run = carry + block_exclusive(sum, wsum, total);
+    for (int k = 0; k < 4; ++k) {
+      if (base + k < m) a[base + k] = run;
+      run += v[k];
+    }
+    carry += total;
+  }
+}
+
+template <typename T>
+void device_scan(T* a, int64_t m_cap, const int32_t* mdev, T* total, T* part, hipStream_t s) {
+  const int64_t tiles = std::max<int64_t>(1, (m_cap + kScanTile - 1) / kScanTile);
+  const int G = (int)std::min<int64_t>(kScanGroups, tiles);
+  scan_reduce_kernel<T><<<G, kThreads, 0, s>>>(a, m_cap, mdev, part, G);
+  scan_part_kernel<T><<<1, kScanGroups, 0, s>>>(part, G, total);
+  scan_apply_kernel<T><<<G, kThreads, 0, s>>>(a, m_cap, mdev, part, G);
 }
 
 // stable scatter by one 8-bit digit: within a workgroup's chunk, elements
@@ -344,32 +425,13 @@ __global__ void halo_kernel(const uint64_t* __restrict__ keys, int64_t n, int le
       }
 }
 
-// The parents' neighbours of box i (level l >= 2) in ascending index order:
-// their children are then in ascending index order too (children keys
-// extend their parent's key, and both levels are sorted).
-__device__ inline int parent_neighbours(const uint64_t* __restrict__ keys_up, int64_t n_up, int level,
-                                        int32_t p, int32_t nb[27]) {
-  int a[3];
-  anchor_of(keys_up[p], level - 1, a);
-  int m = 0;
-  for (int dx = -1; dx <= 1; ++dx)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dz = -1; dz <= 1; ++dz) {
-        const int32_t s = find_box(keys_up, n_up, level - 1, a[0] + dx, a[1] + dy, a[2] + dz);
-        if (s < 0) continue;
-        int k = m++;
-        while (k > 0 && nb[k - 1] > s) {
-          nb[k] = nb[k - 1];
-          --k;
-        }
-        nb[k] = s;
-      }
-  return m;
-}
-
-// Interaction list of box i: children of the parent's neighbours that are
-// not adjacent to the box (Section 2, the M2L), in ascending source index;
-// count pass (tidx == nullptr) or fill pass.
+// Interaction list of box i (level l >= 2): children of the parent's
+// neighbours that are not adjacent to the box (Section 2, the M2L), in
+// ascending source index - the parents' neighbours sorted by index, their
+// children in octant order (children keys extend their parent's key and both
+// levels are sorted, so child indices follow parent indices); count pass
+// (tidx == nullptr) or fill pass.  A child's anchor is 2 (parent anchor) +
+// octant bits, so no key is decoded per child.
 __global__ void interactions_kernel(const uint64_t* __restrict__ keys, int64_t n,
                                     const int32_t* __restrict__ parent,
                                     const uint64_t* __restrict__ keys_up, int64_t n_up,
@@ -380,16 +442,32 @@ __global__ void interactions_kernel(const uint64_t* __restrict__ keys, int64_t n
   if (i >= n) return;
   int a[3];
   anchor_of(keys[i], level, a);
-  int32_t nb[27];
-  const int m = parent_neighbours(keys_up, n_up, level, parent[i], nb);
+  const int pa[3] = {a[0] >> 1, a[1] >> 1, a[2] >> 1};
+  // (index << 5 | direction) of the existing parent neighbours, ascending
+  int64_t nb[27];
+  int m = 0;
+  for (int d = 0; d < 27; ++d) {
+    const int dx = d / 9 - 1, dy = (d / 3) % 3 - 1, dz = d % 3 - 1;
+    const int32_t s = find_box(keys_up, n_up, level - 1, pa[0] + dx, pa[1] + dy, pa[2] + dz);
+    if (s < 0) continue;
+    const int64_t v = (int64_t)s << 5 | d;
+    int k = m++;
+    while (k > 0 && nb[k - 1] > v) {
+      nb[k] = nb[k - 1];
+      --k;
+    }
+    nb[k] = v;
+  }
   int64_t e = tidx ? offs[i] : 0;
-  for (int k = 0; k < m; ++k)
+  for (int k = 0; k < m; ++k) {
+    const int32_t p = (int32_t)(nb[k] >> 5);
+    const int d = (int)(nb[k] & 31);
+    const int bx = 2 * (pa[0] + d / 9 - 1) - a[0], by = 2 * (pa[1] + (d / 3) % 3 - 1) - a[1],
+              bz = 2 * (pa[2] + d % 3 - 1) - a[2];
     for (int o = 0; o < 8; ++o) {
-      const int32_t s = child_up[8 * (int64_t)nb[k] + o];
+      const int32_t s = child_up[8 * (int64_t)p + o];
       if (s < 0) continue;
-      int b[3];
-      anchor_of(keys[s], level, b);
-      const int tx = b[0] - a[0], ty = b[1] - a[1], tz = b[2] - a[2];
+      const int tx = bx + (o & 1), ty = by + ((o >> 1) & 1), tz = bz + ((o >> 2) & 1);
       if (max(abs(tx), max(abs(ty), abs(tz))) <= 1) continue;
       if (tidx) {
         src[e] = s;
@@ -397,6 +475,7 @@ __global__ void interactions_kernel(const uint64_t* __restrict__ keys, int64_t n
       }
       ++e;
     }
+  }
   if (!tidx) offs[i] = e;
 }
 
@@ -462,51 +541,54 @@ __global__ void block_first_kernel(const uint64_t* __restrict__ keys, int64_t n,
   tbase[i] = (own_slot(a) - kHadSlotBias) * kHadRowBytes;
 }
 
-// shell slots some member's 26 neighbour directions reach (216-bit mask)
-__device__ inline void block_mask(const uint64_t* __restrict__ keys, int level, int32_t c0, int32_t c1,
-                                  uint64_t mask[4]) {
-  mask[0] = mask[1] = mask[2] = mask[3] = 0;
-  for (int32_t c = c0; c < c1; ++c) {
-    int a[3];
-    anchor_of(keys[c], level, a);
-    const int own = own_slot(a);
-    for (int dx = -1; dx <= 1; ++dx)
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dz = -1; dz <= 1; ++dz) {
-          if (dx == 0 && dy == 0 && dz == 0) continue;
-          const int s = own + dx + kHadShell * dy + kHadShell * kHadShell * dz;
-          mask[s >> 6] |= 1ull << (s & 63);
-        }
-  }
-}
-
-// count pass (list == nullptr): cnt[b] = slots of block b; fill pass: the
-// block's entries cluster << 8 | slot in ascending slot order, with the
-// empty cluster n where no cluster sits at the slot
-__global__ void block_list_kernel(const uint64_t* __restrict__ keys, int64_t n, int level,
-                                  const int32_t* __restrict__ tgt, int64_t nblk,
-                                  int32_t* __restrict__ cnt, const int32_t* __restrict__ first,
-                                  int32_t* __restrict__ list) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b == 0 && list) list[0] = (int32_t)((uint32_t)n << 8 | 255u);
+// One wave per block.  Slot (x, y, z) of the 6 x 6 x 6 shell is in the
+// block's list when some member's 26 neighbour directions reach it: a member
+// sits at inner position (x - 1 - dx, ...) for some direction d != 0.  Count
+// pass (list == nullptr): cnt[b] = slots of block b; fill pass: the block's
+// entries cluster << 8 | slot in ascending slot order, with the empty
+// cluster n where no cluster sits at the slot.
+__global__ __launch_bounds__(kThreads) void block_list_kernel(
+    const uint64_t* __restrict__ keys, int64_t n, int level, const int32_t* __restrict__ tgt,
+    int64_t nblk, int32_t* __restrict__ cnt, const int32_t* __restrict__ first,
+    int32_t* __restrict__ list) {
+  const int lane = threadIdx.x & 63;
+  const int64_t b = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (b == 0 && lane == 0 && list) list[0] = (int32_t)((uint32_t)n << 8 | 255u);
   if (b >= nblk) return;
   const int32_t c0 = tgt[b], c1 = tgt[b + 1];
-  uint64_t mask[4];
-  block_mask(keys, level, c0, c1, mask);
-  if (!list) {
-    cnt[b] = __popcll(mask[0]) + __popcll(mask[1]) + __popcll(mask[2]) + __popcll(mask[3]);
-    return;
+  // members on the 4 x 4 x 4 cube: bit x + 4 y + 16 z (at most 64 members)
+  uint64_t mem = 0;
+  if (c0 + lane < c1) {
+    int a[3];
+    anchor_of(keys[c0 + lane], level, a);
+    mem = 1ull << ((a[0] & 3) + 4 * (a[1] & 3) + 16 * (a[2] & 3));
   }
+  for (int sh = 1; sh < 64; sh <<= 1) mem |= __shfl_xor(mem, sh, 64);
   int a0[3];
   anchor_of(keys[c0], level, a0);
   const int bx = (a0[0] >> 2) * 4 - 1, by = (a0[1] >> 2) * 4 - 1, bz = (a0[2] >> 2) * 4 - 1;
-  int64_t e = first[b];
-  for (int s = 0; s < kHadSrcSlots; ++s) {
-    if (!((mask[s >> 6] >> (s & 63)) & 1)) continue;
-    const int x = s % kHadShell, y = (s / kHadShell) % kHadShell, z = s / (kHadShell * kHadShell);
-    const int32_t c = find_box(keys, n, level, bx + x, by + y, bz + z);
-    list[e++] = (int32_t)((uint32_t)(c >= 0 ? c : (int32_t)n) << 8 | (uint32_t)s);
+  int64_t e = list ? first[b] : 0;
+  for (int r = 0; r < (kHadSrcSlots + 63) / 64; ++r) {
+    const int sl = r * 64 + lane;
+    bool hit = false;
+    if (sl < kHadSrcSlots) {
+      const int x = sl % kHadShell, y = (sl / kHadShell) % kHadShell, z = sl / (kHadShell * kHadShell);
+      for (int d = 0; d < 27 && !hit; ++d) {
+        if (d == 13) continue;
+        const int px = x - 1 - (d / 9 - 1), py = y - 1 - ((d / 3) % 3 - 1), pz = z - 1 - (d % 3 - 1);
+        if (px < 0 || py < 0 || pz < 0 || px > 3 || py > 3 || pz > 3) continue;
+        hit = (mem >> (px + 4 * py + 16 * pz)) & 1;
+      }
+    }
+    const uint64_t bal = __ballot(hit);
+    if (list && hit) {
+      const int x = sl % kHadShell, y = (sl / kHadShell) % kHadShell, z = sl / (kHadShell * kHadShell);
+      const int32_t c = find_box(keys, n, level, bx + x, by + y, bz + z);
+      list[e + __popcll(bal & ((1ull << lane) - 1))] = (int32_t)((uint32_t)(c >= 0 ? c : (int32_t)n) << 8 | (uint32_t)sl);
+    }
+    e += __popcll(bal);
   }
+  if (!list && lane == 0) cnt[b] = (int32_t)e;
 }
 
 // hb_src[b] = 1 + exclusive count (entry 0 is the empty cluster), and the end
@@ -623,7 +705,7 @@ int64_t level_cap(int64_t n, int l) { return l >= 21 ? n : std::min<int64_t>(n, 
 // stable radix sort of (code, index) by the low `bits` bits of the code;
 // the result is in whichever of the two buffer pairs the last pass wrote
 hipError_t sort_codes(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int32_t* hist, int64_t n,
-                      int bits, uint64_t** k_out, int32_t** v_out, hipStream_t s) {
+                      int bits, uint64_t** k_out, int32_t** v_out, int32_t* part, hipStream_t s) {
   const int64_t nb = (n + kSortChunk - 1) / kSortChunk;
   uint64_t* K[2] = {k0, k1};
   int32_t* V[2] = {v0, v1};
@@ -631,7 +713,7 @@ hipError_t sort_codes(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int3
   for (int p = 0; p < passes; ++p) {
     const int in = p & 1, out = in ^ 1;
     radix_hist_kernel<uint64_t><<<(unsigned)nb, kSortThreads, 0, s>>>(K[in], n, 8 * p, hist, nb);
-    scan_kernel<int32_t><<<1, kScanThreads, 0, s>>>(hist, 256 * nb, nullptr, nullptr);
+    device_scan<int32_t>(hist, 256 * nb, nullptr, nullptr, part, s);
     radix_scatter_kernel<uint64_t><<<(unsigned)nb, kSortThreads, 0, s>>>(K[in], V[in], n, 8 * p, hist,
                                                                          nb, K[out], V[out]);
   }
@@ -642,9 +724,10 @@ hipError_t sort_codes(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int3
 
 // unique codes of a sorted array of n (host-known) codes: out, *count
 hipError_t unique_codes(const uint64_t* code, int64_t n, const int32_t* n_dev, int32_t* flag,
-                        uint64_t* out, int32_t* count, int32_t* parent, int shift, hipStream_t s) {
+                        uint64_t* out, int32_t* count, int32_t* parent, int shift, int32_t* part,
+                        hipStream_t s) {
   head_kernel<<<blocks(n, kThreads), kThreads, 0, s>>>(code, n, n_dev, shift, flag);
-  scan_kernel<int32_t><<<1, kScanThreads, 0, s>>>(flag, n, n_dev, count);
+  device_scan<int32_t>(flag, n, n_dev, count, part, s);
   compact_kernel<<<blocks(n, kThreads), kThreads, 0, s>>>(code, n, n_dev, shift, flag, out, parent);
   return hipGetLastError();
 }
@@ -668,6 +751,7 @@ size_t tree_scratch_bytes(int64_t n_src, int64_t n_tgt, int depth) {
     add(level_cap(cap, l) * 4);                       // parents of level l
   }
   add(64 * 4);                                        // counts
+  add(kScanGroups * 8);                               // scan partial sums
   return b;
 }
 
@@ -701,6 +785,8 @@ hipError_t tree_sort_and_levels(const double* src, int64_t n_src, const double* 
     parent[l] = m.take<int32_t>(level_cap(cap, l));
   }
   int32_t* cnt = m.take<int32_t>(64);
+  int64_t* part64 = m.take<int64_t>(kScanGroups);
+  int32_t* part = reinterpret_cast<int32_t*>(part64);
   // cnt: [0] bad point, [1] leaf set differs, [2 + l] boxes of level l,
   // [20] point counts (src, tgt), [22] unique source / target / target-only
   init_counts_kernel<<<1, 64, 0, s>>>(cnt, (int32_t)n_src, (int32_t)n_tgt);
@@ -712,18 +798,18 @@ hipError_t tree_sort_and_levels(const double* src, int64_t n_src, const double* 
                                                                 origin[2], width, ks[set][0], vs[set][0], cnt);
     uint64_t* ko;
     int32_t* vo;
-    e = sort_codes(ks[set][0], vs[set][0], ks[set][1], vs[set][1], hist, c, 3 * depth, &ko, &vo, s);
+    e = sort_codes(ks[set][0], vs[set][0], ks[set][1], vs[set][1], hist, c, 3 * depth, &ko, &vo, part, s);
     if (e != hipSuccess) return e;
     (set == 0 ? out.code_src : out.code_tgt) = ko;
     (set == 0 ? out.order_src : out.order_tgt) = vo;
   }
   // leaves: union of the non-empty source and target leaves
-  e = unique_codes(out.code_src, n_src, cnt + 20, flag, us, cnt + 22, nullptr, 0, s);
+  e = unique_codes(out.code_src, n_src, cnt + 20, flag, us, cnt + 22, nullptr, 0, part, s);
   if (e != hipSuccess) return e;
-  e = unique_codes(out.code_tgt, n_tgt, cnt + 21, flag, ut, cnt + 23, nullptr, 0, s);
+  e = unique_codes(out.code_tgt, n_tgt, cnt + 21, flag, ut, cnt + 23, nullptr, 0, part, s);
   if (e != hipSuccess) return e;
   not_in_kernel<<<blocks(n_tgt, kThreads), kThreads, 0, s>>>(ut, n_tgt, cnt + 23, us, cnt + 22, flag);
-  scan_kernel<int32_t><<<1, kScanThreads, 0, s>>>(flag, n_tgt, cnt + 23, cnt + 24);
+  device_scan<int32_t>(flag, n_tgt, cnt + 23, cnt + 24, part, s);
   select_kernel<<<blocks(n_tgt, kThreads), kThreads, 0, s>>>(ut, n_tgt, cnt + 23, us, cnt + 22, flag, uto);
   union_kernel<<<blocks(std::max(n_src, n_tgt), kThreads), kThreads, 0, s>>>(
       us, cnt + 22, uto, cnt + 24, std::max(n_src, n_tgt), code[depth], cnt + 2 + depth);
@@ -732,7 +818,7 @@ hipError_t tree_sort_and_levels(const double* src, int64_t n_src, const double* 
   // ancestors level by level: parent code = code >> 3
   for (int l = depth; l >= 1; --l) {
     const int64_t c = level_cap(cap, l);
-    e = unique_codes(code[l], c, cnt + 2 + l, flag, code[l - 1], cnt + 2 + l - 1, parent[l], 3, s);
+    e = unique_codes(code[l], c, cnt + 2 + l, flag, code[l - 1], cnt + 2 + l - 1, parent[l], 3, part, s);
     if (e != hipSuccess) return e;
   }
   for (int l = 0; l <= depth; ++l) {
@@ -778,50 +864,51 @@ hipError_t tree_halo(const uint64_t* keys, int64_t n, int level, int32_t* halo, 
 hipError_t tree_interactions(const uint64_t* keys, int64_t n, const int32_t* parent,
                              const uint64_t* keys_up, int64_t n_up, const int32_t* child_up, int level,
                              const int16_t* tmap, int64_t* offs, int64_t* total, int32_t* src,
-                             int16_t* tidx, hipStream_t s) {
+                             int16_t* tidx, int64_t* part, hipStream_t s) {
   interactions_kernel<<<blocks(n, kThreads), kThreads, 0, s>>>(keys, n, parent, keys_up, n_up, child_up,
                                                                 level, tmap, offs, src, tidx);
   if (!tidx) {
-    scan_kernel<int64_t><<<1, kScanThreads, 0, s>>>(offs, n, nullptr, total);
+    device_scan<int64_t>(offs, n, nullptr, total, part, s);
     close_offsets_kernel<<<1, 1, 0, s>>>(offs, n, total);
   }
   return hipGetLastError();
 }
 
 hipError_t tree_near(const uint64_t* keys, int64_t n, int depth, int64_t* offs, int64_t* total,
-                     int32_t* src, hipStream_t s) {
+                     int32_t* src, int64_t* part, hipStream_t s) {
   near_kernel<<<blocks(n, kThreads), kThreads, 0, s>>>(keys, n, depth, offs, src);
   if (!src) {
-    scan_kernel<int64_t><<<1, kScanThreads, 0, s>>>(offs, n, nullptr, total);
+    device_scan<int64_t>(offs, n, nullptr, total, part, s);
     close_offsets_kernel<<<1, 1, 0, s>>>(offs, n, total);
   }
   return hipGetLastError();
 }
 
 hipError_t tree_blocks(const uint64_t* keys, int64_t n, int level, int32_t* flag, int32_t* tgt,
-                       int32_t* tbase, int32_t* counts, hipStream_t s) {
+                       int32_t* tbase, int32_t* counts, int64_t* part, hipStream_t s) {
   block_head_kernel<<<blocks(n, kThreads), kThreads, 0, s>>>(keys, n, flag);
-  scan_kernel<int32_t><<<1, kScanThreads, 0, s>>>(flag, n, nullptr, counts);
+  device_scan<int32_t>(flag, n, nullptr, counts, reinterpret_cast<int32_t*>(part), s);
   block_first_kernel<<<blocks(n, kThreads), kThreads, 0, s>>>(keys, n, flag, tgt, tbase, level);
   return hipGetLastError();
 }
 
 hipError_t tree_block_lists(const uint64_t* keys, int64_t n, int level, const int32_t* tgt, int64_t nblk,
-                            int32_t* cnt, int32_t* src, int32_t* total, int32_t* list, hipStream_t s) {
+                            int32_t* cnt, int32_t* src, int32_t* total, int32_t* list, int64_t* part,
+                            hipStream_t s) {
   if (!list) {
-    block_list_kernel<<<blocks(nblk, kThreads), kThreads, 0, s>>>(keys, n, level, tgt, nblk, cnt,
-                                                                   nullptr, nullptr);
-    scan_kernel<int32_t><<<1, kScanThreads, 0, s>>>(cnt, nblk, nullptr, total);
+    block_list_kernel<<<blocks(nblk * 64, kThreads), kThreads, 0, s>>>(keys, n, level, tgt, nblk, cnt,
+                                                                        nullptr, nullptr);
+    device_scan<int32_t>(cnt, nblk, nullptr, total, reinterpret_cast<int32_t*>(part), s);
     block_offsets_kernel<<<blocks(nblk, kThreads), kThreads, 0, s>>>(cnt, nblk, total, src);
     return hipGetLastError();
   }
-  block_list_kernel<<<blocks(nblk, kThreads), kThreads, 0, s>>>(keys, n, level, tgt, nblk, nullptr, src,
-                                                                 list);
+  block_list_kernel<<<blocks(nblk * 64, kThreads), kThreads, 0, s>>>(keys, n, level, tgt, nblk, nullptr,
+                                                                      src, list);
   return hipGetLastError();
 }
 
 hipError_t tree_classes(const uint64_t* keys, int64_t n, int32_t* scratch, int32_t* order,
-                        int32_t* counts, hipStream_t s) {
+                        int32_t* counts, int64_t* part, hipStream_t s) {
   // stable order of the boxes by octant class: one radix pass on the class
   const int64_t nb = (n + kSortChunk - 1) / kSortChunk;
   int32_t* cls = scratch;
@@ -831,7 +918,7 @@ hipError_t tree_classes(const uint64_t* keys, int64_t n, int32_t* scratch, int32
   fill_kernel<<<1, 64, 0, s>>>(counts, 8, 0);
   class_key_kernel<<<blocks(n, kThreads), kThreads, 0, s>>>(keys, n, cls, idx, counts);
   radix_hist_kernel<int32_t><<<(unsigned)nb, kSortThreads, 0, s>>>(cls, n, 0, hist, nb);
-  scan_kernel<int32_t><<<1, kScanThreads, 0, s>>>(hist, 256 * nb, nullptr, nullptr);
+  device_scan<int32_t>(hist, 256 * nb, nullptr, nullptr, reinterpret_cast<int32_t*>(part), s);
   radix_scatter_kernel<int32_t><<<(unsigned)nb, kSortThreads, 0, s>>>(cls, idx, n, 0, hist, nb, cls2,
                                                                       order);
   return hipGetLastError();
@@ -844,12 +931,12 @@ size_t tree_classes_scratch_ints(int64_t n) {
 hipError_t tree_tiles(const uint64_t* keys, int64_t n, int level, const int32_t* order,
                       const TileClasses& tc, int TB, int64_t ntiles, const int8_t* tvec,
                       int32_t* tile_box, int32_t* tile_class, int64_t* present, int64_t* total,
-                      hipStream_t s) {
+                      int64_t* part, hipStream_t s) {
   tile_box_kernel<<<blocks(ntiles * TB, kThreads), kThreads, 0, s>>>(order, tc, TB, ntiles, tile_box,
                                                                       tile_class);
   tile_present_kernel<<<blocks(ntiles * kNumT, kThreads), kThreads, 0, s>>>(tile_box, ntiles, TB, keys, n,
                                                                              level, tvec, present);
-  scan_kernel<int64_t><<<1, kScanThreads, 0, s>>>(present, ntiles * kNumT, nullptr, total);
+  device_scan<int64_t>(present, ntiles * kNumT, nullptr, total, part, s);
   close_offsets_kernel<<<1, 1, 0, s>>>(present, ntiles * kNumT, total);
   return hipGetLastError();
 }

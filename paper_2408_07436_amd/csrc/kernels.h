@@ -70,7 +70,10 @@ hipError_t launch_leaf_eval_group(int inst, const LeafArgs* jobs, const int64_t*
 
 // ---- device re-setup for moving points (k_setup.hip) ------------------------
 // Codes are Morton codes without the sentinel bit; level keys carry it at
-// bit 3 l (the host tree's keys).  Every launcher enqueues on s.
+// bit 3 l (the host tree's keys).  Every launcher enqueues on s.  `part`
+// is device scratch of kTreeScanPart int64 for the prefix sums (calls on
+// one stream may share it).
+constexpr int kTreeScanPart = 1024;
 
 // Device results of tree_sort_and_levels (pointers into the scratch):
 // sorted leaf codes of the points with the original index of each sorted
@@ -114,22 +117,23 @@ hipError_t tree_halo(const uint64_t* keys, int64_t n, int level, int32_t* halo, 
 hipError_t tree_interactions(const uint64_t* keys, int64_t n, const int32_t* parent,
                              const uint64_t* keys_up, int64_t n_up, const int32_t* child_up, int level,
                              const int16_t* tmap, int64_t* offs, int64_t* total, int32_t* src,
-                             int16_t* tidx, hipStream_t s);
+                             int16_t* tidx, int64_t* part, hipStream_t s);
 // Near fields of the leaves: with src == nullptr offs[n + 1] and *total, else src.
 hipError_t tree_near(const uint64_t* keys, int64_t n, int depth, int64_t* offs, int64_t* total,
-                     int32_t* src, hipStream_t s);
+                     int32_t* src, int64_t* part, hipStream_t s);
 // FFT-M2L source blocks over the clusters (boxes of `level`): block firsts
 // tgt[nblk + 1], tbase[n], counts[0] = nblk (flag: n ints of scratch).
 hipError_t tree_blocks(const uint64_t* keys, int64_t n, int level, int32_t* flag, int32_t* tgt,
-                       int32_t* tbase, int32_t* counts, hipStream_t s);
+                       int32_t* tbase, int32_t* counts, int64_t* part, hipStream_t s);
 // Block source lists: with list == nullptr src[nblk + 1] and *total (cnt:
 // nblk ints of scratch), else list[1 + total].
 hipError_t tree_block_lists(const uint64_t* keys, int64_t n, int level, const int32_t* tgt, int64_t nblk,
-                            int32_t* cnt, int32_t* src, int32_t* total, int32_t* list, hipStream_t s);
+                            int32_t* cnt, int32_t* src, int32_t* total, int32_t* list, int64_t* part,
+                            hipStream_t s);
 // Boxes in stable octant-class order (order[n]) and counts[8] per class.
 size_t tree_classes_scratch_ints(int64_t n);
 hipError_t tree_classes(const uint64_t* keys, int64_t n, int32_t* scratch, int32_t* order,
-                        int32_t* counts, hipStream_t s);
+                        int32_t* counts, int64_t* part, hipStream_t s);
 struct TileClasses {
   int32_t start[8];       // first position of class o in the class order
   int32_t count[8];       // boxes of class o
@@ -141,7 +145,7 @@ struct TileClasses {
 hipError_t tree_tiles(const uint64_t* keys, int64_t n, int level, const int32_t* order,
                       const TileClasses& tc, int TB, int64_t ntiles, const int8_t* tvec,
                       int32_t* tile_box, int32_t* tile_class, int64_t* present, int64_t* total,
-                      hipStream_t s);
+                      int64_t* part, hipStream_t s);
 hipError_t tree_tiles_fill(const uint64_t* keys, int64_t n, int level, const int32_t* tile_box,
                            const int32_t* tile_class, int64_t ntiles, int TB, const int8_t* tvec,
                            const int64_t* pos, int32_t* tl_t, int32_t* tl_src, int64_t* tl_offs,
