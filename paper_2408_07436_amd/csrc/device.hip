@@ -125,6 +125,7 @@ struct DeviceState {
   double* tmp = nullptr;
   double* tmp2 = nullptr;
   double* gemm_ws = nullptr;  // split-K partials
+  void* nearbuf = nullptr;    // near-field sums in sorted target order (split leaf passes)
   int64_t gemm_ws_elems = 0;
   // FFT-M2L evaluates run as a dependency graph: the leaf level's M2L on
   // the evaluate stream, the coarse levels' M2M and downward work on a
@@ -960,6 +961,9 @@ std::vector<WorkSlot> work_slots(const kifmm_handle* h, DeviceState* d, int nvec
   add((size_t)maxn * nv * kmax * 8, dbl(&d->tmp));
   add((size_t)maxn * nv * kmax * 8, dbl(&d->tmp2));
   add((size_t)gemm_elems * 8, dbl(&d->gemm_ws));
+  // the near-field pass's sums in sorted target order, read back by the
+  // far-field pass (split leaf passes: FFT schedules and batches)
+  add(nv * (size_t)t.n_tgt * qbytes, raw(&d->nearbuf));
   if (h->cfg.m2l != KIFMM_M2L_FFT) {
     add((size_t)maxn * nv * d->kp * (d->blas_mode == 0 ? 8 : 4), raw(&d->qpad));
     if (d->stack_ok && h->tune[KIFMM_TUNE_BLAS_FORM] == 0) {
@@ -1347,8 +1351,8 @@ kifmm_status evaluate_launches(kifmm_handle* h, const void* q, int64_t ldq, int 
       int64_t blocks;
       plan_leaf_eval(d->tgt_xyz, d->src_xyz, leaf.w, d->qs, d->fp64, t.n_src, d->tgt_start, d->tgt_end,
                      d->src_start, d->src_end, d->near_offs, d->near_src, d->leaf_centers, leaf.n,
-                     d->surf, ar_leaf, ns, d->local[depth], d->tgt_perm, phi, ldphi, nvec, mode, a,
-                     inst, blocks);
+                     d->surf, ar_leaf, ns, d->local[depth], d->tgt_perm, phi, ldphi, d->nearbuf,
+                     t.n_tgt, nvec, mode, a, inst, blocks);
       if (inst < 0) return fail(KIFMM_EINVAL, "bad leaf-pass mode");
       if (blocks > 0) d->sink->add(kFamLeaf, inst, a, blocks);
       return KIFMM_OK;
@@ -1356,7 +1360,8 @@ kifmm_status evaluate_launches(kifmm_handle* h, const void* q, int64_t ldq, int 
     KIFMM_LAUNCH(launch_leaf_eval(d->tgt_xyz, d->src_xyz, leaf.w, d->qs, d->fp64, t.n_src,
                                   d->tgt_start, d->tgt_end, d->src_start, d->src_end, d->near_offs,
                                   d->near_src, d->leaf_centers, leaf.n, d->surf, ar_leaf, ns,
-                                  d->local[depth], d->tgt_perm, phi, ldphi, nvec, mode, st));
+                                  d->local[depth], d->tgt_perm, phi, ldphi, d->nearbuf, t.n_tgt, nvec,
+                                  mode, st));
     return KIFMM_OK;
   };
 

@@ -420,14 +420,18 @@ __device__ __forceinline__ void leaf_eval_body(const LeafArgs& a, int64_t blk) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           if (vb + v >= nvec) continue;
-          TQ* o0 = act0 ? &phi[(int64_t)(vb + v) * ldphi + tperm[t0 + ti0]] : nullptr;
-          TQ* o1 = act1 ? &phi[(int64_t)(vb + v) * ldphi + tperm[t0 + ti1]] : nullptr;
           if (MODE == 1) {
-            if (o0) *o0 = (TQ)ap0[v];
-            if (o1) *o1 = (TQ)ap1[v];
+            // sorted target order: coalesced; the far-field pass scatters
+            TQ* nr = static_cast<TQ*>(a.near) + (int64_t)(vb + v) * a.ldnear + t0;
+            if (act0) nr[ti0] = (TQ)ap0[v];
+            if (act1) nr[ti1] = (TQ)ap1[v];
           } else {
-            const double n0 = MODE == 2 ? (o0 ? (double)*o0 : 0.0) : (double)ap0[v];
-            const double n1 = MODE == 2 ? (o1 ? (double)*o1 : 0.0) : (double)ap1[v];
+            TQ* o0 = act0 ? &phi[(int64_t)(vb + v) * ldphi + tperm[t0 + ti0]] : nullptr;
+            TQ* o1 = act1 ? &phi[(int64_t)(vb + v) * ldphi + tperm[t0 + ti1]] : nullptr;
+            const TQ* nr = MODE == 2 ? static_cast<const TQ*>(a.near) + (int64_t)(vb + v) * a.ldnear + t0
+                                     : nullptr;
+            const double n0 = MODE == 2 ? (o0 ? (double)nr[ti0] : 0.0) : (double)ap0[v];
+            const double n1 = MODE == 2 ? (o1 ? (double)nr[ti1] : 0.0) : (double)ap1[v];
             if (o0) *o0 = (TQ)(kInv4Pi * (al0[v] + n0));
             if (o1) *o1 = (TQ)(kInv4Pi * (al1[v] + n1));
           }
@@ -537,11 +541,11 @@ void plan_leaf_eval(const double* tgt_xyz, const double* src_xyz, double leaf_w,
                     const int32_t* sstart, const int32_t* send, const int64_t* near_offs,
                     const int32_t* near_src, const double* centers, int64_t n_leaf,
                     const double* surf, double ar, int ns, const double* local,
-                    const int64_t* tgt_perm, void* phi, int64_t ldphi, int nvec, int mode,
-                    LeafArgs& a, int& inst, int64_t& blocks) {
+                    const int64_t* tgt_perm, void* phi, int64_t ldphi, void* near, int64_t ldnear,
+                    int nvec, int mode, LeafArgs& a, int& inst, int64_t& blocks) {
   const double tau2 = (leaf_w / 16) * (leaf_w / 16);  // FP32: pairs refined below w / 16
   a = LeafArgs{tgt_xyz, src_xyz, qs, n_src, tstart, tend, sstart, send, near_offs, near_src, centers,
-               surf, ar, ns, local, tgt_perm, phi, ldphi, nvec, n_leaf, tau2};
+               surf, ar, ns, local, tgt_perm, phi, ldphi, nvec, n_leaf, tau2, near, ldnear};
   inst = (mode < 0 || mode > 2) ? -1 : leaf_instance(fp64, mode, nvec);
   blocks = 8 * ((n_leaf + 7) / 8);
 }
@@ -552,14 +556,16 @@ hipError_t launch_leaf_eval(const double* tgt_xyz, const double* src_xyz, double
                             const int64_t* near_offs, const int32_t* near_src,
                             const double* centers, int64_t n_leaf, const double* surf, double ar,
                             int ns, const double* local, const int64_t* tgt_perm, void* phi,
-                            int64_t ldphi, int nvec, int mode, hipStream_t stream) {
+                            int64_t ldphi, void* near, int64_t ldnear, int nvec, int mode,
+                            hipStream_t stream) {
   if (n_leaf == 0) return hipSuccess;
+  if (mode != 0 && !near) return hipErrorInvalidValue;
   LeafArgs a;
   int inst;
   int64_t blocks;
   plan_leaf_eval(tgt_xyz, src_xyz, leaf_w, qs, fp64, n_src, tstart, tend, sstart, send, near_offs,
-                 near_src, centers, n_leaf, surf, ar, ns, local, tgt_perm, phi, ldphi, nvec, mode, a,
-                 inst, blocks);
+                 near_src, centers, n_leaf, surf, ar, ns, local, tgt_perm, phi, ldphi, near, ldnear,
+                 nvec, mode, a, inst, blocks);
   return leaf_dispatch(inst, &a, nullptr, nullptr, 0, blocks, stream);
 }
 

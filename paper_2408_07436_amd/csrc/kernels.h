@@ -31,7 +31,8 @@ hipError_t launch_leaf_eval(const double* tgt_xyz, const double* src_xyz, double
                             const int64_t* near_offs, const int32_t* near_src,
                             const double* centers, int64_t n_leaf, const double* surf, double ar,
                             int ns, const double* local, const int64_t* tgt_perm, void* phi,
-                            int64_t ldphi, int nvec, int mode, hipStream_t stream);
+                            int64_t ldphi, void* near, int64_t ldnear, int nvec, int mode,
+                            hipStream_t stream);
 
 // Grouped forms of the point kernels (see "grouped launches" below).
 struct GatherArgs {  // ceil(n / 256) x nvec workgroups
@@ -57,14 +58,15 @@ struct LeafArgs {  // 8 ceil(n_leaf / 8) workgroups (leaves placed by XCD)
   const int32_t* near_src; const double* centers; const double* surf; double ar; int ns;
   const double* local; const int64_t* tgt_perm; void* phi; int64_t ldphi; int nvec; int64_t n_leaf;
   double tau2;
+  void* near; int64_t ldnear;  // near-field sums in sorted target order (modes 1 and 2)
 };
 void plan_leaf_eval(const double* tgt_xyz, const double* src_xyz, double leaf_w, const void* qs,
                     bool fp64, int64_t n_src, const int32_t* tstart, const int32_t* tend,
                     const int32_t* sstart, const int32_t* send, const int64_t* near_offs,
                     const int32_t* near_src, const double* centers, int64_t n_leaf,
                     const double* surf, double ar, int ns, const double* local,
-                    const int64_t* tgt_perm, void* phi, int64_t ldphi, int nvec, int mode,
-                    LeafArgs& a, int& inst, int64_t& blocks);
+                    const int64_t* tgt_perm, void* phi, int64_t ldphi, void* near, int64_t ldnear,
+                    int nvec, int mode, LeafArgs& a, int& inst, int64_t& blocks);
 hipError_t launch_leaf_eval_group(int inst, const LeafArgs* jobs, const int64_t* pre, int nj,
                                   int64_t blocks, hipStream_t stream);
 
