@@ -432,13 +432,66 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_a_kernel(Bl
   for (int rb = 0; rb < 8; ++rb)
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) acc[rb][ct] = V4{T(0), T(0), T(0), T(0)};
-  for (int kb = 0; kb < a.kp; kb += 16) {
-    V4 bq[2];
+  // The workgroup's 128 operator rows are shared by its four waves: each K
+  // slab of 16 is staged once in LDS (double-buffered; rows padded to RS
+  // elements so that a quarter-wave's 16 row reads fall in distinct banks),
+  // the next slab's operator and multipole values are loaded from global
+  // memory before the current slab's MFMAs, and each row block's LDS read is
+  // issued one block ahead.
+  constexpr int RS = sizeof(T) == 8 ? 18 : 20;
+  __shared__ __attribute__((aligned(16))) T lds[2][128 * RS];
+  const V4 zero4 = V4{T(0), T(0), T(0), T(0)};
+  const int srow = threadIdx.x >> 1, shalf = threadIdx.x & 1;
+  const T* asrc = A + (int64_t)srow * a.kp + shalf * 8;
+  V4 st0, st1;  // 8 staged operator values of this thread
+  auto gload = [&](int kb) {
+    st0 = ld4(asrc + kb);
+    st1 = ld4(asrc + kb + 4);
+  };
+  auto swrite = [&](int buf) {
+    T* d = &lds[buf][srow * RS + shalf * 8];
+    if constexpr (sizeof(T) == 8) {
+      reinterpret_cast<double2*>(d)[0] = double2{st0[0], st0[1]};
+      reinterpret_cast<double2*>(d)[1] = double2{st0[2], st0[3]};
+      reinterpret_cast<double2*>(d)[2] = double2{st1[0], st1[1]};
+      reinterpret_cast<double2*>(d)[3] = double2{st1[2], st1[3]};
+    } else {
+      reinterpret_cast<v4f*>(d)[0] = st0;
+      reinterpret_cast<v4f*>(d)[1] = st1;
+    }
+  };
+  // loads without branches (a column without a box reads box 0's values and
+  // discards them; the last slab reloads itself), so that the compiler can
+  // count the loads in flight and wait only for the current slab's
+  const T* qs[2];
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) bq[ct] = qp[ct] ? ld4(qp[ct] + kb + 4 * g4) : V4{T(0), T(0), T(0), T(0)};
+  for (int ct = 0; ct < 2; ++ct) qs[ct] = qp[ct] ? qp[ct] : q;
+  auto load_q = [&](int kb, V4 (&bq)[2]) {
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const V4 v = ld4(qs[ct] + kb + 4 * g4);
+      bq[ct] = qp[ct] ? v : zero4;
+    }
+  };
+  gload(0);
+  swrite(0);
+  V4 bq[2];
+  load_q(0, bq);
+  __syncthreads();
+  int buf = 0;
+  for (int kb = 0; kb < a.kp; kb += 16, buf ^= 1) {
+    const bool more = kb + 16 < a.kp;
+    const int kn = more ? kb + 16 : kb;
+    V4 nbq[2];
+    gload(kn);
+    load_q(kn, nbq);
+    // keep the next slab's loads ahead of this slab's MFMAs
+    __builtin_amdgcn_sched_barrier(0);
+    const T* L = &lds[buf][l16 * RS + 4 * g4];
+    V4 av = ld4(L);
 #pragma unroll
     for (int rb = 0; rb < 8; ++rb) {
-      const V4 av = ld4(A + (int64_t)(rb * 16 + l16) * a.kp + kb + 4 * g4);
+      const V4 nav = rb < 7 ? ld4(L + (rb + 1) * 16 * RS) : zero4;
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -448,7 +501,12 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_a_kernel(Bl
           else
             acc[rb][ct] = mf64(av[s], bq[ct][s], acc[rb][ct]);
         }
+      av = nav;
     }
+    if (more) swrite(buf ^ 1);
+    __syncthreads();
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) bq[ct] = nbq[ct];
   }
   T* xi = static_cast<T*>(a.xi_hi);
 #pragma unroll
