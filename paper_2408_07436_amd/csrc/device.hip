@@ -417,7 +417,9 @@ kifmm_status pack_blas_stacked(kifmm_handle* h, DeviceState* d) {
     return i < kt ? op.Ubar[it][(size_t)m * kt + i] : 0.0;
   };
   const int per = mode == 2 ? 8 : 1;  // values per (lane, row block)
-  std::vector<double> B((size_t)8 * nsteps * 64 * rbo * per, 0.0);
+  // (plus kStackChunk zero steps past the last class: Stage B stages the
+  // operator a chunk of steps ahead and may read past a class's end)
+  std::vector<double> B(((size_t)8 * nsteps + kStackChunk) * 64 * rbo * per, 0.0);
   for (int o = 0; o < 8; ++o)
     for (int n = 0; n < nsteps; ++n)
       for (int lane = 0; lane < 64; ++lane)

@@ -526,8 +526,13 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_a_kernel(Bl
 
 // Stage B, FP32 / FP64: one workgroup per target tile; K step n covers rows
 // 4n .. 4n + 3 of the class's stacked K (one transfer vector j, whose xi
-// rows start at info[n].y).  Loads run ahead of the MFMAs: the table entry
-// three steps, the source box two steps, xi and the operator one step.
+// rows start at info[n].y).  The operator, the same for the four waves, is
+// staged in LDS a chunk of steps at a time (double-buffered; each lane's
+// values padded to a 16-byte multiple off 64 bytes so that 16-byte reads of
+// consecutive lanes spread over the banks), the next chunk loaded from
+// global memory while the current one is used.  The other loads run ahead
+// of the MFMAs: the table entry three steps, the source box two steps, xi
+// and the operator (from LDS) one step.
 // Work item of Stage B: (tile, part of its K steps), consecutive items per
 // XCD; the part's steps [n0, n1).
 struct StackPart {
@@ -554,6 +559,15 @@ __device__ inline double* stack_dst(const BlasStack& a, const StackPart& p, int 
 template <typename T, int RBO>
 __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_b_kernel(BlasStack a) {
   using V4 = typename std::conditional<sizeof(T) == 4, v4f, v4d>::type;
+  // steps per staged chunk: 4 in FP64 where that keeps 16-byte staging (two
+  // workgroups' double buffers fit a CU's LDS), else kStackChunk
+  constexpr int C = sizeof(T) == 8 && RBO % 4 == 0 ? 4 : kStackChunk;
+  // padded values per lane in LDS (16-byte aligned lanes; at RBO = 8 the
+  // lanes of a quarter wave start in distinct bank groups)
+  constexpr int LS = sizeof(T) == 8 ? RBO + 2 : (RBO + 3) / 4 * 4 + 4;
+  constexpr int PT = C * RBO / 4;  // staged values per thread (a multiple of 4: RBO is even)
+  static_assert(RBO % 2 == 0 && PT % 4 == 0, "staging in 16-byte loads and pairs");
+  __shared__ __attribute__((aligned(16))) T ops[2][C * 64 * LS];
   StackPart sp;
   if (!stack_part(a, a.nsteps, sp)) return;
   const int64_t tile = sp.tile;
@@ -563,7 +577,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_b_kernel(Bl
   const StackCols cc = stack_columns(a, wave, l16);
   const int32_t* src = a.tile_src + (int64_t)tile * a.J * a.TB;
   const int2* info = reinterpret_cast<const int2*>(a.info) + (int64_t)cls * a.nsteps;
-  const T* Bop = static_cast<const T*>(a.B_hi) + (int64_t)cls * a.nsteps * 64 * RBO + lane * RBO;
+  const T* Bcls = static_cast<const T*>(a.B_hi) + (int64_t)cls * a.nsteps * 64 * RBO;
   const T* xi = static_cast<const T*>(a.xi_hi);
   const int64_t rs = a.Rs;
   const int nb = sp.n0, nst = sp.n1;  // steps of this part
@@ -572,43 +586,92 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_b_kernel(Bl
   for (int rb = 0; rb < RBO; ++rb)
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) acc[rb][ct] = V4{T(0), T(0), T(0), T(0)};
-  auto source = [&](int2 in, int ct) -> int {
-    return (cc.ok[ct] && in.x >= 0) ? src[in.x * a.TB + cc.slot[ct]] : -1;
+  if (nb >= nst) return;
+  // staging: thread t holds values [t PT, (t + 1) PT) of a chunk (two lanes'
+  // worth in step order), written to LDS at the lanes' padded slots
+  V4 stg[PT / 4];
+  auto gload = [&](int n) {
+    const T* p = Bcls + (int64_t)n * 64 * RBO + threadIdx.x * PT;
+#pragma unroll
+    for (int i = 0; i < PT / 4; ++i) stg[i] = ld4(p + 4 * i);
   };
-  auto xval = [&](int sb, int row, int ct) -> T {
-    return sb >= 0 ? xi[((int64_t)sb * rs + row + g4) * a.nvec + cc.v[ct]] : T(0);
+  auto swrite = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < PT / 4; ++i)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        // pairs never straddle two lanes' values (RBO is even)
+        const int e = threadIdx.x * PT + 4 * i + 2 * h;  // value index within the chunk
+        T* d = &ops[buf][(e / RBO) * LS + e % RBO];
+        if constexpr (sizeof(T) == 8)
+          *reinterpret_cast<double2*>(d) = double2{stg[i][2 * h], stg[i][2 * h + 1]};
+        else
+          *reinterpret_cast<float2*>(d) = float2{stg[i][2 * h], stg[i][2 * h + 1]};
+      }
   };
-  // pipeline registers: in2 = table entry of step n + 2, sb1 / row1 = source
-  // boxes of step n + 1, x0 / o0 = xi and operator values of step n
-  int2 in2 = nb + 2 < nst ? info[nb + 2] : make_int2(-1, 0);
-  const int2 in1 = nb + 1 < nst ? info[nb + 1] : make_int2(-1, 0);
-  const int2 in0 = nb < nst ? info[nb] : make_int2(-1, 0);
-  int sb1[2], row1 = in1.y;
-  T x0[2], o0[RBO];
+  auto oread = [&](int buf, int j, T (&o)[RBO]) {
+    const T* s = &ops[buf][(j * 64 + lane) * LS];
+#pragma unroll
+    for (int rb = 0; rb < RBO; rb += 4) {
+      const V4 v = ld4(s + rb);
+#pragma unroll
+      for (int i = 0; i < 4 && rb + i < RBO; ++i) o[rb + i] = v[i];
+    }
+  };
+  // loads without branches (clamped addresses); a loaded value is masked
+  // where it is used, one step after its load, so that the compiler waits
+  // for it only then
+  const int sl[2] = {cc.ok[0] ? cc.slot[0] : 0, cc.ok[1] ? cc.slot[1] : 0};
+  auto entry = [&](int n) -> int2 {
+    const int2 e = info[min(n, nst - 1)];
+    return n < nst ? e : make_int2(-1, 0);
+  };
+  auto src_raw = [&](int2 in, int ct) -> int { return src[max(in.x, 0) * a.TB + sl[ct]]; };
+  auto x_raw = [&](int sb, int row, int ct) -> T {
+    return xi[((int64_t)max(sb, 0) * rs + row + g4) * a.nvec + cc.v[ct]];
+  };
+  // pipeline registers: in2 = table entry of step n + 2; sr1 / sv1 = raw
+  // source boxes of step n + 1 and their validity, row1 its xi row; xr0 / xv0
+  // = raw xi values of step n and their validity, o0 its operator values
+  int2 in2 = entry(nb + 2);
+  const int2 in1 = entry(nb + 1);
+  const int2 in0 = info[nb];
+  int sr1[2], row1 = in1.y;
+  bool sv1[2], xv0[2];
+  T xr0[2], o0[RBO];
 #pragma unroll
   for (int ct = 0; ct < 2; ++ct) {
-    sb1[ct] = source(in1, ct);
-    x0[ct] = xval(source(in0, ct), in0.y, ct);
+    sr1[ct] = src_raw(in1, ct);
+    sv1[ct] = cc.ok[ct] && in1.x >= 0;
+    const int s0 = src_raw(in0, ct);
+    xv0[ct] = cc.ok[ct] && in0.x >= 0 && s0 >= 0;
+    xr0[ct] = x_raw(xv0[ct] ? s0 : 0, in0.y, ct);
   }
-#pragma unroll
-  for (int rb = 0; rb < RBO; ++rb) o0[rb] = nb < nst ? Bop[(int64_t)nb * 64 * RBO + rb] : T(0);
+  int buf = 0;
+  gload(nb);
+  swrite(0);
+  __syncthreads();
+  oread(0, 0, o0);
   for (int n = nb; n < nst; ++n) {
+    const int j = (n - nb) % C;
     // issue the loads of the next steps
-    const int2 in3 = n + 3 < nst ? info[n + 3] : make_int2(-1, 0);
-    int sb2[2];
+    const int2 in3 = entry(n + 3);
+    int sr2[2];
+    bool sv2[2], xv1[2];
+    T xr1[2], o1[RBO];
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) sb2[ct] = source(in2, ct);
-    T x1[2], o1[RBO];
-#pragma unroll
-    for (int ct = 0; ct < 2; ++ct) x1[ct] = xval(sb1[ct], row1, ct);
-    if (n + 1 < nst) {
-#pragma unroll
-      for (int rb = 0; rb < RBO; ++rb) o1[rb] = Bop[(int64_t)(n + 1) * 64 * RBO + rb];
-    } else {
-#pragma unroll
-      for (int rb = 0; rb < RBO; ++rb) o1[rb] = T(0);
+    for (int ct = 0; ct < 2; ++ct) {
+      sr2[ct] = src_raw(in2, ct);
+      sv2[ct] = cc.ok[ct] && in2.x >= 0;
+      xv1[ct] = sv1[ct] && sr1[ct] >= 0;
+      xr1[ct] = x_raw(xv1[ct] ? sr1[ct] : 0, row1, ct);
     }
+    // the next chunk's operator (the padded buffer keeps the last one in bounds)
+    if (j == 0) gload(n + C);
     // products of step n
+    T x0[2];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) x0[ct] = xv0[ct] ? xr0[ct] : T(0);
 #pragma unroll
     for (int rb = 0; rb < RBO; ++rb)
 #pragma unroll
@@ -618,16 +681,28 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_b_kernel(Bl
         else
           acc[rb][ct] = mf64(o0[rb], x0[ct], acc[rb][ct]);
       }
+    // the next step's operator values, read while the MFMAs run
+    if (j + 1 < C) oread(buf, j + 1, o1);
     // roll
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) {
-      x0[ct] = x1[ct];
-      sb1[ct] = sb2[ct];
+      xr0[ct] = xr1[ct];
+      xv0[ct] = xv1[ct];
+      sr1[ct] = sr2[ct];
+      sv1[ct] = sv2[ct];
+    }
+    row1 = in2.y;
+    in2 = in3;
+    if (j + 1 == C && n + 1 < nst) {
+      // end of a chunk: the next one into the other buffer (its last reader
+      // passed the previous barrier)
+      swrite(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+      oread(buf, 0, o1);
     }
 #pragma unroll
     for (int rb = 0; rb < RBO; ++rb) o0[rb] = o1[rb];
-    row1 = in2.y;
-    in2 = in3;
   }
   const double scale = a.ksplit == 1 ? a.scale : 1.0;
 #pragma unroll

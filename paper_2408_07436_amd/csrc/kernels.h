@@ -324,6 +324,8 @@ hipError_t launch_blas_m2l(const BlasM2L& a, int mode, bool two_stage, hipStream
 //     out[tau] = [Ubar_t for the 189 t of tau, side by side] . xi-rows of
 // the sources tau + t (gathered), one GEMM per class with K = the class's
 // stacked rows.  Each (sigma, t) block of xi is read by exactly one target.
+// Stage B stages its operator in LDS at most kStackChunk K steps at a time.
+constexpr int kStackChunk = 8;
 struct BlasStack {
   int mode;                   // 0 FP64, 1 FP32, 2 BF16x3
   int k, kp;                  // compressed rank; padded (K of Stage A, M of Stage B)
