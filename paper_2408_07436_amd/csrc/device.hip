@@ -417,9 +417,10 @@ kifmm_status pack_blas_stacked(kifmm_handle* h, DeviceState* d) {
     return i < kt ? op.Ubar[it][(size_t)m * kt + i] : 0.0;
   };
   const int per = mode == 2 ? 8 : 1;  // values per (lane, row block)
-  // (plus kStackChunk zero steps past the last class: Stage B stages the
-  // operator a chunk of steps ahead and may read past a class's end)
-  std::vector<double> B(((size_t)8 * nsteps + kStackChunk) * 64 * rbo * per, 0.0);
+  // (plus 2 kStackChunk zero steps past the last class: Stage B stages the
+  // operator one chunk ahead, so a part's last chunk reads up to two chunks
+  // past its last step)
+  std::vector<double> B(((size_t)8 * nsteps + 2 * kStackChunk) * 64 * rbo * per, 0.0);
   for (int o = 0; o < 8; ++o)
     for (int n = 0; n < nsteps; ++n)
       for (int lane = 0; lane < 64; ++lane)

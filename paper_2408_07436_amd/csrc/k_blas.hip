@@ -618,9 +618,13 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_b_kernel(Bl
       for (int i = 0; i < 4 && rb + i < RBO; ++i) o[rb + i] = v[i];
     }
   };
-  // loads without branches (clamped addresses); a loaded value is masked
-  // where it is used, one step after its load, so that the compiler waits
-  // for it only then
+  // Loads without branches (clamped addresses); a loaded value is masked
+  // where it is used, so the compiler waits for it only then.  The chunk's
+  // steps are unrolled, so every iteration issues the same loads and the
+  // waits count exactly.  Pipeline depth: the xi values of step n are loaded
+  // at step n - D, their source boxes at n - D - 1, the table entries at
+  // n - D - 2.
+  constexpr int D = sizeof(T) == 8 ? 2 : 3;
   const int sl[2] = {cc.ok[0] ? cc.slot[0] : 0, cc.ok[1] ? cc.slot[1] : 0};
   auto entry = [&](int n) -> int2 {
     const int2 e = info[min(n, nst - 1)];
@@ -630,79 +634,100 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_b_kernel(Bl
   auto x_raw = [&](int sb, int row, int ct) -> T {
     return xi[((int64_t)max(sb, 0) * rs + row + g4) * a.nvec + cc.v[ct]];
   };
-  // pipeline registers: in2 = table entry of step n + 2; sr1 / sv1 = raw
-  // source boxes of step n + 1 and their validity, row1 its xi row; xr0 / xv0
-  // = raw xi values of step n and their validity, o0 its operator values
-  int2 in2 = entry(nb + 2);
-  const int2 in1 = entry(nb + 1);
-  const int2 in0 = info[nb];
-  int sr1[2], row1 = in1.y;
-  bool sv1[2], xv0[2];
-  T xr0[2], o0[RBO];
+  // pipeline registers: eD / eD1 = table entries of steps n + D and n + D + 1;
+  // sD / svD = raw source boxes of step n + D and their validity; xr[i] /
+  // xv[i] = raw xi values of step n + i and their validity; o0 = operator
+  // values of step n
+  int2 eD = entry(nb + D), eD1 = entry(nb + D + 1);
+  int sD[2];
+  bool svD[2];
+  T xr[D][2];
+  bool xv[D][2];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const int2 e = entry(nb + i);
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const int sb = src_raw(e, ct);
+      xv[i][ct] = cc.ok[ct] && e.x >= 0 && sb >= 0;
+      xr[i][ct] = x_raw(xv[i][ct] ? sb : 0, e.y, ct);
+    }
+  }
 #pragma unroll
   for (int ct = 0; ct < 2; ++ct) {
-    sr1[ct] = src_raw(in1, ct);
-    sv1[ct] = cc.ok[ct] && in1.x >= 0;
-    const int s0 = src_raw(in0, ct);
-    xv0[ct] = cc.ok[ct] && in0.x >= 0 && s0 >= 0;
-    xr0[ct] = x_raw(xv0[ct] ? s0 : 0, in0.y, ct);
+    sD[ct] = src_raw(eD, ct);
+    svD[ct] = cc.ok[ct] && eD.x >= 0;
   }
+  T o0[RBO];
   int buf = 0;
   gload(nb);
   swrite(0);
   __syncthreads();
   oread(0, 0, o0);
-  for (int n = nb; n < nst; ++n) {
-    const int j = (n - nb) % C;
-    // issue the loads of the next steps
-    const int2 in3 = entry(n + 3);
-    int sr2[2];
-    bool sv2[2], xv1[2];
-    T xr1[2], o1[RBO];
-#pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-      sr2[ct] = src_raw(in2, ct);
-      sv2[ct] = cc.ok[ct] && in2.x >= 0;
-      xv1[ct] = sv1[ct] && sr1[ct] >= 0;
-      xr1[ct] = x_raw(xv1[ct] ? sr1[ct] : 0, row1, ct);
-    }
+  for (int c0 = nb; c0 < nst; c0 += C) {
     // the next chunk's operator (the padded buffer keeps the last one in bounds)
-    if (j == 0) gload(n + C);
-    // products of step n
-    T x0[2];
+    gload(c0 + C);
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) x0[ct] = xv0[ct] ? xr0[ct] : T(0);
-#pragma unroll
-    for (int rb = 0; rb < RBO; ++rb)
+    for (int j = 0; j < C; ++j) {
+      const int n = c0 + j;
+      // loads of later steps
+      const int2 eD2 = entry(n + D + 2);
+      int sD1[2];
+      bool svD1[2], xvD[2];
+      T xrD[2];
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) {
-        if constexpr (sizeof(T) == 4)
-          acc[rb][ct] = mf32(o0[rb], x0[ct], acc[rb][ct]);
-        else
-          acc[rb][ct] = mf64(o0[rb], x0[ct], acc[rb][ct]);
+        sD1[ct] = src_raw(eD1, ct);
+        svD1[ct] = cc.ok[ct] && eD1.x >= 0;
+        xvD[ct] = svD[ct] && sD[ct] >= 0;
+        xrD[ct] = x_raw(xvD[ct] ? sD[ct] : 0, eD.y, ct);
       }
-    // the next step's operator values, read while the MFMAs run
-    if (j + 1 < C) oread(buf, j + 1, o1);
-    // roll
+      // products of step n (none past the part's end)
+      T o1[RBO];
+      if (n < nst) {
+        T x0[2];
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-      xr0[ct] = xr1[ct];
-      xv0[ct] = xv1[ct];
-      sr1[ct] = sr2[ct];
-      sv1[ct] = sv2[ct];
-    }
-    row1 = in2.y;
-    in2 = in3;
-    if (j + 1 == C && n + 1 < nst) {
-      // end of a chunk: the next one into the other buffer (its last reader
-      // passed the previous barrier)
-      swrite(buf ^ 1);
-      __syncthreads();
-      buf ^= 1;
-      oread(buf, 0, o1);
-    }
+        for (int ct = 0; ct < 2; ++ct) x0[ct] = xv[0][ct] ? xr[0][ct] : T(0);
 #pragma unroll
-    for (int rb = 0; rb < RBO; ++rb) o0[rb] = o1[rb];
+        for (int rb = 0; rb < RBO; ++rb)
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) {
+            if constexpr (sizeof(T) == 4)
+              acc[rb][ct] = mf32(o0[rb], x0[ct], acc[rb][ct]);
+            else
+              acc[rb][ct] = mf64(o0[rb], x0[ct], acc[rb][ct]);
+          }
+      }
+      // the next step's operator values, read while the MFMAs run
+      if (j + 1 < C) oread(buf, j + 1, o1);
+      // roll
+#pragma unroll
+      for (int i = 0; i + 1 < D; ++i)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          xr[i][ct] = xr[i + 1][ct];
+          xv[i][ct] = xv[i + 1][ct];
+        }
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        xr[D - 1][ct] = xrD[ct];
+        xv[D - 1][ct] = xvD[ct];
+        sD[ct] = sD1[ct];
+        svD[ct] = svD1[ct];
+      }
+      eD = eD1;
+      eD1 = eD2;
+      if (j + 1 < C) {
+#pragma unroll
+        for (int rb = 0; rb < RBO; ++rb) o0[rb] = o1[rb];
+      }
+    }
+    // end of a chunk: the next one into the other buffer (its last reader
+    // passed the previous barrier)
+    swrite(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+    oread(buf, 0, o0);
   }
   const double scale = a.ksplit == 1 ? a.scale : 1.0;
 #pragma unroll
