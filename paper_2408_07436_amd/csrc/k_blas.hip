@@ -797,23 +797,71 @@ __global__ __launch_bounds__(256, 2) void stack_a_bf16_kernel(BlasStack a) {
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) acc[rb][ct] = v4f{0.f, 0.f, 0.f, 0.f};
   const v8bf zero8 = {};
-  for (int kb = 0; kb < a.kp; kb += 32) {
-    v8bf bh[2], bl[2];
+  // As in the FP32 / FP64 Stage A: each K slab (32) of the workgroup's 128
+  // operator rows, high and low parts, staged once in LDS (double-buffered,
+  // rows padded to 80 bytes for conflict-free 16-byte reads), the next
+  // slab's operator and multipole loads issued branch-free ahead of the
+  // current slab's MFMAs.
+  constexpr int RS = 40;  // bf16 values per LDS row
+  __shared__ __attribute__((aligned(16))) __bf16 lds[2][2][128 * RS];
+  const int srow = threadIdx.x >> 1, shalf = threadIdx.x & 1;
+  const int64_t asrc = (int64_t)srow * a.kp + shalf * 16;
+  v8bf sh0, sh1, sl0, sl1;  // 16 staged high and low values of this thread
+  auto gload = [&](int kb) {
+    sh0 = ld8bf(Ah + asrc + kb);
+    sh1 = ld8bf(Ah + asrc + kb + 8);
+    sl0 = ld8bf(Al + asrc + kb);
+    sl1 = ld8bf(Al + asrc + kb + 8);
+  };
+  auto swrite = [&](int buf) {
+    __bf16* dh = &lds[buf][0][srow * RS + shalf * 16];
+    __bf16* dl = &lds[buf][1][srow * RS + shalf * 16];
+    reinterpret_cast<v8bf*>(dh)[0] = sh0;
+    reinterpret_cast<v8bf*>(dh)[1] = sh1;
+    reinterpret_cast<v8bf*>(dl)[0] = sl0;
+    reinterpret_cast<v8bf*>(dl)[1] = sl1;
+  };
+  const int64_t qs[2] = {qo[0] >= 0 ? qo[0] : 0, qo[1] >= 0 ? qo[1] : 0};
+  auto load_q = [&](int kb, v8bf (&bh)[2], v8bf (&bl)[2]) {
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) {
-      bh[ct] = qo[ct] >= 0 ? ld8bf(qh + qo[ct] + kb + 8 * g4) : zero8;
-      bl[ct] = qo[ct] >= 0 ? ld8bf(ql + qo[ct] + kb + 8 * g4) : zero8;
+      const v8bf h = ld8bf(qh + qs[ct] + kb + 8 * g4), l = ld8bf(ql + qs[ct] + kb + 8 * g4);
+      bh[ct] = qo[ct] >= 0 ? h : zero8;
+      bl[ct] = qo[ct] >= 0 ? l : zero8;
     }
+  };
+  gload(0);
+  swrite(0);
+  v8bf bh[2], bl[2];
+  load_q(0, bh, bl);
+  __syncthreads();
+  int buf = 0;
+  for (int kb = 0; kb < a.kp; kb += 32, buf ^= 1) {
+    const bool more = kb + 32 < a.kp;
+    const int kn = more ? kb + 32 : kb;
+    v8bf nbh[2], nbl[2];
+    gload(kn);
+    load_q(kn, nbh, nbl);
+    // keep the next slab's loads ahead of this slab's MFMAs
+    __builtin_amdgcn_sched_barrier(0);
+    const __bf16* Lh = &lds[buf][0][l16 * RS + 8 * g4];
+    const __bf16* Ll = &lds[buf][1][l16 * RS + 8 * g4];
 #pragma unroll
     for (int rb = 0; rb < 8; ++rb) {
-      const int64_t o = (int64_t)(rb * 16 + l16) * a.kp + kb + 8 * g4;
-      const v8bf ah = ld8bf(Ah + o), al = ld8bf(Al + o);
+      const v8bf ah = ld8bf(Lh + rb * 16 * RS), al = ld8bf(Ll + rb * 16 * RS);
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) {
         acc[rb][ct] = mfbf(ah, bh[ct], acc[rb][ct]);
         acc[rb][ct] = mfbf(ah, bl[ct], acc[rb][ct]);
         acc[rb][ct] = mfbf(al, bh[ct], acc[rb][ct]);
       }
+    }
+    if (more) swrite(buf ^ 1);
+    __syncthreads();
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      bh[ct] = nbh[ct];
+      bl[ct] = nbl[ct];
     }
   }
   __bf16* xh = static_cast<__bf16*>(a.xi_hi);
@@ -850,9 +898,9 @@ __global__ __launch_bounds__(256, 2) void stack_b_bf16_kernel(BlasStack a) {
   const StackCols cc = stack_columns(a, wave, l16);
   const int32_t* src = a.tile_src + (int64_t)tile * a.J * a.TB;
   const int2* info = reinterpret_cast<const int2*>(a.info) + (int64_t)cls * a.nsteps * 4;
-  const int64_t boff = (int64_t)cls * a.nsteps * 64 * RBO * 8 + (int64_t)lane * RBO * 8;
-  const __bf16* Bh = static_cast<const __bf16*>(a.B_hi) + boff;
-  const __bf16* Bl = static_cast<const __bf16*>(a.B_lo) + boff;
+  const int64_t coff = (int64_t)cls * a.nsteps * 64 * RBO * 8;
+  const __bf16* Bh = static_cast<const __bf16*>(a.B_hi) + coff;
+  const __bf16* Bl = static_cast<const __bf16*>(a.B_lo) + coff;
   const __bf16* xh = static_cast<const __bf16*>(a.xi_hi);
   const __bf16* xl = static_cast<const __bf16*>(a.xi_lo);
   const int64_t rb8 = a.Rs / 8;
@@ -863,29 +911,95 @@ __global__ __launch_bounds__(256, 2) void stack_b_bf16_kernel(BlasStack a) {
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) acc[rb][ct] = v4f{0.f, 0.f, 0.f, 0.f};
   const v8bf zero8 = {};
-  // offsets of the xi values of one step, -1 if absent
-  auto offsets = [&](int n, int64_t o[2]) {
-    const int2 in = info[4 * n + g4];
+  if (nb >= nst) return;
+  // The step's operator (high and low parts, the same for the four waves)
+  // staged in LDS one step ahead (double-buffered; each lane's values padded
+  // by 16 bytes so that a quarter wave's 16-byte reads spread over the
+  // banks).  Loads without branches, masked where used: the table entries
+  // three steps ahead, the source boxes two, the xi values one.
+  constexpr int LS = RBO * 8 + 8;                  // bf16 values per lane in LDS
+  constexpr int U = RBO % 4 == 0 ? 8 : 4;          // staging unit (bf16 values)
+  constexpr int PU = 2 * RBO / U;                  // units per thread and part
+  typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
+  using SV = typename std::conditional<U == 8, v8bf, v4bf>::type;
+  __shared__ __attribute__((aligned(16))) __bf16 ops[2][2][64 * LS];
+  // thread t stages values [2 RBO t, 2 RBO (t + 1)) of the step's 8 RBO x 64
+  const int st_lane = threadIdx.x / 4, st_off = (threadIdx.x % 4) * 2 * RBO;
+  SV sgh[PU], sgl[PU];
+  auto gload = [&](int n) {
+    const int64_t o = (int64_t)n * 64 * RBO * 8 + (int64_t)threadIdx.x * 2 * RBO;
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-      const int sb = (cc.ok[ct] && in.x >= 0) ? src[in.x * a.TB + cc.slot[ct]] : -1;
-      o[ct] = sb >= 0 ? (((int64_t)sb * rb8 + in.y / 8) * a.nvec + cc.v[ct]) * 8 : -1;
+    for (int u = 0; u < PU; ++u) {
+      sgh[u] = *reinterpret_cast<const SV*>(Bh + o + u * U);
+      sgl[u] = *reinterpret_cast<const SV*>(Bl + o + u * U);
     }
   };
-  int64_t o1[2] = {-1, -1};
-  if (nb < nst) offsets(nb, o1);
+  auto swrite = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      *reinterpret_cast<SV*>(&ops[buf][0][st_lane * LS + st_off + u * U]) = sgh[u];
+      *reinterpret_cast<SV*>(&ops[buf][1][st_lane * LS + st_off + u * U]) = sgl[u];
+    }
+  };
+  const int sl[2] = {cc.ok[0] ? cc.slot[0] : 0, cc.ok[1] ? cc.slot[1] : 0};
+  auto entry = [&](int n) -> int2 {
+    const int2 e = info[4 * min(n, nst - 1) + g4];
+    return n < nst ? e : make_int2(-1, 0);
+  };
+  auto src_raw = [&](int2 e, int ct) -> int { return src[max(e.x, 0) * a.TB + sl[ct]]; };
+  auto xoff = [&](int sb, int2 e, int ct) -> int64_t {
+    return (((int64_t)max(sb, 0) * rb8 + e.y / 8) * a.nvec + cc.v[ct]) * 8;
+  };
+  // pipeline registers: e1 / e2 = table entries of steps n + 1, n + 2;
+  // s1 / sv1 = raw source boxes of step n + 1 and their validity; x0h / x0l
+  // / xv0 = raw xi values of step n and their validity
+  const int2 e0 = entry(nb);
+  int2 e1 = entry(nb + 1), e2 = entry(nb + 2);
+  int s1[2];
+  bool sv1[2], xv0[2];
+  v8bf x0h[2], x0l[2];
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct) {
+    const int s0 = src_raw(e0, ct);
+    xv0[ct] = cc.ok[ct] && e0.x >= 0 && s0 >= 0;
+    const int64_t o = xoff(xv0[ct] ? s0 : 0, e0, ct);
+    x0h[ct] = ld8bf(xh + o);
+    x0l[ct] = ld8bf(xl + o);
+    s1[ct] = src_raw(e1, ct);
+    sv1[ct] = cc.ok[ct] && e1.x >= 0;
+  }
+  int buf = 0;
+  gload(nb);
+  swrite(0);
+  __syncthreads();
   for (int n = nb; n < nst; ++n) {
+    // loads of later steps (the padded operator keeps step n + 1 in bounds)
+    const int2 e3 = entry(n + 3);
+    int s2[2];
+    bool sv2[2], xv1[2];
+    v8bf x1h[2], x1l[2];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      s2[ct] = src_raw(e2, ct);
+      sv2[ct] = cc.ok[ct] && e2.x >= 0;
+      xv1[ct] = sv1[ct] && s1[ct] >= 0;
+      const int64_t o = xoff(xv1[ct] ? s1[ct] : 0, e1, ct);
+      x1h[ct] = ld8bf(xh + o);
+      x1l[ct] = ld8bf(xl + o);
+    }
+    gload(n + 1);
+    // products of step n
     v8bf bh[2], bl[2];
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) {
-      bh[ct] = o1[ct] >= 0 ? ld8bf(xh + o1[ct]) : zero8;
-      bl[ct] = o1[ct] >= 0 ? ld8bf(xl + o1[ct]) : zero8;
+      bh[ct] = xv0[ct] ? x0h[ct] : zero8;
+      bl[ct] = xv0[ct] ? x0l[ct] : zero8;
     }
-    if (n + 1 < nst) offsets(n + 1, o1);
-    const int64_t so = (int64_t)n * 64 * RBO * 8;
+    const __bf16* Lh = &ops[buf][0][lane * LS];
+    const __bf16* Ll = &ops[buf][1][lane * LS];
 #pragma unroll
     for (int rb = 0; rb < RBO; ++rb) {
-      const v8bf ah = ld8bf(Bh + so + rb * 8), al = ld8bf(Bl + so + rb * 8);
+      const v8bf ah = ld8bf(Lh + rb * 8), al = ld8bf(Ll + rb * 8);
 #pragma unroll
       for (int ct = 0; ct < 2; ++ct) {
         acc[rb][ct] = mfbf(ah, bh[ct], acc[rb][ct]);
@@ -893,6 +1007,22 @@ __global__ __launch_bounds__(256, 2) void stack_b_bf16_kernel(BlasStack a) {
         acc[rb][ct] = mfbf(al, bh[ct], acc[rb][ct]);
       }
     }
+    // the next step's operator into the other buffer (its last reader
+    // passed the previous barrier)
+    swrite(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+    // roll
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      x0h[ct] = x1h[ct];
+      x0l[ct] = x1l[ct];
+      xv0[ct] = xv1[ct];
+      s1[ct] = s2[ct];
+      sv1[ct] = sv2[ct];
+    }
+    e1 = e2;
+    e2 = e3;
   }
   const double scale = a.ksplit == 1 ? a.scale : 1.0;
 #pragma unroll
