@@ -221,8 +221,10 @@ kifmm_status kifmm_evaluate_noalloc(kifmm_handle* h, const void* q_dev, int64_t 
                                     int32_t n_vec, void* phi_dev, int64_t ldphi,
                                     void* hip_stream);
 
-/* Release the handle and all device memory it owns.  NULL is accepted.
- * ESTATE (nothing released): a batch holds the handle. */
+/* Release the handle and all device memory it owns: what the setup of
+ * Section 5.1 built (tree, buffers and index pointers, maps, precomputed
+ * operators).  NULL is accepted.  ESTATE (nothing released): a batch holds
+ * the handle. */
 kifmm_status kifmm_destroy(kifmm_handle* h);
 
 /* Message of the last failed call on this thread ("" if none); the
@@ -381,6 +383,9 @@ enum {
 };
 /* Current knob values into knobs[0 .. KIFMM_TUNE_COUNT); cap >= KIFMM_TUNE_COUNT.
  * Host only. */
+/* Current knobs (KIFMM_TUNE_COUNT values; cap >= KIFMM_TUNE_COUNT): the
+ * launch-shape counterparts of the CPU parameters the paper tunes (the
+ * batch size of Appendix A.2, Section 4's parameter search). */
 kifmm_status kifmm_get_tuning(const kifmm_handle* h, int32_t* knobs, int32_t cap);
 /* Set the first n knobs (n <= KIFMM_TUNE_COUNT); EINVAL (nothing changed) if a
  * value is out of range; ESTATE if a batch holds the handle and a value
@@ -447,9 +452,12 @@ kifmm_status kifmm_batch_autotune(kifmm_handle* const* handles, int32_t n,
                                   const int64_t* ldphi, void* hip_stream, int32_t reps,
                                   kifmm_batch** out, double* best_ms);
 /* Launch the recorded graph on hip_stream (asynchronous), with the charge
- * and potential buffers given at creation (their current contents). */
+ * and potential buffers given at creation (their current contents): every
+ * problem's FMM passes (Section 2) with its vectors through the same
+ * launches (Section 3.2's multiple right-hand sides). */
 kifmm_status kifmm_batch_launch(kifmm_batch* batch, void* hip_stream);
-/* Launch the graph on hip_stream with other buffers: q_dev[i] / phi_dev[i]
+/* Launch the graph (the passes of Section 2 for every problem, as
+ * kifmm_batch_launch) on hip_stream with other buffers: q_dev[i] / phi_dev[i]
  * replace problem i's charge and potential buffers (same types, vector
  * counts and leading dimensions as at creation; device pointers owned by
  * the caller).  The buffer addresses are copied into the batch's device
@@ -458,11 +466,14 @@ kifmm_status kifmm_batch_launch(kifmm_batch* batch, void* hip_stream);
  * arguments. */
 kifmm_status kifmm_batch_evaluate(kifmm_batch* batch, const void* const* q_dev,
                                   void* const* phi_dev, void* hip_stream);
-/* info[0] problems, info[1] launches per replay, info[2] of which grouped
+/* Shape of the batch's launch schedule (a property of this library's
+ * grouped launches, not of the paper's method): info[0] problems, info[1]
+ * launches per replay, info[2] of which grouped
  * (the rest are kernels without a grouped form, such as the BLAS-M2L
  * kernels, one per problem and stage).  cap >= 3. */
 kifmm_status kifmm_batch_info(const kifmm_batch* batch, int64_t* info, int32_t cap);
-/* Destroy the graph and its capture streams (not the handles). */
+/* Destroy the graph and its capture streams (not the handles, whose setup
+ * of Section 5.1 stays for their own evaluates). */
 kifmm_status kifmm_batch_destroy(kifmm_batch* batch);
 
 #ifdef __cplusplus
