@@ -306,14 +306,45 @@ __device__ __forceinline__ void fft_forward_body(const FwdArgs& a, int64_t blk, 
 // Inverse transforms, one (row, child) box per item: complex inverse DFTs
 // along x (only x < p kept) and y (y < p), then the complex-to-real step
 // along z (odd length: no Nyquist term) at the p^3 lattice points, and the
-// check-surface points of those, scaled, stored in surface order.  Each
-// stage takes one line per task: the line's inputs in registers, and the
-// outputs one at a time (loop not unrolled) with that output's twiddles
-// conj(Wm[k][j]) at wave-uniform addresses (scalar registers), so the LDS
-// carries each intermediate value once in and once out.  The row's child
-// boxes and the surface-lattice table are read once per workgroup, so the
-// output stores wait on no vector-memory load.
-constexpr int kInvThreads = 512;  // with 8 boxes per workgroup: each y / z line in one pass
+// check-surface points of those, scaled, stored in surface order.  The x and
+// y stages are real products on MFMA: the 2p x 2n real form of the inverse
+// twiddles conj(Wm[k][j]) (held in registers) times 16-column tiles of the
+// lines' real and imaginary parts; the x stage takes its operand straight
+// from the spectra (each lane one complex value per group of four
+// frequencies), the y stage from LDS.  The z stage is a VALU sum per line
+// with the twiddles at wave-uniform addresses.  The row's child boxes and
+// the surface-lattice table are read once per workgroup, so the output
+// stores wait on no vector-memory load.
+constexpr int kInvThreads = 512;
+
+// LDS layout of the inverse transform per order P and complex width W
+// (dwords): `items` boxes per workgroup (within 52 KiB); the x-stage output
+// b2[item][x][ky][kz] (strides s2k, s2x, s2i) and the y-stage output
+// b1[item][x][y][kz] (strides s1y, s1x, s1i), in complex units, padded so
+// that the MFMA stages' stores and operand reads and the z stage's reads
+// spread over the banks (chosen by a bank model of those access patterns);
+// at p = 6 the padding keeps four workgroups per CU (40 KiB each).
+template <int P, int W> struct InvLds;
+#define KIFMM_INV_LDS(PP, WW, IT, A, B, C, D, E, F)                                   \
+  template <> struct InvLds<PP, WW> {                                                \
+    static constexpr int items = IT, s2k = A, s2x = B, s2i = C, s1y = D, s1x = E, s1i = F; \
+  };
+KIFMM_INV_LDS(2, 2, 8, 2, 7, 20, 2, 5, 12)
+KIFMM_INV_LDS(2, 4, 8, 2, 7, 14, 4, 8, 17)
+KIFMM_INV_LDS(3, 2, 8, 3, 15, 52, 5, 15, 45)
+KIFMM_INV_LDS(3, 4, 8, 3, 15, 46, 3, 9, 27)
+KIFMM_INV_LDS(4, 2, 8, 6, 43, 172, 4, 16, 65)
+KIFMM_INV_LDS(4, 4, 8, 4, 29, 118, 4, 17, 70)
+KIFMM_INV_LDS(5, 2, 8, 6, 55, 276, 5, 25, 125)
+KIFMM_INV_LDS(5, 4, 8, 5, 45, 226, 5, 25, 126)
+KIFMM_INV_LDS(6, 2, 8, 6, 67, 404, 6, 36, 219)
+KIFMM_INV_LDS(6, 4, 4, 6, 67, 404, 6, 36, 217)
+KIFMM_INV_LDS(7, 2, 4, 7, 94, 664, 10, 71, 504)
+KIFMM_INV_LDS(7, 4, 2, 7, 95, 680, 9, 63, 456)
+KIFMM_INV_LDS(8, 2, 4, 9, 138, 1112, 8, 65, 524)
+KIFMM_INV_LDS(8, 4, 2, 8, 121, 968, 10, 81, 648)
+#undef KIFMM_INV_LDS
+
 template <typename C2>
 __device__ inline C2 cmulc(C2 a, C2 b) {  // a * conj(b)
   C2 r;
@@ -321,9 +352,13 @@ __device__ inline C2 cmulc(C2 a, C2 b) {  // a * conj(b)
   r.y = a.y * b.x - a.x * b.y;
   return r;
 }
-template <typename T, int P, int ITEMS>
+
+template <typename T, int P>
 __device__ __forceinline__ void fft_inverse_body(const InvArgs& a, int64_t blk) {
   using C2 = typename C2T<T>::type;
+  using V4 = typename V4T<T>::type;
+  using L = InvLds<P, (int)sizeof(T) / 2>;
+  constexpr int ITEMS = L::items;
   const C2* __restrict__ Phat = static_cast<const C2*>(a.Phat);
   const int32_t* __restrict__ child = a.child;
   const int64_t n_rows = a.n_rows;
@@ -333,21 +368,25 @@ __device__ __forceinline__ void fft_inverse_body(const InvArgs& a, int64_t blk) 
   const double scale = a.scale;
   double* __restrict__ out = a.out;
   constexpr int N = 2 * P - 1, H = P, NS = 6 * (P - 1) * (P - 1) + 2;
-  __shared__ C2 b2[ITEMS][P][N][H];
-  __shared__ C2 b1[ITEMS][P][P][H];
+  // frequencies in groups of four along a line: K step 2q holds the real
+  // parts of frequencies 4q .. 4q + 3 (one per lane group), step 2q + 1
+  // their imaginary parts
+  constexpr int KQ = (N + 3) / 4, KS = 2 * KQ, NW = kInvThreads / 64;
+  static_assert(2 * P <= 16, "one 16-row MFMA tile holds a line's outputs");
+  __shared__ C2 b2[ITEMS * L::s2i];
+  __shared__ C2 b1[ITEMS * L::s1i];
   __shared__ int16_t sl[3 * NS];
   // real lattice values of the z stage, in b2 (free after the y stage)
-  static_assert(sizeof(T) * P * P * P <= sizeof(C2) * P * N * H, "lattice fits in b2");
-  T* zb = reinterpret_cast<T*>(&b2[0][0][0][0]);
+  static_assert(sizeof(T) * P * P * P <= sizeof(C2) * L::s2i, "lattice fits in b2");
+  T* zb = reinterpret_cast<T*>(b2);
   static_assert(ITEMS <= 8 && 8 % ITEMS == 0, "a workgroup's items lie within one row");
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wave = tid / 64, lc = tid % 16, lg = (tid % 64) / 16;
   // consecutive rows on one XCD, so the two 64-byte halves of a 128-byte
   // line of Phat are fetched once, into the same L2
   const int64_t nwg = (n_rows * 8 + ITEMS - 1) / ITEMS, per_xcd = (nwg + 7) / 8;
   const int64_t wg = (blk % 8) * per_xcd + blk / 8;
   if (wg >= nwg) return;
   const int64_t g0 = wg * ITEMS;
-  for (int t = tid; t < 3 * NS; t += kInvThreads) sl[t] = surf_lat[t];
   // the row's child boxes, read with scalar loads (uniform addresses), so
   // the output stores need no vector-memory wait between them
   const uint32_t row0 = (uint32_t)(g0 / 8), c0 = row0 / (uint32_t)nvec;
@@ -355,56 +394,102 @@ __device__ __forceinline__ void fft_inverse_body(const InvArgs& a, int64_t blk) 
   int32_t cb[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) cb[j] = child[(int64_t)c0 * 8 + j];
-  // x: complex inverse, only x in [0, p) is kept
-  for (int idx = tid; idx < ITEMS * N * H; idx += kInvThreads) {
-    const int it = idx % ITEMS, col = idx / ITEMS;
-    const int ky = col / H, kz = col % H;
-    const int64_t g = g0 + it, row = g / 8;
-    C2 v[N];
+  // MFMA operand A: lane (lc, lg) holds logical row m = (j, re/im) of the
+  // real form of conj(Wm)^T, column (frequency 4 (ks / 2) + lg, re/im of
+  // the input by the parity of ks); rows j >= p and frequencies >= n are 0,
+  // so the operand reads past a line's end may take any finite value.  Its
+  // twiddles are loaded first, then every x-stage operand of the wave (all
+  // loads in flight together; addresses clamped, so the waits count exactly).
+  const int m = a_row(T(0), lc), jm = m >> 1;
+  C2 wq[KQ];
 #pragma unroll
-    for (int kx = 0; kx < N; ++kx) {
-      const int64_t f = ((int64_t)kx * N + ky) * H + kz;
-      if (row < n_rows) {
-        v[kx] = Phat[(f * n_rows + row) * 8 + (g % 8)];
-      } else {
-        v[kx].x = T(0);
-        v[kx].y = T(0);
-      }
-    }
-    // x not unrolled: each x takes its n twiddles into scalar registers
-#pragma unroll 1
-    for (int x = 0; x < P; ++x) {
-      C2 acc;
-      acc.x = T(0);
-      acc.y = T(0);
+  for (int q = 0; q < KQ; ++q) wq[q] = Wm[min(4 * q + lg, N - 1) * P + min(jm, P - 1)];
+  // x: b2[it][j][ky][kz] = sum_kx Phat[(kx n + ky) p + kz][row][child] conj(Wm[kx][j]);
+  // columns (item, ky, kz), item fastest, so a lane group's eight columns
+  // read one row's contiguous children
+  constexpr int NCX = ITEMS * N * H, NTX = (NCX + 15) / 16, TPX = (NTX + NW - 1) / NW;
+  C2 vx[TPX][KQ];
+  {
+    const int64_t fstride = n_rows * 8;  // complex values per frequency
+    const C2* __restrict__ base = Phat + (int64_t)row0 * 8 + (g0 % 8);
 #pragma unroll
-      for (int kx = 0; kx < N; ++kx) {
-        const C2 t = cmulc(v[kx], Wm[kx * P + x]);
-        acc.x += t.x;
-        acc.y += t.y;
+    for (int u = 0; u < TPX; ++u) {
+      const int col = min(16 * (wave + u * NW) + lc, NCX - 1);
+      const int it = col % ITEMS, rest = col / ITEMS;  // rest = ky p + kz
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) {
+        const int kx = min(4 * q + lg, N - 1);
+        vx[u][q] = base[((int64_t)kx * N * H + rest) * fstride + it];
       }
-      b2[it][x][ky][kz] = acc;
     }
   }
-  __syncthreads();
-  // y: complex inverse, y in [0, p); one task per (item, x, kz) line
-  for (int idx = tid; idx < ITEMS * P * H; idx += kInvThreads) {
-    const int it = idx / (P * H), x = (idx / H) % P, kz = idx % H;
-    C2 v[N];
+  T Ar[KS];
 #pragma unroll
-    for (int ky = 0; ky < N; ++ky) v[ky] = b2[it][x][ky][kz];
-#pragma unroll 1
-    for (int y = 0; y < P; ++y) {
-      C2 acc;
-      acc.x = T(0);
-      acc.y = T(0);
+  for (int ks = 0; ks < KS; ++ks) {
+    const C2 w = wq[ks >> 1];
+    // (vr + i vi)(wr - i wi) = (vr wr + vi wi) + i (vi wr - vr wi)
+    const T val = (m & 1) ? ((ks & 1) ? w.x : -w.y) : ((ks & 1) ? w.y : w.x);
+    Ar[ks] = (jm < P && 4 * (ks >> 1) + lg < N) ? val : T(0);
+  }
 #pragma unroll
-      for (int ky = 0; ky < N; ++ky) {
-        const C2 t = cmulc(v[ky], Wm[ky * P + y]);
-        acc.x += t.x;
-        acc.y += t.y;
+  for (int u = 0; u < TPX; ++u) {
+    const int t = wave + u * NW;
+    if (t < NTX) {
+      V4 acc = V4{T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) {
+        acc = mfma16(Ar[2 * q], vx[u][q].x, acc);
+        acc = mfma16(Ar[2 * q + 1], vx[u][q].y, acc);
       }
-      b1[it][x][y][kz] = acc;
+      const int col = 16 * t + lc;
+      if (col < NCX) {
+        const int it = col % ITEMS, rest = col / ITEMS, ky = rest / H, kz = rest % H;
+        C2* o = b2 + it * L::s2i + ky * L::s2k + kz;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int j = 2 * lg + h;
+          if (j < P) o[j * L::s2x] = C2{acc[2 * h], acc[2 * h + 1]};
+        }
+      }
+    }
+  }
+  // the surface-lattice table, loaded after the spectra (its wait would
+  // otherwise hold back their loads)
+  for (int t = tid; t < 3 * NS; t += kInvThreads) sl[t] = surf_lat[t];
+  __syncthreads();
+  // y: b1[it][x][j][kz] = sum_ky b2[it][x][ky][kz] conj(Wm[ky][j]);
+  // columns (item, x, kz), item fastest; the wave's operands are read first
+  {
+    constexpr int NC = ITEMS * P * H, NT = (NC + 15) / 16, TPY = (NT + NW - 1) / NW;
+    C2 vy[TPY][KQ];
+#pragma unroll
+    for (int u = 0; u < TPY; ++u) {
+      const int col = min(16 * (wave + u * NW) + lc, NC - 1);
+      const int it = col % ITEMS, x = (col / ITEMS) % P, kz = col / (ITEMS * P);
+      const C2* src = b2 + it * L::s2i + x * L::s2x + kz;
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) vy[u][q] = src[min(4 * q + lg, N - 1) * L::s2k];
+    }
+#pragma unroll
+    for (int u = 0; u < TPY; ++u) {
+      const int t = wave + u * NW, col = 16 * t + lc;
+      if (t < NT) {
+        V4 acc = V4{T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+          acc = mfma16(Ar[2 * q], vy[u][q].x, acc);
+          acc = mfma16(Ar[2 * q + 1], vy[u][q].y, acc);
+        }
+        if (col < NC) {
+          const int it = col % ITEMS, x = (col / ITEMS) % P, kz = col / (ITEMS * P);
+          C2* o = b1 + it * L::s1i + x * L::s1x + kz;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int j = 2 * lg + h;
+            if (j < P) o[j * L::s1y] = C2{acc[2 * h], acc[2 * h + 1]};
+          }
+        }
+      }
     }
   }
   __syncthreads();
@@ -413,7 +498,7 @@ __device__ __forceinline__ void fft_inverse_body(const InvArgs& a, int64_t blk) 
     const int it = idx / (P * P), x = (idx / P) % P, y = idx % P;
     C2 v[H];
 #pragma unroll
-    for (int kz = 0; kz < H; ++kz) v[kz] = b1[it][x][y][kz];
+    for (int kz = 0; kz < H; ++kz) v[kz] = b1[it * L::s1i + x * L::s1x + y * L::s1y + kz];
 #pragma unroll 1
     for (int z = 0; z < P; ++z) {
       T acc = T(0);
@@ -795,17 +880,17 @@ __global__ __launch_bounds__((FftCfg<T, P>::threads)) void fft_forward_group_ker
   const FwdArgs a = jobs[j];
   fft_forward_body<T, P>(a, b, pre[j + 1] - pre[j]);
 }
-template <typename T, int P, int IT>
-__global__ __launch_bounds__(kInvThreads) void fft_inverse_kernel(InvArgs a) {
-  fft_inverse_body<T, P, IT>(a, blockIdx.x);
+template <typename T, int P>
+__global__ __launch_bounds__(kInvThreads) __attribute__((amdgpu_waves_per_eu(8))) void fft_inverse_kernel(InvArgs a) {
+  fft_inverse_body<T, P>(a, blockIdx.x);
 }
-template <typename T, int P, int IT>
-__global__ __launch_bounds__(kInvThreads) void fft_inverse_group_kernel(const InvArgs* __restrict__ jobs,
+template <typename T, int P>
+__global__ __launch_bounds__(kInvThreads) __attribute__((amdgpu_waves_per_eu(8))) void fft_inverse_group_kernel(const InvArgs* __restrict__ jobs,
                                                                         const int64_t* __restrict__ pre,
                                                                         int nj) {
   int64_t b;
   const InvArgs a = jobs[group_job(pre, nj, b)];
-  fft_inverse_body<T, P, IT>(a, b);
+  fft_inverse_body<T, P>(a, b);
 }
 template <typename T>
 __global__ __launch_bounds__(kHadThreads) void hadamard_gather_kernel(HadGatherArgs a) {
@@ -866,28 +951,19 @@ void fwd_go(const FwdArgs* one, const FwdArgs* jobs, const int64_t* pre, int nj,
     fft_forward_group_kernel<T, P><<<(unsigned)blocks, TH, 0, s>>>(jobs, pre, nj);
 }
 
-// inverse items per workgroup, sized so the LDS stays within 48 KiB
-template <typename T, int P> struct InvItems {
-  static constexpr int bytes = sizeof(T) * 2;
-  static constexpr int per = P * (2 * P - 1) * P * bytes + P * P * P * bytes;
-  static constexpr int raw = 49152 / per;
-  static constexpr int value = raw >= 8 ? 8 : raw >= 4 ? 4 : raw >= 2 ? 2 : 1;
-};
-
 template <typename T, int P>
 int64_t inv_blocks(int64_t n_rows) {
-  constexpr int IT = InvItems<T, P>::value;
+  constexpr int IT = InvLds<P, (int)sizeof(T) / 2>::items;
   return 8 * (((n_rows * 8 + IT - 1) / IT + 7) / 8);
 }
 
 template <typename T, int P>
 void inv_go(const InvArgs* one, const InvArgs* jobs, const int64_t* pre, int nj, int64_t blocks,
             hipStream_t s) {
-  constexpr int IT = InvItems<T, P>::value;
   if (!jobs)
-    fft_inverse_kernel<T, P, IT><<<(unsigned)blocks, kInvThreads, 0, s>>>(*one);
+    fft_inverse_kernel<T, P><<<(unsigned)blocks, kInvThreads, 0, s>>>(*one);
   else
-    fft_inverse_group_kernel<T, P, IT><<<(unsigned)blocks, kInvThreads, 0, s>>>(jobs, pre, nj);
+    fft_inverse_group_kernel<T, P><<<(unsigned)blocks, kInvThreads, 0, s>>>(jobs, pre, nj);
 }
 
 // p = 2..8 as a template argument
