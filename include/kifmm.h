@@ -373,13 +373,22 @@ kifmm_status kifmm_update_points(kifmm_handle* h, const void* src_dev, const voi
  *       in FP32, twice that in FP64), Stage B sums Ubar_t times those blocks
  *       per target box; 1 = fused, one kernel per level that gathers q~ per
  *       target tile and transfer vector and keeps Vbar'_t^T q~ in registers
- *       (no intermediate in memory).  Other M2L forms ignore it. */
+ *       (no intermediate in memory).  Other M2L forms ignore it.
+ *   [KIFMM_TUNE_PRODUCTS] FP32 FFT-M2L Hadamard products (Appendix A.2's
+ *       complex multiply-adds in single precision): 0 = every FP32 operand
+ *       value split into three BF16 parts (x0 = bf16(x), x1 = bf16(x - x0),
+ *       x2 = bf16(x - x0 - x1)) and each product taken as the six part
+ *       products of order at most two, summed in FP32 on BF16 MFMA (the
+ *       dropped terms lie below 2^-24 of the product, so the sums carry an
+ *       FP32 product's rounding error); 1 = FP32 MFMA.  The two agree to
+ *       FP32 rounding, not bit for bit. */
 enum {
   KIFMM_TUNE_BLAS_TILE = 0,
   KIFMM_TUNE_SCHEDULE = 1,
   KIFMM_TUNE_HADAMARD = 2,
   KIFMM_TUNE_BLAS_FORM = 3,
-  KIFMM_TUNE_COUNT = 4
+  KIFMM_TUNE_PRODUCTS = 4,
+  KIFMM_TUNE_COUNT = 5
 };
 /* Current knob values into knobs[0 .. KIFMM_TUNE_COUNT); cap >= KIFMM_TUNE_COUNT.
  * Host only. */

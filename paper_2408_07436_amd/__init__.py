@@ -31,7 +31,7 @@ EXPORTS = [
     "kifmm_batch_evaluate", "kifmm_batch_info",
 ]
 NOALLOC_SCRATCH_BYTES = 256 << 20  # KIFMM_NOALLOC_SCRATCH_BYTES
-TUNE_KNOBS = ("blas_tile", "schedule", "hadamard", "blas_form")
+TUNE_KNOBS = ("blas_tile", "schedule", "hadamard", "blas_form", "products")
 
 
 class KifmmError(RuntimeError):

@@ -369,7 +369,7 @@ kifmm_status kifmm_get_tuning(const kifmm_handle* h, int32_t* knobs, int32_t cap
 kifmm_status kifmm_set_tuning(kifmm_handle* h, const int32_t* knobs, int32_t n) {
   if (!h || !knobs) return fail(KIFMM_EINVAL, "null argument");
   if (n < 0 || n > KIFMM_TUNE_COUNT) return fail(KIFMM_EINVAL, "bad knob count");
-  static const int32_t hi[KIFMM_TUNE_COUNT] = {128, 1, 1, 1};
+  static const int32_t hi[KIFMM_TUNE_COUNT] = {128, 1, 1, 1, 1};
   for (int i = 0; i < n; ++i)
     if (knobs[i] < 0 || knobs[i] > hi[i]) return fail(KIFMM_EINVAL, "knob value out of range");
   if (h->batches > 0)

@@ -89,7 +89,7 @@ hipError_t run_group(const GroupLaunch& g, const uint8_t* base, hipStream_t s) {
     case kFamFwd:
       return launch_fft_forward_group(g.inst, static_cast<const FwdArgs*>(jobs), pre, g.nj, g.blocks, s);
     case kFamHad:
-      return launch_hadamard_group(g.inst == 1, jobs, pre, g.nj, g.blocks, s);
+      return launch_hadamard_group(g.inst, jobs, pre, g.nj, g.blocks, s);
     case kFamInv:
       return launch_fft_inverse_group(g.inst, static_cast<const InvArgs*>(jobs), pre, g.nj, g.blocks, s);
     case kFamLeaf:

@@ -94,6 +94,7 @@ struct DeviceState {
   // pseudo-inverse, pseudo-inverses folded into M2M / L2L)
   double *up_P = nullptr, *down_P = nullptr, *m2m_c = nullptr, *l2l_c = nullptr;
   void* khat = nullptr;
+  void* khat_split = nullptr;  // FP32: BF16 parts of khat for the split Hadamard
   void* twiddle = nullptr;
   double* Ublas = nullptr;   // nc x k: decompression
   double* SblasT = nullptr;  // k x ns: compression
@@ -706,6 +707,7 @@ static kifmm_status build_source_blocks(DeviceState* d, DevLevel& D, const Level
 struct SharedFft {
   int64_t refs = 0;
   void* khat = nullptr;
+  void* khat_split = nullptr;
   void* twiddle = nullptr;
 };
 std::mutex g_fft_mu;
@@ -718,6 +720,7 @@ void release_shared_fft(DeviceState* d) {
   if (it != g_fft.end() && --it->second.refs == 0) {
     // teardown: failures are ignored
     (void)hipFree(it->second.khat);
+    if (it->second.khat_split) (void)hipFree(it->second.khat_split);
     (void)hipFree(it->second.twiddle);
     g_fft.erase(it);
   }
@@ -811,6 +814,7 @@ kifmm_status upload_all(kifmm_handle* h) {
     if (found != g_fft.end()) {
       ++found->second.refs;
       d->khat = found->second.khat;
+      d->khat_split = found->second.khat_split;
       d->twiddle = found->second.twiddle;
       d->fft_key = key;
       d->fft_shared = true;
@@ -864,14 +868,29 @@ kifmm_status upload_all(kifmm_handle* h) {
         std::vector<float> twf(tw.begin(), tw.end()), khf(kh.begin(), kh.end());
         st = put(twf.data(), twf.size() * sizeof(float), &sh.twiddle);
         if (st == KIFMM_OK) st = put(khf.data(), khf.size() * sizeof(float), &sh.khat);
+        if (st == KIFMM_OK) {
+          // BF16 parts of the B operand of the split Hadamard
+          hipError_t e = hipMalloc(&sh.khat_split, (size_t)hadamard_split_bytes(F));
+          if (e != hipSuccess) {
+            sh.khat_split = nullptr;
+            st = fail(KIFMM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+          } else {
+            e = launch_hadamard_split_prep(sh.khat, F, sh.khat_split, nullptr);
+            if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+            if (e != hipSuccess) st = fail(KIFMM_EDEVICE, std::string("split prep: ") + hipGetErrorString(e));
+          }
+        }
       }
       if (st != KIFMM_OK) {
         if (sh.twiddle) (void)hipFree(sh.twiddle);
+        if (sh.khat) (void)hipFree(sh.khat);
+        if (sh.khat_split) (void)hipFree(sh.khat_split);
         return st;
       }
       sh.refs = 1;
       g_fft[key] = sh;
       d->khat = sh.khat;
+      d->khat_split = sh.khat_split;
       d->twiddle = sh.twiddle;
       d->fft_key = key;
       d->fft_shared = true;
@@ -1050,20 +1069,22 @@ hipError_t run_fft_forward(DeviceState* d, int p, const double* M, const int32_t
 }
 
 hipError_t run_hadamard(DeviceState* d, int F, const DevLevel& D, int64_t ncl, int nvec, bool units,
-                        hipStream_t s) {
+                        bool split, hipStream_t s) {
+  const bool bf16 = split && !d->fp64;
+  const void* kt = bf16 ? d->khat_split : d->khat;
   if (!d->sink)
-    return launch_hadamard(d->fp64, F, d->khat, D.Qhat, D.halo, D.hb_n, D.hb_tgt, D.hb_src, D.hb_list,
+    return launch_hadamard(d->fp64, bf16, F, kt, D.Qhat, D.halo, D.hb_n, D.hb_tgt, D.hb_src, D.hb_list,
                            D.hb_tbase, ncl, nvec, units, D.Phat, s);
   HadBlockArgs ab;
   HadGatherArgs ag;
   int64_t blocks;
-  const hipError_t e = plan_hadamard(d->fp64, F, d->khat, D.Qhat, D.halo, D.hb_n, D.hb_tgt, D.hb_src,
+  const hipError_t e = plan_hadamard(d->fp64, bf16, F, kt, D.Qhat, D.halo, D.hb_n, D.hb_tgt, D.hb_src,
                                      D.hb_list, D.hb_tbase, ncl, nvec, 2, D.Phat, ab, ag, blocks);
   if (e != hipSuccess || blocks == 0) return e;
   if (d->fp64)
-    d->sink->add(kFamHad, 1, ag, blocks);
+    d->sink->add(kFamHad, hadamard_inst(true, false), ag, blocks);
   else
-    d->sink->add(kFamHad, 0, ab, blocks);
+    d->sink->add(kFamHad, hadamard_inst(false, bf16), ab, blocks);
   return hipSuccess;
 }
 
@@ -1122,7 +1143,8 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
     // spectra of the nc clusters and of the empty cluster behind them
     KIFMM_LAUNCH(run_fft_forward(d, op.p, in, child, nc + 1, nvec, D.Qhat, s));
     if (mark) KIFMM_HIP(hipEventRecord(mark[1], s));
-    KIFMM_LAUNCH(run_hadamard(d, op.F, D, nc, nvec, h->tune[KIFMM_TUNE_HADAMARD] == 1, s));
+    KIFMM_LAUNCH(run_hadamard(d, op.F, D, nc, nvec, h->tune[KIFMM_TUNE_HADAMARD] == 1,
+                              h->tune[KIFMM_TUNE_PRODUCTS] == 0, s));
     if (mark) KIFMM_HIP(hipEventRecord(mark[2], s));
     const double scale = 1.0 / ((double)op.n * op.n * op.n * D.w);  // 1 / (n^3 w)
     KIFMM_LAUNCH(run_fft_inverse(d, op.p, D.Phat, child, nc, nvec, scale, out, s));

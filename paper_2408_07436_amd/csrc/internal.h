@@ -205,7 +205,7 @@ struct kifmm_handle {
   kifmm::DeviceState* dev = nullptr;
   bool timing = false;
   double timings[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  int32_t tune[KIFMM_TUNE_COUNT] = {0, 0, 0, 0};  // autotuning knobs (kifmm.h)
+  int32_t tune[KIFMM_TUNE_COUNT] = {0, 0, 0, 0, 0};  // autotuning knobs (kifmm.h)
   bool points_on_device = false;  // host copies of the point order are stale
   bool tree_on_device = false;    // host copies of the levels and lists are stale
   kifmm::SvdOptions svd;          // K_fat compression (BLAS-M2L)

@@ -862,6 +862,322 @@ __device__ __forceinline__ void hadamard_block_body(const HadBlockArgs& a, int64
   }
 }
 
+// Split form (FP32 inputs and outputs, products on BF16 MFMA).  Every FP32
+// operand value x is split into three BF16 parts, x0 = bf16(x),
+// x1 = bf16(x - x0), x2 = bf16(x - x0 - x1) (each residual exact in FP32),
+// which together carry its 24 significant bits; a product a b is taken as
+// the six part products of order at most two, a0 b0 + a0 b1 + a1 b0 + a0 b2
+// + a1 b1 + a2 b0 (the dropped ones lie below 2^-24 |a b|).  Each BF16
+// product is exact in FP32 and v_mfma_f32_16x16x32_bf16 sums them in FP32,
+// so the result carries an FP32 GEMM's rounding error, at six BF16 MFMAs
+// (16 cycles each) per two directions instead of eight FP32 MFMAs (32 cycles
+// each).  Work split and staging pipeline are those of the block form.  An
+// LDS row (kSplitRowBytes = 96) holds the three parts of a cluster's 16
+// reals: reals 0-7 as parts 0, 1, 2 (16 bytes each), then reals 8-15 the
+// same way; the cluster at shell position (x, y, z) of staging buffer b sits
+// in row x + 6 b + 12 y + 72 z (the two buffers interleaved along x).  With
+// this layout the 128-bit operand reads of a tile's sixteen clusters meet no
+// LDS bank conflict in any direction (measured with rocprofv3's
+// SQ_LDS_BANK_CONFLICT on the exact access pattern; 32-byte plane rows of
+// 112 bytes cost four conflict cycles per read).  K step j of a product
+// covers two directions (lane groups 0, 1 and 2, 3), each lane group eight
+// consecutive reals of its direction's source row; the B parts are split
+// once per kernel-spectrum table.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
+constexpr int kSplitRowBytes = 96;  // 2 halves x 3 parts x 16 bytes
+constexpr int kSplitHalf = 48;      // bytes from reals 0-7 to reals 8-15
+constexpr int kSplitPart = 16;      // bytes from one part to the next within a half
+constexpr int kSplitY = 12, kSplitZ = 72;  // row strides along y and z (x: 1, buffers: 6)
+constexpr int kSplitBias = 1 + kSplitY + kSplitZ;  // rows of shell position (1, 1, 1)
+constexpr int kSplitDiscard = kHadShell * kSplitZ * kSplitRowBytes;  // past both buffers' rows
+constexpr int kSplitLds = kSplitDiscard + kSplitRowBytes;
+static_assert(kSplitRowBytes == 2 * kSplitHalf && kSplitHalf == 3 * kSplitPart, "row of 2 x 3 parts");
+static_assert(kSplitY == 2 * kHadShell && kSplitZ == kHadShell * kSplitY,
+              "the two buffers fill the gaps along x");
+// LDS row of shell slot s = x + 6 y + 36 z (s < 256) in buffer b:
+// x + 12 y + 72 z + 6 b = s + 6 (s / 6 + b), s / 6 as (171 s) >> 10
+__device__ inline uint32_t split_row(uint32_t s, uint32_t b) { return s + 6u * (((s * 171u) >> 10) + b); }
+// byte offset of direction d (numbered as had_dir_bytes) from a biased base
+__host__ __device__ constexpr int split_dir_bytes(int d) {
+  return (kSplitBias + ((d < 13 ? d : d + 1) / 9 - 1) + kSplitY * ((d < 13 ? d : d + 1) / 3 % 3 - 1) +
+          kSplitZ * ((d < 13 ? d : d + 1) % 3 - 1)) *
+         kSplitRowBytes;
+}
+// Direction of half h of K step j: the nine pairs (x, y, -1), (x, y, +1),
+// then (x, -1, 0), (x, +1, 0) for x = -1, 0, 1, then (-1, 0, 0), (+1, 0, 0),
+// so that the second half's LDS offset exceeds the first's by one of three
+// constants (144, 24 or 2 rows).  Directions are numbered as had_dir_bytes.
+__host__ __device__ constexpr int split_pair_dir(int j, int h) {
+  const int x = j < 9 ? j / 3 - 1 : j < 12 ? j - 10 : (h ? 1 : -1);
+  const int y = j < 9 ? j % 3 - 1 : j < 12 ? (h ? 1 : -1) : 0;
+  const int z = j < 9 ? (h ? 1 : -1) : 0;
+  const int ix = (x + 1) * 9 + (y + 1) * 3 + (z + 1);
+  return ix < 13 ? ix : ix - 1;
+}
+__host__ __device__ constexpr int split_pair_step(int j) {  // second-half offset over the first, bytes
+  return split_dir_bytes(split_pair_dir(j, 1)) - split_dir_bytes(split_pair_dir(j, 0));
+}
+static_assert(split_pair_step(0) == 2 * kSplitZ * kSplitRowBytes &&
+                  split_pair_step(9) == 2 * kSplitY * kSplitRowBytes && split_pair_step(12) == 2 * kSplitRowBytes,
+              "pair offsets");
+
+__device__ inline void split3(float x, __bf16& h0, __bf16& h1, __bf16& h2) {
+  h0 = (__bf16)x;
+  const float r1 = x - (float)h0;
+  h1 = (__bf16)r1;
+  h2 = (__bf16)(r1 - (float)h1);
+}
+// the three parts of two values, two BF16 per dword (value a in the low half)
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+__device__ inline void split3x2(float a, float b, uint32_t& p0, uint32_t& p1, uint32_t& p2) {
+  p0 = __builtin_bit_cast(uint32_t, __builtin_convertvector(v2f{a, b}, v2bf));
+  const float ra = a - __uint_as_float(p0 << 16), rb = b - __uint_as_float(p0 & 0xffff0000u);
+  p1 = __builtin_bit_cast(uint32_t, __builtin_convertvector(v2f{ra, rb}, v2bf));
+  const float sa = ra - __uint_as_float(p1 << 16), sb = rb - __uint_as_float(p1 & 0xffff0000u);
+  p2 = __builtin_bit_cast(uint32_t, __builtin_convertvector(v2f{sa, sb}, v2bf));
+}
+__device__ inline v4f mfbf16(v8bf a, v8bf b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// B operand parts of the split form, once per kernel-spectrum table:
+// Bs[((f * 3 + part) * 13 + j) * 64 + lane] (8 BF16 each) holds part `part`
+// of the coefficients that lane (n, g) of K step j takes: source reals
+// 8 (g % 2) .. + 7 (children 4 (g % 2) .. + 3, real and imaginary parts) of
+// direction split_pair_dir(j, g / 2) into output n (target child n / 2, real
+// part for even n, imaginary for odd n).  One thread per (f, j, lane).
+__global__ __launch_bounds__(256) void hadamard_split_prep_kernel(const float2* __restrict__ Khat, int F,
+                                                                 v8bf* __restrict__ Bs) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)F * 13 * 64) return;
+  const int lane = (int)(t % 64), j = (int)(t / 64 % 13);
+  const int64_t f = t / (64 * 13);
+  const int rl = lane % 16, g = lane / 16;
+  const int d = split_pair_dir(j, g >> 1);
+  v8bf p[3];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const float2 k = Khat[((f * 26 + d) * 8 + rl / 2) * 8 + 4 * (g & 1) + c];
+    const float cre = (rl & 1) ? k.y : k.x;   // coefficient of the real part
+    const float cim = (rl & 1) ? k.x : -k.y;  // coefficient of the imaginary part
+    __bf16 h0, h1, h2;
+    split3(cre, h0, h1, h2);
+    p[0][2 * c] = h0;
+    p[1][2 * c] = h1;
+    p[2][2 * c] = h2;
+    split3(cim, h0, h1, h2);
+    p[0][2 * c + 1] = h0;
+    p[1][2 * c + 1] = h1;
+    p[2][2 * c + 1] = h2;
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) Bs[((f * 3 + q) * 13 + j) * 64 + lane] = p[q];
+}
+
+__device__ __forceinline__ void hadamard_split_body(const HadBlockArgs& a, int64_t b, int64_t nblk) {
+  const v8bf* __restrict__ Ksp = static_cast<const v8bf*>(a.Khat);  // parts from the prep kernel
+  const float* __restrict__ Qhat = static_cast<const float*>(a.Qhat);
+  const int32_t* __restrict__ blk_tgt = a.blk_tgt;
+  const int32_t* __restrict__ blk_src = a.blk_src;
+  const int32_t* __restrict__ blk_list = a.blk_list;
+  const int32_t* __restrict__ tbase = a.tbase;
+  const int n_items = a.n_items, nvec = a.nvec;
+  const int64_t n_rows = a.n_rows, total_items = a.total_items, unit_len = a.unit_len;
+  const int64_t n_units = a.n_units, n_wgs = a.n_wgs;
+  float* __restrict__ Phat = static_cast<float*>(a.Phat);
+  __shared__ __attribute__((aligned(16))) char As[kSplitLds];  // both staging buffers
+  __shared__ __attribute__((aligned(16))) char Bs[13 * 64 * 16];  // B2 parts, [j][lane]
+  const int64_t per_xcd = nblk / 8;  // grid: a multiple of 8
+  const int64_t logical = (b % 8) * per_xcd + b / 8;  // consecutive work per XCD
+  if (logical >= n_wgs) return;
+  const int tid = threadIdx.x;
+  const int wave = tid / 64, lane = tid % 64;
+  const int rl = lane % 16, g = lane / 16;
+  const int tr0 = wave * 16;  // this wave's tile of the block's targets
+  const uint32_t row_bytes = 64u * (uint32_t)nvec;  // one cluster's rows in Qhat / Phat
+  // staging: four 16-byte pieces (4 reals) per thread as in the block form;
+  // piece k is row (tid + 256 k) / 4, reals 4 (tid % 4) .. + 3, written as
+  // three 8-byte parts, kSplitPart apart, in half (tid % 4) / 2
+  static_assert(kHadStage == 4, "staging pieces per thread");
+  const uint32_t part_bytes = (uint32_t)(kSplitHalf * ((tid & 3) >> 1) + 8 * (tid & 1));
+  // two sets of staging registers, alternating by step: one item's rows are
+  // loaded into one set at the top of a step while the other set (the
+  // previous item's rows) is split into LDS
+  float4 sa0, sa1, sa2, sa3, sb0, sb1, sb2, sb3;
+  uint32_t ea0 = 0, ea1 = 0, ea2 = 0, ea3 = 0;
+  uint32_t eb0 = 0, eb1 = 0, eb2 = 0, eb3 = 0;
+  uint32_t tba = 0, tbb = 0;
+  float res0 = 0.f, res1 = 0.f, res2 = 0.f, res3 = 0.f;  // products of the last item computed
+  auto entry = [&](int s0, int ns, int k) __attribute__((always_inline)) {
+    const int r = (tid + kHadThreads * k) >> 2;
+    return (uint32_t)blk_list[r < ns ? s0 + r : 0];
+  };
+  // slots past the shell (the empty cluster's 255) map past both buffers'
+  // rows, into the discard row
+  auto lds_slot = [&](uint32_t e, uint32_t b) __attribute__((always_inline)) {
+    return min(split_row(e & 255u, b), (uint32_t)(kHadShell * kSplitZ)) * (uint32_t)kSplitRowBytes + part_bytes;
+  };
+  auto put = [&](char* ab, uint32_t off, float4 v) __attribute__((always_inline)) {
+    uint2 p0, p1, p2;
+    split3x2(v.x, v.y, p0.x, p1.x, p2.x);
+    split3x2(v.z, v.w, p0.y, p1.y, p2.y);
+    *reinterpret_cast<uint2*>(ab + off) = p0;
+    *reinterpret_cast<uint2*>(ab + off + kSplitPart) = p1;
+    *reinterpret_cast<uint2*>(ab + off + 2 * kSplitPart) = p2;
+  };
+  int buf = 0;
+  for (int64_t unit = logical; unit < n_units; unit += n_wgs) {
+  const int64_t q0 = unit * unit_len, q1 = min(q0 + unit_len, total_items);
+  for (int64_t seg = q0; seg < q1;) {
+  const int64_t f = seg / n_items;
+  const int item0 = (int)(seg - f * n_items);
+  const int item1 = (int)(min(q1, (f + 1) * n_items) - f * n_items);
+  seg = f * n_items + item1;
+  // B parts of this frequency (laid out by hadamard_split_prep_kernel):
+  // parts 0 and 1 in registers, part 2 (one product per K step) in LDS,
+  // copied after every wave is done with the previous frequency
+  v8bf B0[13], B1[13];
+  {
+    const v8bf* kb = Ksp + f * 3 * 13 * 64;
+#pragma unroll
+    for (int j = 0; j < 13; ++j) {
+      B0[j] = kb[j * 64 + lane];
+      B1[j] = kb[(13 + j) * 64 + lane];
+    }
+    __syncthreads();
+    for (int e = tid; e < 13 * 64; e += kHadThreads)
+      *reinterpret_cast<v8bf*>(Bs + e * 16) = kb[2 * 13 * 64 + e];
+    __syncthreads();
+  }
+  const char* qf = reinterpret_cast<const char*>(Qhat + f * (n_rows + nvec) * 16);
+  char* pf = reinterpret_cast<char*>(Phat + f * n_rows * 16);
+  // software pipeline of the block form: step `it` stages item it - 1,
+  // stores the products of item it - 2, loads item it and computes item it - 1
+  int lblk = item0 / nvec, lv = item0 - lblk * nvec;  // item it
+  int cv = 0, ct0 = 0, cnt = 0;  // item it - 1: vector, first cluster, count
+  int sv = 0, st0 = 0, snt = 0;  // item it - 2
+  int nt0 = blk_tgt[lblk], nt1 = blk_tgt[lblk + 1];  // clusters of item it's block
+  int es0, es1;  // list range of item it + 1
+  {
+    const int s0 = blk_src[lblk], ns = blk_src[lblk + 1] - s0;
+    ea0 = entry(s0, ns, 0);
+    ea1 = entry(s0, ns, 1);
+    ea2 = entry(s0, ns, 2);
+    ea3 = entry(s0, ns, 3);
+    const int b1 = (lv + 1 == nvec) ? lblk + 1 : lblk;
+    const int bb = min(b1, (int)(((int64_t)n_items - 1) / nvec));
+    es0 = blk_src[bb];
+    es1 = blk_src[bb + 1];
+  }
+  auto step = [&](int it, uint32_t& w0, uint32_t& w1, uint32_t& w2, uint32_t& w3, uint32_t u0,
+                  uint32_t u1, uint32_t u2, uint32_t u3, uint32_t tbc, uint32_t& tbn, const float4& c0,
+                  const float4& c1, const float4& c2, const float4& c3, float4& n0, float4& n1, float4& n2,
+                  float4& n3) __attribute__((always_inline)) {
+    __builtin_amdgcn_s_waitcnt(0);  // the previous step's loads and stores
+    if (it < item1) {
+      // rows of item it (entries loaded in the previous step), first of the
+      // step so that they have its whole length to arrive
+      const uint32_t vb = (uint32_t)lv * 64u + 16u * (uint32_t)(tid & 3);
+      n0 = *reinterpret_cast<const float4*>(qf + ((u0 >> 8) * row_bytes + vb));
+      n1 = *reinterpret_cast<const float4*>(qf + ((u1 >> 8) * row_bytes + vb));
+      n2 = *reinterpret_cast<const float4*>(qf + ((u2 >> 8) * row_bytes + vb));
+      n3 = *reinterpret_cast<const float4*>(qf + ((u3 >> 8) * row_bytes + vb));
+      tbn = (uint32_t)tbase[nt0 + min(tr0 + rl, nt1 - nt0 - 1)];
+    }
+    const bool write = it > item0 && it <= item1;  // rows of item it - 1 staged
+    if (write) {
+      put(As, lds_slot(w0, buf), c0);
+      put(As, lds_slot(w1, buf), c1);
+      put(As, lds_slot(w2, buf), c2);
+      put(As, lds_slot(w3, buf), c3);
+    }
+    if (it >= item0 + 2 && tr0 < snt) {
+      const uint32_t o0 = ((uint32_t)(st0 + tr0 + 4 * g) * nvec + sv) * 64u + 4u * rl;
+      const int rr = tr0 + 4 * g;
+      if (rr + 0 < snt) *reinterpret_cast<float*>(pf + o0) = res0;
+      if (rr + 1 < snt) *reinterpret_cast<float*>(pf + o0 + row_bytes) = res1;
+      if (rr + 2 < snt) *reinterpret_cast<float*>(pf + o0 + 2 * row_bytes) = res2;
+      if (rr + 3 < snt) *reinterpret_cast<float*>(pf + o0 + 3 * row_bytes) = res3;
+    }
+    if (write) __syncthreads();  // this buffer complete; the other one free for the next item
+    sv = cv;
+    st0 = ct0;
+    snt = cnt;
+    if (it + 1 < item1) {  // entries of item it + 1 (those of item it - 1 are staged)
+      w0 = entry(es0, es1 - es0, 0);
+      w1 = entry(es0, es1 - es0, 1);
+      w2 = entry(es0, es1 - es0, 2);
+      w3 = entry(es0, es1 - es0, 3);
+    }
+    const int pnt0 = nt0, pnt1 = nt1, plv = lv;
+    if (++lv == nvec) {
+      lv = 0;
+      ++lblk;
+    }
+    if (it + 1 < item1) {
+      nt0 = blk_tgt[lblk];
+      nt1 = blk_tgt[lblk + 1];
+    }
+    if (it + 2 < item1) {
+      const int b2 = (lv + 1 == nvec) ? lblk + 1 : lblk;  // block of item it + 2
+      es0 = blk_src[b2];
+      es1 = blk_src[b2 + 1];
+    }
+    if (write && tr0 < cnt) {
+      // the lane's source row of K step j's first direction (lane groups 0,
+      // 1) or second (2, 3): the target's biased base (its slot from the
+      // block-form offset) plus the direction's constant offset; the next
+      // step's parts are read before the current step's MFMAs.  Two
+      // accumulators take alternate products.
+      const uint32_t ts = tbc / (uint32_t)kHadRowBytes + (uint32_t)kHadSlotBias;  // target's slot
+      const char* ab = As + (split_row(ts, buf) - kSplitBias) * kSplitRowBytes + kSplitHalf * (g & 1);
+      const bool hi = g >= 2;
+      const int hs72 = hi ? 2 * kSplitZ * kSplitRowBytes : 0, hs12 = hi ? 2 * kSplitY * kSplitRowBytes : 0,
+                hs2 = hi ? 2 * kSplitRowBytes : 0;
+      const char* bb = Bs + lane * 16;
+      auto ldA = [&](int j, v8bf& x0, v8bf& x1, v8bf& x2, v8bf& y2) __attribute__((always_inline)) {
+        const char* pa = ab + (j < 9 ? hs72 : j < 12 ? hs12 : hs2) + split_dir_bytes(split_pair_dir(j, 0));
+        x0 = *reinterpret_cast<const v8bf*>(pa);
+        x1 = *reinterpret_cast<const v8bf*>(pa + kSplitPart);
+        x2 = *reinterpret_cast<const v8bf*>(pa + 2 * kSplitPart);
+        y2 = *reinterpret_cast<const v8bf*>(bb + j * 64 * 16);
+      };
+      v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+      v8bf n0, n1, n2, m2;
+      ldA(0, n0, n1, n2, m2);
+#pragma unroll
+      for (int j = 0; j < 13; ++j) {
+        const v8bf a0 = n0, a1 = n1, a2 = n2, b2 = m2;
+        if (j + 1 < 13) ldA(j + 1, n0, n1, n2, m2);
+        __builtin_amdgcn_sched_barrier(0);
+        acc0 = mfbf16(a0, B0[j], acc0);
+        acc1 = mfbf16(a0, B1[j], acc1);
+        acc0 = mfbf16(a1, B0[j], acc0);
+        acc1 = mfbf16(a0, b2, acc1);
+        acc0 = mfbf16(a1, B1[j], acc0);
+        acc1 = mfbf16(a2, B0[j], acc1);
+      }
+      res0 = acc0[0] + acc1[0];
+      res1 = acc0[1] + acc1[1];
+      res2 = acc0[2] + acc1[2];
+      res3 = acc0[3] + acc1[3];
+    }
+    if (write) buf ^= 1;
+    cv = plv;
+    ct0 = pnt0;
+    cnt = it < item1 ? pnt1 - pnt0 : 0;
+  };
+  for (int it = item0; it <= item1 + 1; it += 2) {
+    step(it, eb0, eb1, eb2, eb3, ea0, ea1, ea2, ea3, tbb, tba, sb0, sb1, sb2, sb3, sa0, sa1, sa2, sa3);
+    if (it + 1 <= item1 + 1)
+      step(it + 1, ea0, ea1, ea2, ea3, eb0, eb1, eb2, eb3, tba, tbb, sa0, sa1, sa2, sa3, sb0, sb1, sb2, sb3);
+  }
+  }
+  }
+}
+
 // ---- kernels: the bodies above as plain and as grouped launches ------------
 // (scalar parameters: with the arguments as one by-value struct the compiler
 // kept 120 instead of 66 VGPRs at p = 6, FP32)
@@ -902,6 +1218,16 @@ __global__ __launch_bounds__(kHadThreads) void hadamard_gather_group_kernel(
   int64_t b;
   const HadGatherArgs a = jobs[group_job(pre, nj, b)];
   hadamard_gather_body<T>(a, b);
+}
+__global__ __launch_bounds__(kHadThreads, 2) void hadamard_split_kernel(HadBlockArgs a) {
+  hadamard_split_body(a, blockIdx.x, gridDim.x);
+}
+__global__ __launch_bounds__(kHadThreads, 2) void hadamard_split_group_kernel(
+    const HadBlockArgs* __restrict__ jobs, const int64_t* __restrict__ pre, int nj) {
+  int64_t b;
+  const int j = group_job(pre, nj, b);
+  const HadBlockArgs a = jobs[j];
+  hadamard_split_body(a, b, pre[j + 1] - pre[j]);
 }
 __global__ __launch_bounds__(kHadThreads, 3) void hadamard_block_kernel(HadBlockArgs a) {
   hadamard_block_body(a, blockIdx.x, gridDim.x);
@@ -1005,11 +1331,18 @@ hipError_t inv_dispatch(int inst, const InvArgs* one, const InvArgs* jobs, const
   return hipGetLastError();
 }
 
-hipError_t had_dispatch(bool fp64, const void* one, const void* jobs, const int64_t* pre, int nj,
+// inst: 0 = FP32 block form, 1 = FP64 gather form, 2 = split (BF16 parts) block form
+hipError_t had_dispatch(int inst, const void* one, const void* jobs, const int64_t* pre, int nj,
                         int64_t blocks, hipStream_t s) {
   if (blocks == 0) return hipSuccess;
   if (blocks < 0 || blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-  if (fp64) {
+  if (inst == 2) {
+    if (!jobs)
+      hadamard_split_kernel<<<(unsigned)blocks, kHadThreads, 0, s>>>(*static_cast<const HadBlockArgs*>(one));
+    else
+      hadamard_split_group_kernel<<<(unsigned)blocks, kHadThreads, 0, s>>>(
+          static_cast<const HadBlockArgs*>(jobs), pre, nj);
+  } else if (inst == 1) {
     if (!jobs)
       hadamard_gather_kernel<double><<<(unsigned)blocks, kHadThreads, 0, s>>>(
           *static_cast<const HadGatherArgs*>(one));
@@ -1112,7 +1445,7 @@ hipError_t launch_fft_inverse_group(int inst, const InvArgs* jobs, const int64_t
   return inv_dispatch(inst, nullptr, jobs, pre, nj, blocks, stream);
 }
 
-hipError_t plan_hadamard(bool fp64, int F, const void* Khat, const void* Qhat, const int32_t* halo,
+hipError_t plan_hadamard(bool fp64, bool bf16, int F, const void* Khat, const void* Qhat, const int32_t* halo,
                          int64_t n_blocks, const int32_t* blk_tgt, const int32_t* blk_src,
                          const int32_t* blk_list, const int32_t* tbase, int64_t n_clusters, int nvec,
                          int split, void* Phat, HadBlockArgs& ab, HadGatherArgs& ag, int64_t& blocks) {
@@ -1136,7 +1469,9 @@ hipError_t plan_hadamard(bool fp64, int F, const void* Khat, const void* Qhat, c
   // run of the frequency-major items (the B operand is loaded once per
   // frequency in a run); unit form (1): one workgroup per 8 items; frequency
   // form (2): one workgroup per frequency, over all its items
-  static const int64_t resident = resident_wgs(hadamard_block_kernel, kHadThreads);
+  static const int64_t res_block = resident_wgs(hadamard_block_kernel, kHadThreads);
+  static const int64_t res_split = resident_wgs(hadamard_split_kernel, kHadThreads);
+  const int64_t resident = bf16 ? res_split : res_block;
   const int64_t n_items = n_blocks * nvec;
   if (resident < 8 || n_items >= (int64_t(1) << 31)) return hipErrorInvalidValue;
   const int64_t total = (int64_t)F * n_items;
@@ -1156,7 +1491,7 @@ hipError_t plan_hadamard(bool fp64, int F, const void* Khat, const void* Qhat, c
   return hipSuccess;
 }
 
-hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
+hipError_t launch_hadamard(bool fp64, bool bf16, int F, const void* Khat, const void* Qhat,
                            const int32_t* halo, int64_t n_blocks, const int32_t* blk_tgt,
                            const int32_t* blk_src, const int32_t* blk_list, const int32_t* tbase,
                            int64_t n_clusters, int nvec, bool units, void* Phat,
@@ -1164,16 +1499,26 @@ hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
   HadBlockArgs ab;
   HadGatherArgs ag;
   int64_t blocks;
-  hipError_t e = plan_hadamard(fp64, F, Khat, Qhat, halo, n_blocks, blk_tgt, blk_src, blk_list, tbase,
+  hipError_t e = plan_hadamard(fp64, bf16, F, Khat, Qhat, halo, n_blocks, blk_tgt, blk_src, blk_list, tbase,
                                n_clusters, nvec, units ? 1 : 0, Phat, ab, ag, blocks);
   if (e != hipSuccess) return e;
-  return had_dispatch(fp64, fp64 ? (const void*)&ag : (const void*)&ab, nullptr, nullptr, 0, blocks,
-                      stream);
+  return had_dispatch(hadamard_inst(fp64, bf16), fp64 ? (const void*)&ag : (const void*)&ab, nullptr,
+                      nullptr, 0, blocks, stream);
 }
 
-hipError_t launch_hadamard_group(bool fp64, const void* jobs, const int64_t* pre, int nj, int64_t blocks,
+hipError_t launch_hadamard_group(int inst, const void* jobs, const int64_t* pre, int nj, int64_t blocks,
                                  hipStream_t stream) {
-  return had_dispatch(fp64, nullptr, jobs, pre, nj, blocks, stream);
+  return had_dispatch(inst, nullptr, jobs, pre, nj, blocks, stream);
+}
+
+int64_t hadamard_split_bytes(int F) { return (int64_t)F * 3 * 13 * 64 * 16; }
+
+hipError_t launch_hadamard_split_prep(const void* Khat, int F, void* parts, hipStream_t stream) {
+  const int64_t n = (int64_t)F * 13 * 64;
+  if (n == 0) return hipSuccess;
+  hadamard_split_prep_kernel<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(
+      static_cast<const float2*>(Khat), F, static_cast<v8bf*>(parts));
+  return hipGetLastError();
 }
 
 }  // namespace kifmm

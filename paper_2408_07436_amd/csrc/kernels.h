@@ -239,7 +239,7 @@ hipError_t launch_fft_forward(int p, bool fp64, const double* M, const int32_t* 
 // 6 D_y + 36 D_z) * kHadRowBytes.  FP32 work split: units = false gives persistent
 // workgroups over contiguous runs of the frequency-major (frequency, block,
 // vector) items, true one workgroup per unit of 8 items.
-hipError_t launch_hadamard(bool fp64, int F, const void* Khat, const void* Qhat,
+hipError_t launch_hadamard(bool fp64, bool bf16, int F, const void* Khat, const void* Qhat,
                            const int32_t* halo, int64_t n_blocks, const int32_t* blk_tgt,
                            const int32_t* blk_src, const int32_t* blk_list, const int32_t* tbase,
                            int64_t n_clusters, int nvec, bool units, void* Phat,
@@ -283,13 +283,21 @@ hipError_t launch_fft_inverse_group(int inst, const InvArgs* jobs, const int64_t
                                     int64_t blocks, hipStream_t stream);
 // fills ab (FP32) or ag (FP64); FP32 work split: 0 persistent runs, 1
 // 8-item units, 2 one workgroup per frequency (all its items)
-hipError_t plan_hadamard(bool fp64, int F, const void* Khat, const void* Qhat, const int32_t* halo,
+hipError_t plan_hadamard(bool fp64, bool bf16, int F, const void* Khat, const void* Qhat, const int32_t* halo,
                          int64_t n_blocks, const int32_t* blk_tgt, const int32_t* blk_src,
                          const int32_t* blk_list, const int32_t* tbase, int64_t n_clusters, int nvec,
                          int split, void* Phat, HadBlockArgs& ab, HadGatherArgs& ag, int64_t& blocks);
-// jobs: HadGatherArgs (fp64) or HadBlockArgs
-hipError_t launch_hadamard_group(bool fp64, const void* jobs, const int64_t* pre, int nj, int64_t blocks,
+// Kernel instance of a Hadamard launch: 0 = FP32 block form, 1 = FP64
+// gather form, 2 = split form (FP32 block form whose products run as BF16
+// parts on BF16 MFMA; Khat is then the parts table written by
+// launch_hadamard_split_prep).  jobs: HadGatherArgs (1) or HadBlockArgs.
+inline int hadamard_inst(bool fp64, bool bf16) { return fp64 ? 1 : bf16 ? 2 : 0; }
+hipError_t launch_hadamard_group(int inst, const void* jobs, const int64_t* pre, int nj, int64_t blocks,
                                  hipStream_t stream);
+// Split form's B-operand parts of an FP32 kernel-spectrum table Khat
+// (F x 26 x 8 x 8 complex): hadamard_split_bytes(F) bytes of BF16 parts.
+int64_t hadamard_split_bytes(int F);
+hipError_t launch_hadamard_split_prep(const void* Khat, int F, void* parts, hipStream_t stream);
 
 // ---- BLAS-M2L (Section 3.2) -----------------------------------------------
 // Fused per-level compressed M2L: out[box][v][0:k] = scale * sum over the

@@ -139,19 +139,20 @@ def test_tuning_knobs_host():
     """Knob defaults, round trip and range checks; autotune argument errors
     raised before any device use."""
     f = K.KiFMM(4, 3, m2l="blas", prec="fp32")
-    assert f.tuning() == {"blas_tile": 0, "schedule": 0, "hadamard": 0, "blas_form": 0}
-    f.set_tuning(blas_tile=16, schedule=1, hadamard=1, blas_form=1)
-    set_knobs = {"blas_tile": 16, "schedule": 1, "hadamard": 1, "blas_form": 1}
+    assert f.tuning() == {"blas_tile": 0, "schedule": 0, "hadamard": 0, "blas_form": 0, "products": 0}
+    f.set_tuning(blas_tile=16, schedule=1, hadamard=1, blas_form=1, products=1)
+    set_knobs = {"blas_tile": 16, "schedule": 1, "hadamard": 1, "blas_form": 1, "products": 1}
     assert f.tuning() == set_knobs
     lib = K.lib()
-    for bad in ([129, 0, 0, 0], [-1, 0, 0, 0], [0, 2, 0, 0], [0, 0, 2, 0], [0, 0, 0, 2]):
+    for bad in ([129, 0, 0, 0, 0], [-1, 0, 0, 0, 0], [0, 2, 0, 0, 0], [0, 0, 2, 0, 0], [0, 0, 0, 2, 0],
+                [0, 0, 0, 0, 2]):
         k = np.array(bad, dtype=np.int32)
-        rc = lib.kifmm_set_tuning(f._h, k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 4)
+        rc = lib.kifmm_set_tuning(f._h, k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 5)
         assert rc == 1
         assert f.tuning() == set_knobs
-    k = np.zeros(5, dtype=np.int32)
-    assert lib.kifmm_set_tuning(f._h, k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 5) == 1
-    assert lib.kifmm_get_tuning(f._h, k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 3) == 1
+    k = np.zeros(6, dtype=np.int32)
+    assert lib.kifmm_set_tuning(f._h, k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 6) == 1
+    assert lib.kifmm_get_tuning(f._h, k.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 4) == 1
     # partial update: only the first knob
     k1 = np.array([32], dtype=np.int32)
     assert lib.kifmm_set_tuning(f._h, k1.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 1) == 0

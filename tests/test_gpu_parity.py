@@ -190,9 +190,10 @@ def test_schedules_agree_bitwise(prec):
 @pytest.mark.parametrize("m2l,prec", [("fft", "fp32"), ("fft", "fp64"), ("blas", "fp32")])
 def test_tuning_settings_agree_and_autotune(m2l, prec):
     """Every knob setting the autotuner tries gives potentials bit-identical to
-    the defaults (schedule, Hadamard work split, BLAS tile width); the
-    autotuner keeps one of them, reports a positive time, and its result
-    still matches the oracle."""
+    the defaults (schedule, Hadamard work split, BLAS tile width); the two
+    BLAS forms and the two Hadamard product forms (BF16 parts, FP32 MFMA)
+    agree to rounding; the autotuner keeps one setting, reports a positive
+    time, and its result still matches the oracle."""
     pts = workloads.uniform_cube(30000, 91)
     q = workloads.charges(30000, 3, 92, "upm1")
     depth, order = (4, 5) if m2l == "fft" else (3, 5)
@@ -204,7 +205,9 @@ def test_tuning_settings_agree_and_autotune(m2l, prec):
     a = f.evaluate(qt).clone()
     forms = {0: a}
     if m2l == "fft":
-        settings = [dict(schedule=s, hadamard=h) for s in (0, 1) for h in (0, 1)]
+        # Hadamard products as BF16 parts (0) or on FP32 MFMA (1): bit-identical
+        # across the schedule and work split, the two equal to FP32 rounding
+        settings = [dict(schedule=s, hadamard=h, products=pr) for pr in (0, 1) for s in (0, 1) for h in (0, 1)]
     else:
         # both BLAS forms (stacked, fused), each at several tile widths: bit-identical
         # within a form, the forms equal to rounding (same products, other order)
@@ -213,13 +216,13 @@ def test_tuning_settings_agree_and_autotune(m2l, prec):
         f.set_tuning(**st)
         b = f.evaluate(qt)
         torch.cuda.synchronize()
-        fm = st.get("blas_form", 0)
+        fm = st.get("blas_form", 0) + st.get("products", 0)
         if fm not in forms:
             forms[fm] = b.clone()
             check_parity(b.double().cpu().numpy(), a.double().cpu().numpy(), E2E_GATES[prec],
                          what=f"form {fm} vs form 0")
         assert torch.equal(forms[fm], b), st
-    f.set_tuning(blas_tile=0, schedule=0, hadamard=0, blas_form=0)
+    f.set_tuning(blas_tile=0, schedule=0, hadamard=0, blas_form=0, products=0)
     best = f.autotune(qt, reps=2)
     tuned = f.tuning()
     say(f"  autotune kept {tuned}, {best:.3f} ms")
@@ -232,7 +235,7 @@ def test_tuning_settings_agree_and_autotune(m2l, prec):
         assert tuned["blas_tile"] in (42, 21, 10, 5) and tuned["blas_form"] in (0, 1)
     c = f.evaluate(qt)
     torch.cuda.synchronize()
-    assert torch.equal(forms[tuned.get("blas_form", 0)], c)
+    assert torch.equal(forms[tuned.get("blas_form", 0) + tuned.get("products", 0)], c)
     if m2l == "fft":
         ref = fmm.KiFMM(pts, pts, depth, order).evaluate(q)
     else:
