@@ -988,7 +988,6 @@ __device__ __forceinline__ void hadamard_split_body(const HadBlockArgs& a, int64
   const int64_t n_units = a.n_units, n_wgs = a.n_wgs;
   float* __restrict__ Phat = static_cast<float*>(a.Phat);
   __shared__ __attribute__((aligned(16))) char As[kSplitLds];  // both staging buffers
-  __shared__ __attribute__((aligned(16))) char Bs[13 * 64 * 16];  // B2 parts, [j][lane]
   const int64_t per_xcd = nblk / 8;  // grid: a multiple of 8
   const int64_t logical = (b % 8) * per_xcd + b / 8;  // consecutive work per XCD
   if (logical >= n_wgs) return;
@@ -1002,10 +1001,7 @@ __device__ __forceinline__ void hadamard_split_body(const HadBlockArgs& a, int64
   // three 8-byte parts, kSplitPart apart, in half (tid % 4) / 2
   static_assert(kHadStage == 4, "staging pieces per thread");
   const uint32_t part_bytes = (uint32_t)(kSplitHalf * ((tid & 3) >> 1) + 8 * (tid & 1));
-  // two sets of staging registers, alternating by step: one item's rows are
-  // loaded into one set at the top of a step while the other set (the
-  // previous item's rows) is split into LDS
-  float4 sa0, sa1, sa2, sa3, sb0, sb1, sb2, sb3;
+  float4 stg0, stg1, stg2, stg3;
   uint32_t ea0 = 0, ea1 = 0, ea2 = 0, ea3 = 0;
   uint32_t eb0 = 0, eb1 = 0, eb2 = 0, eb3 = 0;
   uint32_t tba = 0, tbb = 0;
@@ -1035,21 +1031,17 @@ __device__ __forceinline__ void hadamard_split_body(const HadBlockArgs& a, int64
   const int item0 = (int)(seg - f * n_items);
   const int item1 = (int)(min(q1, (f + 1) * n_items) - f * n_items);
   seg = f * n_items + item1;
-  // B parts of this frequency (laid out by hadamard_split_prep_kernel):
-  // parts 0 and 1 in registers, part 2 (one product per K step) in LDS,
-  // copied after every wave is done with the previous frequency
-  v8bf B0[13], B1[13];
+  // B parts of this frequency (laid out by hadamard_split_prep_kernel), in
+  // registers: the LDS carries only the A parts, whose reads bound the rate
+  v8bf B0[13], B1[13], B2[13];
   {
     const v8bf* kb = Ksp + f * 3 * 13 * 64;
 #pragma unroll
     for (int j = 0; j < 13; ++j) {
       B0[j] = kb[j * 64 + lane];
       B1[j] = kb[(13 + j) * 64 + lane];
+      B2[j] = kb[(26 + j) * 64 + lane];
     }
-    __syncthreads();
-    for (int e = tid; e < 13 * 64; e += kHadThreads)
-      *reinterpret_cast<v8bf*>(Bs + e * 16) = kb[2 * 13 * 64 + e];
-    __syncthreads();
   }
   const char* qf = reinterpret_cast<const char*>(Qhat + f * (n_rows + nvec) * 16);
   char* pf = reinterpret_cast<char*>(Phat + f * n_rows * 16);
@@ -1072,26 +1064,15 @@ __device__ __forceinline__ void hadamard_split_body(const HadBlockArgs& a, int64
     es1 = blk_src[bb + 1];
   }
   auto step = [&](int it, uint32_t& w0, uint32_t& w1, uint32_t& w2, uint32_t& w3, uint32_t u0,
-                  uint32_t u1, uint32_t u2, uint32_t u3, uint32_t tbc, uint32_t& tbn, const float4& c0,
-                  const float4& c1, const float4& c2, const float4& c3, float4& n0, float4& n1, float4& n2,
-                  float4& n3) __attribute__((always_inline)) {
+                  uint32_t u1, uint32_t u2, uint32_t u3, uint32_t tbc, uint32_t& tbn)
+                  __attribute__((always_inline)) {
     __builtin_amdgcn_s_waitcnt(0);  // the previous step's loads and stores
-    if (it < item1) {
-      // rows of item it (entries loaded in the previous step), first of the
-      // step so that they have its whole length to arrive
-      const uint32_t vb = (uint32_t)lv * 64u + 16u * (uint32_t)(tid & 3);
-      n0 = *reinterpret_cast<const float4*>(qf + ((u0 >> 8) * row_bytes + vb));
-      n1 = *reinterpret_cast<const float4*>(qf + ((u1 >> 8) * row_bytes + vb));
-      n2 = *reinterpret_cast<const float4*>(qf + ((u2 >> 8) * row_bytes + vb));
-      n3 = *reinterpret_cast<const float4*>(qf + ((u3 >> 8) * row_bytes + vb));
-      tbn = (uint32_t)tbase[nt0 + min(tr0 + rl, nt1 - nt0 - 1)];
-    }
     const bool write = it > item0 && it <= item1;  // rows of item it - 1 staged
     if (write) {
-      put(As, lds_slot(w0, buf), c0);
-      put(As, lds_slot(w1, buf), c1);
-      put(As, lds_slot(w2, buf), c2);
-      put(As, lds_slot(w3, buf), c3);
+      put(As, lds_slot(w0, buf), stg0);
+      put(As, lds_slot(w1, buf), stg1);
+      put(As, lds_slot(w2, buf), stg2);
+      put(As, lds_slot(w3, buf), stg3);
     }
     if (it >= item0 + 2 && tr0 < snt) {
       const uint32_t o0 = ((uint32_t)(st0 + tr0 + 4 * g) * nvec + sv) * 64u + 4u * rl;
@@ -1105,6 +1086,14 @@ __device__ __forceinline__ void hadamard_split_body(const HadBlockArgs& a, int64
     sv = cv;
     st0 = ct0;
     snt = cnt;
+    if (it < item1) {
+      const uint32_t vb = (uint32_t)lv * 64u + 16u * (uint32_t)(tid & 3);
+      stg0 = *reinterpret_cast<const float4*>(qf + ((u0 >> 8) * row_bytes + vb));
+      stg1 = *reinterpret_cast<const float4*>(qf + ((u1 >> 8) * row_bytes + vb));
+      stg2 = *reinterpret_cast<const float4*>(qf + ((u2 >> 8) * row_bytes + vb));
+      stg3 = *reinterpret_cast<const float4*>(qf + ((u3 >> 8) * row_bytes + vb));
+      tbn = (uint32_t)tbase[nt0 + min(tr0 + rl, nt1 - nt0 - 1)];
+    }
     if (it + 1 < item1) {  // entries of item it + 1 (those of item it - 1 are staged)
       w0 = entry(es0, es1 - es0, 0);
       w1 = entry(es0, es1 - es0, 1);
@@ -1136,26 +1125,24 @@ __device__ __forceinline__ void hadamard_split_body(const HadBlockArgs& a, int64
       const bool hi = g >= 2;
       const int hs72 = hi ? 2 * kSplitZ * kSplitRowBytes : 0, hs12 = hi ? 2 * kSplitY * kSplitRowBytes : 0,
                 hs2 = hi ? 2 * kSplitRowBytes : 0;
-      const char* bb = Bs + lane * 16;
-      auto ldA = [&](int j, v8bf& x0, v8bf& x1, v8bf& x2, v8bf& y2) __attribute__((always_inline)) {
+      auto ldA = [&](int j, v8bf& x0, v8bf& x1, v8bf& x2) __attribute__((always_inline)) {
         const char* pa = ab + (j < 9 ? hs72 : j < 12 ? hs12 : hs2) + split_dir_bytes(split_pair_dir(j, 0));
         x0 = *reinterpret_cast<const v8bf*>(pa);
         x1 = *reinterpret_cast<const v8bf*>(pa + kSplitPart);
         x2 = *reinterpret_cast<const v8bf*>(pa + 2 * kSplitPart);
-        y2 = *reinterpret_cast<const v8bf*>(bb + j * 64 * 16);
       };
       v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
-      v8bf n0, n1, n2, m2;
-      ldA(0, n0, n1, n2, m2);
+      v8bf n0, n1, n2;
+      ldA(0, n0, n1, n2);
 #pragma unroll
       for (int j = 0; j < 13; ++j) {
-        const v8bf a0 = n0, a1 = n1, a2 = n2, b2 = m2;
-        if (j + 1 < 13) ldA(j + 1, n0, n1, n2, m2);
+        const v8bf a0 = n0, a1 = n1, a2 = n2;
+        if (j + 1 < 13) ldA(j + 1, n0, n1, n2);
         __builtin_amdgcn_sched_barrier(0);
         acc0 = mfbf16(a0, B0[j], acc0);
         acc1 = mfbf16(a0, B1[j], acc1);
         acc0 = mfbf16(a1, B0[j], acc0);
-        acc1 = mfbf16(a0, b2, acc1);
+        acc1 = mfbf16(a0, B2[j], acc1);
         acc0 = mfbf16(a1, B1[j], acc0);
         acc1 = mfbf16(a2, B0[j], acc1);
       }
@@ -1170,9 +1157,8 @@ __device__ __forceinline__ void hadamard_split_body(const HadBlockArgs& a, int64
     cnt = it < item1 ? pnt1 - pnt0 : 0;
   };
   for (int it = item0; it <= item1 + 1; it += 2) {
-    step(it, eb0, eb1, eb2, eb3, ea0, ea1, ea2, ea3, tbb, tba, sb0, sb1, sb2, sb3, sa0, sa1, sa2, sa3);
-    if (it + 1 <= item1 + 1)
-      step(it + 1, ea0, ea1, ea2, ea3, eb0, eb1, eb2, eb3, tba, tbb, sa0, sa1, sa2, sa3, sb0, sb1, sb2, sb3);
+    step(it, eb0, eb1, eb2, eb3, ea0, ea1, ea2, ea3, tbb, tba);
+    if (it + 1 <= item1 + 1) step(it + 1, ea0, ea1, ea2, ea3, eb0, eb1, eb2, eb3, tba, tbb);
   }
   }
   }
