@@ -128,13 +128,16 @@ __device__ __forceinline__ void fft_forward_body(const FwdArgs& a, int64_t blk, 
   constexpr int IT = FftCfg<T, P>::items, TH = FftCfg<T, P>::threads;
   __shared__ C2 a1[IT * L::s1i];
   __shared__ C2 a2[IT * L::s2i];
-  __shared__ int16_t l2s[P * P * P];
-  __shared__ T sv[IT * NS];  // densities of the group being transformed
+  // densities of the group being transformed on the p^3 lattice (zero off
+  // the surface: the interior is never written), and each surface point's
+  // lattice index
+  __shared__ T dl[IT * P * P * P];
+  __shared__ int16_t s2l[NS];
   static_assert(IT <= 8 && 8 % IT == 0, "an item group lies within one row");
   const int tid = threadIdx.x;
   // Persistent workgroups: while group gc is transformed, the densities of
   // group gc + nwg are loaded into registers (issued before the z stage,
-  // written to sv after the y stage).  The group's eight child box indices
+  // written to dl after the y stage).  The group's eight child box indices
   // are read with scalar loads, so no vector-memory wait (which would also
   // wait for the previous group's spectrum stores) sits between them and
   // the density loads.  Logical workgroups are numbered per XCD, so at each
@@ -144,7 +147,12 @@ __device__ __forceinline__ void fft_forward_body(const FwdArgs& a, int64_t blk, 
   const int64_t n_groups = (n_rows * 8 + IT - 1) / IT;
   const int64_t nwg = nblk, per_xcd = nwg / 8;  // grid: a multiple of 8
   const int64_t wg = (blk % 8) * per_xcd + blk / 8;
-  for (int t = tid; t < P * P * P; t += TH) l2s[t] = lat2surf[t];
+  for (int t = tid; t < P * P * P; t += TH) {
+    const int sidx = lat2surf[t];
+    if (sidx >= 0) s2l[sidx] = (int16_t)t;
+  }
+  for (int t = tid; t < IT * P * P * P; t += TH) dl[t] = T(0);
+  __syncthreads();
   // MFMA operand A of the y and x stages: the real form of Wm, rows
   // (k, re/im), columns (j, re/im); lane (lc, lg) holds row lc, column lg of
   // each 16 x 4 block, rows ordered so that lane (lc, g) of a product holds
@@ -165,12 +173,36 @@ __device__ __forceinline__ void fft_forward_body(const FwdArgs& a, int64_t blk, 
       }
       Ar[mt][ks] = val;
     }
+  // MFMA operand A of the z stage: the real form of Wm[kz][z] on real
+  // input, rows (kz, re/im), columns z
+  constexpr int KZ = (P + 3) / 4;
+  static_assert(2 * H <= 16, "one 16-row tile holds a z line's outputs");
+  T Az[KZ];
+#pragma unroll
+  for (int ks = 0; ks < KZ; ++ks) {
+    const int m = a_row(T(0), lc), z = 4 * ks + lg;
+    T val = T(0);
+    if (m < 2 * H && z < P) {
+      const C2 w = Wm[(m >> 1) * P + z];
+      val = (m & 1) ? w.y : w.x;
+    }
+    Az[ks] = val;
+  }
   const T* a1f = reinterpret_cast<const T*>(a1);
   const T* a2f = reinterpret_cast<const T*>(a2);
   // densities of group gl into pre (box indices of absent children read
-  // box 0; their values are masked when written to sv)
+  // box 0; their values are masked when written to dl), and the lattice
+  // offset in dl of each of the thread's surface values
   double pre[KL];
   uint32_t okm = 0;
+  int dlo[KL];
+#pragma unroll
+  for (int k = 0; k < KL; ++k) {
+    const int idx = tid + TH * k;
+    const int it = idx < IT * NS ? idx / NS : 0, sidx = idx - it * NS;
+    // (clamped: every surface point has its lattice point, so the clamp never acts)
+    dlo[k] = idx < IT * NS ? it * P * P * P + min(max((int)s2l[sidx], 0), P * P * P - 1) : 0;
+  }
   auto load_group = [&](int64_t gl) __attribute__((always_inline)) {
     const int64_t g0 = gl * IT;
     const uint32_t row = (uint32_t)(g0 / 8), c = row / (uint32_t)nvec;
@@ -196,7 +228,7 @@ __device__ __forceinline__ void fft_forward_body(const FwdArgs& a, int64_t blk, 
 #pragma unroll
     for (int k = 0; k < KL; ++k) {
       const int idx = tid + TH * k;
-      if (idx < IT * NS) sv[idx] = (okm >> k) & 1 ? (T)pre[k] : T(0);
+      if (idx < IT * NS) dl[dlo[k]] = (okm >> k) & 1 ? (T)pre[k] : T(0);
     }
   };
   if (wg >= n_groups) return;
@@ -205,30 +237,30 @@ __device__ __forceinline__ void fft_forward_body(const FwdArgs& a, int64_t blk, 
   __syncthreads();
   for (int64_t gc = wg; gc < n_groups; gc += nwg) {
     // past the last group the current one is loaded again (unused), so the
-    // loads and their stores to sv stay unconditional
+    // loads and their stores to dl stay unconditional
     const int64_t gn = gc + nwg, g0 = gc * IT;
     load_group(gn < n_groups ? gn : gc);
-    for (int idx = tid; idx < IT * P * P; idx += TH) {
-      const int it = idx / (P * P), x = (idx / P) % P, y = idx % P;
-      T dz[P];
+    // z stage on MFMA: a1[(kz, re/im)][line] = Az x dl[line][z], line =
+    // (item, x, y); columns past the last line read the last one (zero
+    // columns of Az past z = p - 1 take any finite value)
+    {
+      constexpr int NC = IT * P * P, NT = (NC + 15) / 16;
+      for (int t = wave; t < NT; t += NW) {
+        const int col = 16 * t + lc;
+        const int cc = col < NC ? col : NC - 1;
+        const T* src = dl + cc * P;
+        V4 acc = V4{T(0), T(0), T(0), T(0)};
 #pragma unroll
-      for (int z = 0; z < P; ++z) {
-        const int sidx = l2s[(x * P + y) * P + z];
-        const T dv = sv[it * NS + (sidx < 0 ? 0 : sidx)];
-        dz[z] = sidx < 0 ? T(0) : dv;
-      }
+        for (int ks = 0; ks < KZ; ++ks) acc = mfma16(Az[ks], src[min(4 * ks + lg, P - 1)], acc);
+        if (col < NC) {
+          const int it = cc / (P * P), x = (cc / P) % P, y = cc % P;
+          C2* o = a1 + it * L::s1i + x * L::s1x + y * L::s1y;
 #pragma unroll
-      for (int kz = 0; kz < H; ++kz) {
-        C2 acc;  // Wm[kz][0] = 1
-        acc.x = dz[0];
-        acc.y = T(0);
-#pragma unroll
-        for (int z = 1; z < P; ++z) {
-          const C2 wv = Wm[kz * P + z];
-          acc.x = fma(dz[z], wv.x, acc.x);
-          acc.y = fma(dz[z], wv.y, acc.y);
+          for (int h = 0; h < 2; ++h) {
+            const int kz = 2 * lg + h;
+            if (kz < H) o[kz] = C2{acc[2 * h], acc[2 * h + 1]};
+          }
         }
-        a1[it * L::s1i + x * L::s1x + y * L::s1y + kz] = acc;
       }
     }
     __syncthreads();
@@ -263,7 +295,7 @@ __device__ __forceinline__ void fft_forward_body(const FwdArgs& a, int64_t blk, 
           }
       }
     }
-    store_group();  // the z stage is done with sv
+    store_group();  // the z stage is done with dl
     __syncthreads();
     // x stage on MFMA: Qhat(f, row, child) = Ar x a2[(x, re/im)][col],
     // col = (ky, kz, item), item fastest, f = (kx n + ky) p + kz
