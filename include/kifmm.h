@@ -85,7 +85,9 @@ typedef enum { KIFMM_M2L_DENSE = 0, KIFMM_M2L_FFT = 1, KIFMM_M2L_BLAS = 2 } kifm
  * every mode; P2P runs in the precision of the charges.
  *   KIFMM_FP64   - charges/potentials double; M2L in FP64.
  *   KIFMM_FP32   - charges/potentials float; M2L in FP32 (FFT: FP32 complex
- *                  transforms and Hadamard products; BLAS/DENSE: FP32 GEMMs).
+ *                  transforms and Hadamard products - by default as three
+ *                  BF16 parts per FP32 value on BF16 MFMA, FP32-class
+ *                  rounding, see KIFMM_TUNE_PRODUCTS; BLAS/DENSE: FP32 GEMMs).
  *   KIFMM_BF16X3 - charges/potentials float; BLAS/DENSE M2L GEMMs on bf16
  *                  MFMA with hi+lo split operands (a = hi + lo, products
  *                  hi*hi + hi*lo + lo*hi, FP32 accumulation); FFT M2L as FP32. */

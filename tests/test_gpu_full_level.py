@@ -6,7 +6,9 @@ Section 2.2, which the convolution form of Appendix A.1 reaches exactly, and
 the compressed operator of Section 3.1 for BLAS-M2L), compared element by
 element in check-potential space.  These launches run the kernels' full-size
 work splits (the FP32 Hadamard's persistent schedule over 4,096 clusters,
-the BLAS tiles of every octant class) that smaller trees do not reach."""
+the BLAS tiles of every octant class) that smaller trees do not reach.  The
+FP32 FFT-M2L runs in both Hadamard product forms (BF16 parts, the default,
+and FP32 MFMA)."""
 import numpy as np
 import pytest
 
@@ -57,10 +59,11 @@ class Level:
             self._ref[key] = ora.m2l_level(self.depth, m.transpose(0, 2, 1)).transpose(0, 2, 1)
         return self._ref[key]
 
-    def run(self, m2l, prec, nvec):
+    def run(self, m2l, prec, nvec, products=0):
         kw = dict(svd_rel_tol=BLAS_TOL, svd_rel_tol_dir=BLAS_TOL) if m2l == "blas" else {}
         f = K.KiFMM(self.order, self.depth, m2l=m2l, prec=prec, origin=self.origin,
                     width=self.width, **kw).set_points(self.points).precompute()
+        f.set_tuning(products=products)
         out = f.stage_m2l(self.depth, torch.as_tensor(self.mult(nvec), device="cuda"))
         torch.cuda.synchronize()
         got = out.cpu().numpy()
@@ -82,27 +85,28 @@ def sphere_4m():
     return Level(w.points, w.depth, w.order, w.origin, w.width, 4200)
 
 
-CASES = [("fft", "fp64", 1), ("fft", "fp32", 1), ("blas", "fp32", NVEC_BLAS),
-         ("blas", "bf16x3", NVEC_BLAS), ("blas", "fp64", NVEC_BLAS)]
+# (M2L form, precision, vectors, FP32 Hadamard products: 0 BF16 parts, 1 FP32 MFMA)
+CASES = [("fft", "fp64", 1, 0), ("fft", "fp32", 1, 0), ("fft", "fp32", 1, 1), ("blas", "fp32", NVEC_BLAS, 0),
+         ("blas", "bf16x3", NVEC_BLAS, 0), ("blas", "fp64", NVEC_BLAS, 0)]
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("m2l,prec,nvec", CASES)
-def test_uniform_1M_leaf_level_all_boxes(uniform_1m, m2l, prec, nvec):
+@pytest.mark.parametrize("m2l,prec,nvec,products", CASES)
+def test_uniform_1M_leaf_level_all_boxes(uniform_1m, m2l, prec, nvec, products):
     L = uniform_1m
-    say(f"case: uniform 1M level {L.depth} all boxes, {m2l} {prec} nvec {nvec}")
-    got = L.run(m2l, prec, nvec)
+    say(f"case: uniform 1M level {L.depth} all boxes, {m2l} {prec} nvec {nvec} products {products}")
+    got = L.run(m2l, prec, nvec, products)
     ref = L.ref("blas" if m2l == "blas" else "dense", nvec)
     assert got.shape == ref.shape
     check_parity(got, ref, STAGE_GATES[prec], vec_axis=1, what="check potentials vs oracle")
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("m2l,prec,nvec", CASES)
-def test_sphere_4M_leaf_level_all_boxes(sphere_4m, m2l, prec, nvec):
+@pytest.mark.parametrize("m2l,prec,nvec,products", CASES)
+def test_sphere_4M_leaf_level_all_boxes(sphere_4m, m2l, prec, nvec, products):
     L = sphere_4m
-    say(f"case: sphere 4M level {L.depth} all boxes, {m2l} {prec} nvec {nvec}")
-    got = L.run(m2l, prec, nvec)
+    say(f"case: sphere 4M level {L.depth} all boxes, {m2l} {prec} nvec {nvec} products {products}")
+    got = L.run(m2l, prec, nvec, products)
     ref = L.ref("blas" if m2l == "blas" else "dense", nvec)
     assert got.shape == ref.shape
     check_parity(got, ref, STAGE_GATES[prec], vec_axis=1, what="check potentials vs oracle")
