@@ -1214,12 +1214,18 @@ __global__ __launch_bounds__((FftCfg<T, P>::threads)) void fft_forward_group_ker
   const FwdArgs a = jobs[j];
   fft_forward_body<T, P>(a, b, pre[j + 1] - pre[j]);
 }
+// eight waves per SIMD (four workgroups per CU) where the LDS allows them
+template <typename T, int P> struct InvWaves {
+  using L = InvLds<P, (int)sizeof(T) / 2>;
+  static constexpr int lds = L::items * (L::s2i + L::s1i) * 2 * (int)sizeof(T);
+  static constexpr int value = lds * 4 <= 160 * 1024 - 4 * 1024 ? 8 : 6;
+};
 template <typename T, int P>
-__global__ __launch_bounds__(kInvThreads) __attribute__((amdgpu_waves_per_eu(8))) void fft_inverse_kernel(InvArgs a) {
+__global__ __launch_bounds__(kInvThreads) __attribute__((amdgpu_waves_per_eu(InvWaves<T, P>::value))) void fft_inverse_kernel(InvArgs a) {
   fft_inverse_body<T, P>(a, blockIdx.x);
 }
 template <typename T, int P>
-__global__ __launch_bounds__(kInvThreads) __attribute__((amdgpu_waves_per_eu(8))) void fft_inverse_group_kernel(const InvArgs* __restrict__ jobs,
+__global__ __launch_bounds__(kInvThreads) __attribute__((amdgpu_waves_per_eu(InvWaves<T, P>::value))) void fft_inverse_group_kernel(const InvArgs* __restrict__ jobs,
                                                                         const int64_t* __restrict__ pre,
                                                                         int nj) {
   int64_t b;
