@@ -212,7 +212,7 @@ def direct_error(torch, w, phi, n_sample=1000):
 
 
 def run_blas(K, torch, steps, warmup):
-    """The 32-vector BLAS-M2L workload in FP64, FP32 and bf16x3."""
+    """The 32-vector BLAS-M2L workload in FP64, FP32, bf16x3 and bf16x6."""
     import workloads
     w = workloads.config(3)
     out = {"workload": w.name, "n_vec": w.nvec, "svd_rel_tol": 1e-6, "svd_rel_tol_dir": 1e-6}
@@ -220,7 +220,7 @@ def run_blas(K, torch, steps, warmup):
     flops = None
     sample = workloads.sample_indices(w.n, 1000, workloads.SEED_SAMPLES + 3)
     ref_direct = direct_potentials(torch, w, sample)
-    for prec in ("fp64", "fp32", "bf16x3"):
+    for prec in ("fp64", "fp32", "bf16x3", "bf16x6"):
         dt = torch.float64 if prec == "fp64" else torch.float32
         t0 = time.perf_counter()
         f = K.KiFMM(w.order, w.depth, m2l="blas", prec=prec, svd_rel_tol=1e-6,
@@ -243,6 +243,8 @@ def run_blas(K, torch, steps, warmup):
         phi = torch.empty((w.nvec, w.n), dtype=dt, device="cuda")
         tune_ms = f.autotune(q, phi, reps=2)
         tuning = f.tuning()
+        # BF16x6 has only the stacked form, whatever the form knob holds
+        form = "stacked" if prec == "bf16x6" else ("stacked", "fused")[tuning["blas_form"]]
         for _ in range(warmup):
             f.evaluate(q, phi)
         torch.cuda.synchronize()
@@ -264,7 +266,7 @@ def run_blas(K, torch, steps, warmup):
         rel = float(torch.linalg.norm(phi.double() - ref_phi) / torch.linalg.norm(ref_phi))
         derr = direct_errors(torch, w, phi, ref_direct, sample)
         main_s = tm["m2l_main"] * 1e-3
-        peak = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2500e12 / 3}[prec]
+        peak = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2500e12 / 3, "bf16x6": 2500e12 / 6}[prec]
         out[prec] = {"m2l_ms": round(tm["m2l"], 3), "m2l_ms_per_vector": round(tm["m2l"] / w.nvec, 4),
                      "fused_kernel_ms": round(tm["m2l_main"], 3), "ms_per_step": round(ms_step, 3),
                      "fused_tflops": round(flops / main_s / 1e12, 2),
@@ -273,12 +275,12 @@ def run_blas(K, torch, steps, warmup):
                      "setup_s": round(setup_s, 2),
                      "precompute_s": round(precompute_s, 3),
                      "autotuned_tile_boxes": tuning["blas_tile"],
-                     "autotuned_form": ("stacked", "fused")[tuning["blas_form"]],
+                     "autotuned_form": form,
                      "autotune_best_ms": round(tune_ms, 3)}
         log(f"  blas {prec}: step {ms_step:.2f} ms, m2l {tm['m2l']:.2f} ms (fused {tm['m2l_main']:.2f}), "
             f"{flops / main_s / 1e12:.1f} TFLOP/s, rel vs fp64 {rel:.2e}, vs direct "
             f"{derr['max_over_vectors']:.2e} (max over vectors), autotuned tile {tuning['blas_tile']} boxes, "
-            f"form {('stacked', 'fused')[tuning['blas_form']]}")
+            f"form {form}")
         if prec == "fp64":
             # the plain FP64 comparator: the same M2L form, one charge vector per launch
             q1 = q[:1].contiguous()
@@ -312,10 +314,10 @@ def run_blas(K, torch, steps, warmup):
     del f, q, phi
     torch.cuda.empty_cache()
     out["algorithmic_gflop"] = round(flops / 1e9, 1)
-    out["peaks_tflops"] = {"fp64": 78.6, "fp32": 157.3, "bf16x3": round(2500 / 3, 1)}
+    out["peaks_tflops"] = {"fp64": 78.6, "fp32": 157.3, "bf16x3": round(2500 / 3, 1), "bf16x6": round(2500 / 6, 1)}
     one = out["fp64_one_rhs_per_launch"]["m2l_ms"]
     out["m2l_per_vector_speedup_vs_fp64_one_rhs"] = {
-        p: round(one / out[p]["m2l_ms_per_vector"], 2) for p in ("fp64", "fp32", "bf16x3")}
+        p: round(one / out[p]["m2l_ms_per_vector"], 2) for p in ("fp64", "fp32", "bf16x3", "bf16x6")}
     out["error_targets"] = len(sample)
     return out
 
@@ -420,7 +422,7 @@ def run_sphere(K, torch, steps, warmup):
     ref = direct_potentials(torch, w, sample)
     out = {"workload": w.name, "n_points": w.n, "depth": w.depth, "order": w.order, "n_vec": w.nvec,
            "error_targets": len(sample)}
-    for m2l, precs in (("fft", ("fp32", "fp64")), ("blas", ("fp32", "bf16x3", "fp64"))):
+    for m2l, precs in (("fft", ("fp32", "fp64")), ("blas", ("fp32", "bf16x3", "bf16x6", "fp64"))):
         for prec in precs:
             dt = torch.float64 if prec == "fp64" else torch.float32
             kw = dict(svd_rel_tol=1e-6, svd_rel_tol_dir=1e-6) if m2l == "blas" else {}
@@ -453,7 +455,7 @@ def run_sphere(K, torch, steps, warmup):
             f.close()
             del f, q, phi
             torch.cuda.empty_cache()
-    for m2l, mixed in (("fft", ("fp32",)), ("blas", ("fp32", "bf16x3"))):
+    for m2l, mixed in (("fft", ("fp32",)), ("blas", ("fp32", "bf16x3", "bf16x6"))):
         one = out[f"{m2l}_fp64_one_rhs_per_launch"]["m2l_ms"]
         for prec in mixed + ("fp64",):
             out[f"{m2l}_{prec}"]["m2l_per_vector_speedup_vs_fp64_one_rhs"] = round(
@@ -837,7 +839,7 @@ def main():
     # times the deterministic precompute uncached (the re-setup and check-order
     # sections build BLAS-M2L handles of the same configuration)
     if not args.no_blas:
-        log("blas-m2l workload: 32 vectors, fp64 / fp32 / bf16x3")
+        log("blas-m2l workload: 32 vectors, fp64 / fp32 / bf16x3 / bf16x6")
         line["blas_32rhs"] = run_blas(K, torch, max(1, min(args.steps, 3)), 1)
     if not args.no_resetup:
         log("moving points: host tree build vs device re-setup")

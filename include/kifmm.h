@@ -90,8 +90,15 @@ typedef enum { KIFMM_M2L_DENSE = 0, KIFMM_M2L_FFT = 1, KIFMM_M2L_BLAS = 2 } kifm
  *                  rounding, see KIFMM_TUNE_PRODUCTS; BLAS/DENSE: FP32 GEMMs).
  *   KIFMM_BF16X3 - charges/potentials float; BLAS/DENSE M2L GEMMs on bf16
  *                  MFMA with hi+lo split operands (a = hi + lo, products
- *                  hi*hi + hi*lo + lo*hi, FP32 accumulation); FFT M2L as FP32. */
-typedef enum { KIFMM_FP64 = 0, KIFMM_FP32 = 1, KIFMM_BF16X3 = 2 } kifmm_prec;
+ *                  hi*hi + hi*lo + lo*hi, FP32 accumulation); FFT M2L as FP32.
+ *   KIFMM_BF16X6 - charges/potentials float; BLAS-M2L with directional
+ *                  recompression (Section 3.2's two products per transfer
+ *                  vector, stacked form) on bf16 MFMA with three-part split
+ *                  operands (a = a0 + a1 + a2, the six products of order at
+ *                  most two, FP32 accumulation): FP32-class rounding.  Other
+ *                  M2L forms, and BLAS-M2L without recompression, are
+ *                  refused (EUNSUPPORTED at kifmm_create / kifmm_precompute). */
+typedef enum { KIFMM_FP64 = 0, KIFMM_FP32 = 1, KIFMM_BF16X3 = 2, KIFMM_BF16X6 = 3 } kifmm_prec;
 
 typedef struct {
   uint32_t size;            /* sizeof(kifmm_config), for ABI versioning */

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkifmm.so")
 
 M2L = {"dense": 0, "fft": 1, "blas": 2}
-PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 STATUS = {0: "OK", 1: "EINVAL", 2: "ESTATE", 3: "ENOMEM", 4: "EDEVICE", 5: "EUNSUPPORTED",
           6: "ENUMERIC"}
 
@@ -124,8 +124,8 @@ def _ptr(a: np.ndarray, ctype):
 class KiFMM:
     """A kiFMM problem: configuration, points, precomputed operators.
 
-    ``m2l`` is "dense", "fft" or "blas"; ``prec`` is "fp64", "fp32" or
-    "bf16x3" (see ``include/kifmm.h``).
+    ``m2l`` is "dense", "fft" or "blas"; ``prec`` is "fp64", "fp32", "bf16x3"
+    or "bf16x6" (see ``include/kifmm.h``).
     """
 
     def __init__(self, order: int, depth: int, m2l: str = "fft", prec: str = "fp64",

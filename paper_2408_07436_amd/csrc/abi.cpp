@@ -66,12 +66,14 @@ kifmm_status kifmm_create(const kifmm_config* cfg, kifmm_handle** out) {
   if (cfg->depth < 2 || cfg->depth > 16) return fail(KIFMM_EINVAL, "depth must be in 2..16");
   if (cfg->m2l < KIFMM_M2L_DENSE || cfg->m2l > KIFMM_M2L_BLAS)
     return fail(KIFMM_EINVAL, "unknown m2l form");
-  if (cfg->prec < KIFMM_FP64 || cfg->prec > KIFMM_BF16X3)
+  if (cfg->prec < KIFMM_FP64 || cfg->prec > KIFMM_BF16X6)
     return fail(KIFMM_EINVAL, "unknown precision");
   if (cfg->m2l == KIFMM_M2L_FFT && cfg->order > 8)
     return fail(KIFMM_EUNSUPPORTED, "FFT M2L is built for orders 2..8");
   if (cfg->m2l == KIFMM_M2L_FFT && cfg->prec == KIFMM_BF16X3)
     return fail(KIFMM_EUNSUPPORTED, "bf16 split precision applies to the BLAS and dense M2L only");
+  if (cfg->prec == KIFMM_BF16X6 && cfg->m2l != KIFMM_M2L_BLAS)
+    return fail(KIFMM_EUNSUPPORTED, "BF16x6 applies to the stacked BLAS M2L only");
   if (cfg->check_order != 0 && cfg->check_order < cfg->order)
     return fail(KIFMM_EINVAL, "check_order must be 0 or >= order");
   if (cfg->check_order > cfg->order && cfg->m2l != KIFMM_M2L_BLAS)
@@ -125,12 +127,20 @@ kifmm_status kifmm_precompute(kifmm_handle* h) {
   const Key key{c.order * 64 + pc, c.m2l, blas ? c.svd_rel_tol : 0.0, blas ? c.svd_rel_tol_dir : 0.0,
                 c.alpha_inner, c.alpha_outer, rnd ? 1 : 0, rnd ? h->svd.rank : 0,
                 rnd ? h->svd.oversample : 0, rnd ? h->svd.seed : 0};
+  // BF16x6 runs only the stacked form, which needs the second compression
+  auto usable = [h]() -> kifmm_status {
+    if (h->cfg.prec == KIFMM_BF16X6 && !h->op.recompressed) {
+      h->op = kifmm::Operators{};
+      return fail(KIFMM_EUNSUPPORTED, "BF16x6 needs directional recompression (svd_rel_tol_dir >= 0)");
+    }
+    return KIFMM_OK;
+  };
   {
     std::lock_guard<std::mutex> lock(mu);
     auto it = cache.find(key);
     if (it != cache.end()) {
       h->op = it->second;
-      return KIFMM_OK;
+      return usable();
     }
   }
   kifmm::SvdOptions svd = h->svd;
@@ -139,7 +149,7 @@ kifmm_status kifmm_precompute(kifmm_handle* h) {
   if (st != KIFMM_OK) return st;
   std::lock_guard<std::mutex> lock(mu);
   cache.emplace(key, h->op);
-  return KIFMM_OK;
+  return usable();
 }
 
 kifmm_status kifmm_set_svd(kifmm_handle* h, int32_t mode, int32_t rank, int32_t oversample,

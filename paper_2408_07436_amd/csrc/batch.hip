@@ -275,7 +275,8 @@ kifmm_status kifmm_batch_autotune(kifmm_handle* const* handles, int32_t n,
   for (int i = 0; i < n; ++i) {
     const kifmm_config& c = handles[i]->cfg;
     if (c.m2l != KIFMM_M2L_FFT) tiled = true;
-    if (c.m2l == KIFMM_M2L_BLAS && handles[i]->op.recompressed) stacked = true;
+    // the form knob chooses between two forms (BF16x6 has the stacked one only)
+    if (c.m2l == KIFMM_M2L_BLAS && handles[i]->op.recompressed && c.prec != KIFMM_BF16X6) stacked = true;
   }
   // candidates: (BLAS form, BLAS tile shift): the tile width of problem i is
   // (128 / n_vec[i]) >> shift.  The FFT schedule and Hadamard work split do

@@ -114,9 +114,10 @@ struct DeviceState {
   bool stack_ok = false;
   int st_Rs = 0, st_Rpad = 0, st_nsteps = 0, st_rbo = 0, st_J = 0;
   void *st_A_hi = nullptr, *st_A_lo = nullptr, *st_B_hi = nullptr, *st_B_lo = nullptr;
+  void *st_A_p2 = nullptr, *st_B_p2 = nullptr;  // BF16x6: third parts
   int32_t* st_info = nullptr;
   std::vector<int32_t> st_jof;  // [8][316]
-  void *xi_hi = nullptr, *xi_lo = nullptr;  // work: stacked intermediates
+  void *xi_hi = nullptr, *xi_lo = nullptr, *xi_p2 = nullptr;  // work: stacked intermediates
   std::vector<DevLevel> lv;
   // work buffers
   int nvec_cap = 0;
@@ -210,6 +211,12 @@ float bf16_value(uint16_t b) {
   return x;
 }
 
+// The stacked BLAS form runs when its operators exist and the knob asks for
+// it; BF16x6 has no fused form, so it always runs stacked.
+bool use_stacked(const kifmm_handle* h, const DeviceState* d) {
+  return d->stack_ok && (h->tune[KIFMM_TUNE_BLAS_FORM] == 0 || d->blas_mode == 3);
+}
+
 // Position of column c of a second-product operator in its packed row, per
 // mode: FP32 keeps the order; FP64 accumulator rows are g + 4 s, so a lane's
 // four K values (c = 16 j + g + 4 s) are packed at 16 j + 4 g + s; bf16 steps
@@ -244,8 +251,12 @@ int xi_row(int mode, int r) {
 // ktp = k_t and kp = k rounded up to 16 (FP32 / FP64) or 32 (bf16).
 kifmm_status pack_blas_operators(kifmm_handle* h, DeviceState* d) {
   const Operators& op = h->op;
-  const int mode = h->cfg.prec == KIFMM_FP64 ? 0 : (h->cfg.prec == KIFMM_FP32 ? 1 : 2);
-  const int q = mode == 2 ? 32 : 16;
+  const int mode = h->cfg.prec == KIFMM_FP64 ? 0 : h->cfg.prec == KIFMM_FP32 ? 1
+                   : h->cfg.prec == KIFMM_BF16X3 ? 2 : 3;
+  // BF16x6 runs the stacked form only (three-part operands of Stage A / B)
+  if (mode == 3 && !op.recompressed)
+    return fail(KIFMM_EUNSUPPORTED, "BF16x6 needs directional recompression (the stacked BLAS form)");
+  const int q = mode >= 2 ? 32 : 16;
   const int k = op.k;
   const int kp = (k + q - 1) / q * q;
   if (kp > 160) return fail(KIFMM_EUNSUPPORTED, "compressed rank above 160 is not supported");
@@ -266,7 +277,7 @@ kifmm_status pack_blas_operators(kifmm_handle* h, DeviceState* d) {
     }
     const int kt = op.kt[t];
     const int tp = (kt + q - 1) / q * q;
-    if (tp > (mode == 2 ? 64 : 48))
+    if (mode != 3 && tp > (mode == 2 ? 64 : 48))
       return fail(KIFMM_EUNSUPPORTED, "directional rank above the fused kernel's limit");
     ktp[t] = tp;
     ktq[t] = mode == 1 ? (kt + 3) / 4 : tp / 4;
@@ -296,6 +307,8 @@ kifmm_status pack_blas_operators(kifmm_handle* h, DeviceState* d) {
     float* p;
     KIFMM_TRY(upload(d, &p, f.data(), f.size()));
     d->op_hi = p;
+  } else if (mode == 3) {
+    d->op_hi = d->op_lo = nullptr;  // no fused form in BF16x6
   } else {
     std::vector<uint16_t> hi(packed.size()), lo(packed.size());
     for (size_t i = 0; i < packed.size(); ++i) {
@@ -328,7 +341,7 @@ kifmm_status pack_blas_operators(kifmm_handle* h, DeviceState* d) {
 kifmm_status pack_blas_stacked(kifmm_handle* h, DeviceState* d) {
   const Operators& op = h->op;
   const int mode = d->blas_mode, k = op.k, kp = d->kp;
-  const int P = mode == 2 ? 8 : 4, KS = mode == 2 ? 32 : 4, G = mode == 2 ? 8 : 4;
+  const int P = mode >= 2 ? 8 : 4, KS = mode >= 2 ? 32 : 4, G = mode >= 2 ? 8 : 4;
   const int rbo = (kp / 16 + 1) / 2 * 2;
   auto admissible = [](int o, const int t[3]) {
     for (int ax = 0; ax < 3; ++ax) {
@@ -417,7 +430,7 @@ kifmm_status pack_blas_stacked(kifmm_handle* h, DeviceState* d) {
     const int kt = op.kt[it], i = rt_i[(size_t)o * nsteps * KS + r];
     return i < kt ? op.Ubar[it][(size_t)m * kt + i] : 0.0;
   };
-  const int per = mode == 2 ? 8 : 1;  // values per (lane, row block)
+  const int per = mode >= 2 ? 8 : 1;  // values per (lane, row block)
   // (plus 2 kStackChunk zero steps past the last class: Stage B stages the
   // operator one chunk ahead, so a part's last chunk reads up to two chunks
   // past its last step)
@@ -428,10 +441,10 @@ kifmm_status pack_blas_stacked(kifmm_handle* h, DeviceState* d) {
         for (int rb = 0; rb < rbo; ++rb)
           for (int e = 0; e < per; ++e) {
             const int m = rb * 16 + lane % 16;
-            const int r = mode == 2 ? 32 * n + 8 * (lane / 16) + e : 4 * n + lane / 16;
+            const int r = mode >= 2 ? 32 * n + 8 * (lane / 16) + e : 4 * n + lane / 16;
             B[((((size_t)o * nsteps + n) * 64 + lane) * rbo + rb) * per + e] = ubar(o, m, r);
           }
-  auto put = [&](const std::vector<double>& v, void** hi, void** lo) -> kifmm_status {
+  auto put = [&](const std::vector<double>& v, void** hi, void** lo, void** p2) -> kifmm_status {
     if (mode == 0) {
       double* p;
       KIFMM_TRY(upload(d, &p, v.data(), v.size()));
@@ -442,22 +455,30 @@ kifmm_status pack_blas_stacked(kifmm_handle* h, DeviceState* d) {
       KIFMM_TRY(upload(d, &p, f.data(), f.size()));
       *hi = p;
     } else {
-      std::vector<uint16_t> vh(v.size()), vl(v.size());
+      // BF16 parts: x0 = bf16(x), x1 = bf16(x - x0) (and x2 = bf16(x - x0 - x1))
+      std::vector<uint16_t> vh(v.size()), vl(v.size()), v2(mode == 3 ? v.size() : 0);
       for (size_t i = 0; i < v.size(); ++i) {
         const float x = (float)v[i];
         vh[i] = bf16_bits(x);
-        vl[i] = bf16_bits(x - bf16_value(vh[i]));
+        const float r1 = x - bf16_value(vh[i]);
+        vl[i] = bf16_bits(r1);
+        if (mode == 3) v2[i] = bf16_bits(r1 - bf16_value(vl[i]));
       }
       uint16_t *ph, *pl;
       KIFMM_TRY(upload(d, &ph, vh.data(), vh.size()));
       KIFMM_TRY(upload(d, &pl, vl.data(), vl.size()));
       *hi = ph;
       *lo = pl;
+      if (mode == 3) {
+        uint16_t* p3;
+        KIFMM_TRY(upload(d, &p3, v2.data(), v2.size()));
+        *p2 = p3;
+      }
     }
     return KIFMM_OK;
   };
-  KIFMM_TRY(put(A, &d->st_A_hi, &d->st_A_lo));
-  KIFMM_TRY(put(B, &d->st_B_hi, &d->st_B_lo));
+  KIFMM_TRY(put(A, &d->st_A_hi, &d->st_A_lo, &d->st_A_p2));
+  KIFMM_TRY(put(B, &d->st_B_hi, &d->st_B_lo, &d->st_B_p2));
   KIFMM_TRY(upload(d, &d->st_info, info.data(), info.size()));
   d->st_Rs = Rs;
   d->st_Rpad = Rpad;
@@ -987,12 +1008,15 @@ std::vector<WorkSlot> work_slots(const kifmm_handle* h, DeviceState* d, int nvec
   // far-field pass (split leaf passes: FFT schedules and batches)
   add(nv * (size_t)t.n_tgt * qbytes, raw(&d->nearbuf));
   if (h->cfg.m2l != KIFMM_M2L_FFT) {
-    add((size_t)maxn * nv * d->kp * (d->blas_mode == 0 ? 8 : 4), raw(&d->qpad));
-    if (d->stack_ok && h->tune[KIFMM_TUNE_BLAS_FORM] == 0) {
+    // padded compressed multipoles: FP64 8 bytes, FP32 / two BF16 parts 4,
+    // three BF16 parts 6 per value
+    add((size_t)maxn * nv * d->kp * (d->blas_mode == 0 ? 8 : d->blas_mode == 3 ? 6 : 4), raw(&d->qpad));
+    if (use_stacked(h, d)) {
       const size_t xi = (size_t)maxn * nv * d->st_Rs;
-      if (d->blas_mode == 2) {
+      if (d->blas_mode >= 2) {
         add(xi * 2, raw(&d->xi_hi));
         add(xi * 2, raw(&d->xi_lo));
+        if (d->blas_mode == 3) add(xi * 2, raw(&d->xi_p2));
       } else {
         add(xi * (d->blas_mode == 0 ? 8 : 4), raw(&d->xi_hi));
       }
@@ -1020,11 +1044,11 @@ kifmm_status ensure_work(kifmm_handle* h, int nvec) {
       KIFMM_TRY(build_blas_tiles(h, d, TB));
     }
   }
-  const bool need_xi = d->stack_ok && h->tune[KIFMM_TUNE_BLAS_FORM] == 0 && h->cfg.m2l != KIFMM_M2L_FFT;
+  const bool need_xi = use_stacked(h, d) && h->cfg.m2l != KIFMM_M2L_FFT;
   if (nvec <= d->nvec_cap && (!need_xi || d->xi_hi)) return KIFMM_OK;
   if (h->batches > 0)
     return fail(KIFMM_ESTATE, "a batch holds this handle: more vectors than its buffers hold");
-  d->xi_hi = d->xi_lo = nullptr;
+  d->xi_hi = d->xi_lo = d->xi_p2 = nullptr;
   nvec = std::max(nvec, d->nvec_cap);
   for (void* p : d->work_allocs) (void)hipFree(p);
   d->work_allocs.clear();
@@ -1162,15 +1186,18 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
     KIFMM_LAUNCH(gemm(d, g, s));
     qsrc = d->tmp;
   }
-  if (!dense && d->stack_ok && h->tune[KIFMM_TUNE_BLAS_FORM] == 0) {
+  if (!dense && use_stacked(h, d)) {
     // stacked form: Stage A (xi of every source box), Stage B (targets)
     void* qlo = nullptr;
-    if (d->blas_mode == 2) {
-      qlo = static_cast<char*>(d->qpad) + (size_t)D.n * nvec * d->kp * 2;
+    void* qp2 = nullptr;
+    if (d->blas_mode >= 2) {
+      const size_t part = (size_t)D.n * nvec * d->kp * 2;  // bytes of one BF16 part
+      qlo = static_cast<char*>(d->qpad) + part;
+      if (d->blas_mode == 3) qp2 = static_cast<char*>(d->qpad) + 2 * part;
       void* qhi = d->qpad;
       const int kp = d->kp;
       const int64_t ncols = D.n * nvec;
-      KIFMM_LAUNCH(run_single(d, [=](hipStream_t st) { return launch_pad_split(qsrc, k, ncols, kp, qhi, qlo, st); }, s));
+      KIFMM_LAUNCH(run_single(d, [=](hipStream_t st) { return launch_pad_split(qsrc, k, ncols, kp, qhi, qlo, qp2, st); }, s));
     } else {
       void* qp = d->qpad;
       const int kp = d->kp;
@@ -1204,6 +1231,10 @@ kifmm_status m2l_level(kifmm_handle* h, int l, const double* in, double* out, in
     b.q_lo = qlo;
     b.xi_hi = d->xi_hi;
     b.xi_lo = d->xi_lo;
+    b.A_p2 = d->st_A_p2;
+    b.B_p2 = d->st_B_p2;
+    b.q_p2 = qp2;
+    b.xi_p2 = d->xi_p2;
     b.out = d->tmp2;
     b.scale = 1.0 / D.w;
     // levels with few tiles split Stage B's K steps over up to 16 workgroups
@@ -1744,7 +1775,7 @@ kifmm_status device_autotune(kifmm_handle* h, const void* q, int64_t ldq, int nv
       }
   } else {
     const int tb_max = std::max(1, 128 / nvec);
-    const bool two_forms = h->cfg.m2l == KIFMM_M2L_BLAS && h->op.recompressed;
+    const bool two_forms = h->cfg.m2l == KIFMM_M2L_BLAS && h->op.recompressed && h->cfg.prec != KIFMM_BF16X6;
     for (int form = 0; form < (two_forms ? 2 : 1); ++form) {
       int last = -1;
       for (int k = 0; k < 4; ++k) {
@@ -1845,7 +1876,7 @@ kifmm_status rebuild_tree(kifmm_handle* h, const TreeBuild& tb, const std::vecto
   for (void* p : d->work_allocs) (void)hipFree(p);
   d->work_allocs.clear();
   d->nvec_cap = 0;
-  d->xi_hi = d->xi_lo = nullptr;
+  d->xi_hi = d->xi_lo = d->xi_p2 = nullptr;
   d->tile_tb = 0;
   // from here on the handle holds the new tree; its host arrays are filled
   // from the device on demand (refresh_host_tree)

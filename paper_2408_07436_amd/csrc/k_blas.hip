@@ -757,18 +757,23 @@ __global__ void stack_reduce_kernel(BlasStack a) {
 }
 
 // x = hi + lo for four floats, round-to-nearest-even bf16 parts
-__device__ inline void split4(const v4f x, __bf16* hi, __bf16* lo) {
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const __bf16 h = (__bf16)x[e];
-    hi[e] = h;
-    lo[e] = (__bf16)(x[e] - (float)h);
+// Stage A, BF16 parts: operands split into NP = 2 parts (BF16x3: hi + lo,
+// three products) or NP = 3 (BF16x6: x0 + x1 + x2, the six products of
+// order at most two, FP32-class), FP32 accumulation; xi stored split,
+// [box][Rs / 8][v][8] so that eight consecutive rows of one column are one
+// 16-byte load in Stage B.
+template <int NP>
+__device__ __forceinline__ void parts_mfma(v4f& acc, const v8bf (&a)[NP], const v8bf (&b)[NP]) {
+  acc = mfbf(a[0], b[0], acc);
+  acc = mfbf(a[0], b[1], acc);
+  acc = mfbf(a[1], b[0], acc);
+  if (NP == 3) {
+    acc = mfbf(a[0], b[NP - 1], acc);
+    acc = mfbf(a[1], b[1], acc);
+    acc = mfbf(a[NP - 1], b[0], acc);
   }
 }
-
-// Stage A, BF16x3: operands split hi + lo (three products, FP32
-// accumulation); xi stored split, [box][Rs / 8][v][8] so that eight
-// consecutive rows of one column are one 16-byte load in Stage B.
+template <int NP>
 __global__ __launch_bounds__(256, 2) void stack_a_bf16_kernel(BlasStack a) {
   const int nmb = a.Rpad / 128;
   const int64_t w = xcd_item();
@@ -778,11 +783,11 @@ __global__ __launch_bounds__(256, 2) void stack_a_bf16_kernel(BlasStack a) {
   const int cls = a.tile_class[tile];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int l16 = lane % 16, g4 = lane / 16;
-  const __bf16* qh = static_cast<const __bf16*>(a.q_hi);
-  const __bf16* ql = static_cast<const __bf16*>(a.q_lo);
+  const __bf16* qp[3] = {static_cast<const __bf16*>(a.q_hi), static_cast<const __bf16*>(a.q_lo),
+                         static_cast<const __bf16*>(a.q_p2)};
   const int64_t aoff = ((int64_t)cls * a.Rpad + (int64_t)mb * 128) * a.kp;
-  const __bf16* Ah = static_cast<const __bf16*>(a.A_hi) + aoff;
-  const __bf16* Al = static_cast<const __bf16*>(a.A_lo) + aoff;
+  const __bf16* Ap[3] = {static_cast<const __bf16*>(a.A_hi) + aoff, static_cast<const __bf16*>(a.A_lo) + aoff,
+                         NP == 3 ? static_cast<const __bf16*>(a.A_p2) + aoff : nullptr};
   const StackCols cc = stack_columns(a, wave, l16);
   int box[2];
   int64_t qo[2];
@@ -798,74 +803,71 @@ __global__ __launch_bounds__(256, 2) void stack_a_bf16_kernel(BlasStack a) {
     for (int ct = 0; ct < 2; ++ct) acc[rb][ct] = v4f{0.f, 0.f, 0.f, 0.f};
   const v8bf zero8 = {};
   // As in the FP32 / FP64 Stage A: each K slab (32) of the workgroup's 128
-  // operator rows, high and low parts, staged once in LDS (double-buffered,
-  // rows padded to 80 bytes for conflict-free 16-byte reads), the next
-  // slab's operator and multipole loads issued branch-free ahead of the
-  // current slab's MFMAs.
+  // operator rows, every part, staged once in LDS (double-buffered, rows
+  // padded to 80 bytes for conflict-free 16-byte reads), the next slab's
+  // operator and multipole loads issued branch-free ahead of the current
+  // slab's MFMAs.
   constexpr int RS = 40;  // bf16 values per LDS row
-  __shared__ __attribute__((aligned(16))) __bf16 lds[2][2][128 * RS];
+  __shared__ __attribute__((aligned(16))) __bf16 lds[2][NP][128 * RS];
   const int srow = threadIdx.x >> 1, shalf = threadIdx.x & 1;
   const int64_t asrc = (int64_t)srow * a.kp + shalf * 16;
-  v8bf sh0, sh1, sl0, sl1;  // 16 staged high and low values of this thread
+  v8bf sg[NP][2];  // 16 staged values of each part of this thread
   auto gload = [&](int kb) {
-    sh0 = ld8bf(Ah + asrc + kb);
-    sh1 = ld8bf(Ah + asrc + kb + 8);
-    sl0 = ld8bf(Al + asrc + kb);
-    sl1 = ld8bf(Al + asrc + kb + 8);
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      sg[q][0] = ld8bf(Ap[q] + asrc + kb);
+      sg[q][1] = ld8bf(Ap[q] + asrc + kb + 8);
+    }
   };
   auto swrite = [&](int buf) {
-    __bf16* dh = &lds[buf][0][srow * RS + shalf * 16];
-    __bf16* dl = &lds[buf][1][srow * RS + shalf * 16];
-    reinterpret_cast<v8bf*>(dh)[0] = sh0;
-    reinterpret_cast<v8bf*>(dh)[1] = sh1;
-    reinterpret_cast<v8bf*>(dl)[0] = sl0;
-    reinterpret_cast<v8bf*>(dl)[1] = sl1;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      __bf16* dq = &lds[buf][q][srow * RS + shalf * 16];
+      reinterpret_cast<v8bf*>(dq)[0] = sg[q][0];
+      reinterpret_cast<v8bf*>(dq)[1] = sg[q][1];
+    }
   };
   const int64_t qs[2] = {qo[0] >= 0 ? qo[0] : 0, qo[1] >= 0 ? qo[1] : 0};
-  auto load_q = [&](int kb, v8bf (&bh)[2], v8bf (&bl)[2]) {
+  auto load_q = [&](int kb, v8bf (&bq)[2][NP]) {
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-      const v8bf h = ld8bf(qh + qs[ct] + kb + 8 * g4), l = ld8bf(ql + qs[ct] + kb + 8 * g4);
-      bh[ct] = qo[ct] >= 0 ? h : zero8;
-      bl[ct] = qo[ct] >= 0 ? l : zero8;
-    }
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        const v8bf v = ld8bf(qp[q] + qs[ct] + kb + 8 * g4);
+        bq[ct][q] = qo[ct] >= 0 ? v : zero8;
+      }
   };
   gload(0);
   swrite(0);
-  v8bf bh[2], bl[2];
-  load_q(0, bh, bl);
+  v8bf bq[2][NP];
+  load_q(0, bq);
   __syncthreads();
   int buf = 0;
   for (int kb = 0; kb < a.kp; kb += 32, buf ^= 1) {
     const bool more = kb + 32 < a.kp;
     const int kn = more ? kb + 32 : kb;
-    v8bf nbh[2], nbl[2];
+    v8bf nbq[2][NP];
     gload(kn);
-    load_q(kn, nbh, nbl);
+    load_q(kn, nbq);
     // keep the next slab's loads ahead of this slab's MFMAs
     __builtin_amdgcn_sched_barrier(0);
-    const __bf16* Lh = &lds[buf][0][l16 * RS + 8 * g4];
-    const __bf16* Ll = &lds[buf][1][l16 * RS + 8 * g4];
 #pragma unroll
     for (int rb = 0; rb < 8; ++rb) {
-      const v8bf ah = ld8bf(Lh + rb * 16 * RS), al = ld8bf(Ll + rb * 16 * RS);
+      v8bf ap[NP];
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct) {
-        acc[rb][ct] = mfbf(ah, bh[ct], acc[rb][ct]);
-        acc[rb][ct] = mfbf(ah, bl[ct], acc[rb][ct]);
-        acc[rb][ct] = mfbf(al, bh[ct], acc[rb][ct]);
-      }
+      for (int q = 0; q < NP; ++q) ap[q] = ld8bf(&lds[buf][q][l16 * RS + 8 * g4] + rb * 16 * RS);
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) parts_mfma<NP>(acc[rb][ct], ap, bq[ct]);
     }
     if (more) swrite(buf ^ 1);
     __syncthreads();
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-      bh[ct] = nbh[ct];
-      bl[ct] = nbl[ct];
-    }
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int q = 0; q < NP; ++q) bq[ct][q] = nbq[ct][q];
   }
-  __bf16* xh = static_cast<__bf16*>(a.xi_hi);
-  __bf16* xl = static_cast<__bf16*>(a.xi_lo);
+  __bf16* xp[3] = {static_cast<__bf16*>(a.xi_hi), static_cast<__bf16*>(a.xi_lo),
+                   static_cast<__bf16*>(a.xi_p2)};
   const int64_t rb8 = a.Rs / 8;
 #pragma unroll
   for (int ct = 0; ct < 2; ++ct) {
@@ -875,19 +877,29 @@ __global__ __launch_bounds__(256, 2) void stack_a_bf16_kernel(BlasStack a) {
       const int row = mb * 128 + rb * 16 + 4 * g4;  // rows row .. row + 3 of this lane
       if (row >= a.Rs) continue;
       const int64_t o = (((int64_t)box[ct] * rb8 + row / 8) * a.nvec + cc.v[ct]) * 8 + row % 8;
-      __bf16 h[4], l[4];
-      split4(acc[rb][ct], h, l);
       typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
-      *reinterpret_cast<v4bf*>(xh + o) = v4bf{h[0], h[1], h[2], h[3]};
-      *reinterpret_cast<v4bf*>(xl + o) = v4bf{l[0], l[1], l[2], l[3]};
+      v4bf pv[3];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float x = acc[rb][ct][i];
+        const __bf16 h0 = (__bf16)x;
+        const float r1 = x - (float)h0;
+        const __bf16 h1 = (__bf16)r1;
+        pv[0][i] = h0;
+        pv[1][i] = h1;
+        pv[2][i] = (__bf16)(r1 - (float)h1);
+      }
+#pragma unroll
+      for (int q = 0; q < NP; ++q) *reinterpret_cast<v4bf*>(xp[q] + o) = pv[q];
     }
   }
 }
 
-// Stage B, BF16x3: K steps of 32 rows; lane group g4 takes the eight rows of
-// row group 4n + g4 (info per group), possibly of another transfer vector
-// than its neighbours.  Operators [8][nsteps][64 lanes][RBO][8] hi / lo.
-template <int RBO>
+// Stage B, BF16 parts (NP = 2 or 3, as Stage A): K steps of 32 rows; lane
+// group g4 takes the eight rows of row group 4n + g4 (info per group),
+// possibly of another transfer vector than its neighbours.  Operators
+// [8][nsteps][64 lanes][RBO][8] per part.
+template <int RBO, int NP>
 __global__ __launch_bounds__(256, 2) void stack_b_bf16_kernel(BlasStack a) {
   StackPart sp;
   if (!stack_part(a, a.nsteps, sp)) return;
@@ -899,10 +911,10 @@ __global__ __launch_bounds__(256, 2) void stack_b_bf16_kernel(BlasStack a) {
   const int32_t* src = a.tile_src + (int64_t)tile * a.J * a.TB;
   const int2* info = reinterpret_cast<const int2*>(a.info) + (int64_t)cls * a.nsteps * 4;
   const int64_t coff = (int64_t)cls * a.nsteps * 64 * RBO * 8;
-  const __bf16* Bh = static_cast<const __bf16*>(a.B_hi) + coff;
-  const __bf16* Bl = static_cast<const __bf16*>(a.B_lo) + coff;
-  const __bf16* xh = static_cast<const __bf16*>(a.xi_hi);
-  const __bf16* xl = static_cast<const __bf16*>(a.xi_lo);
+  const __bf16* Bp[3] = {static_cast<const __bf16*>(a.B_hi) + coff, static_cast<const __bf16*>(a.B_lo) + coff,
+                         NP == 3 ? static_cast<const __bf16*>(a.B_p2) + coff : nullptr};
+  const __bf16* xq[3] = {static_cast<const __bf16*>(a.xi_hi), static_cast<const __bf16*>(a.xi_lo),
+                         static_cast<const __bf16*>(a.xi_p2)};
   const int64_t rb8 = a.Rs / 8;
   const int nb = sp.n0, nst = sp.n1;  // steps of this part
   v4f acc[RBO][2];
@@ -912,7 +924,7 @@ __global__ __launch_bounds__(256, 2) void stack_b_bf16_kernel(BlasStack a) {
     for (int ct = 0; ct < 2; ++ct) acc[rb][ct] = v4f{0.f, 0.f, 0.f, 0.f};
   const v8bf zero8 = {};
   if (nb >= nst) return;
-  // The step's operator (high and low parts, the same for the four waves)
+  // The step's operator (every part, the same for the four waves)
   // staged in LDS one step ahead (double-buffered; each lane's values padded
   // by 16 bytes so that a quarter wave's 16-byte reads spread over the
   // banks).  Loads without branches, masked where used: the table entries
@@ -922,24 +934,22 @@ __global__ __launch_bounds__(256, 2) void stack_b_bf16_kernel(BlasStack a) {
   constexpr int PU = 2 * RBO / U;                  // units per thread and part
   typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
   using SV = typename std::conditional<U == 8, v8bf, v4bf>::type;
-  __shared__ __attribute__((aligned(16))) __bf16 ops[2][2][64 * LS];
+  __shared__ __attribute__((aligned(16))) __bf16 ops[2][NP][64 * LS];
   // thread t stages values [2 RBO t, 2 RBO (t + 1)) of the step's 8 RBO x 64
   const int st_lane = threadIdx.x / 4, st_off = (threadIdx.x % 4) * 2 * RBO;
-  SV sgh[PU], sgl[PU];
+  SV sg[NP][PU];
   auto gload = [&](int n) {
     const int64_t o = (int64_t)n * 64 * RBO * 8 + (int64_t)threadIdx.x * 2 * RBO;
 #pragma unroll
-    for (int u = 0; u < PU; ++u) {
-      sgh[u] = *reinterpret_cast<const SV*>(Bh + o + u * U);
-      sgl[u] = *reinterpret_cast<const SV*>(Bl + o + u * U);
-    }
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+      for (int u = 0; u < PU; ++u) sg[q][u] = *reinterpret_cast<const SV*>(Bp[q] + o + u * U);
   };
   auto swrite = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < PU; ++u) {
-      *reinterpret_cast<SV*>(&ops[buf][0][st_lane * LS + st_off + u * U]) = sgh[u];
-      *reinterpret_cast<SV*>(&ops[buf][1][st_lane * LS + st_off + u * U]) = sgl[u];
-    }
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+      for (int u = 0; u < PU; ++u) *reinterpret_cast<SV*>(&ops[buf][q][st_lane * LS + st_off + u * U]) = sg[q][u];
   };
   const int sl[2] = {cc.ok[0] ? cc.slot[0] : 0, cc.ok[1] ? cc.slot[1] : 0};
   auto entry = [&](int n) -> int2 {
@@ -951,20 +961,20 @@ __global__ __launch_bounds__(256, 2) void stack_b_bf16_kernel(BlasStack a) {
     return (((int64_t)max(sb, 0) * rb8 + e.y / 8) * a.nvec + cc.v[ct]) * 8;
   };
   // pipeline registers: e1 / e2 = table entries of steps n + 1, n + 2;
-  // s1 / sv1 = raw source boxes of step n + 1 and their validity; x0h / x0l
-  // / xv0 = raw xi values of step n and their validity
+  // s1 / sv1 = raw source boxes of step n + 1 and their validity; x0 / xv0 =
+  // raw xi parts of step n and their validity
   const int2 e0 = entry(nb);
   int2 e1 = entry(nb + 1), e2 = entry(nb + 2);
   int s1[2];
   bool sv1[2], xv0[2];
-  v8bf x0h[2], x0l[2];
+  v8bf x0[2][NP];
 #pragma unroll
   for (int ct = 0; ct < 2; ++ct) {
     const int s0 = src_raw(e0, ct);
     xv0[ct] = cc.ok[ct] && e0.x >= 0 && s0 >= 0;
     const int64_t o = xoff(xv0[ct] ? s0 : 0, e0, ct);
-    x0h[ct] = ld8bf(xh + o);
-    x0l[ct] = ld8bf(xl + o);
+#pragma unroll
+    for (int q = 0; q < NP; ++q) x0[ct][q] = ld8bf(xq[q] + o);
     s1[ct] = src_raw(e1, ct);
     sv1[ct] = cc.ok[ct] && e1.x >= 0;
   }
@@ -977,35 +987,30 @@ __global__ __launch_bounds__(256, 2) void stack_b_bf16_kernel(BlasStack a) {
     const int2 e3 = entry(n + 3);
     int s2[2];
     bool sv2[2], xv1[2];
-    v8bf x1h[2], x1l[2];
+    v8bf x1[2][NP];
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) {
       s2[ct] = src_raw(e2, ct);
       sv2[ct] = cc.ok[ct] && e2.x >= 0;
       xv1[ct] = sv1[ct] && s1[ct] >= 0;
       const int64_t o = xoff(xv1[ct] ? s1[ct] : 0, e1, ct);
-      x1h[ct] = ld8bf(xh + o);
-      x1l[ct] = ld8bf(xl + o);
+#pragma unroll
+      for (int q = 0; q < NP; ++q) x1[ct][q] = ld8bf(xq[q] + o);
     }
     gload(n + 1);
     // products of step n
-    v8bf bh[2], bl[2];
+    v8bf bq[2][NP];
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-      bh[ct] = xv0[ct] ? x0h[ct] : zero8;
-      bl[ct] = xv0[ct] ? x0l[ct] : zero8;
-    }
-    const __bf16* Lh = &ops[buf][0][lane * LS];
-    const __bf16* Ll = &ops[buf][1][lane * LS];
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int q = 0; q < NP; ++q) bq[ct][q] = xv0[ct] ? x0[ct][q] : zero8;
 #pragma unroll
     for (int rb = 0; rb < RBO; ++rb) {
-      const v8bf ah = ld8bf(Lh + rb * 8), al = ld8bf(Ll + rb * 8);
+      v8bf ap[NP];
 #pragma unroll
-      for (int ct = 0; ct < 2; ++ct) {
-        acc[rb][ct] = mfbf(ah, bh[ct], acc[rb][ct]);
-        acc[rb][ct] = mfbf(ah, bl[ct], acc[rb][ct]);
-        acc[rb][ct] = mfbf(al, bh[ct], acc[rb][ct]);
-      }
+      for (int q = 0; q < NP; ++q) ap[q] = ld8bf(&ops[buf][q][lane * LS] + rb * 8);
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct) parts_mfma<NP>(acc[rb][ct], ap, bq[ct]);
     }
     // the next step's operator into the other buffer (its last reader
     // passed the previous barrier)
@@ -1015,8 +1020,8 @@ __global__ __launch_bounds__(256, 2) void stack_b_bf16_kernel(BlasStack a) {
     // roll
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) {
-      x0h[ct] = x1h[ct];
-      x0l[ct] = x1l[ct];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) x0[ct][q] = x1[ct][q];
       xv0[ct] = xv1[ct];
       s1[ct] = s2[ct];
       sv1[ct] = sv2[ct];
@@ -1041,17 +1046,21 @@ __global__ __launch_bounds__(256, 2) void stack_b_bf16_kernel(BlasStack a) {
   }
 }
 
-// q~ (FP64, [box][v][k]) -> padded [box][v][kp] bf16 high and low parts
+// q~ (FP64, [box][v][k]) -> padded [box][v][kp] bf16 parts: high and low
+// (p2 null), or three parts x0, x1, x2
 __global__ void pad_split_kernel(const double* __restrict__ in, int k, int64_t ncols, int kp,
-                                 __bf16* __restrict__ hi, __bf16* __restrict__ lo) {
+                                 __bf16* __restrict__ hi, __bf16* __restrict__ lo, __bf16* __restrict__ p2) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= ncols * kp) return;
   const int64_t col = i / kp;
   const int r = (int)(i - col * kp);
   const float x = r < k ? (float)in[col * k + r] : 0.f;
   const __bf16 h = (__bf16)x;
+  const float r1 = x - (float)h;
+  const __bf16 l = (__bf16)r1;
   hi[i] = h;
-  lo[i] = (__bf16)(x - (float)h);
+  lo[i] = l;
+  if (p2) p2[i] = (__bf16)(r1 - (float)l);
 }
 
 // q~ (FP64, [box][v][k]) -> padded [box][v][kp] in T
@@ -1103,8 +1112,10 @@ hipError_t launch_blas_m2l(const BlasM2L& a, int mode, bool two_stage, hipStream
 
 hipError_t launch_blas_stacked(const BlasStack& a, hipStream_t stream) {
   if (a.ntiles == 0) return hipSuccess;
-  if (a.C > 128 || a.Rpad % 128 != 0 || a.Rs > a.Rpad || a.kp % (a.mode == 2 ? 32 : 16) != 0 ||
-      a.rbo * 16 < a.kp || a.kp < a.k || (a.mode == 2 && a.Rs % 8 != 0))
+  const bool parts = a.mode >= 2;  // BF16 parts: 2 (BF16x3) or 3 (BF16x6)
+  if (a.C > 128 || a.Rpad % 128 != 0 || a.Rs > a.Rpad || a.kp % (parts ? 32 : 16) != 0 ||
+      a.rbo * 16 < a.kp || a.kp < a.k || (parts && a.Rs % 8 != 0) || a.mode > 3 ||
+      (a.mode == 3 && (!a.A_p2 || !a.B_p2 || !a.q_p2 || !a.xi_p2)))
     return hipErrorInvalidValue;
   if (a.ksplit < 1 || (a.ksplit > 1 && !a.partial)) return hipErrorInvalidValue;
   const int64_t nwork = a.ntiles * (a.Rpad / 128);
@@ -1113,13 +1124,15 @@ hipError_t launch_blas_stacked(const BlasStack& a, hipStream_t stream) {
   const dim3 block(256);
   if (a.mode == 0) stack_a_kernel<double><<<grid_a, block, 0, stream>>>(a);
   else if (a.mode == 1) stack_a_kernel<float><<<grid_a, block, 0, stream>>>(a);
-  else stack_a_bf16_kernel<<<grid_a, block, 0, stream>>>(a);
+  else if (a.mode == 2) stack_a_bf16_kernel<2><<<grid_a, block, 0, stream>>>(a);
+  else stack_a_bf16_kernel<3><<<grid_a, block, 0, stream>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
 #define KIFMM_STACK_B(RR)                                                        \
   if (a.mode == 0) stack_b_kernel<double, RR><<<grid_b, block, 0, stream>>>(a);  \
   else if (a.mode == 1) stack_b_kernel<float, RR><<<grid_b, block, 0, stream>>>(a); \
-  else stack_b_bf16_kernel<RR><<<grid_b, block, 0, stream>>>(a);
+  else if (a.mode == 2) stack_b_bf16_kernel<RR, 2><<<grid_b, block, 0, stream>>>(a); \
+  else stack_b_bf16_kernel<RR, 3><<<grid_b, block, 0, stream>>>(a);
   switch (a.rbo) {
     case 2: KIFMM_STACK_B(2) break;
     case 4: KIFMM_STACK_B(4) break;
@@ -1138,12 +1151,12 @@ hipError_t launch_blas_stacked(const BlasStack& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_pad_split(const double* in, int k, int64_t ncols, int kp, void* hi, void* lo,
+hipError_t launch_pad_split(const double* in, int k, int64_t ncols, int kp, void* hi, void* lo, void* p2,
                             hipStream_t stream) {
   const int64_t n = ncols * kp;
   if (n == 0) return hipSuccess;
   pad_split_kernel<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(in, k, ncols, kp, (__bf16*)hi,
-                                                                    (__bf16*)lo);
+                                                                    (__bf16*)lo, (__bf16*)p2);
   return hipGetLastError();
 }
 

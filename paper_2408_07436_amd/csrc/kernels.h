@@ -335,7 +335,7 @@ hipError_t launch_blas_m2l(const BlasM2L& a, int mode, bool two_stage, hipStream
 // Stage B stages its operator in LDS at most kStackChunk K steps at a time.
 constexpr int kStackChunk = 8;
 struct BlasStack {
-  int mode;                   // 0 FP64, 1 FP32, 2 BF16x3
+  int mode;                   // 0 FP64, 1 FP32, 2 BF16x3, 3 BF16x6 (three BF16 parts)
   int k, kp;                  // compressed rank; padded (K of Stage A, M of Stage B)
   int nvec, TB, C;            // vectors, boxes per tile, columns per tile (TB * nvec <= 128)
   int64_t ntiles;
@@ -347,15 +347,19 @@ struct BlasStack {
   int Rpad;                   // Stage A operator rows per class (Rs rounded up to 128)
   int nsteps;                 // Stage B K steps per class (4 rows; 32 for BF16x3)
   int rbo;                    // Stage B operator row blocks of 16 (kp / 16)
-  const void* A_hi;           // Stage A operators [8][Rpad][kp] (BF16x3: high parts)
-  const void* A_lo;           //   BF16x3 low parts
+  const void* A_hi;           // Stage A operators [8][Rpad][kp] (BF16 parts: first)
+  const void* A_lo;           //   BF16 parts: second
   const void* B_hi;           // Stage B operators in MFMA lane order (see device.hip)
   const void* B_lo;
   const int32_t* info;        // [8][groups][2]: (j, first xi row) per row group of Stage B's K
-  const void* q_hi;           // padded compressed multipoles [box][v][kp] (BF16x3: high parts)
-  const void* q_lo;           //   BF16x3 low parts
-  void* xi_hi;                // [box][Rs][v] (BF16x3: [box][Rs / 8][v][8] high parts)
-  void* xi_lo;                //   BF16x3 low parts
+  const void* q_hi;           // padded compressed multipoles [box][v][kp] (BF16 parts: first)
+  const void* q_lo;           //   BF16 parts: second
+  void* xi_hi;                // [box][Rs][v] (BF16 parts: [box][Rs / 8][v][8], first)
+  void* xi_lo;                //   BF16 parts: second
+  const void* A_p2 = nullptr;  // BF16x6: third parts of A, B, q and xi
+  const void* B_p2 = nullptr;
+  const void* q_p2 = nullptr;
+  void* xi_p2 = nullptr;
   double* out;                // [box][v][k]
   double scale;
   // Stage B's K steps split over ksplit workgroups per tile (levels with
@@ -366,8 +370,9 @@ struct BlasStack {
   double* partial = nullptr;
 };
 hipError_t launch_blas_stacked(const BlasStack& a, hipStream_t stream);
-// q~ [col][k] FP64 -> [col][kp] zero-padded bf16 high and low parts
-hipError_t launch_pad_split(const double* in, int k, int64_t ncols, int kp, void* hi, void* lo,
+// q~ [col][k] FP64 -> [col][kp] zero-padded bf16 parts: high and low (p2
+// null), or the three parts of the BF16x6 mode
+hipError_t launch_pad_split(const double* in, int k, int64_t ncols, int kp, void* hi, void* lo, void* p2,
                             hipStream_t stream);
 // q~ [col][k] FP64 -> [col][kp] zero-padded, FP64 or FP32
 hipError_t launch_pad_convert(const double* in, int k, int64_t ncols, int kp, bool fp64, void* out,

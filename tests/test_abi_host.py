@@ -114,6 +114,20 @@ def test_error_codes():
     with pytest.raises(K.KifmmError) as e:
         K.KiFMM(4, 3, m2l="fft", prec="bf16x3")
     assert e.value.code == 5
+    for m2l in ("fft", "dense"):
+        with pytest.raises(K.KifmmError) as e:
+            K.KiFMM(4, 3, m2l=m2l, prec="bf16x6")
+        assert e.value.code == 5
+    # three-part BF16 runs the stacked BLAS form only: no directional
+    # recompression is refused once the operators are known
+    g = K.KiFMM(3, 3, m2l="blas", prec="bf16x6", svd_rel_tol=1e-6, svd_rel_tol_dir=-1.0)
+    with pytest.raises(K.KifmmError) as e:
+        g.precompute()
+    assert e.value.code == 5
+    with pytest.raises(K.KifmmError) as e:  # refused again from the operator cache
+        g.precompute()
+    assert e.value.code == 5
+    K.KiFMM(3, 3, m2l="blas", prec="bf16x6", svd_rel_tol=1e-6, svd_rel_tol_dir=1e-6).precompute()
     f = K.KiFMM(4, 3)
     with pytest.raises(K.KifmmError) as e:
         f.set_points(np.array([[0.5, 0.5, 1.5]]))

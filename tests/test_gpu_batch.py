@@ -24,6 +24,7 @@ PROBLEMS = [
     (9000, 3, 4, "blas", "bf16x3", 4),
     (7000, 3, 3, "dense", "fp64", 1),
     (15000, 4, 5, "fft", "fp64", 5),
+    (8000, 3, 5, "blas", "bf16x6", 2),
 ]
 
 

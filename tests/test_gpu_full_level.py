@@ -87,7 +87,8 @@ def sphere_4m():
 
 # (M2L form, precision, vectors, FP32 Hadamard products: 0 BF16 parts, 1 FP32 MFMA)
 CASES = [("fft", "fp64", 1, 0), ("fft", "fp32", 1, 0), ("fft", "fp32", 1, 1), ("blas", "fp32", NVEC_BLAS, 0),
-         ("blas", "bf16x3", NVEC_BLAS, 0), ("blas", "fp64", NVEC_BLAS, 0)]
+         ("blas", "bf16x3", NVEC_BLAS, 0), ("blas", "bf16x6", NVEC_BLAS, 0),
+         ("blas", "fp64", NVEC_BLAS, 0)]
 
 
 @pytest.mark.timeout(600)

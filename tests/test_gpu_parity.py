@@ -114,6 +114,20 @@ def test_blas_fused_precisions(prec, gate, nvec, form):
     check_parity(got, ref, E2E_GATES[prec], what="vs oracle (projected operator)")
 
 
+@pytest.mark.parametrize("nvec", [1, 3])
+def test_blas_bf16x6(nvec):
+    """Three-part BF16 operands run the stacked form whatever the form knob
+    holds: both knob values give identical potentials, within the FP32 gates."""
+    pts = workloads.uniform_cube(20000, 93)
+    q = workloads.charges(20000, nvec, 94, "upm1")
+    say(f"case: blas bf16x6 tol 1e-6/1e-6 uniform 20k depth 3 p6 nvec {nvec}")
+    got0, _ = evaluate(K, pts, q, 3, 6, "blas", "bf16x6", tol=1e-6, tol_dir=1e-6, tune=dict(blas_form=0))
+    got1, _ = evaluate(K, pts, q, 3, 6, "blas", "bf16x6", tol=1e-6, tol_dir=1e-6, tune=dict(blas_form=1))
+    assert np.array_equal(got0, got1)
+    ref = fmm.KiFMM(pts, pts, 3, 6, m2l="blas", svd_rel_tol=1e-6, svd_rel_tol_dir=1e-6).evaluate(q)
+    check_parity(got0, ref, E2E_GATES["bf16x6"], what="vs oracle (projected operator)")
+
+
 @pytest.mark.parametrize("prec,gate", [("fp32", FP32_GATE), ("bf16x3", FP32_GATE)])
 def test_dense_reduced_precision_20k(prec, gate):
     w = workloads.config(1)
@@ -127,10 +141,12 @@ def test_dense_reduced_precision_20k(prec, gate):
 # sqrt(k) * 2^-24 ~ 7e-7 relative (L2 gate 2e-6 here); bf16x3 operands carry
 # about 16 bits.
 @pytest.mark.parametrize("prec,gate", [("fp64", STAGE_GATES["fp64"]), ("fp32", (2e-6, 1e-5)),
-                                       ("bf16x3", STAGE_GATES["bf16x3"])])
+                                       ("bf16x3", STAGE_GATES["bf16x3"]), ("bf16x6", (2e-6, 1e-5))])
 @pytest.mark.parametrize("tol_dir", [1e-6, -1.0])
 @pytest.mark.parametrize("form", [0, 1])
 def test_blas_stage_check_potentials(prec, gate, tol_dir, form):
+    if prec == "bf16x6" and (tol_dir < 0 or form == 1):
+        pytest.skip("BF16x6 runs the stacked form only (directional recompression)")
     pts = workloads.sphere_surface(30000, 95)
     ora = fmm.KiFMM(pts, pts, 5, 5, origin=(-1, -1, -1), width=2.0, m2l="blas",
                     svd_rel_tol=1e-7, svd_rel_tol_dir=tol_dir)
@@ -149,7 +165,7 @@ def test_blas_stage_check_potentials(prec, gate, tol_dir, form):
         check_parity(got, ref, gate, vec_axis=1, what="check potentials vs oracle (projected)")
 
 
-@pytest.mark.parametrize("prec,gate", [("fp32", FP32_GATE), ("bf16x3", FP32_GATE)])
+@pytest.mark.parametrize("prec,gate", [("fp32", FP32_GATE), ("bf16x3", FP32_GATE), ("bf16x6", FP32_GATE)])
 def test_blas_full_size_sampled(prec, gate):
     w = workloads.config(3)
     s = workloads.sample_indices(w.n, 200, workloads.SEED_SAMPLES + 3)
@@ -185,6 +201,25 @@ def test_schedules_agree_bitwise(prec):
     assert tm["m2l_levels"] == 3
     ref = fmm.KiFMM(pts, pts, 4, 5).evaluate(q)
     check_parity(a.double().cpu().numpy(), ref, E2E_GATES[prec])
+
+
+@pytest.mark.parametrize("m2l,prec", [("blas", "fp64"), ("blas", "bf16x6"), ("fft", "fp32")])
+def test_autotune_as_first_device_call(m2l, prec):
+    """The autotuner may be a handle's first device call (it sets the device
+    state up itself); BF16x6 keeps the stacked form, its only one."""
+    pts = workloads.uniform_cube(8000, 98)
+    q = workloads.charges(8000, 2, 99, "upm1")
+    say(f"case: autotune before any evaluate, {m2l} {prec} 8k depth 3 p4 nvec 2")
+    kw = dict(svd_rel_tol=1e-6, svd_rel_tol_dir=1e-6) if m2l == "blas" else {}
+    f = K.KiFMM(4, 3, m2l=m2l, prec=prec, **kw).set_points(pts).precompute()
+    qt = torch.as_tensor(q, dtype=f.dtype, device="cuda")
+    assert f.autotune(qt, reps=1) > 0.0
+    if prec == "bf16x6":
+        assert f.tuning()["blas_form"] == 0
+    got = f.evaluate(qt)
+    torch.cuda.synchronize()
+    ref = fmm.KiFMM(pts, pts, 3, 4, **(dict(m2l="blas", **kw) if m2l == "blas" else {})).evaluate(q)
+    check_parity(got.double().cpu().numpy(), ref, E2E_GATES[prec])
 
 
 @pytest.mark.parametrize("m2l,prec", [("fft", "fp32"), ("fft", "fp64"), ("blas", "fp32")])
