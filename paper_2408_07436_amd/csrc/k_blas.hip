@@ -509,18 +509,29 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_a_kernel(Bl
     for (int ct = 0; ct < 2; ++ct) bq[ct] = nbq[ct];
   }
   T* xi = static_cast<T*>(a.xi_hi);
+  // FP32 accumulator rows are 4 g4 + i, FP64 rows g4 + 4 i; Rs is a multiple
+  // of 4, so an FP32 lane's four rows exist together and an FP64 row block's
+  // rows g4 + 4 i exist for i below a bound that is the same for every lane
+  const int rows_left = a.Rs - mb * 128;
 #pragma unroll
   for (int ct = 0; ct < 2; ++ct) {
     if (box[ct] < 0) continue;
-    T* dst = xi + (int64_t)box[ct] * a.Rs * a.nvec + cc.v[ct];
+    T* dst = xi + ((int64_t)box[ct] * a.Rs + mb * 128 + (sizeof(T) == 4 ? 4 * g4 : g4)) * a.nvec + cc.v[ct];
 #pragma unroll
-    for (int rb = 0; rb < 8; ++rb)
+    for (int rb = 0; rb < 8; ++rb) {
+      if (16 * rb >= rows_left) break;
+      T* d = dst + (int64_t)16 * rb * a.nvec;
+      if constexpr (sizeof(T) == 4) {
+        if (16 * rb + 4 * g4 < rows_left) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        // FP32 accumulator rows are 4 g4 + i, FP64 rows g4 + 4 i
-        const int row = mb * 128 + rb * 16 + (sizeof(T) == 4 ? 4 * g4 + i : g4 + 4 * i);
-        if (row < a.Rs) dst[(int64_t)row * a.nvec] = acc[rb][ct][i];
+          for (int i = 0; i < 4; ++i) d[(int64_t)i * a.nvec] = acc[rb][ct][i];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (16 * rb + 4 * i < rows_left) d[(int64_t)4 * i * a.nvec] = acc[rb][ct][i];
       }
+    }
   }
 }
 
@@ -756,12 +767,27 @@ __global__ void stack_reduce_kernel(BlasStack a) {
   a.out[i] = a.scale * sum;
 }
 
-// x = hi + lo for four floats, round-to-nearest-even bf16 parts
 // Stage A, BF16 parts: operands split into NP = 2 parts (BF16x3: hi + lo,
 // three products) or NP = 3 (BF16x6: x0 + x1 + x2, the six products of
 // order at most two, FP32-class), FP32 accumulation; xi stored split,
 // [box][Rs / 8][v][8] so that eight consecutive rows of one column are one
 // 16-byte load in Stage B.
+// The NP bf16 parts (round to nearest even; each residual exact in FP32) of
+// two values, packed two per dword (value x in the low half) into word w of
+// each part's uint2.
+template <int NP>
+__device__ __forceinline__ void split_pairs(float x, float y, uint2 (&p)[NP], int w) {
+  typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+  typedef float v2f __attribute__((ext_vector_type(2)));
+  float rx = x, ry = y;
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_convertvector(v2f{rx, ry}, v2bf));
+    if (w == 0) p[q].x = h; else p[q].y = h;
+    rx -= __uint_as_float(h << 16);
+    ry -= __uint_as_float(h & 0xffff0000u);
+  }
+}
 template <int NP>
 __device__ __forceinline__ void parts_mfma(v4f& acc, const v8bf (&a)[NP], const v8bf (&b)[NP]) {
   acc = mfbf(a[0], b[0], acc);
@@ -868,29 +894,23 @@ __global__ __launch_bounds__(256, 2) void stack_a_bf16_kernel(BlasStack a) {
   }
   __bf16* xp[3] = {static_cast<__bf16*>(a.xi_hi), static_cast<__bf16*>(a.xi_lo),
                    static_cast<__bf16*>(a.xi_p2)};
-  const int64_t rb8 = a.Rs / 8;
+  // rows mb 128 + 16 rb + 4 g4 .. + 3 of this lane: half g4 % 2 of eight-row
+  // group 16 mb + 2 rb + g4 / 2, so one column tile's stores step by 16 nvec
+  // values per row block (Rs is a multiple of 8: the four rows exist together)
+  const int rows_left = a.Rs - mb * 128 - 4 * g4;
+  const int64_t rb_step = (int64_t)16 * a.nvec;
 #pragma unroll
   for (int ct = 0; ct < 2; ++ct) {
     if (box[ct] < 0) continue;
+    const int64_t o = (((int64_t)box[ct] * (a.Rs / 8) + 16 * mb + (g4 >> 1)) * a.nvec + cc.v[ct]) * 8 + 4 * (g4 & 1);
 #pragma unroll
     for (int rb = 0; rb < 8; ++rb) {
-      const int row = mb * 128 + rb * 16 + 4 * g4;  // rows row .. row + 3 of this lane
-      if (row >= a.Rs) continue;
-      const int64_t o = (((int64_t)box[ct] * rb8 + row / 8) * a.nvec + cc.v[ct]) * 8 + row % 8;
-      typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
-      v4bf pv[3];
+      if (16 * rb >= rows_left) break;
+      uint2 pv[NP];
+      split_pairs<NP>(acc[rb][ct][0], acc[rb][ct][1], pv, 0);
+      split_pairs<NP>(acc[rb][ct][2], acc[rb][ct][3], pv, 1);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float x = acc[rb][ct][i];
-        const __bf16 h0 = (__bf16)x;
-        const float r1 = x - (float)h0;
-        const __bf16 h1 = (__bf16)r1;
-        pv[0][i] = h0;
-        pv[1][i] = h1;
-        pv[2][i] = (__bf16)(r1 - (float)h1);
-      }
-#pragma unroll
-      for (int q = 0; q < NP; ++q) *reinterpret_cast<v4bf*>(xp[q] + o) = pv[q];
+      for (int q = 0; q < NP; ++q) *reinterpret_cast<uint2*>(xp[q] + o + rb * rb_step) = pv[q];
     }
   }
 }
@@ -1114,7 +1134,7 @@ hipError_t launch_blas_stacked(const BlasStack& a, hipStream_t stream) {
   if (a.ntiles == 0) return hipSuccess;
   const bool parts = a.mode >= 2;  // BF16 parts: 2 (BF16x3) or 3 (BF16x6)
   if (a.C > 128 || a.Rpad % 128 != 0 || a.Rs > a.Rpad || a.kp % (parts ? 32 : 16) != 0 ||
-      a.rbo * 16 < a.kp || a.kp < a.k || (parts && a.Rs % 8 != 0) || a.mode > 3 ||
+      a.rbo * 16 < a.kp || a.kp < a.k || a.Rs % (parts ? 8 : 4) != 0 || a.mode > 3 ||
       (a.mode == 3 && (!a.A_p2 || !a.B_p2 || !a.q_p2 || !a.xi_p2)))
     return hipErrorInvalidValue;
   if (a.ksplit < 1 || (a.ksplit > 1 && !a.partial)) return hipErrorInvalidValue;
