@@ -23,6 +23,7 @@ CASES = [("fft", "fp64", 4, 4, 0.0, (30000, 3), (9000, 1)),
          ("fft", "fp32", 6, 4, 0.0, (40000, 2), (8000, 1)),
          ("blas", "fp32", 5, 3, 1e-6, (20000, 4), (6000, 2)),
          ("blas", "bf16x3", 5, 3, 1e-6, (12000, 2), (5000, 1)),
+         ("blas", "bf16x6", 5, 3, 1e-6, (12000, 3), (5000, 2)),
          ("dense", "fp64", 3, 3, 0.0, (20000, 1), (5000, 1))]
 
 
