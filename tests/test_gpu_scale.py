@@ -1,5 +1,5 @@
 """Full-size runs beyond the 1M-point workloads: the 4M-point sphere with 64
-charge vectors (FFT-M2L in FP32 and FP64, BLAS-M2L in FP32 and FP64) against
+charge vectors (FFT-M2L in FP32 and FP64, BLAS-M2L in FP32, BF16x3, BF16x6 and FP64) against
 the oracle at sampled targets, and the 8M-point uniform cube (the paper's
 larger size) against the FP64 direct sum at sampled targets.  Gates as in
 the parity tests; against the direct sum the bar is the order-6 expansion's
@@ -46,10 +46,10 @@ def test_sphere_4M_64rhs_fft_sampled(sphere4m):
 
 def test_sphere_4M_64rhs_blas_sampled(sphere4m):
     w, s = sphere4m
-    say(f"case: {w.name} blas tol 1e-6/1e-6 fp32/fp64, 64 vectors at 64 sampled targets")
+    say(f"case: {w.name} blas tol 1e-6/1e-6 fp32/bf16x3/bf16x6/fp64, 64 vectors at 64 sampled targets")
     ref = fmm.KiFMM(w.points, w.points, w.depth, w.order, origin=w.origin, width=w.width,
                     m2l="blas", svd_rel_tol=1e-6, svd_rel_tol_dir=1e-6).evaluate(w.q, s)
-    for prec, gate in (("fp32", FP32_GATE), ("fp64", FP64_GATE)):
+    for prec in ("fp32", "bf16x3", "bf16x6", "fp64"):
         got, _ = evaluate(K, w.points, w.q, w.depth, w.order, "blas", prec, origin=w.origin,
                           width=w.width, tol=1e-6, tol_dir=1e-6)
         check_parity(got[:, s], ref, E2E_GATES[prec], what=f"blas {prec} vs oracle (projected operator)")
