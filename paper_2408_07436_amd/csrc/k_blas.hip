@@ -799,19 +799,24 @@ __device__ __forceinline__ void parts_mfma(v4f& acc, const v8bf (&a)[NP], const 
     acc = mfbf(a[NP - 1], b[0], acc);
   }
 }
+// A workgroup takes rpw consecutive 128-row blocks of one tile (fewer in the
+// class's last part) as one pipeline of K slabs, so that only its first slab
+// waits for loads with nothing in flight.
 template <int NP>
-__global__ __launch_bounds__(256, 2) void stack_a_bf16_kernel(BlasStack a) {
-  const int nmb = a.Rpad / 128;
+__global__ __launch_bounds__(256, 2) void stack_a_bf16_kernel(BlasStack a, int rpw) {
+  const int nmb = a.Rpad / 128, nparts = (nmb + rpw - 1) / rpw;
   const int64_t w = xcd_item();
-  if (w >= a.ntiles * nmb) return;
-  const int64_t tile = w / nmb;
-  const int mb = (int)(w - tile * nmb);
+  if (w >= a.ntiles * nparts) return;
+  const int64_t tile = w / nparts;
+  const int mb0 = (int)(w - tile * nparts) * rpw;
+  const int nrb = min(rpw, nmb - mb0);
+  const int nsl = a.kp / 32;  // K slabs per row block
   const int cls = a.tile_class[tile];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int l16 = lane % 16, g4 = lane / 16;
   const __bf16* qp[3] = {static_cast<const __bf16*>(a.q_hi), static_cast<const __bf16*>(a.q_lo),
                          static_cast<const __bf16*>(a.q_p2)};
-  const int64_t aoff = ((int64_t)cls * a.Rpad + (int64_t)mb * 128) * a.kp;
+  const int64_t aoff = (int64_t)cls * a.Rpad * a.kp;
   const __bf16* Ap[3] = {static_cast<const __bf16*>(a.A_hi) + aoff, static_cast<const __bf16*>(a.A_lo) + aoff,
                          NP == 3 ? static_cast<const __bf16*>(a.A_p2) + aoff : nullptr};
   const StackCols cc = stack_columns(a, wave, l16);
@@ -836,13 +841,14 @@ __global__ __launch_bounds__(256, 2) void stack_a_bf16_kernel(BlasStack a) {
   constexpr int RS = 40;  // bf16 values per LDS row
   __shared__ __attribute__((aligned(16))) __bf16 lds[2][NP][128 * RS];
   const int srow = threadIdx.x >> 1, shalf = threadIdx.x & 1;
-  const int64_t asrc = (int64_t)srow * a.kp + shalf * 16;
   v8bf sg[NP][2];  // 16 staged values of each part of this thread
-  auto gload = [&](int kb) {
+  // slab s of the pipeline: row block mb0 + s / nsl, K from 32 (s % nsl)
+  auto gload = [&](int s) {
+    const int64_t o = ((int64_t)(mb0 + s / nsl) * 128 + srow) * a.kp + shalf * 16 + 32 * (s % nsl);
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
-      sg[q][0] = ld8bf(Ap[q] + asrc + kb);
-      sg[q][1] = ld8bf(Ap[q] + asrc + kb + 8);
+      sg[q][0] = ld8bf(Ap[q] + o);
+      sg[q][1] = ld8bf(Ap[q] + o + 8);
     }
   };
   auto swrite = [&](int buf) {
@@ -863,18 +869,43 @@ __global__ __launch_bounds__(256, 2) void stack_a_bf16_kernel(BlasStack a) {
         bq[ct][q] = qo[ct] >= 0 ? v : zero8;
       }
   };
+  __bf16* xp[3] = {static_cast<__bf16*>(a.xi_hi), static_cast<__bf16*>(a.xi_lo),
+                   static_cast<__bf16*>(a.xi_p2)};
+  const int64_t rb_step = (int64_t)16 * a.nvec;
+  // row block mb's results: rows mb 128 + 16 rb + 4 g4 .. + 3 of this lane,
+  // half g4 % 2 of eight-row group 16 mb + 2 rb + g4 / 2, so one column
+  // tile's stores step by 16 nvec values per row block (Rs is a multiple of
+  // 8: the four rows exist together)
+  auto store_block = [&](int mb) {
+    const int rows_left = a.Rs - mb * 128 - 4 * g4;
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      if (box[ct] < 0) continue;
+      const int64_t o = (((int64_t)box[ct] * (a.Rs / 8) + 16 * mb + (g4 >> 1)) * a.nvec + cc.v[ct]) * 8 + 4 * (g4 & 1);
+#pragma unroll
+      for (int rb = 0; rb < 8; ++rb) {
+        if (16 * rb >= rows_left) break;
+        uint2 pv[NP];
+        split_pairs<NP>(acc[rb][ct][0], acc[rb][ct][1], pv, 0);
+        split_pairs<NP>(acc[rb][ct][2], acc[rb][ct][3], pv, 1);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) *reinterpret_cast<uint2*>(xp[q] + o + rb * rb_step) = pv[q];
+      }
+    }
+  };
+  const int nst = nrb * nsl;
   gload(0);
   swrite(0);
   v8bf bq[2][NP];
   load_q(0, bq);
   __syncthreads();
   int buf = 0;
-  for (int kb = 0; kb < a.kp; kb += 32, buf ^= 1) {
-    const bool more = kb + 32 < a.kp;
-    const int kn = more ? kb + 32 : kb;
+  for (int st = 0; st < nst; ++st, buf ^= 1) {
+    const bool more = st + 1 < nst;
+    const int sn = more ? st + 1 : st;
     v8bf nbq[2][NP];
-    gload(kn);
-    load_q(kn, nbq);
+    gload(sn);
+    load_q(32 * (sn % nsl), nbq);
     // keep the next slab's loads ahead of this slab's MFMAs
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -891,26 +922,12 @@ __global__ __launch_bounds__(256, 2) void stack_a_bf16_kernel(BlasStack a) {
     for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
       for (int q = 0; q < NP; ++q) bq[ct][q] = nbq[ct][q];
-  }
-  __bf16* xp[3] = {static_cast<__bf16*>(a.xi_hi), static_cast<__bf16*>(a.xi_lo),
-                   static_cast<__bf16*>(a.xi_p2)};
-  // rows mb 128 + 16 rb + 4 g4 .. + 3 of this lane: half g4 % 2 of eight-row
-  // group 16 mb + 2 rb + g4 / 2, so one column tile's stores step by 16 nvec
-  // values per row block (Rs is a multiple of 8: the four rows exist together)
-  const int rows_left = a.Rs - mb * 128 - 4 * g4;
-  const int64_t rb_step = (int64_t)16 * a.nvec;
+    if (st % nsl == nsl - 1) {  // the row block's last slab: its results out
+      store_block(mb0 + st / nsl);
 #pragma unroll
-  for (int ct = 0; ct < 2; ++ct) {
-    if (box[ct] < 0) continue;
-    const int64_t o = (((int64_t)box[ct] * (a.Rs / 8) + 16 * mb + (g4 >> 1)) * a.nvec + cc.v[ct]) * 8 + 4 * (g4 & 1);
+      for (int rb = 0; rb < 8; ++rb)
 #pragma unroll
-    for (int rb = 0; rb < 8; ++rb) {
-      if (16 * rb >= rows_left) break;
-      uint2 pv[NP];
-      split_pairs<NP>(acc[rb][ct][0], acc[rb][ct][1], pv, 0);
-      split_pairs<NP>(acc[rb][ct][2], acc[rb][ct][3], pv, 1);
-#pragma unroll
-      for (int q = 0; q < NP; ++q) *reinterpret_cast<uint2*>(xp[q] + o + rb * rb_step) = pv[q];
+        for (int ct = 0; ct < 2; ++ct) acc[rb][ct] = v4f{0.f, 0.f, 0.f, 0.f};
     }
   }
 }
@@ -1141,11 +1158,22 @@ hipError_t launch_blas_stacked(const BlasStack& a, hipStream_t stream) {
   const int64_t nwork = a.ntiles * (a.Rpad / 128);
   const int64_t nb_items = a.ntiles * a.ksplit;
   const dim3 grid_a((unsigned)(8 * ((nwork + 7) / 8))), grid_b((unsigned)(8 * ((nb_items + 7) / 8)));
+  // BF16 Stage A: up to five row blocks per workgroup where the grid stays
+  // above 16,384 workgroups
+  const int nmb = a.Rpad / 128;
+  int rpw = 1;
+  for (int r = 5; r > 1; --r)
+    if (a.ntiles * ((nmb + r - 1) / r) >= 16384) {
+      rpw = r;
+      break;
+    }
+  const int64_t nwork_b16 = a.ntiles * ((nmb + rpw - 1) / rpw);
+  const dim3 grid_a16((unsigned)(8 * ((nwork_b16 + 7) / 8)));
   const dim3 block(256);
   if (a.mode == 0) stack_a_kernel<double><<<grid_a, block, 0, stream>>>(a);
   else if (a.mode == 1) stack_a_kernel<float><<<grid_a, block, 0, stream>>>(a);
-  else if (a.mode == 2) stack_a_bf16_kernel<2><<<grid_a, block, 0, stream>>>(a);
-  else stack_a_bf16_kernel<3><<<grid_a, block, 0, stream>>>(a);
+  else if (a.mode == 2) stack_a_bf16_kernel<2><<<grid_a16, block, 0, stream>>>(a, rpw);
+  else stack_a_bf16_kernel<3><<<grid_a16, block, 0, stream>>>(a, rpw);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
 #define KIFMM_STACK_B(RR)                                                        \
