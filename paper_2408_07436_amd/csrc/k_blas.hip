@@ -404,21 +404,24 @@ __device__ inline int64_t xcd_item() {
   return (b % 8) * per_xcd + b / 8;
 }
 
-// Stage A, FP32 / FP64: one workgroup per (tile, 128-row block of the
-// class's stacked operator); xi[box][row][v] for rows < Rs.
+// Stage A, FP32 / FP64: one workgroup per (tile, rpw consecutive 128-row
+// blocks of the class's stacked operator), the blocks' K slabs as one
+// pipeline; xi[box][row][v] for rows < Rs.
 template <typename T>
-__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_a_kernel(BlasStack a) {
+__global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_a_kernel(BlasStack a, int rpw) {
   using V4 = typename std::conditional<sizeof(T) == 4, v4f, v4d>::type;
-  const int nmb = a.Rpad / 128;
+  const int nmb = a.Rpad / 128, nparts = (nmb + rpw - 1) / rpw;
   const int64_t w = xcd_item();
-  if (w >= a.ntiles * nmb) return;
-  const int64_t tile = w / nmb;
-  const int mb = (int)(w - tile * nmb);
+  if (w >= a.ntiles * nparts) return;
+  const int64_t tile = w / nparts;
+  const int mb0 = (int)(w - tile * nparts) * rpw;
+  const int nrb = min(rpw, nmb - mb0);
+  const int nsl = a.kp / 16;  // K slabs per row block
   const int cls = a.tile_class[tile];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int l16 = lane % 16, g4 = lane / 16;
   const T* q = static_cast<const T*>(a.q_hi);
-  const T* A = static_cast<const T*>(a.A_hi) + ((int64_t)cls * a.Rpad + (int64_t)mb * 128) * a.kp;
+  const T* A = static_cast<const T*>(a.A_hi) + (int64_t)cls * a.Rpad * a.kp;
   const StackCols cc = stack_columns(a, wave, l16);
   int box[2];
   const T* qp[2];
@@ -442,11 +445,12 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_a_kernel(Bl
   __shared__ __attribute__((aligned(16))) T lds[2][128 * RS];
   const V4 zero4 = V4{T(0), T(0), T(0), T(0)};
   const int srow = threadIdx.x >> 1, shalf = threadIdx.x & 1;
-  const T* asrc = A + (int64_t)srow * a.kp + shalf * 8;
   V4 st0, st1;  // 8 staged operator values of this thread
-  auto gload = [&](int kb) {
-    st0 = ld4(asrc + kb);
-    st1 = ld4(asrc + kb + 4);
+  // slab s of the pipeline: row block mb0 + s / nsl, K from 16 (s % nsl)
+  auto gload = [&](int s) {
+    const T* src = A + ((int64_t)(mb0 + s / nsl) * 128 + srow) * a.kp + shalf * 8 + 16 * (s % nsl);
+    st0 = ld4(src);
+    st1 = ld4(src + 4);
   };
   auto swrite = [&](int buf) {
     T* d = &lds[buf][srow * RS + shalf * 8];
@@ -473,18 +477,47 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_a_kernel(Bl
       bq[ct] = qp[ct] ? v : zero4;
     }
   };
+  T* xi = static_cast<T*>(a.xi_hi);
+  // row block mb's results.  FP32 accumulator rows are 4 g4 + i, FP64 rows
+  // g4 + 4 i; Rs is a multiple of 4, so an FP32 lane's four rows exist
+  // together and an FP64 row block's rows g4 + 4 i exist for i below a bound
+  // that is the same for every lane
+  auto store_block = [&](int mb) {
+    const int rows_left = a.Rs - mb * 128;
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      if (box[ct] < 0) continue;
+      T* dst = xi + ((int64_t)box[ct] * a.Rs + mb * 128 + (sizeof(T) == 4 ? 4 * g4 : g4)) * a.nvec + cc.v[ct];
+#pragma unroll
+      for (int rb = 0; rb < 8; ++rb) {
+        if (16 * rb >= rows_left) break;
+        T* d = dst + (int64_t)16 * rb * a.nvec;
+        if constexpr (sizeof(T) == 4) {
+          if (16 * rb + 4 * g4 < rows_left) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) d[(int64_t)i * a.nvec] = acc[rb][ct][i];
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (16 * rb + 4 * i < rows_left) d[(int64_t)4 * i * a.nvec] = acc[rb][ct][i];
+        }
+      }
+    }
+  };
+  const int nst = nrb * nsl;
   gload(0);
   swrite(0);
   V4 bq[2];
   load_q(0, bq);
   __syncthreads();
   int buf = 0;
-  for (int kb = 0; kb < a.kp; kb += 16, buf ^= 1) {
-    const bool more = kb + 16 < a.kp;
-    const int kn = more ? kb + 16 : kb;
+  for (int st = 0; st < nst; ++st, buf ^= 1) {
+    const bool more = st + 1 < nst;
+    const int sn = more ? st + 1 : st;
     V4 nbq[2];
-    gload(kn);
-    load_q(kn, nbq);
+    gload(sn);
+    load_q(16 * (sn % nsl), nbq);
     // keep the next slab's loads ahead of this slab's MFMAs
     __builtin_amdgcn_sched_barrier(0);
     const T* L = &lds[buf][l16 * RS + 4 * g4];
@@ -507,32 +540,19 @@ __global__ __launch_bounds__(256, sizeof(T) == 8 ? 2 : 3) void stack_a_kernel(Bl
     __syncthreads();
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) bq[ct] = nbq[ct];
-  }
-  T* xi = static_cast<T*>(a.xi_hi);
-  // FP32 accumulator rows are 4 g4 + i, FP64 rows g4 + 4 i; Rs is a multiple
-  // of 4, so an FP32 lane's four rows exist together and an FP64 row block's
-  // rows g4 + 4 i exist for i below a bound that is the same for every lane
-  const int rows_left = a.Rs - mb * 128;
+    // FP32: a row block's results out after its last slab; FP64 (whose
+    // accumulators fill the registers) runs one row block per workgroup
+    if constexpr (sizeof(T) == 4) {
+      if (st % nsl == nsl - 1) {
+        store_block(mb0 + st / nsl);
 #pragma unroll
-  for (int ct = 0; ct < 2; ++ct) {
-    if (box[ct] < 0) continue;
-    T* dst = xi + ((int64_t)box[ct] * a.Rs + mb * 128 + (sizeof(T) == 4 ? 4 * g4 : g4)) * a.nvec + cc.v[ct];
+        for (int rb = 0; rb < 8; ++rb)
 #pragma unroll
-    for (int rb = 0; rb < 8; ++rb) {
-      if (16 * rb >= rows_left) break;
-      T* d = dst + (int64_t)16 * rb * a.nvec;
-      if constexpr (sizeof(T) == 4) {
-        if (16 * rb + 4 * g4 < rows_left) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) d[(int64_t)i * a.nvec] = acc[rb][ct][i];
-        }
-      } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (16 * rb + 4 * i < rows_left) d[(int64_t)4 * i * a.nvec] = acc[rb][ct][i];
+          for (int ct = 0; ct < 2; ++ct) acc[rb][ct] = zero4;
       }
     }
   }
+  if constexpr (sizeof(T) == 8) store_block(mb0);
 }
 
 // Stage B, FP32 / FP64: one workgroup per target tile; K step n covers rows
@@ -1155,25 +1175,24 @@ hipError_t launch_blas_stacked(const BlasStack& a, hipStream_t stream) {
       (a.mode == 3 && (!a.A_p2 || !a.B_p2 || !a.q_p2 || !a.xi_p2)))
     return hipErrorInvalidValue;
   if (a.ksplit < 1 || (a.ksplit > 1 && !a.partial)) return hipErrorInvalidValue;
-  const int64_t nwork = a.ntiles * (a.Rpad / 128);
   const int64_t nb_items = a.ntiles * a.ksplit;
-  const dim3 grid_a((unsigned)(8 * ((nwork + 7) / 8))), grid_b((unsigned)(8 * ((nb_items + 7) / 8)));
-  // BF16 Stage A: up to five row blocks per workgroup where the grid stays
-  // above 16,384 workgroups
+  const dim3 grid_b((unsigned)(8 * ((nb_items + 7) / 8)));
+  // Stage A: up to five row blocks per workgroup (FP64: one) where the grid
+  // stays above 16,384 workgroups
   const int nmb = a.Rpad / 128;
   int rpw = 1;
-  for (int r = 5; r > 1; --r)
+  for (int r = a.mode == 0 ? 1 : 5; r > 1; --r)
     if (a.ntiles * ((nmb + r - 1) / r) >= 16384) {
       rpw = r;
       break;
     }
-  const int64_t nwork_b16 = a.ntiles * ((nmb + rpw - 1) / rpw);
-  const dim3 grid_a16((unsigned)(8 * ((nwork_b16 + 7) / 8)));
+  const int64_t nwork_a = a.ntiles * ((nmb + rpw - 1) / rpw);
+  const dim3 grid_a((unsigned)(8 * ((nwork_a + 7) / 8)));
   const dim3 block(256);
-  if (a.mode == 0) stack_a_kernel<double><<<grid_a, block, 0, stream>>>(a);
-  else if (a.mode == 1) stack_a_kernel<float><<<grid_a, block, 0, stream>>>(a);
-  else if (a.mode == 2) stack_a_bf16_kernel<2><<<grid_a16, block, 0, stream>>>(a, rpw);
-  else stack_a_bf16_kernel<3><<<grid_a16, block, 0, stream>>>(a, rpw);
+  if (a.mode == 0) stack_a_kernel<double><<<grid_a, block, 0, stream>>>(a, rpw);
+  else if (a.mode == 1) stack_a_kernel<float><<<grid_a, block, 0, stream>>>(a, rpw);
+  else if (a.mode == 2) stack_a_bf16_kernel<2><<<grid_a, block, 0, stream>>>(a, rpw);
+  else stack_a_bf16_kernel<3><<<grid_a, block, 0, stream>>>(a, rpw);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
 #define KIFMM_STACK_B(RR)                                                        \
